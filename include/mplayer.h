@@ -1,0 +1,248 @@
+/*
+ * mplayer.h - C ABI of the consistent neural message-passing layer on gfx950.
+ *
+ * The layer is the paper's consistent NMP layer (Eq. 4a-e of
+ * "Scalable and Consistent Graph Neural Networks for Distributed Mesh-based
+ * Data-driven Modeling"): an edge MLP on every directed edge, a 1/d_ij
+ * weighted sum of edge states into receivers, a halo exchange that sums the
+ * partial aggregates of every global node held by several sub-graphs, and a
+ * residual node MLP.  All R sub-graphs of a partition live on one GPU as
+ * row ranges of one set of buffers; the halo exchange is an in-device
+ * gather/scatter over groups of rows that share a global id.
+ *
+ * Conventions (every entry point):
+ *  - Every function returns MP_OK (0) or a positive error code; on error
+ *    mp_last_error() returns a thread-local message.  Nothing throws across
+ *    the ABI and nothing calls exit().
+ *  - Validation happens before any launch: on an error return no kernel was
+ *    launched and no output was written.
+ *  - The caller owns every buffer.  The library owns only the opaque host
+ *    objects mp_graph and mp_halo_plan, released by their *_destroy call.
+ *  - Device entry points never allocate device memory; scratch comes from a
+ *    caller workspace sized by the matching *_workspace_size call.
+ *  - Device entry points are asynchronous on the given HIP stream (NULL is
+ *    the default stream).  Inputs must stay alive until the stream reaches
+ *    the work.
+ *  - Matrices are row-major with features contiguous.  Weights follow the
+ *    nn.Linear layout W[out][in].  Device pointers must be 16-byte aligned.
+ *  - Reductions use fixed orders and no floating-point atomics, so every
+ *    device result is bitwise reproducible run to run.
+ */
+#ifndef MPLAYER_H
+#define MPLAYER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MP_ABI_VERSION 1
+
+enum {
+  MP_OK = 0,
+  MP_EINVAL = 1, /* bad pointer, size, width, dtype or aliasing */
+  MP_EPLAN = 2,  /* graph / plan descriptor inconsistent */
+  MP_ENOMEM = 3, /* host allocation failed, or workspace too small */
+  MP_EHIP = 4    /* HIP runtime or launch error */
+};
+
+enum { MP_F32 = 0, MP_BF16 = 1 }; /* arithmetic type of the MLP GEMM operands */
+
+typedef struct ihipStream_t* mp_stream_t; /* the same type as hipStream_t */
+
+int mp_abi_version(void);
+const char* mp_last_error(void);
+
+/* ---------------------------------------------------------------------
+ * Host: distributed graph generation (Sec. II-A, Figs. 2-4).
+ * ------------------------------------------------------------------- */
+
+/* Element-local graph links of a hexahedral element of order P (Sec. II-A,
+ * Fig. 2): undirected pairs of neighbouring GLL points, in local point
+ * numbering a + (P+1)*(b + (P+1)*c).  With links == NULL only *n_links is
+ * written ((P+1)^2 * P * 3 pairs).  links is [n_links][2], host memory. */
+int mp_hex_links(int32_t P, int32_t* links, int32_t* n_links);
+
+typedef struct mp_graph mp_graph;
+
+/* Build the reduced distributed graph (Sec. II-A, Fig. 3c) of an element
+ * partition.  Inputs (host memory, read only):
+ *   elem_gid [n_elem][npe]  global node id of every element-local point;
+ *   links    [n_links][2]   element-local point pairs joined by an edge;
+ *   elem_part[n_elem]       sub-graph of every element, in [0, R).
+ * Sub-graph r holds the distinct global ids of its elements' points as rows
+ * (local coincident nodes collapsed), in ascending global id, and both
+ * directions of every distinct link of its elements.  The R sub-graphs are
+ * concatenated in r order.  Edges are sorted by (receiver row, sender row).
+ * edge_mult d_ij = number of sub-graphs holding the link (the edge degree
+ * under Eq. 4b); node_mult d_i = number of sub-graphs holding the node
+ * (Eq. 6b-c).  Errors: MP_EINVAL for bad sizes, ids out of range, parts
+ * out of range, self-links, empty sub-graphs or more than 2^31-1 rows or
+ * edges; MP_ENOMEM on host allocation failure. */
+int graph_partition(int64_t n_elem, int32_t npe, const int64_t* elem_gid,
+                    int32_t n_links, const int32_t* links,
+                    const int32_t* elem_part, int32_t R, mp_graph** out);
+
+int mp_graph_sizes(const mp_graph* g, int64_t* n_rows, int64_t* n_edges, int32_t* R);
+
+/* Copy the graph out (host memory, sizes from mp_graph_sizes; any pointer
+ * may be NULL to skip that array):
+ *   row_off[R+1], edge_off[R+1]  row / edge range of each sub-graph;
+ *   row_gid[N]                   global id of every row;
+ *   rowptr[N+1]                  CSR offsets of each row's incoming edges;
+ *   recv[E], col[E]              receiver and sender row of every edge;
+ *   rev[E]                       index of the edge's reverse (j->i for i->j);
+ *   edge_mult[E], node_mult[N]   degrees d_ij and d_i. */
+int mp_graph_export(const mp_graph* g, int64_t* row_off, int64_t* edge_off,
+                    int64_t* row_gid, int32_t* rowptr, int32_t* recv, int32_t* col,
+                    int32_t* rev, uint8_t* edge_mult, uint8_t* node_mult);
+int mp_graph_destroy(mp_graph* g);
+
+typedef struct mp_halo_plan mp_halo_plan;
+
+/* Halo plan of a graph (Eq. 4c-d, Fig. 4).  One-GPU form: groups of rows
+ * that hold the same global id (only ids held by two or more sub-graphs),
+ * members in ascending row order, groups in ascending global id.
+ * Multi-GPU form (exported for a distributed runtime): for every ordered
+ * pair (r, s) of sub-graphs sharing ids, the rows of r to send to s (r's
+ * send mask) and the matching rows of s (where s's halo rows sum into),
+ * in ascending global id; plus per-sub-graph halo-row and neighbour
+ * counts (the columns of Table II). */
+int halo_plan_build(const mp_graph* g, mp_halo_plan** out);
+int mp_halo_plan_sizes(const mp_halo_plan* p, int64_t* n_groups, int64_t* n_members,
+                       int64_t* n_pairs, int64_t* n_pair_rows);
+/* Host arrays, any may be NULL: group_ptr[n_groups+1], member[n_members],
+ * pair_r[n_pairs], pair_s[n_pairs], pair_ptr[n_pairs+1],
+ * pair_rows_r[n_pair_rows], pair_rows_s[n_pair_rows] (global row indices),
+ * halo_rows[R], neighbours[R]. */
+int mp_halo_plan_export(const mp_halo_plan* p, int32_t* group_ptr, int32_t* member,
+                        int32_t* pair_r, int32_t* pair_s, int64_t* pair_ptr,
+                        int32_t* pair_rows_r, int32_t* pair_rows_s,
+                        int64_t* halo_rows, int32_t* neighbours);
+int mp_halo_plan_destroy(mp_halo_plan* p);
+
+/* ---------------------------------------------------------------------
+ * Device graph descriptor.  All arrays are device memory exported from
+ * mp_graph / mp_halo_plan; the caller keeps them alive.  seal is the value
+ * mp_dev_graph_seal() computes from the sizes; entry points reject a
+ * descriptor whose seal does not match (MP_EPLAN).
+ * ------------------------------------------------------------------- */
+typedef struct {
+  int64_t n_rows, n_edges, n_groups, n_members;
+  const int32_t* rowptr;    /* [n_rows+1] */
+  const int32_t* recv;      /* [n_edges] receiver row */
+  const int32_t* col;       /* [n_edges] sender row */
+  const int32_t* rev;       /* [n_edges] reverse edge */
+  const uint8_t* edge_mult; /* [n_edges] d_ij >= 1 */
+  const int32_t* group_ptr; /* [n_groups+1] */
+  const int32_t* member;    /* [n_members] */
+  uint64_t seal;
+} mp_dev_graph;
+
+uint64_t mp_dev_graph_seal(const mp_dev_graph* g);
+
+/* ---------------------------------------------------------------------
+ * One consistent NMP layer (Eq. 4a-e) on all sub-graphs at once.
+ * ------------------------------------------------------------------- */
+typedef struct {
+  int32_t H;          /* hidden width: 32, 64 or 128 */
+  int32_t layernorm;  /* 1: LayerNorm on the output of both MLPs */
+  int32_t halo;       /* 1: consistent (Eq. 4c-d); 0: "None" mode, halo skipped */
+  int32_t gemm_dtype; /* MP_F32 or MP_BF16 (operands rounded to nearest even) */
+  float ln_eps;
+} mp_layer_cfg;
+
+/* Parameters of one layer, device FP32.  Edge MLP: Linear(3H->H), ELU,
+ * Linear(H->H) [, LayerNorm]; the input is [x_i (receiver), x_j (sender),
+ * e_ij] (Eq. 4a).  Node MLP: Linear(2H->H), ELU, Linear(H->H)
+ * [, LayerNorm] on [a*_i, x_i] (Eq. 4e).  Both updates are residual. */
+typedef struct {
+  const float *We1, *be1; /* [H][3H], [H] */
+  const float *We2, *be2; /* [H][H],  [H] */
+  const float *ge, *bge;  /* LayerNorm gain/shift [H] (unused without LN) */
+  const float *Wn1, *bn1; /* [H][2H], [H] */
+  const float *Wn2, *bn2; /* [H][H],  [H] */
+  const float *gn, *bgn;  /* [H] */
+} mp_layer_params;
+
+/* Gradients, same shapes; overwritten (not accumulated) by the backward. */
+typedef struct {
+  float *We1, *be1, *We2, *be2, *ge, *bge;
+  float *Wn1, *bn1, *Wn2, *bn2, *gn, *bgn;
+} mp_layer_grads;
+
+int mp_layer_workspace_size(const mp_layer_cfg* cfg, const mp_dev_graph* g,
+                            int backward, size_t* bytes);
+
+/* Forward.  x_in[N][H], e_in[E][H] -> x_out[N][H], e_out[E][H] (FP32).
+ * a_star_out[N][H] receives the synchronised aggregate a* (needed by the
+ * backward); it may be NULL.  Outputs must not alias inputs. */
+int mp_layer_forward(const mp_layer_cfg* cfg, const mp_layer_params* p,
+                     const mp_dev_graph* g, const float* x_in, const float* e_in,
+                     float* x_out, float* e_out, float* a_star_out,
+                     void* ws, size_t ws_bytes, mp_stream_t stream);
+
+/* Backward (adjoint of the forward, Eq. 3): given the forward inputs, the
+ * saved a*, and the gradients of the loss with respect to x_out and e_out,
+ * write the gradients with respect to x_in and e_in and every parameter.
+ * Edge-MLP activations are recomputed from (x_in, e_in), not stored.  The
+ * halo sum is its own adjoint and is applied to the a* gradient.  g_e_out
+ * may be NULL (zero). */
+int mp_layer_backward(const mp_layer_cfg* cfg, const mp_layer_params* p,
+                      const mp_dev_graph* g, const float* x_in, const float* e_in,
+                      const float* a_star, const float* g_x_out, const float* g_e_out,
+                      float* g_x_in, float* g_e_in, const mp_layer_grads* grads,
+                      void* ws, size_t ws_bytes, mp_stream_t stream);
+
+/* ---------------------------------------------------------------------
+ * Encoder / decoder MLPs, edge inputs and loss (Sec. III, Eq. 5-6).
+ * ------------------------------------------------------------------- */
+typedef struct {
+  int32_t n_in;       /* input features: 3, 4, or a multiple of 16 up to 128 */
+  int32_t H;          /* hidden width: 32, 64 or 128 */
+  int32_t n_out;      /* output features: H, or 1..4 (decoder) */
+  int32_t layernorm;  /* LayerNorm on the output (requires n_out == H) */
+  int32_t gemm_dtype; /* MP_F32 or MP_BF16 for the H x H products */
+  float ln_eps;
+} mp_mlp_cfg;
+
+/* Linear(n_in->H), ELU, Linear(H->n_out) [, LayerNorm]. */
+typedef struct {
+  const float *W0, *b0, *W1, *b1, *ln_g, *ln_b;
+} mp_mlp_params;
+typedef struct {
+  float *W0, *b0, *W1, *b1, *ln_g, *ln_b;
+} mp_mlp_grads;
+
+int mp_mlp_workspace_size(const mp_mlp_cfg* cfg, int64_t n_rows, int backward, size_t* bytes);
+int mp_mlp_forward(const mp_mlp_cfg* cfg, const mp_mlp_params* p, int64_t n_rows,
+                   const float* in, float* out, void* ws, size_t ws_bytes,
+                   mp_stream_t stream);
+/* g_in may be NULL (input gradient not needed). */
+int mp_mlp_backward(const mp_mlp_cfg* cfg, const mp_mlp_params* p, int64_t n_rows,
+                    const float* in, const float* g_out, float* g_in,
+                    const mp_mlp_grads* grads, void* ws, size_t ws_bytes,
+                    mp_stream_t stream);
+
+/* Edge input features of Sec. III: e0[k] = (p_j - p_i, |p_j - p_i|) for
+ * edge k with receiver i and sender j; row_pos[N][3] in FP64, the
+ * difference taken in FP64 and rounded once to FP32.  e0 is [E][4]. */
+int mp_edge_inputs(const mp_dev_graph* g, const double* row_pos, float* e0,
+                   mp_stream_t stream);
+
+/* Consistent MSE (Eq. 6a-c): loss = sum_i sum_f (1/d_i)(Y-T)^2 / (N_eff F)
+ * with N_eff = sum_i 1/d_i, over all rows of all sub-graphs; for R=1
+ * (every d_i = 1) this is the MSE of Eq. 5.  Y, T are [N][F] FP32,
+ * node_mult[N] the degrees d_i; writes loss[1] (FP32, summed in FP64 in a
+ * fixed order) and gY[N][F] = dloss/dY.  gY may be NULL. */
+int mp_consistent_mse(int64_t n_rows, int32_t F, const float* Y, const float* T,
+                      const uint8_t* node_mult, float* loss, float* gY,
+                      void* ws, size_t ws_bytes, mp_stream_t stream);
+int mp_consistent_mse_workspace_size(int64_t n_rows, size_t* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MPLAYER_H */

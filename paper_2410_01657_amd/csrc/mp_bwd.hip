@@ -1,0 +1,707 @@
+// Backward (adjoint) kernels of the consistent message-passing layer and of
+// the row MLPs.  Gradient consistency (Eq. 3) needs the exact adjoint of
+// every forward step: the segment sum's adjoint is a gather scaled by
+// 1/d_ij, the halo sum is symmetric and reuses the forward kernel, and the
+// gathers of receiver/sender features become in-row sums (the sender part
+// through the reverse-edge index, so no atomics are needed).
+//
+// Weight gradients are sums over all rows of outer products.  Each
+// workgroup of 4 waves walks its rows in lock step: every wave stages one
+// 16-row block of the two factors in LDS, then each wave accumulates its own
+// subset of 16x16 gradient tiles over the 64 staged rows with MFMA.  Each
+// workgroup writes one slab of partial gradients; launch_wreduce adds the
+// slabs in workgroup order.  Schedules are static, so the result is
+// bitwise reproducible.
+#include <algorithm>
+
+#include "mp_device.hpp"
+#include "mp_kernels.hpp"
+
+namespace mp {
+
+constexpr size_t kLdsLimit = 160 * 1024 - 1024;
+constexpr int kWaves = 4;  // waves per workgroup in the lock-step kernels
+
+// Row stride (floats) of an LDS staging tile of width W: 16 floats of
+// padding keep the transposed MFMA reads free of bank conflicts.
+template <int W>
+constexpr int tile_stride() { return W + 16; }
+template <int W>
+constexpr size_t tile_bytes() { return size_t(64) * tile_stride<W>() * 4; }
+
+template <int W>
+__device__ __forceinline__ void stage_row(float* __restrict__ tile, int row, int g, const float (&v)[W / 4]) {
+#pragma unroll
+  for (int b = 0; b < W / 16; ++b)
+    *reinterpret_cast<float4*>(tile + row * tile_stride<W>() + 16 * b + 4 * g) =
+        make_float4(v[4 * b], v[4 * b + 1], v[4 * b + 2], v[4 * b + 3]);
+}
+
+template <int GW, int AW>
+constexpr int dw_tiles_per_wave() { return ((GW / 16) * (AW / 16) + kWaves - 1) / kWaves; }
+
+// acc[n] += sum over the 64 staged rows of G[row][f] * A[row][k] for the
+// tiles t = wave + 4n (t = fb * (AW/16) + kb) this wave owns.
+template <int GW, int AW>
+__device__ __forceinline__ void dw_tiles(const float* __restrict__ G, const float* __restrict__ A,
+                                         v4f (&acc)[dw_tiles_per_wave<GW, AW>()], int wave, int lane) {
+  constexpr int NT = dw_tiles_per_wave<GW, AW>(), NTILE = (GW / 16) * (AW / 16), KBN = AW / 16;
+  constexpr int GS = tile_stride<GW>(), AS = tile_stride<AW>();
+#pragma unroll
+  for (int n = 0; n < NT; ++n) {
+    const int t = wave + kWaves * n;
+    if (t < NTILE) {
+      const int fb = t / KBN, kb = t % KBN;
+#pragma unroll
+      for (int s = 0; s < 16; ++s) {
+        const int r = 4 * s + (lane >> 4);
+        const float av = G[r * GS + 16 * fb + (lane & 15)];
+        const float bv = A[r * AS + 16 * kb + (lane & 15)];
+        acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[n], 0, 0, 0);
+      }
+    }
+  }
+}
+
+// Write the owned tiles into a row-major [GW][kcols] block of the slab
+// (kcols <= AW drops padded columns).
+template <int GW, int AW>
+__device__ __forceinline__ void dw_store(const v4f (&acc)[dw_tiles_per_wave<GW, AW>()], float* __restrict__ dst,
+                                         int kcols, int wave, int lane) {
+  constexpr int NT = dw_tiles_per_wave<GW, AW>(), NTILE = (GW / 16) * (AW / 16), KBN = AW / 16;
+#pragma unroll
+  for (int n = 0; n < NT; ++n) {
+    const int t = wave + kWaves * n;
+    if (t < NTILE) {
+      const int fb = t / KBN, kb = t % KBN;
+      const int k = 16 * kb + (lane & 15);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int f = 16 * fb + 4 * (lane >> 4) + v;
+        if (k < kcols) dst[f * kcols + k] = acc[n][v];
+      }
+    }
+  }
+}
+
+// Sum a per-lane row-block vector over all 64 rows of the workgroup (16
+// lanes x 4 waves) in a fixed order and write the W sums to dst.  Uses
+// `scratch` (at least 64*W floats of LDS); contains barriers.
+template <int W>
+__device__ __forceinline__ void block_sum_vec(const float (&v)[W / 4], float* __restrict__ scratch,
+                                              float* __restrict__ dst, int wave, int lane) {
+  const int j = lane & 15, g = lane >> 4;
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < W / 4; ++i) scratch[(wave * 16 + j) * W + 16 * (i / 4) + 4 * g + (i % 4)] = v[i];
+  __syncthreads();
+  for (int t = threadIdx.x; t < W; t += blockDim.x) {
+    float s = 0.f;
+    for (int r = 0; r < 64; ++r) s += scratch[r * W + t];
+    dst[t] = s;
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ void stage_frags(uint4* __restrict__ dst, const void* __restrict__ src, size_t bytes) {
+  const uint4* s = reinterpret_cast<const uint4*>(src);
+  for (size_t i = threadIdx.x; i < bytes / 16; i += blockDim.x) dst[i] = s[i];
+}
+
+// ----------------------------------------------------------- edge adjoint
+
+
+template <int H, bool BF>
+struct EdgeBwdCfg {
+  static constexpr size_t FB = frag_bytes(H, H, BF);
+  static constexpr size_t STAGE = 4 * tile_bytes<H>();
+  static constexpr bool LDS_FRAG = 4 * FB + STAGE <= kLdsLimit;
+  static constexpr size_t LDS = STAGE + (LDS_FRAG ? 4 * FB : 0);
+};
+
+// Per edge k (receiver i, sender j), with the forward recomputed:
+//   gE   = g_e_out[k] + g_a[i] / d_k         (adjoint of Eq. 4b plus the
+//                                             gradient reaching e' directly)
+//   gm   = LayerNorm adjoint of gE; db2 += gm; dW2 += gm u^T
+//   gh   = (W2^T gm) * ELU'(h);   dW1c += gh e^T
+//   g_e  = gE + W1c^T gh                     (residual + first Linear)
+//   g_P[i] = sum of gh over i's incoming edges (segmented scan, as forward)
+//   g_h[k] = gh, summed per sender by k_gq through the reverse edges.
+template <int H, bool BF>
+__global__ __launch_bounds__(256) void k_edge_bwd(EdgeBwdArgs a) {
+  using C = EdgeBwdCfg<H, BF>;
+  constexpr int NF = H / 4, MB = H / 16, NT = dw_tiles_per_wave<H, H>();
+  extern __shared__ uint4 smem[];
+  float* tG2 = reinterpret_cast<float*>(smem);
+  float* tA2 = tG2 + 64 * tile_stride<H>();
+  float* tG1 = tA2 + 64 * tile_stride<H>();
+  float* tA1 = tG1 + 64 * tile_stride<H>();
+  const char* fr;
+  if constexpr (C::LDS_FRAG) {
+    uint4* fl = smem + C::STAGE / 16;
+    stage_frags(fl, a.frag, 4 * C::FB);
+    fr = reinterpret_cast<const char*>(fl);
+  } else {
+    fr = reinterpret_cast<const char*>(a.frag);
+  }
+  __syncthreads();
+  const char* fW1c = fr;
+  const char* fW2 = fr + C::FB;
+  const char* fW2t = fr + 2 * C::FB;
+  const char* fW1ct = fr + 3 * C::FB;
+
+  const DevGraph& gr = a.g;
+  const int lane = lane_id(), j = lane & 15, g = lane >> 4, wave = threadIdx.x / 64;
+  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t nparts = (int64_t)gridDim.x * kWaves;
+  int64_t r0, r1;
+  part_rows(gr.rowptr, gr.n_rows, nparts, blk * kWaves + wave, r0, r1);
+  const int64_t e0 = gr.rowptr[r0], e1 = gr.rowptr[r1];
+  // lock-step trip count: the most 16-edge blocks of any wave here
+  int64_t n_iter = 0;
+  for (int w = 0; w < kWaves; ++w) {
+    int64_t q0, q1;
+    part_rows(gr.rowptr, gr.n_rows, nparts, blk * kWaves + w, q0, q1);
+    n_iter = std::max<int64_t>(n_iter, (gr.rowptr[q1] - gr.rowptr[q0] + 15) / 16);
+  }
+
+  float b2v[NF], gam[NF], bet[NF];
+  load_vec<H>(a.b2, g, b2v);
+  if (a.ln) {
+    load_vec<H>(a.lng, g, gam);
+    load_vec<H>(a.lnb, g, bet);
+  }
+  v4f acc2[NT], acc1[NT];
+#pragma unroll
+  for (int n = 0; n < NT; ++n) acc2[n] = acc1[n] = v4f{0.f, 0.f, 0.f, 0.f};
+  float db2[NF], dga[NF], dbe[NF], carry[NF];
+#pragma unroll
+  for (int i = 0; i < NF; ++i) db2[i] = dga[i] = dbe[i] = carry[i] = 0.f;
+  int carry_key = 0;
+
+  for (int64_t it = 0; it < n_iter; ++it) {
+    const int64_t k = e0 + it * 16 + j;
+    const bool valid = k < e1;
+    const int64_t kk = valid ? k : (e1 > e0 ? e1 - 1 : 0);
+    const int ri = gr.recv[kk];
+    const int sj = gr.col[kk];
+    const float inv_d = 1.f / (float)gr.mult[kk];
+    const int next = (k + 1 < e1) ? gr.recv[k + 1] : -1;
+    const bool last = valid && next != ri;
+    const int key = valid ? ri + 1 : -1;
+
+    // recompute the forward
+    float ev[NF], u[NF], t[NF];
+    load_row<H>(a.e_in + kk * H, g, ev);
+    load_row<H>(a.P + (int64_t)ri * H, g, u);
+    load_row<H>(a.Q + (int64_t)sj * H, g, t);
+#pragma unroll
+    for (int i = 0; i < NF; ++i) u[i] += t[i];
+    gemm<BF, MB, MB>(fW1c, ev, u, lane);
+#pragma unroll
+    for (int i = 0; i < NF; ++i) u[i] = elu(u[i]);
+    float mp[NF];
+#pragma unroll
+    for (int i = 0; i < NF; ++i) mp[i] = b2v[i];
+    gemm<BF, MB, MB>(fW2, u, mp, lane);
+
+    // gradient reaching e'
+    float gE[NF];
+    load_row<H>(a.g_a + (int64_t)ri * H, g, gE);
+    if (a.g_e_out) load_row<H>(a.g_e_out + kk * H, g, t);
+#pragma unroll
+    for (int i = 0; i < NF; ++i) {
+      const float v = gE[i] * inv_d + (a.g_e_out ? t[i] : 0.f);
+      gE[i] = valid ? v : 0.f;
+    }
+    // LayerNorm adjoint (mp becomes the pre-LN gradient gm)
+    if (a.ln) {
+      float mean, rstd;
+      ln_stats<H>(mp, a.eps, mean, rstd);
+      float s1 = 0.f, s2 = 0.f;
+#pragma unroll
+      for (int i = 0; i < NF; ++i) {
+        const float xh = (mp[i] - mean) * rstd;
+        dga[i] += gE[i] * xh;
+        dbe[i] += gE[i];
+        const float gx = gE[i] * gam[i];
+        s1 += gx;
+        s2 += gx * xh;
+        mp[i] = xh;
+      }
+      s1 = row_sum(s1) * (1.f / H);
+      s2 = row_sum(s2) * (1.f / H);
+#pragma unroll
+      for (int i = 0; i < NF; ++i) mp[i] = rstd * (gE[i] * gam[i] - s1 - mp[i] * s2);
+    } else {
+#pragma unroll
+      for (int i = 0; i < NF; ++i) mp[i] = gE[i];
+    }
+#pragma unroll
+    for (int i = 0; i < NF; ++i) db2[i] += mp[i];
+    stage_row<H>(tG2, wave * 16 + j, g, mp);
+    stage_row<H>(tA2, wave * 16 + j, g, u);
+    // gh = (W2^T gm) * ELU'(h); ELU'(h) = 1 for h > 0 else exp(h) = u + 1
+#pragma unroll
+    for (int i = 0; i < NF; ++i) t[i] = 0.f;
+    gemm<BF, MB, MB>(fW2t, mp, t, lane);
+#pragma unroll
+    for (int i = 0; i < NF; ++i) t[i] *= (u[i] > 0.f ? 1.f : u[i] + 1.f);
+    stage_row<H>(tG1, wave * 16 + j, g, t);
+    stage_row<H>(tA1, wave * 16 + j, g, ev);
+    // g_e = gE + W1c^T gh
+    gemm<BF, MB, MB>(fW1ct, t, gE, lane);
+    if (valid) {
+      store_row<H>(a.g_e_in + k * H, g, gE);
+      store_row<H>(a.g_h + k * H, g, t);
+    }
+    // g_P: segmented sum of gh per receiver
+#pragma unroll
+    for (int i = 0; i < NF; ++i) {
+      float v = valid ? t[i] : 0.f;
+      if (j == 0 && key == carry_key) v += carry[i];
+      t[i] = v;
+    }
+    seg_scan16<NF>(t, key);
+    if (last) store_row<H>(a.g_P + (int64_t)ri * H, g, t);
+#pragma unroll
+    for (int i = 0; i < NF; ++i) carry[i] = from_prev_lane(t[i]);
+    carry_key = from_prev_lane_i(key);
+
+    __syncthreads();
+    dw_tiles<H, H>(tG2, tA2, acc2, wave, lane);
+    dw_tiles<H, H>(tG1, tA1, acc1, wave, lane);
+    __syncthreads();
+  }
+  for (int64_t r = r0 + (lane >> 2); r < r1; r += 16) {
+    if (gr.rowptr[r] == gr.rowptr[r + 1]) {
+      float* dst = a.g_P + r * H;
+      for (int c = (lane & 3) * 4; c < H; c += 16) *reinterpret_cast<float4*>(dst + c) = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  }
+  float* slab = a.part + blockIdx.x * a.slab;
+  dw_store<H, H>(acc1, slab, H, wave, lane);
+  dw_store<H, H>(acc2, slab + H * H, H, wave, lane);
+  float* scratch = tG2;
+  block_sum_vec<H>(db2, scratch, slab + 2 * H * H, wave, lane);
+  block_sum_vec<H>(dga, scratch, slab + 2 * H * H + H, wave, lane);
+  block_sum_vec<H>(dbe, scratch, slab + 2 * H * H + 2 * H, wave, lane);
+}
+
+template <int H, bool BF>
+static hipError_t launch_edge_bwd_t(const EdgeBwdArgs& a, int grid, hipStream_t s) {
+  using C = EdgeBwdCfg<H, BF>;
+  (void)hipFuncSetAttribute((const void*)k_edge_bwd<H, BF>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)C::LDS);
+  hipLaunchKernelGGL((k_edge_bwd<H, BF>), dim3(grid), dim3(256), C::LDS, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_edge_bwd(const EdgeBwdArgs& a, int grid, hipStream_t s) {
+#define MP_CASE(HH) \
+  if (a.H == HH) return a.bf ? launch_edge_bwd_t<HH, true>(a, grid, s) : launch_edge_bwd_t<HH, false>(a, grid, s);
+  MP_CASE(32) MP_CASE(64) MP_CASE(128)
+#undef MP_CASE
+  return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------- sender-side gradients
+
+
+template <int H, bool BF>
+struct GqCfg {
+  static constexpr size_t FB = frag_bytes(H, 2 * H, BF);
+  static constexpr size_t STAGE = tile_bytes<2 * H>() + tile_bytes<H>();
+  static constexpr bool LDS_FRAG = FB + STAGE <= kLdsLimit;
+  static constexpr size_t LDS = STAGE + (LDS_FRAG ? FB : 0);
+};
+
+// Per node j: g_Q[j] = sum of g_h over j's outgoing edges, read as the
+// reverse edges of j's incoming edges (in ascending order), then
+//   g_x[j] += W1a^T g_P[j] + W1b^T g_Q[j]
+//   dW1a += g_P x^T, dW1b += g_Q x^T, db1 += g_P.
+template <int H, bool BF>
+__global__ __launch_bounds__(256) void k_gq(GqArgs a) {
+  using C = GqCfg<H, BF>;
+  constexpr int NF = H / 4, MB = H / 16, NT = dw_tiles_per_wave<2 * H, H>();
+  extern __shared__ uint4 smem[];
+  float* tG = reinterpret_cast<float*>(smem);
+  float* tA = tG + 64 * tile_stride<2 * H>();
+  const char* fr;
+  if constexpr (C::LDS_FRAG) {
+    uint4* fl = smem + C::STAGE / 16;
+    stage_frags(fl, a.frag_abt, C::FB);
+    fr = reinterpret_cast<const char*>(fl);
+  } else {
+    fr = reinterpret_cast<const char*>(a.frag_abt);
+  }
+  __syncthreads();
+  const DevGraph& gr = a.g;
+  const int lane = lane_id(), j = lane & 15, g = lane >> 4, wave = threadIdx.x / 64;
+  const int64_t n = gr.n_rows, nblk = (n + 15) / 16;
+  // contiguous row blocks per workgroup, 4 blocks (one per wave) per step
+  const int64_t per = (nblk + gridDim.x - 1) / gridDim.x;
+  const int64_t b0 = blockIdx.x * per, b1 = std::min(nblk, b0 + per);
+  const int64_t n_iter = (b1 - b0 + kWaves - 1) / kWaves;
+  v4f acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+  float db1[NF];
+#pragma unroll
+  for (int i = 0; i < NF; ++i) db1[i] = 0.f;
+
+  for (int64_t it = 0; it < n_iter; ++it) {
+    const int64_t bk = b0 + it * kWaves + wave;
+    const int64_t row = bk * 16 + j;
+    const bool valid = bk < b1 && row < n;
+    const int64_t rr = valid ? row : n - 1;
+    float in[2 * NF], xv[NF];
+    load_row<H>(a.g_P + rr * H, g, xv);
+#pragma unroll
+    for (int i = 0; i < NF; ++i) {
+      in[i] = xv[i];
+      in[NF + i] = 0.f;
+    }
+    const int p0 = gr.rowptr[rr], p1 = gr.rowptr[rr + 1];
+    for (int e = p0; e < p1; ++e) {
+      float t[NF];
+      load_row<H>(a.g_h + (int64_t)gr.rev[e] * H, g, t);
+#pragma unroll
+      for (int i = 0; i < NF; ++i) in[NF + i] += t[i];
+    }
+    load_row<H>(a.x + rr * H, g, xv);
+    if (!valid) {
+#pragma unroll
+      for (int i = 0; i < 2 * NF; ++i) in[i] = 0.f;
+    }
+#pragma unroll
+    for (int i = 0; i < NF; ++i) db1[i] += in[i];
+    stage_row<2 * H>(tG, wave * 16 + j, g, in);
+    stage_row<H>(tA, wave * 16 + j, g, xv);
+    float gx[NF];
+    load_row<H>(a.g_x + rr * H, g, gx);
+    gemm<BF, MB, 2 * MB>(fr, in, gx, lane);
+    if (valid) store_row<H>(a.g_x + row * H, g, gx);
+    __syncthreads();
+    dw_tiles<2 * H, H>(tG, tA, acc, wave, lane);
+    __syncthreads();
+  }
+  float* slab = a.part + blockIdx.x * a.slab;
+  dw_store<2 * H, H>(acc, slab, H, wave, lane);
+  block_sum_vec<H>(db1, tG, slab + 2 * H * H, wave, lane);
+}
+
+template <int H, bool BF>
+static hipError_t launch_gq_t(const GqArgs& a, int grid, hipStream_t s) {
+  using C = GqCfg<H, BF>;
+  (void)hipFuncSetAttribute((const void*)k_gq<H, BF>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)C::LDS);
+  hipLaunchKernelGGL((k_gq<H, BF>), dim3(grid), dim3(256), C::LDS, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_gq(const GqArgs& a, int grid, hipStream_t s) {
+#define MP_CASE(HH) if (a.H == HH) return a.bf ? launch_gq_t<HH, true>(a, grid, s) : launch_gq_t<HH, false>(a, grid, s);
+  MP_CASE(32) MP_CASE(64) MP_CASE(128)
+#undef MP_CASE
+  return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------- row MLP adjoint
+
+
+template <int H, int KIN, bool TIN, bool TOUT, bool BF>
+struct MlpBwdCfg {
+  static constexpr int AW0 = TIN ? 16 : KIN;  // staged input width
+  static constexpr size_t F0 = TIN ? 0 : frag_bytes(H, KIN, BF);
+  static constexpr size_t F1 = TOUT ? 0 : frag_bytes(H, H, BF);
+  // fragments: W0, W1, W1^T, W0^T
+  static constexpr size_t FRAG = 2 * F0 + 2 * F1;
+  static constexpr size_t STAGE0 = tile_bytes<H>() + tile_bytes<AW0>();
+  static constexpr size_t STAGE1 = TOUT ? 0 : 2 * tile_bytes<H>();
+  static constexpr size_t STAGE = STAGE0 > STAGE1 ? STAGE0 : STAGE1;
+  static constexpr bool LDS_FRAG = FRAG + STAGE <= kLdsLimit;
+  static constexpr size_t LDS = STAGE + (LDS_FRAG ? FRAG : 0);
+};
+
+// Adjoint of k_mlp_fwd, forward recomputed per row block:
+//   z = W0 in + b0, u = ELU(z), y = W1 u + b1, out = [resid +] LN(y)
+// The two staging phases (dW1 then dW0) share the same LDS.
+template <int H, int KIN, bool TIN, bool TOUT, bool BF>
+__global__ __launch_bounds__(256) void k_mlp_bwd(MlpBwdArgs a) {
+  using C = MlpBwdCfg<H, KIN, TIN, TOUT, BF>;
+  constexpr int NF = H / 4, MB = H / 16, KB = TIN ? 1 : KIN / 16, AW0 = C::AW0;
+  constexpr int NT1 = dw_tiles_per_wave<H, H>(), NT0 = dw_tiles_per_wave<H, AW0>();
+  extern __shared__ uint4 smem[];
+  float* tG = reinterpret_cast<float*>(smem);
+  float* tA = tG + 64 * tile_stride<H>();
+  const char* fr;
+  if constexpr (C::LDS_FRAG) {
+    uint4* fl = smem + C::STAGE / 16;
+    stage_frags(fl, a.frag0, C::F0);
+    stage_frags(fl + C::F0 / 16, a.frag1, C::F1);
+    stage_frags(fl + (C::F0 + C::F1) / 16, a.frag1t, C::F1);
+    if (a.frag0t) stage_frags(fl + (C::F0 + 2 * C::F1) / 16, a.frag0t, C::F0);
+    fr = reinterpret_cast<const char*>(fl);
+  } else {
+    fr = nullptr;
+  }
+  __syncthreads();
+  const char* f0 = C::LDS_FRAG ? fr : reinterpret_cast<const char*>(a.frag0);
+  const char* f1 = C::LDS_FRAG ? fr + C::F0 : reinterpret_cast<const char*>(a.frag1);
+  const char* f1t = C::LDS_FRAG ? fr + C::F0 + C::F1 : reinterpret_cast<const char*>(a.frag1t);
+  const char* f0t = C::LDS_FRAG ? fr + C::F0 + 2 * C::F1 : reinterpret_cast<const char*>(a.frag0t);
+  const bool want_gin = (a.g_src0 || a.g_src1) && !TIN;
+
+  const int lane = lane_id(), j = lane & 15, g = lane >> 4, wave = threadIdx.x / 64;
+  const int64_t n = a.n_rows, nblk = (n + 15) / 16;
+  const int64_t per = (nblk + gridDim.x - 1) / gridDim.x;
+  const int64_t b0 = blockIdx.x * per, b1 = std::min(nblk, b0 + per);
+  const int64_t n_iter = (b1 - b0 + kWaves - 1) / kWaves;
+  const int NO = TOUT ? a.n_out : H;
+
+  v4f acc1[NT1], acc0[NT0];
+#pragma unroll
+  for (int t = 0; t < NT1; ++t) acc1[t] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int t = 0; t < NT0; ++t) acc0[t] = v4f{0.f, 0.f, 0.f, 0.f};
+  float db0[NF], db1[NF], dga[NF], dbe[NF];
+#pragma unroll
+  for (int i = 0; i < NF; ++i) db0[i] = db1[i] = dga[i] = dbe[i] = 0.f;
+  float dW1s[4][NF];  // small-output dW1 rows (n_out <= 4)
+  float db1s[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int o = 0; o < 4; ++o)
+#pragma unroll
+    for (int i = 0; i < NF; ++i) dW1s[o][i] = 0.f;
+  float gam[NF];
+  if (a.ln) load_vec<H>(a.lng, g, gam);
+
+  for (int64_t it = 0; it < n_iter; ++it) {
+    const int64_t bk = b0 + it * kWaves + wave;
+    const int64_t row = bk * 16 + j;
+    const bool valid = bk < b1 && row < n;
+    const int64_t rr = valid ? row : n - 1;
+    // ---- recompute
+    float in[TIN ? 4 : KIN / 4];
+    float z[NF];
+    load_vec<H>(a.b0, g, z);
+    if constexpr (TIN) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) in[k] = k < a.k0 ? a.src0[rr * a.k0 + k] : 0.f;
+#pragma unroll
+      for (int i = 0; i < NF; ++i) {
+        const int f = 16 * (i / 4) + 4 * g + (i % 4);
+        for (int k = 0; k < a.k0; ++k) z[i] += a.W0[f * a.k0 + k] * in[k];
+      }
+    } else {
+      if constexpr (KIN == 2 * H) {
+        float t0[NF], t1[NF];
+        load_row<H>(a.src0 + rr * H, g, t0);
+        load_row<H>(a.src1 + rr * H, g, t1);
+#pragma unroll
+        for (int i = 0; i < NF; ++i) {
+          in[i] = t0[i];
+          in[NF + i] = t1[i];
+        }
+      } else {
+        load_row<KIN>(a.src0 + rr * KIN, g, in);
+      }
+      gemm<BF, MB, KB>(f0, in, z, lane);
+    }
+    float u[NF];
+#pragma unroll
+    for (int i = 0; i < NF; ++i) u[i] = elu(z[i]);
+    // ---- gradient at u
+    float gu[NF];
+    if constexpr (TOUT) {
+      float go[4];
+#pragma unroll
+      for (int o = 0; o < 4; ++o) go[o] = (o < NO && valid) ? a.g_out[rr * NO + o] : 0.f;
+#pragma unroll
+      for (int i = 0; i < NF; ++i) {
+        const int f = 16 * (i / 4) + 4 * g + (i % 4);
+        float s = 0.f;
+        for (int o = 0; o < NO; ++o) s += a.W1[o * H + f] * go[o];
+        gu[i] = s;
+      }
+#pragma unroll
+      for (int o = 0; o < 4; ++o)
+#pragma unroll
+        for (int i = 0; i < NF; ++i) dW1s[o][i] += go[o] * u[i];
+      // db1 (n_out values): one copy per row, in lane group 0
+      if (g == 0) {
+#pragma unroll
+        for (int o = 0; o < 4; ++o) db1s[o] += go[o];
+      }
+    } else {
+      float y[NF], go[NF];
+      load_vec<H>(a.b1, g, y);
+      gemm<BF, MB, MB>(f1, u, y, lane);
+      load_row<H>(a.g_out + rr * H, g, go);
+      if (!valid) {
+#pragma unroll
+        for (int i = 0; i < NF; ++i) go[i] = 0.f;
+      }
+      if (a.ln) {
+        float mean, rstd, s1 = 0.f, s2 = 0.f;
+        ln_stats<H>(y, a.eps, mean, rstd);
+#pragma unroll
+        for (int i = 0; i < NF; ++i) {
+          const float xh = (y[i] - mean) * rstd;
+          dga[i] += go[i] * xh;
+          dbe[i] += go[i];
+          const float gx = go[i] * gam[i];
+          s1 += gx;
+          s2 += gx * xh;
+          y[i] = xh;
+        }
+        s1 = row_sum(s1) * (1.f / H);
+        s2 = row_sum(s2) * (1.f / H);
+#pragma unroll
+        for (int i = 0; i < NF; ++i) y[i] = rstd * (go[i] * gam[i] - s1 - y[i] * s2);
+      } else {
+#pragma unroll
+        for (int i = 0; i < NF; ++i) y[i] = go[i];
+      }
+#pragma unroll
+      for (int i = 0; i < NF; ++i) db1[i] += y[i];
+      // phase 1: dW1 += gy u^T
+      stage_row<H>(tG, wave * 16 + j, g, y);
+      stage_row<H>(tA, wave * 16 + j, g, u);
+      __syncthreads();
+      dw_tiles<H, H>(tG, tA, acc1, wave, lane);
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < NF; ++i) gu[i] = 0.f;
+      gemm<BF, MB, MB>(f1t, y, gu, lane);
+    }
+    // ---- gradient at z, dW0, db0
+#pragma unroll
+    for (int i = 0; i < NF; ++i) gu[i] *= (u[i] > 0.f ? 1.f : u[i] + 1.f);
+#pragma unroll
+    for (int i = 0; i < NF; ++i) db0[i] += gu[i];
+    stage_row<H>(tG, wave * 16 + j, g, gu);
+    if constexpr (TIN) {
+      float in16[4] = {0.f, 0.f, 0.f, 0.f};  // lane group g holds input features 4g..4g+3
+      if (g == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) in16[k] = in[k];
+      }
+      stage_row<16>(tA, wave * 16 + j, g, in16);
+    } else {
+      stage_row<KIN>(tA, wave * 16 + j, g, in);
+    }
+    __syncthreads();
+    dw_tiles<H, AW0>(tG, tA, acc0, wave, lane);
+    __syncthreads();
+    // ---- input gradient
+    if constexpr (!TIN) {
+      if (want_gin) {
+        float gi[KIN / 4];
+#pragma unroll
+        for (int i = 0; i < KIN / 4; ++i) gi[i] = 0.f;
+        gemm<BF, KIN / 16, MB>(f0t, gu, gi, lane);
+        if constexpr (KIN == 2 * H) {
+          float t0[NF], t1[NF];
+#pragma unroll
+          for (int i = 0; i < NF; ++i) {
+            t0[i] = gi[i];
+            t1[i] = gi[NF + i];
+          }
+          if (a.g_add1) {
+            float r[NF];
+            load_row<H>(a.g_add1 + rr * H, g, r);
+#pragma unroll
+            for (int i = 0; i < NF; ++i) t1[i] += r[i];
+          }
+          if (valid && a.g_src0) store_row<H>(a.g_src0 + row * H, g, t0);
+          if (valid && a.g_src1) store_row<H>(a.g_src1 + row * H, g, t1);
+        } else {
+          if (valid && a.g_src0) store_row<KIN>(a.g_src0 + row * KIN, g, gi);
+        }
+      }
+    }
+  }
+  // ---- write the slab
+  float* slab = a.part + blockIdx.x * a.slab;
+  const int k0w = TIN ? a.k0 : KIN;
+  dw_store<H, AW0>(acc0, slab, k0w, wave, lane);
+  float* scratch = tG;
+  block_sum_vec<H>(db0, scratch, slab + H * k0w, wave, lane);
+  float* s1 = slab + H * k0w + H;
+  if constexpr (TOUT) {
+    for (int o = 0; o < NO; ++o) block_sum_vec<H>(dW1s[o], scratch, s1 + o * H, wave, lane);
+    // db1: summed over the workgroup's lanes in a fixed order
+    __syncthreads();
+#pragma unroll
+    for (int o = 0; o < 4; ++o) scratch[threadIdx.x * 4 + o] = (g == 0) ? db1s[o] : 0.f;
+    __syncthreads();
+    if ((int)threadIdx.x < NO) {
+      float sum = 0.f;
+      for (int t = 0; t < (int)blockDim.x; ++t) sum += scratch[t * 4 + threadIdx.x];
+      s1[NO * H + threadIdx.x] = sum;
+    }
+    __syncthreads();
+  } else {
+    dw_store<H, H>(acc1, s1, H, wave, lane);
+    block_sum_vec<H>(db1, scratch, s1 + H * H, wave, lane);
+    if (a.ln) {
+      block_sum_vec<H>(dga, scratch, s1 + H * H + H, wave, lane);
+      block_sum_vec<H>(dbe, scratch, s1 + H * H + 2 * H, wave, lane);
+    }
+  }
+}
+
+template <int H, int KIN, bool TIN, bool TOUT, bool BF>
+static hipError_t launch_mlp_bwd_t(const MlpBwdArgs& a, int grid, hipStream_t s) {
+  using C = MlpBwdCfg<H, KIN, TIN, TOUT, BF>;
+  const size_t lds = C::LDS;
+  (void)hipFuncSetAttribute((const void*)k_mlp_bwd<H, KIN, TIN, TOUT, BF>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)lds);
+  hipLaunchKernelGGL((k_mlp_bwd<H, KIN, TIN, TOUT, BF>), dim3(grid), dim3(256), lds, s, a);
+  return hipGetLastError();
+}
+
+template <int H, bool BF>
+static hipError_t launch_mlp_bwd_h(const MlpBwdArgs& a, int grid, hipStream_t s) {
+  const bool tin = a.k0 <= 4, tout = a.n_out < 16;
+  const int kin = a.k0 + a.k1;
+  if (tin && !tout) return launch_mlp_bwd_t<H, 4, true, false, BF>(a, grid, s);
+  if (!tin && kin == H && tout) return launch_mlp_bwd_t<H, H, false, true, BF>(a, grid, s);
+  if (!tin && kin == H && !tout) return launch_mlp_bwd_t<H, H, false, false, BF>(a, grid, s);
+  if (!tin && kin == 2 * H && !tout) return launch_mlp_bwd_t<H, 2 * H, false, false, BF>(a, grid, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_mlp_bwd(const MlpBwdArgs& a, int grid, hipStream_t s) {
+#define MP_CASE(HH) \
+  if (a.H == HH) return a.bf ? launch_mlp_bwd_h<HH, true>(a, grid, s) : launch_mlp_bwd_h<HH, false>(a, grid, s);
+  MP_CASE(32) MP_CASE(64) MP_CASE(128)
+#undef MP_CASE
+  return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------ slab reduction
+
+// dst[r][col0 + c] = sum over slabs (in slab order) of slab[src_off + r*cols + c].
+__global__ __launch_bounds__(256) void k_wreduce(ReduceSegs segs) {
+  const ReduceSeg S = segs.seg[blockIdx.y];
+  const int64_t n = (int64_t)S.rows * S.cols;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const float* p = S.part + S.src_off + e;
+    float s = 0.f;
+    for (int b = 0; b < S.n_slabs; ++b) s += p[(int64_t)b * S.slab];
+    const int64_t r = e / S.cols, c = e % S.cols;
+    S.dst[r * S.ld + S.col0 + c] = s;
+  }
+}
+
+hipError_t launch_wreduce(const ReduceSegs& segs, hipStream_t s) {
+  if (segs.n <= 0) return hipSuccess;
+  int64_t mx = 0;
+  for (int i = 0; i < segs.n; ++i) mx = std::max<int64_t>(mx, (int64_t)segs.seg[i].rows * segs.seg[i].cols);
+  const int grid = (int)std::min<int64_t>((mx + 255) / 256, 512);
+  hipLaunchKernelGGL(k_wreduce, dim3(grid, segs.n), dim3(256), 0, s, segs);
+  return hipGetLastError();
+}
+
+}  // namespace mp

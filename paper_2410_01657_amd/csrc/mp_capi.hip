@@ -1,0 +1,645 @@
+// C ABI entry points: validation, workspace layout and launch sequences.
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "mp_internal.hpp"
+#include "mp_device.hpp"
+#include "mp_kernels.hpp"
+
+using namespace mp;
+
+static thread_local char g_err[512] = "";
+
+int mp_fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+extern "C" int mp_abi_version(void) { return MP_ABI_VERSION; }
+extern "C" const char* mp_last_error(void) { return g_err; }
+
+extern "C" uint64_t mp_dev_graph_seal(const mp_dev_graph* g) {
+  if (!g) return 0;
+  uint64_t h = 1469598103934665603ull;  // FNV-1a over the four sizes
+  const int64_t v[4] = {g->n_rows, g->n_edges, g->n_groups, g->n_members};
+  const unsigned char* p = reinterpret_cast<const unsigned char*>(v);
+  for (size_t i = 0; i < sizeof(v); ++i) {
+    h ^= p[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+inline bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+int hip_check(hipError_t e, const char* where) {
+  if (e == hipSuccess) return MP_OK;
+  return mp_fail(MP_EHIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+int check_graph(const mp_dev_graph* g, bool need_rev) {
+  if (!g) return mp_fail(MP_EINVAL, "graph descriptor is NULL");
+  if (g->n_rows <= 0 || g->n_edges <= 0 || g->n_groups < 0 || g->n_members < 0)
+    return mp_fail(MP_EINVAL, "graph sizes must be positive (rows %lld, edges %lld)", (long long)g->n_rows,
+                   (long long)g->n_edges);
+  if (g->n_rows >= (int64_t(1) << 31) - 1 || g->n_edges >= (int64_t(1) << 31) - 1)
+    return mp_fail(MP_EINVAL, "graph has 2^31-1 or more rows or edges");
+  if (!g->rowptr || !g->recv || !g->col || !g->edge_mult || (need_rev && !g->rev))
+    return mp_fail(MP_EINVAL, "graph array is NULL");
+  if (g->n_groups > 0 && (!g->group_ptr || !g->member)) return mp_fail(MP_EINVAL, "halo plan array is NULL");
+  if (g->seal != mp_dev_graph_seal(g)) return mp_fail(MP_EPLAN, "graph descriptor seal does not match its sizes");
+  return MP_OK;
+}
+
+DevGraph dev_graph(const mp_dev_graph* g) {
+  DevGraph d;
+  d.n_rows = g->n_rows;
+  d.n_edges = g->n_edges;
+  d.n_groups = g->n_groups;
+  d.rowptr = g->rowptr;
+  d.recv = g->recv;
+  d.col = g->col;
+  d.rev = g->rev;
+  d.mult = g->edge_mult;
+  d.group_ptr = g->group_ptr;
+  d.member = g->member;
+  return d;
+}
+
+int check_cfg(const mp_layer_cfg* c) {
+  if (!c) return mp_fail(MP_EINVAL, "layer config is NULL");
+  if (c->H != 32 && c->H != 64 && c->H != 128) return mp_fail(MP_EINVAL, "H must be 32, 64 or 128 (got %d)", c->H);
+  if (c->gemm_dtype != MP_F32 && c->gemm_dtype != MP_BF16) return mp_fail(MP_EINVAL, "gemm_dtype must be MP_F32 or MP_BF16");
+  if (c->layernorm && !(c->ln_eps > 0.f)) return mp_fail(MP_EINVAL, "ln_eps must be positive");
+  return MP_OK;
+}
+
+// Grid sizes: persistent edge kernels give every wave at least ~64 edges.
+int edge_grid(int64_t E) { return (int)std::max<int64_t>(1, std::min<int64_t>(1024, E / 256)); }
+int edge_bwd_grid(int64_t E) { return (int)std::max<int64_t>(1, std::min<int64_t>(512, E / 256)); }
+int row_grid(int64_t N) { return (int)std::max<int64_t>(1, std::min<int64_t>(1024, (N + 63) / 64)); }
+int row_bwd_grid(int64_t N) { return (int)std::max<int64_t>(1, std::min<int64_t>(512, (N + 255) / 256)); }
+
+// Packed fragments of one layer, in this order:
+// W1a W1b | W1c W2 W2^T W1c^T | Wn1 Wn2 Wn2^T Wn1^T | [W1a|W1b]^T
+struct LayerFrags {
+  size_t f1, f2;  // bytes of an H x H and an H x 2H matrix
+  size_t proj, edge, node, gq, total;
+  LayerFrags(int H, bool bf) {
+    f1 = frag_bytes(H, H, bf);
+    f2 = frag_bytes(H, 2 * H, bf);
+    proj = 0;
+    edge = proj + 2 * f1;
+    node = edge + 4 * f1;
+    gq = node + 2 * f2 + 2 * f1;
+    total = align_up(gq + f2);
+  }
+};
+
+struct LayerWs {
+  LayerFrags fr;
+  size_t P, Q, a, gP, gh, part_e, part_n, part_q, total;
+  int ge, gbe, gn, gbn;
+  LayerWs(const mp_layer_cfg* c, const mp_dev_graph* g, bool bwd) : fr(c->H, c->gemm_dtype == MP_BF16) {
+    const size_t H = c->H, N = g->n_rows, E = g->n_edges;
+    ge = edge_grid(E);
+    gbe = edge_bwd_grid(E);
+    gn = row_grid(N);
+    gbn = row_bwd_grid(N);
+    size_t o = fr.total;
+    P = o; o = align_up(o + N * H * 4);
+    Q = o; o = align_up(o + N * H * 4);
+    a = o; o = align_up(o + N * H * 4);
+    gP = gh = part_e = part_n = part_q = 0;
+    if (bwd) {
+      gP = o; o = align_up(o + N * H * 4);
+      gh = o; o = align_up(o + E * H * 4);
+      part_e = o; o = align_up(o + (size_t)gbe * edge_slab(c->H) * 4);
+      part_n = o; o = align_up(o + (size_t)gbn * mlp_slab(c->H, 2 * c->H, c->H) * 4);
+      part_q = o; o = align_up(o + (size_t)gbn * gq_slab(c->H) * 4);
+    }
+    total = o;
+  }
+};
+
+PackView view(const float* p, int ld, int off, int trans) { return PackView{p, ld, off, trans}; }
+
+void add_job(PackJobs& J, int rows, int cols, PackView a, size_t dst, PackView b = PackView{nullptr, 0, 0, 0},
+             int split = -1) {
+  PackJob& j = J.job[J.n++];
+  j.a = a;
+  j.b = b.p ? b : a;
+  j.rows = rows;
+  j.cols = cols;
+  j.split = split < 0 ? cols : split;
+  j.dst_off = (int64_t)dst;
+}
+
+// Jobs for the layer fragments; the transposed ones only for the backward.
+PackJobs layer_jobs(const mp_layer_cfg* c, const mp_layer_params* p, const LayerFrags& F, bool bwd) {
+  const int H = c->H;
+  PackJobs J;
+  J.n = 0;
+  J.bf = c->gemm_dtype == MP_BF16;
+  add_job(J, H, H, view(p->We1, 3 * H, 0, 0), F.proj);                     // W1a
+  add_job(J, H, H, view(p->We1, 3 * H, H, 0), F.proj + F.f1);              // W1b
+  add_job(J, H, H, view(p->We1, 3 * H, 2 * H, 0), F.edge);                 // W1c
+  add_job(J, H, H, view(p->We2, H, 0, 0), F.edge + F.f1);                  // W2
+  add_job(J, H, 2 * H, view(p->Wn1, 2 * H, 0, 0), F.node);                 // Wn1
+  add_job(J, H, H, view(p->Wn2, H, 0, 0), F.node + F.f2);                  // Wn2
+  if (bwd) {
+    add_job(J, H, H, view(p->We2, H, 0, 1), F.edge + 2 * F.f1);            // W2^T
+    add_job(J, H, H, view(p->We1, 3 * H, 2 * H, 1), F.edge + 3 * F.f1);    // W1c^T
+    add_job(J, H, H, view(p->Wn2, H, 0, 1), F.node + F.f2 + F.f1);         // Wn2^T
+    add_job(J, 2 * H, H, view(p->Wn1, 2 * H, 0, 1), F.node + F.f2 + 2 * F.f1);  // Wn1^T
+    // [W1a | W1b]^T: element (k, c) = c < H ? We1[c][k] : We1[c-H][H+k]
+    add_job(J, H, 2 * H, view(p->We1, 3 * H, 0, 1), F.gq, view(p->We1, 3 * H, H, 1), H);
+  }
+  return J;
+}
+
+int check_layer_params(const mp_layer_cfg* c, const mp_layer_params* p) {
+  if (!p) return mp_fail(MP_EINVAL, "layer parameters are NULL");
+  const void* req[] = {p->We1, p->be1, p->We2, p->be2, p->Wn1, p->bn1, p->Wn2, p->bn2};
+  for (const void* q : req)
+    if (!q || !aligned16(q)) return mp_fail(MP_EINVAL, "a layer parameter is NULL or not 16-byte aligned");
+  if (c->layernorm) {
+    const void* lq[] = {p->ge, p->bge, p->gn, p->bgn};
+    for (const void* q : lq)
+      if (!q || !aligned16(q)) return mp_fail(MP_EINVAL, "a LayerNorm parameter is NULL or not 16-byte aligned");
+  }
+  return MP_OK;
+}
+
+char* ws_at(void* ws, size_t off) { return reinterpret_cast<char*>(ws) + off; }
+float* wsf(void* ws, size_t off) { return reinterpret_cast<float*>(ws_at(ws, off)); }
+
+}  // namespace
+
+// ------------------------------------------------------- launch profiling
+// Optional per-kernel timing: when enabled, every launch is bracketed by
+// two HIP events recorded on the launch's own stream.
+namespace {
+struct ProfRec {
+  std::string name;
+  hipEvent_t a, b;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof;
+std::vector<hipEvent_t> g_prof_pool;
+
+hipEvent_t prof_event() {
+  hipEvent_t e = nullptr;
+  if (!g_prof_pool.empty()) {
+    e = g_prof_pool.back();
+    g_prof_pool.pop_back();
+  } else if (hipEventCreate(&e) != hipSuccess) {
+    e = nullptr;
+  }
+  return e;
+}
+
+long prof_begin(const char* name, hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  if (!g_prof_on) return -1;
+  ProfRec r{name, prof_event(), prof_event()};
+  if (!r.a || !r.b) return -1;
+  (void)hipEventRecord(r.a, s);
+  g_prof.push_back(r);
+  return (long)g_prof.size() - 1;
+}
+
+void prof_end(long idx, hipStream_t s) {
+  if (idx < 0) return;
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  if (idx < (long)g_prof.size()) (void)hipEventRecord(g_prof[idx].b, s);
+}
+
+template <class F>
+int run(const char* name, hipStream_t s, F&& f) {
+  const long slot = prof_begin(name, s);
+  const hipError_t e = f();
+  prof_end(slot, s);
+  return hip_check(e, name);
+}
+}  // namespace
+
+extern "C" int mp_profile_enable(int on) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  for (auto& r : g_prof) {
+    g_prof_pool.push_back(r.a);
+    g_prof_pool.push_back(r.b);
+  }
+  g_prof.clear();
+  g_prof_on = on != 0;
+  return MP_OK;
+}
+
+extern "C" int mp_profile_read(const char* kernel, double* total_ms, int64_t* launches) {
+  if (!kernel || !total_ms || !launches) return mp_fail(MP_EINVAL, "mp_profile_read: NULL argument");
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  double t = 0.0;
+  int64_t n = 0;
+  for (auto& r : g_prof) {
+    if (r.name != kernel) continue;
+    float ms = 0.f;
+    if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess)
+      return mp_fail(MP_EHIP, "mp_profile_read: event query failed");
+    t += ms;
+    ++n;
+  }
+  *total_ms = t;
+  *launches = n;
+  return MP_OK;
+}
+
+extern "C" int mp_layer_workspace_size(const mp_layer_cfg* cfg, const mp_dev_graph* g, int backward, size_t* bytes) {
+  int rc;
+  if ((rc = check_cfg(cfg)) || (rc = check_graph(g, false))) return rc;
+  if (!bytes) return mp_fail(MP_EINVAL, "bytes is NULL");
+  *bytes = LayerWs(cfg, g, backward != 0).total;
+  return MP_OK;
+}
+
+extern "C" int mp_layer_forward(const mp_layer_cfg* cfg, const mp_layer_params* p, const mp_dev_graph* g,
+                                const float* x_in, const float* e_in, float* x_out, float* e_out, float* a_star_out,
+                                void* ws, size_t ws_bytes, mp_stream_t stream) {
+  int rc;
+  if ((rc = check_cfg(cfg)) || (rc = check_graph(g, false)) || (rc = check_layer_params(cfg, p))) return rc;
+  if (!x_in || !e_in || !x_out || !e_out || !ws) return mp_fail(MP_EINVAL, "mp_layer_forward: NULL buffer");
+  if (!aligned16(x_in) || !aligned16(e_in) || !aligned16(x_out) || !aligned16(e_out) || !aligned16(ws) ||
+      (a_star_out && !aligned16(a_star_out)))
+    return mp_fail(MP_EINVAL, "mp_layer_forward: buffers must be 16-byte aligned");
+  if (x_out == x_in || e_out == e_in || (const float*)e_out == x_in || (const float*)x_out == e_in)
+    return mp_fail(MP_EINVAL, "mp_layer_forward: outputs must not alias inputs");
+  const LayerWs W(cfg, g, false);
+  if (ws_bytes < W.total) return mp_fail(MP_ENOMEM, "mp_layer_forward: workspace %zu < %zu bytes", ws_bytes, W.total);
+  const int H = cfg->H;
+  const bool bf = cfg->gemm_dtype == MP_BF16;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const DevGraph d = dev_graph(g);
+  float* P = wsf(ws, W.P);
+  float* Q = wsf(ws, W.Q);
+  float* a = a_star_out ? a_star_out : wsf(ws, W.a);
+  if ((rc = run("pack", s, [&] { return launch_pack(layer_jobs(cfg, p, W.fr, false), ws, s); }))) return rc;
+  if ((rc = run("proj", s, [&] { return launch_proj(H, bf, d, x_in, ws_at(ws, W.fr.proj), p->be1, P, Q, W.gn, s); }))) return rc;
+  if ((rc = run("edge_fwd", s, [&] { return launch_edge_fwd(H, cfg->layernorm != 0, bf, d, P, Q, e_in, ws_at(ws, W.fr.edge), p->be2,
+                                      p->ge, p->bge, cfg->ln_eps, e_out, a, W.ge, s); })))
+    return rc;
+  if (cfg->halo && (rc = run("halo", s, [&] { return launch_halo(H, d, a, s); }))) return rc;
+  MlpFwdArgs m{};
+  m.n_rows = g->n_rows;
+  m.src0 = a;
+  m.src1 = x_in;
+  m.resid = x_in;
+  m.k0 = H;
+  m.k1 = H;
+  m.H = H;
+  m.n_out = H;
+  m.ln = cfg->layernorm;
+  m.bf = bf;
+  m.b0 = p->bn1;
+  m.b1 = p->bn2;
+  m.lng = p->gn;
+  m.lnb = p->bgn;
+  m.eps = cfg->ln_eps;
+  m.frag0 = ws_at(ws, W.fr.node);
+  m.frag1 = ws_at(ws, W.fr.node + W.fr.f2);
+  m.out = x_out;
+  return run("node_fwd", s, [&] { return launch_mlp_fwd(m, W.gn, s); });
+}
+
+extern "C" int mp_layer_backward(const mp_layer_cfg* cfg, const mp_layer_params* p, const mp_dev_graph* g,
+                                 const float* x_in, const float* e_in, const float* a_star, const float* g_x_out,
+                                 const float* g_e_out, float* g_x_in, float* g_e_in, const mp_layer_grads* gr,
+                                 void* ws, size_t ws_bytes, mp_stream_t stream) {
+  int rc;
+  if ((rc = check_cfg(cfg)) || (rc = check_graph(g, true)) || (rc = check_layer_params(cfg, p))) return rc;
+  if (!x_in || !e_in || !a_star || !g_x_out || !g_x_in || !g_e_in || !gr || !ws)
+    return mp_fail(MP_EINVAL, "mp_layer_backward: NULL buffer");
+  const void* al[] = {x_in, e_in, a_star, g_x_out, g_x_in, g_e_in, ws};
+  for (const void* q : al)
+    if (!aligned16(q)) return mp_fail(MP_EINVAL, "mp_layer_backward: buffers must be 16-byte aligned");
+  if (g_e_out && !aligned16(g_e_out)) return mp_fail(MP_EINVAL, "mp_layer_backward: g_e_out not aligned");
+  float* gw[] = {gr->We1, gr->be1, gr->We2, gr->be2, gr->Wn1, gr->bn1, gr->Wn2, gr->bn2};
+  for (float* q : gw)
+    if (!q) return mp_fail(MP_EINVAL, "mp_layer_backward: a gradient buffer is NULL");
+  if (cfg->layernorm && (!gr->ge || !gr->bge || !gr->gn || !gr->bgn))
+    return mp_fail(MP_EINVAL, "mp_layer_backward: a LayerNorm gradient buffer is NULL");
+  if ((const float*)g_x_in == g_x_out || (const float*)g_e_in == g_e_out || (const float*)g_e_in == e_in ||
+      (const float*)g_x_in == x_in)
+    return mp_fail(MP_EINVAL, "mp_layer_backward: gradient outputs must not alias inputs");
+  const LayerWs W(cfg, g, true);
+  if (ws_bytes < W.total) return mp_fail(MP_ENOMEM, "mp_layer_backward: workspace %zu < %zu bytes", ws_bytes, W.total);
+  const int H = cfg->H;
+  const bool bf = cfg->gemm_dtype == MP_BF16;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const DevGraph d = dev_graph(g);
+  float* P = wsf(ws, W.P);
+  float* Q = wsf(ws, W.Q);
+  float* ga = wsf(ws, W.a);
+  float* gP = wsf(ws, W.gP);
+  float* gh = wsf(ws, W.gh);
+  if ((rc = run("pack", s, [&] { return launch_pack(layer_jobs(cfg, p, W.fr, true), ws, s); }))) return rc;
+  if ((rc = run("proj", s, [&] { return launch_proj(H, bf, d, x_in, ws_at(ws, W.fr.proj), p->be1, P, Q, W.gn, s); }))) return rc;
+  // node MLP adjoint: g_a* and g_x (residual + node-MLP part)
+  MlpBwdArgs m{};
+  m.n_rows = g->n_rows;
+  m.src0 = a_star;
+  m.src1 = x_in;
+  m.k0 = H;
+  m.k1 = H;
+  m.H = H;
+  m.n_out = H;
+  m.ln = cfg->layernorm;
+  m.bf = bf;
+  m.resid = 1;
+  m.b0 = p->bn1;
+  m.b1 = p->bn2;
+  m.lng = p->gn;
+  m.lnb = p->bgn;
+  m.eps = cfg->ln_eps;
+  m.frag0 = ws_at(ws, W.fr.node);
+  m.frag1 = ws_at(ws, W.fr.node + W.fr.f2);
+  m.frag1t = ws_at(ws, W.fr.node + W.fr.f2 + W.fr.f1);
+  m.frag0t = ws_at(ws, W.fr.node + W.fr.f2 + 2 * W.fr.f1);
+  m.g_out = g_x_out;
+  m.g_src0 = ga;
+  m.g_src1 = g_x_in;
+  m.g_add1 = g_x_out;
+  m.part = wsf(ws, W.part_n);
+  m.slab = mlp_slab(H, 2 * H, H);
+  if ((rc = run("node_bwd", s, [&] { return launch_mlp_bwd(m, W.gbn, s); }))) return rc;
+  // the halo sum is symmetric: its adjoint is the same group sum
+  if (cfg->halo && (rc = run("halo_adj", s, [&] { return launch_halo(H, d, ga, s); }))) return rc;
+  EdgeBwdArgs eb{};
+  eb.g = d;
+  eb.H = H;
+  eb.ln = cfg->layernorm;
+  eb.bf = bf;
+  eb.P = P;
+  eb.Q = Q;
+  eb.e_in = e_in;
+  eb.g_e_out = g_e_out;
+  eb.g_a = ga;
+  eb.frag = ws_at(ws, W.fr.edge);
+  eb.b2 = p->be2;
+  eb.lng = p->ge;
+  eb.lnb = p->bge;
+  eb.eps = cfg->ln_eps;
+  eb.g_e_in = g_e_in;
+  eb.g_h = gh;
+  eb.g_P = gP;
+  eb.part = wsf(ws, W.part_e);
+  eb.slab = edge_slab(H);
+  if ((rc = run("edge_bwd", s, [&] { return launch_edge_bwd(eb, W.gbe, s); }))) return rc;
+  GqArgs q{};
+  q.g = d;
+  q.H = H;
+  q.bf = bf;
+  q.x = x_in;
+  q.g_P = gP;
+  q.g_h = gh;
+  q.frag_abt = ws_at(ws, W.fr.gq);
+  q.g_x = g_x_in;
+  q.part = wsf(ws, W.part_q);
+  q.slab = gq_slab(H);
+  if ((rc = run("gq", s, [&] { return launch_gq(q, W.gbn, s); }))) return rc;
+  // weight gradients: fixed-order sums of the workgroup slabs
+  ReduceSegs R;
+  R.n = 0;
+  auto seg = [&](const float* part, int n_slabs, int64_t slab, int64_t off, int rows, int cols, float* dst, int ld,
+                 int col0) { R.seg[R.n++] = ReduceSeg{part, n_slabs, slab, off, rows, cols, dst, ld, col0}; };
+  const float* pn = wsf(ws, W.part_n);
+  const int64_t sn = mlp_slab(H, 2 * H, H);
+  seg(pn, W.gbn, sn, 0, H, 2 * H, gr->Wn1, 2 * H, 0);
+  seg(pn, W.gbn, sn, 2 * H * H, 1, H, gr->bn1, H, 0);
+  seg(pn, W.gbn, sn, 2 * H * H + H, H, H, gr->Wn2, H, 0);
+  seg(pn, W.gbn, sn, 3 * H * H + H, 1, H, gr->bn2, H, 0);
+  if (cfg->layernorm) {
+    seg(pn, W.gbn, sn, 3 * H * H + 2 * H, 1, H, gr->gn, H, 0);
+    seg(pn, W.gbn, sn, 3 * H * H + 3 * H, 1, H, gr->bgn, H, 0);
+  }
+  const float* pe = wsf(ws, W.part_e);
+  const int64_t se = edge_slab(H);
+  seg(pe, W.gbe, se, 0, H, H, gr->We1, 3 * H, 2 * H);
+  seg(pe, W.gbe, se, H * H, H, H, gr->We2, H, 0);
+  seg(pe, W.gbe, se, 2 * H * H, 1, H, gr->be2, H, 0);
+  if (cfg->layernorm) {
+    seg(pe, W.gbe, se, 2 * H * H + H, 1, H, gr->ge, H, 0);
+    seg(pe, W.gbe, se, 2 * H * H + 2 * H, 1, H, gr->bge, H, 0);
+  }
+  const float* pq = wsf(ws, W.part_q);
+  const int64_t sq = gq_slab(H);
+  seg(pq, W.gbn, sq, 0, H, H, gr->We1, 3 * H, 0);
+  seg(pq, W.gbn, sq, H * H, H, H, gr->We1, 3 * H, H);
+  seg(pq, W.gbn, sq, 2 * H * H, 1, H, gr->be1, H, 0);
+  return run("wreduce", s, [&] { return launch_wreduce(R, s); });
+}
+
+// ------------------------------------------------------------ row MLPs
+
+namespace {
+
+int check_mlp_cfg(const mp_mlp_cfg* c) {
+  if (!c) return mp_fail(MP_EINVAL, "mlp config is NULL");
+  if (c->H != 32 && c->H != 64 && c->H != 128) return mp_fail(MP_EINVAL, "H must be 32, 64 or 128 (got %d)", c->H);
+  if (!((c->n_in >= 1 && c->n_in <= 4) || c->n_in == c->H))
+    return mp_fail(MP_EINVAL, "n_in must be 1..4 or H (got %d)", c->n_in);
+  if (!((c->n_out >= 1 && c->n_out <= 4) || c->n_out == c->H))
+    return mp_fail(MP_EINVAL, "n_out must be 1..4 or H (got %d)", c->n_out);
+  if (c->n_in <= 4 && c->n_out <= 4) return mp_fail(MP_EINVAL, "small input and small output together are not supported");
+  if (c->layernorm && c->n_out != c->H) return mp_fail(MP_EINVAL, "LayerNorm needs n_out == H");
+  if (c->layernorm && !(c->ln_eps > 0.f)) return mp_fail(MP_EINVAL, "ln_eps must be positive");
+  if (c->gemm_dtype != MP_F32 && c->gemm_dtype != MP_BF16) return mp_fail(MP_EINVAL, "bad gemm_dtype");
+  return MP_OK;
+}
+
+struct MlpWs {
+  size_t f0, f1, fr0, fr1, fr1t, fr0t, part, total;
+  int grid, gridb;
+  MlpWs(const mp_mlp_cfg* c, int64_t n, bool bwd) {
+    const bool bf = c->gemm_dtype == MP_BF16;
+    f0 = c->n_in > 4 ? frag_bytes(c->H, c->n_in, bf) : 0;
+    f1 = c->n_out > 4 ? frag_bytes(c->H, c->H, bf) : 0;
+    size_t o = 0;
+    fr0 = o; o = align_up(o + f0);
+    fr1 = o; o = align_up(o + f1);
+    fr1t = o; o = align_up(o + (bwd ? f1 : 0));
+    fr0t = o; o = align_up(o + (bwd ? f0 : 0));
+    grid = row_grid(n);
+    gridb = row_bwd_grid(n);
+    part = o;
+    if (bwd) o = align_up(o + (size_t)gridb * mlp_slab(c->H, c->n_in, c->n_out) * 4);
+    total = std::max<size_t>(o, kAlign);
+  }
+};
+
+PackJobs mlp_jobs(const mp_mlp_cfg* c, const mp_mlp_params* p, const MlpWs& W, bool bwd) {
+  PackJobs J;
+  J.n = 0;
+  J.bf = c->gemm_dtype == MP_BF16;
+  const int H = c->H;
+  if (W.f0) add_job(J, H, c->n_in, view(p->W0, c->n_in, 0, 0), W.fr0);
+  if (W.f1) add_job(J, H, H, view(p->W1, H, 0, 0), W.fr1);
+  if (bwd && W.f1) add_job(J, H, H, view(p->W1, H, 0, 1), W.fr1t);
+  if (bwd && W.f0) add_job(J, c->n_in, H, view(p->W0, c->n_in, 0, 1), W.fr0t);
+  return J;
+}
+
+int check_mlp_params(const mp_mlp_cfg* c, const mp_mlp_params* p) {
+  if (!p || !p->W0 || !p->b0 || !p->W1 || !p->b1) return mp_fail(MP_EINVAL, "mlp parameter is NULL");
+  if (!aligned16(p->b0) || !aligned16(p->W1) || !aligned16(p->W0) || !aligned16(p->b1))
+    return mp_fail(MP_EINVAL, "mlp parameters must be 16-byte aligned");
+  if (c->layernorm && (!p->ln_g || !p->ln_b || !aligned16(p->ln_g) || !aligned16(p->ln_b)))
+    return mp_fail(MP_EINVAL, "LayerNorm parameter is NULL or unaligned");
+  return MP_OK;
+}
+
+}  // namespace
+
+extern "C" int mp_mlp_workspace_size(const mp_mlp_cfg* cfg, int64_t n_rows, int backward, size_t* bytes) {
+  int rc;
+  if ((rc = check_mlp_cfg(cfg))) return rc;
+  if (n_rows <= 0 || !bytes) return mp_fail(MP_EINVAL, "mp_mlp_workspace_size: bad n_rows or bytes");
+  *bytes = MlpWs(cfg, n_rows, backward != 0).total;
+  return MP_OK;
+}
+
+extern "C" int mp_mlp_forward(const mp_mlp_cfg* cfg, const mp_mlp_params* p, int64_t n_rows, const float* in,
+                              float* out, void* ws, size_t ws_bytes, mp_stream_t stream) {
+  int rc;
+  if ((rc = check_mlp_cfg(cfg)) || (rc = check_mlp_params(cfg, p))) return rc;
+  if (n_rows <= 0 || !in || !out || !ws) return mp_fail(MP_EINVAL, "mp_mlp_forward: bad size or NULL buffer");
+  if (!aligned16(in) || !aligned16(out) || !aligned16(ws)) return mp_fail(MP_EINVAL, "mp_mlp_forward: unaligned buffer");
+  if ((const float*)out == in) return mp_fail(MP_EINVAL, "mp_mlp_forward: out must not alias in");
+  const MlpWs W(cfg, n_rows, false);
+  if (ws_bytes < W.total) return mp_fail(MP_ENOMEM, "mp_mlp_forward: workspace %zu < %zu bytes", ws_bytes, W.total);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if ((rc = run("pack", s, [&] { return launch_pack(mlp_jobs(cfg, p, W, false), ws, s); }))) return rc;
+  MlpFwdArgs m{};
+  m.n_rows = n_rows;
+  m.src0 = in;
+  m.k0 = cfg->n_in;
+  m.k1 = 0;
+  m.H = cfg->H;
+  m.n_out = cfg->n_out;
+  m.ln = cfg->layernorm;
+  m.bf = cfg->gemm_dtype == MP_BF16;
+  m.W0 = p->W0;
+  m.b0 = p->b0;
+  m.W1 = p->W1;
+  m.b1 = p->b1;
+  m.lng = p->ln_g;
+  m.lnb = p->ln_b;
+  m.eps = cfg->ln_eps;
+  m.frag0 = ws_at(ws, W.fr0);
+  m.frag1 = ws_at(ws, W.fr1);
+  m.out = out;
+  return run("mlp_fwd", s, [&] { return launch_mlp_fwd(m, W.grid, s); });
+}
+
+extern "C" int mp_mlp_backward(const mp_mlp_cfg* cfg, const mp_mlp_params* p, int64_t n_rows, const float* in,
+                               const float* g_out, float* g_in, const mp_mlp_grads* gr, void* ws, size_t ws_bytes,
+                               mp_stream_t stream) {
+  int rc;
+  if ((rc = check_mlp_cfg(cfg)) || (rc = check_mlp_params(cfg, p))) return rc;
+  if (n_rows <= 0 || !in || !g_out || !gr || !ws) return mp_fail(MP_EINVAL, "mp_mlp_backward: bad size or NULL buffer");
+  if (!gr->W0 || !gr->b0 || !gr->W1 || !gr->b1 || (cfg->layernorm && (!gr->ln_g || !gr->ln_b)))
+    return mp_fail(MP_EINVAL, "mp_mlp_backward: a gradient buffer is NULL");
+  if (!aligned16(in) || !aligned16(g_out) || !aligned16(ws) || (g_in && !aligned16(g_in)))
+    return mp_fail(MP_EINVAL, "mp_mlp_backward: unaligned buffer");
+  if (g_in && cfg->n_in <= 4) return mp_fail(MP_EINVAL, "mp_mlp_backward: no input gradient for n_in <= 4");
+  if (g_in && ((const float*)g_in == g_out || (const float*)g_in == in))
+    return mp_fail(MP_EINVAL, "mp_mlp_backward: g_in must not alias inputs");
+  const MlpWs W(cfg, n_rows, true);
+  if (ws_bytes < W.total) return mp_fail(MP_ENOMEM, "mp_mlp_backward: workspace %zu < %zu bytes", ws_bytes, W.total);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if ((rc = run("pack", s, [&] { return launch_pack(mlp_jobs(cfg, p, W, true), ws, s); }))) return rc;
+  const int H = cfg->H;
+  MlpBwdArgs m{};
+  m.n_rows = n_rows;
+  m.src0 = in;
+  m.k0 = cfg->n_in;
+  m.k1 = 0;
+  m.H = H;
+  m.n_out = cfg->n_out;
+  m.ln = cfg->layernorm;
+  m.bf = cfg->gemm_dtype == MP_BF16;
+  m.W0 = p->W0;
+  m.b0 = p->b0;
+  m.W1 = p->W1;
+  m.b1 = p->b1;
+  m.lng = p->ln_g;
+  m.lnb = p->ln_b;
+  m.eps = cfg->ln_eps;
+  m.frag0 = ws_at(ws, W.fr0);
+  m.frag1 = ws_at(ws, W.fr1);
+  m.frag1t = ws_at(ws, W.fr1t);
+  m.frag0t = g_in ? ws_at(ws, W.fr0t) : nullptr;
+  m.g_out = g_out;
+  m.g_src0 = g_in;
+  m.part = wsf(ws, W.part);
+  m.slab = mlp_slab(H, cfg->n_in, cfg->n_out);
+  if ((rc = run("mlp_bwd", s, [&] { return launch_mlp_bwd(m, W.gridb, s); }))) return rc;
+  ReduceSegs R;
+  R.n = 0;
+  const float* pp = wsf(ws, W.part);
+  const int kin = cfg->n_in, no = cfg->n_out;
+  const int64_t sl = m.slab;
+  R.seg[R.n++] = ReduceSeg{pp, W.gridb, sl, 0, H, kin, gr->W0, kin, 0};
+  R.seg[R.n++] = ReduceSeg{pp, W.gridb, sl, (int64_t)H * kin, 1, H, gr->b0, H, 0};
+  R.seg[R.n++] = ReduceSeg{pp, W.gridb, sl, (int64_t)H * kin + H, no, H, gr->W1, H, 0};
+  R.seg[R.n++] = ReduceSeg{pp, W.gridb, sl, (int64_t)H * kin + H + (int64_t)no * H, 1, no, gr->b1, no, 0};
+  if (cfg->layernorm) {
+    const int64_t o = (int64_t)H * kin + H + (int64_t)no * H + no;
+    R.seg[R.n++] = ReduceSeg{pp, W.gridb, sl, o, 1, H, gr->ln_g, H, 0};
+    R.seg[R.n++] = ReduceSeg{pp, W.gridb, sl, o + H, 1, H, gr->ln_b, H, 0};
+  }
+  return run("wreduce", s, [&] { return launch_wreduce(R, s); });
+}
+
+// ------------------------------------------------------- edge inputs, loss
+
+extern "C" int mp_edge_inputs(const mp_dev_graph* g, const double* row_pos, float* e0, mp_stream_t stream) {
+  int rc;
+  if ((rc = check_graph(g, false))) return rc;
+  if (!row_pos || !e0 || !aligned16(e0)) return mp_fail(MP_EINVAL, "mp_edge_inputs: NULL or unaligned buffer");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  return run("edge_inputs", s, [&] { return launch_edge_inputs(dev_graph(g), row_pos, e0, s); });
+}
+
+static int loss_parts(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(256, (n + 4095) / 4096)); }
+
+extern "C" int mp_consistent_mse_workspace_size(int64_t n_rows, size_t* bytes) {
+  if (n_rows <= 0 || !bytes) return mp_fail(MP_EINVAL, "mp_consistent_mse_workspace_size: bad arguments");
+  *bytes = align_up((size_t)(2 * loss_parts(n_rows) + 2) * sizeof(double));
+  return MP_OK;
+}
+
+extern "C" int mp_consistent_mse(int64_t n_rows, int32_t F, const float* Y, const float* T, const uint8_t* node_mult,
+                                 float* loss, float* gY, void* ws, size_t ws_bytes, mp_stream_t stream) {
+  if (n_rows <= 0 || F <= 0 || F > 64 || !Y || !T || !node_mult || !loss || !ws)
+    return mp_fail(MP_EINVAL, "mp_consistent_mse: bad size or NULL buffer");
+  size_t need;
+  mp_consistent_mse_workspace_size(n_rows, &need);
+  if (ws_bytes < need) return mp_fail(MP_ENOMEM, "mp_consistent_mse: workspace %zu < %zu bytes", ws_bytes, need);
+  if ((reinterpret_cast<uintptr_t>(ws) & 7) != 0) return mp_fail(MP_EINVAL, "mp_consistent_mse: workspace unaligned");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  return run("loss", s, [&] {
+    return launch_loss(n_rows, F, Y, T, node_mult, reinterpret_cast<double*>(ws), loss_parts(n_rows), loss, gY, s);
+  });
+}

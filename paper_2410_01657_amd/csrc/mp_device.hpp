@@ -1,0 +1,241 @@
+// Device building blocks for the message-passing kernels (gfx950, wave64).
+//
+// Row-block layout.  A wave works on blocks of 16 rows (edges or nodes).
+// Lane l handles row j = l % 16 of the block and lane group g = l / 16.  For
+// a feature vector of width W (a multiple of 16) the lane holds W/4 values:
+//   v[4*b + r]  <->  feature 16*b + 4*g + r      (b < W/16, r < 4)
+// so the four lanes of a row together hold the whole row, each lane as W/16
+// contiguous float4 chunks.  This is exactly the accumulator layout of the
+// 16x16 MFMA instructions when the product is computed transposed
+// (output features x rows), which lets the output of one Linear feed the
+// next one with no data movement: the K ordering of each product is permuted
+// to match, and the weight fragments are packed in that order.
+//
+// Weight fragments.  A product out[f][row] = sum_k A[f][k] in[k][row] with
+// A of shape [M][K] is stored as
+//   FP32 (v_mfma_f32_16x16x4f32):  frag[(mb*(K/4) + s)*64 + lane]
+//        = A[16*mb + lane%16][16*(s/4) + 4*(lane/16) + s%4]
+//   BF16 (v_mfma_f32_16x16x32_bf16): frag16[(mb*(K/32) + t)*64 + lane] =
+//        8 values q = 0..7 of A[16*mb + lane%16][32*t + 16*(q/4) + 4*(lane/16) + q%4]
+// and the input operand of step s (FP32) is in[s], of step t (BF16) is
+// in[8t .. 8t+7], directly in the row-block layout.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mp {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+// ------------------------------------------------------------------ loads
+
+// Load the row-block slice of a W-wide row (ptr = start of the row).
+template <int W>
+__device__ __forceinline__ void load_row(const float* __restrict__ ptr, int g, float (&v)[W / 4]) {
+#pragma unroll
+  for (int b = 0; b < W / 16; ++b) {
+    const float4 t = *reinterpret_cast<const float4*>(ptr + 16 * b + 4 * g);
+    v[4 * b + 0] = t.x;
+    v[4 * b + 1] = t.y;
+    v[4 * b + 2] = t.z;
+    v[4 * b + 3] = t.w;
+  }
+}
+
+template <int W>
+__device__ __forceinline__ void store_row(float* __restrict__ ptr, int g, const float (&v)[W / 4]) {
+#pragma unroll
+  for (int b = 0; b < W / 16; ++b)
+    *reinterpret_cast<float4*>(ptr + 16 * b + 4 * g) =
+        make_float4(v[4 * b + 0], v[4 * b + 1], v[4 * b + 2], v[4 * b + 3]);
+}
+
+// Per-feature vector (bias, LayerNorm gain) in row-block layout.
+template <int W>
+__device__ __forceinline__ void load_vec(const float* __restrict__ p, int g, float (&v)[W / 4]) {
+  load_row<W>(p, g, v);
+}
+
+// ------------------------------------------------------------- GEMMs
+
+// acc[f] += sum_k A[f][k] in[k]  (A packed as FP32 fragments; MB = M/16,
+// KB = K/16).  Independent output blocks are interleaved so consecutive
+// MFMAs do not depend on each other.
+template <int MB, int KB>
+__device__ __forceinline__ void gemm_f32(const float* __restrict__ frag, const float (&in)[4 * KB],
+                                         float (&acc)[4 * MB], int lane) {
+  v4f c[MB];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb) c[mb] = v4f{acc[4 * mb], acc[4 * mb + 1], acc[4 * mb + 2], acc[4 * mb + 3]};
+#pragma unroll
+  for (int s = 0; s < 4 * KB; ++s) {
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+      c[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(frag[(mb * 4 * KB + s) * 64 + lane], in[s], c[mb], 0, 0, 0);
+  }
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb) {
+    acc[4 * mb] = c[mb][0];
+    acc[4 * mb + 1] = c[mb][1];
+    acc[4 * mb + 2] = c[mb][2];
+    acc[4 * mb + 3] = c[mb][3];
+  }
+}
+
+__device__ __forceinline__ v8bf to_bf8(const float* x) {
+  v8bf r;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) r[q] = (__bf16)x[q];  // round to nearest even
+  return r;
+}
+
+template <int MB, int KB>
+__device__ __forceinline__ void gemm_bf16(const uint4* __restrict__ frag, const float (&in)[4 * KB],
+                                          float (&acc)[4 * MB], int lane) {
+  static_assert(KB % 2 == 0, "BF16 products need K to be a multiple of 32");
+  constexpr int T = KB / 2;
+  v4f c[MB];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb) c[mb] = v4f{acc[4 * mb], acc[4 * mb + 1], acc[4 * mb + 2], acc[4 * mb + 3]};
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    const v8bf b = to_bf8(&in[8 * t]);
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+      const uint4 a = frag[(mb * T + t) * 64 + lane];
+      c[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a), b, c[mb], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb) {
+    acc[4 * mb] = c[mb][0];
+    acc[4 * mb + 1] = c[mb][1];
+    acc[4 * mb + 2] = c[mb][2];
+    acc[4 * mb + 3] = c[mb][3];
+  }
+}
+
+// Dispatch on the GEMM operand type.  frag points at the fragments of one
+// matrix (FP32: M*K floats; BF16: M*K bf16 values).
+template <bool BF, int MB, int KB>
+__device__ __forceinline__ void gemm(const void* frag, const float (&in)[4 * KB], float (&acc)[4 * MB], int lane) {
+  if constexpr (BF)
+    gemm_bf16<MB, KB>(reinterpret_cast<const uint4*>(frag), in, acc, lane);
+  else
+    gemm_f32<MB, KB>(reinterpret_cast<const float*>(frag), in, acc, lane);
+}
+
+// Bytes of the packed fragments of an M x K matrix.
+__host__ __device__ constexpr size_t frag_bytes(int M, int K, bool bf) { return size_t(M) * K * (bf ? 2 : 4); }
+
+// --------------------------------------------------- elementwise helpers
+
+__device__ __forceinline__ float elu(float z) { return z > 0.f ? z : expm1f(z); }
+__device__ __forceinline__ float elu_deriv(float z) { return z > 0.f ? 1.f : expf(z); }
+
+// Sum over the four lanes that share a row (lane groups g = 0..3).
+__device__ __forceinline__ float row_sum(float s) {
+  s += __shfl_xor(s, 16);
+  s += __shfl_xor(s, 32);
+  return s;
+}
+
+// LayerNorm statistics (biased variance) of a W-wide row in row-block layout.
+template <int W>
+__device__ __forceinline__ void ln_stats(const float (&v)[W / 4], float eps, float& mean, float& rstd) {
+  float s = 0.f;
+#pragma unroll
+  for (int i = 0; i < W / 4; ++i) s += v[i];
+  mean = row_sum(s) * (1.f / W);
+  float q = 0.f;
+#pragma unroll
+  for (int i = 0; i < W / 4; ++i) {
+    const float d = v[i] - mean;
+    q += d * d;
+  }
+  const float var = row_sum(q) * (1.f / W);
+  rstd = 1.f / sqrtf(var + eps);
+}
+
+// ------------------------------------------- segmented sums over 16 lanes
+
+// DPP row_shr:n within each 16-lane row; lanes j < n read 0.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, 0xf, 0xf, true));
+}
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xf, 0xf, true);
+}
+constexpr int DPP_ROW_SHR1 = 0x111, DPP_ROW_SHR2 = 0x112, DPP_ROW_SHR4 = 0x114, DPP_ROW_SHR8 = 0x118;
+constexpr int DPP_ROW_ROR1 = 0x121;  // lane j reads lane (j-1) mod 16
+
+// Inclusive segmented scan over the 16 lanes j of each lane group.  key
+// identifies the segment (equal keys are contiguous in j) and must be
+// nonzero, because lanes shifted in from outside the row read key 0.
+template <int N>
+__device__ __forceinline__ void seg_scan16(float (&v)[N], int key) {
+#define MP_SEG_STEP(CTRL)                                     \
+  {                                                           \
+    const bool same = dpp_i<CTRL>(key) == key;                \
+    _Pragma("unroll") for (int i = 0; i < N; ++i) {           \
+      const float t = dpp_f<CTRL>(v[i]);                      \
+      v[i] += same ? t : 0.f;                                 \
+    }                                                         \
+  }
+  MP_SEG_STEP(DPP_ROW_SHR1)
+  MP_SEG_STEP(DPP_ROW_SHR2)
+  MP_SEG_STEP(DPP_ROW_SHR4)
+  MP_SEG_STEP(DPP_ROW_SHR8)
+#undef MP_SEG_STEP
+}
+
+// Value of lane 15 of the same lane group, delivered to lane 0 (and lane
+// j+1 receives lane j, which callers ignore).
+__device__ __forceinline__ float from_prev_lane(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), DPP_ROW_ROR1, 0xf, 0xf, false));
+}
+__device__ __forceinline__ int from_prev_lane_i(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, DPP_ROW_ROR1, 0xf, 0xf, false);
+}
+
+// ----------------------------------------- static wave schedules over rows
+
+// Split rows [0, n_rows) into n_parts contiguous ranges with about equal
+// edge counts: part p starts at the first row whose first edge index is at
+// least floor(p * E / n_parts); the last part ends at n_rows.
+__device__ __forceinline__ int64_t lower_bound_i32(const int32_t* __restrict__ a, int64_t n, int64_t key) {
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if ((int64_t)a[mid] < key) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+__device__ __forceinline__ void part_rows(const int32_t* __restrict__ rowptr, int64_t n_rows, int64_t n_parts,
+                                          int64_t p, int64_t& r0, int64_t& r1) {
+  const int64_t E = rowptr[n_rows];
+  r0 = (p == 0) ? 0 : lower_bound_i32(rowptr, n_rows + 1, (p * E) / n_parts);
+  r1 = (p + 1 >= n_parts) ? n_rows : lower_bound_i32(rowptr, n_rows + 1, ((p + 1) * E) / n_parts);
+  if (r0 > n_rows) r0 = n_rows;
+  if (r1 > n_rows) r1 = n_rows;
+  if (r1 < r0) r1 = r0;
+}
+
+// XCD-aware block numbering: the dispatcher hands consecutive workgroups to
+// the 8 XCDs in turn; renumber so that each XCD gets one contiguous eighth
+// of the work (its L2 then sees neighbouring rows).
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
+  const int64_t per = (nb + 7) / 8;
+  const int64_t x = b % 8, i = b / 8;
+  const int64_t full = nb % 8 == 0 ? 8 : nb % 8;  // XCDs that get `per` blocks
+  // blocks dealt round robin: XCD x receives per or per-1 blocks
+  const int64_t start = x < full ? x * per : full * per + (x - full) * (per - 1);
+  return start + i;
+}
+
+}  // namespace mp

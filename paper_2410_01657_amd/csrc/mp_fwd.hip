@@ -1,0 +1,518 @@
+// Forward kernels of the consistent message-passing layer and its model
+// wrapper: weight packing, node projections, the fused edge update with the
+// 1/d-weighted aggregation (Eq. 4a-b), the in-device halo sum (Eq. 4c-d),
+// row MLPs (node update Eq. 4e, encoders, decoder), edge inputs and loss
+// (Eq. 5-6).
+#include <algorithm>
+
+#include "mp_device.hpp"
+#include "mp_kernels.hpp"
+
+namespace mp {
+
+constexpr size_t kRowMlpLdsBudget = 100 * 1024;
+constexpr size_t kEdgeLdsBudget = 128 * 1024;
+
+// --------------------------------------------------------------- packing
+
+__device__ __forceinline__ float view_elem(const PackView& v, int r, int c) {
+  return v.trans ? v.p[(int64_t)c * v.ld + v.off + r] : v.p[(int64_t)r * v.ld + v.off + c];
+}
+
+__global__ void k_pack(PackJobs jobs, char* __restrict__ dst) {
+  const PackJob J = jobs.job[blockIdx.y];
+  const int64_t n = (int64_t)J.rows * J.cols;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    int row, col;
+    if (!jobs.bf) {
+      const int S = J.cols / 4;
+      const int lane = (int)(e % 64);
+      const int64_t t = e / 64;
+      const int s = (int)(t % S), mb = (int)(t / S);
+      row = 16 * mb + lane % 16;
+      col = 16 * (s / 4) + 4 * (lane / 16) + s % 4;
+    } else {
+      const int T = J.cols / 32;
+      const int q = (int)(e % 8);
+      int64_t t = e / 8;
+      const int lane = (int)(t % 64);
+      t /= 64;
+      const int tt = (int)(t % T), mb = (int)(t / T);
+      row = 16 * mb + lane % 16;
+      col = 32 * tt + 16 * (q / 4) + 4 * (lane / 16) + q % 4;
+    }
+    const float v = col < J.split ? view_elem(J.a, row, col) : view_elem(J.b, row, col - J.split);
+    if (!jobs.bf)
+      reinterpret_cast<float*>(dst + J.dst_off)[e] = v;
+    else
+      reinterpret_cast<__bf16*>(dst + J.dst_off)[e] = (__bf16)v;
+  }
+}
+
+hipError_t launch_pack(const PackJobs& jobs, void* dst, hipStream_t s) {
+  if (jobs.n <= 0) return hipSuccess;
+  int64_t mx = 0;
+  for (int i = 0; i < jobs.n; ++i) mx = std::max<int64_t>(mx, (int64_t)jobs.job[i].rows * jobs.job[i].cols);
+  const int grid = (int)std::min<int64_t>((mx + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_pack, dim3(grid, jobs.n), dim3(256), 0, s, jobs, reinterpret_cast<char*>(dst));
+  return hipGetLastError();
+}
+
+// Copy `bytes` (a multiple of 16) from global to LDS with the whole block.
+__device__ __forceinline__ void stage_to_lds(uint4* __restrict__ dst, const void* __restrict__ src, size_t bytes) {
+  const uint4* s = reinterpret_cast<const uint4*>(src);
+  for (size_t i = threadIdx.x; i < bytes / 16; i += blockDim.x) dst[i] = s[i];
+}
+
+// ------------------------------------------------------------ projections
+
+// P = W1a x + b1, Q = W1b x: the receiver and sender parts of the first
+// edge-MLP Linear applied once per node instead of once per edge.  This
+// splits the Linear of Eq. 4a over its concatenated input; the products
+// are the same, only the summation grouping differs.
+template <int H, bool BF>
+__global__ __launch_bounds__(256) void k_proj(int64_t n_rows, const float* __restrict__ x,
+                                              const void* __restrict__ frag, const float* __restrict__ b1,
+                                              float* __restrict__ P, float* __restrict__ Q) {
+  constexpr int NF = H / 4, MB = H / 16;
+  constexpr size_t FB = frag_bytes(H, H, BF);
+  constexpr bool LDS = 2 * FB <= kRowMlpLdsBudget;
+  extern __shared__ uint4 smem[];
+  const char* fr;
+  if constexpr (LDS) {
+    stage_to_lds(smem, frag, 2 * FB);
+    __syncthreads();
+    fr = reinterpret_cast<const char*>(smem);
+  } else {
+    fr = reinterpret_cast<const char*>(frag);
+  }
+  const int lane = lane_id(), j = lane & 15, g = lane >> 4;
+  const int nw = blockDim.x / 64;
+  const int64_t nblk = (n_rows + 15) / 16;
+  for (int64_t blk = (int64_t)blockIdx.x * nw + threadIdx.x / 64; blk < nblk; blk += (int64_t)gridDim.x * nw) {
+    const int64_t row = blk * 16 + j;
+    const bool valid = row < n_rows;
+    const int64_t rr = valid ? row : n_rows - 1;
+    float xv[NF], p[NF], q[NF];
+    load_row<H>(x + rr * H, g, xv);
+    load_vec<H>(b1, g, p);
+#pragma unroll
+    for (int i = 0; i < NF; ++i) q[i] = 0.f;
+    gemm<BF, MB, MB>(fr, xv, p, lane);
+    gemm<BF, MB, MB>(fr + FB, xv, q, lane);
+    if (valid) {
+      store_row<H>(P + row * H, g, p);
+      store_row<H>(Q + row * H, g, q);
+    }
+  }
+}
+
+template <int H, bool BF>
+static hipError_t launch_proj_t(const DevGraph& gr, const float* x, const void* frag, const float* b1,
+                                float* P, float* Q, int grid, hipStream_t s) {
+  constexpr size_t FB = frag_bytes(H, H, BF);
+  const size_t lds = (2 * FB <= kRowMlpLdsBudget) ? 2 * FB : 0;
+  if (lds > 64 * 1024) (void)hipFuncSetAttribute((const void*)k_proj<H, BF>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL((k_proj<H, BF>), dim3(grid), dim3(256), lds, s, gr.n_rows, x, frag, b1, P, Q);
+  return hipGetLastError();
+}
+
+hipError_t launch_proj(int H, bool bf, const DevGraph& g, const float* x, const void* frag, const float* b1,
+                       float* P, float* Q, int grid, hipStream_t s) {
+#define MP_CASE(HH)                                                            \
+  if (H == HH) return bf ? launch_proj_t<HH, true>(g, x, frag, b1, P, Q, grid, s) \
+                         : launch_proj_t<HH, false>(g, x, frag, b1, P, Q, grid, s);
+  MP_CASE(32) MP_CASE(64) MP_CASE(128)
+#undef MP_CASE
+  return hipErrorInvalidValue;
+}
+
+// --------------------------------------------- edge update + aggregation
+
+// Eq. 4a-b on a static row range per wave.  For every directed edge k
+// (receiver i, sender j):
+//   h  = P_i + Q_j + W1c e_k             (first Linear of the edge MLP)
+//   m  = W2 ELU(h) + b2  [-> LayerNorm]  (second Linear)
+//   e'_k = e_k + m                        (residual edge update)
+// and a_i = sum_k e'_k / d_k over the receiver's edges, formed by a
+// segmented scan across the 16 edges of each block with the open row
+// carried into the next block.  Every row's sum is written once by the lane
+// holding its last edge; no atomics, so results are bitwise reproducible.
+template <int H, bool BF>
+__global__ __launch_bounds__(256) void k_edge_fwd(DevGraph gr, const float* __restrict__ P,
+                                                  const float* __restrict__ Q, const float* __restrict__ e_in,
+                                                  const void* __restrict__ frag, const float* __restrict__ b2,
+                                                  const float* __restrict__ lng, const float* __restrict__ lnb,
+                                                  int ln, float eps, float* __restrict__ e_out,
+                                                  float* __restrict__ a_out) {
+  constexpr int NF = H / 4, MB = H / 16;
+  constexpr size_t FB = frag_bytes(H, H, BF);
+  constexpr bool LDS = 2 * FB <= kEdgeLdsBudget;
+  extern __shared__ uint4 smem[];
+  const char* fr;
+  if constexpr (LDS) {
+    stage_to_lds(smem, frag, 2 * FB);
+    __syncthreads();
+    fr = reinterpret_cast<const char*>(smem);
+  } else {
+    fr = reinterpret_cast<const char*>(frag);
+  }
+  const int lane = lane_id(), j = lane & 15, g = lane >> 4;
+  const int nw = blockDim.x / 64;
+  const int64_t wave = xcd_block(blockIdx.x, gridDim.x) * nw + threadIdx.x / 64;
+  int64_t r0, r1;
+  part_rows(gr.rowptr, gr.n_rows, (int64_t)gridDim.x * nw, wave, r0, r1);
+  const int64_t e0 = gr.rowptr[r0], e1 = gr.rowptr[r1];
+
+  float bias2[NF], gam[NF], bet[NF];
+  load_vec<H>(b2, g, bias2);
+  if (ln) {
+    load_vec<H>(lng, g, gam);
+    load_vec<H>(lnb, g, bet);
+  }
+  float carry[NF];
+#pragma unroll
+  for (int i = 0; i < NF; ++i) carry[i] = 0.f;
+  int carry_key = 0;
+
+  for (int64_t base = e0; base < e1; base += 16) {
+    const int64_t k = base + j;
+    const bool valid = k < e1;
+    const int64_t kk = valid ? k : e1 - 1;
+    const int ri = gr.recv[kk];
+    const int sj = gr.col[kk];
+    const float inv_d = 1.f / (float)gr.mult[kk];
+    const int next = (k + 1 < e1) ? gr.recv[k + 1] : -1;
+    const bool last = valid && next != ri;
+    const int key = valid ? ri + 1 : -1;
+
+    float ev[NF], h[NF], q[NF];
+    load_row<H>(e_in + kk * H, g, ev);
+    load_row<H>(P + (int64_t)ri * H, g, h);
+    load_row<H>(Q + (int64_t)sj * H, g, q);
+#pragma unroll
+    for (int i = 0; i < NF; ++i) h[i] += q[i];
+    gemm<BF, MB, MB>(fr, ev, h, lane);
+#pragma unroll
+    for (int i = 0; i < NF; ++i) h[i] = elu(h[i]);
+    float m[NF];
+#pragma unroll
+    for (int i = 0; i < NF; ++i) m[i] = bias2[i];
+    gemm<BF, MB, MB>(fr + FB, h, m, lane);
+    if (ln) {
+      float mean, rstd;
+      ln_stats<H>(m, eps, mean, rstd);
+#pragma unroll
+      for (int i = 0; i < NF; ++i) m[i] = (m[i] - mean) * rstd * gam[i] + bet[i];
+    }
+#pragma unroll
+    for (int i = 0; i < NF; ++i) ev[i] += m[i];
+    if (valid) store_row<H>(e_out + k * H, g, ev);
+
+    // aggregation: segmented scan of e'/d across the block, plus carry
+#pragma unroll
+    for (int i = 0; i < NF; ++i) {
+      float v = valid ? ev[i] * inv_d : 0.f;
+      if (j == 0 && key == carry_key) v += carry[i];
+      ev[i] = v;
+    }
+    seg_scan16<NF>(ev, key);
+    if (last) store_row<H>(a_out + (int64_t)ri * H, g, ev);
+#pragma unroll
+    for (int i = 0; i < NF; ++i) carry[i] = from_prev_lane(ev[i]);
+    carry_key = from_prev_lane_i(key);
+  }
+  // rows without incoming edges aggregate to zero
+  for (int64_t r = r0 + (lane >> 2); r < r1; r += 16) {
+    if (gr.rowptr[r] == gr.rowptr[r + 1]) {
+      float* dst = a_out + r * H;
+      for (int c = (lane & 3) * 4; c < H; c += 16) *reinterpret_cast<float4*>(dst + c) = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  }
+}
+
+template <int H, bool BF>
+static hipError_t launch_edge_fwd_t(const DevGraph& g, const float* P, const float* Q, const float* e_in,
+                                    const void* frag, const float* b2, const float* lng, const float* lnb, int ln,
+                                    float eps, float* e_out, float* a_out, int grid, hipStream_t s) {
+  constexpr size_t FB = frag_bytes(H, H, BF);
+  const size_t lds = (2 * FB <= kEdgeLdsBudget) ? 2 * FB : 0;
+  if (lds > 64 * 1024)
+    (void)hipFuncSetAttribute((const void*)k_edge_fwd<H, BF>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL((k_edge_fwd<H, BF>), dim3(grid), dim3(256), lds, s, g, P, Q, e_in, frag, b2, lng, lnb, ln,
+                     eps, e_out, a_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_edge_fwd(int H, bool ln, bool bf, const DevGraph& g, const float* P, const float* Q,
+                           const float* e_in, const void* frag, const float* b2, const float* lng, const float* lnb,
+                           float eps, float* e_out, float* a_out, int grid, hipStream_t s) {
+#define MP_CASE(HH)                                                                                    \
+  if (H == HH)                                                                                         \
+    return bf ? launch_edge_fwd_t<HH, true>(g, P, Q, e_in, frag, b2, lng, lnb, ln, eps, e_out, a_out, grid, s) \
+              : launch_edge_fwd_t<HH, false>(g, P, Q, e_in, frag, b2, lng, lnb, ln, eps, e_out, a_out, grid, s);
+  MP_CASE(32) MP_CASE(64) MP_CASE(128)
+#undef MP_CASE
+  return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------------- halo sum
+
+// Eq. 4c-d on one GPU: every group lists the rows (one per sub-graph) that
+// hold one global id.  Each copy receives the sum of all copies' local
+// aggregates, added in ascending row order; rows in no group keep a.
+// One thread per (group, 4 features); groups are disjoint, so the update
+// in place is race free.
+template <int H>
+__global__ __launch_bounds__(256) void k_halo(int64_t n_groups, const int32_t* __restrict__ gptr,
+                                              const int32_t* __restrict__ member, float* __restrict__ a) {
+  constexpr int C = H / 4;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t grp = t / C;
+  if (grp >= n_groups) return;
+  const int c = (int)(t % C) * 4;
+  const int m0 = gptr[grp], m1 = gptr[grp + 1];
+  float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+  for (int m = m0; m < m1; ++m) {
+    const float4 v = *reinterpret_cast<const float4*>(a + (int64_t)member[m] * H + c);
+    s.x += v.x;
+    s.y += v.y;
+    s.z += v.z;
+    s.w += v.w;
+  }
+  for (int m = m0; m < m1; ++m) *reinterpret_cast<float4*>(a + (int64_t)member[m] * H + c) = s;
+}
+
+hipError_t launch_halo(int H, const DevGraph& g, float* a, hipStream_t s) {
+  if (g.n_groups == 0) return hipSuccess;
+  const int64_t threads = g.n_groups * (H / 4);
+  const int grid = (int)((threads + 255) / 256);
+  if (H == 32) hipLaunchKernelGGL(k_halo<32>, dim3(grid), dim3(256), 0, s, g.n_groups, g.group_ptr, g.member, a);
+  else if (H == 64) hipLaunchKernelGGL(k_halo<64>, dim3(grid), dim3(256), 0, s, g.n_groups, g.group_ptr, g.member, a);
+  else if (H == 128) hipLaunchKernelGGL(k_halo<128>, dim3(grid), dim3(256), 0, s, g.n_groups, g.group_ptr, g.member, a);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------- row MLPs
+
+// out = [resid +] [LN] (W1 ELU(W0 in + b0) + b1), in = [src0, src1].
+// TIN: in has k0 <= 4 features; the first Linear is done with FMAs from
+// the raw weights.  TOUT: n_out < 16 outputs; the second Linear is done
+// with FMAs and a reduction over the four lanes of each row.
+template <int H, int KIN, bool TIN, bool TOUT, bool BF>
+__global__ __launch_bounds__(256) void k_mlp_fwd(MlpFwdArgs a) {
+  constexpr int NF = H / 4, MB = H / 16, KB = TIN ? 1 : KIN / 16;
+  constexpr size_t F0 = TIN ? 0 : frag_bytes(H, KIN, BF);
+  constexpr size_t F1 = TOUT ? 0 : frag_bytes(H, H, BF);
+  constexpr bool LDS = (F0 + F1) <= kRowMlpLdsBudget;
+  extern __shared__ uint4 smem[];
+  const char* f0;
+  const char* f1;
+  if constexpr (LDS) {
+    if (F0) stage_to_lds(smem, a.frag0, F0);
+    if (F1) stage_to_lds(smem + F0 / 16, a.frag1, F1);
+    __syncthreads();
+    f0 = reinterpret_cast<const char*>(smem);
+    f1 = f0 + F0;
+  } else {
+    f0 = reinterpret_cast<const char*>(a.frag0);
+    f1 = reinterpret_cast<const char*>(a.frag1);
+  }
+  const int lane = lane_id(), j = lane & 15, g = lane >> 4;
+  const int nw = blockDim.x / 64;
+  const int64_t n = a.n_rows, nblk = (n + 15) / 16;
+  for (int64_t blk = (int64_t)blockIdx.x * nw + threadIdx.x / 64; blk < nblk; blk += (int64_t)gridDim.x * nw) {
+    const int64_t row = blk * 16 + j;
+    const bool valid = row < n;
+    const int64_t rr = valid ? row : n - 1;
+    float z[NF];
+    load_vec<H>(a.b0, g, z);
+    if constexpr (TIN) {
+      float in[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) in[k] = k < a.k0 ? a.src0[rr * a.k0 + k] : 0.f;
+#pragma unroll
+      for (int i = 0; i < NF; ++i) {
+        const int f = 16 * (i / 4) + 4 * g + (i % 4);
+        for (int k = 0; k < a.k0; ++k) z[i] += a.W0[f * a.k0 + k] * in[k];
+      }
+    } else {
+      float in[KIN / 4];
+      if constexpr (KIN == 2 * H) {
+        float t0[NF], t1[NF];
+        load_row<H>(a.src0 + rr * H, g, t0);
+        load_row<H>(a.src1 + rr * H, g, t1);
+#pragma unroll
+        for (int i = 0; i < NF; ++i) {
+          in[i] = t0[i];
+          in[NF + i] = t1[i];
+        }
+      } else {
+        load_row<KIN>(a.src0 + rr * KIN, g, in);
+      }
+      gemm<BF, MB, KB>(f0, in, z, lane);
+    }
+#pragma unroll
+    for (int i = 0; i < NF; ++i) z[i] = elu(z[i]);
+    if constexpr (TOUT) {
+      for (int o = 0; o < a.n_out; ++o) {
+        float p = 0.f;
+#pragma unroll
+        for (int i = 0; i < NF; ++i) p += a.W1[o * H + 16 * (i / 4) + 4 * g + (i % 4)] * z[i];
+        p = row_sum(p);
+        if (valid && g == 0) a.out[row * a.n_out + o] = p + a.b1[o];
+      }
+    } else {
+      float y[NF];
+      load_vec<H>(a.b1, g, y);
+      gemm<BF, MB, MB>(f1, z, y, lane);
+      if (a.ln) {
+        float mean, rstd, gm[NF], bt[NF];
+        load_vec<H>(a.lng, g, gm);
+        load_vec<H>(a.lnb, g, bt);
+        ln_stats<H>(y, a.eps, mean, rstd);
+#pragma unroll
+        for (int i = 0; i < NF; ++i) y[i] = (y[i] - mean) * rstd * gm[i] + bt[i];
+      }
+      if (a.resid) {
+        float r[NF];
+        load_row<H>(a.resid + rr * H, g, r);
+#pragma unroll
+        for (int i = 0; i < NF; ++i) y[i] += r[i];
+      }
+      if (valid) store_row<H>(a.out + row * H, g, y);
+    }
+  }
+}
+
+template <int H, int KIN, bool TIN, bool TOUT, bool BF>
+static hipError_t launch_mlp_fwd_t(const MlpFwdArgs& a, int grid, hipStream_t s) {
+  constexpr size_t F0 = TIN ? 0 : frag_bytes(H, KIN, BF);
+  constexpr size_t F1 = TOUT ? 0 : frag_bytes(H, H, BF);
+  const size_t lds = (F0 + F1 <= kRowMlpLdsBudget) ? F0 + F1 : 0;
+  if (lds > 64 * 1024)
+    (void)hipFuncSetAttribute((const void*)k_mlp_fwd<H, KIN, TIN, TOUT, BF>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)lds);
+  hipLaunchKernelGGL((k_mlp_fwd<H, KIN, TIN, TOUT, BF>), dim3(grid), dim3(256), lds, s, a);
+  return hipGetLastError();
+}
+
+template <int H, bool BF>
+static hipError_t launch_mlp_fwd_h(const MlpFwdArgs& a, int grid, hipStream_t s) {
+  const bool tin = a.k0 <= 4, tout = a.n_out < 16;
+  const int kin = a.k0 + a.k1;
+  if (tin && !tout) return launch_mlp_fwd_t<H, 4, true, false, BF>(a, grid, s);
+  if (!tin && kin == H && tout) return launch_mlp_fwd_t<H, H, false, true, BF>(a, grid, s);
+  if (!tin && kin == H && !tout) return launch_mlp_fwd_t<H, H, false, false, BF>(a, grid, s);
+  if (!tin && kin == 2 * H && !tout) return launch_mlp_fwd_t<H, 2 * H, false, false, BF>(a, grid, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_mlp_fwd(const MlpFwdArgs& a, int grid, hipStream_t s) {
+#define MP_CASE(HH) \
+  if (a.H == HH) return a.bf ? launch_mlp_fwd_h<HH, true>(a, grid, s) : launch_mlp_fwd_h<HH, false>(a, grid, s);
+  MP_CASE(32) MP_CASE(64) MP_CASE(128)
+#undef MP_CASE
+  return hipErrorInvalidValue;
+}
+
+// ----------------------------------------------------------- edge inputs
+
+// Edge features of Sec. III: (p_j - p_i, |p_j - p_i|) with i the receiver
+// and j the sender, differences in FP64, rounded once to FP32.
+__global__ __launch_bounds__(256) void k_edge_inputs(int64_t n_edges, const int32_t* __restrict__ recv,
+                                                     const int32_t* __restrict__ col, const double* __restrict__ pos,
+                                                     float* __restrict__ e0) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_edges) return;
+  const int64_t i = recv[k], jj = col[k];
+  const double dx = pos[3 * jj] - pos[3 * i];
+  const double dy = pos[3 * jj + 1] - pos[3 * i + 1];
+  const double dz = pos[3 * jj + 2] - pos[3 * i + 2];
+  const double r = sqrt(dx * dx + dy * dy + dz * dz);
+  *reinterpret_cast<float4*>(e0 + 4 * k) = make_float4((float)dx, (float)dy, (float)dz, (float)r);
+}
+
+hipError_t launch_edge_inputs(const DevGraph& g, const double* pos, float* e0, hipStream_t s) {
+  if (g.n_edges == 0) return hipSuccess;
+  const int grid = (int)((g.n_edges + 255) / 256);
+  hipLaunchKernelGGL(k_edge_inputs, dim3(grid), dim3(256), 0, s, g.n_edges, g.recv, g.col, pos, e0);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ loss
+
+// Eq. 6: per block, FP64 partial sums over a fixed row range of
+// S = sum (1/d_i)(Y - T)^2 and N = sum 1/d_i; block tree in fixed order.
+__global__ __launch_bounds__(256) void k_loss_part(int64_t n_rows, int F, const float* __restrict__ Y,
+                                                   const float* __restrict__ T, const uint8_t* __restrict__ mult,
+                                                   double* __restrict__ part) {
+  __shared__ double sS[256], sN[256];
+  const int64_t per = (n_rows + gridDim.x - 1) / gridDim.x;
+  const int64_t r0 = (int64_t)blockIdx.x * per, r1 = min(n_rows, r0 + per);
+  double S = 0.0, N = 0.0;
+  for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
+    const double w = 1.0 / (double)mult[r];
+    double e = 0.0;
+    for (int f = 0; f < F; ++f) {
+      const double d = (double)Y[r * F + f] - (double)T[r * F + f];
+      e += d * d;
+    }
+    S += w * e;
+    N += w;
+  }
+  sS[threadIdx.x] = S;
+  sN[threadIdx.x] = N;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      sS[threadIdx.x] += sS[threadIdx.x + o];
+      sN[threadIdx.x] += sN[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = sS[0];
+    part[2 * blockIdx.x + 1] = sN[0];
+  }
+}
+
+// Sum the block partials in block order (single thread: a few hundred
+// values) and publish loss and N_eff.
+__global__ void k_loss_final(int n_part, int F, const double* __restrict__ part, double* __restrict__ tot,
+                             float* __restrict__ loss) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double S = 0.0, N = 0.0;
+  for (int b = 0; b < n_part; ++b) {
+    S += part[2 * b];
+    N += part[2 * b + 1];
+  }
+  tot[0] = S;
+  tot[1] = N;
+  *loss = (float)(S / (N * F));
+}
+
+__global__ __launch_bounds__(256) void k_loss_grad(int64_t n, int F, const float* __restrict__ Y,
+                                                   const float* __restrict__ T, const uint8_t* __restrict__ mult,
+                                                   const double* __restrict__ tot, float* __restrict__ gY) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * F) return;
+  const int64_t r = t / F;
+  const double c = 2.0 / (tot[1] * F * (double)mult[r]);
+  gY[t] = (float)(c * ((double)Y[t] - (double)T[t]));
+}
+
+hipError_t launch_loss(int64_t n_rows, int F, const float* Y, const float* T, const uint8_t* mult, double* part,
+                       int n_part, float* loss, float* gY, hipStream_t s) {
+  hipLaunchKernelGGL(k_loss_part, dim3(n_part), dim3(256), 0, s, n_rows, F, Y, T, mult, part);
+  double* tot = part + 2 * n_part;
+  hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, s, n_part, F, part, tot, loss);
+  if (gY) {
+    const int grid = (int)((n_rows * F + 255) / 256);
+    hipLaunchKernelGGL(k_loss_grad, dim3(grid), dim3(256), 0, s, n_rows, F, Y, T, mult, tot, gY);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace mp

@@ -1,0 +1,169 @@
+// Kernel declarations and launch-side structures shared by the C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mp {
+
+// One matrix to pack into MFMA fragments: element (r, c) of the packed
+// [rows][cols] matrix is  c < split ? A(r, c) : B(r, c - split)  where a
+// view X(r, c) = trans ? p[c*ld + off + r] : p[r*ld + off + c].
+struct PackView {
+  const float* p;
+  int ld, off, trans;
+};
+struct PackJob {
+  PackView a, b;
+  int rows, cols, split;
+  int64_t dst_off;  // byte offset of the fragments in the packed buffer
+};
+constexpr int kMaxPackJobs = 12;
+struct PackJobs {
+  PackJob job[kMaxPackJobs];
+  int n;
+  int bf;  // 1: BF16 fragments
+};
+
+// Device graph arrays (see mp_dev_graph).
+struct DevGraph {
+  int64_t n_rows, n_edges, n_groups;
+  const int32_t* rowptr;
+  const int32_t* recv;
+  const int32_t* col;
+  const int32_t* rev;
+  const uint8_t* mult;
+  const int32_t* group_ptr;
+  const int32_t* member;
+};
+
+// Launch helpers; each returns the hipError_t of the launch.
+hipError_t launch_pack(const PackJobs& jobs, void* dst, hipStream_t s);
+
+hipError_t launch_proj(int H, bool bf, const DevGraph& g, const float* x, const void* frag_ab,
+                       const float* b1, float* P, float* Q, int grid, hipStream_t s);
+
+hipError_t launch_edge_fwd(int H, bool ln, bool bf, const DevGraph& g, const float* P, const float* Q,
+                           const float* e_in, const void* frag_c2, const float* b2, const float* lng,
+                           const float* lnb, float eps, float* e_out, float* a_out, int grid,
+                           hipStream_t s);
+
+hipError_t launch_halo(int H, const DevGraph& g, float* a, hipStream_t s);
+
+// Row MLP: out = [resid +] [LN] (W1 . ELU(W0 . in + b0) + b1) with
+// in = [src0 (k0 features), src1 (k1 features)]; k0 in {3, 4} is the
+// small-input form (first Linear by FMA, W0 read directly); n_out < 16 is
+// the small-output form (second Linear by FMA, no LayerNorm).
+struct MlpFwdArgs {
+  int64_t n_rows;
+  const float* src0;
+  const float* src1;
+  const float* resid;
+  int k0, k1, H, n_out, ln, bf;
+  const float* W0;  // raw weights (small-input form)
+  const float* b0;
+  const float* W1;  // raw weights (small-output form)
+  const float* b1;
+  const float* lng;
+  const float* lnb;
+  float eps;
+  const void* frag0;  // packed W0 (when k0 >= 16)
+  const void* frag1;  // packed W1 (when n_out == H)
+  float* out;
+};
+hipError_t launch_mlp_fwd(const MlpFwdArgs& a, int grid, hipStream_t s);
+
+hipError_t launch_edge_inputs(const DevGraph& g, const double* pos, float* e0, hipStream_t s);
+
+hipError_t launch_loss(int64_t n_rows, int F, const float* Y, const float* T, const uint8_t* mult,
+                       double* part, int n_part, float* loss, float* gY, hipStream_t s);
+
+// ---------------------------------------------------------------- backward
+
+// Floats per workgroup slab of partial weight gradients.
+// edge adjoint: [dW1c H*H][dW2 H*H][db2 H][dgamma H][dbeta H]
+__host__ __device__ constexpr int64_t edge_slab(int H) { return 2 * (int64_t)H * H + 3 * H; }
+// sender-side pass: [dW1a H*H][dW1b H*H][db1 H]
+__host__ __device__ constexpr int64_t gq_slab(int H) { return 2 * (int64_t)H * H + H; }
+// row MLP adjoint: [dW0 H*kin][db0 H][dW1 n_out*H][db1 n_out][dgamma H][dbeta H]
+__host__ __device__ constexpr int64_t mlp_slab(int H, int kin, int n_out) {
+  return (int64_t)H * kin + H + (int64_t)n_out * H + n_out + 2 * H;
+}
+
+// Partial weight gradients: one slab of `slab` floats per workgroup of the
+// producing kernel; launch_wreduce sums the slabs in workgroup order.
+struct ReduceSeg {
+  const float* part;  // first slab
+  int n_slabs;
+  int64_t slab;       // floats per slab
+  int64_t src_off;    // float offset of this block inside a slab
+  int rows, cols;     // gradient block shape (row-major inside the slab)
+  float* dst;         // destination, leading dimension ld, first column col0
+  int ld, col0;
+};
+constexpr int kMaxReduceSegs = 16;
+struct ReduceSegs {
+  ReduceSeg seg[kMaxReduceSegs];
+  int n;
+};
+hipError_t launch_wreduce(const ReduceSegs& segs, hipStream_t s);
+
+struct EdgeBwdArgs {
+  DevGraph g;
+  int H, ln, bf;
+  const float* P;
+  const float* Q;
+  const float* e_in;
+  const float* g_e_out;  // may be null
+  const float* g_a;      // gradient of a (after the adjoint halo sum)
+  const void* frag;      // W1c, W2, W2^T, W1c^T fragments, consecutive
+  const float* b2;
+  const float* lng;
+  const float* lnb;
+  float eps;
+  float* g_e_in;
+  float* g_h;            // [E][H] gradient of the first pre-activation
+  float* g_P;            // [N][H] sum of g_h over each row's incoming edges
+  float* part;           // partial weight gradients, slab per workgroup
+  int64_t slab;
+};
+hipError_t launch_edge_bwd(const EdgeBwdArgs& a, int grid, hipStream_t s);
+
+struct MlpBwdArgs {
+  int64_t n_rows;
+  const float* src0;
+  const float* src1;
+  int k0, k1, H, n_out, ln, bf, resid;
+  const float* W0;
+  const float* b0;
+  const float* W1;
+  const float* b1;
+  const float* lng;
+  const float* lnb;
+  float eps;
+  const void* frag0;   // W0 (k0 >= 16)
+  const void* frag1;   // W1 (n_out == H)
+  const void* frag1t;  // W1^T (n_out == H)
+  const void* frag0t;  // W0^T (k0 >= 16 and an input gradient is wanted)
+  const float* g_out;
+  float* g_src0;       // may be null
+  float* g_src1;       // may be null
+  const float* g_add1; // added to g_src1 (residual path); may be null
+  float* part;
+  int64_t slab;
+};
+hipError_t launch_mlp_bwd(const MlpBwdArgs& a, int grid, hipStream_t s);
+
+struct GqArgs {
+  DevGraph g;
+  int H, bf;
+  const float* x;
+  const float* g_P;
+  const float* g_h;
+  const void* frag_abt;  // [W1a | W1b]^T as an H x 2H matrix
+  float* g_x;            // accumulated: g_x += W1a^T g_P + W1b^T g_Q
+  float* part;
+  int64_t slab;
+};
+hipError_t launch_gq(const GqArgs& a, int grid, hipStream_t s);
+
+}  // namespace mp

@@ -1,0 +1,96 @@
+"""Encode-process-decode GNN of consistent NMP layers (Sec. III, Table I).
+
+Node encoder MLP (3 -> H), edge encoder MLP (4 -> H), M consistent
+message-passing layers (Eq. 4a-e), node decoder MLP (H -> 3), and the
+consistent MSE (Eq. 6).  Every piece runs through libmplayer.so.
+"""
+
+import numpy as np
+import torch
+
+from .graph import DeviceGraph, build_graph
+from .ops import (ConsistentMSEFn, MLPFn, MPLayerFn, edge_inputs, layer_cfg, mlp_cfg)
+
+
+def _layer_param_names(m, ln):
+    pre = f"mp{m}"
+    names = {"We1": f"{pre}.edge.lin0.W", "be1": f"{pre}.edge.lin0.b",
+             "We2": f"{pre}.edge.lin1.W", "be2": f"{pre}.edge.lin1.b",
+             "Wn1": f"{pre}.node.lin0.W", "bn1": f"{pre}.node.lin0.b",
+             "Wn2": f"{pre}.node.lin1.W", "bn2": f"{pre}.node.lin1.b"}
+    if ln:
+        names.update({"ge": f"{pre}.edge.ln.g", "bge": f"{pre}.edge.ln.b",
+                      "gn": f"{pre}.node.ln.g", "bgn": f"{pre}.node.ln.b"})
+    return names
+
+
+def _mlp_param_names(prefix, ln):
+    names = {"W0": f"{prefix}.lin0.W", "b0": f"{prefix}.lin0.b",
+             "W1": f"{prefix}.lin1.W", "b1": f"{prefix}.lin1.b"}
+    if ln:
+        names.update({"ln_g": f"{prefix}.ln.g", "ln_b": f"{prefix}.ln.b"})
+    return names
+
+
+class ConsistentGNN:
+    """Parameters live in ``self.params`` (name -> device tensor, FP32)."""
+
+    LAYER_ORDER = ["We1", "be1", "We2", "be2", "ge", "bge", "Wn1", "bn1", "Wn2", "bn2", "gn", "bgn"]
+    MLP_ORDER = ["W0", "b0", "W1", "b1", "ln_g", "ln_b"]
+
+    def __init__(self, spec, params, device="cuda", gemm="f32", halo=True):
+        if spec.n_hidden != 0:
+            raise NotImplementedError("the GPU path implements MLPs of two Linear layers")
+        self.spec, self.gemm, self.halo = spec, gemm, halo
+        self.device = torch.device(device)
+        self.params = {k: torch.as_tensor(np.asarray(v), dtype=torch.float32).to(self.device).contiguous()
+                       for k, v in params.items()}
+
+    def requires_grad_(self, flag=True):
+        for t in self.params.values():
+            t.requires_grad_(flag)
+        return self
+
+    def _mlp(self, prefix, x, n_in, n_out, ln):
+        names = _mlp_param_names(prefix, ln)
+        cfg = mlp_cfg(n_in, self.spec.H, n_out, ln, self.gemm, self.spec.ln_eps)
+        args = [self.params[names[f]] if f in names else None for f in self.MLP_ORDER]
+        return MLPFn.apply(cfg, x, *args)
+
+    def encode(self, X, E0):
+        s = self.spec
+        x = self._mlp("nenc", X, s.node_in, s.H, s.layernorm)
+        e = self._mlp("eenc", E0, s.edge_in, s.H, s.layernorm)
+        return x, e
+
+    def process(self, dg, x, e):
+        s = self.spec
+        cfg = layer_cfg(s.H, s.layernorm, self.halo, self.gemm, s.ln_eps)
+        for m in range(s.n_layers):
+            names = _layer_param_names(m, s.layernorm)
+            args = [self.params[names[f]] if f in names else None for f in self.LAYER_ORDER]
+            x, e = MPLayerFn.apply(cfg, dg, x, e, *args)
+        return x, e
+
+    def decode(self, x):
+        return self._mlp("dec", x, self.spec.H, self.spec.out, False)
+
+    def forward(self, dg, X, E0):
+        x, e = self.encode(X, E0)
+        x, _ = self.process(dg, x, e)
+        return self.decode(x)
+
+    def loss(self, dg, Y, T):
+        return ConsistentMSEFn.apply(dg, Y, T)
+
+
+class Problem:
+    """Device graph, node inputs, edge inputs and target for one workload."""
+
+    def __init__(self, mesh, field, target, elem_part, R, device="cuda"):
+        self.host = build_graph(mesh.elem_gid, mesh.P, elem_part, R)
+        self.dg = DeviceGraph(self.host, device)
+        self.X = self.dg.rows_of(field).float().contiguous()
+        self.T = self.dg.rows_of(target).float().contiguous()
+        self.pos = self.dg.rows_of(mesh.pos).double().contiguous()
+        self.E0 = edge_inputs(self.dg, self.pos)

@@ -1,0 +1,213 @@
+"""Python binding of the layer, MLP, edge-input and loss entry points.
+
+Tensors supply device memory and the current HIP stream; every step runs
+in libmplayer.so.  The autograd Functions call the hand-written adjoint
+entry points, so training goes through the library's kernels too.
+"""
+
+import ctypes as C
+
+import torch
+
+from ._lib import (LAYER_FIELDS, MLP_FIELDS, MP_BF16, MP_F32, MpLayerCfg, MpLayerGrads,
+                   MpLayerParams, MpMlpCfg, MpMlpGrads, MpMlpParams, call)
+
+_GEMM = {"f32": MP_F32, "bf16": MP_BF16}
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _p(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p()
+
+
+def _check(*ts):
+    for t in ts:
+        if t is None:
+            continue
+        if not t.is_cuda:
+            raise ValueError("tensor is not on the GPU")
+        if not t.is_contiguous():
+            raise ValueError("tensor is not contiguous")
+
+
+class _Workspace:
+    """Grow-only scratch buffer per device (the library never allocates)."""
+
+    def __init__(self):
+        self.buf = {}
+
+    def get(self, nbytes, device):
+        key = (device.type, device.index)
+        b = self.buf.get(key)
+        if b is None or b.numel() < nbytes:
+            b = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+            self.buf[key] = b
+        return b
+
+
+WS = _Workspace()
+
+
+# ------------------------------------------------------------------ layer
+
+def layer_cfg(H, layernorm=True, halo=True, gemm="f32", ln_eps=1e-5):
+    c = MpLayerCfg()
+    c.H, c.layernorm, c.halo, c.gemm_dtype, c.ln_eps = H, int(layernorm), int(halo), _GEMM[gemm], ln_eps
+    return c
+
+
+def _layer_params(p):
+    s = MpLayerParams()
+    for f in LAYER_FIELDS:
+        setattr(s, f, p[f].data_ptr() if p.get(f) is not None else None)
+    return s
+
+
+def layer_forward(cfg, p, dg, x, e):
+    """One consistent NMP layer; returns (x_out, e_out, a_star)."""
+    _check(x, e)
+    x_out, e_out, a_star = torch.empty_like(x), torch.empty_like(e), torch.empty_like(x)
+    nb = C.c_size_t()
+    call("mp_layer_workspace_size", C.byref(cfg), C.byref(dg.desc), 0, C.byref(nb))
+    ws = WS.get(nb.value, x.device)
+    call("mp_layer_forward", C.byref(cfg), C.byref(_layer_params(p)), C.byref(dg.desc), _p(x), _p(e),
+         _p(x_out), _p(e_out), _p(a_star), _p(ws), ws.numel(), _stream())
+    return x_out, e_out, a_star
+
+
+def layer_backward(cfg, p, dg, x, e, a_star, g_x_out, g_e_out):
+    _check(x, e, a_star, g_x_out, g_e_out)
+    g_x, g_e = torch.empty_like(x), torch.empty_like(e)
+    grads = {f: (torch.empty_like(p[f]) if p.get(f) is not None else None) for f in LAYER_FIELDS}
+    gs = MpLayerGrads()
+    for f in LAYER_FIELDS:
+        setattr(gs, f, grads[f].data_ptr() if grads[f] is not None else None)
+    nb = C.c_size_t()
+    call("mp_layer_workspace_size", C.byref(cfg), C.byref(dg.desc), 1, C.byref(nb))
+    ws = WS.get(nb.value, x.device)
+    call("mp_layer_backward", C.byref(cfg), C.byref(_layer_params(p)), C.byref(dg.desc), _p(x), _p(e),
+         _p(a_star), _p(g_x_out), _p(g_e_out), _p(g_x), _p(g_e), C.byref(gs), _p(ws), ws.numel(),
+         _stream())
+    return g_x, g_e, grads
+
+
+class MPLayerFn(torch.autograd.Function):
+    """(x, e, *layer params) -> (x', e') with the library's adjoint as backward."""
+
+    @staticmethod
+    def forward(ctx, cfg, dg, x, e, *params):
+        p = dict(zip(LAYER_FIELDS, params))
+        x_out, e_out, a_star = layer_forward(cfg, p, dg, x, e)
+        ctx.cfg, ctx.dg = cfg, dg
+        ctx.save_for_backward(x, e, a_star, *[t if t is not None else torch.empty(0) for t in params])
+        ctx.has = [t is not None for t in params]
+        return x_out, e_out
+
+    @staticmethod
+    def backward(ctx, g_x_out, g_e_out):
+        x, e, a_star, *ps = ctx.saved_tensors
+        p = {f: (t if h else None) for f, t, h in zip(LAYER_FIELDS, ps, ctx.has)}
+        g_x_out = g_x_out.contiguous()
+        g_e_out = g_e_out.contiguous() if g_e_out is not None else None
+        g_x, g_e, grads = layer_backward(ctx.cfg, p, ctx.dg, x, e, a_star, g_x_out, g_e_out)
+        return (None, None, g_x, g_e) + tuple(grads[f] for f in LAYER_FIELDS)
+
+
+# -------------------------------------------------------------------- MLPs
+
+def mlp_cfg(n_in, H, n_out, layernorm, gemm="f32", ln_eps=1e-5):
+    c = MpMlpCfg()
+    c.n_in, c.H, c.n_out, c.layernorm, c.gemm_dtype, c.ln_eps = n_in, H, n_out, int(layernorm), _GEMM[gemm], ln_eps
+    return c
+
+
+def _mlp_params(p):
+    s = MpMlpParams()
+    for f in MLP_FIELDS:
+        setattr(s, f, p[f].data_ptr() if p.get(f) is not None else None)
+    return s
+
+
+def mlp_forward(cfg, p, x):
+    _check(x)
+    out = torch.empty((x.shape[0], cfg.n_out), dtype=torch.float32, device=x.device)
+    nb = C.c_size_t()
+    call("mp_mlp_workspace_size", C.byref(cfg), x.shape[0], 0, C.byref(nb))
+    ws = WS.get(nb.value, x.device)
+    call("mp_mlp_forward", C.byref(cfg), C.byref(_mlp_params(p)), x.shape[0], _p(x), _p(out), _p(ws),
+         ws.numel(), _stream())
+    return out
+
+
+def mlp_backward(cfg, p, x, g_out, want_g_in):
+    _check(x, g_out)
+    g_in = torch.empty_like(x) if want_g_in else None
+    grads = {f: (torch.empty_like(p[f]) if p.get(f) is not None else None) for f in MLP_FIELDS}
+    gs = MpMlpGrads()
+    for f in MLP_FIELDS:
+        setattr(gs, f, grads[f].data_ptr() if grads[f] is not None else None)
+    nb = C.c_size_t()
+    call("mp_mlp_workspace_size", C.byref(cfg), x.shape[0], 1, C.byref(nb))
+    ws = WS.get(nb.value, x.device)
+    call("mp_mlp_backward", C.byref(cfg), C.byref(_mlp_params(p)), x.shape[0], _p(x), _p(g_out), _p(g_in),
+         C.byref(gs), _p(ws), ws.numel(), _stream())
+    return g_in, grads
+
+
+class MLPFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, cfg, x, *params):
+        p = dict(zip(MLP_FIELDS, params))
+        ctx.cfg = cfg
+        ctx.has = [t is not None for t in params]
+        ctx.save_for_backward(x, *[t if t is not None else torch.empty(0) for t in params])
+        return mlp_forward(cfg, p, x)
+
+    @staticmethod
+    def backward(ctx, g_out):
+        x, *ps = ctx.saved_tensors
+        p = {f: (t if h else None) for f, t, h in zip(MLP_FIELDS, ps, ctx.has)}
+        want = ctx.needs_input_grad[1] and ctx.cfg.n_in > 4
+        g_in, grads = mlp_backward(ctx.cfg, p, x, g_out.contiguous(), want)
+        return (None, g_in) + tuple(grads[f] for f in MLP_FIELDS)
+
+
+# ----------------------------------------------------------- inputs, loss
+
+def edge_inputs(dg, row_pos):
+    """(p_j - p_i, |p_j - p_i|) per edge from FP64 row positions [N, 3]."""
+    _check(row_pos)
+    if row_pos.dtype != torch.float64:
+        raise ValueError("row positions must be float64")
+    e0 = torch.empty((dg.n_edges, 4), dtype=torch.float32, device=row_pos.device)
+    call("mp_edge_inputs", C.byref(dg.desc), _p(row_pos), _p(e0), _stream())
+    return e0
+
+
+def consistent_mse(dg, Y, T, want_grad=True):
+    """Eq. 6 loss over all rows (Eq. 5 when every node degree is 1)."""
+    _check(Y, T)
+    loss = torch.empty(1, dtype=torch.float32, device=Y.device)
+    gY = torch.empty_like(Y) if want_grad else None
+    nb = C.c_size_t()
+    call("mp_consistent_mse_workspace_size", Y.shape[0], C.byref(nb))
+    ws = torch.empty(nb.value, dtype=torch.uint8, device=Y.device)
+    call("mp_consistent_mse", Y.shape[0], Y.shape[1], _p(Y), _p(T), _p(dg.node_mult), _p(loss), _p(gY),
+         _p(ws), ws.numel(), _stream())
+    return loss, gY
+
+
+class ConsistentMSEFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, dg, Y, T):
+        loss, gY = consistent_mse(dg, Y, T, True)
+        ctx.save_for_backward(gY)
+        return loss[0]
+
+    @staticmethod
+    def backward(ctx, g):
+        (gY,) = ctx.saved_tensors
+        return None, gY * g, None

@@ -1,0 +1,211 @@
+"""C ABI on the CPU: exports, the host graph builder against the oracle's
+own graphs, halo plans, and the validation paths of the device entry
+points (which must reject bad input before touching a GPU)."""
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from mpinputs import CONFIGS, block_partition, box_mesh, make_inputs, rcb_partition, slab_partition
+from oracle.graph import partition_graph, table2_stats
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2410_01657_amd import _lib
+    return _lib
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "mplayer.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*([A-Za-z_][A-Za-z0-9_]*)\s*\(",
+                       text, flags=re.M)
+    return sorted(set(n for n in names if not n.startswith("MP")))
+
+
+def test_exports_every_declared_symbol(L):
+    lib = L.lib()
+    declared = _declared_functions()
+    assert len(declared) >= 20
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert set(declared) == set(L.EXPORTED)
+    assert lib.mp_abi_version() == 1
+
+
+def test_hex_links_counts():
+    from paper_2410_01657_amd import hex_links
+    from oracle.graph import element_links
+    for P in (1, 2, 3, 5, 7):
+        links = hex_links(P)
+        assert links.shape == (3 * P * (P + 1) ** 2, 2)
+        ref = element_links(P)
+        assert set(map(tuple, links.tolist())) == set(map(tuple, ref.tolist()))
+
+
+def _compare_with_oracle(mesh, part, R):
+    from paper_2410_01657_amd import build_graph
+    hg = build_graph(mesh.elem_gid, mesh.P, part, R)
+    og, copies = partition_graph(mesh.elem_gid, mesh.P, part, R)
+    assert hg.R == R
+    for r, G in enumerate(og):
+        r0, r1 = hg.row_off[r], hg.row_off[r + 1]
+        e0, e1 = hg.edge_off[r], hg.edge_off[r + 1]
+        np.testing.assert_array_equal(hg.row_gid[r0:r1], G.gid)
+        np.testing.assert_array_equal(hg.recv[e0:e1] - r0, G.recv)
+        np.testing.assert_array_equal(hg.col[e0:e1] - r0, G.send)
+        np.testing.assert_array_equal(hg.edge_mult[e0:e1], G.d_edge.astype(np.uint8))
+        np.testing.assert_array_equal(hg.node_mult[r0:r1], G.d_node.astype(np.uint8))
+    # CSR and reverse-edge invariants
+    assert hg.rowptr[0] == 0 and hg.rowptr[-1] == hg.n_edges
+    np.testing.assert_array_equal(np.repeat(np.arange(hg.n_rows), np.diff(hg.rowptr)), hg.recv)
+    np.testing.assert_array_equal(hg.rev[hg.rev], np.arange(hg.n_edges))
+    np.testing.assert_array_equal(hg.recv[hg.rev], hg.col)
+    # halo groups = the oracle's copies, as global rows
+    groups = {}
+    for gidx in range(hg.n_groups):
+        mem = hg.member[hg.group_ptr[gidx]:hg.group_ptr[gidx + 1]]
+        gids = set(hg.row_gid[mem].tolist())
+        assert len(gids) == 1
+        groups[gids.pop()] = mem.tolist()
+    ref = {g: [int(hg.row_off[r]) + i for r, i in cps] for g, cps in copies.items()}
+    assert groups == ref
+    rows, halo, nbrs = table2_stats(og, copies)
+    np.testing.assert_array_equal(hg.halo_rows, halo)
+    np.testing.assert_array_equal(hg.neighbours, nbrs)
+    # pair lists: every (r, s) pair's rows share ids, in ascending id
+    for k in range(hg.pair_r.shape[0]):
+        a, b = hg.pair_ptr[k], hg.pair_ptr[k + 1]
+        rr, rs = hg.pair_rows_r[a:b], hg.pair_rows_s[a:b]
+        np.testing.assert_array_equal(hg.row_gid[rr], hg.row_gid[rs])
+        assert np.all(np.diff(hg.row_gid[rr]) > 0)
+    return hg
+
+
+def test_graph_c0_r1_r8():
+    inp = make_inputs(CONFIGS["C0"])
+    _compare_with_oracle(inp.mesh, np.zeros(inp.mesh.n_elem, np.int32), 1)
+    hg = _compare_with_oracle(inp.mesh, inp.elem_part, 8)
+    assert (hg.n_rows, hg.n_edges, hg.n_groups, hg.member.shape[0]) == (2744, 14112, 469, 1016)
+
+
+def test_graph_rcb_t_junctions():
+    nel = (6, 5, 4)
+    m = box_mesh(nel, 2)
+    part, _ = rcb_partition(nel, 8, seed=11, ratio=(1.0, 10.0))
+    hg = _compare_with_oracle(m, part, 8)
+    assert 3 in set(hg.edge_mult.tolist())
+
+
+@pytest.mark.slow
+def test_graph_c1_r16_sizes():
+    from paper_2410_01657_amd import build_graph
+    cfg = CONFIGS["C1"]
+    m = box_mesh(cfg.nel, cfg.P, with_positions=False)
+    hg = build_graph(m.elem_gid, 5, slab_partition(cfg.nel, 16), 16)
+    assert (hg.n_rows, hg.n_edges, hg.n_groups, hg.member.shape[0]) == (629856, 3538080, 98415, 196830)
+
+
+@pytest.mark.slow
+def test_graph_table2_r8_row():
+    from paper_2410_01657_amd import build_graph
+    nel = (16, 16, 128)
+    m = box_mesh(nel, 5, periodic=(True, True, True), with_positions=False)
+    hg = build_graph(m.elem_gid, 5, slab_partition(nel, 8), 8)
+    np.testing.assert_array_equal(np.diff(hg.row_off), 518400)
+    np.testing.assert_array_equal(hg.halo_rows, 12800)
+    np.testing.assert_array_equal(hg.neighbours, 2)
+
+
+# ------------------------------------------------------------ error paths
+
+
+def test_graph_partition_rejects_bad_input(L):
+    from paper_2410_01657_amd import hex_links
+    from paper_2410_01657_amd._lib import MPError, call
+    m = box_mesh((2, 1, 1), 1)
+    links = hex_links(1)
+    eg = np.ascontiguousarray(m.elem_gid)
+    g = C.c_void_p()
+    ptr = lambda a: a.ctypes.data_as(C.c_void_p)
+    bad_part = np.array([0, 2], np.int32)
+    with pytest.raises(MPError) as e:
+        call("graph_partition", 2, 8, ptr(eg), links.shape[0], ptr(links), ptr(bad_part), 2, C.byref(g))
+    assert e.value.code == L.MP_EINVAL and "part" in str(e.value)
+    empty_part = np.array([0, 0], np.int32)
+    with pytest.raises(MPError):
+        call("graph_partition", 2, 8, ptr(eg), links.shape[0], ptr(links), ptr(empty_part), 2, C.byref(g))
+    bad_links = links.copy()
+    bad_links[0] = (3, 3)
+    with pytest.raises(MPError):
+        call("graph_partition", 2, 8, ptr(eg), links.shape[0], ptr(bad_links), ptr(empty_part), 1, C.byref(g))
+    with pytest.raises(MPError):
+        call("graph_partition", 2, 8, None, links.shape[0], ptr(links), ptr(empty_part), 1, C.byref(g))
+    assert g.value is None
+
+
+def _fake_desc(L, n_rows=10, n_edges=20):
+    d = L.MpDevGraph()
+    d.n_rows, d.n_edges, d.n_groups, d.n_members = n_rows, n_edges, 0, 0
+    for f in ("rowptr", "recv", "col", "rev", "edge_mult"):
+        setattr(d, f, 4096)  # never dereferenced: validation fails first
+    d.seal = L.lib().mp_dev_graph_seal(C.byref(d))
+    return d
+
+
+def test_device_entry_points_validate_before_launch(L):
+    from paper_2410_01657_amd._lib import MPError, call
+    from paper_2410_01657_amd.ops import layer_cfg
+    d = _fake_desc(L)
+    nb = C.c_size_t()
+    bad = layer_cfg(48)
+    with pytest.raises(MPError) as e:
+        call("mp_layer_workspace_size", C.byref(bad), C.byref(d), 0, C.byref(nb))
+    assert e.value.code == L.MP_EINVAL
+    cfg = layer_cfg(32)
+    call("mp_layer_workspace_size", C.byref(cfg), C.byref(d), 1, C.byref(nb))
+    assert nb.value > 0
+    d.n_edges = 21  # descriptor changed after sealing
+    with pytest.raises(MPError) as e:
+        call("mp_layer_workspace_size", C.byref(cfg), C.byref(d), 0, C.byref(nb))
+    assert e.value.code == L.MP_EPLAN
+    d = _fake_desc(L)
+    params = L.MpLayerParams()
+    with pytest.raises(MPError) as e:  # NULL parameters
+        call("mp_layer_forward", C.byref(cfg), C.byref(params), C.byref(d), None, None, None, None, None,
+             None, 0, None)
+    assert e.value.code == L.MP_EINVAL
+    for f in L.LAYER_FIELDS:
+        setattr(params, f, 4096)
+    with pytest.raises(MPError) as e:  # workspace too small
+        call("mp_layer_forward", C.byref(cfg), C.byref(params), C.byref(d), 4096, 8192, 12288, 16384, None,
+             4096, 16, None)
+    assert e.value.code == L.MP_ENOMEM
+    with pytest.raises(MPError) as e:  # aliasing
+        call("mp_layer_forward", C.byref(cfg), C.byref(params), C.byref(d), 4096, 8192, 4096, 16384, None,
+             4096, 1 << 30, None)
+    assert e.value.code == L.MP_EINVAL
+    with pytest.raises(MPError):  # unaligned
+        call("mp_layer_forward", C.byref(cfg), C.byref(params), C.byref(d), 4100, 8192, 12288, 16384, None,
+             4096, 1 << 30, None)
+
+
+def test_mlp_and_loss_validation(L):
+    from paper_2410_01657_amd._lib import MPError, call
+    from paper_2410_01657_amd.ops import mlp_cfg
+    nb = C.c_size_t()
+    with pytest.raises(MPError):
+        call("mp_mlp_workspace_size", C.byref(mlp_cfg(5, 64, 64, True)), 10, 0, C.byref(nb))
+    with pytest.raises(MPError):
+        call("mp_mlp_workspace_size", C.byref(mlp_cfg(3, 64, 3, False)), 10, 0, C.byref(nb))
+    with pytest.raises(MPError):  # LayerNorm on a small output
+        call("mp_mlp_workspace_size", C.byref(mlp_cfg(64, 64, 3, True)), 10, 0, C.byref(nb))
+    call("mp_mlp_workspace_size", C.byref(mlp_cfg(64, 64, 3, False)), 10, 1, C.byref(nb))
+    with pytest.raises(MPError):
+        call("mp_consistent_mse", 0, 3, None, None, None, None, None, None, 0, None)

@@ -1,0 +1,218 @@
+"""GPU parity of the consistent NMP layer against the FP64 oracle.
+
+Every comparison runs the library through its C ABI and the oracle on the
+same seeded inputs.  Tolerances are normwise, max|gpu - oracle| / max|oracle|:
+FP32 forward 1e-5 (one layer), FP32 gradients 1e-4, BF16 GEMMs 3e-2.
+Integer-valued aggregation checks are bitwise.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from mpinputs import CONFIGS, ModelSpec, block_partition, box_mesh, make_inputs, rcb_partition
+from oracle.graph import lattice_graph, partition_graph, halo_lists
+from oracle.nmp import nmp_layer_bwd, nmp_layer_fwd
+
+from _util import layer_params, normwise, split_rows
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def _graphs(mesh, part, R):
+    from paper_2410_01657_amd import DeviceGraph, build_graph
+    hg = build_graph(mesh.elem_gid, mesh.P, part, R)
+    og, copies = partition_graph(mesh.elem_gid, mesh.P, part, R)
+    return DeviceGraph(hg, DEV), og, halo_lists(og, copies)
+
+
+@pytest.fixture(scope="module")
+def c0():
+    inp = make_inputs(CONFIGS["C0"])
+    out = {}
+    for R in (1, 8):
+        part = np.zeros(inp.mesh.n_elem, np.int32) if R == 1 else inp.elem_part
+        out[R] = _graphs(inp.mesh, part, R)
+    return inp, out
+
+
+@pytest.fixture(scope="module")
+def rcb():
+    nel = (6, 5, 4)
+    m = box_mesh(nel, 3)
+    part, _ = rcb_partition(nel, 8, seed=11, ratio=(1.0, 10.0))
+    return m, _graphs(m, part, 8)
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(DEV)
+
+
+def _lib_params(o, names):
+    return {k: _t(o[v]) for k, v in names.items()}
+
+
+# ------------------------------------------------------------ exact sums
+
+
+def test_halo_sum_exact_in_degree(c0):
+    """Zero weights, b2 = 1, e = 0: every edge state becomes 1, so a* is
+    the global in-degree exactly, at every copy (1/d is a power of two)."""
+    from paper_2410_01657_amd.ops import layer_cfg, layer_forward
+    inp, gs = c0
+    dg, og, _ = gs[8]
+    H = 32
+    _, o, names = layer_params(H, False)
+    p = {k: torch.zeros_like(_t(o[v])) for k, v in names.items()}
+    p["be2"] += 1.0
+    x = torch.randn(dg.n_rows, H, device=DEV)
+    e = torch.zeros(dg.n_edges, H, device=DEV)
+    _, _, a_star = layer_forward(layer_cfg(H, False), p, dg, x, e)
+    n = inp.mesh.npts[0]
+    gid = dg.host.row_gid
+    I, J, K = gid % n, (gid // n) % n, gid // (n * n)
+    deg = sum((c > 0).astype(np.int64) + (c < n - 1).astype(np.int64) for c in (I, J, K))
+    a = a_star.cpu().numpy()
+    assert np.array_equal(a, np.repeat(deg[:, None].astype(np.float32), H, axis=1))
+
+
+@pytest.mark.parametrize("which", ["c0", "rcb"])
+def test_halo_sum_integer_messages(c0, rcb, which):
+    """Zero weights and biases: e' = e.  With integer messages the
+    consistent aggregate equals the R=1 integer sum bitwise (C0 blocks) or
+    to rounding of 1/3 (T-junctions)."""
+    from paper_2410_01657_amd.ops import layer_cfg, layer_forward
+    if which == "c0":
+        mesh, (dg, og, _) = c0[0].mesh, c0[1][8]
+    else:
+        mesh, (dg, og, _) = rcb
+    H = 32
+    _, o, names = layer_params(H, False)
+    p = {k: torch.zeros_like(_t(o[v])) for k, v in names.items()}
+    gid = dg.host.row_gid
+    msg = ((gid[dg.host.recv] + 3 * gid[dg.host.col]) % 17).astype(np.float32)
+    e = _t(np.repeat(msg[:, None], H, axis=1))
+    x = torch.zeros(dg.n_rows, H, device=DEV)
+    _, e_out, a_star = layer_forward(layer_cfg(H, False), p, dg, x, e)
+    assert torch.equal(e_out, e)
+    L = lattice_graph(mesh.npts)
+    ref = np.zeros(L.n)
+    np.add.at(ref, L.recv, (L.gid[L.recv] + 3 * L.gid[L.send]) % 17)
+    a = a_star.cpu().numpy()[:, 0]
+    if which == "c0":
+        assert np.array_equal(a, ref[gid].astype(np.float32))
+    else:
+        np.testing.assert_allclose(a, ref[gid], rtol=1e-6, atol=0)
+
+
+# ----------------------------------------------------- one-layer parity
+
+
+def _oracle_layer(o, spec, og, pairs, x, e, halo=True):
+    xs = split_rows(x.astype(np.float64), [0] + list(np.cumsum([G.n for G in og])))
+    es = split_rows(e.astype(np.float64), [0] + list(np.cumsum([G.e for G in og])))
+    xo, eo, cache = nmp_layer_fwd(o, 0, spec, og, pairs, xs, es, halo)
+    return np.concatenate(xo), np.concatenate(eo), np.concatenate(cache["a_star"]), cache, xs, es
+
+
+@pytest.mark.parametrize("H,ln,R,halo", [(32, False, 8, True), (32, True, 1, True), (64, True, 8, True),
+                                         (128, True, 8, True), (64, False, 8, False)])
+def test_layer_forward_fp32(c0, H, ln, R, halo):
+    from paper_2410_01657_amd.ops import layer_cfg, layer_forward
+    inp, gs = c0
+    dg, og, pairs = gs[R]
+    spec, o, names = layer_params(H, ln)
+    rng = np.random.default_rng(H + R)
+    x = rng.standard_normal((dg.n_rows, H)).astype(np.float32)
+    e = rng.standard_normal((dg.n_edges, H)).astype(np.float32)
+    xg, eg, ag = layer_forward(layer_cfg(H, ln, halo), _lib_params(o, names), dg, _t(x), _t(e))
+    xr, er, ar, *_ = _oracle_layer(o, spec, og, pairs, x, e, halo)
+    tol = 1e-5
+    assert normwise(ag.cpu().numpy(), ar) < tol
+    assert normwise(eg.cpu().numpy(), er) < tol
+    assert normwise(xg.cpu().numpy(), xr) < tol
+
+
+@pytest.mark.parametrize("H,ln", [(32, False), (64, True), (128, True)])
+def test_layer_forward_bf16(c0, H, ln):
+    from paper_2410_01657_amd.ops import layer_cfg, layer_forward
+    inp, gs = c0
+    dg, og, pairs = gs[8]
+    spec, o, names = layer_params(H, ln)
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal((dg.n_rows, H)).astype(np.float32)
+    e = rng.standard_normal((dg.n_edges, H)).astype(np.float32)
+    xg, eg, ag = layer_forward(layer_cfg(H, ln, gemm="bf16"), _lib_params(o, names), dg, _t(x), _t(e))
+    xr, er, ar, *_ = _oracle_layer(o, spec, og, pairs, x, e)
+    for got, ref in ((ag, ar), (eg, er), (xg, xr)):
+        err = normwise(got.cpu().numpy(), ref)
+        assert 1e-6 < err < 3e-2, err  # rounded (not silently FP32) and close
+
+
+def test_layer_forward_rcb(rcb):
+    from paper_2410_01657_amd.ops import layer_cfg, layer_forward
+    m, (dg, og, pairs) = rcb
+    H = 64
+    spec, o, names = layer_params(H, True)
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal((dg.n_rows, H)).astype(np.float32)
+    e = rng.standard_normal((dg.n_edges, H)).astype(np.float32)
+    xg, eg, ag = layer_forward(layer_cfg(H, True), _lib_params(o, names), dg, _t(x), _t(e))
+    xr, er, ar, *_ = _oracle_layer(o, spec, og, pairs, x, e)
+    assert normwise(ag.cpu().numpy(), ar) < 1e-5
+    assert normwise(xg.cpu().numpy(), xr) < 1e-5
+
+
+# ---------------------------------------------------- one-layer adjoint
+
+
+@pytest.mark.parametrize("H,ln,R,gemm", [(32, False, 8, "f32"), (64, True, 8, "f32"), (64, True, 1, "f32"),
+                                         (128, True, 8, "f32"), (64, True, 8, "bf16")])
+def test_layer_backward(c0, H, ln, R, gemm):
+    from paper_2410_01657_amd.ops import layer_backward, layer_cfg, layer_forward
+    inp, gs = c0
+    dg, og, pairs = gs[R]
+    spec, o, names = layer_params(H, ln)
+    rng = np.random.default_rng(11 + H)
+    x = rng.standard_normal((dg.n_rows, H)).astype(np.float32)
+    e = rng.standard_normal((dg.n_edges, H)).astype(np.float32)
+    gx = rng.standard_normal((dg.n_rows, H)).astype(np.float32)
+    ge = rng.standard_normal((dg.n_edges, H)).astype(np.float32)
+    cfg = layer_cfg(H, ln, gemm=gemm)
+    p = _lib_params(o, names)
+    _, _, a_star = layer_forward(cfg, p, dg, _t(x), _t(e))
+    g_x, g_e, grads = layer_backward(cfg, p, dg, _t(x), _t(e), a_star, _t(gx), _t(ge))
+    xr, er, ar, cache, xs, es = _oracle_layer(o, spec, og, pairs, x, e)
+    n_off = [0] + list(np.cumsum([G.n for G in og]))
+    e_off = [0] + list(np.cumsum([G.e for G in og]))
+    ogr = {}
+    gxs, ges = nmp_layer_bwd(o, 0, spec, og, pairs, cache, split_rows(gx.astype(np.float64), n_off),
+                             split_rows(ge.astype(np.float64), e_off), ogr)
+    tol = 1e-4 if gemm == "f32" else 5e-2
+    assert normwise(g_x.cpu().numpy(), np.concatenate(gxs)) < tol
+    assert normwise(g_e.cpu().numpy(), np.concatenate(ges)) < tol
+    for k, v in names.items():
+        err = normwise(grads[k].cpu().numpy(), ogr[v])
+        assert err < tol, (k, err)
+
+
+def test_layer_deterministic(c0):
+    from paper_2410_01657_amd.ops import layer_backward, layer_cfg, layer_forward
+    inp, gs = c0
+    dg, og, pairs = gs[8]
+    H = 64
+    spec, o, names = layer_params(H, True)
+    rng = np.random.default_rng(0)
+    x, e = _t(rng.standard_normal((dg.n_rows, H))), _t(rng.standard_normal((dg.n_edges, H)))
+    gx, ge = _t(rng.standard_normal((dg.n_rows, H))), _t(rng.standard_normal((dg.n_edges, H)))
+    cfg = layer_cfg(H, True)
+    p = _lib_params(o, names)
+    runs = []
+    for _ in range(2):
+        xo, eo, a = layer_forward(cfg, p, dg, x, e)
+        g = layer_backward(cfg, p, dg, x, e, a, gx, ge)
+        runs.append([xo, eo, a, g[0], g[1]] + [g[2][k] for k in sorted(names)])
+    for a, b in zip(*runs):
+        assert torch.equal(a, b)
