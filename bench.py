@@ -1,0 +1,207 @@
+"""Benchmark: consistent message-passing fwd+bwd edges/s on one MI355X.
+
+Workload: 16^3 spectral elements of order 5 (81^3 = 531,441 GLL nodes,
+3,149,280 directed edges), split into 16 z-slab sub-graphs with halos
+(629,856 rows, 3,538,080 sub-graph edges), encode-process-decode model with
+4 consistent NMP layers, hidden width 64, LayerNorm, consistent MSE (Eq. 6)
+against the field shifted by one node.  Seeded synthetic Taylor-Green-like
+input, Xavier-uniform weights.
+
+One step = the whole model forward, loss and backward (every layer's edge
+update, aggregation, halo sum, node update and their adjoints, plus the
+encoders, decoder and loss).  value = global directed edges x layers / step
+time, for the BF16-GEMM path; the FP32 path is measured beside it.
+
+    python bench.py [--gpus 1] [--steps 10] [--warmup 3]
+
+Prints one JSON line.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+
+def _parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 comparison path")
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--sample-nodes", type=int, default=24, help="nodes for the error vs FP64")
+    return ap.parse_args()
+
+
+def run_path(gemm, spec, params, prob, steps, warmup):
+    """Time `steps` full fwd+bwd steps; returns timing, per-kernel stats, outputs."""
+    import ctypes as C
+
+    import torch
+
+    from paper_2410_01657_amd._lib import call
+    from paper_2410_01657_amd.model import ConsistentGNN
+
+    model = ConsistentGNN(spec, params, "cuda", gemm=gemm).requires_grad_(True)
+
+    def step():
+        for t in model.params.values():
+            t.grad = None
+        Y = model.forward(prob.dg, prob.X, prob.E0)
+        loss = model.loss(prob.dg, Y, prob.T)
+        loss.backward()
+        return Y, loss
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    call("mp_profile_enable", 1)
+    stream = torch.cuda.current_stream()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for _ in range(steps):
+        Y, loss = step()
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / steps
+    kernels = {}
+    for name in ("pack", "proj", "edge_fwd", "halo", "halo_adj", "node_fwd", "node_bwd", "edge_bwd",
+                 "gq", "wreduce", "mlp_fwd", "mlp_bwd", "edge_inputs", "loss"):
+        tot, n = C.c_double(), C.c_int64()
+        call("mp_profile_read", name.encode(), C.byref(tot), C.byref(n))
+        if n.value:
+            kernels[name] = {"ms_total": tot.value / steps, "launches_per_step": n.value / steps,
+                             "ms_avg": tot.value / n.value}
+    call("mp_profile_enable", 0)
+    return ms, kernels, Y.detach(), float(loss.detach().cpu())
+
+
+def cpu_baseline(cfg, inp, prob_host, n_layers, sample_gids, outs):
+    """The FP64 oracle as it stands, timed on a bounded sample: full model
+    fwd+bwd on the first sub-graph alone; plus the oracle's exact outputs
+    at sampled nodes, which state the GPU paths' error vs FP64."""
+    from threadpoolctl import threadpool_info
+
+    from oracle.ball import ball_output
+    from oracle.graph import partition_graph
+    from oracle.nmp import consistent_loss, edge_inputs, model_bwd, model_fwd
+
+    keep = inp.elem_part == 0
+    mesh = inp.mesh
+    (G,), _ = partition_graph(mesh.elem_gid[keep], mesh.P, np.zeros(int(keep.sum()), np.int32), 1)
+    X = inp.field.astype(np.float64)[G.gid]
+    T = inp.target.astype(np.float64)[G.gid]
+    E0 = edge_inputs(G, mesh.pos)
+    t = time.perf_counter()
+    Y, cache = model_fwd(inp.params, cfg.spec, [G], {}, [X], [E0])
+    L, gY, _ = consistent_loss(Y, [T], [G])
+    model_bwd(inp.params, cfg.spec, [G], {}, cache, gY)
+    dt = time.perf_counter() - t
+    threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    ref = np.stack([ball_output(inp.params, cfg.spec, mesh, inp.field, int(c)) for c in sample_gids])
+    errs = {}
+    for name, Ys in outs.items():
+        d = np.abs(Ys - ref)
+        errs[name] = {"max_rel": float(d.max() / np.abs(ref).max()),
+                      "mean_rel": float(d.mean() / np.abs(ref).mean())}
+    base = {"value": G.e * n_layers / dt, "unit": "edges/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"full model fwd+bwd (FP64 NumPy) on sub-graph 0 of 16: {G.n} rows, {G.e} edges, "
+                      f"{n_layers} layers, {dt:.1f} s"}
+    return base, errs
+
+
+def main():
+    a = _parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
+                          "n_gpus": a.gpus}))
+        sys.exit(2)
+    import torch
+
+    from mpinputs import CONFIGS, make_inputs
+    from paper_2410_01657_amd.model import Problem
+    from paper_2410_01657_amd.roofline import PEAK, PEAK_HBM, bound_of, layer_kernels
+
+    cfg = CONFIGS["C1"]
+    spec = cfg.spec
+    inp = make_inputs(cfg, base_seed=a.seed)
+    prob = Problem(inp.mesh, inp.field, inp.target, inp.elem_part, cfg.R, "cuda")
+    hg = prob.dg.host
+    n = inp.mesh.npts[0]
+    E_global = 6 * n * n * (n - 1)
+    N, E, G, M = hg.n_rows, hg.n_edges, hg.n_groups, int(hg.member.shape[0])
+
+    rng = np.random.default_rng(a.seed + 1)
+    sample_gids = rng.choice(inp.mesh.n_gid, size=a.sample_nodes, replace=False)
+    # a row holding each sampled id (the first copy)
+    row_of = {}
+    for r, g in enumerate(hg.row_gid):
+        row_of.setdefault(int(g), r)
+    sample_rows = np.array([row_of[int(g)] for g in sample_gids])
+
+    paths = ["bf16"] + ([] if a.no_fp32 else ["f32"])
+    res, outs = {}, {}
+    for gemm in paths:
+        ms, kern, Y, loss = run_path(gemm, spec, inp.params, prob, a.steps, a.warmup)
+        res[gemm] = {"ms": ms, "kernels": kern, "loss": loss}
+        outs[gemm] = Y.cpu().numpy()[sample_rows].astype(np.float64)
+        del Y
+        torch.cuda.empty_cache()
+
+    main_path = res["bf16"]
+    value = E_global * spec.n_layers / (main_path["ms"] * 1e-3)
+    # dominant kernel of the main path and its roofline
+    work = layer_kernels(N, E, G, M, spec.H)
+    kern = main_path["kernels"]
+    dom = max((k for k in kern if k in work), key=lambda k: kern[k]["ms_total"])
+    w = work[dom]
+    bnd = bound_of(w, "bf16")
+    avg_s = kern[dom]["ms_avg"] * 1e-3
+    if bnd == "hbm":
+        roof = {"bound": "hbm", "achieved": w.bytes / avg_s / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s"}
+    else:
+        roof = {"bound": "mfma", "achieved": w.flops / avg_s / 1e12, "peak": PEAK["bf16"] / 1e12,
+                "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = dom
+    roof["ms_avg"] = kern[dom]["ms_avg"]
+
+    line = {
+        "metric": "MP-layer fwd+bwd edges/sec, BF16-MFMA vs FP32, at stated rel. error vs FP64",
+        "value": value,
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": main_path["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": "C1 mesh fwd+bwd: 16^3 elements P=5 (531441 nodes, 3149280 edges), "
+                               "R=16 z-slabs with halos, 4 layers, H=64, LayerNorm, consistent MSE",
+                   "sub_graph_rows": N, "sub_graph_edges": E, "halo_groups": G, "halo_members": M,
+                   "global_edges": E_global, "layers": spec.n_layers, "H": spec.H},
+        "roofline": roof,
+    }
+    if "f32" in res:
+        line["fp32"] = {"value": E_global * spec.n_layers / (res["f32"]["ms"] * 1e-3),
+                        "ms_per_step": res["f32"]["ms"]}
+        line["bf16_over_fp32"] = res["f32"]["ms"] / main_path["ms"]
+    line["kernels"] = {g: {k: round(v["ms_total"], 4) for k, v in res[g]["kernels"].items()} for g in res}
+    if not a.no_cpu_baseline:
+        base, errs = cpu_baseline(cfg, inp, hg, spec.n_layers, sample_gids, outs)
+        line["cpu_baseline"] = base
+        line["rel_error_vs_fp64"] = errs
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -242,6 +242,18 @@ int mp_consistent_mse(int64_t n_rows, int32_t F, const float* Y, const float* T,
                       void* ws, size_t ws_bytes, mp_stream_t stream);
 int mp_consistent_mse_workspace_size(int64_t n_rows, size_t* bytes);
 
+/* ---------------------------------------------------------------------
+ * Measurement hooks.  While profiling is on, every kernel launch made by
+ * the entry points above is bracketed by two HIP events recorded on the
+ * launch's own stream.  mp_profile_enable clears the records (and turns
+ * recording on or off); mp_profile_read waits for and sums the elapsed
+ * times of one kernel's launches recorded since then.  Kernel names:
+ * pack, proj, edge_fwd, halo, halo_adj, node_fwd, node_bwd, edge_bwd, gq,
+ * wreduce, mlp_fwd, mlp_bwd, edge_inputs, loss.
+ * ------------------------------------------------------------------- */
+int mp_profile_enable(int on);
+int mp_profile_read(const char* kernel, double* total_ms, int64_t* launches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -82,6 +82,8 @@ _SIGS = {
     "mp_edge_inputs": (c_i32, [P(MpDevGraph), vp, vp, vp]),
     "mp_consistent_mse_workspace_size": (c_i32, [c_i64, P(C.c_size_t)]),
     "mp_consistent_mse": (c_i32, [c_i64, c_i32, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]),
+    "mp_profile_enable": (c_i32, [c_i32]),
+    "mp_profile_read": (c_i32, [C.c_char_p, P(C.c_double), P(c_i64)]),
 }
 EXPORTED = sorted(_SIGS)
 

@@ -1,0 +1,51 @@
+"""Algorithmic work of each kernel of one layer: the bytes it must move
+through HBM and the flops it must execute, independent of how it is built.
+
+Units: N rows (node copies over all sub-graphs), E directed sub-graph edges,
+G halo groups with M members, hidden width H, FP32 node and edge states.
+Index arrays: int32 receiver and sender per edge plus a uint8 degree;
+int32 reverse-edge and row-offset arrays where a kernel follows them.
+Each row or edge is counted once per kernel even when it is gathered several
+times (repeat gathers are cache traffic, not algorithmic traffic).
+
+Flops count the MLP products (2 per multiply-add); elementwise work (ELU,
+LayerNorm, the 1/d sums) is below 1% and left out.
+"""
+
+from dataclasses import dataclass
+
+# MI355X published peaks
+PEAK_HBM = 8.0e12          # bytes/s
+PEAK = {"f32": 157.3e12, "bf16": 2.5e15}   # dense MFMA flop/s by operand type
+
+
+@dataclass(frozen=True)
+class Work:
+    bytes: float
+    flops: float
+
+
+def layer_kernels(N, E, G, M, H):
+    """Per launch, for one layer; keys match the library's profile names."""
+    f = 4.0  # bytes per FP32 value
+    return {
+        # x -> P = W1a x + b1, Q = W1b x
+        "proj": Work(N * 3 * H * f, N * 2 * 2 * H * H),
+        # e, P_i, Q_j -> e', a ; per edge 2 H x H products
+        "edge_fwd": Work(E * (2 * H * f + 9) + N * 3 * H * f, E * 2 * 2 * H * H),
+        # every member row read and written once, plus the plan
+        "halo": Work(M * 2 * H * f + 4 * (M + G + 1), 0.0),
+        # [a*, x] -> x' ; products 2H x H and H x H
+        "node_fwd": Work(N * 3 * H * f, N * 2 * 3 * H * H),
+        # a*, x, g_x' -> g_a*, g_x ; recompute (3H^2) + input grads (3H^2) + weight grads (3H^2)
+        "node_bwd": Work(N * 5 * H * f, N * 2 * 9 * H * H),
+        # e, g_e', P_i, Q_j, g_a_i -> g_e, g_h, g_P ; 6 H x H products per edge
+        "edge_bwd": Work(E * (4 * H * f + 9) + N * 4 * H * f, E * 2 * 6 * H * H),
+        # g_P, g_h (through reverse edges), x, g_x -> g_x ; 2 (2H x H) products per node
+        "gq": Work(E * (H * f + 4) + N * (4 * H * f + 4), N * 2 * 4 * H * H),
+    }
+
+
+def bound_of(work, gemm):
+    """'hbm' or 'mfma': whichever roof takes longer for this work."""
+    return "hbm" if work.bytes / PEAK_HBM >= work.flops / PEAK[gemm] else "mfma"
