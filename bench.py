@@ -35,7 +35,22 @@ def _parse():
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 comparison path")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--sample-nodes", type=int, default=24, help="nodes for the error vs FP64")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device copy (reference for HBM byte counters)")
     return ap.parse_args()
+
+
+def copy_calibration():
+    """A plain copy of a known size: FETCH_SIZE / WRITE_SIZE of this dispatch
+    calibrate the counters against 256 MiB read and 256 MiB written."""
+    import torch
+    n = 256 * 1024 * 1024 // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n * 4}), flush=True)
 
 
 def run_path(gemm, spec, params, prob, steps, warmup):
@@ -121,6 +136,9 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
                           "n_gpus": a.gpus}))
         sys.exit(2)
+    if a.copy_calibration:
+        copy_calibration()
+        return
     import torch
 
     from mpinputs import CONFIGS, make_inputs

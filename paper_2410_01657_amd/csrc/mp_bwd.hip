@@ -13,6 +13,7 @@
 // slabs in workgroup order.  Schedules are static, so the result is
 // bitwise reproducible.
 #include <algorithm>
+#include <type_traits>
 
 #include "mp_device.hpp"
 #include "mp_kernels.hpp"
@@ -20,58 +21,97 @@
 namespace mp {
 
 constexpr size_t kLdsLimit = 160 * 1024 - 1024;
-constexpr int kWaves = 4;  // waves per workgroup in the lock-step kernels
+constexpr int kWaves = 4;  // waves per workgroup in the row-MLP lock-step kernels
 
-// Row stride (floats) of an LDS staging tile of width W: 16 floats of
-// padding keep the transposed MFMA reads free of bank conflicts.
-template <int W>
-constexpr int tile_stride() { return W + 16; }
-template <int W>
-constexpr size_t tile_bytes() { return size_t(64) * tile_stride<W>() * 4; }
+// LDS staging of a ROWS-row block of a W-wide operand, transposed: element
+// (row r, feature f) sits at tile[f * RS + r], so the MFMA operands of the
+// weight-gradient products (rows along K) are contiguous 16-byte reads.
+// Each feature row is padded (4 floats, or 8 bf16 values) to spread banks.
+template <bool BF, int ROWS>
+struct Stg {
+  using T = typename std::conditional<BF, __bf16, float>::type;
+  static constexpr int RS = ROWS + (BF ? 8 : 4);
+};
+template <int W, bool BF, int ROWS = 64>
+constexpr size_t tile_bytes() { return size_t(W) * Stg<BF, ROWS>::RS * (BF ? 2 : 4); }
 
-template <int W>
-__device__ __forceinline__ void stage_row(float* __restrict__ tile, int row, int g, const float (&v)[W / 4]) {
+template <int W, bool BF, int ROWS = 64>
+__device__ __forceinline__ void stage_row(void* __restrict__ tile, int row, int g, const float (&v)[W / 4]) {
+  using T = typename Stg<BF, ROWS>::T;
+  T* t = reinterpret_cast<T*>(tile);
 #pragma unroll
-  for (int b = 0; b < W / 16; ++b)
-    *reinterpret_cast<float4*>(tile + row * tile_stride<W>() + 16 * b + 4 * g) =
-        make_float4(v[4 * b], v[4 * b + 1], v[4 * b + 2], v[4 * b + 3]);
+  for (int i = 0; i < W / 4; ++i) t[(16 * (i / 4) + 4 * g + (i % 4)) * Stg<BF, ROWS>::RS + row] = (T)v[i];
 }
 
-template <int GW, int AW>
-constexpr int dw_tiles_per_wave() { return ((GW / 16) * (AW / 16) + kWaves - 1) / kWaves; }
+template <int GW, int AW, int NW = kWaves>
+constexpr int dw_tiles_per_wave() { return ((GW / 16) * (AW / 16) + NW - 1) / NW; }
 
-// acc[n] += sum over the 64 staged rows of G[row][f] * A[row][k] for the
-// tiles t = wave + 4n (t = fb * (AW/16) + kb) this wave owns.
-template <int GW, int AW>
-__device__ __forceinline__ void dw_tiles(const float* __restrict__ G, const float* __restrict__ A,
-                                         v4f (&acc)[dw_tiles_per_wave<GW, AW>()], int wave, int lane) {
-  constexpr int NT = dw_tiles_per_wave<GW, AW>(), NTILE = (GW / 16) * (AW / 16), KBN = AW / 16;
-  constexpr int GS = tile_stride<GW>(), AS = tile_stride<AW>();
+// acc[n] += sum over the 16*NW staged rows of G[f][row] * A[k][row] for the
+// tiles t = wave + NW*n (t = fb * (AW/16) + kb) this wave owns.
+// FP32: v_mfma_f32_16x16x4f32, lane (i, kk) covering rows kk*4NW + s;
+// BF16: v_mfma_f32_16x16x32_bf16, lane (i, kk) covering rows 32t + 8kk + q.
+template <int GW, int AW, bool BF, int NW = kWaves>
+__device__ __forceinline__ void dw_tiles(const void* __restrict__ G, const void* __restrict__ A,
+                                         v4f (&acc)[dw_tiles_per_wave<GW, AW, NW>()], int wave, int lane) {
+  constexpr int NT = dw_tiles_per_wave<GW, AW, NW>(), NTILE = (GW / 16) * (AW / 16), KBN = AW / 16;
+  constexpr int ROWS = 16 * NW, RS = Stg<BF, ROWS>::RS;
+  const int li = lane & 15, kk = lane >> 4;
 #pragma unroll
   for (int n = 0; n < NT; ++n) {
-    const int t = wave + kWaves * n;
+    const int t = wave + NW * n;
     if (t < NTILE) {
       const int fb = t / KBN, kb = t % KBN;
+      if constexpr (BF) {
+        const __bf16* g = reinterpret_cast<const __bf16*>(G) + (16 * fb + li) * RS + 8 * kk;
+        const __bf16* a = reinterpret_cast<const __bf16*>(A) + (16 * kb + li) * RS + 8 * kk;
 #pragma unroll
-      for (int s = 0; s < 16; ++s) {
-        const int r = 4 * s + (lane >> 4);
-        const float av = G[r * GS + 16 * fb + (lane & 15)];
-        const float bv = A[r * AS + 16 * kb + (lane & 15)];
-        acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[n], 0, 0, 0);
+        for (int tt = 0; tt < ROWS / 32; ++tt) {
+          const v8bf gv = *reinterpret_cast<const v8bf*>(g + 32 * tt);
+          const v8bf av = *reinterpret_cast<const v8bf*>(a + 32 * tt);
+          acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gv, av, acc[n], 0, 0, 0);
+        }
+      } else {
+        const float* g = reinterpret_cast<const float*>(G) + (16 * fb + li) * RS + (ROWS / 4) * kk;
+        const float* a = reinterpret_cast<const float*>(A) + (16 * kb + li) * RS + (ROWS / 4) * kk;
+#pragma unroll
+        for (int q = 0; q < ROWS / 16; ++q) {
+          const float4 gv = *reinterpret_cast<const float4*>(g + 4 * q);
+          const float4 av = *reinterpret_cast<const float4*>(a + 4 * q);
+          acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv.x, av.x, acc[n], 0, 0, 0);
+          acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv.y, av.y, acc[n], 0, 0, 0);
+          acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv.z, av.z, acc[n], 0, 0, 0);
+          acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv.w, av.w, acc[n], 0, 0, 0);
+        }
       }
     }
   }
 }
 
+// Per-thread column sums of a staged W-wide tile: thread t adds the rows
+// [s*W/4... ) segment of feature t % W it owns (64*NW threads, W features,
+// 64*NW/W segments of ROWS*W/(64*NW) rows each).
+template <int W, bool BF, int NW>
+__device__ __forceinline__ float tile_colsum(const void* __restrict__ tile) {
+  constexpr int ROWS = 16 * NW, RS = Stg<BF, ROWS>::RS, NSEG = 64 * NW / W, LEN = ROWS / NSEG;
+  static_assert(NSEG >= 1 && LEN % 8 == 0, "segment layout");
+  using T = typename Stg<BF, ROWS>::T;
+  const int f = threadIdx.x % W, sg = threadIdx.x / W;
+  const T* p = reinterpret_cast<const T*>(tile) + f * RS + sg * LEN;
+  float s = 0.f;
+#pragma unroll
+  for (int r = 0; r < LEN; ++r) s += (float)p[r];
+  return s;
+}
+
 // Write the owned tiles into a row-major [GW][kcols] block of the slab
 // (kcols <= AW drops padded columns).
-template <int GW, int AW>
-__device__ __forceinline__ void dw_store(const v4f (&acc)[dw_tiles_per_wave<GW, AW>()], float* __restrict__ dst,
+template <int GW, int AW, int NW = kWaves>
+__device__ __forceinline__ void dw_store(const v4f (&acc)[dw_tiles_per_wave<GW, AW, NW>()], float* __restrict__ dst,
                                          int kcols, int wave, int lane) {
-  constexpr int NT = dw_tiles_per_wave<GW, AW>(), NTILE = (GW / 16) * (AW / 16), KBN = AW / 16;
+  constexpr int NT = dw_tiles_per_wave<GW, AW, NW>(), NTILE = (GW / 16) * (AW / 16), KBN = AW / 16;
 #pragma unroll
   for (int n = 0; n < NT; ++n) {
-    const int t = wave + kWaves * n;
+    const int t = wave + NW * n;
     if (t < NTILE) {
       const int fb = t / KBN, kb = t % KBN;
       const int k = 16 * kb + (lane & 15);
@@ -113,8 +153,17 @@ __device__ __forceinline__ void stage_frags(uint4* __restrict__ dst, const void*
 
 template <int H, bool BF>
 struct EdgeBwdCfg {
+  // BF16: eight waves per workgroup (128 staged rows) so the fragments are
+  // shared by more waves; FP32 (MFMA-bound) and H=128: four waves.
+  static constexpr int NW = (BF && H <= 64) ? 8 : 4;
+  static constexpr int ROWS = 16 * NW;
+  // BF16: bias / LayerNorm gradients are column sums of staged tiles instead
+  // of per-lane accumulators (frees registers); FP32 keeps them per lane.
+  static constexpr bool VEC = BF;
+  static constexpr int NTILES = VEC ? 6 : 4;
   static constexpr size_t FB = frag_bytes(H, H, BF);
-  static constexpr size_t STAGE = 4 * tile_bytes<H>();
+  static constexpr size_t TB = tile_bytes<H, BF, ROWS>();
+  static constexpr size_t STAGE = NTILES * TB;
   static constexpr bool LDS_FRAG = 4 * FB + STAGE <= kLdsLimit;
   static constexpr size_t LDS = STAGE + (LDS_FRAG ? 4 * FB : 0);
 };
@@ -128,14 +177,16 @@ struct EdgeBwdCfg {
 //   g_P[i] = sum of gh over i's incoming edges (segmented scan, as forward)
 //   g_h[k] = gh, summed per sender by k_gq through the reverse edges.
 template <int H, bool BF>
-__global__ __launch_bounds__(256) void k_edge_bwd(EdgeBwdArgs a) {
+__global__ __launch_bounds__((64 * EdgeBwdCfg<H, BF>::NW)) void k_edge_bwd(EdgeBwdArgs a) {
   using C = EdgeBwdCfg<H, BF>;
-  constexpr int NF = H / 4, MB = H / 16, NT = dw_tiles_per_wave<H, H>();
+  constexpr int NF = H / 4, MB = H / 16, NW = C::NW, ROWS = C::ROWS, NT = dw_tiles_per_wave<H, H, NW>();
   extern __shared__ uint4 smem[];
-  float* tG2 = reinterpret_cast<float*>(smem);
-  float* tA2 = tG2 + 64 * tile_stride<H>();
-  float* tG1 = tA2 + 64 * tile_stride<H>();
-  float* tA1 = tG1 + 64 * tile_stride<H>();
+  char* tG2 = reinterpret_cast<char*>(smem);
+  char* tA2 = tG2 + C::TB;
+  char* tG1 = tA2 + C::TB;
+  char* tA1 = tG1 + C::TB;
+  char* tGE = tA1 + C::TB;   // VEC: gE and gE * LN-normalised m, for dbeta / dgamma
+  char* tGM = tGE + C::TB;
   const char* fr;
   if constexpr (C::LDS_FRAG) {
     uint4* fl = smem + C::STAGE / 16;
@@ -145,41 +196,48 @@ __global__ __launch_bounds__(256) void k_edge_bwd(EdgeBwdArgs a) {
     fr = reinterpret_cast<const char*>(a.frag);
   }
   __syncthreads();
-  const char* fW1c = fr;
-  const char* fW2 = fr + C::FB;
-  const char* fW2t = fr + 2 * C::FB;
-  const char* fW1ct = fr + 3 * C::FB;
 
   const DevGraph& gr = a.g;
   const int lane = lane_id(), j = lane & 15, g = lane >> 4, wave = threadIdx.x / 64;
   const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
-  const int64_t nparts = (int64_t)gridDim.x * kWaves;
+  const int64_t nparts = (int64_t)gridDim.x * NW;
   int64_t r0, r1;
-  part_rows(gr.rowptr, gr.n_rows, nparts, blk * kWaves + wave, r0, r1);
+  part_rows(gr.rowptr, gr.n_rows, nparts, blk * NW + wave, r0, r1);
   const int64_t e0 = gr.rowptr[r0], e1 = gr.rowptr[r1];
   // lock-step trip count: the most 16-edge blocks of any wave here
   int64_t n_iter = 0;
-  for (int w = 0; w < kWaves; ++w) {
-    int64_t q0, q1;
-    part_rows(gr.rowptr, gr.n_rows, nparts, blk * kWaves + w, q0, q1);
-    n_iter = std::max<int64_t>(n_iter, (gr.rowptr[q1] - gr.rowptr[q0] + 15) / 16);
+  {
+    int64_t q0, q1, qa, qb;
+    part_rows(gr.rowptr, gr.n_rows, nparts, blk * NW, q0, qa);
+    for (int w = 0; w < NW; ++w) {
+      part_rows(gr.rowptr, gr.n_rows, nparts, blk * NW + w, qb, q1);
+      n_iter = std::max<int64_t>(n_iter, (gr.rowptr[q1] - gr.rowptr[qb] + 15) / 16);
+    }
+    (void)q0;
+    (void)qa;
   }
 
-  float b2v[NF], gam[NF], bet[NF];
+  float b2v[NF], gam[NF];
   load_vec<H>(a.b2, g, b2v);
-  if (a.ln) {
-    load_vec<H>(a.lng, g, gam);
-    load_vec<H>(a.lnb, g, bet);
-  }
+  if (a.ln) load_vec<H>(a.lng, g, gam);
   v4f acc2[NT], acc1[NT];
 #pragma unroll
   for (int n = 0; n < NT; ++n) acc2[n] = acc1[n] = v4f{0.f, 0.f, 0.f, 0.f};
-  float db2[NF], dga[NF], dbe[NF], carry[NF];
+  constexpr int NV = C::VEC ? 1 : NF;  // per-lane vector accumulators (FP32 path)
+  float db2[NV], dga[NV], dbe[NV], carry[NF];
 #pragma unroll
-  for (int i = 0; i < NF; ++i) db2[i] = dga[i] = dbe[i] = carry[i] = 0.f;
+  for (int i = 0; i < NV; ++i) db2[i] = dga[i] = dbe[i] = 0.f;
+#pragma unroll
+  for (int i = 0; i < NF; ++i) carry[i] = 0.f;
   int carry_key = 0;
 
   for (int64_t it = 0; it < n_iter; ++it) {
+    const char* frb = fr + opaque_zero();  // re-read the fragments each block
+    const char* fW1c = frb;
+    const char* fW2 = frb + C::FB;
+    const char* fW2t = frb + 2 * C::FB;
+    const char* fW1ct = frb + 3 * C::FB;
+    const int srow = wave * 16 + j;
     const int64_t k = e0 + it * 16 + j;
     const bool valid = k < e1;
     const int64_t kk = valid ? k : (e1 > e0 ? e1 - 1 : 0);
@@ -222,12 +280,20 @@ __global__ __launch_bounds__(256) void k_edge_bwd(EdgeBwdArgs a) {
 #pragma unroll
       for (int i = 0; i < NF; ++i) {
         const float xh = (mp[i] - mean) * rstd;
-        dga[i] += gE[i] * xh;
-        dbe[i] += gE[i];
+        if constexpr (!C::VEC) {
+          dga[i] += gE[i] * xh;
+          dbe[i] += gE[i];
+        } else {
+          t[i] = gE[i] * xh;
+        }
         const float gx = gE[i] * gam[i];
         s1 += gx;
         s2 += gx * xh;
         mp[i] = xh;
+      }
+      if constexpr (C::VEC) {
+        stage_row<H, BF, ROWS>(tGE, srow, g, gE);
+        stage_row<H, BF, ROWS>(tGM, srow, g, t);
       }
       s1 = row_sum(s1) * (1.f / H);
       s2 = row_sum(s2) * (1.f / H);
@@ -237,18 +303,20 @@ __global__ __launch_bounds__(256) void k_edge_bwd(EdgeBwdArgs a) {
 #pragma unroll
       for (int i = 0; i < NF; ++i) mp[i] = gE[i];
     }
+    if constexpr (!C::VEC) {
 #pragma unroll
-    for (int i = 0; i < NF; ++i) db2[i] += mp[i];
-    stage_row<H>(tG2, wave * 16 + j, g, mp);
-    stage_row<H>(tA2, wave * 16 + j, g, u);
+      for (int i = 0; i < NF; ++i) db2[i] += mp[i];
+    }
+    stage_row<H, BF, ROWS>(tG2, srow, g, mp);
+    stage_row<H, BF, ROWS>(tA2, srow, g, u);
     // gh = (W2^T gm) * ELU'(h); ELU'(h) = 1 for h > 0 else exp(h) = u + 1
 #pragma unroll
     for (int i = 0; i < NF; ++i) t[i] = 0.f;
     gemm<BF, MB, MB>(fW2t, mp, t, lane);
 #pragma unroll
     for (int i = 0; i < NF; ++i) t[i] *= (u[i] > 0.f ? 1.f : u[i] + 1.f);
-    stage_row<H>(tG1, wave * 16 + j, g, t);
-    stage_row<H>(tA1, wave * 16 + j, g, ev);
+    stage_row<H, BF, ROWS>(tG1, srow, g, t);
+    stage_row<H, BF, ROWS>(tA1, srow, g, ev);
     // g_e = gE + W1c^T gh
     gemm<BF, MB, MB>(fW1ct, t, gE, lane);
     if (valid) {
@@ -269,8 +337,15 @@ __global__ __launch_bounds__(256) void k_edge_bwd(EdgeBwdArgs a) {
     carry_key = from_prev_lane_i(key);
 
     __syncthreads();
-    dw_tiles<H, H>(tG2, tA2, acc2, wave, lane);
-    dw_tiles<H, H>(tG1, tA1, acc1, wave, lane);
+    dw_tiles<H, H, BF, NW>(tG2, tA2, acc2, wave, lane);
+    dw_tiles<H, H, BF, NW>(tG1, tA1, acc1, wave, lane);
+    if constexpr (C::VEC) {
+      db2[0] += tile_colsum<H, BF, NW>(tG2);
+      if (a.ln) {
+        dbe[0] += tile_colsum<H, BF, NW>(tGE);
+        dga[0] += tile_colsum<H, BF, NW>(tGM);
+      }
+    }
     __syncthreads();
   }
   for (int64_t r = r0 + (lane >> 2); r < r1; r += 16) {
@@ -280,19 +355,35 @@ __global__ __launch_bounds__(256) void k_edge_bwd(EdgeBwdArgs a) {
     }
   }
   float* slab = a.part + blockIdx.x * a.slab;
-  dw_store<H, H>(acc1, slab, H, wave, lane);
-  dw_store<H, H>(acc2, slab + H * H, H, wave, lane);
-  float* scratch = tG2;
-  block_sum_vec<H>(db2, scratch, slab + 2 * H * H, wave, lane);
-  block_sum_vec<H>(dga, scratch, slab + 2 * H * H + H, wave, lane);
-  block_sum_vec<H>(dbe, scratch, slab + 2 * H * H + 2 * H, wave, lane);
+  dw_store<H, H, NW>(acc1, slab, H, wave, lane);
+  dw_store<H, H, NW>(acc2, slab + H * H, H, wave, lane);
+  float* scratch = reinterpret_cast<float*>(tG2);
+  if constexpr (C::VEC) {
+    // thread (feature f, segment s) partial sums; add segments in order
+    constexpr int NSEG = 64 * NW / H;
+    float* v3[3] = {db2, dga, dbe};
+    for (int q = 0; q < 3; ++q) {
+      __syncthreads();
+      scratch[threadIdx.x] = v3[q][0];
+      __syncthreads();
+      if ((int)threadIdx.x < H) {
+        float sum = 0.f;
+        for (int sg = 0; sg < NSEG; ++sg) sum += scratch[sg * H + threadIdx.x];
+        slab[2 * H * H + q * H + threadIdx.x] = sum;
+      }
+    }
+  } else {
+    block_sum_vec<H>(db2, scratch, slab + 2 * H * H, wave, lane);
+    block_sum_vec<H>(dga, scratch, slab + 2 * H * H + H, wave, lane);
+    block_sum_vec<H>(dbe, scratch, slab + 2 * H * H + 2 * H, wave, lane);
+  }
 }
 
 template <int H, bool BF>
 static hipError_t launch_edge_bwd_t(const EdgeBwdArgs& a, int grid, hipStream_t s) {
   using C = EdgeBwdCfg<H, BF>;
   (void)hipFuncSetAttribute((const void*)k_edge_bwd<H, BF>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)C::LDS);
-  hipLaunchKernelGGL((k_edge_bwd<H, BF>), dim3(grid), dim3(256), C::LDS, s, a);
+  hipLaunchKernelGGL((k_edge_bwd<H, BF>), dim3(grid), dim3(64 * C::NW), C::LDS, s, a);
   return hipGetLastError();
 }
 
@@ -310,7 +401,7 @@ hipError_t launch_edge_bwd(const EdgeBwdArgs& a, int grid, hipStream_t s) {
 template <int H, bool BF>
 struct GqCfg {
   static constexpr size_t FB = frag_bytes(H, 2 * H, BF);
-  static constexpr size_t STAGE = tile_bytes<2 * H>() + tile_bytes<H>();
+  static constexpr size_t STAGE = tile_bytes<2 * H, BF>() + tile_bytes<H, BF>();
   static constexpr bool LDS_FRAG = FB + STAGE <= kLdsLimit;
   static constexpr size_t LDS = STAGE + (LDS_FRAG ? FB : 0);
 };
@@ -324,8 +415,8 @@ __global__ __launch_bounds__(256) void k_gq(GqArgs a) {
   using C = GqCfg<H, BF>;
   constexpr int NF = H / 4, MB = H / 16, NT = dw_tiles_per_wave<2 * H, H>();
   extern __shared__ uint4 smem[];
-  float* tG = reinterpret_cast<float*>(smem);
-  float* tA = tG + 64 * tile_stride<2 * H>();
+  char* tG = reinterpret_cast<char*>(smem);
+  char* tA = tG + tile_bytes<2 * H, BF>();
   const char* fr;
   if constexpr (C::LDS_FRAG) {
     uint4* fl = smem + C::STAGE / 16;
@@ -375,19 +466,19 @@ __global__ __launch_bounds__(256) void k_gq(GqArgs a) {
     }
 #pragma unroll
     for (int i = 0; i < NF; ++i) db1[i] += in[i];
-    stage_row<2 * H>(tG, wave * 16 + j, g, in);
-    stage_row<H>(tA, wave * 16 + j, g, xv);
+    stage_row<2 * H, BF>(tG, wave * 16 + j, g, in);
+    stage_row<H, BF>(tA, wave * 16 + j, g, xv);
     float gx[NF];
     load_row<H>(a.g_x + rr * H, g, gx);
     gemm<BF, MB, 2 * MB>(fr, in, gx, lane);
     if (valid) store_row<H>(a.g_x + row * H, g, gx);
     __syncthreads();
-    dw_tiles<2 * H, H>(tG, tA, acc, wave, lane);
+    dw_tiles<2 * H, H, BF>(tG, tA, acc, wave, lane);
     __syncthreads();
   }
   float* slab = a.part + blockIdx.x * a.slab;
   dw_store<2 * H, H>(acc, slab, H, wave, lane);
-  block_sum_vec<H>(db1, tG, slab + 2 * H * H, wave, lane);
+  block_sum_vec<H>(db1, reinterpret_cast<float*>(tG), slab + 2 * H * H, wave, lane);
 }
 
 template <int H, bool BF>
@@ -415,11 +506,12 @@ struct MlpBwdCfg {
   static constexpr size_t F1 = TOUT ? 0 : frag_bytes(H, H, BF);
   // fragments: W0, W1, W1^T, W0^T
   static constexpr size_t FRAG = 2 * F0 + 2 * F1;
-  static constexpr size_t STAGE0 = tile_bytes<H>() + tile_bytes<AW0>();
-  static constexpr size_t STAGE1 = TOUT ? 0 : 2 * tile_bytes<H>();
+  static constexpr size_t STAGE0 = tile_bytes<H, BF>() + tile_bytes<AW0, BF>();
+  static constexpr size_t STAGE1 = TOUT ? 0 : 2 * tile_bytes<H, BF>();
   static constexpr size_t STAGE = STAGE0 > STAGE1 ? STAGE0 : STAGE1;
-  static constexpr bool LDS_FRAG = FRAG + STAGE <= kLdsLimit;
-  static constexpr size_t LDS = STAGE + (LDS_FRAG ? FRAG : 0);
+  static constexpr size_t SMALL = (TIN || TOUT) ? 16 * H : 0;  // small W0 / W1, [.][4] or [4][H]
+  static constexpr bool LDS_FRAG = FRAG + STAGE + SMALL <= kLdsLimit;
+  static constexpr size_t LDS = STAGE + (LDS_FRAG ? FRAG : 0) + SMALL;
 };
 
 // Adjoint of k_mlp_fwd, forward recomputed per row block:
@@ -431,8 +523,8 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(MlpBwdArgs a) {
   constexpr int NF = H / 4, MB = H / 16, KB = TIN ? 1 : KIN / 16, AW0 = C::AW0;
   constexpr int NT1 = dw_tiles_per_wave<H, H>(), NT0 = dw_tiles_per_wave<H, AW0>();
   extern __shared__ uint4 smem[];
-  float* tG = reinterpret_cast<float*>(smem);
-  float* tA = tG + 64 * tile_stride<H>();
+  char* tG = reinterpret_cast<char*>(smem);
+  char* tA = tG + tile_bytes<H, BF>();
   const char* fr;
   if constexpr (C::LDS_FRAG) {
     uint4* fl = smem + C::STAGE / 16;
@@ -444,6 +536,10 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(MlpBwdArgs a) {
   } else {
     fr = nullptr;
   }
+  float* small = reinterpret_cast<float*>(reinterpret_cast<char*>(smem) + C::STAGE + (C::LDS_FRAG ? C::FRAG : 0));
+  if constexpr (TIN) stage_small(small, a.W0, H, a.k0);
+  if constexpr (TOUT)
+    for (int t = threadIdx.x; t < 4 * H; t += blockDim.x) small[t] = (t / H) < a.n_out ? a.W1[t] : 0.f;
   __syncthreads();
   const char* f0 = C::LDS_FRAG ? fr : reinterpret_cast<const char*>(a.frag0);
   const char* f1 = C::LDS_FRAG ? fr + C::F0 : reinterpret_cast<const char*>(a.frag1);
@@ -487,11 +583,7 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(MlpBwdArgs a) {
     if constexpr (TIN) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) in[k] = k < a.k0 ? a.src0[rr * a.k0 + k] : 0.f;
-#pragma unroll
-      for (int i = 0; i < NF; ++i) {
-        const int f = 16 * (i / 4) + 4 * g + (i % 4);
-        for (int k = 0; k < a.k0; ++k) z[i] += a.W0[f * a.k0 + k] * in[k];
-      }
+      small_in_linear<H>(small, in, g, z);
     } else {
       if constexpr (KIN == 2 * H) {
         float t0[NF], t1[NF];
@@ -517,11 +609,13 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(MlpBwdArgs a) {
 #pragma unroll
       for (int o = 0; o < 4; ++o) go[o] = (o < NO && valid) ? a.g_out[rr * NO + o] : 0.f;
 #pragma unroll
-      for (int i = 0; i < NF; ++i) {
-        const int f = 16 * (i / 4) + 4 * g + (i % 4);
-        float s = 0.f;
-        for (int o = 0; o < NO; ++o) s += a.W1[o * H + f] * go[o];
-        gu[i] = s;
+      for (int i = 0; i < NF; ++i) gu[i] = 0.f;
+#pragma unroll
+      for (int o = 0; o < 4; ++o) {
+        float w[NF];
+        load_vec<H>(small + o * H, g, w);
+#pragma unroll
+        for (int i = 0; i < NF; ++i) gu[i] += w[i] * go[o];
       }
 #pragma unroll
       for (int o = 0; o < 4; ++o)
@@ -565,10 +659,10 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(MlpBwdArgs a) {
 #pragma unroll
       for (int i = 0; i < NF; ++i) db1[i] += y[i];
       // phase 1: dW1 += gy u^T
-      stage_row<H>(tG, wave * 16 + j, g, y);
-      stage_row<H>(tA, wave * 16 + j, g, u);
+      stage_row<H, BF>(tG, wave * 16 + j, g, y);
+      stage_row<H, BF>(tA, wave * 16 + j, g, u);
       __syncthreads();
-      dw_tiles<H, H>(tG, tA, acc1, wave, lane);
+      dw_tiles<H, H, BF>(tG, tA, acc1, wave, lane);
       __syncthreads();
 #pragma unroll
       for (int i = 0; i < NF; ++i) gu[i] = 0.f;
@@ -579,19 +673,19 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(MlpBwdArgs a) {
     for (int i = 0; i < NF; ++i) gu[i] *= (u[i] > 0.f ? 1.f : u[i] + 1.f);
 #pragma unroll
     for (int i = 0; i < NF; ++i) db0[i] += gu[i];
-    stage_row<H>(tG, wave * 16 + j, g, gu);
+    stage_row<H, BF>(tG, wave * 16 + j, g, gu);
     if constexpr (TIN) {
       float in16[4] = {0.f, 0.f, 0.f, 0.f};  // lane group g holds input features 4g..4g+3
       if (g == 0) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) in16[k] = in[k];
       }
-      stage_row<16>(tA, wave * 16 + j, g, in16);
+      stage_row<16, BF>(tA, wave * 16 + j, g, in16);
     } else {
-      stage_row<KIN>(tA, wave * 16 + j, g, in);
+      stage_row<KIN, BF>(tA, wave * 16 + j, g, in);
     }
     __syncthreads();
-    dw_tiles<H, AW0>(tG, tA, acc0, wave, lane);
+    dw_tiles<H, AW0, BF>(tG, tA, acc0, wave, lane);
     __syncthreads();
     // ---- input gradient
     if constexpr (!TIN) {
@@ -625,7 +719,7 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(MlpBwdArgs a) {
   float* slab = a.part + blockIdx.x * a.slab;
   const int k0w = TIN ? a.k0 : KIN;
   dw_store<H, AW0>(acc0, slab, k0w, wave, lane);
-  float* scratch = tG;
+  float* scratch = reinterpret_cast<float*>(tG);
   block_sum_vec<H>(db0, scratch, slab + H * k0w, wave, lane);
   float* s1 = slab + H * k0w + H;
   if constexpr (TOUT) {
@@ -682,16 +776,40 @@ hipError_t launch_mlp_bwd(const MlpBwdArgs& a, int grid, hipStream_t s) {
 
 // ------------------------------------------------------ slab reduction
 
-// dst[r][col0 + c] = sum over slabs (in slab order) of slab[src_off + r*cols + c].
+// dst[r][col0 + c] = sum over slabs of slab[src_off + r*cols + c].  A block
+// covers 32 consecutive elements with 8 slab groups: thread (t, q) sums slabs
+// q, q+8, q+16, ... of element t (4 loads in flight), then the 8 group sums
+// are added in group order.  The order is fixed, so the result is bitwise
+// reproducible.
 __global__ __launch_bounds__(256) void k_wreduce(ReduceSegs segs) {
+  __shared__ float part[8][33];
   const ReduceSeg S = segs.seg[blockIdx.y];
   const int64_t n = (int64_t)S.rows * S.cols;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
-    const float* p = S.part + S.src_off + e;
-    float s = 0.f;
-    for (int b = 0; b < S.n_slabs; ++b) s += p[(int64_t)b * S.slab];
-    const int64_t r = e / S.cols, c = e % S.cols;
-    S.dst[r * S.ld + S.col0 + c] = s;
+  const int t = threadIdx.x & 31, q = threadIdx.x >> 5;
+  for (int64_t e0 = (int64_t)blockIdx.x * 32; e0 < n; e0 += (int64_t)gridDim.x * 32) {
+    const int64_t e = e0 + t;
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+    if (e < n) {
+      const float* p = S.part + S.src_off + e;
+      int b = q;
+      for (; b + 24 < S.n_slabs; b += 32) {
+        s0 += p[(int64_t)b * S.slab];
+        s1 += p[(int64_t)(b + 8) * S.slab];
+        s2 += p[(int64_t)(b + 16) * S.slab];
+        s3 += p[(int64_t)(b + 24) * S.slab];
+      }
+      for (; b < S.n_slabs; b += 8) s0 += p[(int64_t)b * S.slab];
+    }
+    part[q][t] = (s0 + s1) + (s2 + s3);
+    __syncthreads();
+    if (q == 0 && e < n) {
+      float s = 0.f;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) s += part[k][t];
+      const int64_t r = e / S.cols, c = e % S.cols;
+      S.dst[r * S.ld + S.col0 + c] = s;
+    }
+    __syncthreads();
   }
 }
 
@@ -699,7 +817,7 @@ hipError_t launch_wreduce(const ReduceSegs& segs, hipStream_t s) {
   if (segs.n <= 0) return hipSuccess;
   int64_t mx = 0;
   for (int i = 0; i < segs.n; ++i) mx = std::max<int64_t>(mx, (int64_t)segs.seg[i].rows * segs.seg[i].cols);
-  const int grid = (int)std::min<int64_t>((mx + 255) / 256, 512);
+  const int grid = (int)std::min<int64_t>((mx + 31) / 32, 1024);
   hipLaunchKernelGGL(k_wreduce, dim3(grid, segs.n), dim3(256), 0, s, segs);
   return hipGetLastError();
 }

@@ -131,10 +131,22 @@ __device__ __forceinline__ void gemm(const void* frag, const float (&in)[4 * KB]
 // Bytes of the packed fragments of an M x K matrix.
 __host__ __device__ constexpr size_t frag_bytes(int M, int K, bool bf) { return size_t(M) * K * (bf ? 2 : 4); }
 
+// An opaque zero: adding it to an LDS offset inside a loop keeps the
+// compiler from hoisting every weight-fragment read out of the loop (which
+// would pin the whole matrix in registers and cut occupancy).
+__device__ __forceinline__ int opaque_zero() {
+  int z = 0;
+  asm volatile("" : "+v"(z));
+  return z;
+}
+
 // --------------------------------------------------- elementwise helpers
 
-__device__ __forceinline__ float elu(float z) { return z > 0.f ? z : expm1f(z); }
-__device__ __forceinline__ float elu_deriv(float z) { return z > 0.f ? 1.f : expf(z); }
+// ELU with alpha = 1.  The negative branch uses the hardware exponential
+// (v_exp_f32 on a prescaled argument, a few ulp): exp(z) - 1 is then off by
+// at most ~1e-7 in absolute terms for z <= 0, far below FP32 tolerances.
+__device__ __forceinline__ float elu(float z) { return z > 0.f ? z : __expf(z) - 1.f; }
+__device__ __forceinline__ float elu_deriv(float z) { return z > 0.f ? 1.f : __expf(z); }
 
 // Sum over the four lanes that share a row (lane groups g = 0..3).
 __device__ __forceinline__ float row_sum(float s) {
@@ -158,6 +170,29 @@ __device__ __forceinline__ void ln_stats(const float (&v)[W / 4], float eps, flo
   }
   const float var = row_sum(q) * (1.f / W);
   rstd = 1.f / sqrtf(var + eps);
+}
+
+// --------------------------------------------- small first/last Linears
+
+// Stage W[rows][k] (k <= 4) into LDS as [rows][4], zero padded, with the
+// whole block (callers synchronise afterwards).
+__device__ __forceinline__ void stage_small(float* __restrict__ dst, const float* __restrict__ W, int rows, int k) {
+  for (int t = threadIdx.x; t < rows * 4; t += blockDim.x) {
+    const int r = t >> 2, c = t & 3;
+    dst[t] = c < k ? W[r * k + c] : 0.f;
+  }
+}
+
+// z[f] += sum_k W0[f][k] in[k] for the lane's features, W0 staged as [H][4].
+template <int H>
+__device__ __forceinline__ void small_in_linear(const float* __restrict__ w0s, const float (&in)[4], int g,
+                                                float (&z)[H / 4]) {
+#pragma unroll
+  for (int i = 0; i < H / 4; ++i) {
+    const int f = 16 * (i / 4) + 4 * g + (i % 4);
+    const float4 w = *reinterpret_cast<const float4*>(w0s + 4 * f);
+    z[i] += w.x * in[0] + w.y * in[1] + w.z * in[2] + w.w * in[3];
+  }
 }
 
 // ------------------------------------------- segmented sums over 16 lanes

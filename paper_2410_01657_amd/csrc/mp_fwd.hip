@@ -150,13 +150,18 @@ __global__ __launch_bounds__(256) void k_edge_fwd(DevGraph gr, const float* __re
   constexpr bool LDS = 2 * FB <= kEdgeLdsBudget;
   extern __shared__ uint4 smem[];
   const char* fr;
+  // per-feature vectors (b2, LayerNorm gain and shift) live in LDS after the
+  // fragments and are re-read per block rather than held in registers
+  float* vecs = reinterpret_cast<float*>(reinterpret_cast<char*>(smem) + (LDS ? 2 * FB : 0));
+  for (int t = threadIdx.x; t < 3 * H; t += blockDim.x)
+    vecs[t] = t < H ? b2[t] : (ln ? (t < 2 * H ? lng[t - H] : lnb[t - 2 * H]) : 0.f);
   if constexpr (LDS) {
     stage_to_lds(smem, frag, 2 * FB);
-    __syncthreads();
     fr = reinterpret_cast<const char*>(smem);
   } else {
     fr = reinterpret_cast<const char*>(frag);
   }
+  __syncthreads();
   const int lane = lane_id(), j = lane & 15, g = lane >> 4;
   const int nw = blockDim.x / 64;
   const int64_t wave = xcd_block(blockIdx.x, gridDim.x) * nw + threadIdx.x / 64;
@@ -164,18 +169,13 @@ __global__ __launch_bounds__(256) void k_edge_fwd(DevGraph gr, const float* __re
   part_rows(gr.rowptr, gr.n_rows, (int64_t)gridDim.x * nw, wave, r0, r1);
   const int64_t e0 = gr.rowptr[r0], e1 = gr.rowptr[r1];
 
-  float bias2[NF], gam[NF], bet[NF];
-  load_vec<H>(b2, g, bias2);
-  if (ln) {
-    load_vec<H>(lng, g, gam);
-    load_vec<H>(lnb, g, bet);
-  }
   float carry[NF];
 #pragma unroll
   for (int i = 0; i < NF; ++i) carry[i] = 0.f;
   int carry_key = 0;
 
   for (int64_t base = e0; base < e1; base += 16) {
+    const char* frb = fr + opaque_zero();  // re-read the fragments each block
     const int64_t k = base + j;
     const bool valid = k < e1;
     const int64_t kk = valid ? k : e1 - 1;
@@ -192,16 +192,18 @@ __global__ __launch_bounds__(256) void k_edge_fwd(DevGraph gr, const float* __re
     load_row<H>(Q + (int64_t)sj * H, g, q);
 #pragma unroll
     for (int i = 0; i < NF; ++i) h[i] += q[i];
-    gemm<BF, MB, MB>(fr, ev, h, lane);
+    gemm<BF, MB, MB>(frb, ev, h, lane);
 #pragma unroll
     for (int i = 0; i < NF; ++i) h[i] = elu(h[i]);
     float m[NF];
-#pragma unroll
-    for (int i = 0; i < NF; ++i) m[i] = bias2[i];
-    gemm<BF, MB, MB>(fr + FB, h, m, lane);
+    const float* vb = vecs + opaque_zero();
+    load_vec<H>(vb, g, m);
+    gemm<BF, MB, MB>(frb + FB, h, m, lane);
     if (ln) {
-      float mean, rstd;
+      float mean, rstd, gam[NF], bet[NF];
       ln_stats<H>(m, eps, mean, rstd);
+      load_vec<H>(vb + H, g, gam);
+      load_vec<H>(vb + 2 * H, g, bet);
 #pragma unroll
       for (int i = 0; i < NF; ++i) m[i] = (m[i] - mean) * rstd * gam[i] + bet[i];
     }
@@ -236,7 +238,7 @@ static hipError_t launch_edge_fwd_t(const DevGraph& g, const float* P, const flo
                                     const void* frag, const float* b2, const float* lng, const float* lnb, int ln,
                                     float eps, float* e_out, float* a_out, int grid, hipStream_t s) {
   constexpr size_t FB = frag_bytes(H, H, BF);
-  const size_t lds = (2 * FB <= kEdgeLdsBudget) ? 2 * FB : 0;
+  const size_t lds = ((2 * FB <= kEdgeLdsBudget) ? 2 * FB : 0) + 3 * H * sizeof(float);
   if (lds > 64 * 1024)
     (void)hipFuncSetAttribute((const void*)k_edge_fwd<H, BF>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   hipLaunchKernelGGL((k_edge_fwd<H, BF>), dim3(grid), dim3(256), lds, s, g, P, Q, e_in, frag, b2, lng, lnb, ln,
@@ -309,16 +311,21 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(MlpFwdArgs a) {
   extern __shared__ uint4 smem[];
   const char* f0;
   const char* f1;
+  // small weights (W0 of a small input, W1 of a small output) after the fragments
+  float* small = reinterpret_cast<float*>(reinterpret_cast<char*>(smem) + (LDS ? F0 + F1 : 0));
+  if constexpr (TIN) stage_small(small, a.W0, H, a.k0);
+  if constexpr (TOUT)
+    for (int t = threadIdx.x; t < 4 * H; t += blockDim.x) small[t] = (t / H) < a.n_out ? a.W1[t] : 0.f;
   if constexpr (LDS) {
     if (F0) stage_to_lds(smem, a.frag0, F0);
     if (F1) stage_to_lds(smem + F0 / 16, a.frag1, F1);
-    __syncthreads();
     f0 = reinterpret_cast<const char*>(smem);
     f1 = f0 + F0;
   } else {
     f0 = reinterpret_cast<const char*>(a.frag0);
     f1 = reinterpret_cast<const char*>(a.frag1);
   }
+  __syncthreads();
   const int lane = lane_id(), j = lane & 15, g = lane >> 4;
   const int nw = blockDim.x / 64;
   const int64_t n = a.n_rows, nblk = (n + 15) / 16;
@@ -332,11 +339,7 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(MlpFwdArgs a) {
       float in[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) in[k] = k < a.k0 ? a.src0[rr * a.k0 + k] : 0.f;
-#pragma unroll
-      for (int i = 0; i < NF; ++i) {
-        const int f = 16 * (i / 4) + 4 * g + (i % 4);
-        for (int k = 0; k < a.k0; ++k) z[i] += a.W0[f * a.k0 + k] * in[k];
-      }
+      small_in_linear<H>(small, in, g, z);
     } else {
       float in[KIN / 4];
       if constexpr (KIN == 2 * H) {
@@ -357,9 +360,11 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(MlpFwdArgs a) {
     for (int i = 0; i < NF; ++i) z[i] = elu(z[i]);
     if constexpr (TOUT) {
       for (int o = 0; o < a.n_out; ++o) {
+        float w[NF];
+        load_vec<H>(small + o * H, g, w);
         float p = 0.f;
 #pragma unroll
-        for (int i = 0; i < NF; ++i) p += a.W1[o * H + 16 * (i / 4) + 4 * g + (i % 4)] * z[i];
+        for (int i = 0; i < NF; ++i) p += w[i] * z[i];
         p = row_sum(p);
         if (valid && g == 0) a.out[row * a.n_out + o] = p + a.b1[o];
       }
@@ -390,7 +395,7 @@ template <int H, int KIN, bool TIN, bool TOUT, bool BF>
 static hipError_t launch_mlp_fwd_t(const MlpFwdArgs& a, int grid, hipStream_t s) {
   constexpr size_t F0 = TIN ? 0 : frag_bytes(H, KIN, BF);
   constexpr size_t F1 = TOUT ? 0 : frag_bytes(H, H, BF);
-  const size_t lds = (F0 + F1 <= kRowMlpLdsBudget) ? F0 + F1 : 0;
+  const size_t lds = ((F0 + F1 <= kRowMlpLdsBudget) ? F0 + F1 : 0) + ((TIN || TOUT) ? 16 * H : 0);
   if (lds > 64 * 1024)
     (void)hipFuncSetAttribute((const void*)k_mlp_fwd<H, KIN, TIN, TOUT, BF>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)lds);
