@@ -1,29 +1,42 @@
 """Benchmark: consistent message-passing fwd+bwd edges/s on one MI355X.
 
-Workload: 16^3 spectral elements of order 5 (81^3 = 531,441 GLL nodes,
-3,149,280 directed edges), split into 16 z-slab sub-graphs with halos
-(629,856 rows, 3,538,080 sub-graph edges), encode-process-decode model with
-4 consistent NMP layers, hidden width 64, LayerNorm, consistent MSE (Eq. 6)
-against the field shifted by one node.  Seeded synthetic Taylor-Green-like
-input, Xavier-uniform weights.
+Default workload (C1 mesh): 16^3 spectral elements of order 5 (81^3 =
+531,441 GLL nodes, 3,149,280 directed edges), split into 16 z-slab
+sub-graphs with halos (629,856 rows, 3,538,080 sub-graph edges), an
+encode-process-decode model with 4 consistent NMP layers, hidden width 64,
+LayerNorm, and the consistent MSE (Eq. 6) against the field shifted by one
+node.  Seeded synthetic Taylor-Green-like input, Xavier-uniform weights.
+`--workload C3` (24^3 elements, H=128, one graph) and `--workload C4`
+(32^3 elements of order 7, 64 uneven sub-graphs) measure the other
+fwd+bwd workloads the same way.
 
 One step = the whole model forward, loss and backward (every layer's edge
 update, aggregation, halo sum, node update and their adjoints, plus the
 encoders, decoder and loss).  value = global directed edges x layers / step
-time, for the BF16-GEMM path; the FP32 path is measured beside it.
+time, for the BF16-GEMM path; the FP32 path is measured beside it.  The
+edge-kernel schedule is autotuned first (outside the timed region).
 
-    python bench.py [--gpus 1] [--steps 10] [--warmup 3]
+    python bench.py [--gpus 1] [--steps 10] [--warmup 3] [--workload C1]
 
 Prints one JSON line.
 """
 
 import argparse
 import json
-import os
 import sys
 import time
 
 import numpy as np
+
+WORKLOADS = {
+    "C1": {"desc": "C1 mesh fwd+bwd: 16^3 elements P=5 (531441 nodes, 3149280 edges), "
+                   "R=16 z-slabs with halos, 4 layers, H=64, LayerNorm, consistent MSE", "R": None},
+    "C3": {"desc": "C3 mesh fwd+bwd: 24^3 elements P=5 (1771561 nodes, 10541520 edges), "
+                   "one graph, 4 layers, H=128, LayerNorm, MSE", "R": 1},
+    "C4": {"desc": "C4 mesh fwd+bwd: 32^3 elements P=7 (11390625 nodes, 68040000 edges), "
+                   "64 uneven sub-graphs (seeded bisection) with halos, 4 layers, H=64, LayerNorm, "
+                   "consistent MSE", "R": None},
+}
 
 
 def _parse():
@@ -32,8 +45,10 @@ def _parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--workload", default="C1", choices=sorted(WORKLOADS))
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 comparison path")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-autotune", action="store_true", help="use the library's default schedule")
     ap.add_argument("--sample-nodes", type=int, default=24, help="nodes for the error vs FP64")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (reference for HBM byte counters)")
@@ -53,7 +68,11 @@ def copy_calibration():
     print(json.dumps({"copy_bytes": n * 4}), flush=True)
 
 
-def run_path(gemm, spec, params, prob, steps, warmup):
+KERNELS = ("pack", "tiles", "proj", "edge_fwd", "halo", "halo_adj", "node_fwd", "node_bwd", "edge_bwd",
+           "gq", "wreduce", "mlp_fwd", "mlp_bwd", "edge_inputs", "loss")
+
+
+def run_path(gemm, spec, params, prob, steps, warmup, schedule):
     """Time `steps` full fwd+bwd steps; returns timing, per-kernel stats, outputs."""
     import ctypes as C
 
@@ -62,7 +81,7 @@ def run_path(gemm, spec, params, prob, steps, warmup):
     from paper_2410_01657_amd._lib import call
     from paper_2410_01657_amd.model import ConsistentGNN
 
-    model = ConsistentGNN(spec, params, "cuda", gemm=gemm).requires_grad_(True)
+    model = ConsistentGNN(spec, params, "cuda", gemm=gemm, schedule=schedule).requires_grad_(True)
 
     def step():
         for t in model.params.values():
@@ -85,28 +104,33 @@ def run_path(gemm, spec, params, prob, steps, warmup):
     torch.cuda.synchronize()
     ms = t0.elapsed_time(t1) / steps
     kernels = {}
-    for name in ("pack", "proj", "edge_fwd", "halo", "halo_adj", "node_fwd", "node_bwd", "edge_bwd",
-                 "gq", "wreduce", "mlp_fwd", "mlp_bwd", "edge_inputs", "loss"):
+    for name in KERNELS:
         tot, n = C.c_double(), C.c_int64()
         call("mp_profile_read", name.encode(), C.byref(tot), C.byref(n))
         if n.value:
             kernels[name] = {"ms_total": tot.value / steps, "launches_per_step": n.value / steps,
                              "ms_avg": tot.value / n.value}
     call("mp_profile_enable", 0)
-    return ms, kernels, Y.detach(), float(loss.detach().cpu())
+    out = Y.detach(), float(loss.detach().cpu())
+    del model
+    return (ms, kernels) + out
 
 
-def cpu_baseline(cfg, inp, prob_host, n_layers, sample_gids, outs):
+def cpu_baseline(cfg, inp, n_layers, sample_gids, outs):
     """The FP64 oracle as it stands, timed on a bounded sample: full model
-    fwd+bwd on the first sub-graph alone; plus the oracle's exact outputs
+    fwd+bwd on the first sub-graph alone (for an unpartitioned workload, on
+    the elements of its first 1/16 z-slab); plus the oracle's exact outputs
     at sampled nodes, which state the GPU paths' error vs FP64."""
     from threadpoolctl import threadpool_info
 
+    from mpinputs import slab_partition
     from oracle.ball import ball_output
     from oracle.graph import partition_graph
     from oracle.nmp import consistent_loss, edge_inputs, model_bwd, model_fwd
 
-    keep = inp.elem_part == 0
+    part = (inp.elem_part if inp.elem_part.max() > 0 else
+            slab_partition(cfg.nel, 16 if cfg.nel[2] % 16 == 0 else 8))
+    keep = part == 0
     mesh = inp.mesh
     (G,), _ = partition_graph(mesh.elem_gid[keep], mesh.P, np.zeros(int(keep.sum()), np.int32), 1)
     X = inp.field.astype(np.float64)[G.gid]
@@ -125,8 +149,8 @@ def cpu_baseline(cfg, inp, prob_host, n_layers, sample_gids, outs):
         errs[name] = {"max_rel": float(d.max() / np.abs(ref).max()),
                       "mean_rel": float(d.mean() / np.abs(ref).mean())}
     base = {"value": G.e * n_layers / dt, "unit": "edges/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"full model fwd+bwd (FP64 NumPy) on sub-graph 0 of 16: {G.n} rows, {G.e} edges, "
-                      f"{n_layers} layers, {dt:.1f} s"}
+            "sample": f"full model fwd+bwd (FP64 NumPy) on one sub-graph (elements of part 0): {G.n} rows, "
+                      f"{G.e} edges, {n_layers} layers, {dt:.1f} s"}
     return base, errs
 
 
@@ -142,13 +166,16 @@ def main():
     import torch
 
     from mpinputs import CONFIGS, make_inputs
+    from paper_2410_01657_amd.autotune import tuned_schedule
     from paper_2410_01657_amd.model import Problem
     from paper_2410_01657_amd.roofline import PEAK, PEAK_HBM, bound_of, layer_kernels
 
-    cfg = CONFIGS["C1"]
+    wl = WORKLOADS[a.workload]
+    cfg = CONFIGS[a.workload]
     spec = cfg.spec
-    inp = make_inputs(cfg, base_seed=a.seed)
-    prob = Problem(inp.mesh, inp.field, inp.target, inp.elem_part, cfg.R, "cuda")
+    R = wl["R"] or cfg.R
+    inp = make_inputs(cfg, base_seed=a.seed, R=R)
+    prob = Problem(inp.mesh, inp.field, inp.target, inp.elem_part, R, "cuda")
     hg = prob.dg.host
     n = inp.mesh.npts[0]
     E_global = 6 * n * n * (n - 1)
@@ -156,16 +183,15 @@ def main():
 
     rng = np.random.default_rng(a.seed + 1)
     sample_gids = rng.choice(inp.mesh.n_gid, size=a.sample_nodes, replace=False)
-    # a row holding each sampled id (the first copy)
-    row_of = {}
-    for r, g in enumerate(hg.row_gid):
-        row_of.setdefault(int(g), r)
-    sample_rows = np.array([row_of[int(g)] for g in sample_gids])
+    order = np.argsort(hg.row_gid, kind="stable")
+    sample_rows = order[np.searchsorted(hg.row_gid[order], sample_gids)]
 
     paths = ["bf16"] + ([] if a.no_fp32 else ["f32"])
-    res, outs = {}, {}
+    res, outs, scheds = {}, {}, {}
     for gemm in paths:
-        ms, kern, Y, loss = run_path(gemm, spec, inp.params, prob, a.steps, a.warmup)
+        sched = None if a.no_autotune else tuned_schedule(prob.dg, spec.H, spec.layernorm, gemm)
+        scheds[gemm] = sched
+        ms, kern, Y, loss = run_path(gemm, spec, inp.params, prob, a.steps, a.warmup, sched)
         res[gemm] = {"ms": ms, "kernels": kern, "loss": loss}
         outs[gemm] = Y.cpu().numpy()[sample_rows].astype(np.float64)
         del Y
@@ -189,6 +215,7 @@ def main():
     roof["traffic"] = None
     roof["kernel"] = dom
     roof["ms_avg"] = kern[dom]["ms_avg"]
+    roof["algorithmic_GB"] = w.bytes / 1e9
 
     line = {
         "metric": "MP-layer fwd+bwd edges/sec, BF16-MFMA vs FP32, at stated rel. error vs FP64",
@@ -203,10 +230,9 @@ def main():
         "vs_baseline": None,
         "dtype": "bf16",
         "data": "synthetic",
-        "config": {"workload": "C1 mesh fwd+bwd: 16^3 elements P=5 (531441 nodes, 3149280 edges), "
-                               "R=16 z-slabs with halos, 4 layers, H=64, LayerNorm, consistent MSE",
-                   "sub_graph_rows": N, "sub_graph_edges": E, "halo_groups": G, "halo_members": M,
-                   "global_edges": E_global, "layers": spec.n_layers, "H": spec.H},
+        "config": {"workload": wl["desc"], "sub_graphs": hg.R, "sub_graph_rows": N, "sub_graph_edges": E,
+                   "halo_groups": G, "halo_members": M, "global_edges": E_global, "layers": spec.n_layers,
+                   "H": spec.H, "schedule": scheds},
         "roofline": roof,
     }
     if "f32" in res:
@@ -215,7 +241,7 @@ def main():
         line["bf16_over_fp32"] = res["f32"]["ms"] / main_path["ms"]
     line["kernels"] = {g: {k: round(v["ms_total"], 4) for k, v in res[g]["kernels"].items()} for g in res}
     if not a.no_cpu_baseline:
-        base, errs = cpu_baseline(cfg, inp, hg, spec.n_layers, sample_gids, outs)
+        base, errs = cpu_baseline(cfg, inp, spec.n_layers, sample_gids, outs)
         line["cpu_baseline"] = base
         line["rel_error_vs_fp64"] = errs
     print(json.dumps(line), flush=True)

@@ -152,6 +152,14 @@ typedef struct {
   int32_t halo;       /* 1: consistent (Eq. 4c-d); 0: "None" mode, halo skipped */
   int32_t gemm_dtype; /* MP_F32 or MP_BF16 (operands rounded to nearest even) */
   float ln_eps;
+  /* Schedule (0 = library default): edges per row-aligned tile of the edge
+   * kernels (16..4096), and the persistent workgroup counts of the forward
+   * and adjoint edge kernels (1..65536).  Results are bitwise reproducible
+   * for a fixed schedule; another schedule only regroups floating-point
+   * sums (block boundaries of the aggregation scan, weight-gradient slabs). */
+  int32_t tile_edges;
+  int32_t edge_grid;
+  int32_t edge_bwd_grid;
 } mp_layer_cfg;
 
 /* Parameters of one layer, device FP32.  Edge MLP: Linear(3H->H), ELU,

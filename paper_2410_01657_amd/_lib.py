@@ -26,7 +26,7 @@ class MpDevGraph(C.Structure):
 
 class MpLayerCfg(C.Structure):
     _fields_ = [("H", c_i32), ("layernorm", c_i32), ("halo", c_i32), ("gemm_dtype", c_i32),
-                ("ln_eps", c_f32)]
+                ("ln_eps", c_f32), ("tile_edges", c_i32), ("edge_grid", c_i32), ("edge_bwd_grid", c_i32)]
 
 
 LAYER_FIELDS = ["We1", "be1", "We2", "be2", "ge", "bge", "Wn1", "bn1", "Wn2", "bn2", "gn", "bgn"]

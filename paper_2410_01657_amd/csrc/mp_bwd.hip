@@ -127,7 +127,7 @@ __device__ __forceinline__ void dw_store(const v4f (&acc)[dw_tiles_per_wave<GW, 
 // Sum a per-lane row-block vector over all 64 rows of the workgroup (16
 // lanes x 4 waves) in a fixed order and write the W sums to dst.  Uses
 // `scratch` (at least 64*W floats of LDS); contains barriers.
-template <int W>
+template <int W, int NW = kWaves>
 __device__ __forceinline__ void block_sum_vec(const float (&v)[W / 4], float* __restrict__ scratch,
                                               float* __restrict__ dst, int wave, int lane) {
   const int j = lane & 15, g = lane >> 4;
@@ -137,8 +137,24 @@ __device__ __forceinline__ void block_sum_vec(const float (&v)[W / 4], float* __
   __syncthreads();
   for (int t = threadIdx.x; t < W; t += blockDim.x) {
     float s = 0.f;
-    for (int r = 0; r < 64; ++r) s += scratch[r * W + t];
+    for (int r = 0; r < 16 * NW; ++r) s += scratch[r * W + t];
     dst[t] = s;
+  }
+  __syncthreads();
+}
+
+// Fixed-order sum over the workgroup of one value per thread held by the
+// threads (feature t % W, segment t / W) of a column-sum pass; writes W sums.
+template <int W, int NW>
+__device__ __forceinline__ void block_sum_segments(float v, float* __restrict__ scratch, float* __restrict__ dst) {
+  constexpr int NSEG = 64 * NW / W;
+  __syncthreads();
+  scratch[threadIdx.x] = v;
+  __syncthreads();
+  if ((int)threadIdx.x < W) {
+    float sum = 0.f;
+    for (int sg = 0; sg < NSEG; ++sg) sum += scratch[sg * W + threadIdx.x];
+    dst[threadIdx.x] = sum;
   }
   __syncthreads();
 }
@@ -165,7 +181,8 @@ struct EdgeBwdCfg {
   static constexpr size_t TB = tile_bytes<H, BF, ROWS>();
   static constexpr size_t STAGE = NTILES * TB;
   static constexpr bool LDS_FRAG = 4 * FB + STAGE <= kLdsLimit;
-  static constexpr size_t LDS = STAGE + (LDS_FRAG ? 4 * FB : 0);
+  static constexpr size_t VECS = 2 * H * sizeof(float);  // b2 and the LayerNorm gain
+  static constexpr size_t LDS = STAGE + (LDS_FRAG ? 4 * FB : 0) + VECS;
 };
 
 // Per edge k (receiver i, sender j), with the forward recomputed:
@@ -195,163 +212,164 @@ __global__ __launch_bounds__((64 * EdgeBwdCfg<H, BF>::NW)) void k_edge_bwd(EdgeB
   } else {
     fr = reinterpret_cast<const char*>(a.frag);
   }
+  float* vecs = reinterpret_cast<float*>(reinterpret_cast<char*>(smem) + C::LDS - C::VECS);
+  for (int t = threadIdx.x; t < 2 * H; t += blockDim.x) vecs[t] = t < H ? a.b2[t] : (a.ln ? a.lng[t - H] : 0.f);
   __syncthreads();
 
   const DevGraph& gr = a.g;
   const int lane = lane_id(), j = lane & 15, g = lane >> 4, wave = threadIdx.x / 64;
-  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
-  const int64_t nparts = (int64_t)gridDim.x * NW;
-  int64_t r0, r1;
-  part_rows(gr.rowptr, gr.n_rows, nparts, blk * NW + wave, r0, r1);
-  const int64_t e0 = gr.rowptr[r0], e1 = gr.rowptr[r1];
-  // lock-step trip count: the most 16-edge blocks of any wave here
-  int64_t n_iter = 0;
-  {
-    int64_t q0, q1, qa, qb;
-    part_rows(gr.rowptr, gr.n_rows, nparts, blk * NW, q0, qa);
-    for (int w = 0; w < NW; ++w) {
-      part_rows(gr.rowptr, gr.n_rows, nparts, blk * NW + w, qb, q1);
-      n_iter = std::max<int64_t>(n_iter, (gr.rowptr[q1] - gr.rowptr[qb] + 15) / 16);
-    }
-    (void)q0;
-    (void)qa;
-  }
-
-  float b2v[NF], gam[NF];
-  load_vec<H>(a.b2, g, b2v);
-  if (a.ln) load_vec<H>(a.lng, g, gam);
+  const TileSched ts = tile_sched(gr.n_tiles);
   v4f acc2[NT], acc1[NT];
 #pragma unroll
   for (int n = 0; n < NT; ++n) acc2[n] = acc1[n] = v4f{0.f, 0.f, 0.f, 0.f};
   constexpr int NV = C::VEC ? 1 : NF;  // per-lane vector accumulators (FP32 path)
-  float db2[NV], dga[NV], dbe[NV], carry[NF];
+  float db2[NV], dga[NV], dbe[NV];
 #pragma unroll
   for (int i = 0; i < NV; ++i) db2[i] = dga[i] = dbe[i] = 0.f;
-#pragma unroll
-  for (int i = 0; i < NF; ++i) carry[i] = 0.f;
-  int carry_key = 0;
 
-  for (int64_t it = 0; it < n_iter; ++it) {
-    const char* frb = fr + opaque_zero();  // re-read the fragments each block
-    const char* fW1c = frb;
-    const char* fW2 = frb + C::FB;
-    const char* fW2t = frb + 2 * C::FB;
-    const char* fW1ct = frb + 3 * C::FB;
-    const int srow = wave * 16 + j;
-    const int64_t k = e0 + it * 16 + j;
-    const bool valid = k < e1;
-    const int64_t kk = valid ? k : (e1 > e0 ? e1 - 1 : 0);
-    const int ri = gr.recv[kk];
-    const int sj = gr.col[kk];
-    const float inv_d = 1.f / (float)gr.mult[kk];
-    const int next = (k + 1 < e1) ? gr.recv[k + 1] : -1;
-    const bool last = valid && next != ri;
-    const int key = valid ? ri + 1 : -1;
-
-    // recompute the forward
-    float ev[NF], u[NF], t[NF];
-    load_row<H>(a.e_in + kk * H, g, ev);
-    load_row<H>(a.P + (int64_t)ri * H, g, u);
-    load_row<H>(a.Q + (int64_t)sj * H, g, t);
-#pragma unroll
-    for (int i = 0; i < NF; ++i) u[i] += t[i];
-    gemm<BF, MB, MB>(fW1c, ev, u, lane);
-#pragma unroll
-    for (int i = 0; i < NF; ++i) u[i] = elu(u[i]);
-    float mp[NF];
-#pragma unroll
-    for (int i = 0; i < NF; ++i) mp[i] = b2v[i];
-    gemm<BF, MB, MB>(fW2, u, mp, lane);
-
-    // gradient reaching e'
-    float gE[NF];
-    load_row<H>(a.g_a + (int64_t)ri * H, g, gE);
-    if (a.g_e_out) load_row<H>(a.g_e_out + kk * H, g, t);
-#pragma unroll
-    for (int i = 0; i < NF; ++i) {
-      const float v = gE[i] * inv_d + (a.g_e_out ? t[i] : 0.f);
-      gE[i] = valid ? v : 0.f;
+  // groups of NW consecutive tiles, one per wave, processed in lock step
+  for (int64_t tg = ts.t0 + ts.rank * NW; tg < ts.t1; tg += ts.nr * NW) {
+    const int64_t tile = tg + wave;
+    const bool has = tile < ts.t1;
+    const int64_t r0 = has ? gr.tile_r[tile] : 0, r1 = has ? gr.tile_r[tile + 1] : 0;
+    const int64_t e0 = has ? gr.tile_e[tile] : 0, e1 = has ? gr.tile_e[tile + 1] : 0;
+    // lock-step trip count: the most 16-edge blocks of any tile of the group
+    int64_t n_iter = 0;
+    for (int w = 0; w < NW; ++w) {
+      const int64_t tw = tg + w;
+      if (tw < ts.t1) n_iter = std::max<int64_t>(n_iter, (gr.tile_e[tw + 1] - gr.tile_e[tw] + 15) / 16);
     }
-    // LayerNorm adjoint (mp becomes the pre-LN gradient gm)
-    if (a.ln) {
-      float mean, rstd;
-      ln_stats<H>(mp, a.eps, mean, rstd);
-      float s1 = 0.f, s2 = 0.f;
+    float carry[NF];
+#pragma unroll
+    for (int i = 0; i < NF; ++i) carry[i] = 0.f;
+    int carry_key = 0;
+
+    for (int64_t it = 0; it < n_iter; ++it) {
+      const char* frb = fr + opaque_zero();  // re-read the fragments each block
+      const char* fW1c = frb;
+      const char* fW2 = frb + C::FB;
+      const char* fW2t = frb + 2 * C::FB;
+      const char* fW1ct = frb + 3 * C::FB;
+      const int srow = wave * 16 + j;
+      const int64_t k = e0 + it * 16 + j;
+      const bool valid = k < e1;
+      const int64_t kk = valid ? k : (e1 > e0 ? e1 - 1 : 0);
+      const int ri = gr.recv[kk];
+      const int sj = gr.col[kk];
+      const float inv_d = 1.f / (float)gr.mult[kk];
+      const int next = (k + 1 < e1) ? gr.recv[k + 1] : -1;
+      const bool last = valid && next != ri;
+      const int key = valid ? ri + 1 : -1;
+
+      // recompute the forward
+      float ev[NF], u[NF], t[NF];
+      load_row_nt<H>(a.e_in + kk * H, g, ev);
+      load_row<H>(a.P + (int64_t)ri * H, g, u);
+      load_row<H>(a.Q + (int64_t)sj * H, g, t);
+#pragma unroll
+      for (int i = 0; i < NF; ++i) u[i] += t[i];
+      gemm<BF, MB, MB>(fW1c, ev, u, lane);
+#pragma unroll
+      for (int i = 0; i < NF; ++i) u[i] = elu(u[i]);
+      float mp[NF];
+      const float* vb = vecs + opaque_zero();
+      load_vec<H>(vb, g, mp);
+      gemm<BF, MB, MB>(fW2, u, mp, lane);
+
+      // gradient reaching e'
+      float gE[NF];
+      load_row<H>(a.g_a + (int64_t)ri * H, g, gE);
+      if (a.g_e_out) load_row_nt<H>(a.g_e_out + kk * H, g, t);
 #pragma unroll
       for (int i = 0; i < NF; ++i) {
-        const float xh = (mp[i] - mean) * rstd;
-        if constexpr (!C::VEC) {
-          dga[i] += gE[i] * xh;
-          dbe[i] += gE[i];
-        } else {
-          t[i] = gE[i] * xh;
-        }
-        const float gx = gE[i] * gam[i];
-        s1 += gx;
-        s2 += gx * xh;
-        mp[i] = xh;
+        const float v = gE[i] * inv_d + (a.g_e_out ? t[i] : 0.f);
+        gE[i] = valid ? v : 0.f;
       }
-      if constexpr (C::VEC) {
-        stage_row<H, BF, ROWS>(tGE, srow, g, gE);
-        stage_row<H, BF, ROWS>(tGM, srow, g, t);
-      }
-      s1 = row_sum(s1) * (1.f / H);
-      s2 = row_sum(s2) * (1.f / H);
-#pragma unroll
-      for (int i = 0; i < NF; ++i) mp[i] = rstd * (gE[i] * gam[i] - s1 - mp[i] * s2);
-    } else {
-#pragma unroll
-      for (int i = 0; i < NF; ++i) mp[i] = gE[i];
-    }
-    if constexpr (!C::VEC) {
-#pragma unroll
-      for (int i = 0; i < NF; ++i) db2[i] += mp[i];
-    }
-    stage_row<H, BF, ROWS>(tG2, srow, g, mp);
-    stage_row<H, BF, ROWS>(tA2, srow, g, u);
-    // gh = (W2^T gm) * ELU'(h); ELU'(h) = 1 for h > 0 else exp(h) = u + 1
-#pragma unroll
-    for (int i = 0; i < NF; ++i) t[i] = 0.f;
-    gemm<BF, MB, MB>(fW2t, mp, t, lane);
-#pragma unroll
-    for (int i = 0; i < NF; ++i) t[i] *= (u[i] > 0.f ? 1.f : u[i] + 1.f);
-    stage_row<H, BF, ROWS>(tG1, srow, g, t);
-    stage_row<H, BF, ROWS>(tA1, srow, g, ev);
-    // g_e = gE + W1c^T gh
-    gemm<BF, MB, MB>(fW1ct, t, gE, lane);
-    if (valid) {
-      store_row<H>(a.g_e_in + k * H, g, gE);
-      store_row<H>(a.g_h + k * H, g, t);
-    }
-    // g_P: segmented sum of gh per receiver
-#pragma unroll
-    for (int i = 0; i < NF; ++i) {
-      float v = valid ? t[i] : 0.f;
-      if (j == 0 && key == carry_key) v += carry[i];
-      t[i] = v;
-    }
-    seg_scan16<NF>(t, key);
-    if (last) store_row<H>(a.g_P + (int64_t)ri * H, g, t);
-#pragma unroll
-    for (int i = 0; i < NF; ++i) carry[i] = from_prev_lane(t[i]);
-    carry_key = from_prev_lane_i(key);
-
-    __syncthreads();
-    dw_tiles<H, H, BF, NW>(tG2, tA2, acc2, wave, lane);
-    dw_tiles<H, H, BF, NW>(tG1, tA1, acc1, wave, lane);
-    if constexpr (C::VEC) {
-      db2[0] += tile_colsum<H, BF, NW>(tG2);
+      // LayerNorm adjoint (mp becomes the pre-LN gradient gm)
       if (a.ln) {
-        dbe[0] += tile_colsum<H, BF, NW>(tGE);
-        dga[0] += tile_colsum<H, BF, NW>(tGM);
+        float mean, rstd, gam[NF];
+        ln_stats<H>(mp, a.eps, mean, rstd);
+        load_vec<H>(vb + H, g, gam);
+        float s1 = 0.f, s2 = 0.f;
+#pragma unroll
+        for (int i = 0; i < NF; ++i) {
+          const float xh = (mp[i] - mean) * rstd;
+          if constexpr (!C::VEC) {
+            dga[i] += gE[i] * xh;
+            dbe[i] += gE[i];
+          } else {
+            t[i] = gE[i] * xh;
+          }
+          const float gx = gE[i] * gam[i];
+          s1 += gx;
+          s2 += gx * xh;
+          mp[i] = xh;
+        }
+        if constexpr (C::VEC) {
+          stage_row<H, BF, ROWS>(tGE, srow, g, gE);
+          stage_row<H, BF, ROWS>(tGM, srow, g, t);
+        }
+        s1 = row_sum(s1) * (1.f / H);
+        s2 = row_sum(s2) * (1.f / H);
+#pragma unroll
+        for (int i = 0; i < NF; ++i) mp[i] = rstd * (gE[i] * gam[i] - s1 - mp[i] * s2);
+      } else {
+#pragma unroll
+        for (int i = 0; i < NF; ++i) mp[i] = gE[i];
       }
+      if constexpr (!C::VEC) {
+#pragma unroll
+        for (int i = 0; i < NF; ++i) db2[i] += mp[i];
+      }
+      stage_row<H, BF, ROWS>(tG2, srow, g, mp);
+      stage_row<H, BF, ROWS>(tA2, srow, g, u);
+      // gh = (W2^T gm) * ELU'(h); ELU'(h) = 1 for h > 0 else exp(h) = u + 1
+#pragma unroll
+      for (int i = 0; i < NF; ++i) t[i] = 0.f;
+      gemm<BF, MB, MB>(fW2t, mp, t, lane);
+#pragma unroll
+      for (int i = 0; i < NF; ++i) t[i] *= (u[i] > 0.f ? 1.f : u[i] + 1.f);
+      stage_row<H, BF, ROWS>(tG1, srow, g, t);
+      stage_row<H, BF, ROWS>(tA1, srow, g, ev);
+      // g_e = gE + W1c^T gh
+      gemm<BF, MB, MB>(fW1ct, t, gE, lane);
+      if (valid) {
+        store_row_nt<H>(a.g_e_in + k * H, g, gE);
+        if constexpr (BF)
+          store_row_bf16_nt<H>(reinterpret_cast<__bf16*>(a.g_h) + k * H, g, t);
+        else
+          store_row_nt<H>(reinterpret_cast<float*>(a.g_h) + k * H, g, t);
+      }
+      // g_P: segmented sum of gh per receiver
+#pragma unroll
+      for (int i = 0; i < NF; ++i) {
+        float v = valid ? t[i] : 0.f;
+        if (j == 0 && key == carry_key) v += carry[i];
+        t[i] = v;
+      }
+      seg_scan16<NF>(t, key);
+      if (last) store_row<H>(a.g_P + (int64_t)ri * H, g, t);
+#pragma unroll
+      for (int i = 0; i < NF; ++i) carry[i] = from_prev_lane(t[i]);
+      carry_key = from_prev_lane_i(key);
+
+      __syncthreads();
+      dw_tiles<H, H, BF, NW>(tG2, tA2, acc2, wave, lane);
+      dw_tiles<H, H, BF, NW>(tG1, tA1, acc1, wave, lane);
+      if constexpr (C::VEC) {
+        db2[0] += tile_colsum<H, BF, NW>(tG2);
+        if (a.ln) {
+          dbe[0] += tile_colsum<H, BF, NW>(tGE);
+          dga[0] += tile_colsum<H, BF, NW>(tGM);
+        }
+      }
+      __syncthreads();
     }
-    __syncthreads();
-  }
-  for (int64_t r = r0 + (lane >> 2); r < r1; r += 16) {
-    if (gr.rowptr[r] == gr.rowptr[r + 1]) {
-      float* dst = a.g_P + r * H;
-      for (int c = (lane & 3) * 4; c < H; c += 16) *reinterpret_cast<float4*>(dst + c) = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int64_t r = r0 + (lane >> 2); r < r1; r += 16) {
+      if (gr.rowptr[r] == gr.rowptr[r + 1]) {
+        float* dst = a.g_P + r * H;
+        for (int c = (lane & 3) * 4; c < H; c += 16) *reinterpret_cast<float4*>(dst + c) = make_float4(0.f, 0.f, 0.f, 0.f);
+      }
     }
   }
   float* slab = a.part + blockIdx.x * a.slab;
@@ -452,12 +470,28 @@ __global__ __launch_bounds__(256) void k_gq(GqArgs a) {
       in[i] = xv[i];
       in[NF + i] = 0.f;
     }
-    const int p0 = gr.rowptr[rr], p1 = gr.rowptr[rr + 1];
-    for (int e = p0; e < p1; ++e) {
-      float t[NF];
-      load_row<H>(a.g_h + (int64_t)gr.rev[e] * H, g, t);
+    // gather in chunks of 4 edges with all loads issued before the sums
+    // (added in ascending edge order); absent edges read the first one's row
+    const int p0 = gr.rowptr[rr], deg = gr.rowptr[rr + 1] - p0;
+    const int rv0 = deg > 0 ? gr.rev[p0] : 0;
+    for (int c = 0; __ballot(c < deg) != 0; c += 4) {
+      int rv[4];
 #pragma unroll
-      for (int i = 0; i < NF; ++i) in[NF + i] += t[i];
+      for (int q = 0; q < 4; ++q) rv[q] = (c + q < deg) ? gr.rev[p0 + c + q] : rv0;
+      float t[4][NF];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if constexpr (BF)
+          load_row_bf16<H>(reinterpret_cast<const __bf16*>(a.g_h) + (int64_t)rv[q] * H, g, t[q]);
+        else
+          load_row<H>(reinterpret_cast<const float*>(a.g_h) + (int64_t)rv[q] * H, g, t[q]);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (c + q < deg) {
+#pragma unroll
+          for (int i = 0; i < NF; ++i) in[NF + i] += t[q][i];
+        }
     }
     load_row<H>(a.x + rr * H, g, xv);
     if (!valid) {
@@ -501,30 +535,39 @@ hipError_t launch_gq(const GqArgs& a, int grid, hipStream_t s) {
 
 template <int H, int KIN, bool TIN, bool TOUT, bool BF>
 struct MlpBwdCfg {
+  static constexpr int NW = (BF && H <= 64) ? 8 : 4;  // waves per workgroup
+  static constexpr int ROWS = 16 * NW;
+  // BF16: bias / LayerNorm gradients are column sums of staged tiles
+  static constexpr bool VEC = BF && !TOUT;
   static constexpr int AW0 = TIN ? 16 : KIN;  // staged input width
   static constexpr size_t F0 = TIN ? 0 : frag_bytes(H, KIN, BF);
   static constexpr size_t F1 = TOUT ? 0 : frag_bytes(H, H, BF);
   // fragments: W0, W1, W1^T, W0^T
   static constexpr size_t FRAG = 2 * F0 + 2 * F1;
-  static constexpr size_t STAGE0 = tile_bytes<H, BF>() + tile_bytes<AW0, BF>();
-  static constexpr size_t STAGE1 = TOUT ? 0 : 2 * tile_bytes<H, BF>();
+  static constexpr size_t TB = tile_bytes<H, BF, ROWS>();
+  static constexpr size_t STAGE0 = TB + tile_bytes<AW0, BF, ROWS>();
+  static constexpr size_t STAGE1 = TOUT ? 0 : (VEC ? 4 : 2) * TB;
   static constexpr size_t STAGE = STAGE0 > STAGE1 ? STAGE0 : STAGE1;
   static constexpr size_t SMALL = (TIN || TOUT) ? 16 * H : 0;  // small W0 / W1, [.][4] or [4][H]
-  static constexpr bool LDS_FRAG = FRAG + STAGE + SMALL <= kLdsLimit;
-  static constexpr size_t LDS = STAGE + (LDS_FRAG ? FRAG : 0) + SMALL;
+  static constexpr size_t VECS = 3 * H * sizeof(float);         // b0, b1, LayerNorm gain
+  static constexpr bool LDS_FRAG = FRAG + STAGE + SMALL + VECS <= kLdsLimit;
+  static constexpr size_t LDS = STAGE + (LDS_FRAG ? FRAG : 0) + SMALL + VECS;
 };
 
 // Adjoint of k_mlp_fwd, forward recomputed per row block:
 //   z = W0 in + b0, u = ELU(z), y = W1 u + b1, out = [resid +] LN(y)
-// The two staging phases (dW1 then dW0) share the same LDS.
+// Two staging phases per step (dW1 with its bias / LayerNorm sums, then
+// dW0 and db0) share the same LDS.
 template <int H, int KIN, bool TIN, bool TOUT, bool BF>
-__global__ __launch_bounds__(256) void k_mlp_bwd(MlpBwdArgs a) {
+__global__ __launch_bounds__((64 * MlpBwdCfg<H, KIN, TIN, TOUT, BF>::NW)) void k_mlp_bwd(MlpBwdArgs a) {
   using C = MlpBwdCfg<H, KIN, TIN, TOUT, BF>;
-  constexpr int NF = H / 4, MB = H / 16, KB = TIN ? 1 : KIN / 16, AW0 = C::AW0;
-  constexpr int NT1 = dw_tiles_per_wave<H, H>(), NT0 = dw_tiles_per_wave<H, AW0>();
+  constexpr int NF = H / 4, MB = H / 16, KB = TIN ? 1 : KIN / 16, AW0 = C::AW0, NW = C::NW, ROWS = C::ROWS;
+  constexpr int NT1 = dw_tiles_per_wave<H, H, NW>(), NT0 = dw_tiles_per_wave<H, AW0, NW>();
   extern __shared__ uint4 smem[];
   char* tG = reinterpret_cast<char*>(smem);
-  char* tA = tG + tile_bytes<H, BF>();
+  char* tA = tG + C::TB;
+  char* tGE = tA + C::TB;  // phase 1, VEC: g_out and g_out * normalised y
+  char* tGM = tGE + C::TB;
   const char* fr;
   if constexpr (C::LDS_FRAG) {
     uint4* fl = smem + C::STAGE / 16;
@@ -537,21 +580,21 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(MlpBwdArgs a) {
     fr = nullptr;
   }
   float* small = reinterpret_cast<float*>(reinterpret_cast<char*>(smem) + C::STAGE + (C::LDS_FRAG ? C::FRAG : 0));
+  float* vecs = small + C::SMALL / 4;
   if constexpr (TIN) stage_small(small, a.W0, H, a.k0);
   if constexpr (TOUT)
     for (int t = threadIdx.x; t < 4 * H; t += blockDim.x) small[t] = (t / H) < a.n_out ? a.W1[t] : 0.f;
+  for (int t = threadIdx.x; t < 3 * H; t += blockDim.x)
+    vecs[t] = t < H ? a.b0[t] : (t < 2 * H ? (TOUT ? 0.f : a.b1[t - H]) : (a.ln ? a.lng[t - 2 * H] : 0.f));
   __syncthreads();
-  const char* f0 = C::LDS_FRAG ? fr : reinterpret_cast<const char*>(a.frag0);
-  const char* f1 = C::LDS_FRAG ? fr + C::F0 : reinterpret_cast<const char*>(a.frag1);
-  const char* f1t = C::LDS_FRAG ? fr + C::F0 + C::F1 : reinterpret_cast<const char*>(a.frag1t);
-  const char* f0t = C::LDS_FRAG ? fr + C::F0 + 2 * C::F1 : reinterpret_cast<const char*>(a.frag0t);
   const bool want_gin = (a.g_src0 || a.g_src1) && !TIN;
 
   const int lane = lane_id(), j = lane & 15, g = lane >> 4, wave = threadIdx.x / 64;
+  const int srow = wave * 16 + j;
   const int64_t n = a.n_rows, nblk = (n + 15) / 16;
   const int64_t per = (nblk + gridDim.x - 1) / gridDim.x;
   const int64_t b0 = blockIdx.x * per, b1 = std::min(nblk, b0 + per);
-  const int64_t n_iter = (b1 - b0 + kWaves - 1) / kWaves;
+  const int64_t n_iter = (b1 - b0 + NW - 1) / NW;
   const int NO = TOUT ? a.n_out : H;
 
   v4f acc1[NT1], acc0[NT0];
@@ -559,27 +602,33 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(MlpBwdArgs a) {
   for (int t = 0; t < NT1; ++t) acc1[t] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int t = 0; t < NT0; ++t) acc0[t] = v4f{0.f, 0.f, 0.f, 0.f};
-  float db0[NF], db1[NF], dga[NF], dbe[NF];
+  constexpr int NV = C::VEC ? 1 : NF;  // per-lane vector accumulators (FP32 path)
+  float db0[NV], db1[NV], dga[NV], dbe[NV];
 #pragma unroll
-  for (int i = 0; i < NF; ++i) db0[i] = db1[i] = dga[i] = dbe[i] = 0.f;
-  float dW1s[4][NF];  // small-output dW1 rows (n_out <= 4)
+  for (int i = 0; i < NV; ++i) db0[i] = db1[i] = dga[i] = dbe[i] = 0.f;
+  constexpr int NS = TOUT ? NF : 1;
+  float dW1s[4][NS];  // small-output dW1 rows (n_out <= 4)
   float db1s[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int o = 0; o < 4; ++o)
 #pragma unroll
-    for (int i = 0; i < NF; ++i) dW1s[o][i] = 0.f;
-  float gam[NF];
-  if (a.ln) load_vec<H>(a.lng, g, gam);
+    for (int i = 0; i < NS; ++i) dW1s[o][i] = 0.f;
 
   for (int64_t it = 0; it < n_iter; ++it) {
-    const int64_t bk = b0 + it * kWaves + wave;
+    const int oz = opaque_zero();  // re-read fragments and vectors each block
+    const char* f0 = (C::LDS_FRAG ? fr : reinterpret_cast<const char*>(a.frag0)) + oz;
+    const char* f1 = (C::LDS_FRAG ? fr + C::F0 : reinterpret_cast<const char*>(a.frag1)) + oz;
+    const char* f1t = (C::LDS_FRAG ? fr + C::F0 + C::F1 : reinterpret_cast<const char*>(a.frag1t)) + oz;
+    const char* f0t = (C::LDS_FRAG ? fr + C::F0 + 2 * C::F1 : reinterpret_cast<const char*>(a.frag0t)) + oz;
+    const float* vb = vecs + oz;
+    const int64_t bk = b0 + it * NW + wave;
     const int64_t row = bk * 16 + j;
     const bool valid = bk < b1 && row < n;
     const int64_t rr = valid ? row : n - 1;
     // ---- recompute
     float in[TIN ? 4 : KIN / 4];
     float z[NF];
-    load_vec<H>(a.b0, g, z);
+    load_vec<H>(vb, g, z);
     if constexpr (TIN) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) in[k] = k < a.k0 ? a.src0[rr * a.k0 + k] : 0.f;
@@ -620,7 +669,7 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(MlpBwdArgs a) {
 #pragma unroll
       for (int o = 0; o < 4; ++o)
 #pragma unroll
-        for (int i = 0; i < NF; ++i) dW1s[o][i] += go[o] * u[i];
+        for (int i = 0; i < NS; ++i) dW1s[o][i] += go[o] * u[i];
       // db1 (n_out values): one copy per row, in lane group 0
       if (g == 0) {
 #pragma unroll
@@ -628,7 +677,7 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(MlpBwdArgs a) {
       }
     } else {
       float y[NF], go[NF];
-      load_vec<H>(a.b1, g, y);
+      load_vec<H>(vb + H, g, y);
       gemm<BF, MB, MB>(f1, u, y, lane);
       load_row<H>(a.g_out + rr * H, g, go);
       if (!valid) {
@@ -636,17 +685,27 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(MlpBwdArgs a) {
         for (int i = 0; i < NF; ++i) go[i] = 0.f;
       }
       if (a.ln) {
-        float mean, rstd, s1 = 0.f, s2 = 0.f;
+        float mean, rstd, s1 = 0.f, s2 = 0.f, gam[NF];
         ln_stats<H>(y, a.eps, mean, rstd);
+        load_vec<H>(vb + 2 * H, g, gam);
 #pragma unroll
         for (int i = 0; i < NF; ++i) {
           const float xh = (y[i] - mean) * rstd;
-          dga[i] += go[i] * xh;
-          dbe[i] += go[i];
+          if constexpr (!C::VEC) {
+            dga[i] += go[i] * xh;
+            dbe[i] += go[i];
+          }
           const float gx = go[i] * gam[i];
           s1 += gx;
           s2 += gx * xh;
           y[i] = xh;
+        }
+        if constexpr (C::VEC) {
+          float t[NF];
+#pragma unroll
+          for (int i = 0; i < NF; ++i) t[i] = go[i] * y[i];
+          stage_row<H, BF, ROWS>(tGE, srow, g, go);
+          stage_row<H, BF, ROWS>(tGM, srow, g, t);
         }
         s1 = row_sum(s1) * (1.f / H);
         s2 = row_sum(s2) * (1.f / H);
@@ -656,13 +715,22 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(MlpBwdArgs a) {
 #pragma unroll
         for (int i = 0; i < NF; ++i) y[i] = go[i];
       }
+      if constexpr (!C::VEC) {
 #pragma unroll
-      for (int i = 0; i < NF; ++i) db1[i] += y[i];
-      // phase 1: dW1 += gy u^T
-      stage_row<H, BF>(tG, wave * 16 + j, g, y);
-      stage_row<H, BF>(tA, wave * 16 + j, g, u);
+        for (int i = 0; i < NF; ++i) db1[i] += y[i];
+      }
+      // phase 1: dW1 += gy u^T (and the bias / LayerNorm column sums)
+      stage_row<H, BF, ROWS>(tG, srow, g, y);
+      stage_row<H, BF, ROWS>(tA, srow, g, u);
       __syncthreads();
-      dw_tiles<H, H, BF>(tG, tA, acc1, wave, lane);
+      dw_tiles<H, H, BF, NW>(tG, tA, acc1, wave, lane);
+      if constexpr (C::VEC) {
+        db1[0] += tile_colsum<H, BF, NW>(tG);
+        if (a.ln) {
+          dbe[0] += tile_colsum<H, BF, NW>(tGE);
+          dga[0] += tile_colsum<H, BF, NW>(tGM);
+        }
+      }
       __syncthreads();
 #pragma unroll
       for (int i = 0; i < NF; ++i) gu[i] = 0.f;
@@ -671,21 +739,24 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(MlpBwdArgs a) {
     // ---- gradient at z, dW0, db0
 #pragma unroll
     for (int i = 0; i < NF; ++i) gu[i] *= (u[i] > 0.f ? 1.f : u[i] + 1.f);
+    if constexpr (!C::VEC) {
 #pragma unroll
-    for (int i = 0; i < NF; ++i) db0[i] += gu[i];
-    stage_row<H, BF>(tG, wave * 16 + j, g, gu);
+      for (int i = 0; i < NF; ++i) db0[i] += gu[i];
+    }
+    stage_row<H, BF, ROWS>(tG, srow, g, gu);
     if constexpr (TIN) {
       float in16[4] = {0.f, 0.f, 0.f, 0.f};  // lane group g holds input features 4g..4g+3
       if (g == 0) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) in16[k] = in[k];
       }
-      stage_row<16, BF>(tA, wave * 16 + j, g, in16);
+      stage_row<16, BF, ROWS>(tA, srow, g, in16);
     } else {
-      stage_row<KIN, BF>(tA, wave * 16 + j, g, in);
+      stage_row<KIN, BF, ROWS>(tA, srow, g, in);
     }
     __syncthreads();
-    dw_tiles<H, AW0, BF>(tG, tA, acc0, wave, lane);
+    dw_tiles<H, AW0, BF, NW>(tG, tA, acc0, wave, lane);
+    if constexpr (C::VEC) db0[0] += tile_colsum<H, BF, NW>(tG);
     __syncthreads();
     // ---- input gradient
     if constexpr (!TIN) {
@@ -718,12 +789,15 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(MlpBwdArgs a) {
   // ---- write the slab
   float* slab = a.part + blockIdx.x * a.slab;
   const int k0w = TIN ? a.k0 : KIN;
-  dw_store<H, AW0>(acc0, slab, k0w, wave, lane);
+  dw_store<H, AW0, NW>(acc0, slab, k0w, wave, lane);
   float* scratch = reinterpret_cast<float*>(tG);
-  block_sum_vec<H>(db0, scratch, slab + H * k0w, wave, lane);
+  if constexpr (C::VEC)
+    block_sum_segments<H, NW>(db0[0], scratch, slab + H * k0w);
+  else
+    block_sum_vec<H, NW>(db0, scratch, slab + H * k0w, wave, lane);
   float* s1 = slab + H * k0w + H;
   if constexpr (TOUT) {
-    for (int o = 0; o < NO; ++o) block_sum_vec<H>(dW1s[o], scratch, s1 + o * H, wave, lane);
+    for (int o = 0; o < NO; ++o) block_sum_vec<H, NW>(dW1s[o], scratch, s1 + o * H, wave, lane);
     // db1: summed over the workgroup's lanes in a fixed order
     __syncthreads();
 #pragma unroll
@@ -736,11 +810,19 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(MlpBwdArgs a) {
     }
     __syncthreads();
   } else {
-    dw_store<H, H>(acc1, s1, H, wave, lane);
-    block_sum_vec<H>(db1, scratch, s1 + H * H, wave, lane);
-    if (a.ln) {
-      block_sum_vec<H>(dga, scratch, s1 + H * H + H, wave, lane);
-      block_sum_vec<H>(dbe, scratch, s1 + H * H + 2 * H, wave, lane);
+    dw_store<H, H, NW>(acc1, s1, H, wave, lane);
+    if constexpr (C::VEC) {
+      block_sum_segments<H, NW>(db1[0], scratch, s1 + H * H);
+      if (a.ln) {
+        block_sum_segments<H, NW>(dga[0], scratch, s1 + H * H + H);
+        block_sum_segments<H, NW>(dbe[0], scratch, s1 + H * H + 2 * H);
+      }
+    } else {
+      block_sum_vec<H, NW>(db1, scratch, s1 + H * H, wave, lane);
+      if (a.ln) {
+        block_sum_vec<H, NW>(dga, scratch, s1 + H * H + H, wave, lane);
+        block_sum_vec<H, NW>(dbe, scratch, s1 + H * H + 2 * H, wave, lane);
+      }
     }
   }
 }
@@ -750,8 +832,8 @@ static hipError_t launch_mlp_bwd_t(const MlpBwdArgs& a, int grid, hipStream_t s)
   using C = MlpBwdCfg<H, KIN, TIN, TOUT, BF>;
   const size_t lds = C::LDS;
   (void)hipFuncSetAttribute((const void*)k_mlp_bwd<H, KIN, TIN, TOUT, BF>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                      (int)lds);
-  hipLaunchKernelGGL((k_mlp_bwd<H, KIN, TIN, TOUT, BF>), dim3(grid), dim3(256), lds, s, a);
+                            (int)lds);
+  hipLaunchKernelGGL((k_mlp_bwd<H, KIN, TIN, TOUT, BF>), dim3(grid), dim3(64 * C::NW), lds, s, a);
   return hipGetLastError();
 }
 

@@ -75,7 +75,14 @@ DevGraph dev_graph(const mp_dev_graph* g) {
   d.mult = g->edge_mult;
   d.group_ptr = g->group_ptr;
   d.member = g->member;
+  d.n_tiles = 0;
+  d.tile_r = d.tile_e = nullptr;
   return d;
+}
+
+int64_t n_tiles_for(int64_t E, int tile_edges) {
+  const int64_t te = tile_edges > 0 ? tile_edges : kTileEdges;
+  return std::max<int64_t>(1, (E + te - 1) / te);
 }
 
 int check_cfg(const mp_layer_cfg* c) {
@@ -83,6 +90,10 @@ int check_cfg(const mp_layer_cfg* c) {
   if (c->H != 32 && c->H != 64 && c->H != 128) return mp_fail(MP_EINVAL, "H must be 32, 64 or 128 (got %d)", c->H);
   if (c->gemm_dtype != MP_F32 && c->gemm_dtype != MP_BF16) return mp_fail(MP_EINVAL, "gemm_dtype must be MP_F32 or MP_BF16");
   if (c->layernorm && !(c->ln_eps > 0.f)) return mp_fail(MP_EINVAL, "ln_eps must be positive");
+  if (c->tile_edges != 0 && (c->tile_edges < 16 || c->tile_edges > 4096))
+    return mp_fail(MP_EINVAL, "tile_edges must be 0 or in [16, 4096] (got %d)", c->tile_edges);
+  if (c->edge_grid < 0 || c->edge_grid > 65536 || c->edge_bwd_grid < 0 || c->edge_bwd_grid > 65536)
+    return mp_fail(MP_EINVAL, "edge grids must be 0 or in [1, 65536]");
   return MP_OK;
 }
 
@@ -110,22 +121,26 @@ struct LayerFrags {
 
 struct LayerWs {
   LayerFrags fr;
-  size_t P, Q, a, gP, gh, part_e, part_n, part_q, total;
+  size_t P, Q, a, gP, gh, part_e, part_n, part_q, tile_r, tile_e, total;
   int ge, gbe, gn, gbn;
+  int64_t n_tiles;
   LayerWs(const mp_layer_cfg* c, const mp_dev_graph* g, bool bwd) : fr(c->H, c->gemm_dtype == MP_BF16) {
     const size_t H = c->H, N = g->n_rows, E = g->n_edges;
-    ge = edge_grid(E);
-    gbe = edge_bwd_grid(E);
+    ge = c->edge_grid > 0 ? c->edge_grid : edge_grid(E);
+    gbe = c->edge_bwd_grid > 0 ? c->edge_bwd_grid : edge_bwd_grid(E);
     gn = row_grid(N);
     gbn = row_bwd_grid(N);
+    n_tiles = n_tiles_for(E, c->tile_edges);
     size_t o = fr.total;
+    tile_r = o; o = align_up(o + (size_t)(n_tiles + 1) * 4);
+    tile_e = o; o = align_up(o + (size_t)(n_tiles + 1) * 4);
     P = o; o = align_up(o + N * H * 4);
     Q = o; o = align_up(o + N * H * 4);
     a = o; o = align_up(o + N * H * 4);
     gP = gh = part_e = part_n = part_q = 0;
     if (bwd) {
       gP = o; o = align_up(o + N * H * 4);
-      gh = o; o = align_up(o + E * H * 4);
+      gh = o; o = align_up(o + E * H * (c->gemm_dtype == MP_BF16 ? 2 : 4));
       part_e = o; o = align_up(o + (size_t)gbe * edge_slab(c->H) * 4);
       part_n = o; o = align_up(o + (size_t)gbn * mlp_slab(c->H, 2 * c->H, c->H) * 4);
       part_q = o; o = align_up(o + (size_t)gbn * gq_slab(c->H) * 4);
@@ -290,10 +305,18 @@ extern "C" int mp_layer_forward(const mp_layer_cfg* cfg, const mp_layer_params* 
   const int H = cfg->H;
   const bool bf = cfg->gemm_dtype == MP_BF16;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  const DevGraph d = dev_graph(g);
+  DevGraph d = dev_graph(g);
+  d.n_tiles = W.n_tiles;
+  d.tile_r = reinterpret_cast<const int32_t*>(ws_at(ws, W.tile_r));
+  d.tile_e = reinterpret_cast<const int32_t*>(ws_at(ws, W.tile_e));
   float* P = wsf(ws, W.P);
   float* Q = wsf(ws, W.Q);
   float* a = a_star_out ? a_star_out : wsf(ws, W.a);
+  if ((rc = run("tiles", s, [&] {
+         return launch_tiles(d, reinterpret_cast<int32_t*>(ws_at(ws, W.tile_r)),
+                             reinterpret_cast<int32_t*>(ws_at(ws, W.tile_e)), s);
+       })))
+    return rc;
   if ((rc = run("pack", s, [&] { return launch_pack(layer_jobs(cfg, p, W.fr, false), ws, s); }))) return rc;
   if ((rc = run("proj", s, [&] { return launch_proj(H, bf, d, x_in, ws_at(ws, W.fr.proj), p->be1, P, Q, W.gn, s); }))) return rc;
   if ((rc = run("edge_fwd", s, [&] { return launch_edge_fwd(H, cfg->layernorm != 0, bf, d, P, Q, e_in, ws_at(ws, W.fr.edge), p->be2,
@@ -347,12 +370,20 @@ extern "C" int mp_layer_backward(const mp_layer_cfg* cfg, const mp_layer_params*
   const int H = cfg->H;
   const bool bf = cfg->gemm_dtype == MP_BF16;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  const DevGraph d = dev_graph(g);
+  DevGraph d = dev_graph(g);
+  d.n_tiles = W.n_tiles;
+  d.tile_r = reinterpret_cast<const int32_t*>(ws_at(ws, W.tile_r));
+  d.tile_e = reinterpret_cast<const int32_t*>(ws_at(ws, W.tile_e));
   float* P = wsf(ws, W.P);
   float* Q = wsf(ws, W.Q);
   float* ga = wsf(ws, W.a);
+  if ((rc = run("tiles", s, [&] {
+         return launch_tiles(d, reinterpret_cast<int32_t*>(ws_at(ws, W.tile_r)),
+                             reinterpret_cast<int32_t*>(ws_at(ws, W.tile_e)), s);
+       })))
+    return rc;
   float* gP = wsf(ws, W.gP);
-  float* gh = wsf(ws, W.gh);
+  void* gh = ws_at(ws, W.gh);
   if ((rc = run("pack", s, [&] { return launch_pack(layer_jobs(cfg, p, W.fr, true), ws, s); }))) return rc;
   if ((rc = run("proj", s, [&] { return launch_proj(H, bf, d, x_in, ws_at(ws, W.fr.proj), p->be1, P, Q, W.gn, s); }))) return rc;
   // node MLP adjoint: g_a* and g_x (residual + node-MLP part)

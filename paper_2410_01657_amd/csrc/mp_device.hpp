@@ -53,6 +53,51 @@ __device__ __forceinline__ void store_row(float* __restrict__ ptr, int g, const 
         make_float4(v[4 * b + 0], v[4 * b + 1], v[4 * b + 2], v[4 * b + 3]);
 }
 
+// BF16 storage of a row (round to nearest even) and its FP32 read-back.
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 v4bf __attribute__((ext_vector_type(4)));
+template <int W>
+__device__ __forceinline__ void store_row_bf16_nt(__bf16* __restrict__ ptr, int g, const float (&v)[W / 4]) {
+#pragma unroll
+  for (int b = 0; b < W / 16; ++b) {
+    const v4bf t = {(__bf16)v[4 * b], (__bf16)v[4 * b + 1], (__bf16)v[4 * b + 2], (__bf16)v[4 * b + 3]};
+    __builtin_nontemporal_store(__builtin_bit_cast(u32x2, t), reinterpret_cast<u32x2*>(ptr + 16 * b + 4 * g));
+  }
+}
+template <int W>
+__device__ __forceinline__ void load_row_bf16(const __bf16* __restrict__ ptr, int g, float (&v)[W / 4]) {
+#pragma unroll
+  for (int b = 0; b < W / 16; ++b) {
+    const v4bf t = __builtin_bit_cast(v4bf, *reinterpret_cast<const u32x2*>(ptr + 16 * b + 4 * g));
+    v[4 * b + 0] = (float)t[0];
+    v[4 * b + 1] = (float)t[1];
+    v[4 * b + 2] = (float)t[2];
+    v[4 * b + 3] = (float)t[3];
+  }
+}
+
+// Streaming variants for arrays touched exactly once per kernel (edge
+// states and their gradients): non-temporal hints keep them from evicting
+// the gathered node rows from L2.
+template <int W>
+__device__ __forceinline__ void load_row_nt(const float* __restrict__ ptr, int g, float (&v)[W / 4]) {
+#pragma unroll
+  for (int b = 0; b < W / 16; ++b) {
+    const v4f t = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(ptr + 16 * b + 4 * g));
+    v[4 * b + 0] = t[0];
+    v[4 * b + 1] = t[1];
+    v[4 * b + 2] = t[2];
+    v[4 * b + 3] = t[3];
+  }
+}
+template <int W>
+__device__ __forceinline__ void store_row_nt(float* __restrict__ ptr, int g, const float (&v)[W / 4]) {
+#pragma unroll
+  for (int b = 0; b < W / 16; ++b)
+    __builtin_nontemporal_store(v4f{v[4 * b + 0], v[4 * b + 1], v[4 * b + 2], v[4 * b + 3]},
+                                reinterpret_cast<v4f*>(ptr + 16 * b + 4 * g));
+}
+
 // Per-feature vector (bias, LayerNorm gain) in row-block layout.
 template <int W>
 __device__ __forceinline__ void load_vec(const float* __restrict__ p, int g, float (&v)[W / 4]) {
@@ -214,18 +259,22 @@ constexpr int DPP_ROW_ROR1 = 0x121;  // lane j reads lane (j-1) mod 16
 // nonzero, because lanes shifted in from outside the row read key 0.
 template <int N>
 __device__ __forceinline__ void seg_scan16(float (&v)[N], int key) {
+  // Each step adds the value `off` lanes back when that lane is in the same
+  // segment, written as v += shifted * (0 or 1) so the shift folds into the
+  // multiply-add as a DPP operand.  Steps 4 and 8 are skipped (uniformly for
+  // the wave) when no segment in the block is that long.
 #define MP_SEG_STEP(CTRL)                                     \
   {                                                           \
-    const bool same = dpp_i<CTRL>(key) == key;                \
-    _Pragma("unroll") for (int i = 0; i < N; ++i) {           \
-      const float t = dpp_f<CTRL>(v[i]);                      \
-      v[i] += same ? t : 0.f;                                 \
-    }                                                         \
+    const float same = dpp_i<CTRL>(key) == key ? 1.f : 0.f;   \
+    _Pragma("unroll") for (int i = 0; i < N; ++i)             \
+      v[i] = fmaf(dpp_f<CTRL>(v[i]), same, v[i]);             \
   }
   MP_SEG_STEP(DPP_ROW_SHR1)
   MP_SEG_STEP(DPP_ROW_SHR2)
-  MP_SEG_STEP(DPP_ROW_SHR4)
-  MP_SEG_STEP(DPP_ROW_SHR8)
+  if (__ballot(dpp_i<DPP_ROW_SHR4>(key) == key) != 0) {
+    MP_SEG_STEP(DPP_ROW_SHR4)
+    if (__ballot(dpp_i<DPP_ROW_SHR8>(key) == key) != 0) MP_SEG_STEP(DPP_ROW_SHR8)
+  }
 #undef MP_SEG_STEP
 }
 
@@ -259,6 +308,28 @@ __device__ __forceinline__ void part_rows(const int32_t* __restrict__ rowptr, in
   if (r0 > n_rows) r0 = n_rows;
   if (r1 > n_rows) r1 = n_rows;
   if (r1 < r0) r1 = r0;
+}
+
+// Tiled schedule for the edge kernels.  The rows are cut into n_tiles
+// row-aligned tiles of about equal edge count (tile boundaries precomputed by
+// k_tiles).  Workgroups are dealt round robin to the 8 XCDs, so workgroup b
+// runs on XCD b % 8; each XCD takes one contiguous eighth of the tiles, and
+// inside it the XCD's waves take consecutive tiles in turn.  All waves of an
+// XCD thus sweep a compact window of rows together, and a node row gathered
+// by edges a few planes apart is still in that XCD's L2.
+struct TileSched {
+  int64_t t0, t1;    // this group's tile range
+  int64_t rank, nr;  // block rank inside the group, blocks in the group
+};
+__device__ __forceinline__ TileSched tile_sched(int64_t n_tiles) {
+  const int64_t G = gridDim.x, V = G < 8 ? G : 8;
+  const int64_t vx = blockIdx.x % V;
+  TileSched s;
+  s.rank = blockIdx.x / V;
+  s.nr = (G - vx + V - 1) / V;
+  s.t0 = vx * n_tiles / V;
+  s.t1 = (vx + 1) * n_tiles / V;
+  return s;
 }
 
 // XCD-aware block numbering: the dispatcher hands consecutive workgroups to

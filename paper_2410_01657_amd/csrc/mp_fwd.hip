@@ -129,8 +129,28 @@ hipError_t launch_proj(int H, bool bf, const DevGraph& g, const float* x, const 
 
 // --------------------------------------------- edge update + aggregation
 
-// Eq. 4a-b on a static row range per wave.  For every directed edge k
-// (receiver i, sender j):
+// Row-aligned tiles of about kTileEdges edges: tile t starts at the first
+// row whose first edge index is at least floor(t * E / T); the last tile
+// ends at n_rows.  One thread per boundary.
+__global__ __launch_bounds__(256) void k_tiles(const int32_t* __restrict__ rowptr, int64_t n_rows, int64_t T,
+                                               int32_t* __restrict__ tile_r, int32_t* __restrict__ tile_e) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t > T) return;
+  const int64_t E = rowptr[n_rows];
+  int64_t r = (t == 0) ? 0 : (t == T ? n_rows : lower_bound_i32(rowptr, n_rows + 1, (t * E) / T));
+  if (r > n_rows) r = n_rows;
+  tile_r[t] = (int32_t)r;
+  tile_e[t] = rowptr[r];
+}
+
+hipError_t launch_tiles(const DevGraph& g, int32_t* tile_r, int32_t* tile_e, hipStream_t s) {
+  const int grid = (int)((g.n_tiles + 1 + 255) / 256);
+  hipLaunchKernelGGL(k_tiles, dim3(grid), dim3(256), 0, s, g.rowptr, g.n_rows, g.n_tiles, tile_r, tile_e);
+  return hipGetLastError();
+}
+
+// Eq. 4a-b, one row-aligned tile at a time per wave (schedule: tile_sched).
+// For every directed edge k (receiver i, sender j):
 //   h  = P_i + Q_j + W1c e_k             (first Linear of the edge MLP)
 //   m  = W2 ELU(h) + b2  [-> LayerNorm]  (second Linear)
 //   e'_k = e_k + m                        (residual edge update)
@@ -164,71 +184,72 @@ __global__ __launch_bounds__(256) void k_edge_fwd(DevGraph gr, const float* __re
   __syncthreads();
   const int lane = lane_id(), j = lane & 15, g = lane >> 4;
   const int nw = blockDim.x / 64;
-  const int64_t wave = xcd_block(blockIdx.x, gridDim.x) * nw + threadIdx.x / 64;
-  int64_t r0, r1;
-  part_rows(gr.rowptr, gr.n_rows, (int64_t)gridDim.x * nw, wave, r0, r1);
-  const int64_t e0 = gr.rowptr[r0], e1 = gr.rowptr[r1];
+  const TileSched ts = tile_sched(gr.n_tiles);
 
-  float carry[NF];
+  for (int64_t tile = ts.t0 + ts.rank * nw + threadIdx.x / 64; tile < ts.t1; tile += ts.nr * nw) {
+    const int64_t r0 = gr.tile_r[tile], r1 = gr.tile_r[tile + 1];
+    const int64_t e0 = gr.tile_e[tile], e1 = gr.tile_e[tile + 1];
+    float carry[NF];
 #pragma unroll
-  for (int i = 0; i < NF; ++i) carry[i] = 0.f;
-  int carry_key = 0;
+    for (int i = 0; i < NF; ++i) carry[i] = 0.f;
+    int carry_key = 0;
 
-  for (int64_t base = e0; base < e1; base += 16) {
-    const char* frb = fr + opaque_zero();  // re-read the fragments each block
-    const int64_t k = base + j;
-    const bool valid = k < e1;
-    const int64_t kk = valid ? k : e1 - 1;
-    const int ri = gr.recv[kk];
-    const int sj = gr.col[kk];
-    const float inv_d = 1.f / (float)gr.mult[kk];
-    const int next = (k + 1 < e1) ? gr.recv[k + 1] : -1;
-    const bool last = valid && next != ri;
-    const int key = valid ? ri + 1 : -1;
+    for (int64_t base = e0; base < e1; base += 16) {
+      const char* frb = fr + opaque_zero();  // re-read the fragments each block
+      const int64_t k = base + j;
+      const bool valid = k < e1;
+      const int64_t kk = valid ? k : e1 - 1;
+      const int ri = gr.recv[kk];
+      const int sj = gr.col[kk];
+      const float inv_d = 1.f / (float)gr.mult[kk];
+      const int next = (k + 1 < e1) ? gr.recv[k + 1] : -1;
+      const bool last = valid && next != ri;
+      const int key = valid ? ri + 1 : -1;
 
-    float ev[NF], h[NF], q[NF];
-    load_row<H>(e_in + kk * H, g, ev);
-    load_row<H>(P + (int64_t)ri * H, g, h);
-    load_row<H>(Q + (int64_t)sj * H, g, q);
+      float ev[NF], h[NF], q[NF];
+      load_row_nt<H>(e_in + kk * H, g, ev);
+      load_row<H>(P + (int64_t)ri * H, g, h);
+      load_row<H>(Q + (int64_t)sj * H, g, q);
 #pragma unroll
-    for (int i = 0; i < NF; ++i) h[i] += q[i];
-    gemm<BF, MB, MB>(frb, ev, h, lane);
+      for (int i = 0; i < NF; ++i) h[i] += q[i];
+      gemm<BF, MB, MB>(frb, ev, h, lane);
 #pragma unroll
-    for (int i = 0; i < NF; ++i) h[i] = elu(h[i]);
-    float m[NF];
-    const float* vb = vecs + opaque_zero();
-    load_vec<H>(vb, g, m);
-    gemm<BF, MB, MB>(frb + FB, h, m, lane);
-    if (ln) {
-      float mean, rstd, gam[NF], bet[NF];
-      ln_stats<H>(m, eps, mean, rstd);
-      load_vec<H>(vb + H, g, gam);
-      load_vec<H>(vb + 2 * H, g, bet);
+      for (int i = 0; i < NF; ++i) h[i] = elu(h[i]);
+      float m[NF];
+      const float* vb = vecs + opaque_zero();
+      load_vec<H>(vb, g, m);
+      gemm<BF, MB, MB>(frb + FB, h, m, lane);
+      if (ln) {
+        float mean, rstd, gam[NF], bet[NF];
+        ln_stats<H>(m, eps, mean, rstd);
+        load_vec<H>(vb + H, g, gam);
+        load_vec<H>(vb + 2 * H, g, bet);
 #pragma unroll
-      for (int i = 0; i < NF; ++i) m[i] = (m[i] - mean) * rstd * gam[i] + bet[i];
+        for (int i = 0; i < NF; ++i) m[i] = (m[i] - mean) * rstd * gam[i] + bet[i];
+      }
+#pragma unroll
+      for (int i = 0; i < NF; ++i) ev[i] += m[i];
+      if (valid) store_row_nt<H>(e_out + k * H, g, ev);
+
+      // aggregation: segmented scan of e'/d across the block, plus carry
+#pragma unroll
+      for (int i = 0; i < NF; ++i) {
+        float v = valid ? ev[i] * inv_d : 0.f;
+        if (j == 0 && key == carry_key) v += carry[i];
+        ev[i] = v;
+      }
+      seg_scan16<NF>(ev, key);
+      if (last) store_row<H>(a_out + (int64_t)ri * H, g, ev);
+#pragma unroll
+      for (int i = 0; i < NF; ++i) carry[i] = from_prev_lane(ev[i]);
+      carry_key = from_prev_lane_i(key);
     }
-#pragma unroll
-    for (int i = 0; i < NF; ++i) ev[i] += m[i];
-    if (valid) store_row<H>(e_out + k * H, g, ev);
-
-    // aggregation: segmented scan of e'/d across the block, plus carry
-#pragma unroll
-    for (int i = 0; i < NF; ++i) {
-      float v = valid ? ev[i] * inv_d : 0.f;
-      if (j == 0 && key == carry_key) v += carry[i];
-      ev[i] = v;
-    }
-    seg_scan16<NF>(ev, key);
-    if (last) store_row<H>(a_out + (int64_t)ri * H, g, ev);
-#pragma unroll
-    for (int i = 0; i < NF; ++i) carry[i] = from_prev_lane(ev[i]);
-    carry_key = from_prev_lane_i(key);
-  }
-  // rows without incoming edges aggregate to zero
-  for (int64_t r = r0 + (lane >> 2); r < r1; r += 16) {
-    if (gr.rowptr[r] == gr.rowptr[r + 1]) {
-      float* dst = a_out + r * H;
-      for (int c = (lane & 3) * 4; c < H; c += 16) *reinterpret_cast<float4*>(dst + c) = make_float4(0.f, 0.f, 0.f, 0.f);
+    // rows without incoming edges aggregate to zero
+    for (int64_t r = r0 + (lane >> 2); r < r1; r += 16) {
+      if (gr.rowptr[r] == gr.rowptr[r + 1]) {
+        float* dst = a_out + r * H;
+        for (int c = (lane & 3) * 4; c < H; c += 16) *reinterpret_cast<float4*>(dst + c) = make_float4(0.f, 0.f, 0.f, 0.f);
+      }
     }
   }
 }

@@ -34,7 +34,16 @@ struct DevGraph {
   const uint8_t* mult;
   const int32_t* group_ptr;
   const int32_t* member;
+  // row-aligned tiles of about equal edge count (built by launch_tiles):
+  // tile t = rows [tile_r[t], tile_r[t+1]) = edges [tile_e[t], tile_e[t+1])
+  int64_t n_tiles;
+  const int32_t* tile_r;
+  const int32_t* tile_e;
 };
+
+// Edges per tile of the edge kernels' schedule.
+constexpr int kTileEdges = 128;
+hipError_t launch_tiles(const DevGraph& g, int32_t* tile_r, int32_t* tile_e, hipStream_t s);
 
 // Launch helpers; each returns the hipError_t of the launch.
 hipError_t launch_pack(const PackJobs& jobs, void* dst, hipStream_t s);
@@ -121,7 +130,7 @@ struct EdgeBwdArgs {
   const float* lnb;
   float eps;
   float* g_e_in;
-  float* g_h;            // [E][H] gradient of the first pre-activation
+  void* g_h;             // [E][H] gradient of the first pre-activation (BF16 on the BF16 path)
   float* g_P;            // [N][H] sum of g_h over each row's incoming edges
   float* part;           // partial weight gradients, slab per workgroup
   int64_t slab;
@@ -158,7 +167,7 @@ struct GqArgs {
   int H, bf;
   const float* x;
   const float* g_P;
-  const float* g_h;
+  const void* g_h;       // [E][H], FP32 or (BF16 path) BF16
   const void* frag_abt;  // [W1a | W1b]^T as an H x 2H matrix
   float* g_x;            // accumulated: g_x += W1a^T g_P + W1b^T g_Q
   float* part;

@@ -38,10 +38,13 @@ class ConsistentGNN:
     LAYER_ORDER = ["We1", "be1", "We2", "be2", "ge", "bge", "Wn1", "bn1", "Wn2", "bn2", "gn", "bgn"]
     MLP_ORDER = ["W0", "b0", "W1", "b1", "ln_g", "ln_b"]
 
-    def __init__(self, spec, params, device="cuda", gemm="f32", halo=True):
+    def __init__(self, spec, params, device="cuda", gemm="f32", halo=True, schedule=None):
         if spec.n_hidden != 0:
             raise NotImplementedError("the GPU path implements MLPs of two Linear layers")
         self.spec, self.gemm, self.halo = spec, gemm, halo
+        # edge-kernel schedule: None (library defaults) or a dict with
+        # tile_edges / edge_grid / edge_bwd_grid (see autotune.py)
+        self.schedule = schedule
         self.device = torch.device(device)
         self.params = {k: torch.as_tensor(np.asarray(v), dtype=torch.float32).to(self.device).contiguous()
                        for k, v in params.items()}
@@ -66,6 +69,10 @@ class ConsistentGNN:
     def process(self, dg, x, e):
         s = self.spec
         cfg = layer_cfg(s.H, s.layernorm, self.halo, self.gemm, s.ln_eps)
+        if self.schedule:
+            cfg.tile_edges = int(self.schedule.get("tile_edges", 0))
+            cfg.edge_grid = int(self.schedule.get("edge_grid", 0))
+            cfg.edge_bwd_grid = int(self.schedule.get("edge_bwd_grid", 0))
         for m in range(s.n_layers):
             names = _layer_param_names(m, s.layernorm)
             args = [self.params[names[f]] if f in names else None for f in self.LAYER_ORDER]

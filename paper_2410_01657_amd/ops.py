@@ -102,6 +102,9 @@ class MPLayerFn(torch.autograd.Function):
         p = dict(zip(LAYER_FIELDS, params))
         x_out, e_out, a_star = layer_forward(cfg, p, dg, x, e)
         ctx.cfg, ctx.dg = cfg, dg
+        # an unused edge-state output (the last layer's) arrives as None in
+        # the backward instead of a materialised zero tensor
+        ctx.set_materialize_grads(False)
         ctx.save_for_backward(x, e, a_star, *[t if t is not None else torch.empty(0) for t in params])
         ctx.has = [t is not None for t in params]
         return x_out, e_out
@@ -110,7 +113,7 @@ class MPLayerFn(torch.autograd.Function):
     def backward(ctx, g_x_out, g_e_out):
         x, e, a_star, *ps = ctx.saved_tensors
         p = {f: (t if h else None) for f, t, h in zip(LAYER_FIELDS, ps, ctx.has)}
-        g_x_out = g_x_out.contiguous()
+        g_x_out = g_x_out.contiguous() if g_x_out is not None else torch.zeros_like(x)
         g_e_out = g_e_out.contiguous() if g_e_out is not None else None
         g_x, g_e, grads = layer_backward(ctx.cfg, p, ctx.dg, x, e, a_star, g_x_out, g_e_out)
         return (None, None, g_x, g_e) + tuple(grads[f] for f in LAYER_FIELDS)
