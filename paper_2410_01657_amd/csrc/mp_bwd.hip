@@ -95,11 +95,17 @@ __device__ __forceinline__ float tile_colsum(const void* __restrict__ tile) {
   constexpr int ROWS = 16 * NW, RS = Stg<BF, ROWS>::RS, NSEG = 64 * NW / W, LEN = ROWS / NSEG;
   static_assert(NSEG >= 1 && LEN % 8 == 0, "segment layout");
   using T = typename Stg<BF, ROWS>::T;
+  constexpr int PER = 16 / sizeof(T);  // values per 16-byte read (rows are 16-byte aligned)
   const int f = threadIdx.x % W, sg = threadIdx.x / W;
   const T* p = reinterpret_cast<const T*>(tile) + f * RS + sg * LEN;
   float s = 0.f;
 #pragma unroll
-  for (int r = 0; r < LEN; ++r) s += (float)p[r];
+  for (int r = 0; r < LEN; r += PER) {
+    const uint4 q = *reinterpret_cast<const uint4*>(p + r);
+    const T* v = reinterpret_cast<const T*>(&q);
+#pragma unroll
+    for (int c = 0; c < PER; ++c) s += (float)v[c];
+  }
   return s;
 }
 
@@ -229,20 +235,41 @@ __global__ __launch_bounds__((64 * EdgeBwdCfg<H, BF>::NW)) void k_edge_bwd(EdgeB
 
   // groups of NW consecutive tiles, one per wave, processed in lock step
   for (int64_t tg = ts.t0 + ts.rank * NW; tg < ts.t1; tg += ts.nr * NW) {
+    // Tile bounds, clamped to the range end (a wave past it gets an empty
+    // tile); all loads are independent so they share one round trip.
     const int64_t tile = tg + wave;
-    const bool has = tile < ts.t1;
-    const int64_t r0 = has ? gr.tile_r[tile] : 0, r1 = has ? gr.tile_r[tile + 1] : 0;
-    const int64_t e0 = has ? gr.tile_e[tile] : 0, e1 = has ? gr.tile_e[tile + 1] : 0;
-    // lock-step trip count: the most 16-edge blocks of any tile of the group
-    int64_t n_iter = 0;
-    for (int w = 0; w < NW; ++w) {
-      const int64_t tw = tg + w;
-      if (tw < ts.t1) n_iter = std::max<int64_t>(n_iter, (gr.tile_e[tw + 1] - gr.tile_e[tw] + 15) / 16);
-    }
+    const int64_t tc0 = std::min<int64_t>(tile, ts.t1), tc1 = std::min<int64_t>(tile + 1, ts.t1);
+    const int64_t r0 = gr.tile_r[tc0], r1 = gr.tile_r[tc1];
+    const int64_t e0 = gr.tile_e[tc0], e1 = gr.tile_e[tc1];
+    // lock-step trip count: the most 16-edge blocks of any tile of the
+    // group; lane w < NW reads the bounds of tile tg + w
+    const int wl = lane < NW ? lane : 0;
+    const int32_t eb0 = gr.tile_e[std::min<int64_t>(tg + wl, ts.t1)];
+    const int32_t eb1 = gr.tile_e[std::min<int64_t>(tg + wl + 1, ts.t1)];
+    int nb = lane < NW ? (eb1 - eb0 + 15) / 16 : 0;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) nb = std::max(nb, __shfl_xor(nb, off));
+    const int64_t n_iter = __builtin_amdgcn_readfirstlane(nb);  // the same in every lane and wave
     float carry[NF];
 #pragma unroll
     for (int i = 0; i < NF; ++i) carry[i] = 0.f;
     int carry_key = 0;
+
+    // Index loads run one block ahead, so each block waits on a single
+    // round trip to memory (its rows), not on indices and then rows.
+    const int64_t e_last = e1 > e0 ? e1 - 1 : 0;  // in-bounds stand-in for absent edges
+    int ri_n, sj_n, md_n, nx_n;
+    {
+      const int64_t k = e0 + j, kk = k < e1 ? k : e_last;
+      ri_n = gr.recv[kk];
+      sj_n = gr.col[kk];
+      md_n = gr.mult[kk];
+      nx_n = (k + 1 < e1) ? gr.recv[k + 1] : -1;
+      // complete these loads here, so that the loop's entry state holds no
+      // pending loads (else the compiler's wait at the loop head, merged
+      // with the back edge, also drains the previous block's stores)
+      asm volatile("" : "+v"(ri_n), "+v"(sj_n), "+v"(md_n), "+v"(nx_n));
+    }
 
     for (int64_t it = 0; it < n_iter; ++it) {
       const char* frb = fr + opaque_zero();  // re-read the fragments each block
@@ -253,19 +280,38 @@ __global__ __launch_bounds__((64 * EdgeBwdCfg<H, BF>::NW)) void k_edge_bwd(EdgeB
       const int srow = wave * 16 + j;
       const int64_t k = e0 + it * 16 + j;
       const bool valid = k < e1;
-      const int64_t kk = valid ? k : (e1 > e0 ? e1 - 1 : 0);
-      const int ri = gr.recv[kk];
-      const int sj = gr.col[kk];
-      const float inv_d = 1.f / (float)gr.mult[kk];
-      const int next = (k + 1 < e1) ? gr.recv[k + 1] : -1;
+      const int64_t kk = valid ? k : e_last;
+      const int ri = ri_n;
+      const int sj = sj_n;
+      const float inv_d = 1.f / (float)md_n;
+      const int next = nx_n;
       const bool last = valid && next != ri;
       const int key = valid ? ri + 1 : -1;
 
-      // recompute the forward
-      float ev[NF], u[NF], t[NF];
+      // next block's indices first (the only loads issued before this
+      // block's stores that the next block waits on), then every row this
+      // block reads, issued together
+      {
+        const int64_t k2 = k + 16, kk2 = k2 < e1 ? k2 : e_last;
+        ri_n = gr.recv[kk2];
+        sj_n = gr.col[kk2];
+        md_n = gr.mult[kk2];
+        nx_n = (k2 + 1 < e1) ? gr.recv[k2 + 1] : -1;
+      }
+      float ev[NF], u[NF], t[NF], gE[NF], go[NF];
       load_row_nt<H>(a.e_in + kk * H, g, ev);
       load_row<H>(a.P + (int64_t)ri * H, g, u);
       load_row<H>(a.Q + (int64_t)sj * H, g, t);
+      load_row<H>(a.g_a + (int64_t)ri * H, g, gE);
+      if (a.g_e_out) {
+        load_row_nt<H>(a.g_e_out + kk * H, g, go);
+      } else {
+#pragma unroll
+        for (int i = 0; i < NF; ++i) go[i] = 0.f;
+      }
+      __builtin_amdgcn_sched_barrier(0);  // all row loads issue before any use
+
+      // recompute the forward
 #pragma unroll
       for (int i = 0; i < NF; ++i) u[i] += t[i];
       gemm<BF, MB, MB>(fW1c, ev, u, lane);
@@ -277,12 +323,9 @@ __global__ __launch_bounds__((64 * EdgeBwdCfg<H, BF>::NW)) void k_edge_bwd(EdgeB
       gemm<BF, MB, MB>(fW2, u, mp, lane);
 
       // gradient reaching e'
-      float gE[NF];
-      load_row<H>(a.g_a + (int64_t)ri * H, g, gE);
-      if (a.g_e_out) load_row_nt<H>(a.g_e_out + kk * H, g, t);
 #pragma unroll
       for (int i = 0; i < NF; ++i) {
-        const float v = gE[i] * inv_d + (a.g_e_out ? t[i] : 0.f);
+        const float v = gE[i] * inv_d + go[i];
         gE[i] = valid ? v : 0.f;
       }
       // LayerNorm adjoint (mp becomes the pre-LN gradient gm)
@@ -416,6 +459,40 @@ hipError_t launch_edge_bwd(const EdgeBwdArgs& a, int grid, hipStream_t s) {
 // ------------------------------------------------- sender-side gradients
 
 
+// One gathered row of g_h as loaded (BF16 pairs or FP32), converted to
+// FP32 only when added; lane (j, g) holds features 16b + 4g + r.
+template <int H, bool BF>
+struct GqRaw {
+  static constexpr int NB = H / 16;
+  typename std::conditional<BF, u32x2, float4>::type v[NB];
+  __device__ __forceinline__ void load(const void* __restrict__ base, int64_t r, int g) {
+    if constexpr (BF) {
+      const __bf16* p = reinterpret_cast<const __bf16*>(base) + r * H + 4 * g;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) v[b] = *reinterpret_cast<const u32x2*>(p + 16 * b);
+    } else {
+      const float* p = reinterpret_cast<const float*>(base) + r * H + 4 * g;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) v[b] = *reinterpret_cast<const float4*>(p + 16 * b);
+    }
+  }
+  __device__ __forceinline__ void add_to(float* __restrict__ s) const {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      if constexpr (BF) {
+        const v4bf t = __builtin_bit_cast(v4bf, v[b]);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) s[4 * b + r] += (float)t[r];
+      } else {
+        s[4 * b + 0] += v[b].x;
+        s[4 * b + 1] += v[b].y;
+        s[4 * b + 2] += v[b].z;
+        s[4 * b + 3] += v[b].w;
+      }
+    }
+  }
+};
+
 template <int H, bool BF>
 struct GqCfg {
   static constexpr size_t FB = frag_bytes(H, 2 * H, BF);
@@ -432,6 +509,10 @@ template <int H, bool BF>
 __global__ __launch_bounds__(256) void k_gq(GqArgs a) {
   using C = GqCfg<H, BF>;
   constexpr int NF = H / 4, MB = H / 16, NT = dw_tiles_per_wave<2 * H, H>();
+  // edges gathered per round trip: as many raw rows as fit in 48 registers
+  // (6 at H=64 in BF16, the lattice's largest degree), at least 2, at most 8
+  constexpr int RAWREG = BF ? H / 8 : H / 4;
+  constexpr int GQ_CH = 48 / RAWREG < 2 ? 2 : (48 / RAWREG > 8 ? 8 : 48 / RAWREG);
   extern __shared__ uint4 smem[];
   char* tG = reinterpret_cast<char*>(smem);
   char* tA = tG + tile_bytes<2 * H, BF>();
@@ -458,42 +539,60 @@ __global__ __launch_bounds__(256) void k_gq(GqArgs a) {
 #pragma unroll
   for (int i = 0; i < NF; ++i) db1[i] = 0.f;
 
+  // CSR bounds run one block ahead; completed before the loop so that its
+  // entry state holds no pending loads
+  const int64_t E = gr.n_edges;
+  int p0_n, p1_n;
+  {
+    const int64_t bk = b0 + wave, row = bk * 16 + j;
+    const int64_t rr = (bk < b1 && row < n) ? row : n - 1;
+    p0_n = gr.rowptr[rr];
+    p1_n = gr.rowptr[rr + 1];
+    asm volatile("" : "+v"(p0_n), "+v"(p1_n));
+  }
+
   for (int64_t it = 0; it < n_iter; ++it) {
     const int64_t bk = b0 + it * kWaves + wave;
     const int64_t row = bk * 16 + j;
     const bool valid = bk < b1 && row < n;
     const int64_t rr = valid ? row : n - 1;
-    float in[2 * NF], xv[NF];
-    load_row<H>(a.g_P + rr * H, g, xv);
+    const int p0 = p0_n, deg = p1_n - p0_n;
+    {
+      const int64_t bk2 = bk + kWaves, row2 = bk2 * 16 + j;
+      const int64_t rr2 = (bk2 < b1 && row2 < n) ? row2 : n - 1;
+      p0_n = gr.rowptr[rr2];
+      p1_n = gr.rowptr[rr2 + 1];
+    }
+    // reverse-edge indices of the first GQ_CH incoming edges (positions past
+    // the row's end read an in-bounds index whose row is loaded, not added),
+    // and the node rows, all in one round trip
+    int rv[GQ_CH];
+#pragma unroll
+    for (int q = 0; q < GQ_CH; ++q) rv[q] = gr.rev[std::min<int64_t>(p0 + q, E - 1)];
+    float in[2 * NF], gp[NF], xv[NF], gx[NF];
+    load_row<H>(a.g_P + rr * H, g, gp);
+    load_row<H>(a.x + rr * H, g, xv);
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int i = 0; i < NF; ++i) {
-      in[i] = xv[i];
+      in[i] = gp[i];
       in[NF + i] = 0.f;
     }
-    // gather in chunks of 4 edges with all loads issued before the sums
-    // (added in ascending edge order); absent edges read the first one's row
-    const int p0 = gr.rowptr[rr], deg = gr.rowptr[rr + 1] - p0;
-    const int rv0 = deg > 0 ? gr.rev[p0] : 0;
-    for (int c = 0; __ballot(c < deg) != 0; c += 4) {
-      int rv[4];
+    // g_Q = sum of g_h over the reverse edges, added in ascending edge order
+    for (int c = 0;;) {
+      GqRaw<H, BF> t[GQ_CH];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) rv[q] = (c + q < deg) ? gr.rev[p0 + c + q] : rv0;
-      float t[4][NF];
+      for (int q = 0; q < GQ_CH; ++q) t[q].load(a.g_h, rv[q], g);
+      if (c == 0) load_row<H>(a.g_x + rr * H, g, gx);  // in flight with the gathers
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        if constexpr (BF)
-          load_row_bf16<H>(reinterpret_cast<const __bf16*>(a.g_h) + (int64_t)rv[q] * H, g, t[q]);
-        else
-          load_row<H>(reinterpret_cast<const float*>(a.g_h) + (int64_t)rv[q] * H, g, t[q]);
-      }
+      for (int q = 0; q < GQ_CH; ++q)
+        if (c + q < deg) t[q].add_to(in + NF);
+      c += GQ_CH;
+      if (__ballot(c < deg) == 0) break;
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        if (c + q < deg) {
-#pragma unroll
-          for (int i = 0; i < NF; ++i) in[NF + i] += t[q][i];
-        }
+      for (int q = 0; q < GQ_CH; ++q) rv[q] = gr.rev[std::min<int64_t>(p0 + c + q, E - 1)];
     }
-    load_row<H>(a.x + rr * H, g, xv);
     if (!valid) {
 #pragma unroll
       for (int i = 0; i < 2 * NF; ++i) in[i] = 0.f;
@@ -502,8 +601,6 @@ __global__ __launch_bounds__(256) void k_gq(GqArgs a) {
     for (int i = 0; i < NF; ++i) db1[i] += in[i];
     stage_row<2 * H, BF>(tG, wave * 16 + j, g, in);
     stage_row<H, BF>(tA, wave * 16 + j, g, xv);
-    float gx[NF];
-    load_row<H>(a.g_x + rr * H, g, gx);
     gemm<BF, MB, 2 * MB>(fr, in, gx, lane);
     if (valid) store_row<H>(a.g_x + row * H, g, gx);
     __syncthreads();

@@ -194,22 +194,46 @@ __global__ __launch_bounds__(256) void k_edge_fwd(DevGraph gr, const float* __re
     for (int i = 0; i < NF; ++i) carry[i] = 0.f;
     int carry_key = 0;
 
+    // Index loads run one block ahead (issued before the block's row
+    // loads), so each block waits on one round trip to memory, for its rows.
+    const int64_t e_last = e1 > e0 ? e1 - 1 : 0;  // in-bounds stand-in for absent edges
+    int ri_n, sj_n, md_n, nx_n;
+    {
+      const int64_t k = e0 + j, kk = k < e1 ? k : e_last;
+      ri_n = gr.recv[kk];
+      sj_n = gr.col[kk];
+      md_n = gr.mult[kk];
+      nx_n = (k + 1 < e1) ? gr.recv[k + 1] : -1;
+      // complete these here: the loop's entry state then holds no pending
+      // loads, so the compiler's wait at the loop head (merged with the
+      // back edge) does not also drain the previous block's stores
+      asm volatile("" : "+v"(ri_n), "+v"(sj_n), "+v"(md_n), "+v"(nx_n));
+    }
+
     for (int64_t base = e0; base < e1; base += 16) {
       const char* frb = fr + opaque_zero();  // re-read the fragments each block
       const int64_t k = base + j;
       const bool valid = k < e1;
-      const int64_t kk = valid ? k : e1 - 1;
-      const int ri = gr.recv[kk];
-      const int sj = gr.col[kk];
-      const float inv_d = 1.f / (float)gr.mult[kk];
-      const int next = (k + 1 < e1) ? gr.recv[k + 1] : -1;
+      const int64_t kk = valid ? k : e_last;
+      const int ri = ri_n;
+      const int sj = sj_n;
+      const float inv_d = 1.f / (float)md_n;
+      const int next = nx_n;
       const bool last = valid && next != ri;
       const int key = valid ? ri + 1 : -1;
+      {
+        const int64_t k2 = k + 16, kk2 = k2 < e1 ? k2 : e_last;
+        ri_n = gr.recv[kk2];
+        sj_n = gr.col[kk2];
+        md_n = gr.mult[kk2];
+        nx_n = (k2 + 1 < e1) ? gr.recv[k2 + 1] : -1;
+      }
 
       float ev[NF], h[NF], q[NF];
       load_row_nt<H>(e_in + kk * H, g, ev);
       load_row<H>(P + (int64_t)ri * H, g, h);
       load_row<H>(Q + (int64_t)sj * H, g, q);
+      __builtin_amdgcn_sched_barrier(0);  // all row loads issue before any use
 #pragma unroll
       for (int i = 0; i < NF; ++i) h[i] += q[i];
       gemm<BF, MB, MB>(frb, ev, h, lane);
