@@ -109,11 +109,11 @@ __device__ __forceinline__ float tile_colsum(const void* __restrict__ tile) {
   return s;
 }
 
-// Write the owned tiles into a row-major [GW][kcols] block of the slab
-// (kcols <= AW drops padded columns).
+// Write the owned tiles into a row-major [frows][kcols] block of the slab
+// (kcols <= AW and frows <= GW drop padded columns and rows).
 template <int GW, int AW, int NW = kWaves>
 __device__ __forceinline__ void dw_store(const v4f (&acc)[dw_tiles_per_wave<GW, AW, NW>()], float* __restrict__ dst,
-                                         int kcols, int wave, int lane) {
+                                         int kcols, int wave, int lane, int frows = GW) {
   constexpr int NT = dw_tiles_per_wave<GW, AW, NW>(), NTILE = (GW / 16) * (AW / 16), KBN = AW / 16;
 #pragma unroll
   for (int n = 0; n < NT; ++n) {
@@ -124,7 +124,7 @@ __device__ __forceinline__ void dw_store(const v4f (&acc)[dw_tiles_per_wave<GW, 
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int f = 16 * fb + 4 * (lane >> 4) + v;
-        if (k < kcols) dst[f * kcols + k] = acc[n][v];
+        if (k < kcols && f < frows) dst[f * kcols + k] = acc[n][v];
       }
     }
   }
@@ -643,7 +643,8 @@ struct MlpBwdCfg {
   static constexpr size_t FRAG = 2 * F0 + 2 * F1;
   static constexpr size_t TB = tile_bytes<H, BF, ROWS>();
   static constexpr size_t STAGE0 = TB + tile_bytes<AW0, BF, ROWS>();
-  static constexpr size_t STAGE1 = TOUT ? 0 : (VEC ? 4 : 2) * TB;
+  // phase 1: [g_y, u (, g_out, g_out * normalised y)]; small output: [g_out (16 wide), u]
+  static constexpr size_t STAGE1 = (VEC ? 4 : 2) * TB;
   static constexpr size_t STAGE = STAGE0 > STAGE1 ? STAGE0 : STAGE1;
   static constexpr size_t SMALL = (TIN || TOUT) ? 16 * H : 0;  // small W0 / W1, [.][4] or [4][H]
   static constexpr size_t VECS = 3 * H * sizeof(float);         // b0, b1, LayerNorm gain
@@ -651,15 +652,62 @@ struct MlpBwdCfg {
   static constexpr size_t LDS = STAGE + (LDS_FRAG ? FRAG : 0) + SMALL + VECS;
 };
 
+// The rows one 16-row block of k_mlp_bwd reads: its inputs and the
+// gradient at its output.
+template <int H, int KIN, bool TIN, bool TOUT>
+struct MlpBwdIn {
+  static constexpr int NF = H / 4, NIN = TIN ? 4 : KIN / 4, NGO = TOUT ? 4 : H / 4;
+  float in[NIN];
+  float go[NGO];
+  __device__ __forceinline__ void load(const MlpBwdArgs& a, int64_t rr, int g) {
+    if constexpr (TIN) {
+      // k0 <= 4 features per row; columns past k0 read column k0-1, then 0
+#pragma unroll
+      for (int k = 0; k < 4; ++k) in[k] = a.src0[rr * a.k0 + (k < a.k0 ? k : a.k0 - 1)];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) in[k] = k < a.k0 ? in[k] : 0.f;
+    } else if constexpr (KIN == 2 * H) {
+      float t0[NF], t1[NF];
+      load_row<H>(a.src0 + rr * H, g, t0);
+      load_row<H>(a.src1 + rr * H, g, t1);
+#pragma unroll
+      for (int i = 0; i < NF; ++i) {
+        in[i] = t0[i];
+        in[NF + i] = t1[i];
+      }
+    } else {
+      load_row<KIN>(a.src0 + rr * KIN, g, in);
+    }
+    if constexpr (TOUT) {
+      // n_out <= 4 outputs; the same clamp-then-zero as the inputs
+#pragma unroll
+      for (int o = 0; o < 4; ++o) go[o] = a.g_out[rr * a.n_out + (o < a.n_out ? o : a.n_out - 1)];
+#pragma unroll
+      for (int o = 0; o < 4; ++o) go[o] = o < a.n_out ? go[o] : 0.f;
+    } else {
+      load_row<H>(a.g_out + rr * H, g, go);
+    }
+  }
+  __device__ __forceinline__ void settle() {
+#pragma unroll
+    for (int i = 0; i < NIN; ++i) asm volatile("" : "+v"(in[i]));
+#pragma unroll
+    for (int i = 0; i < NGO; ++i) asm volatile("" : "+v"(go[i]));
+  }
+};
+
 // Adjoint of k_mlp_fwd, forward recomputed per row block:
 //   z = W0 in + b0, u = ELU(z), y = W1 u + b1, out = [resid +] LN(y)
 // Two staging phases per step (dW1 with its bias / LayerNorm sums, then
-// dW0 and db0) share the same LDS.
+// dW0 and db0) share the same LDS.  The next block's rows are loaded while
+// the current one is processed (one block ahead, as in k_mlp_fwd).
 template <int H, int KIN, bool TIN, bool TOUT, bool BF>
 __global__ __launch_bounds__((64 * MlpBwdCfg<H, KIN, TIN, TOUT, BF>::NW)) void k_mlp_bwd(MlpBwdArgs a) {
   using C = MlpBwdCfg<H, KIN, TIN, TOUT, BF>;
+  using In = MlpBwdIn<H, KIN, TIN, TOUT>;
   constexpr int NF = H / 4, MB = H / 16, KB = TIN ? 1 : KIN / 16, AW0 = C::AW0, NW = C::NW, ROWS = C::ROWS;
-  constexpr int NT1 = dw_tiles_per_wave<H, H, NW>(), NT0 = dw_tiles_per_wave<H, AW0, NW>();
+  constexpr int NT1 = TOUT ? dw_tiles_per_wave<16, H, NW>() : dw_tiles_per_wave<H, H, NW>();
+  constexpr int NT0 = dw_tiles_per_wave<H, AW0, NW>();
   extern __shared__ uint4 smem[];
   char* tG = reinterpret_cast<char*>(smem);
   char* tA = tG + C::TB;
@@ -685,6 +733,8 @@ __global__ __launch_bounds__((64 * MlpBwdCfg<H, KIN, TIN, TOUT, BF>::NW)) void k
     vecs[t] = t < H ? a.b0[t] : (t < 2 * H ? (TOUT ? 0.f : a.b1[t - H]) : (a.ln ? a.lng[t - 2 * H] : 0.f));
   __syncthreads();
   const bool want_gin = (a.g_src0 || a.g_src1) && !TIN;
+  // the residual path's gradient is usually g_out itself (node update)
+  const bool add1_is_gout = a.g_add1 != nullptr && a.g_add1 == a.g_out;
 
   const int lane = lane_id(), j = lane & 15, g = lane >> 4, wave = threadIdx.x / 64;
   const int srow = wave * 16 + j;
@@ -703,14 +753,16 @@ __global__ __launch_bounds__((64 * MlpBwdCfg<H, KIN, TIN, TOUT, BF>::NW)) void k
   float db0[NV], db1[NV], dga[NV], dbe[NV];
 #pragma unroll
   for (int i = 0; i < NV; ++i) db0[i] = db1[i] = dga[i] = dbe[i] = 0.f;
-  constexpr int NS = TOUT ? NF : 1;
-  float dW1s[4][NS];  // small-output dW1 rows (n_out <= 4)
-  float db1s[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-  for (int o = 0; o < 4; ++o)
-#pragma unroll
-    for (int i = 0; i < NS; ++i) dW1s[o][i] = 0.f;
+  float db1s[4] = {0.f, 0.f, 0.f, 0.f};  // small-output db1 (lane group 0)
 
+  // one-block-ahead loads where registers allow (H <= 64)
+  constexpr bool PF = H <= 64;
+  In nx;
+  if constexpr (PF) {
+    const int64_t row = b0 * 16 + wave * 16 + j;
+    nx.load(a, (b0 + wave < b1 && row < n) ? row : n - 1, g);
+    nx.settle();  // the loop's entry state holds no pending loads
+  }
   for (int64_t it = 0; it < n_iter; ++it) {
     const int oz = opaque_zero();  // re-read fragments and vectors each block
     const char* f0 = (C::LDS_FRAG ? fr : reinterpret_cast<const char*>(a.frag0)) + oz;
@@ -722,65 +774,61 @@ __global__ __launch_bounds__((64 * MlpBwdCfg<H, KIN, TIN, TOUT, BF>::NW)) void k
     const int64_t row = bk * 16 + j;
     const bool valid = bk < b1 && row < n;
     const int64_t rr = valid ? row : n - 1;
+    In cur;
+    if constexpr (PF) {
+      cur = nx;
+      const int64_t bk2 = bk + NW, row2 = bk2 * 16 + j;
+      nx.load(a, (bk2 < b1 && row2 < n) ? row2 : n - 1, g);
+    } else {
+      cur.load(a, rr, g);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    if (!valid) {
+#pragma unroll
+      for (int i = 0; i < In::NGO; ++i) cur.go[i] = 0.f;
+    }
     // ---- recompute
-    float in[TIN ? 4 : KIN / 4];
     float z[NF];
     load_vec<H>(vb, g, z);
     if constexpr (TIN) {
-#pragma unroll
-      for (int k = 0; k < 4; ++k) in[k] = k < a.k0 ? a.src0[rr * a.k0 + k] : 0.f;
-      small_in_linear<H>(small, in, g, z);
+      small_in_linear<H>(small + oz, cur.in, g, z);
     } else {
-      if constexpr (KIN == 2 * H) {
-        float t0[NF], t1[NF];
-        load_row<H>(a.src0 + rr * H, g, t0);
-        load_row<H>(a.src1 + rr * H, g, t1);
-#pragma unroll
-        for (int i = 0; i < NF; ++i) {
-          in[i] = t0[i];
-          in[NF + i] = t1[i];
-        }
-      } else {
-        load_row<KIN>(a.src0 + rr * KIN, g, in);
-      }
-      gemm<BF, MB, KB>(f0, in, z, lane);
+      gemm<BF, MB, KB>(f0, cur.in, z, lane);
     }
     float u[NF];
 #pragma unroll
     for (int i = 0; i < NF; ++i) u[i] = elu(z[i]);
-    // ---- gradient at u
+    // ---- gradient at u, and phase 1: dW1 (with its bias / LayerNorm sums)
     float gu[NF];
     if constexpr (TOUT) {
-      float go[4];
-#pragma unroll
-      for (int o = 0; o < 4; ++o) go[o] = (o < NO && valid) ? a.g_out[rr * NO + o] : 0.f;
 #pragma unroll
       for (int i = 0; i < NF; ++i) gu[i] = 0.f;
 #pragma unroll
       for (int o = 0; o < 4; ++o) {
         float w[NF];
-        load_vec<H>(small + o * H, g, w);
+        load_vec<H>(small + oz + o * H, g, w);
 #pragma unroll
-        for (int i = 0; i < NF; ++i) gu[i] += w[i] * go[o];
+        for (int i = 0; i < NF; ++i) gu[i] += w[i] * cur.go[o];
       }
-#pragma unroll
-      for (int o = 0; o < 4; ++o)
-#pragma unroll
-        for (int i = 0; i < NS; ++i) dW1s[o][i] += go[o] * u[i];
       // db1 (n_out values): one copy per row, in lane group 0
       if (g == 0) {
 #pragma unroll
-        for (int o = 0; o < 4; ++o) db1s[o] += go[o];
+        for (int o = 0; o < 4; ++o) db1s[o] += cur.go[o];
       }
+      // dW1 += g_out u^T: g_out staged 16 wide (lane group 0 holds outputs 0..3)
+      float go16[4];
+#pragma unroll
+      for (int o = 0; o < 4; ++o) go16[o] = g == 0 ? cur.go[o] : 0.f;
+      stage_row<16, BF, ROWS>(tG, srow, g, go16);
+      stage_row<H, BF, ROWS>(tA, srow, g, u);
+      __syncthreads();
+      dw_tiles<16, H, BF, NW>(tG, tA, acc1, wave, lane);
+      __syncthreads();
     } else {
-      float y[NF], go[NF];
+      float y[NF];
       load_vec<H>(vb + H, g, y);
       gemm<BF, MB, MB>(f1, u, y, lane);
-      load_row<H>(a.g_out + rr * H, g, go);
-      if (!valid) {
-#pragma unroll
-        for (int i = 0; i < NF; ++i) go[i] = 0.f;
-      }
+      const float* go = cur.go;
       if (a.ln) {
         float mean, rstd, s1 = 0.f, s2 = 0.f, gam[NF];
         ln_stats<H>(y, a.eps, mean, rstd);
@@ -801,7 +849,7 @@ __global__ __launch_bounds__((64 * MlpBwdCfg<H, KIN, TIN, TOUT, BF>::NW)) void k
           float t[NF];
 #pragma unroll
           for (int i = 0; i < NF; ++i) t[i] = go[i] * y[i];
-          stage_row<H, BF, ROWS>(tGE, srow, g, go);
+          stage_row<H, BF, ROWS>(tGE, srow, g, cur.go);
           stage_row<H, BF, ROWS>(tGM, srow, g, t);
         }
         s1 = row_sum(s1) * (1.f / H);
@@ -816,7 +864,6 @@ __global__ __launch_bounds__((64 * MlpBwdCfg<H, KIN, TIN, TOUT, BF>::NW)) void k
 #pragma unroll
         for (int i = 0; i < NF; ++i) db1[i] += y[i];
       }
-      // phase 1: dW1 += gy u^T (and the bias / LayerNorm column sums)
       stage_row<H, BF, ROWS>(tG, srow, g, y);
       stage_row<H, BF, ROWS>(tA, srow, g, u);
       __syncthreads();
@@ -833,7 +880,7 @@ __global__ __launch_bounds__((64 * MlpBwdCfg<H, KIN, TIN, TOUT, BF>::NW)) void k
       for (int i = 0; i < NF; ++i) gu[i] = 0.f;
       gemm<BF, MB, MB>(f1t, y, gu, lane);
     }
-    // ---- gradient at z, dW0, db0
+    // ---- gradient at z; phase 0: dW0, db0
 #pragma unroll
     for (int i = 0; i < NF; ++i) gu[i] *= (u[i] > 0.f ? 1.f : u[i] + 1.f);
     if constexpr (!C::VEC) {
@@ -842,14 +889,12 @@ __global__ __launch_bounds__((64 * MlpBwdCfg<H, KIN, TIN, TOUT, BF>::NW)) void k
     }
     stage_row<H, BF, ROWS>(tG, srow, g, gu);
     if constexpr (TIN) {
-      float in16[4] = {0.f, 0.f, 0.f, 0.f};  // lane group g holds input features 4g..4g+3
-      if (g == 0) {
+      float in16[4];  // lane group g holds input features 4g..4g+3
 #pragma unroll
-        for (int k = 0; k < 4; ++k) in16[k] = in[k];
-      }
+      for (int k = 0; k < 4; ++k) in16[k] = g == 0 ? cur.in[k] : 0.f;
       stage_row<16, BF, ROWS>(tA, srow, g, in16);
     } else {
-      stage_row<KIN, BF, ROWS>(tA, srow, g, in);
+      stage_row<KIN, BF, ROWS>(tA, srow, g, cur.in);
     }
     __syncthreads();
     dw_tiles<H, AW0, BF, NW>(tG, tA, acc0, wave, lane);
@@ -869,21 +914,26 @@ __global__ __launch_bounds__((64 * MlpBwdCfg<H, KIN, TIN, TOUT, BF>::NW)) void k
             t0[i] = gi[i];
             t1[i] = gi[NF + i];
           }
-          if (a.g_add1) {
+          if (add1_is_gout) {
+#pragma unroll
+            for (int i = 0; i < NF; ++i) t1[i] += cur.go[i];
+          } else if (a.g_add1) {
             float r[NF];
             load_row<H>(a.g_add1 + rr * H, g, r);
 #pragma unroll
             for (int i = 0; i < NF; ++i) t1[i] += r[i];
           }
+          if constexpr (PF) nx.settle();  // next block's loads complete before this block's stores
           if (valid && a.g_src0) store_row<H>(a.g_src0 + row * H, g, t0);
           if (valid && a.g_src1) store_row<H>(a.g_src1 + row * H, g, t1);
         } else {
+          if constexpr (PF) nx.settle();
           if (valid && a.g_src0) store_row<KIN>(a.g_src0 + row * KIN, g, gi);
         }
       }
     }
   }
-  // ---- write the slab
+  // ---- write the slab: [dW0 | db0 | dW1 | db1 | dgamma | dbeta]
   float* slab = a.part + blockIdx.x * a.slab;
   const int k0w = TIN ? a.k0 : KIN;
   dw_store<H, AW0, NW>(acc0, slab, k0w, wave, lane);
@@ -894,7 +944,7 @@ __global__ __launch_bounds__((64 * MlpBwdCfg<H, KIN, TIN, TOUT, BF>::NW)) void k
     block_sum_vec<H, NW>(db0, scratch, slab + H * k0w, wave, lane);
   float* s1 = slab + H * k0w + H;
   if constexpr (TOUT) {
-    for (int o = 0; o < NO; ++o) block_sum_vec<H, NW>(dW1s[o], scratch, s1 + o * H, wave, lane);
+    dw_store<16, H, NW>(acc1, s1, H, wave, lane, NO);
     // db1: summed over the workgroup's lanes in a fixed order
     __syncthreads();
 #pragma unroll

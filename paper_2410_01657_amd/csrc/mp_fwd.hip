@@ -88,18 +88,28 @@ __global__ __launch_bounds__(256) void k_proj(int64_t n_rows, const float* __res
   }
   const int lane = lane_id(), j = lane & 15, g = lane >> 4;
   const int nw = blockDim.x / 64;
-  const int64_t nblk = (n_rows + 15) / 16;
-  for (int64_t blk = (int64_t)blockIdx.x * nw + threadIdx.x / 64; blk < nblk; blk += (int64_t)gridDim.x * nw) {
+  const int64_t nblk = (n_rows + 15) / 16, stride = (int64_t)gridDim.x * nw;
+  // one block ahead: the next block's x row loads before this block computes
+  int64_t blk = (int64_t)blockIdx.x * nw + threadIdx.x / 64;
+  float xn[NF];
+  load_row<H>(x + std::min<int64_t>(blk * 16 + j, n_rows - 1) * H, g, xn);
+#pragma unroll
+  for (int i = 0; i < NF; ++i) asm volatile("" : "+v"(xn[i]));  // no pending loads at the loop entry
+  for (; blk < nblk; blk += stride) {
     const int64_t row = blk * 16 + j;
     const bool valid = row < n_rows;
-    const int64_t rr = valid ? row : n_rows - 1;
     float xv[NF], p[NF], q[NF];
-    load_row<H>(x + rr * H, g, xv);
+#pragma unroll
+    for (int i = 0; i < NF; ++i) xv[i] = xn[i];
+    load_row<H>(x + std::min<int64_t>((blk + stride) * 16 + j, n_rows - 1) * H, g, xn);
+    __builtin_amdgcn_sched_barrier(0);
     load_vec<H>(b1, g, p);
 #pragma unroll
     for (int i = 0; i < NF; ++i) q[i] = 0.f;
     gemm<BF, MB, MB>(fr, xv, p, lane);
     gemm<BF, MB, MB>(fr + FB, xv, q, lane);
+#pragma unroll
+    for (int i = 0; i < NF; ++i) asm volatile("" : "+v"(xn[i]));  // before this block's stores
     if (valid) {
       store_row<H>(P + row * H, g, p);
       store_row<H>(Q + row * H, g, q);
@@ -347,25 +357,78 @@ hipError_t launch_halo(int H, const DevGraph& g, float* a, hipStream_t s) {
 // TIN: in has k0 <= 4 features; the first Linear is done with FMAs from
 // the raw weights.  TOUT: n_out < 16 outputs; the second Linear is done
 // with FMAs and a reduction over the four lanes of each row.
+//
+// Each wave walks its 16-row blocks software-pipelined: the next block's
+// inputs are loaded before this block is computed and stored, so a block
+// waits on memory only for loads issued one block earlier.  Per-feature
+// vectors (b0, b1, LayerNorm gain and shift) and small weights sit in LDS.
+template <int H, int KIN, bool TIN, bool TOUT>
+struct MlpFwdIn {
+  static constexpr int NF = H / 4, NIN = TIN ? 4 : KIN / 4;
+  float in[NIN];
+  float r[(KIN == 2 * H || TIN || TOUT) ? 1 : NF];  // residual row when it is not src1
+  __device__ __forceinline__ void load(const MlpFwdArgs& a, int64_t rr, int g, bool sep_resid) {
+    if constexpr (TIN) {
+      // k0 <= 4 features per row; columns past k0 read column k0-1, then 0
+#pragma unroll
+      for (int k = 0; k < 4; ++k) in[k] = a.src0[rr * a.k0 + (k < a.k0 ? k : a.k0 - 1)];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) in[k] = k < a.k0 ? in[k] : 0.f;
+    } else if constexpr (KIN == 2 * H) {
+      float t0[NF], t1[NF];
+      load_row<H>(a.src0 + rr * H, g, t0);
+      load_row<H>(a.src1 + rr * H, g, t1);
+#pragma unroll
+      for (int i = 0; i < NF; ++i) {
+        in[i] = t0[i];
+        in[NF + i] = t1[i];
+      }
+    } else {
+      load_row<KIN>(a.src0 + rr * KIN, g, in);
+      if constexpr (!TOUT) {
+        if (sep_resid) load_row<H>(a.resid + rr * H, g, r);
+      }
+    }
+  }
+  __device__ __forceinline__ void settle() {
+#pragma unroll
+    for (int i = 0; i < NIN; ++i) asm volatile("" : "+v"(in[i]));
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(r) / sizeof(float)); ++i) asm volatile("" : "+v"(r[i]));
+  }
+};
+
+template <int H, int KIN, bool TIN, bool TOUT, bool BF>
+struct MlpFwdCfg {
+  static constexpr size_t F0 = TIN ? 0 : frag_bytes(H, KIN, BF);
+  static constexpr size_t F1 = TOUT ? 0 : frag_bytes(H, H, BF);
+  static constexpr bool LDS_FRAG = (F0 + F1) <= kRowMlpLdsBudget;
+  static constexpr size_t SMALL = (TIN || TOUT) ? 16 * H : 0;  // small W0 [H][4] or W1 [4][H]
+  static constexpr size_t VECS = 4 * H * sizeof(float);        // b0, b1, LayerNorm gain, shift
+  static constexpr size_t LDS = (LDS_FRAG ? F0 + F1 : 0) + SMALL + VECS;
+};
+
 template <int H, int KIN, bool TIN, bool TOUT, bool BF>
 __global__ __launch_bounds__(256) void k_mlp_fwd(MlpFwdArgs a) {
+  using C = MlpFwdCfg<H, KIN, TIN, TOUT, BF>;
   constexpr int NF = H / 4, MB = H / 16, KB = TIN ? 1 : KIN / 16;
-  constexpr size_t F0 = TIN ? 0 : frag_bytes(H, KIN, BF);
-  constexpr size_t F1 = TOUT ? 0 : frag_bytes(H, H, BF);
-  constexpr bool LDS = (F0 + F1) <= kRowMlpLdsBudget;
   extern __shared__ uint4 smem[];
   const char* f0;
   const char* f1;
-  // small weights (W0 of a small input, W1 of a small output) after the fragments
-  float* small = reinterpret_cast<float*>(reinterpret_cast<char*>(smem) + (LDS ? F0 + F1 : 0));
+  float* small = reinterpret_cast<float*>(reinterpret_cast<char*>(smem) + (C::LDS_FRAG ? C::F0 + C::F1 : 0));
+  float* vecs = small + C::SMALL / 4;
   if constexpr (TIN) stage_small(small, a.W0, H, a.k0);
   if constexpr (TOUT)
     for (int t = threadIdx.x; t < 4 * H; t += blockDim.x) small[t] = (t / H) < a.n_out ? a.W1[t] : 0.f;
-  if constexpr (LDS) {
-    if (F0) stage_to_lds(smem, a.frag0, F0);
-    if (F1) stage_to_lds(smem + F0 / 16, a.frag1, F1);
+  for (int t = threadIdx.x; t < 4 * H; t += blockDim.x) {
+    const int q = t / H, f = t % H;
+    vecs[t] = q == 0 ? a.b0[f] : q == 1 ? (TOUT ? 0.f : a.b1[f]) : q == 2 ? (a.ln ? a.lng[f] : 0.f) : (a.ln ? a.lnb[f] : 0.f);
+  }
+  if constexpr (C::LDS_FRAG) {
+    if (C::F0) stage_to_lds(smem, a.frag0, C::F0);
+    if (C::F1) stage_to_lds(smem + C::F0 / 16, a.frag1, C::F1);
     f0 = reinterpret_cast<const char*>(smem);
-    f1 = f0 + F0;
+    f1 = f0 + C::F0;
   } else {
     f0 = reinterpret_cast<const char*>(a.frag0);
     f1 = reinterpret_cast<const char*>(a.frag1);
@@ -373,64 +436,69 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(MlpFwdArgs a) {
   __syncthreads();
   const int lane = lane_id(), j = lane & 15, g = lane >> 4;
   const int nw = blockDim.x / 64;
-  const int64_t n = a.n_rows, nblk = (n + 15) / 16;
-  for (int64_t blk = (int64_t)blockIdx.x * nw + threadIdx.x / 64; blk < nblk; blk += (int64_t)gridDim.x * nw) {
+  const int64_t n = a.n_rows, nblk = (n + 15) / 16, stride = (int64_t)gridDim.x * nw;
+  // the residual is src1 for the node update; otherwise it is a row of its own
+  const bool sep_resid = !TOUT && a.resid != nullptr && !(KIN == 2 * H && a.resid == a.src1);
+  const bool has_resid = !TOUT && a.resid != nullptr;
+
+  int64_t blk = (int64_t)blockIdx.x * nw + threadIdx.x / 64;
+  MlpFwdIn<H, KIN, TIN, TOUT> nx;
+  nx.load(a, std::min<int64_t>(blk * 16 + j, n - 1), g, sep_resid);
+  nx.settle();  // the loop's entry state holds no pending loads
+  for (; blk < nblk; blk += stride) {
     const int64_t row = blk * 16 + j;
     const bool valid = row < n;
-    const int64_t rr = valid ? row : n - 1;
+    const MlpFwdIn<H, KIN, TIN, TOUT> cur = nx;
+    nx.load(a, std::min<int64_t>((blk + stride) * 16 + j, n - 1), g, sep_resid);
+    __builtin_amdgcn_sched_barrier(0);
+
+    const float* vb = vecs + opaque_zero();  // re-read the vectors each block
     float z[NF];
-    load_vec<H>(a.b0, g, z);
+    load_vec<H>(vb, g, z);
     if constexpr (TIN) {
-      float in[4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) in[k] = k < a.k0 ? a.src0[rr * a.k0 + k] : 0.f;
-      small_in_linear<H>(small, in, g, z);
+      small_in_linear<H>(small + opaque_zero(), cur.in, g, z);
     } else {
-      float in[KIN / 4];
-      if constexpr (KIN == 2 * H) {
-        float t0[NF], t1[NF];
-        load_row<H>(a.src0 + rr * H, g, t0);
-        load_row<H>(a.src1 + rr * H, g, t1);
-#pragma unroll
-        for (int i = 0; i < NF; ++i) {
-          in[i] = t0[i];
-          in[NF + i] = t1[i];
-        }
-      } else {
-        load_row<KIN>(a.src0 + rr * KIN, g, in);
-      }
-      gemm<BF, MB, KB>(f0, in, z, lane);
+      gemm<BF, MB, KB>(f0 + opaque_zero(), cur.in, z, lane);
     }
 #pragma unroll
     for (int i = 0; i < NF; ++i) z[i] = elu(z[i]);
     if constexpr (TOUT) {
-      for (int o = 0; o < a.n_out; ++o) {
+      float p[4];
+      for (int o = 0; o < 4; ++o) {
         float w[NF];
         load_vec<H>(small + o * H, g, w);
-        float p = 0.f;
+        float t = 0.f;
 #pragma unroll
-        for (int i = 0; i < NF; ++i) p += w[i] * z[i];
-        p = row_sum(p);
-        if (valid && g == 0) a.out[row * a.n_out + o] = p + a.b1[o];
+        for (int i = 0; i < NF; ++i) t += w[i] * z[i];
+        p[o] = row_sum(t);
       }
+      nx.settle();  // next block's loads complete before this block's stores
+      for (int o = 0; o < a.n_out; ++o)
+        if (valid && g == 0) a.out[row * a.n_out + o] = p[o] + a.b1[o];
     } else {
       float y[NF];
-      load_vec<H>(a.b1, g, y);
-      gemm<BF, MB, MB>(f1, z, y, lane);
+      load_vec<H>(vb + H, g, y);
+      gemm<BF, MB, MB>(f1 + opaque_zero(), z, y, lane);
       if (a.ln) {
         float mean, rstd, gm[NF], bt[NF];
-        load_vec<H>(a.lng, g, gm);
-        load_vec<H>(a.lnb, g, bt);
+        load_vec<H>(vb + 2 * H, g, gm);
+        load_vec<H>(vb + 3 * H, g, bt);
         ln_stats<H>(y, a.eps, mean, rstd);
 #pragma unroll
         for (int i = 0; i < NF; ++i) y[i] = (y[i] - mean) * rstd * gm[i] + bt[i];
       }
-      if (a.resid) {
-        float r[NF];
-        load_row<H>(a.resid + rr * H, g, r);
+      if (has_resid) {
+        if constexpr (KIN == 2 * H) {
+          if (!sep_resid) {
 #pragma unroll
-        for (int i = 0; i < NF; ++i) y[i] += r[i];
+            for (int i = 0; i < NF; ++i) y[i] += cur.in[NF + i];
+          }
+        } else if constexpr (!TIN) {
+#pragma unroll
+          for (int i = 0; i < NF; ++i) y[i] += cur.r[i];
+        }
       }
+      nx.settle();  // next block's loads complete before this block's stores
       if (valid) store_row<H>(a.out + row * H, g, y);
     }
   }
@@ -438,13 +506,13 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(MlpFwdArgs a) {
 
 template <int H, int KIN, bool TIN, bool TOUT, bool BF>
 static hipError_t launch_mlp_fwd_t(const MlpFwdArgs& a, int grid, hipStream_t s) {
-  constexpr size_t F0 = TIN ? 0 : frag_bytes(H, KIN, BF);
-  constexpr size_t F1 = TOUT ? 0 : frag_bytes(H, H, BF);
-  const size_t lds = ((F0 + F1 <= kRowMlpLdsBudget) ? F0 + F1 : 0) + ((TIN || TOUT) ? 16 * H : 0);
-  if (lds > 64 * 1024)
+  using C = MlpFwdCfg<H, KIN, TIN, TOUT, BF>;
+  // residual rows other than src1 exist only for the H-input form
+  if (a.resid && !(KIN == H && !TIN && !TOUT) && !(KIN == 2 * H && a.resid == a.src1)) return hipErrorInvalidValue;
+  if (C::LDS > 64 * 1024)
     (void)hipFuncSetAttribute((const void*)k_mlp_fwd<H, KIN, TIN, TOUT, BF>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)lds);
-  hipLaunchKernelGGL((k_mlp_fwd<H, KIN, TIN, TOUT, BF>), dim3(grid), dim3(256), lds, s, a);
+                              (int)C::LDS);
+  hipLaunchKernelGGL((k_mlp_fwd<H, KIN, TIN, TOUT, BF>), dim3(grid), dim3(256), C::LDS, s, a);
   return hipGetLastError();
 }
 
