@@ -68,6 +68,45 @@ def copy_calibration():
     print(json.dumps({"copy_bytes": n * 4}), flush=True)
 
 
+# Measured HBM traffic of the dominant kernel: a summary of two rocprofv3
+# --pmc runs (FETCH_SIZE, WRITE_SIZE), scaled by the same counters on a plain
+# copy of known size.  It holds the SHA-256 of the kernel's source files and
+# is used only while they are unchanged (else traffic is null).
+TRAFFIC_PROFILE = "profiles/c1_r16_bf16_hbm_traffic.md"
+KERNEL_SOURCES = {"edge_bwd": ("mp_bwd.hip", "mp_device.hpp", "mp_kernels.hpp"),
+                  "edge_fwd": ("mp_fwd.hip", "mp_device.hpp", "mp_kernels.hpp")}
+
+
+def sources_sha256(kernel):
+    import hashlib
+    import os
+    h = hashlib.sha256()
+    root = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2410_01657_amd", "csrc")
+    for f in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(root, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(kernel, workload):
+    """HBM bytes per launch (read + write) of `kernel` from the traffic
+    summary, or None when absent, for another workload, or stale."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), TRAFFIC_PROFILE)
+    if kernel not in KERNEL_SOURCES or not os.path.exists(path):
+        return None
+    rec = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("traffic:"):
+                kv = dict(t.split("=", 1) for t in line.split()[1:])
+                if kv.get("kernel") == kernel:
+                    rec = kv
+    if not rec or rec.get("workload") != workload or rec.get("sources_sha256") != sources_sha256(kernel):
+        return None
+    return float(rec["read_bytes"]) + float(rec["write_bytes"])
+
+
 KERNELS = ("pack", "tiles", "proj", "edge_fwd", "halo", "halo_adj", "node_fwd", "node_bwd", "edge_bwd",
            "gq", "wreduce", "mlp_fwd", "mlp_bwd", "edge_inputs", "loss")
 
@@ -209,7 +248,7 @@ def main():
     main_path = res["bf16"]
     value = E_global * spec.n_layers / (main_path["ms"] * 1e-3)
     # dominant kernel of the main path and its roofline
-    work = layer_kernels(N, E, G, M, spec.H)
+    work = layer_kernels(N, E, G, M, spec.H, "bf16", spec.n_layers)
     kern = main_path["kernels"]
     dom = max((k for k in kern if k in work), key=lambda k: kern[k]["ms_total"])
     w = work[dom]
@@ -221,10 +260,12 @@ def main():
         roof = {"bound": "mfma", "achieved": w.flops / avg_s / 1e12, "peak": PEAK["bf16"] / 1e12,
                 "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    tr = recorded_traffic(dom, a.workload)
+    roof["traffic"] = tr / 1e9 if tr is not None else None  # GB per launch, measured
     roof["kernel"] = dom
     roof["ms_avg"] = kern[dom]["ms_avg"]
     roof["algorithmic_GB"] = w.bytes / 1e9
+    roof["traffic_unit"] = "GB per launch (HBM read + write)"
 
     line = {
         "metric": "MP-layer fwd+bwd edges/sec, BF16-MFMA vs FP32, at stated rel. error vs FP64",

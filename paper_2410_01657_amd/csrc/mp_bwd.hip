@@ -35,12 +35,31 @@ struct Stg {
 template <int W, bool BF, int ROWS = 64>
 constexpr size_t tile_bytes() { return size_t(W) * Stg<BF, ROWS>::RS * (BF ? 2 : 4); }
 
-template <int W, bool BF, int ROWS = 64>
+template <int W, bool BF, int ROWS = 64, bool PK = true>
 __device__ __forceinline__ void stage_row(void* __restrict__ tile, int row, int g, const float (&v)[W / 4]) {
-  using T = typename Stg<BF, ROWS>::T;
-  T* t = reinterpret_cast<T*>(tile);
+  constexpr int RS = Stg<BF, ROWS>::RS;
+  if constexpr (BF && !PK) {
+    // one conversion per value (fewer live registers than the packed form)
+    __bf16* t = reinterpret_cast<__bf16*>(tile);
 #pragma unroll
-  for (int i = 0; i < W / 4; ++i) t[(16 * (i / 4) + 4 * g + (i % 4)) * Stg<BF, ROWS>::RS + row] = (T)v[i];
+    for (int i = 0; i < W / 4; ++i) t[(16 * (i / 4) + 4 * g + (i % 4)) * RS + row] = (__bf16)v[i];
+  } else if constexpr (BF) {
+    // features f, f+1 (consecutive in the lane) are rounded as one pair and
+    // written as the low and high halves of the packed value
+    uint16_t* t = reinterpret_cast<uint16_t*>(tile);
+#pragma unroll
+    for (int i = 0; i < W / 4; i += 2) {
+      const int f = 16 * (i / 4) + 4 * g + (i % 4);
+      uint32_t pk = __builtin_bit_cast(uint32_t, v2bf{(__bf16)v[i], (__bf16)v[i + 1]});
+      asm volatile("" : "+v"(pk));  // keep the pair packed (one conversion, two half stores)
+      t[f * RS + row] = (uint16_t)pk;
+      t[(f + 1) * RS + row] = (uint16_t)(pk >> 16);
+    }
+  } else {
+    float* t = reinterpret_cast<float*>(tile);
+#pragma unroll
+    for (int i = 0; i < W / 4; ++i) t[(16 * (i / 4) + 4 * g + (i % 4)) * RS + row] = v[i];
+  }
 }
 
 template <int GW, int AW, int NW = kWaves>
@@ -87,27 +106,95 @@ __device__ __forceinline__ void dw_tiles(const void* __restrict__ G, const void*
   }
 }
 
-// Per-thread column sums of a staged W-wide tile: thread t adds the rows
-// [s*W/4... ) segment of feature t % W it owns (64*NW threads, W features,
-// 64*NW/W segments of ROWS*W/(64*NW) rows each).
-template <int W, bool BF, int NW>
-__device__ __forceinline__ float tile_colsum(const void* __restrict__ tile) {
-  constexpr int ROWS = 16 * NW, RS = Stg<BF, ROWS>::RS, NSEG = 64 * NW / W, LEN = ROWS / NSEG;
-  static_assert(NSEG >= 1 && LEN % 8 == 0, "segment layout");
-  using T = typename Stg<BF, ROWS>::T;
-  constexpr int PER = 16 / sizeof(T);  // values per 16-byte read (rows are 16-byte aligned)
-  const int f = threadIdx.x % W, sg = threadIdx.x / W;
-  const T* p = reinterpret_cast<const T*>(tile) + f * RS + sg * LEN;
-  float s = 0.f;
+// Column sums of a staged W-wide BF16 tile over its 16*NW rows, on MFMA:
+// with a B operand of ones, D[f][c] = sum over the rows of T[f][r] for every
+// column c.  Wave w covers feature block(s) fb and 32-row chunks:
+//   W/16 <= NW: fb = w % (W/16), chunks w / (W/16) + k * NW / (W/16);
+//   W/16 >  NW: fb = w + a * NW (a < W/16/NW), every chunk.
+// Lanes 0, 16, 32, 48 then hold features 16 fb + 4 (lane / 16) + v.
+template <int W, int NW>
+struct ColSum {
+  static constexpr int FBN = W / 16, CH = NW / 2;  // feature blocks, 32-row chunks
+  static constexpr int NA = FBN > NW ? FBN / NW : 1;
+  static constexpr int WPF = FBN >= NW ? 1 : NW / FBN;  // waves per feature block
+  static constexpr int CPW = CH / WPF;                  // chunks per wave
+  static_assert(CPW >= 1 && CH % WPF == 0 && (FBN <= NW || FBN % NW == 0), "column-sum layout");
+  v4f acc[NA];
+  __device__ __forceinline__ void zero() {
 #pragma unroll
-  for (int r = 0; r < LEN; r += PER) {
-    const uint4 q = *reinterpret_cast<const uint4*>(p + r);
-    const T* v = reinterpret_cast<const T*>(&q);
-#pragma unroll
-    for (int c = 0; c < PER; ++c) s += (float)v[c];
+    for (int q = 0; q < NA; ++q) acc[q] = v4f{0.f, 0.f, 0.f, 0.f};
   }
-  return s;
-}
+  __device__ __forceinline__ void add(const void* __restrict__ tile, int wave, int lane) {
+    constexpr int RS = Stg<true, 16 * NW>::RS;
+    const v8bf ones = __builtin_bit_cast(v8bf, uint4{0x3F803F80u, 0x3F803F80u, 0x3F803F80u, 0x3F803F80u});
+    const int li = lane & 15, kk = lane >> 4;
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      const int fb = FBN > NW ? wave + q * NW : wave % FBN;
+      const int c0 = FBN >= NW ? 0 : wave / FBN;
+      const __bf16* t = reinterpret_cast<const __bf16*>(tile) + (16 * fb + li) * RS + 8 * kk;
+#pragma unroll
+      for (int k = 0; k < CPW; ++k) {
+        const v8bf a = *reinterpret_cast<const v8bf*>(t + 32 * (c0 + k * WPF));
+        acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, ones, acc[q], 0, 0, 0);
+      }
+    }
+  }
+  // Sum the waves' partials in a fixed order and write the W sums to dst.
+  // `scratch` holds at least WPF * W floats of LDS; contains barriers.
+  __device__ __forceinline__ void store(float* __restrict__ scratch, float* __restrict__ dst, int wave,
+                                        int lane) const {
+    __syncthreads();
+    if ((lane & 15) == 0) {
+#pragma unroll
+      for (int q = 0; q < NA; ++q) {
+        const int fb = FBN > NW ? wave + q * NW : wave % FBN;
+        const int slot = FBN >= NW ? 0 : wave / FBN;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) scratch[slot * W + 16 * fb + 4 * (lane >> 4) + v] = acc[q][v];
+      }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < W) {
+      float sum = 0.f;
+      for (int sl = 0; sl < WPF; ++sl) sum += scratch[sl * W + threadIdx.x];
+      dst[threadIdx.x] = sum;
+    }
+    __syncthreads();
+  }
+};
+
+// The same column sums on the vector ALU (one float per thread instead of
+// MFMA accumulators, for kernels short of registers): thread t adds the
+// rows of segment t / W of feature t % W; store() adds the segments in order.
+template <int W, int NW>
+struct ColSumValu {
+  static constexpr int ROWS = 16 * NW, RS = Stg<true, ROWS>::RS, NSEG = 64 * NW / W, LEN = ROWS / NSEG;
+  static_assert(NSEG >= 1 && LEN % 8 == 0, "segment layout");
+  float acc;
+  __device__ __forceinline__ void zero() { acc = 0.f; }
+  __device__ __forceinline__ void add(const void* __restrict__ tile, int, int) {
+    const int f = threadIdx.x % W, sg = threadIdx.x / W;
+    const __bf16* p = reinterpret_cast<const __bf16*>(tile) + f * RS + sg * LEN;
+#pragma unroll
+    for (int r = 0; r < LEN; r += 8) {
+      const v8bf q = *reinterpret_cast<const v8bf*>(p + r);
+#pragma unroll
+      for (int c = 0; c < 8; ++c) acc += (float)q[c];
+    }
+  }
+  __device__ __forceinline__ void store(float* __restrict__ scratch, float* __restrict__ dst, int, int) const {
+    __syncthreads();
+    scratch[threadIdx.x] = acc;
+    __syncthreads();
+    if ((int)threadIdx.x < W) {
+      float sum = 0.f;
+      for (int sg = 0; sg < NSEG; ++sg) sum += scratch[sg * W + threadIdx.x];
+      dst[threadIdx.x] = sum;
+    }
+    __syncthreads();
+  }
+};
 
 // Write the owned tiles into a row-major [frows][kcols] block of the slab
 // (kcols <= AW and frows <= GW drop padded columns and rows).
@@ -149,22 +236,6 @@ __device__ __forceinline__ void block_sum_vec(const float (&v)[W / 4], float* __
   __syncthreads();
 }
 
-// Fixed-order sum over the workgroup of one value per thread held by the
-// threads (feature t % W, segment t / W) of a column-sum pass; writes W sums.
-template <int W, int NW>
-__device__ __forceinline__ void block_sum_segments(float v, float* __restrict__ scratch, float* __restrict__ dst) {
-  constexpr int NSEG = 64 * NW / W;
-  __syncthreads();
-  scratch[threadIdx.x] = v;
-  __syncthreads();
-  if ((int)threadIdx.x < W) {
-    float sum = 0.f;
-    for (int sg = 0; sg < NSEG; ++sg) sum += scratch[sg * W + threadIdx.x];
-    dst[threadIdx.x] = sum;
-  }
-  __syncthreads();
-}
-
 __device__ __forceinline__ void stage_frags(uint4* __restrict__ dst, const void* __restrict__ src, size_t bytes) {
   const uint4* s = reinterpret_cast<const uint4*>(src);
   for (size_t i = threadIdx.x; i < bytes / 16; i += blockDim.x) dst[i] = s[i];
@@ -188,7 +259,8 @@ struct EdgeBwdCfg {
   static constexpr size_t STAGE = NTILES * TB;
   static constexpr bool LDS_FRAG = 4 * FB + STAGE <= kLdsLimit;
   static constexpr size_t VECS = 2 * H * sizeof(float);  // b2 and the LayerNorm gain
-  static constexpr size_t LDS = STAGE + (LDS_FRAG ? 4 * FB : 0) + VECS;
+  static constexpr size_t CARRY = NW * H * sizeof(float);  // per-wave open-row sums between blocks
+  static constexpr size_t LDS = STAGE + (LDS_FRAG ? 4 * FB : 0) + CARRY + VECS;
 };
 
 // Per edge k (receiver i, sender j), with the forward recomputed:
@@ -219,6 +291,10 @@ __global__ __launch_bounds__((64 * EdgeBwdCfg<H, BF>::NW)) void k_edge_bwd(EdgeB
     fr = reinterpret_cast<const char*>(a.frag);
   }
   float* vecs = reinterpret_cast<float*>(reinterpret_cast<char*>(smem) + C::LDS - C::VECS);
+  // the open row's partial g_P sum, handed from lane 15 of one block to lane
+  // 0 of the next through LDS (same wave, so no barrier is needed)
+  float* carry = reinterpret_cast<float*>(reinterpret_cast<char*>(smem) + C::LDS - C::VECS - C::CARRY) +
+                 (threadIdx.x / 64) * H + (threadIdx.x / 16 % 4) * (H / 4);
   for (int t = threadIdx.x; t < 2 * H; t += blockDim.x) vecs[t] = t < H ? a.b2[t] : (a.ln ? a.lng[t - H] : 0.f);
   __syncthreads();
 
@@ -232,6 +308,10 @@ __global__ __launch_bounds__((64 * EdgeBwdCfg<H, BF>::NW)) void k_edge_bwd(EdgeB
   float db2[NV], dga[NV], dbe[NV];
 #pragma unroll
   for (int i = 0; i < NV; ++i) db2[i] = dga[i] = dbe[i] = 0.f;
+  ColSum<H, NW> cs_b2, cs_ga, cs_be;  // BF16: MFMA column sums of the staged tiles
+  cs_b2.zero();
+  cs_ga.zero();
+  cs_be.zero();
 
   // groups of NW consecutive tiles, one per wave, processed in lock step
   for (int64_t tg = ts.t0 + ts.rank * NW; tg < ts.t1; tg += ts.nr * NW) {
@@ -250,10 +330,7 @@ __global__ __launch_bounds__((64 * EdgeBwdCfg<H, BF>::NW)) void k_edge_bwd(EdgeB
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) nb = std::max(nb, __shfl_xor(nb, off));
     const int64_t n_iter = __builtin_amdgcn_readfirstlane(nb);  // the same in every lane and wave
-    float carry[NF];
-#pragma unroll
-    for (int i = 0; i < NF; ++i) carry[i] = 0.f;
-    int carry_key = 0;
+    int carry_key = 0;  // no open row at the start of a tile
 
     // Index loads run one block ahead, so each block waits on a single
     // round trip to memory (its rows), not on indices and then rows.
@@ -299,12 +376,12 @@ __global__ __launch_bounds__((64 * EdgeBwdCfg<H, BF>::NW)) void k_edge_bwd(EdgeB
         nx_n = (k2 + 1 < e1) ? gr.recv[k2 + 1] : -1;
       }
       float ev[NF], u[NF], t[NF], gE[NF], go[NF];
-      load_row_nt<H>(a.e_in + kk * H, g, ev);
+      load_row<H>(a.e_in + kk * H, g, ev);
       load_row<H>(a.P + (int64_t)ri * H, g, u);
       load_row<H>(a.Q + (int64_t)sj * H, g, t);
       load_row<H>(a.g_a + (int64_t)ri * H, g, gE);
       if (a.g_e_out) {
-        load_row_nt<H>(a.g_e_out + kk * H, g, go);
+        load_row<H>(a.g_e_out + kk * H, g, go);
       } else {
 #pragma unroll
         for (int i = 0; i < NF; ++i) go[i] = 0.f;
@@ -377,33 +454,41 @@ __global__ __launch_bounds__((64 * EdgeBwdCfg<H, BF>::NW)) void k_edge_bwd(EdgeB
       // g_e = gE + W1c^T gh
       gemm<BF, MB, MB>(fW1ct, t, gE, lane);
       if (valid) {
-        store_row_nt<H>(a.g_e_in + k * H, g, gE);
+        store_row<H>(a.g_e_in + k * H, g, gE);
         if constexpr (BF)
-          store_row_bf16_nt<H>(reinterpret_cast<__bf16*>(a.g_h) + k * H, g, t);
+          store_row_bf16<H>(reinterpret_cast<__bf16*>(a.g_h) + k * H, g, t);
         else
-          store_row_nt<H>(reinterpret_cast<float*>(a.g_h) + k * H, g, t);
+          store_row<H>(reinterpret_cast<float*>(a.g_h) + k * H, g, t);
       }
       // g_P: segmented sum of gh per receiver
 #pragma unroll
-      for (int i = 0; i < NF; ++i) {
-        float v = valid ? t[i] : 0.f;
-        if (j == 0 && key == carry_key) v += carry[i];
-        t[i] = v;
+      for (int i = 0; i < NF; ++i) t[i] = valid ? t[i] : 0.f;
+      if (j == 0 && key == carry_key) {
+#pragma unroll
+        for (int i = 0; i < NF; i += 4) {
+          const float4 c = *reinterpret_cast<const float4*>(carry + i);
+          t[i] += c.x;
+          t[i + 1] += c.y;
+          t[i + 2] += c.z;
+          t[i + 3] += c.w;
+        }
       }
       seg_scan16<NF>(t, key);
       if (last) store_row<H>(a.g_P + (int64_t)ri * H, g, t);
+      if (j == 15) {
 #pragma unroll
-      for (int i = 0; i < NF; ++i) carry[i] = from_prev_lane(t[i]);
+        for (int i = 0; i < NF; i += 4) *reinterpret_cast<float4*>(carry + i) = make_float4(t[i], t[i + 1], t[i + 2], t[i + 3]);
+      }
       carry_key = from_prev_lane_i(key);
 
       __syncthreads();
       dw_tiles<H, H, BF, NW>(tG2, tA2, acc2, wave, lane);
       dw_tiles<H, H, BF, NW>(tG1, tA1, acc1, wave, lane);
       if constexpr (C::VEC) {
-        db2[0] += tile_colsum<H, BF, NW>(tG2);
+        cs_b2.add(tG2, wave, lane);
         if (a.ln) {
-          dbe[0] += tile_colsum<H, BF, NW>(tGE);
-          dga[0] += tile_colsum<H, BF, NW>(tGM);
+          cs_be.add(tGE, wave, lane);
+          cs_ga.add(tGM, wave, lane);
         }
       }
       __syncthreads();
@@ -420,19 +505,9 @@ __global__ __launch_bounds__((64 * EdgeBwdCfg<H, BF>::NW)) void k_edge_bwd(EdgeB
   dw_store<H, H, NW>(acc2, slab + H * H, H, wave, lane);
   float* scratch = reinterpret_cast<float*>(tG2);
   if constexpr (C::VEC) {
-    // thread (feature f, segment s) partial sums; add segments in order
-    constexpr int NSEG = 64 * NW / H;
-    float* v3[3] = {db2, dga, dbe};
-    for (int q = 0; q < 3; ++q) {
-      __syncthreads();
-      scratch[threadIdx.x] = v3[q][0];
-      __syncthreads();
-      if ((int)threadIdx.x < H) {
-        float sum = 0.f;
-        for (int sg = 0; sg < NSEG; ++sg) sum += scratch[sg * H + threadIdx.x];
-        slab[2 * H * H + q * H + threadIdx.x] = sum;
-      }
-    }
+    cs_b2.store(scratch, slab + 2 * H * H, wave, lane);
+    cs_ga.store(scratch, slab + 2 * H * H + H, wave, lane);
+    cs_be.store(scratch, slab + 2 * H * H + 2 * H, wave, lane);
   } else {
     block_sum_vec<H>(db2, scratch, slab + 2 * H * H, wave, lane);
     block_sum_vec<H>(dga, scratch, slab + 2 * H * H + H, wave, lane);
@@ -642,10 +717,17 @@ struct MlpBwdCfg {
   // fragments: W0, W1, W1^T, W0^T
   static constexpr size_t FRAG = 2 * F0 + 2 * F1;
   static constexpr size_t TB = tile_bytes<H, BF, ROWS>();
-  static constexpr size_t STAGE0 = TB + tile_bytes<AW0, BF, ROWS>();
-  // phase 1: [g_y, u (, g_out, g_out * normalised y)]; small output: [g_out (16 wide), u]
+  // phase 1: [g_y, u (, g_out, g_out * normalised y)]; small output: [g_out (16 wide), u];
+  // phase 0 reuses the first tile for g_z.  The input tile has its own
+  // region, staged as soon as the block's input has been used.
   static constexpr size_t STAGE1 = (VEC ? 4 : 2) * TB;
-  static constexpr size_t STAGE = STAGE0 > STAGE1 ? STAGE0 : STAGE1;
+  static constexpr size_t TA0 = tile_bytes<AW0, BF, ROWS>();
+  static constexpr size_t SMALL_ = (TIN || TOUT) ? 16 * H : 0;
+  // a separate input tile when everything (with the fragments) still fits;
+  // otherwise phase 0 stages the input into the second phase-1 tile
+  static constexpr bool SEP_A0 = STAGE1 + TA0 + 2 * F0 + 2 * F1 + SMALL_ + 3 * H * sizeof(float) <= kLdsLimit;
+  static constexpr size_t STAGE0 = TB + TA0;
+  static constexpr size_t STAGE = SEP_A0 ? STAGE1 + TA0 : (STAGE0 > STAGE1 ? STAGE0 : STAGE1);
   static constexpr size_t SMALL = (TIN || TOUT) ? 16 * H : 0;  // small W0 / W1, [.][4] or [4][H]
   static constexpr size_t VECS = 3 * H * sizeof(float);         // b0, b1, LayerNorm gain
   static constexpr bool LDS_FRAG = FRAG + STAGE + SMALL + VECS <= kLdsLimit;
@@ -705,6 +787,7 @@ template <int H, int KIN, bool TIN, bool TOUT, bool BF>
 __global__ __launch_bounds__((64 * MlpBwdCfg<H, KIN, TIN, TOUT, BF>::NW)) void k_mlp_bwd(MlpBwdArgs a) {
   using C = MlpBwdCfg<H, KIN, TIN, TOUT, BF>;
   using In = MlpBwdIn<H, KIN, TIN, TOUT>;
+  constexpr bool PK = KIN != 2 * H;  // packed BF16 staging, except where registers are short
   constexpr int NF = H / 4, MB = H / 16, KB = TIN ? 1 : KIN / 16, AW0 = C::AW0, NW = C::NW, ROWS = C::ROWS;
   constexpr int NT1 = TOUT ? dw_tiles_per_wave<16, H, NW>() : dw_tiles_per_wave<H, H, NW>();
   constexpr int NT0 = dw_tiles_per_wave<H, AW0, NW>();
@@ -713,6 +796,7 @@ __global__ __launch_bounds__((64 * MlpBwdCfg<H, KIN, TIN, TOUT, BF>::NW)) void k
   char* tA = tG + C::TB;
   char* tGE = tA + C::TB;  // phase 1, VEC: g_out and g_out * normalised y
   char* tGM = tGE + C::TB;
+  char* tA0 = C::SEP_A0 ? tG + C::STAGE1 : tA;  // phase 0: the input rows
   const char* fr;
   if constexpr (C::LDS_FRAG) {
     uint4* fl = smem + C::STAGE / 16;
@@ -753,6 +837,14 @@ __global__ __launch_bounds__((64 * MlpBwdCfg<H, KIN, TIN, TOUT, BF>::NW)) void k
   float db0[NV], db1[NV], dga[NV], dbe[NV];
 #pragma unroll
   for (int i = 0; i < NV; ++i) db0[i] = db1[i] = dga[i] = dbe[i] = 0.f;
+  // BF16: column sums of the staged tiles (MFMA, or the vector ALU for the
+  // node update, whose registers are fully used)
+  using CS = typename std::conditional<KIN == 2 * H, ColSumValu<H, NW>, ColSum<H, NW>>::type;
+  CS cs_b0, cs_b1, cs_ga, cs_be;
+  cs_b0.zero();
+  cs_b1.zero();
+  cs_ga.zero();
+  cs_be.zero();
   float db1s[4] = {0.f, 0.f, 0.f, 0.f};  // small-output db1 (lane group 0)
 
   // one-block-ahead loads where registers allow (H <= 64)
@@ -795,6 +887,18 @@ __global__ __launch_bounds__((64 * MlpBwdCfg<H, KIN, TIN, TOUT, BF>::NW)) void k
     } else {
       gemm<BF, MB, KB>(f0, cur.in, z, lane);
     }
+    // the input tile for dW0: staged now when it has its own region
+    auto stage_in = [&]() {
+      if constexpr (TIN) {
+        float in16[4];  // lane group g holds input features 4g..4g+3
+#pragma unroll
+        for (int k = 0; k < 4; ++k) in16[k] = g == 0 ? cur.in[k] : 0.f;
+        stage_row<16, BF, ROWS, PK>(tA0, srow, g, in16);
+      } else {
+        stage_row<KIN, BF, ROWS, PK>(tA0, srow, g, cur.in);
+      }
+    };
+    if constexpr (C::SEP_A0) stage_in();
     float u[NF];
 #pragma unroll
     for (int i = 0; i < NF; ++i) u[i] = elu(z[i]);
@@ -819,8 +923,8 @@ __global__ __launch_bounds__((64 * MlpBwdCfg<H, KIN, TIN, TOUT, BF>::NW)) void k
       float go16[4];
 #pragma unroll
       for (int o = 0; o < 4; ++o) go16[o] = g == 0 ? cur.go[o] : 0.f;
-      stage_row<16, BF, ROWS>(tG, srow, g, go16);
-      stage_row<H, BF, ROWS>(tA, srow, g, u);
+      stage_row<16, BF, ROWS, PK>(tG, srow, g, go16);
+      stage_row<H, BF, ROWS, PK>(tA, srow, g, u);
       __syncthreads();
       dw_tiles<16, H, BF, NW>(tG, tA, acc1, wave, lane);
       __syncthreads();
@@ -849,8 +953,8 @@ __global__ __launch_bounds__((64 * MlpBwdCfg<H, KIN, TIN, TOUT, BF>::NW)) void k
           float t[NF];
 #pragma unroll
           for (int i = 0; i < NF; ++i) t[i] = go[i] * y[i];
-          stage_row<H, BF, ROWS>(tGE, srow, g, cur.go);
-          stage_row<H, BF, ROWS>(tGM, srow, g, t);
+          stage_row<H, BF, ROWS, PK>(tGE, srow, g, cur.go);
+          stage_row<H, BF, ROWS, PK>(tGM, srow, g, t);
         }
         s1 = row_sum(s1) * (1.f / H);
         s2 = row_sum(s2) * (1.f / H);
@@ -864,15 +968,15 @@ __global__ __launch_bounds__((64 * MlpBwdCfg<H, KIN, TIN, TOUT, BF>::NW)) void k
 #pragma unroll
         for (int i = 0; i < NF; ++i) db1[i] += y[i];
       }
-      stage_row<H, BF, ROWS>(tG, srow, g, y);
-      stage_row<H, BF, ROWS>(tA, srow, g, u);
+      stage_row<H, BF, ROWS, PK>(tG, srow, g, y);
+      stage_row<H, BF, ROWS, PK>(tA, srow, g, u);
       __syncthreads();
       dw_tiles<H, H, BF, NW>(tG, tA, acc1, wave, lane);
       if constexpr (C::VEC) {
-        db1[0] += tile_colsum<H, BF, NW>(tG);
+        cs_b1.add(tG, wave, lane);
         if (a.ln) {
-          dbe[0] += tile_colsum<H, BF, NW>(tGE);
-          dga[0] += tile_colsum<H, BF, NW>(tGM);
+          cs_be.add(tGE, wave, lane);
+          cs_ga.add(tGM, wave, lane);
         }
       }
       __syncthreads();
@@ -887,18 +991,11 @@ __global__ __launch_bounds__((64 * MlpBwdCfg<H, KIN, TIN, TOUT, BF>::NW)) void k
 #pragma unroll
       for (int i = 0; i < NF; ++i) db0[i] += gu[i];
     }
-    stage_row<H, BF, ROWS>(tG, srow, g, gu);
-    if constexpr (TIN) {
-      float in16[4];  // lane group g holds input features 4g..4g+3
-#pragma unroll
-      for (int k = 0; k < 4; ++k) in16[k] = g == 0 ? cur.in[k] : 0.f;
-      stage_row<16, BF, ROWS>(tA, srow, g, in16);
-    } else {
-      stage_row<KIN, BF, ROWS>(tA, srow, g, cur.in);
-    }
+    stage_row<H, BF, ROWS, PK>(tG, srow, g, gu);
+    if constexpr (!C::SEP_A0) stage_in();
     __syncthreads();
-    dw_tiles<H, AW0, BF, NW>(tG, tA, acc0, wave, lane);
-    if constexpr (C::VEC) db0[0] += tile_colsum<H, BF, NW>(tG);
+    dw_tiles<H, AW0, BF, NW>(tG, tA0, acc0, wave, lane);
+    if constexpr (C::VEC) cs_b0.add(tG, wave, lane);
     __syncthreads();
     // ---- input gradient
     if constexpr (!TIN) {
@@ -939,7 +1036,7 @@ __global__ __launch_bounds__((64 * MlpBwdCfg<H, KIN, TIN, TOUT, BF>::NW)) void k
   dw_store<H, AW0, NW>(acc0, slab, k0w, wave, lane);
   float* scratch = reinterpret_cast<float*>(tG);
   if constexpr (C::VEC)
-    block_sum_segments<H, NW>(db0[0], scratch, slab + H * k0w);
+    cs_b0.store(scratch, slab + H * k0w, wave, lane);
   else
     block_sum_vec<H, NW>(db0, scratch, slab + H * k0w, wave, lane);
   float* s1 = slab + H * k0w + H;
@@ -959,10 +1056,10 @@ __global__ __launch_bounds__((64 * MlpBwdCfg<H, KIN, TIN, TOUT, BF>::NW)) void k
   } else {
     dw_store<H, H, NW>(acc1, s1, H, wave, lane);
     if constexpr (C::VEC) {
-      block_sum_segments<H, NW>(db1[0], scratch, s1 + H * H);
+      cs_b1.store(scratch, s1 + H * H, wave, lane);
       if (a.ln) {
-        block_sum_segments<H, NW>(dga[0], scratch, s1 + H * H + H);
-        block_sum_segments<H, NW>(dbe[0], scratch, s1 + H * H + 2 * H);
+        cs_ga.store(scratch, s1 + H * H + H, wave, lane);
+        cs_be.store(scratch, s1 + H * H + 2 * H, wave, lane);
       }
     } else {
       block_sum_vec<H, NW>(db1, scratch, s1 + H * H, wave, lane);

@@ -33,6 +33,11 @@ __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 // ------------------------------------------------------------------ loads
 
 // Load the row-block slice of a W-wide row (ptr = start of the row).
+// Lane (j, g) moves features 16b + 4g .. +3, so one instruction covers half
+// of each 128-byte line of a row.  All row traffic uses ordinary cached
+// loads and stores: L2 then merges the two halves of a line (non-temporal
+// stores wrote about 40% more bytes than the arrays hold, and non-temporal
+// loads measured slower as well).
 template <int W>
 __device__ __forceinline__ void load_row(const float* __restrict__ ptr, int g, float (&v)[W / 4]) {
 #pragma unroll
@@ -56,12 +61,13 @@ __device__ __forceinline__ void store_row(float* __restrict__ ptr, int g, const 
 // BF16 storage of a row (round to nearest even) and its FP32 read-back.
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 v4bf __attribute__((ext_vector_type(4)));
+typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
 template <int W>
-__device__ __forceinline__ void store_row_bf16_nt(__bf16* __restrict__ ptr, int g, const float (&v)[W / 4]) {
+__device__ __forceinline__ void store_row_bf16(__bf16* __restrict__ ptr, int g, const float (&v)[W / 4]) {
 #pragma unroll
   for (int b = 0; b < W / 16; ++b) {
     const v4bf t = {(__bf16)v[4 * b], (__bf16)v[4 * b + 1], (__bf16)v[4 * b + 2], (__bf16)v[4 * b + 3]};
-    __builtin_nontemporal_store(__builtin_bit_cast(u32x2, t), reinterpret_cast<u32x2*>(ptr + 16 * b + 4 * g));
+    *reinterpret_cast<u32x2*>(ptr + 16 * b + 4 * g) = __builtin_bit_cast(u32x2, t);
   }
 }
 template <int W>
@@ -74,28 +80,6 @@ __device__ __forceinline__ void load_row_bf16(const __bf16* __restrict__ ptr, in
     v[4 * b + 2] = (float)t[2];
     v[4 * b + 3] = (float)t[3];
   }
-}
-
-// Streaming variants for arrays touched exactly once per kernel (edge
-// states and their gradients): non-temporal hints keep them from evicting
-// the gathered node rows from L2.
-template <int W>
-__device__ __forceinline__ void load_row_nt(const float* __restrict__ ptr, int g, float (&v)[W / 4]) {
-#pragma unroll
-  for (int b = 0; b < W / 16; ++b) {
-    const v4f t = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(ptr + 16 * b + 4 * g));
-    v[4 * b + 0] = t[0];
-    v[4 * b + 1] = t[1];
-    v[4 * b + 2] = t[2];
-    v[4 * b + 3] = t[3];
-  }
-}
-template <int W>
-__device__ __forceinline__ void store_row_nt(float* __restrict__ ptr, int g, const float (&v)[W / 4]) {
-#pragma unroll
-  for (int b = 0; b < W / 16; ++b)
-    __builtin_nontemporal_store(v4f{v[4 * b + 0], v[4 * b + 1], v[4 * b + 2], v[4 * b + 3]},
-                                reinterpret_cast<v4f*>(ptr + 16 * b + 4 * g));
 }
 
 // Per-feature vector (bias, LayerNorm gain) in row-block layout.
@@ -193,11 +177,14 @@ __device__ __forceinline__ int opaque_zero() {
 __device__ __forceinline__ float elu(float z) { return z > 0.f ? z : __expf(z) - 1.f; }
 __device__ __forceinline__ float elu_deriv(float z) { return z > 0.f ? 1.f : __expf(z); }
 
-// Sum over the four lanes that share a row (lane groups g = 0..3).
+// Sum over the four lanes that share a row (lane groups g = 0..3), on the
+// matrix unit: v_mfma_f32_16x16x4f32 with A = 1 and B[k][j] = the value of
+// lane j + 16k gives D[i][j] = sum over k for every i, and lane j + 16g
+// receives D[4g..4g+3][j].  One FP32 MFMA instead of two dependent LDS
+// permutes; must be called with all lanes active.
 __device__ __forceinline__ float row_sum(float s) {
-  s += __shfl_xor(s, 16);
-  s += __shfl_xor(s, 32);
-  return s;
+  const v4f d = __builtin_amdgcn_mfma_f32_16x16x4f32(1.f, s, v4f{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+  return d[0];
 }
 
 // LayerNorm statistics (biased variance) of a W-wide row in row-block layout.

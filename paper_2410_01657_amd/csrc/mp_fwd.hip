@@ -169,7 +169,7 @@ hipError_t launch_tiles(const DevGraph& g, int32_t* tile_r, int32_t* tile_e, hip
 // carried into the next block.  Every row's sum is written once by the lane
 // holding its last edge; no atomics, so results are bitwise reproducible.
 template <int H, bool BF>
-__global__ __launch_bounds__(256) void k_edge_fwd(DevGraph gr, const float* __restrict__ P,
+__global__ __launch_bounds__(256, (H <= 64 ? 4 : 2)) void k_edge_fwd(DevGraph gr, const float* __restrict__ P,
                                                   const float* __restrict__ Q, const float* __restrict__ e_in,
                                                   const void* __restrict__ frag, const float* __restrict__ b2,
                                                   const float* __restrict__ lng, const float* __restrict__ lnb,
@@ -183,6 +183,9 @@ __global__ __launch_bounds__(256) void k_edge_fwd(DevGraph gr, const float* __re
   // per-feature vectors (b2, LayerNorm gain and shift) live in LDS after the
   // fragments and are re-read per block rather than held in registers
   float* vecs = reinterpret_cast<float*>(reinterpret_cast<char*>(smem) + (LDS ? 2 * FB : 0));
+  // the open row's partial sum, handed from lane 15 of one block to lane 0
+  // of the next through LDS (same wave, so no barrier is needed)
+  float* carry = vecs + 3 * H + (threadIdx.x / 64) * H + (threadIdx.x / 16 % 4) * (H / 4);
   for (int t = threadIdx.x; t < 3 * H; t += blockDim.x)
     vecs[t] = t < H ? b2[t] : (ln ? (t < 2 * H ? lng[t - H] : lnb[t - 2 * H]) : 0.f);
   if constexpr (LDS) {
@@ -199,10 +202,7 @@ __global__ __launch_bounds__(256) void k_edge_fwd(DevGraph gr, const float* __re
   for (int64_t tile = ts.t0 + ts.rank * nw + threadIdx.x / 64; tile < ts.t1; tile += ts.nr * nw) {
     const int64_t r0 = gr.tile_r[tile], r1 = gr.tile_r[tile + 1];
     const int64_t e0 = gr.tile_e[tile], e1 = gr.tile_e[tile + 1];
-    float carry[NF];
-#pragma unroll
-    for (int i = 0; i < NF; ++i) carry[i] = 0.f;
-    int carry_key = 0;
+    int carry_key = 0;  // no open row at the start of a tile
 
     // Index loads run one block ahead (issued before the block's row
     // loads), so each block waits on one round trip to memory, for its rows.
@@ -240,7 +240,7 @@ __global__ __launch_bounds__(256) void k_edge_fwd(DevGraph gr, const float* __re
       }
 
       float ev[NF], h[NF], q[NF];
-      load_row_nt<H>(e_in + kk * H, g, ev);
+      load_row<H>(e_in + kk * H, g, ev);
       load_row<H>(P + (int64_t)ri * H, g, h);
       load_row<H>(Q + (int64_t)sj * H, g, q);
       __builtin_amdgcn_sched_barrier(0);  // all row loads issue before any use
@@ -263,19 +263,27 @@ __global__ __launch_bounds__(256) void k_edge_fwd(DevGraph gr, const float* __re
       }
 #pragma unroll
       for (int i = 0; i < NF; ++i) ev[i] += m[i];
-      if (valid) store_row_nt<H>(e_out + k * H, g, ev);
+      if (valid) store_row<H>(e_out + k * H, g, ev);
 
       // aggregation: segmented scan of e'/d across the block, plus carry
 #pragma unroll
-      for (int i = 0; i < NF; ++i) {
-        float v = valid ? ev[i] * inv_d : 0.f;
-        if (j == 0 && key == carry_key) v += carry[i];
-        ev[i] = v;
+      for (int i = 0; i < NF; ++i) ev[i] = valid ? ev[i] * inv_d : 0.f;
+      if (j == 0 && key == carry_key) {
+#pragma unroll
+        for (int i = 0; i < NF; i += 4) {
+          const float4 c = *reinterpret_cast<const float4*>(carry + i);
+          ev[i] += c.x;
+          ev[i + 1] += c.y;
+          ev[i + 2] += c.z;
+          ev[i + 3] += c.w;
+        }
       }
       seg_scan16<NF>(ev, key);
       if (last) store_row<H>(a_out + (int64_t)ri * H, g, ev);
+      if (j == 15) {
 #pragma unroll
-      for (int i = 0; i < NF; ++i) carry[i] = from_prev_lane(ev[i]);
+        for (int i = 0; i < NF; i += 4) *reinterpret_cast<float4*>(carry + i) = make_float4(ev[i], ev[i + 1], ev[i + 2], ev[i + 3]);
+      }
       carry_key = from_prev_lane_i(key);
     }
     // rows without incoming edges aggregate to zero
@@ -293,7 +301,8 @@ static hipError_t launch_edge_fwd_t(const DevGraph& g, const float* P, const flo
                                     const void* frag, const float* b2, const float* lng, const float* lnb, int ln,
                                     float eps, float* e_out, float* a_out, int grid, hipStream_t s) {
   constexpr size_t FB = frag_bytes(H, H, BF);
-  const size_t lds = ((2 * FB <= kEdgeLdsBudget) ? 2 * FB : 0) + 3 * H * sizeof(float);
+  // fragments, 3 per-feature vectors, per-wave carries (4 waves)
+  const size_t lds = ((2 * FB <= kEdgeLdsBudget) ? 2 * FB : 0) + 3 * H * sizeof(float) + 4 * H * sizeof(float);
   if (lds > 64 * 1024)
     (void)hipFuncSetAttribute((const void*)k_edge_fwd<H, BF>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   hipLaunchKernelGGL((k_edge_fwd<H, BF>), dim3(grid), dim3(256), lds, s, g, P, Q, e_in, frag, b2, lng, lnb, ln,
@@ -409,7 +418,7 @@ struct MlpFwdCfg {
 };
 
 template <int H, int KIN, bool TIN, bool TOUT, bool BF>
-__global__ __launch_bounds__(256) void k_mlp_fwd(MlpFwdArgs a) {
+__global__ __launch_bounds__(256, (H <= 64 ? 4 : 1)) void k_mlp_fwd(MlpFwdArgs a) {
   using C = MlpFwdCfg<H, KIN, TIN, TOUT, BF>;
   constexpr int NF = H / 4, MB = H / 16, KB = TIN ? 1 : KIN / 16;
   extern __shared__ uint4 smem[];

@@ -25,9 +25,16 @@ class Work:
     flops: float
 
 
-def layer_kernels(N, E, G, M, H):
-    """Per launch, for one layer; keys match the library's profile names."""
-    f = 4.0  # bytes per FP32 value
+def layer_kernels(N, E, G, M, H, gemm="bf16", n_layers=1):
+    """Per launch, for one layer; keys match the library's profile names.
+
+    gemm: "bf16" stores the edge-state adjoint g_h in BF16 (2 bytes per
+    value), "f32" in FP32.  n_layers: the adjoint kernels are averaged over
+    the layers of a model, whose last layer gets no gradient at its edge
+    output (g_e' is absent there)."""
+    f = 4.0                              # bytes per FP32 value
+    fh = 2.0 if gemm == "bf16" else 4.0  # bytes per g_h value
+    ge = (n_layers - 1) / n_layers if n_layers > 1 else 1.0  # launches that read g_e'
     return {
         # x -> P = W1a x + b1, Q = W1b x
         "proj": Work(N * 3 * H * f, N * 2 * 2 * H * H),
@@ -39,10 +46,10 @@ def layer_kernels(N, E, G, M, H):
         "node_fwd": Work(N * 3 * H * f, N * 2 * 3 * H * H),
         # a*, x, g_x' -> g_a*, g_x ; recompute (3H^2) + input grads (3H^2) + weight grads (3H^2)
         "node_bwd": Work(N * 5 * H * f, N * 2 * 9 * H * H),
-        # e, g_e', P_i, Q_j, g_a_i -> g_e, g_h, g_P ; 6 H x H products per edge
-        "edge_bwd": Work(E * (4 * H * f + 9) + N * 4 * H * f, E * 2 * 6 * H * H),
+        # e, [g_e'], P_i, Q_j, g_a_i -> g_e, g_h, g_P ; 6 H x H products per edge
+        "edge_bwd": Work(E * ((2 + ge) * H * f + H * fh + 9) + N * 4 * H * f, E * 2 * 6 * H * H),
         # g_P, g_h (through reverse edges), x, g_x -> g_x ; 2 (2H x H) products per node
-        "gq": Work(E * (H * f + 4) + N * (4 * H * f + 4), N * 2 * 4 * H * H),
+        "gq": Work(E * (H * fh + 4) + N * (4 * H * f + 4), N * 2 * 4 * H * H),
     }
 
 
