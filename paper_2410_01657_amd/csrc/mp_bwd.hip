@@ -531,6 +531,369 @@ hipError_t launch_edge_bwd(const EdgeBwdArgs& a, int grid, hipStream_t s) {
   return hipErrorInvalidValue;
 }
 
+// ------------------------------------------- split edge adjoint (wide H)
+
+// Stores of a row-block vector as FP32 or BF16.
+template <int H, bool BF>
+__device__ __forceinline__ void store_row_t(void* __restrict__ base, int64_t row, int g, const float (&v)[H / 4]) {
+  if constexpr (BF)
+    store_row_bf16<H>(reinterpret_cast<__bf16*>(base) + row * H, g, v);
+  else
+    store_row<H>(reinterpret_cast<float*>(base) + row * H, g, v);
+}
+template <int H, bool BF>
+__device__ __forceinline__ void load_row_t(const void* __restrict__ base, int64_t row, int g, float (&v)[H / 4]) {
+  if constexpr (BF)
+    load_row_bf16<H>(reinterpret_cast<const __bf16*>(base) + row * H, g, v);
+  else
+    load_row<H>(reinterpret_cast<const float*>(base) + row * H, g, v);
+}
+
+template <int H, bool BF>
+struct EdgeBwdSplitCfg {
+  static constexpr int NW = 8;  // independent waves sharing the LDS weight fragments
+  static constexpr size_t FB = frag_bytes(H, H, BF);
+  static constexpr size_t VECS = 2 * H * sizeof(float);
+  static constexpr size_t CARRY = NW * H * sizeof(float);
+  static constexpr bool LDS_FRAG = 4 * FB + VECS + CARRY <= kLdsLimit;
+  static constexpr size_t LDS = (LDS_FRAG ? 4 * FB : 0) + CARRY + VECS;
+};
+
+// The edge adjoint without its weight gradients, for widths where the
+// fused kernel's staging tiles and accumulators do not fit next to the
+// weights.  Per edge it computes what k_edge_bwd computes (g_e, g_h, the
+// segmented g_P) and writes the factors of the weight gradients instead of
+// accumulating them: gm and u (dW2 = sum gm u^T, db2 = sum gm), gE and
+// gE * normalised m (dbeta, dgamma); dW1c = sum g_h e^T is formed from g_h
+// and e.  Waves walk their tiles independently (no barriers in the loop).
+template <int H, bool BF>
+__global__ __launch_bounds__((64 * EdgeBwdSplitCfg<H, BF>::NW)) void k_edge_bwd_split(EdgeBwdArgs a) {
+  using C = EdgeBwdSplitCfg<H, BF>;
+  constexpr int NF = H / 4, MB = H / 16, NW = C::NW;
+  extern __shared__ uint4 smem[];
+  const char* fr;
+  if constexpr (C::LDS_FRAG) {
+    stage_frags(smem, a.frag, 4 * C::FB);
+    fr = reinterpret_cast<const char*>(smem);
+  } else {
+    fr = reinterpret_cast<const char*>(a.frag);
+  }
+  float* vecs = reinterpret_cast<float*>(reinterpret_cast<char*>(smem) + C::LDS - C::VECS);
+  float* carry = reinterpret_cast<float*>(reinterpret_cast<char*>(smem) + C::LDS - C::VECS - C::CARRY) +
+                 (threadIdx.x / 64) * H + (threadIdx.x / 16 % 4) * (H / 4);
+  for (int t = threadIdx.x; t < 2 * H; t += blockDim.x) vecs[t] = t < H ? a.b2[t] : (a.ln ? a.lng[t - H] : 0.f);
+  __syncthreads();
+
+  const DevGraph& gr = a.g;
+  const int lane = lane_id(), j = lane & 15, g = lane >> 4, wave = threadIdx.x / 64;
+  const TileSched ts = tile_sched(gr.n_tiles);
+  for (int64_t tile = ts.t0 + ts.rank * NW + wave; tile < ts.t1; tile += ts.nr * NW) {
+    const int64_t r0 = gr.tile_r[tile], r1 = gr.tile_r[tile + 1];
+    const int64_t e0 = gr.tile_e[tile], e1 = gr.tile_e[tile + 1];
+    int carry_key = 0;  // no open row at the start of a tile
+    const int64_t e_last = e1 > e0 ? e1 - 1 : 0;
+    int ri_n, sj_n, md_n, nx_n;  // next block's indices, one block ahead
+    {
+      const int64_t k = e0 + j, kk = k < e1 ? k : e_last;
+      ri_n = gr.recv[kk];
+      sj_n = gr.col[kk];
+      md_n = gr.mult[kk];
+      nx_n = (k + 1 < e1) ? gr.recv[k + 1] : -1;
+      asm volatile("" : "+v"(ri_n), "+v"(sj_n), "+v"(md_n), "+v"(nx_n));
+    }
+    for (int64_t base = e0; base < e1; base += 16) {
+      const char* frb = fr + opaque_zero();
+      const char* fW1c = frb;
+      const char* fW2 = frb + C::FB;
+      const char* fW2t = frb + 2 * C::FB;
+      const char* fW1ct = frb + 3 * C::FB;
+      const int64_t k = base + j;
+      const bool valid = k < e1;
+      const int64_t kk = valid ? k : e_last;
+      const int ri = ri_n, sj = sj_n;
+      const float inv_d = 1.f / (float)md_n;
+      const bool last = valid && nx_n != ri;
+      const int key = valid ? ri + 1 : -1;
+      {
+        const int64_t k2 = k + 16, kk2 = k2 < e1 ? k2 : e_last;
+        ri_n = gr.recv[kk2];
+        sj_n = gr.col[kk2];
+        md_n = gr.mult[kk2];
+        nx_n = (k2 + 1 < e1) ? gr.recv[k2 + 1] : -1;
+      }
+      float ev[NF], u[NF], t[NF], gE[NF];
+      load_row<H>(a.e_in + kk * H, g, ev);
+      load_row<H>(a.P + (int64_t)ri * H, g, u);
+      load_row<H>(a.Q + (int64_t)sj * H, g, t);
+      load_row<H>(a.g_a + (int64_t)ri * H, g, gE);
+      __builtin_amdgcn_sched_barrier(0);
+      // recompute the forward
+#pragma unroll
+      for (int i = 0; i < NF; ++i) u[i] += t[i];
+      gemm<BF, MB, MB>(fW1c, ev, u, lane);
+#pragma unroll
+      for (int i = 0; i < NF; ++i) u[i] = elu(u[i]);
+      if (valid) store_row_t<H, BF>(a.u, k, g, u);
+      float mp[NF];
+      const float* vb = vecs + opaque_zero();
+      load_vec<H>(vb, g, mp);
+      gemm<BF, MB, MB>(fW2, u, mp, lane);
+      // gradient reaching e'
+      if (a.g_e_out) {
+        load_row<H>(a.g_e_out + kk * H, g, t);
+#pragma unroll
+        for (int i = 0; i < NF; ++i) gE[i] = gE[i] * inv_d + t[i];
+      } else {
+#pragma unroll
+        for (int i = 0; i < NF; ++i) gE[i] *= inv_d;
+      }
+#pragma unroll
+      for (int i = 0; i < NF; ++i) gE[i] = valid ? gE[i] : 0.f;
+      if (a.ln) {
+        float mean, rstd, gam[NF];
+        ln_stats<H>(mp, a.eps, mean, rstd);
+        load_vec<H>(vb + H, g, gam);
+        float s1 = 0.f, s2 = 0.f;
+#pragma unroll
+        for (int i = 0; i < NF; ++i) {
+          const float xh = (mp[i] - mean) * rstd;
+          t[i] = gE[i] * xh;
+          const float gx = gE[i] * gam[i];
+          s1 += gx;
+          s2 += gx * xh;
+          mp[i] = xh;
+        }
+        if (valid) {
+          store_row_t<H, BF>(a.gE, k, g, gE);
+          store_row_t<H, BF>(a.gEx, k, g, t);
+        }
+        s1 = row_sum(s1) * (1.f / H);
+        s2 = row_sum(s2) * (1.f / H);
+#pragma unroll
+        for (int i = 0; i < NF; ++i) mp[i] = rstd * (gE[i] * gam[i] - s1 - mp[i] * s2);
+      } else {
+#pragma unroll
+        for (int i = 0; i < NF; ++i) mp[i] = gE[i];
+        if (valid) store_row_t<H, BF>(a.gE, k, g, gE);
+      }
+      if (valid) store_row_t<H, BF>(a.gm, k, g, mp);
+      // gh = (W2^T gm) * ELU'(h); ELU'(h) = 1 for h > 0 else exp(h) = u + 1
+#pragma unroll
+      for (int i = 0; i < NF; ++i) t[i] = 0.f;
+      gemm<BF, MB, MB>(fW2t, mp, t, lane);
+#pragma unroll
+      for (int i = 0; i < NF; ++i) t[i] *= (u[i] > 0.f ? 1.f : u[i] + 1.f);
+      // g_e = gE + W1c^T gh
+      gemm<BF, MB, MB>(fW1ct, t, gE, lane);
+      if (valid) {
+        store_row<H>(a.g_e_in + k * H, g, gE);
+        store_row_t<H, BF>(a.g_h, k, g, t);
+      }
+      // g_P: segmented sum of gh per receiver (carry through LDS)
+#pragma unroll
+      for (int i = 0; i < NF; ++i) t[i] = valid ? t[i] : 0.f;
+      if (j == 0 && key == carry_key) {
+#pragma unroll
+        for (int i = 0; i < NF; i += 4) {
+          const float4 c = *reinterpret_cast<const float4*>(carry + i);
+          t[i] += c.x;
+          t[i + 1] += c.y;
+          t[i + 2] += c.z;
+          t[i + 3] += c.w;
+        }
+      }
+      seg_scan16<NF>(t, key);
+      if (last) store_row<H>(a.g_P + (int64_t)ri * H, g, t);
+      if (j == 15) {
+#pragma unroll
+        for (int i = 0; i < NF; i += 4) *reinterpret_cast<float4*>(carry + i) = make_float4(t[i], t[i + 1], t[i + 2], t[i + 3]);
+      }
+      carry_key = from_prev_lane_i(key);
+    }
+    for (int64_t r = r0 + (lane >> 2); r < r1; r += 16) {
+      if (gr.rowptr[r] == gr.rowptr[r + 1]) {
+        float* dst = a.g_P + r * H;
+        for (int c = (lane & 3) * 4; c < H; c += 16) *reinterpret_cast<float4*>(dst + c) = make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+    }
+  }
+}
+
+template <int H, bool BF>
+static hipError_t launch_edge_bwd_split_t(const EdgeBwdArgs& a, int grid, hipStream_t s) {
+  using C = EdgeBwdSplitCfg<H, BF>;
+  (void)hipFuncSetAttribute((const void*)k_edge_bwd_split<H, BF>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)C::LDS);
+  hipLaunchKernelGGL((k_edge_bwd_split<H, BF>), dim3(grid), dim3(64 * C::NW), C::LDS, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_edge_bwd_split(const EdgeBwdArgs& a, int grid, hipStream_t s) {
+  if (a.H == 128) return a.bf ? launch_edge_bwd_split_t<128, true>(a, grid, s) : launch_edge_bwd_split_t<128, false>(a, grid, s);
+  return hipErrorInvalidValue;
+}
+
+// ---------------------------------------- weight gradients from row pairs
+
+template <int GW, int AW, bool BF>
+struct RowDwCfg {
+  static constexpr int NW = 8;
+  static constexpr int ROWS = 16 * NW;
+  static constexpr size_t TG = tile_bytes<GW, BF, ROWS>(), TA = tile_bytes<AW, BF, ROWS>();
+  // the column-sum scratch (FP32 path: 16 NW x GW floats) reuses the A tile
+  static constexpr size_t LDS = TG + TA;
+  static_assert(BF || TA >= 16 * NW * GW * sizeof(float), "column-sum scratch");
+};
+
+// dst[GW][AW] = sum over rows of G[r] (x) A[r], lock-step waves staging
+// 16-row blocks in LDS as the fused kernels do (same rounding of the
+// operands to BF16 on the BF16 path); column sums of G from the staged tile.
+template <int GW, int AW, bool BF, bool GBF, bool ABF>
+__global__ __launch_bounds__((64 * RowDwCfg<GW, AW, BF>::NW)) void k_row_dw(RowDwArgs a) {
+  using C = RowDwCfg<GW, AW, BF>;
+  constexpr int NW = C::NW, ROWS = C::ROWS, NT = dw_tiles_per_wave<GW, AW, NW>();
+  extern __shared__ uint4 smem[];
+  char* tG = reinterpret_cast<char*>(smem);
+  char* tA = tG + C::TG;
+  const int lane = lane_id(), j = lane & 15, g = lane >> 4, wave = threadIdx.x / 64;
+  const int srow = wave * 16 + j;
+  const int64_t n = a.n_rows, nblk = (n + 15) / 16;
+  const int64_t per = (nblk + gridDim.x - 1) / gridDim.x;
+  const int64_t b0 = blockIdx.x * per, b1 = std::min(nblk, b0 + per);
+  const int64_t n_iter = (b1 - b0 + NW - 1) / NW;
+  v4f acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+  ColSum<GW, NW> cs;  // BF16 tiles
+  cs.zero();
+  float csf[GW / 4];  // FP32 tiles: per-lane sums
+#pragma unroll
+  for (int i = 0; i < GW / 4; ++i) csf[i] = 0.f;
+  const bool want_cs = a.colsum_off >= 0;
+  // one block ahead
+  float gn[GW / 4], an[AW / 4];
+  {
+    const int64_t row = std::min<int64_t>((b0 + wave) * 16 + j, n - 1);
+    load_row_t<GW, GBF>(a.G, row, g, gn);
+    load_row_t<AW, ABF>(a.A, row, g, an);
+#pragma unroll
+    for (int i = 0; i < GW / 4; ++i) asm volatile("" : "+v"(gn[i]));
+#pragma unroll
+    for (int i = 0; i < AW / 4; ++i) asm volatile("" : "+v"(an[i]));
+  }
+  for (int64_t it = 0; it < n_iter; ++it) {
+    const int64_t bk = b0 + it * NW + wave;
+    const int64_t row = bk * 16 + j;
+    const bool valid = bk < b1 && row < n;
+    float gv[GW / 4], av[AW / 4];
+#pragma unroll
+    for (int i = 0; i < GW / 4; ++i) gv[i] = valid ? gn[i] : 0.f;
+#pragma unroll
+    for (int i = 0; i < AW / 4; ++i) av[i] = an[i];
+    {
+      const int64_t bk2 = bk + NW, row2 = std::min<int64_t>(bk2 * 16 + j, n - 1);
+      load_row_t<GW, GBF>(a.G, row2, g, gn);
+      load_row_t<AW, ABF>(a.A, row2, g, an);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (!BF) {
+#pragma unroll
+      for (int i = 0; i < GW / 4; ++i) csf[i] += gv[i];
+    }
+    stage_row<GW, BF, ROWS>(tG, srow, g, gv);
+    stage_row<AW, BF, ROWS>(tA, srow, g, av);
+    __syncthreads();
+    dw_tiles<GW, AW, BF, NW>(tG, tA, acc, wave, lane);
+    if constexpr (BF) {
+      if (want_cs) cs.add(tG, wave, lane);
+    }
+    __syncthreads();
+  }
+  float* slab = a.part + blockIdx.x * a.slab;
+  dw_store<GW, AW, NW>(acc, slab + a.off, AW, wave, lane);
+  if (want_cs) {
+    float* scratch = reinterpret_cast<float*>(tA);
+    if constexpr (BF)
+      cs.store(scratch, slab + a.colsum_off, wave, lane);
+    else
+      block_sum_vec<GW, NW>(csf, scratch, slab + a.colsum_off, wave, lane);
+  }
+}
+
+template <int GW, int AW, bool BF, bool GBF, bool ABF>
+static hipError_t launch_row_dw_t(const RowDwArgs& a, int grid, hipStream_t s) {
+  using C = RowDwCfg<GW, AW, BF>;
+  (void)hipFuncSetAttribute((const void*)k_row_dw<GW, AW, BF, GBF, ABF>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)C::LDS);
+  hipLaunchKernelGGL((k_row_dw<GW, AW, BF, GBF, ABF>), dim3(grid), dim3(64 * C::NW), C::LDS, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_row_dw(const RowDwArgs& a, int grid, hipStream_t s) {
+  if (a.GW != 128 || a.AW != 128) return hipErrorInvalidValue;
+  // BF16 products take BF16 or FP32 operands; FP32 products FP32 operands
+  if (a.bf) {
+    if (a.g_bf && a.a_bf) return launch_row_dw_t<128, 128, true, true, true>(a, grid, s);
+    if (a.g_bf && !a.a_bf) return launch_row_dw_t<128, 128, true, true, false>(a, grid, s);
+    return hipErrorInvalidValue;
+  }
+  if (!a.g_bf && !a.a_bf) return launch_row_dw_t<128, 128, false, false, false>(a, grid, s);
+  return hipErrorInvalidValue;
+}
+
+// Column sums of two [R][W] arrays: thread t sums feature group t % (W/4)
+// (4 features) over rows t / (W/4), + P, + 2P, ... of the workgroup's
+// range, then the row phases are added in order.
+template <int W, bool BF>
+__global__ __launch_bounds__(256) void k_colsum2(int64_t n_rows, const void* __restrict__ X,
+                                                 const void* __restrict__ Y, float* __restrict__ part,
+                                                 int64_t slab, int64_t offx, int64_t offy) {
+  constexpr int FG = W / 4, P = 256 / FG;
+  __shared__ float4 sx[256], sy[256];
+  const int fg = threadIdx.x % FG, ph = threadIdx.x / FG;
+  const int64_t per = (n_rows + gridDim.x - 1) / gridDim.x;
+  const int64_t r0 = blockIdx.x * per, r1 = std::min(n_rows, r0 + per);
+  float4 ax = make_float4(0.f, 0.f, 0.f, 0.f), ay = ax;
+  for (int64_t r = r0 + ph; r < r1; r += P) {
+    float4 x, y;
+    if constexpr (BF) {
+      const v4bf bx = __builtin_bit_cast(v4bf, *reinterpret_cast<const u32x2*>(reinterpret_cast<const __bf16*>(X) + r * W + 4 * fg));
+      const v4bf by = __builtin_bit_cast(v4bf, *reinterpret_cast<const u32x2*>(reinterpret_cast<const __bf16*>(Y) + r * W + 4 * fg));
+      x = make_float4((float)bx[0], (float)bx[1], (float)bx[2], (float)bx[3]);
+      y = make_float4((float)by[0], (float)by[1], (float)by[2], (float)by[3]);
+    } else {
+      x = *reinterpret_cast<const float4*>(reinterpret_cast<const float*>(X) + r * W + 4 * fg);
+      y = *reinterpret_cast<const float4*>(reinterpret_cast<const float*>(Y) + r * W + 4 * fg);
+    }
+    ax.x += x.x; ax.y += x.y; ax.z += x.z; ax.w += x.w;
+    ay.x += y.x; ay.y += y.y; ay.z += y.z; ay.w += y.w;
+  }
+  sx[threadIdx.x] = ax;
+  sy[threadIdx.x] = ay;
+  __syncthreads();
+  if ((int)threadIdx.x < FG) {
+    float4 tx = make_float4(0.f, 0.f, 0.f, 0.f), ty = tx;
+    for (int q = 0; q < P; ++q) {
+      const float4 u = sx[q * FG + threadIdx.x], v = sy[q * FG + threadIdx.x];
+      tx.x += u.x; tx.y += u.y; tx.z += u.z; tx.w += u.w;
+      ty.x += v.x; ty.y += v.y; ty.z += v.z; ty.w += v.w;
+    }
+    float* sl = part + blockIdx.x * slab;
+    *reinterpret_cast<float4*>(sl + offx + 4 * threadIdx.x) = tx;
+    *reinterpret_cast<float4*>(sl + offy + 4 * threadIdx.x) = ty;
+  }
+}
+
+hipError_t launch_colsum2(int64_t n_rows, int W, int bf, const void* X, const void* Y, float* part, int64_t slab,
+                          int64_t offx, int64_t offy, int grid, hipStream_t s) {
+  if (W != 128) return hipErrorInvalidValue;
+  if (bf)
+    hipLaunchKernelGGL((k_colsum2<128, true>), dim3(grid), dim3(256), 0, s, n_rows, X, Y, part, slab, offx, offy);
+  else
+    hipLaunchKernelGGL((k_colsum2<128, false>), dim3(grid), dim3(256), 0, s, n_rows, X, Y, part, slab, offx, offy);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------- sender-side gradients
 
 

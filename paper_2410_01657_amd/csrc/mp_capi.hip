@@ -122,6 +122,7 @@ struct LayerFrags {
 struct LayerWs {
   LayerFrags fr;
   size_t P, Q, a, gP, gh, part_e, part_n, part_q, tile_r, tile_e, total;
+  size_t sgm, su, sgE, sgEx;  // split edge adjoint: per-edge weight-gradient factors
   int ge, gbe, gn, gbn;
   int64_t n_tiles;
   LayerWs(const mp_layer_cfg* c, const mp_dev_graph* g, bool bwd) : fr(c->H, c->gemm_dtype == MP_BF16) {
@@ -138,9 +139,17 @@ struct LayerWs {
     Q = o; o = align_up(o + N * H * 4);
     a = o; o = align_up(o + N * H * 4);
     gP = gh = part_e = part_n = part_q = 0;
+    sgm = su = sgE = sgEx = 0;
     if (bwd) {
+      const size_t eb = E * H * (c->gemm_dtype == MP_BF16 ? 2 : 4);
       gP = o; o = align_up(o + N * H * 4);
-      gh = o; o = align_up(o + E * H * (c->gemm_dtype == MP_BF16 ? 2 : 4));
+      gh = o; o = align_up(o + eb);
+      if (edge_bwd_split(c->H)) {
+        sgm = o; o = align_up(o + eb);
+        su = o; o = align_up(o + eb);
+        sgE = o; o = align_up(o + eb);
+        sgEx = o; o = align_up(o + eb);
+      }
       part_e = o; o = align_up(o + (size_t)gbe * edge_slab(c->H) * 4);
       part_n = o; o = align_up(o + (size_t)gbn * mlp_slab(c->H, 2 * c->H, c->H) * 4);
       part_q = o; o = align_up(o + (size_t)gbn * gq_slab(c->H) * 4);
@@ -436,7 +445,42 @@ extern "C" int mp_layer_backward(const mp_layer_cfg* cfg, const mp_layer_params*
   eb.g_P = gP;
   eb.part = wsf(ws, W.part_e);
   eb.slab = edge_slab(H);
-  if ((rc = run("edge_bwd", s, [&] { return launch_edge_bwd(eb, W.gbe, s); }))) return rc;
+  if (edge_bwd_split(H)) {
+    // wide layers: the adjoint writes the per-edge factors, then the weight
+    // gradients are summed from them (same slab layout as the fused kernel)
+    eb.gm = ws_at(ws, W.sgm);
+    eb.u = ws_at(ws, W.su);
+    eb.gE = ws_at(ws, W.sgE);
+    eb.gEx = ws_at(ws, W.sgEx);
+    if ((rc = run("edge_bwd", s, [&] { return launch_edge_bwd_split(eb, W.gbe, s); }))) return rc;
+    RowDwArgs rd{};
+    rd.n_rows = g->n_edges;
+    rd.GW = rd.AW = H;
+    rd.bf = bf;
+    rd.part = eb.part;
+    rd.slab = eb.slab;
+    rd.G = gh;  // dW1c = sum g_h e^T
+    rd.g_bf = bf;
+    rd.A = e_in;
+    rd.a_bf = 0;
+    rd.off = 0;
+    rd.colsum_off = -1;
+    if ((rc = run("edge_dw", s, [&] { return launch_row_dw(rd, W.gbe, s); }))) return rc;
+    rd.G = eb.gm;  // dW2 = sum gm u^T, db2 = sum gm
+    rd.A = eb.u;
+    rd.a_bf = bf;
+    rd.off = (int64_t)H * H;
+    rd.colsum_off = 2 * (int64_t)H * H;
+    if ((rc = run("edge_dw", s, [&] { return launch_row_dw(rd, W.gbe, s); }))) return rc;
+    if (cfg->layernorm &&
+        (rc = run("edge_dw", s, [&] {
+           return launch_colsum2(g->n_edges, H, bf, eb.gEx, eb.gE, eb.part, eb.slab, 2 * (int64_t)H * H + H,
+                                 2 * (int64_t)H * H + 2 * H, W.gbe, s);
+         })))
+      return rc;
+  } else if ((rc = run("edge_bwd", s, [&] { return launch_edge_bwd(eb, W.gbe, s); }))) {
+    return rc;
+  }
   GqArgs q{};
   q.g = d;
   q.H = H;

@@ -134,8 +134,38 @@ struct EdgeBwdArgs {
   float* g_P;            // [N][H] sum of g_h over each row's incoming edges
   float* part;           // partial weight gradients, slab per workgroup
   int64_t slab;
+  // split form (edge_bwd_split): per-edge factors of the weight gradients,
+  // [E][H] each, BF16 on the BF16 path: gm (pre-LayerNorm gradient), u
+  // (ELU output), gE (gradient reaching e') and gEx (gE * normalised m)
+  void* gm;
+  void* u;
+  void* gE;
+  void* gEx;
 };
 hipError_t launch_edge_bwd(const EdgeBwdArgs& a, int grid, hipStream_t s);
+// Whether layers of width H use the split edge adjoint (the fused kernel's
+// weight-gradient tiles and all four weight matrices do not fit on chip).
+constexpr bool edge_bwd_split(int H) { return H > 64; }
+hipError_t launch_edge_bwd_split(const EdgeBwdArgs& a, int grid, hipStream_t s);
+// dst slab block [GW][AW] += sum over rows r of G[r] (x) A[r]  (G: [R][GW],
+// A: [R][AW]; BF16 or FP32 as `g_bf` / `a_bf`), one slab per workgroup at
+// part + blockIdx.x * slab + off; with colsum_off >= 0 also the column sums
+// of G at colsum_off.  Rows split in contiguous ranges per workgroup.
+struct RowDwArgs {
+  int64_t n_rows;
+  int GW, AW, bf;       // bf: staging and products in BF16
+  const void* G;
+  int g_bf;             // G stored as BF16
+  const void* A;
+  int a_bf;             // A stored as BF16
+  float* part;
+  int64_t slab, off, colsum_off;
+};
+hipError_t launch_row_dw(const RowDwArgs& a, int grid, hipStream_t s);
+// Column sums of X[R][W] and Y[R][W] (BF16 or FP32) into slab offsets
+// offx / offy per workgroup, rows split as in launch_row_dw.
+hipError_t launch_colsum2(int64_t n_rows, int W, int bf, const void* X, const void* Y, float* part, int64_t slab,
+                          int64_t offx, int64_t offy, int grid, hipStream_t s);
 
 struct MlpBwdArgs {
   int64_t n_rows;

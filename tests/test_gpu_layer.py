@@ -168,9 +168,14 @@ def test_layer_forward_rcb(rcb):
 # ---------------------------------------------------- one-layer adjoint
 
 
-@pytest.mark.parametrize("H,ln,R,gemm", [(32, False, 8, "f32"), (64, True, 8, "f32"), (64, True, 1, "f32"),
-                                         (128, True, 8, "f32"), (64, True, 8, "bf16")])
-def test_layer_backward(c0, H, ln, R, gemm):
+# H=128 runs the split adjoint (per-edge factors + separate weight-gradient
+# sums); the other widths the fused kernel.  no_ge: the last layer's case,
+# no gradient at the edge output.
+@pytest.mark.parametrize("H,ln,R,gemm,no_ge", [(32, False, 8, "f32", False), (64, True, 8, "f32", False),
+                                               (64, True, 1, "f32", False), (128, True, 8, "f32", False),
+                                               (64, True, 8, "bf16", False), (128, True, 8, "bf16", False),
+                                               (128, False, 1, "f32", True), (64, True, 8, "bf16", True)])
+def test_layer_backward(c0, H, ln, R, gemm, no_ge):
     from paper_2410_01657_amd.ops import layer_backward, layer_cfg, layer_forward
     inp, gs = c0
     dg, og, pairs = gs[R]
@@ -180,10 +185,12 @@ def test_layer_backward(c0, H, ln, R, gemm):
     e = rng.standard_normal((dg.n_edges, H)).astype(np.float32)
     gx = rng.standard_normal((dg.n_rows, H)).astype(np.float32)
     ge = rng.standard_normal((dg.n_edges, H)).astype(np.float32)
+    if no_ge:
+        ge[:] = 0.0
     cfg = layer_cfg(H, ln, gemm=gemm)
     p = _lib_params(o, names)
     _, _, a_star = layer_forward(cfg, p, dg, _t(x), _t(e))
-    g_x, g_e, grads = layer_backward(cfg, p, dg, _t(x), _t(e), a_star, _t(gx), _t(ge))
+    g_x, g_e, grads = layer_backward(cfg, p, dg, _t(x), _t(e), a_star, _t(gx), None if no_ge else _t(ge))
     xr, er, ar, cache, xs, es = _oracle_layer(o, spec, og, pairs, x, e)
     n_off = [0] + list(np.cumsum([G.n for G in og]))
     e_off = [0] + list(np.cumsum([G.e for G in og]))
@@ -198,16 +205,16 @@ def test_layer_backward(c0, H, ln, R, gemm):
         assert err < tol, (k, err)
 
 
-def test_layer_deterministic(c0):
+@pytest.mark.parametrize("H,gemm", [(64, "f32"), (128, "bf16")])
+def test_layer_deterministic(c0, H, gemm):
     from paper_2410_01657_amd.ops import layer_backward, layer_cfg, layer_forward
     inp, gs = c0
     dg, og, pairs = gs[8]
-    H = 64
     spec, o, names = layer_params(H, True)
     rng = np.random.default_rng(0)
     x, e = _t(rng.standard_normal((dg.n_rows, H))), _t(rng.standard_normal((dg.n_edges, H)))
     gx, ge = _t(rng.standard_normal((dg.n_rows, H))), _t(rng.standard_normal((dg.n_edges, H)))
-    cfg = layer_cfg(H, True)
+    cfg = layer_cfg(H, True, gemm=gemm)
     p = _lib_params(o, names)
     runs = []
     for _ in range(2):
