@@ -186,10 +186,13 @@ int mp_layer_workspace_size(const mp_layer_cfg* cfg, const mp_dev_graph* g,
 
 /* Forward.  x_in[N][H], e_in[E][H] -> x_out[N][H], e_out[E][H] (FP32).
  * a_star_out[N][H] receives the synchronised aggregate a* (needed by the
- * backward); it may be NULL.  Outputs must not alias inputs. */
+ * backward); it may be NULL.  pq_out[2][N][H], if not NULL, receives the
+ * node projections of the first edge-MLP Linear (Eq. 4a split over its
+ * input): P = W1a x_in + b1, then Q = W1b x_in; handing them to the
+ * backward saves recomputing them.  Outputs must not alias inputs. */
 int mp_layer_forward(const mp_layer_cfg* cfg, const mp_layer_params* p,
                      const mp_dev_graph* g, const float* x_in, const float* e_in,
-                     float* x_out, float* e_out, float* a_star_out,
+                     float* x_out, float* e_out, float* a_star_out, float* pq_out,
                      void* ws, size_t ws_bytes, mp_stream_t stream);
 
 /* Backward (adjoint of the forward, Eq. 3): given the forward inputs, the
@@ -197,10 +200,11 @@ int mp_layer_forward(const mp_layer_cfg* cfg, const mp_layer_params* p,
  * write the gradients with respect to x_in and e_in and every parameter.
  * Edge-MLP activations are recomputed from (x_in, e_in), not stored.  The
  * halo sum is its own adjoint and is applied to the a* gradient.  g_e_out
- * may be NULL (zero). */
+ * may be NULL (zero).  pq is the forward's pq_out for the same inputs and
+ * parameters, or NULL (then P and Q are recomputed). */
 int mp_layer_backward(const mp_layer_cfg* cfg, const mp_layer_params* p,
                       const mp_dev_graph* g, const float* x_in, const float* e_in,
-                      const float* a_star, const float* g_x_out, const float* g_e_out,
+                      const float* a_star, const float* pq, const float* g_x_out, const float* g_e_out,
                       float* g_x_in, float* g_e_in, const mp_layer_grads* grads,
                       void* ws, size_t ws_bytes, mp_stream_t stream);
 

@@ -72,8 +72,8 @@ _SIGS = {
     "mp_dev_graph_seal": (c_u64, [P(MpDevGraph)]),
     "mp_layer_workspace_size": (c_i32, [P(MpLayerCfg), P(MpDevGraph), c_i32, P(C.c_size_t)]),
     "mp_layer_forward": (c_i32, [P(MpLayerCfg), P(MpLayerParams), P(MpDevGraph), vp, vp, vp, vp, vp,
-                                 vp, C.c_size_t, vp]),
-    "mp_layer_backward": (c_i32, [P(MpLayerCfg), P(MpLayerParams), P(MpDevGraph), vp, vp, vp, vp, vp,
+                                 vp, vp, C.c_size_t, vp]),
+    "mp_layer_backward": (c_i32, [P(MpLayerCfg), P(MpLayerParams), P(MpDevGraph), vp, vp, vp, vp, vp, vp,
                                   vp, vp, P(MpLayerGrads), vp, C.c_size_t, vp]),
     "mp_mlp_workspace_size": (c_i32, [P(MpMlpCfg), c_i64, c_i32, P(C.c_size_t)]),
     "mp_mlp_forward": (c_i32, [P(MpMlpCfg), P(MpMlpParams), c_i64, vp, vp, vp, C.c_size_t, vp]),

@@ -300,14 +300,15 @@ extern "C" int mp_layer_workspace_size(const mp_layer_cfg* cfg, const mp_dev_gra
 
 extern "C" int mp_layer_forward(const mp_layer_cfg* cfg, const mp_layer_params* p, const mp_dev_graph* g,
                                 const float* x_in, const float* e_in, float* x_out, float* e_out, float* a_star_out,
-                                void* ws, size_t ws_bytes, mp_stream_t stream) {
+                                float* pq_out, void* ws, size_t ws_bytes, mp_stream_t stream) {
   int rc;
   if ((rc = check_cfg(cfg)) || (rc = check_graph(g, false)) || (rc = check_layer_params(cfg, p))) return rc;
   if (!x_in || !e_in || !x_out || !e_out || !ws) return mp_fail(MP_EINVAL, "mp_layer_forward: NULL buffer");
   if (!aligned16(x_in) || !aligned16(e_in) || !aligned16(x_out) || !aligned16(e_out) || !aligned16(ws) ||
-      (a_star_out && !aligned16(a_star_out)))
+      (a_star_out && !aligned16(a_star_out)) || (pq_out && !aligned16(pq_out)))
     return mp_fail(MP_EINVAL, "mp_layer_forward: buffers must be 16-byte aligned");
-  if (x_out == x_in || e_out == e_in || (const float*)e_out == x_in || (const float*)x_out == e_in)
+  if (x_out == x_in || e_out == e_in || (const float*)e_out == x_in || (const float*)x_out == e_in ||
+      (pq_out && ((const float*)pq_out == x_in || (const float*)pq_out == e_in)))
     return mp_fail(MP_EINVAL, "mp_layer_forward: outputs must not alias inputs");
   const LayerWs W(cfg, g, false);
   if (ws_bytes < W.total) return mp_fail(MP_ENOMEM, "mp_layer_forward: workspace %zu < %zu bytes", ws_bytes, W.total);
@@ -318,8 +319,8 @@ extern "C" int mp_layer_forward(const mp_layer_cfg* cfg, const mp_layer_params* 
   d.n_tiles = W.n_tiles;
   d.tile_r = reinterpret_cast<const int32_t*>(ws_at(ws, W.tile_r));
   d.tile_e = reinterpret_cast<const int32_t*>(ws_at(ws, W.tile_e));
-  float* P = wsf(ws, W.P);
-  float* Q = wsf(ws, W.Q);
+  float* P = pq_out ? pq_out : wsf(ws, W.P);
+  float* Q = pq_out ? pq_out + (size_t)g->n_rows * cfg->H : wsf(ws, W.Q);
   float* a = a_star_out ? a_star_out : wsf(ws, W.a);
   if ((rc = run("tiles", s, [&] {
          return launch_tiles(d, reinterpret_cast<int32_t*>(ws_at(ws, W.tile_r)),
@@ -355,8 +356,9 @@ extern "C" int mp_layer_forward(const mp_layer_cfg* cfg, const mp_layer_params* 
 }
 
 extern "C" int mp_layer_backward(const mp_layer_cfg* cfg, const mp_layer_params* p, const mp_dev_graph* g,
-                                 const float* x_in, const float* e_in, const float* a_star, const float* g_x_out,
-                                 const float* g_e_out, float* g_x_in, float* g_e_in, const mp_layer_grads* gr,
+                                 const float* x_in, const float* e_in, const float* a_star, const float* pq,
+                                 const float* g_x_out, const float* g_e_out, float* g_x_in, float* g_e_in,
+                                 const mp_layer_grads* gr,
                                  void* ws, size_t ws_bytes, mp_stream_t stream) {
   int rc;
   if ((rc = check_cfg(cfg)) || (rc = check_graph(g, true)) || (rc = check_layer_params(cfg, p))) return rc;
@@ -366,6 +368,7 @@ extern "C" int mp_layer_backward(const mp_layer_cfg* cfg, const mp_layer_params*
   for (const void* q : al)
     if (!aligned16(q)) return mp_fail(MP_EINVAL, "mp_layer_backward: buffers must be 16-byte aligned");
   if (g_e_out && !aligned16(g_e_out)) return mp_fail(MP_EINVAL, "mp_layer_backward: g_e_out not aligned");
+  if (pq && !aligned16(pq)) return mp_fail(MP_EINVAL, "mp_layer_backward: pq not aligned");
   float* gw[] = {gr->We1, gr->be1, gr->We2, gr->be2, gr->Wn1, gr->bn1, gr->Wn2, gr->bn2};
   for (float* q : gw)
     if (!q) return mp_fail(MP_EINVAL, "mp_layer_backward: a gradient buffer is NULL");
@@ -383,8 +386,8 @@ extern "C" int mp_layer_backward(const mp_layer_cfg* cfg, const mp_layer_params*
   d.n_tiles = W.n_tiles;
   d.tile_r = reinterpret_cast<const int32_t*>(ws_at(ws, W.tile_r));
   d.tile_e = reinterpret_cast<const int32_t*>(ws_at(ws, W.tile_e));
-  float* P = wsf(ws, W.P);
-  float* Q = wsf(ws, W.Q);
+  const float* P = pq ? pq : wsf(ws, W.P);
+  const float* Q = pq ? pq + (size_t)g->n_rows * H : wsf(ws, W.Q);
   float* ga = wsf(ws, W.a);
   if ((rc = run("tiles", s, [&] {
          return launch_tiles(d, reinterpret_cast<int32_t*>(ws_at(ws, W.tile_r)),
@@ -394,7 +397,10 @@ extern "C" int mp_layer_backward(const mp_layer_cfg* cfg, const mp_layer_params*
   float* gP = wsf(ws, W.gP);
   void* gh = ws_at(ws, W.gh);
   if ((rc = run("pack", s, [&] { return launch_pack(layer_jobs(cfg, p, W.fr, true), ws, s); }))) return rc;
-  if ((rc = run("proj", s, [&] { return launch_proj(H, bf, d, x_in, ws_at(ws, W.fr.proj), p->be1, P, Q, W.gn, s); }))) return rc;
+  if (!pq && (rc = run("proj", s, [&] {
+                return launch_proj(H, bf, d, x_in, ws_at(ws, W.fr.proj), p->be1, wsf(ws, W.P), wsf(ws, W.Q), W.gn, s);
+              })))
+    return rc;
   // node MLP adjoint: g_a* and g_x (residual + node-MLP part)
   MlpBwdArgs m{};
   m.n_rows = g->n_rows;
@@ -517,11 +523,11 @@ extern "C" int mp_layer_backward(const mp_layer_cfg* cfg, const mp_layer_params*
     seg(pe, W.gbe, se, 2 * H * H + H, 1, H, gr->ge, H, 0);
     seg(pe, W.gbe, se, 2 * H * H + 2 * H, 1, H, gr->bge, H, 0);
   }
-  const float* pq = wsf(ws, W.part_q);
+  const float* pgq = wsf(ws, W.part_q);
   const int64_t sq = gq_slab(H);
-  seg(pq, W.gbn, sq, 0, H, H, gr->We1, 3 * H, 0);
-  seg(pq, W.gbn, sq, H * H, H, H, gr->We1, 3 * H, H);
-  seg(pq, W.gbn, sq, 2 * H * H, 1, H, gr->be1, H, 0);
+  seg(pgq, W.gbn, sq, 0, H, H, gr->We1, 3 * H, 0);
+  seg(pgq, W.gbn, sq, H * H, H, H, gr->We1, 3 * H, H);
+  seg(pgq, W.gbn, sq, 2 * H * H, 1, H, gr->be1, H, 0);
   return run("wreduce", s, [&] { return launch_wreduce(R, s); });
 }
 

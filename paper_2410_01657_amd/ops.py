@@ -66,20 +66,24 @@ def _layer_params(p):
     return s
 
 
-def layer_forward(cfg, p, dg, x, e):
-    """One consistent NMP layer; returns (x_out, e_out, a_star)."""
+def layer_forward(cfg, p, dg, x, e, want_pq=False):
+    """One consistent NMP layer; returns (x_out, e_out, a_star), plus the node
+    projections pq = [P; Q] ([2, N, H], for the backward) when want_pq."""
     _check(x, e)
     x_out, e_out, a_star = torch.empty_like(x), torch.empty_like(e), torch.empty_like(x)
+    pq = torch.empty((2,) + tuple(x.shape), dtype=x.dtype, device=x.device) if want_pq else None
     nb = C.c_size_t()
     call("mp_layer_workspace_size", C.byref(cfg), C.byref(dg.desc), 0, C.byref(nb))
     ws = WS.get(nb.value, x.device)
     call("mp_layer_forward", C.byref(cfg), C.byref(_layer_params(p)), C.byref(dg.desc), _p(x), _p(e),
-         _p(x_out), _p(e_out), _p(a_star), _p(ws), ws.numel(), _stream())
-    return x_out, e_out, a_star
+         _p(x_out), _p(e_out), _p(a_star), _p(pq), _p(ws), ws.numel(), _stream())
+    return (x_out, e_out, a_star, pq) if want_pq else (x_out, e_out, a_star)
 
 
-def layer_backward(cfg, p, dg, x, e, a_star, g_x_out, g_e_out):
-    _check(x, e, a_star, g_x_out, g_e_out)
+def layer_backward(cfg, p, dg, x, e, a_star, g_x_out, g_e_out, pq=None):
+    """Adjoint of layer_forward; pq (from layer_forward(want_pq=True)) skips
+    recomputing the node projections."""
+    _check(x, e, a_star, g_x_out, g_e_out, pq)
     g_x, g_e = torch.empty_like(x), torch.empty_like(e)
     grads = {f: (torch.empty_like(p[f]) if p.get(f) is not None else None) for f in LAYER_FIELDS}
     gs = MpLayerGrads()
@@ -89,7 +93,7 @@ def layer_backward(cfg, p, dg, x, e, a_star, g_x_out, g_e_out):
     call("mp_layer_workspace_size", C.byref(cfg), C.byref(dg.desc), 1, C.byref(nb))
     ws = WS.get(nb.value, x.device)
     call("mp_layer_backward", C.byref(cfg), C.byref(_layer_params(p)), C.byref(dg.desc), _p(x), _p(e),
-         _p(a_star), _p(g_x_out), _p(g_e_out), _p(g_x), _p(g_e), C.byref(gs), _p(ws), ws.numel(),
+         _p(a_star), _p(pq), _p(g_x_out), _p(g_e_out), _p(g_x), _p(g_e), C.byref(gs), _p(ws), ws.numel(),
          _stream())
     return g_x, g_e, grads
 
@@ -100,22 +104,22 @@ class MPLayerFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, cfg, dg, x, e, *params):
         p = dict(zip(LAYER_FIELDS, params))
-        x_out, e_out, a_star = layer_forward(cfg, p, dg, x, e)
+        x_out, e_out, a_star, pq = layer_forward(cfg, p, dg, x, e, want_pq=True)
         ctx.cfg, ctx.dg = cfg, dg
         # an unused edge-state output (the last layer's) arrives as None in
         # the backward instead of a materialised zero tensor
         ctx.set_materialize_grads(False)
-        ctx.save_for_backward(x, e, a_star, *[t if t is not None else torch.empty(0) for t in params])
+        ctx.save_for_backward(x, e, a_star, pq, *[t if t is not None else torch.empty(0) for t in params])
         ctx.has = [t is not None for t in params]
         return x_out, e_out
 
     @staticmethod
     def backward(ctx, g_x_out, g_e_out):
-        x, e, a_star, *ps = ctx.saved_tensors
+        x, e, a_star, pq, *ps = ctx.saved_tensors
         p = {f: (t if h else None) for f, t, h in zip(LAYER_FIELDS, ps, ctx.has)}
         g_x_out = g_x_out.contiguous() if g_x_out is not None else torch.zeros_like(x)
         g_e_out = g_e_out.contiguous() if g_e_out is not None else None
-        g_x, g_e, grads = layer_backward(ctx.cfg, p, ctx.dg, x, e, a_star, g_x_out, g_e_out)
+        g_x, g_e, grads = layer_backward(ctx.cfg, p, ctx.dg, x, e, a_star, g_x_out, g_e_out, pq)
         return (None, None, g_x, g_e) + tuple(grads[f] for f in LAYER_FIELDS)
 
 

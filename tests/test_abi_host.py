@@ -179,21 +179,21 @@ def test_device_entry_points_validate_before_launch(L):
     params = L.MpLayerParams()
     with pytest.raises(MPError) as e:  # NULL parameters
         call("mp_layer_forward", C.byref(cfg), C.byref(params), C.byref(d), None, None, None, None, None,
-             None, 0, None)
+             None, None, 0, None)
     assert e.value.code == L.MP_EINVAL
     for f in L.LAYER_FIELDS:
         setattr(params, f, 4096)
     with pytest.raises(MPError) as e:  # workspace too small
         call("mp_layer_forward", C.byref(cfg), C.byref(params), C.byref(d), 4096, 8192, 12288, 16384, None,
-             4096, 16, None)
+             None, 4096, 16, None)
     assert e.value.code == L.MP_ENOMEM
     with pytest.raises(MPError) as e:  # aliasing
         call("mp_layer_forward", C.byref(cfg), C.byref(params), C.byref(d), 4096, 8192, 4096, 16384, None,
-             4096, 1 << 30, None)
+             None, 4096, 1 << 30, None)
     assert e.value.code == L.MP_EINVAL
     with pytest.raises(MPError):  # unaligned
         call("mp_layer_forward", C.byref(cfg), C.byref(params), C.byref(d), 4100, 8192, 12288, 16384, None,
-             4096, 1 << 30, None)
+             None, 4096, 1 << 30, None)
 
 
 def test_mlp_and_loss_validation(L):

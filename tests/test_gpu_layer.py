@@ -223,3 +223,26 @@ def test_layer_deterministic(c0, H, gemm):
         runs.append([xo, eo, a, g[0], g[1]] + [g[2][k] for k in sorted(names)])
     for a, b in zip(*runs):
         assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("H,gemm", [(64, "bf16"), (128, "f32")])
+def test_layer_backward_with_forward_projections(c0, H, gemm):
+    """The backward given the forward's node projections (pq) equals the
+    backward that recomputes them, bit for bit (same kernel, same inputs)."""
+    from paper_2410_01657_amd.ops import layer_backward, layer_cfg, layer_forward
+    inp, gs = c0
+    dg, og, pairs = gs[8]
+    spec, o, names = layer_params(H, True)
+    rng = np.random.default_rng(5)
+    x, e = _t(rng.standard_normal((dg.n_rows, H))), _t(rng.standard_normal((dg.n_edges, H)))
+    gx, ge = _t(rng.standard_normal((dg.n_rows, H))), _t(rng.standard_normal((dg.n_edges, H)))
+    cfg = layer_cfg(H, True, gemm=gemm)
+    p = _lib_params(o, names)
+    xo, eo, a, pq = layer_forward(cfg, p, dg, x, e, want_pq=True)
+    xo2, eo2, a2 = layer_forward(cfg, p, dg, x, e)
+    assert torch.equal(xo, xo2) and torch.equal(eo, eo2) and torch.equal(a, a2)
+    g1 = layer_backward(cfg, p, dg, x, e, a, gx, ge, pq)
+    g2 = layer_backward(cfg, p, dg, x, e, a, gx, ge)
+    assert torch.equal(g1[0], g2[0]) and torch.equal(g1[1], g2[1])
+    for k in names:
+        assert torch.equal(g1[2][k], g2[2][k]), k
