@@ -944,7 +944,7 @@ struct GqCfg {
 //   g_x[j] += W1a^T g_P[j] + W1b^T g_Q[j]
 //   dW1a += g_P x^T, dW1b += g_Q x^T, db1 += g_P.
 template <int H, bool BF>
-__global__ __launch_bounds__(256) void k_gq(GqArgs a) {
+__global__ __launch_bounds__(256, (H <= 64 ? 2 : 1)) void k_gq(GqArgs a) {
   using C = GqCfg<H, BF>;
   constexpr int NF = H / 4, MB = H / 16, NT = dw_tiles_per_wave<2 * H, H>();
   // edges gathered per round trip: as many raw rows as fit in 48 registers
@@ -1090,7 +1090,10 @@ struct MlpBwdCfg {
   // otherwise phase 0 stages the input into the second phase-1 tile
   static constexpr bool SEP_A0 = STAGE1 + TA0 + 2 * F0 + 2 * F1 + SMALL_ + 3 * H * sizeof(float) <= kLdsLimit;
   static constexpr size_t STAGE0 = TB + TA0;
-  static constexpr size_t STAGE = SEP_A0 ? STAGE1 + TA0 : (STAGE0 > STAGE1 ? STAGE0 : STAGE1);
+  // one staging round per block (both phases' tiles at once, two barriers
+  // instead of four) when g_z has a tile of its own as well
+  static constexpr bool ONE = SEP_A0 && STAGE1 + TA0 + TB + 2 * F0 + 2 * F1 + SMALL_ + 3 * H * sizeof(float) <= kLdsLimit;
+  static constexpr size_t STAGE = ONE ? STAGE1 + TA0 + TB : SEP_A0 ? STAGE1 + TA0 : (STAGE0 > STAGE1 ? STAGE0 : STAGE1);
   static constexpr size_t SMALL = (TIN || TOUT) ? 16 * H : 0;  // small W0 / W1, [.][4] or [4][H]
   static constexpr size_t VECS = 3 * H * sizeof(float);         // b0, b1, LayerNorm gain
   static constexpr bool LDS_FRAG = FRAG + STAGE + SMALL + VECS <= kLdsLimit;
@@ -1159,7 +1162,8 @@ __global__ __launch_bounds__((64 * MlpBwdCfg<H, KIN, TIN, TOUT, BF>::NW)) void k
   char* tA = tG + C::TB;
   char* tGE = tA + C::TB;  // phase 1, VEC: g_out and g_out * normalised y
   char* tGM = tGE + C::TB;
-  char* tA0 = C::SEP_A0 ? tG + C::STAGE1 : tA;  // phase 0: the input rows
+  char* tA0 = C::SEP_A0 ? tG + C::STAGE1 : tA;            // phase 0: the input rows
+  char* tG0 = C::ONE ? tG + C::STAGE1 + C::TA0 : tG;      // phase 0: g_z
   const char* fr;
   if constexpr (C::LDS_FRAG) {
     uint4* fl = smem + C::STAGE / 16;
@@ -1204,6 +1208,21 @@ __global__ __launch_bounds__((64 * MlpBwdCfg<H, KIN, TIN, TOUT, BF>::NW)) void k
   // node update, whose registers are fully used)
   using CS = typename std::conditional<KIN == 2 * H, ColSumValu<H, NW>, ColSum<H, NW>>::type;
   CS cs_b0, cs_b1, cs_ga, cs_be;
+  // dW1 (and its bias / LayerNorm column sums) from the phase-1 tiles
+  auto phase1_products = [&]() {
+    if constexpr (TOUT) {
+      dw_tiles<16, H, BF, NW>(tG, tA, acc1, wave, lane);
+    } else {
+      dw_tiles<H, H, BF, NW>(tG, tA, acc1, wave, lane);
+      if constexpr (C::VEC) {
+        cs_b1.add(tG, wave, lane);
+        if (a.ln) {
+          cs_be.add(tGE, wave, lane);
+          cs_ga.add(tGM, wave, lane);
+        }
+      }
+    }
+  };
   cs_b0.zero();
   cs_b1.zero();
   cs_ga.zero();
@@ -1288,9 +1307,11 @@ __global__ __launch_bounds__((64 * MlpBwdCfg<H, KIN, TIN, TOUT, BF>::NW)) void k
       for (int o = 0; o < 4; ++o) go16[o] = g == 0 ? cur.go[o] : 0.f;
       stage_row<16, BF, ROWS, PK>(tG, srow, g, go16);
       stage_row<H, BF, ROWS, PK>(tA, srow, g, u);
-      __syncthreads();
-      dw_tiles<16, H, BF, NW>(tG, tA, acc1, wave, lane);
-      __syncthreads();
+      if constexpr (!C::ONE) {
+        __syncthreads();
+        phase1_products();
+        __syncthreads();
+      }
     } else {
       float y[NF];
       load_vec<H>(vb + H, g, y);
@@ -1333,16 +1354,11 @@ __global__ __launch_bounds__((64 * MlpBwdCfg<H, KIN, TIN, TOUT, BF>::NW)) void k
       }
       stage_row<H, BF, ROWS, PK>(tG, srow, g, y);
       stage_row<H, BF, ROWS, PK>(tA, srow, g, u);
-      __syncthreads();
-      dw_tiles<H, H, BF, NW>(tG, tA, acc1, wave, lane);
-      if constexpr (C::VEC) {
-        cs_b1.add(tG, wave, lane);
-        if (a.ln) {
-          cs_be.add(tGE, wave, lane);
-          cs_ga.add(tGM, wave, lane);
-        }
+      if constexpr (!C::ONE) {
+        __syncthreads();
+        phase1_products();
+        __syncthreads();
       }
-      __syncthreads();
 #pragma unroll
       for (int i = 0; i < NF; ++i) gu[i] = 0.f;
       gemm<BF, MB, MB>(f1t, y, gu, lane);
@@ -1354,11 +1370,12 @@ __global__ __launch_bounds__((64 * MlpBwdCfg<H, KIN, TIN, TOUT, BF>::NW)) void k
 #pragma unroll
       for (int i = 0; i < NF; ++i) db0[i] += gu[i];
     }
-    stage_row<H, BF, ROWS, PK>(tG, srow, g, gu);
+    stage_row<H, BF, ROWS, PK>(tG0, srow, g, gu);
     if constexpr (!C::SEP_A0) stage_in();
     __syncthreads();
-    dw_tiles<H, AW0, BF, NW>(tG, tA0, acc0, wave, lane);
-    if constexpr (C::VEC) cs_b0.add(tG, wave, lane);
+    if constexpr (C::ONE) phase1_products();
+    dw_tiles<H, AW0, BF, NW>(tG0, tA0, acc0, wave, lane);
+    if constexpr (C::VEC) cs_b0.add(tG0, wave, lane);
     __syncthreads();
     // ---- input gradient
     if constexpr (!TIN) {

@@ -71,7 +71,7 @@ __device__ __forceinline__ void stage_to_lds(uint4* __restrict__ dst, const void
 // splits the Linear of Eq. 4a over its concatenated input; the products
 // are the same, only the summation grouping differs.
 template <int H, bool BF>
-__global__ __launch_bounds__(256) void k_proj(int64_t n_rows, const float* __restrict__ x,
+__global__ __launch_bounds__(256, (H <= 64 ? 4 : 1)) void k_proj(int64_t n_rows, const float* __restrict__ x,
                                               const void* __restrict__ frag, const float* __restrict__ b1,
                                               float* __restrict__ P, float* __restrict__ Q) {
   constexpr int NF = H / 4, MB = H / 16;
