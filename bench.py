@@ -107,7 +107,7 @@ def recorded_traffic(kernel, workload):
     return float(rec["read_bytes"]) + float(rec["write_bytes"])
 
 
-KERNELS = ("pack", "tiles", "proj", "edge_fwd", "halo", "halo_adj", "node_fwd", "node_bwd", "edge_bwd", "edge_dw",
+KERNELS = ("pack", "tiles", "proj", "edge_fwd", "halo", "halo_adj", "node_fwd", "node_bwd", "edge_bwd", "edge_dw", "node_dw",
            "gq", "wreduce", "mlp_fwd", "mlp_bwd", "edge_inputs", "loss")
 
 

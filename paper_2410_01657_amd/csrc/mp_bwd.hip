@@ -553,10 +553,13 @@ template <int H, bool BF>
 struct EdgeBwdSplitCfg {
   static constexpr int NW = 8;  // independent waves sharing the LDS weight fragments
   static constexpr size_t FB = frag_bytes(H, H, BF);
+  // BF16 keeps W1c, W2, W2^T, W1c^T; FP32 only W1c and W2 (the transposed
+  // products read them at transposed addresses, gemm_f32_tr)
+  static constexpr int NFR = BF ? 4 : 2;
   static constexpr size_t VECS = 2 * H * sizeof(float);
   static constexpr size_t CARRY = NW * H * sizeof(float);
-  static constexpr bool LDS_FRAG = 4 * FB + VECS + CARRY <= kLdsLimit;
-  static constexpr size_t LDS = (LDS_FRAG ? 4 * FB : 0) + CARRY + VECS;
+  static constexpr bool LDS_FRAG = NFR * FB + VECS + CARRY <= kLdsLimit;
+  static constexpr size_t LDS = (LDS_FRAG ? NFR * FB : 0) + CARRY + VECS;
 };
 
 // The edge adjoint without its weight gradients, for widths where the
@@ -573,7 +576,7 @@ __global__ __launch_bounds__((64 * EdgeBwdSplitCfg<H, BF>::NW)) void k_edge_bwd_
   extern __shared__ uint4 smem[];
   const char* fr;
   if constexpr (C::LDS_FRAG) {
-    stage_frags(smem, a.frag, 4 * C::FB);
+    stage_frags(smem, a.frag, C::NFR * C::FB);
     fr = reinterpret_cast<const char*>(smem);
   } else {
     fr = reinterpret_cast<const char*>(a.frag);
@@ -680,11 +683,17 @@ __global__ __launch_bounds__((64 * EdgeBwdSplitCfg<H, BF>::NW)) void k_edge_bwd_
       // gh = (W2^T gm) * ELU'(h); ELU'(h) = 1 for h > 0 else exp(h) = u + 1
 #pragma unroll
       for (int i = 0; i < NF; ++i) t[i] = 0.f;
-      gemm<BF, MB, MB>(fW2t, mp, t, lane);
+      if constexpr (!BF && C::LDS_FRAG)
+        gemm_f32_tr<H>(reinterpret_cast<const float*>(fW2), mp, t, lane);
+      else
+        gemm<BF, MB, MB>(fW2t, mp, t, lane);
 #pragma unroll
       for (int i = 0; i < NF; ++i) t[i] *= (u[i] > 0.f ? 1.f : u[i] + 1.f);
       // g_e = gE + W1c^T gh
-      gemm<BF, MB, MB>(fW1ct, t, gE, lane);
+      if constexpr (!BF && C::LDS_FRAG)
+        gemm_f32_tr<H>(reinterpret_cast<const float*>(fW1c), t, gE, lane);
+      else
+        gemm<BF, MB, MB>(fW1ct, t, gE, lane);
       if (valid) {
         store_row<H>(a.g_e_in + k * H, g, gE);
         store_row_t<H, BF>(a.g_h, k, g, t);
@@ -737,7 +746,7 @@ hipError_t launch_edge_bwd_split(const EdgeBwdArgs& a, int grid, hipStream_t s) 
 
 template <int GW, int AW, bool BF>
 struct RowDwCfg {
-  static constexpr int NW = 8;
+  static constexpr int NW = BF ? 8 : 4;
   static constexpr int ROWS = 16 * NW;
   static constexpr size_t TG = tile_bytes<GW, BF, ROWS>(), TA = tile_bytes<AW, BF, ROWS>();
   // the column-sum scratch (FP32 path: 16 NW x GW floats) reuses the A tile
@@ -748,7 +757,8 @@ struct RowDwCfg {
 // dst[GW][AW] = sum over rows of G[r] (x) A[r], lock-step waves staging
 // 16-row blocks in LDS as the fused kernels do (same rounding of the
 // operands to BF16 on the BF16 path); column sums of G from the staged tile.
-template <int GW, int AW, bool BF, bool GBF, bool ABF>
+// A2: the A row is the concatenation [A[r], A2[r]] of two AW/2-wide rows.
+template <int GW, int AW, bool BF, bool GBF, bool ABF, bool A2>
 __global__ __launch_bounds__((64 * RowDwCfg<GW, AW, BF>::NW)) void k_row_dw(RowDwArgs a) {
   using C = RowDwCfg<GW, AW, BF>;
   constexpr int NW = C::NW, ROWS = C::ROWS, NT = dw_tiles_per_wave<GW, AW, NW>();
@@ -772,10 +782,18 @@ __global__ __launch_bounds__((64 * RowDwCfg<GW, AW, BF>::NW)) void k_row_dw(RowD
   const bool want_cs = a.colsum_off >= 0;
   // one block ahead
   float gn[GW / 4], an[AW / 4];
+  auto load_a = [&](int64_t row) {
+    if constexpr (A2) {  // the two halves land directly in an[0, AW/8) and an[AW/8, AW/4)
+      load_row_t<AW / 2, ABF>(a.A, row, g, *reinterpret_cast<float(*)[AW / 8]>(an));
+      load_row_t<AW / 2, ABF>(a.A2, row, g, *reinterpret_cast<float(*)[AW / 8]>(an + AW / 8));
+    } else {
+      load_row_t<AW, ABF>(a.A, row, g, an);
+    }
+  };
   {
     const int64_t row = std::min<int64_t>((b0 + wave) * 16 + j, n - 1);
     load_row_t<GW, GBF>(a.G, row, g, gn);
-    load_row_t<AW, ABF>(a.A, row, g, an);
+    load_a(row);
 #pragma unroll
     for (int i = 0; i < GW / 4; ++i) asm volatile("" : "+v"(gn[i]));
 #pragma unroll
@@ -785,23 +803,21 @@ __global__ __launch_bounds__((64 * RowDwCfg<GW, AW, BF>::NW)) void k_row_dw(RowD
     const int64_t bk = b0 + it * NW + wave;
     const int64_t row = bk * 16 + j;
     const bool valid = bk < b1 && row < n;
-    float gv[GW / 4], av[AW / 4];
+    // stage this block's rows, then reuse their registers for the next
+    // block's loads (their latency overlaps the barrier and the products)
 #pragma unroll
-    for (int i = 0; i < GW / 4; ++i) gv[i] = valid ? gn[i] : 0.f;
+    for (int i = 0; i < GW / 4; ++i) gn[i] = valid ? gn[i] : 0.f;
+    if constexpr (!BF) {
 #pragma unroll
-    for (int i = 0; i < AW / 4; ++i) av[i] = an[i];
+      for (int i = 0; i < GW / 4; ++i) csf[i] += gn[i];
+    }
+    stage_row<GW, BF, ROWS>(tG, srow, g, gn);
+    stage_row<AW, BF, ROWS>(tA, srow, g, an);
     {
       const int64_t bk2 = bk + NW, row2 = std::min<int64_t>(bk2 * 16 + j, n - 1);
       load_row_t<GW, GBF>(a.G, row2, g, gn);
-      load_row_t<AW, ABF>(a.A, row2, g, an);
+      load_a(row2);
     }
-    __builtin_amdgcn_sched_barrier(0);
-    if constexpr (!BF) {
-#pragma unroll
-      for (int i = 0; i < GW / 4; ++i) csf[i] += gv[i];
-    }
-    stage_row<GW, BF, ROWS>(tG, srow, g, gv);
-    stage_row<AW, BF, ROWS>(tA, srow, g, av);
     __syncthreads();
     dw_tiles<GW, AW, BF, NW>(tG, tA, acc, wave, lane);
     if constexpr (BF) {
@@ -820,31 +836,50 @@ __global__ __launch_bounds__((64 * RowDwCfg<GW, AW, BF>::NW)) void k_row_dw(RowD
   }
 }
 
-template <int GW, int AW, bool BF, bool GBF, bool ABF>
+template <int GW, int AW, bool BF, bool GBF, bool ABF, bool A2>
 static hipError_t launch_row_dw_t(const RowDwArgs& a, int grid, hipStream_t s) {
   using C = RowDwCfg<GW, AW, BF>;
-  (void)hipFuncSetAttribute((const void*)k_row_dw<GW, AW, BF, GBF, ABF>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)C::LDS);
-  hipLaunchKernelGGL((k_row_dw<GW, AW, BF, GBF, ABF>), dim3(grid), dim3(64 * C::NW), C::LDS, s, a);
+  (void)hipFuncSetAttribute((const void*)k_row_dw<GW, AW, BF, GBF, ABF, A2>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)C::LDS);
+  hipLaunchKernelGGL((k_row_dw<GW, AW, BF, GBF, ABF, A2>), dim3(grid), dim3(64 * C::NW), C::LDS, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_row_dw(const RowDwArgs& a, int grid, hipStream_t s) {
-  if (a.GW != 128 || a.AW != 128) return hipErrorInvalidValue;
-  // BF16 products take BF16 or FP32 operands; FP32 products FP32 operands
-  if (a.bf) {
-    if (a.g_bf && a.a_bf) return launch_row_dw_t<128, 128, true, true, true>(a, grid, s);
-    if (a.g_bf && !a.a_bf) return launch_row_dw_t<128, 128, true, true, false>(a, grid, s);
+  // forms in use: 128 x 128 (edge adjoint: G BF16/FP32, A BF16/FP32) and
+  // 128 x [128 | 128] (node update: A = [a*, x], FP32)
+  if (a.GW != 128) return hipErrorInvalidValue;
+  if (a.AW == 128 && !a.A2) {
+    // BF16 products take BF16 or FP32 operands; FP32 products FP32 operands
+    if (a.bf) {
+      if (a.g_bf && a.a_bf) return launch_row_dw_t<128, 128, true, true, true, false>(a, grid, s);
+      if (a.g_bf && !a.a_bf) return launch_row_dw_t<128, 128, true, true, false, false>(a, grid, s);
+      return hipErrorInvalidValue;
+    }
+    if (!a.g_bf && !a.a_bf) return launch_row_dw_t<128, 128, false, false, false, false>(a, grid, s);
     return hipErrorInvalidValue;
   }
-  if (!a.g_bf && !a.a_bf) return launch_row_dw_t<128, 128, false, false, false>(a, grid, s);
+  if (a.AW == 256 && a.A2 && !a.a_bf) {
+    if (a.bf && a.g_bf) return launch_row_dw_t<128, 256, true, true, false, true>(a, grid, s);
+    if (!a.bf && !a.g_bf) return launch_row_dw_t<128, 256, false, false, false, true>(a, grid, s);
+  }
   return hipErrorInvalidValue;
+}
+
+template <bool BF>
+__device__ __forceinline__ float4 load4(const void* __restrict__ p, int64_t off) {
+  if constexpr (BF) {
+    const v4bf b = __builtin_bit_cast(v4bf, *reinterpret_cast<const u32x2*>(reinterpret_cast<const __bf16*>(p) + off));
+    return make_float4((float)b[0], (float)b[1], (float)b[2], (float)b[3]);
+  } else {
+    return *reinterpret_cast<const float4*>(reinterpret_cast<const float*>(p) + off);
+  }
 }
 
 // Column sums of two [R][W] arrays: thread t sums feature group t % (W/4)
 // (4 features) over rows t / (W/4), + P, + 2P, ... of the workgroup's
 // range, then the row phases are added in order.
-template <int W, bool BF>
+template <int W, bool XBF, bool YBF>
 __global__ __launch_bounds__(256) void k_colsum2(int64_t n_rows, const void* __restrict__ X,
                                                  const void* __restrict__ Y, float* __restrict__ part,
                                                  int64_t slab, int64_t offx, int64_t offy) {
@@ -855,16 +890,7 @@ __global__ __launch_bounds__(256) void k_colsum2(int64_t n_rows, const void* __r
   const int64_t r0 = blockIdx.x * per, r1 = std::min(n_rows, r0 + per);
   float4 ax = make_float4(0.f, 0.f, 0.f, 0.f), ay = ax;
   for (int64_t r = r0 + ph; r < r1; r += P) {
-    float4 x, y;
-    if constexpr (BF) {
-      const v4bf bx = __builtin_bit_cast(v4bf, *reinterpret_cast<const u32x2*>(reinterpret_cast<const __bf16*>(X) + r * W + 4 * fg));
-      const v4bf by = __builtin_bit_cast(v4bf, *reinterpret_cast<const u32x2*>(reinterpret_cast<const __bf16*>(Y) + r * W + 4 * fg));
-      x = make_float4((float)bx[0], (float)bx[1], (float)bx[2], (float)bx[3]);
-      y = make_float4((float)by[0], (float)by[1], (float)by[2], (float)by[3]);
-    } else {
-      x = *reinterpret_cast<const float4*>(reinterpret_cast<const float*>(X) + r * W + 4 * fg);
-      y = *reinterpret_cast<const float4*>(reinterpret_cast<const float*>(Y) + r * W + 4 * fg);
-    }
+    const float4 x = load4<XBF>(X, r * W + 4 * fg), y = load4<YBF>(Y, r * W + 4 * fg);
     ax.x += x.x; ax.y += x.y; ax.z += x.z; ax.w += x.w;
     ay.x += y.x; ay.y += y.y; ay.z += y.z; ay.w += y.w;
   }
@@ -884,14 +910,17 @@ __global__ __launch_bounds__(256) void k_colsum2(int64_t n_rows, const void* __r
   }
 }
 
-hipError_t launch_colsum2(int64_t n_rows, int W, int bf, const void* X, const void* Y, float* part, int64_t slab,
-                          int64_t offx, int64_t offy, int grid, hipStream_t s) {
+hipError_t launch_colsum2(int64_t n_rows, int W, int x_bf, int y_bf, const void* X, const void* Y, float* part,
+                          int64_t slab, int64_t offx, int64_t offy, int grid, hipStream_t s) {
   if (W != 128) return hipErrorInvalidValue;
-  if (bf)
-    hipLaunchKernelGGL((k_colsum2<128, true>), dim3(grid), dim3(256), 0, s, n_rows, X, Y, part, slab, offx, offy);
-  else
-    hipLaunchKernelGGL((k_colsum2<128, false>), dim3(grid), dim3(256), 0, s, n_rows, X, Y, part, slab, offx, offy);
-  return hipGetLastError();
+#define MP_CS(XB, YB)                                                                                          \
+  if (!!x_bf == XB && !!y_bf == YB) {                                                                          \
+    hipLaunchKernelGGL((k_colsum2<128, XB, YB>), dim3(grid), dim3(256), 0, s, n_rows, X, Y, part, slab, offx, offy); \
+    return hipGetLastError();                                                                                  \
+  }
+  MP_CS(true, true) MP_CS(false, false) MP_CS(true, false)
+#undef MP_CS
+  return hipErrorInvalidValue;
 }
 
 // ------------------------------------------------- sender-side gradients
@@ -1478,6 +1507,155 @@ hipError_t launch_mlp_bwd(const MlpBwdArgs& a, int grid, hipStream_t s) {
   MP_CASE(32) MP_CASE(64) MP_CASE(128)
 #undef MP_CASE
   return hipErrorInvalidValue;
+}
+
+// ------------------------------------ split node-update adjoint (wide H)
+
+template <int H, bool BF>
+struct NodeBwdSplitCfg {
+  static constexpr int NW = 8;  // independent waves sharing the LDS weights
+  static constexpr size_t F0 = frag_bytes(H, 2 * H, BF), F1 = frag_bytes(H, H, BF);
+  static constexpr size_t VECS = 3 * H * sizeof(float);  // b0, b1, LayerNorm gain
+  static constexpr size_t LDS1 = F0 + 2 * F1 + VECS;     // pass 1: W0, W1, W1^T
+  static constexpr size_t LDS2 = F0;                      // pass 2: W0^T
+  static_assert(LDS1 <= kLdsLimit, "split node adjoint: weights must fit in LDS");
+};
+
+// Adjoint of the node update x' = x + LN(W1 ELU(W0 [a*, x] + b0) + b1)
+// without its weight gradients (the fused kernel's tiles, accumulators and
+// all four weight matrices do not fit at this width), in two passes whose
+// weights each fit in LDS.  Pass 1 writes per row the factors u, g_y
+// (dW1 = sum g_y u^T, db1), g_z (dW0 = sum g_z [a*, x]^T, db0) and
+// g_out * normalised y (dgamma; dbeta sums g_out itself).
+template <int H, bool BF>
+__global__ __launch_bounds__((64 * NodeBwdSplitCfg<H, BF>::NW)) void k_node_bwd_split(MlpBwdArgs a, void* u_out,
+                                                                                      void* gy_out, void* gz_out,
+                                                                                      void* goxh_out) {
+  using C = NodeBwdSplitCfg<H, BF>;
+  constexpr int NF = H / 4, MB = H / 16, KB = 2 * H / 16, NW = C::NW;
+  extern __shared__ uint4 smem[];
+  stage_frags(smem, a.frag0, C::F0);
+  stage_frags(smem + C::F0 / 16, a.frag1, C::F1);
+  stage_frags(smem + (C::F0 + C::F1) / 16, a.frag1t, C::F1);
+  const char* f0 = reinterpret_cast<const char*>(smem);
+  const char* f1 = f0 + C::F0;
+  const char* f1t = f1 + C::F1;
+  float* vecs = reinterpret_cast<float*>(reinterpret_cast<char*>(smem) + C::LDS1 - C::VECS);
+  for (int t = threadIdx.x; t < 3 * H; t += blockDim.x)
+    vecs[t] = t < H ? a.b0[t] : (t < 2 * H ? a.b1[t - H] : (a.ln ? a.lng[t - 2 * H] : 0.f));
+  __syncthreads();
+  const int lane = lane_id(), j = lane & 15, g = lane >> 4, wave = threadIdx.x / 64;
+  const int64_t n = a.n_rows, nblk = (n + 15) / 16;
+  for (int64_t blk = (int64_t)blockIdx.x * NW + wave; blk < nblk; blk += (int64_t)gridDim.x * NW) {
+    const int oz = opaque_zero();
+    const float* vb = vecs + oz;
+    const int64_t row = blk * 16 + j;
+    const bool valid = row < n;
+    const int64_t rr = valid ? row : n - 1;
+    float in[2 * NF], go[NF];
+    load_row<H>(a.src0 + rr * H, g, *reinterpret_cast<float(*)[NF]>(in));
+    load_row<H>(a.src1 + rr * H, g, *reinterpret_cast<float(*)[NF]>(in + NF));
+    load_row<H>(a.g_out + rr * H, g, go);
+    __builtin_amdgcn_sched_barrier(0);
+    if (!valid) {
+#pragma unroll
+      for (int i = 0; i < NF; ++i) go[i] = 0.f;
+    }
+    float u[NF];
+    load_vec<H>(vb, g, u);
+    gemm<BF, MB, KB>(f0 + oz, in, u, lane);
+#pragma unroll
+    for (int i = 0; i < NF; ++i) u[i] = elu(u[i]);
+    if (valid) store_row_t<H, BF>(u_out, row, g, u);
+    float y[NF];
+    load_vec<H>(vb + H, g, y);
+    gemm<BF, MB, MB>(f1 + oz, u, y, lane);
+    if (a.ln) {
+      float mean, rstd, s1 = 0.f, s2 = 0.f, gam[NF], t[NF];
+      ln_stats<H>(y, a.eps, mean, rstd);
+      load_vec<H>(vb + 2 * H, g, gam);
+#pragma unroll
+      for (int i = 0; i < NF; ++i) {
+        const float xh = (y[i] - mean) * rstd;
+        t[i] = go[i] * xh;
+        const float gx = go[i] * gam[i];
+        s1 += gx;
+        s2 += gx * xh;
+        y[i] = xh;
+      }
+      if (valid) store_row_t<H, BF>(goxh_out, row, g, t);
+      s1 = row_sum(s1) * (1.f / H);
+      s2 = row_sum(s2) * (1.f / H);
+#pragma unroll
+      for (int i = 0; i < NF; ++i) y[i] = rstd * (go[i] * gam[i] - s1 - y[i] * s2);
+    } else {
+#pragma unroll
+      for (int i = 0; i < NF; ++i) y[i] = go[i];
+    }
+    if (valid) store_row_t<H, BF>(gy_out, row, g, y);
+    float gu[NF];
+#pragma unroll
+    for (int i = 0; i < NF; ++i) gu[i] = 0.f;
+    gemm<BF, MB, MB>(f1t + oz, y, gu, lane);
+#pragma unroll
+    for (int i = 0; i < NF; ++i) gu[i] *= (u[i] > 0.f ? 1.f : u[i] + 1.f);
+    if (valid) store_row_t<H, BF>(gz_out, row, g, gu);
+  }
+}
+
+// Pass 2: [g_a*, g_x] = W0^T g_z, plus the residual path's gradient
+// (g_add1, normally g_out) on g_x.
+template <int H, bool BF>
+__global__ __launch_bounds__((64 * NodeBwdSplitCfg<H, BF>::NW)) void k_node_gin(MlpBwdArgs a, const void* gz) {
+  using C = NodeBwdSplitCfg<H, BF>;
+  constexpr int NF = H / 4, MB = H / 16, NW = C::NW;
+  extern __shared__ uint4 smem[];
+  stage_frags(smem, a.frag0t, C::F0);
+  const char* f0t = reinterpret_cast<const char*>(smem);
+  __syncthreads();
+  const int lane = lane_id(), j = lane & 15, g = lane >> 4, wave = threadIdx.x / 64;
+  const int64_t n = a.n_rows, nblk = (n + 15) / 16;
+  for (int64_t blk = (int64_t)blockIdx.x * NW + wave; blk < nblk; blk += (int64_t)gridDim.x * NW) {
+    const int oz = opaque_zero();
+    const int64_t row = blk * 16 + j;
+    const bool valid = row < n;
+    const int64_t rr = valid ? row : n - 1;
+    float gu[NF], gi[2 * NF];
+    load_row_t<H, BF>(gz, rr, g, gu);
+#pragma unroll
+    for (int i = 0; i < NF; ++i) gi[i] = 0.f;
+    if (a.g_add1) {
+      load_row<H>(a.g_add1 + rr * H, g, *reinterpret_cast<float(*)[NF]>(gi + NF));
+    } else {
+#pragma unroll
+      for (int i = 0; i < NF; ++i) gi[NF + i] = 0.f;
+    }
+    gemm<BF, 2 * MB, MB>(f0t + oz, gu, gi, lane);
+    if (valid) {
+      if (a.g_src0) store_row<H>(a.g_src0 + row * H, g, *reinterpret_cast<float(*)[NF]>(gi));
+      if (a.g_src1) store_row<H>(a.g_src1 + row * H, g, *reinterpret_cast<float(*)[NF]>(gi + NF));
+    }
+  }
+}
+
+template <int H, bool BF>
+static hipError_t launch_node_bwd_split_t(const MlpBwdArgs& a, void* u, void* gy, void* gz, void* goxh, int grid,
+                                          hipStream_t s) {
+  using C = NodeBwdSplitCfg<H, BF>;
+  (void)hipFuncSetAttribute((const void*)k_node_bwd_split<H, BF>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)C::LDS1);
+  hipLaunchKernelGGL((k_node_bwd_split<H, BF>), dim3(grid), dim3(64 * C::NW), C::LDS1, s, a, u, gy, gz, goxh);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  (void)hipFuncSetAttribute((const void*)k_node_gin<H, BF>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)C::LDS2);
+  hipLaunchKernelGGL((k_node_gin<H, BF>), dim3(grid), dim3(64 * C::NW), C::LDS2, s, a, (const void*)gz);
+  return hipGetLastError();
+}
+
+hipError_t launch_node_bwd_split(const MlpBwdArgs& a, void* u, void* gy, void* gz, void* goxh, int grid,
+                                 hipStream_t s) {
+  if (a.H != 128 || a.k0 != a.H || a.k1 != a.H || a.n_out != a.H || !a.bf) return hipErrorInvalidValue;
+  return launch_node_bwd_split_t<128, true>(a, u, gy, gz, goxh, grid, s);
 }
 
 // ------------------------------------------------------ slab reduction

@@ -123,6 +123,7 @@ struct LayerWs {
   LayerFrags fr;
   size_t P, Q, a, gP, gh, part_e, part_n, part_q, tile_r, tile_e, total;
   size_t sgm, su, sgE, sgEx;  // split edge adjoint: per-edge weight-gradient factors
+  size_t nu, ngy, ngz, ngx;   // split node adjoint: per-row weight-gradient factors
   int ge, gbe, gn, gbn;
   int64_t n_tiles;
   LayerWs(const mp_layer_cfg* c, const mp_dev_graph* g, bool bwd) : fr(c->H, c->gemm_dtype == MP_BF16) {
@@ -140,6 +141,7 @@ struct LayerWs {
     a = o; o = align_up(o + N * H * 4);
     gP = gh = part_e = part_n = part_q = 0;
     sgm = su = sgE = sgEx = 0;
+    nu = ngy = ngz = ngx = 0;
     if (bwd) {
       const size_t eb = E * H * (c->gemm_dtype == MP_BF16 ? 2 : 4);
       gP = o; o = align_up(o + N * H * 4);
@@ -149,6 +151,13 @@ struct LayerWs {
         su = o; o = align_up(o + eb);
         sgE = o; o = align_up(o + eb);
         sgEx = o; o = align_up(o + eb);
+      }
+      if (node_bwd_split(c->H, c->gemm_dtype == MP_BF16)) {
+        const size_t nb = N * H * 2;  // BF16
+        nu = o; o = align_up(o + nb);
+        ngy = o; o = align_up(o + nb);
+        ngz = o; o = align_up(o + nb);
+        ngx = o; o = align_up(o + nb);
       }
       part_e = o; o = align_up(o + (size_t)gbe * edge_slab(c->H) * 4);
       part_n = o; o = align_up(o + (size_t)gbn * mlp_slab(c->H, 2 * c->H, c->H) * 4);
@@ -428,7 +437,46 @@ extern "C" int mp_layer_backward(const mp_layer_cfg* cfg, const mp_layer_params*
   m.g_add1 = g_x_out;
   m.part = wsf(ws, W.part_n);
   m.slab = mlp_slab(H, 2 * H, H);
-  if ((rc = run("node_bwd", s, [&] { return launch_mlp_bwd(m, W.gbn, s); }))) return rc;
+  if (node_bwd_split(H, bf)) {
+    // wide layers: the adjoint writes per-row factors, then the weight
+    // gradients are summed from them into the fused kernel's slab layout
+    void* nu = ws_at(ws, W.nu);
+    void* ngy = ws_at(ws, W.ngy);
+    void* ngz = ws_at(ws, W.ngz);
+    void* ngx = ws_at(ws, W.ngx);
+    if ((rc = run("node_bwd", s, [&] { return launch_node_bwd_split(m, nu, ngy, ngz, ngx, W.gbn, s); }))) return rc;
+    const int64_t s1 = 2 * (int64_t)H * H + H;  // dW1 block of the slab
+    RowDwArgs rd{};
+    rd.n_rows = g->n_rows;
+    rd.GW = H;
+    rd.bf = 1;
+    rd.part = m.part;
+    rd.slab = m.slab;
+    rd.AW = H;  // dW1 = sum g_y u^T, db1 = sum g_y
+    rd.G = ngy;
+    rd.g_bf = 1;
+    rd.A = nu;
+    rd.a_bf = 1;
+    rd.off = s1;
+    rd.colsum_off = s1 + (int64_t)H * H;
+    if ((rc = run("node_dw", s, [&] { return launch_row_dw(rd, W.gbn, s); }))) return rc;
+    rd.AW = 2 * H;  // dW0 = sum g_z [a*, x]^T, db0 = sum g_z
+    rd.G = ngz;
+    rd.A = a_star;
+    rd.A2 = x_in;
+    rd.a_bf = 0;
+    rd.off = 0;
+    rd.colsum_off = 2 * (int64_t)H * H;
+    if ((rc = run("node_dw", s, [&] { return launch_row_dw(rd, W.gbn, s); }))) return rc;
+    if (cfg->layernorm &&
+        (rc = run("node_dw", s, [&] {
+           return launch_colsum2(g->n_rows, H, 1, 0, ngx, g_x_out, m.part, m.slab, s1 + (int64_t)H * H + H,
+                                 s1 + (int64_t)H * H + 2 * H, W.gbn, s);
+         })))
+      return rc;
+  } else if ((rc = run("node_bwd", s, [&] { return launch_mlp_bwd(m, W.gbn, s); }))) {
+    return rc;
+  }
   // the halo sum is symmetric: its adjoint is the same group sum
   if (cfg->halo && (rc = run("halo_adj", s, [&] { return launch_halo(H, d, ga, s); }))) return rc;
   EdgeBwdArgs eb{};
@@ -480,7 +528,7 @@ extern "C" int mp_layer_backward(const mp_layer_cfg* cfg, const mp_layer_params*
     if ((rc = run("edge_dw", s, [&] { return launch_row_dw(rd, W.gbe, s); }))) return rc;
     if (cfg->layernorm &&
         (rc = run("edge_dw", s, [&] {
-           return launch_colsum2(g->n_edges, H, bf, eb.gEx, eb.gE, eb.part, eb.slab, 2 * (int64_t)H * H + H,
+           return launch_colsum2(g->n_edges, H, bf, bf, eb.gEx, eb.gE, eb.part, eb.slab, 2 * (int64_t)H * H + H,
                                  2 * (int64_t)H * H + 2 * H, W.gbe, s);
          })))
       return rc;

@@ -114,6 +114,38 @@ __device__ __forceinline__ void gemm_f32(const float* __restrict__ frag, const f
   }
 }
 
+// acc += W^T in for a square H x H matrix W stored as FP32 fragments (the
+// layout gemm_f32 reads for W in).  Fragment element (mb, s, lane i + 16k)
+// holds W[16 mb + i][f(s, k)] with f(s, k) = 16 (s/4) + 4k + s%4, the
+// feature order of the row-block layout; W^T's element for step s, output
+// block mb' and lane (i, k) is W[f(s, k)][16 mb' + i], found at fragment
+// (s/4, 4 mb' + i%4, lane 4k + s%4 + 16 (i/4)).  One LDS read per MFMA as
+// in gemm_f32, so the transposed matrix need not be stored.
+template <int H>
+__device__ __forceinline__ void gemm_f32_tr(const float* __restrict__ frag, const float (&in)[H / 4],
+                                            float (&acc)[H / 4], int lane) {
+  constexpr int MB = H / 16, S = H / 4;
+  const int i = lane & 15, k = lane >> 4;
+  const int lane_off = (i & 3) * 64 + 4 * k + 16 * (i >> 2);
+  v4f c[MB];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb) c[mb] = v4f{acc[4 * mb], acc[4 * mb + 1], acc[4 * mb + 2], acc[4 * mb + 3]};
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+      c[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(frag[((s >> 2) * S + 4 * mb) * 64 + (s & 3) + lane_off], in[s],
+                                                   c[mb], 0, 0, 0);
+  }
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb) {
+    acc[4 * mb] = c[mb][0];
+    acc[4 * mb + 1] = c[mb][1];
+    acc[4 * mb + 2] = c[mb][2];
+    acc[4 * mb + 3] = c[mb][3];
+  }
+}
+
 __device__ __forceinline__ v8bf to_bf8(const float* x) {
   v8bf r;
 #pragma unroll

@@ -156,16 +156,17 @@ struct RowDwArgs {
   int GW, AW, bf;       // bf: staging and products in BF16
   const void* G;
   int g_bf;             // G stored as BF16
-  const void* A;
+  const void* A;        // [R][AW], or with A2: the first AW/2 columns
+  const void* A2;       // optional second half of A ([R][AW/2], same type)
   int a_bf;             // A stored as BF16
   float* part;
   int64_t slab, off, colsum_off;
 };
 hipError_t launch_row_dw(const RowDwArgs& a, int grid, hipStream_t s);
-// Column sums of X[R][W] and Y[R][W] (BF16 or FP32) into slab offsets
-// offx / offy per workgroup, rows split as in launch_row_dw.
-hipError_t launch_colsum2(int64_t n_rows, int W, int bf, const void* X, const void* Y, float* part, int64_t slab,
-                          int64_t offx, int64_t offy, int grid, hipStream_t s);
+// Column sums of X[R][W] and Y[R][W] (each BF16 or FP32: x_bf, y_bf) into
+// slab offsets offx / offy per workgroup, rows split as in launch_row_dw.
+hipError_t launch_colsum2(int64_t n_rows, int W, int x_bf, int y_bf, const void* X, const void* Y, float* part,
+                          int64_t slab, int64_t offx, int64_t offy, int grid, hipStream_t s);
 
 struct MlpBwdArgs {
   int64_t n_rows;
@@ -191,6 +192,10 @@ struct MlpBwdArgs {
   int64_t slab;
 };
 hipError_t launch_mlp_bwd(const MlpBwdArgs& a, int grid, hipStream_t s);
+// Whether the node update's adjoint (2H input) at width H uses the split
+// form: BF16 only (the FP32 weights of the split passes do not fit in LDS).
+constexpr bool node_bwd_split(int H, bool bf) { return H > 64 && bf; }
+hipError_t launch_node_bwd_split(const MlpBwdArgs& a, void* u, void* gy, void* gz, void* goxh, int grid, hipStream_t s);
 
 struct GqArgs {
   DevGraph g;

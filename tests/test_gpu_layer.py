@@ -168,13 +168,15 @@ def test_layer_forward_rcb(rcb):
 # ---------------------------------------------------- one-layer adjoint
 
 
-# H=128 runs the split adjoint (per-edge factors + separate weight-gradient
-# sums); the other widths the fused kernel.  no_ge: the last layer's case,
+# H=128 runs the split adjoints (per-edge / per-row factors + separate
+# weight-gradient sums; the node update's split form is BF16 only); the
+# other widths the fused kernels.  no_ge: the last layer's case,
 # no gradient at the edge output.
 @pytest.mark.parametrize("H,ln,R,gemm,no_ge", [(32, False, 8, "f32", False), (64, True, 8, "f32", False),
                                                (64, True, 1, "f32", False), (128, True, 8, "f32", False),
                                                (64, True, 8, "bf16", False), (128, True, 8, "bf16", False),
-                                               (128, False, 1, "f32", True), (64, True, 8, "bf16", True)])
+                                               (128, False, 1, "f32", True), (64, True, 8, "bf16", True),
+                                               (128, False, 8, "bf16", False)])
 def test_layer_backward(c0, H, ln, R, gemm, no_ge):
     from paper_2410_01657_amd.ops import layer_backward, layer_cfg, layer_forward
     inp, gs = c0
