@@ -1,0 +1,41 @@
+"""bench.py's command-line contract that holds without a GPU: more than one
+GPU is refused with a JSON message and exit status 2; the byte model and
+the recorded-traffic lookup behave as documented."""
+
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, cwd=ROOT, timeout=120)
+    assert p.returncode == 2
+    line = json.loads(p.stdout.strip().splitlines()[-1])
+    assert line["n_gpus"] == 2 and "one GPU" in line["error"]
+
+
+def test_edge_adjoint_byte_model():
+    sys.path.insert(0, ROOT)
+    from paper_2410_01657_amd.roofline import layer_kernels
+    N, E, H = 629856, 3538080, 64
+    w = layer_kernels(N, E, 98415, 196830, H, "bf16", 4)["edge_bwd"]
+    # e (4H) + 3/4 of the layers' g_e' (4H) + g_e (4H) + BF16 g_h (2H) + 9 index bytes per edge,
+    # P, Q, g_a read and g_P written per row
+    assert w.bytes == E * (4 * H + 3 * H + 4 * H + 2 * H + 9) + N * 16 * H
+    w32 = layer_kernels(N, E, 98415, 196830, H, "f32", 1)["edge_bwd"]
+    assert w32.bytes == E * (16 * H + 9) + N * 16 * H
+    assert w.flops == E * 12 * H * H
+
+
+def test_recorded_traffic_requires_matching_sources(tmp_path):
+    sys.path.insert(0, ROOT)
+    import bench
+    # a workload or kernel without a record gives None
+    assert bench.recorded_traffic("edge_bwd", "no-such-workload") is None
+    assert bench.recorded_traffic("gq", "C1") is None
+    sha = bench.sources_sha256("edge_bwd")
+    assert len(sha) == 64 and sha == bench.sources_sha256("edge_bwd")
