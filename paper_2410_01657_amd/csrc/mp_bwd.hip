@@ -5,13 +5,15 @@
 // gathers of receiver/sender features become in-row sums (the sender part
 // through the reverse-edge index, so no atomics are needed).
 //
-// Weight gradients are sums over all rows of outer products.  Each
-// workgroup of 4 waves walks its rows in lock step: every wave stages one
-// 16-row block of the two factors in LDS, then each wave accumulates its own
-// subset of 16x16 gradient tiles over the 64 staged rows with MFMA.  Each
-// workgroup writes one slab of partial gradients; launch_wreduce adds the
-// slabs in workgroup order.  Schedules are static, so the result is
-// bitwise reproducible.
+// Weight gradients are sums over all rows of outer products.  The NW waves
+// of a workgroup (4 or 8) walk their rows in lock step: every wave stages
+// one 16-row block of the two factors in LDS, transposed, then each wave
+// accumulates its own subset of 16x16 gradient tiles over the 16*NW staged
+// rows with MFMA.  Each workgroup writes one slab of partial gradients;
+// launch_wreduce adds the slabs in workgroup order.  Where the fused form
+// does not fit on chip (H = 128), a streaming kernel writes the per-row
+// factors and k_row_dw forms the same sums from them.  Schedules are
+// static, so every result is bitwise reproducible.
 #include <algorithm>
 #include <type_traits>
 
@@ -217,9 +219,9 @@ __device__ __forceinline__ void dw_store(const v4f (&acc)[dw_tiles_per_wave<GW, 
   }
 }
 
-// Sum a per-lane row-block vector over all 64 rows of the workgroup (16
-// lanes x 4 waves) in a fixed order and write the W sums to dst.  Uses
-// `scratch` (at least 64*W floats of LDS); contains barriers.
+// Sum a per-lane row-block vector over all 16*NW rows of the workgroup (16
+// lanes x NW waves) in a fixed order and write the W sums to dst.  Uses
+// `scratch` (at least 16*NW*W floats of LDS); contains barriers.
 template <int W, int NW = kWaves>
 __device__ __forceinline__ void block_sum_vec(const float (&v)[W / 4], float* __restrict__ scratch,
                                               float* __restrict__ dst, int wave, int lane) {
