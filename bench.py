@@ -247,19 +247,27 @@ def main():
 
     main_path = res["bf16"]
     value = E_global * spec.n_layers / (main_path["ms"] * 1e-3)
+
+    def dominant_roofline(gemm):
+        """Roofline of the path's longest-running kernel: algorithmic bytes
+        (or flops) per launch / its average launch time, against the peak
+        of whichever roof bounds that kernel."""
+        work = layer_kernels(N, E, G, M, spec.H, gemm, spec.n_layers)
+        kern = res[gemm]["kernels"]
+        dom = max((k for k in kern if k in work), key=lambda k: kern[k]["ms_total"])
+        w = work[dom]
+        avg_s = kern[dom]["ms_avg"] * 1e-3
+        if bound_of(w, gemm) == "hbm":
+            r = {"bound": "hbm", "achieved": w.bytes / avg_s / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s"}
+        else:
+            r = {"bound": "mfma", "achieved": w.flops / avg_s / 1e12, "peak": PEAK[gemm] / 1e12,
+                 "unit": "TFLOP/s"}
+        r["frac"] = r["achieved"] / r["peak"]
+        return dom, w, r
+
     # dominant kernel of the main path and its roofline
-    work = layer_kernels(N, E, G, M, spec.H, "bf16", spec.n_layers)
+    dom, w, roof = dominant_roofline("bf16")
     kern = main_path["kernels"]
-    dom = max((k for k in kern if k in work), key=lambda k: kern[k]["ms_total"])
-    w = work[dom]
-    bnd = bound_of(w, "bf16")
-    avg_s = kern[dom]["ms_avg"] * 1e-3
-    if bnd == "hbm":
-        roof = {"bound": "hbm", "achieved": w.bytes / avg_s / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s"}
-    else:
-        roof = {"bound": "mfma", "achieved": w.flops / avg_s / 1e12, "peak": PEAK["bf16"] / 1e12,
-                "unit": "TFLOP/s"}
-    roof["frac"] = roof["achieved"] / roof["peak"]
     tr = recorded_traffic(dom, a.workload)
     roof["traffic"] = tr / 1e9 if tr is not None else None  # GB per launch, measured
     roof["kernel"] = dom
@@ -286,8 +294,10 @@ def main():
         "roofline": roof,
     }
     if "f32" in res:
+        dom32, w32, roof32 = dominant_roofline("f32")
+        roof32.update({"kernel": dom32, "ms_avg": res["f32"]["kernels"][dom32]["ms_avg"]})
         line["fp32"] = {"value": E_global * spec.n_layers / (res["f32"]["ms"] * 1e-3),
-                        "ms_per_step": res["f32"]["ms"]}
+                        "ms_per_step": res["f32"]["ms"], "roofline": roof32}
         line["bf16_over_fp32"] = res["f32"]["ms"] / main_path["ms"]
     line["kernels"] = {g: {k: round(v["ms_total"], 4) for k, v in res[g]["kernels"].items()} for g in res}
     if not a.no_cpu_baseline:
