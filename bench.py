@@ -55,6 +55,27 @@ def _parse():
     return ap.parse_args()
 
 
+def copy_bandwidth(gib=2, reps=10):
+    """Achievable HBM bandwidth for context: a device-to-device copy of
+    `gib` GiB, timed with HIP events over `reps` copies (read + write bytes
+    / time).  Runs before the timed steps, outside them."""
+    import torch
+    n = gib * (1 << 30) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    t1.record()
+    torch.cuda.synchronize()
+    gbps = 2 * n * 4 * reps / (t0.elapsed_time(t1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbps
+
+
 def copy_calibration():
     """A plain copy of a known size: FETCH_SIZE / WRITE_SIZE of this dispatch
     calibrate the counters against 256 MiB read and 256 MiB written."""
@@ -234,6 +255,7 @@ def main():
     order = np.argsort(hg.row_gid, kind="stable")
     sample_rows = order[np.searchsorted(hg.row_gid[order], sample_gids)]
 
+    copy_gbps = copy_bandwidth()
     paths = ["bf16"] + ([] if a.no_fp32 else ["f32"])
     res, outs, scheds = {}, {}, {}
     for gemm in paths:
@@ -274,6 +296,10 @@ def main():
     roof["ms_avg"] = kern[dom]["ms_avg"]
     roof["algorithmic_GB"] = w.bytes / 1e9
     roof["traffic_unit"] = "GB per launch (HBM read + write)"
+    # context: the same kernel against the bandwidth a plain 2 GiB copy reaches
+    if roof["bound"] == "hbm":
+        roof["copy_GBps"] = copy_gbps
+        roof["frac_of_copy"] = roof["achieved"] / copy_gbps
 
     line = {
         "metric": "MP-layer fwd+bwd edges/sec, BF16-MFMA vs FP32, at stated rel. error vs FP64",
