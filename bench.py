@@ -6,9 +6,11 @@ sub-graphs with halos (629,856 rows, 3,538,080 sub-graph edges), an
 encode-process-decode model with 4 consistent NMP layers, hidden width 64,
 LayerNorm, and the consistent MSE (Eq. 6) against the field shifted by one
 node.  Seeded synthetic Taylor-Green-like input, Xavier-uniform weights.
-`--workload C3` (24^3 elements, H=128, one graph) and `--workload C4`
-(32^3 elements of order 7, 64 uneven sub-graphs) measure the other
-fwd+bwd workloads the same way.
+`--workload C3` (24^3 elements, H=128, one graph), `--workload C4`
+(32^3 elements of order 7, 64 uneven sub-graphs) and `--workload T2R8`
+(the periodic 16 x 16 x 128-element p=5 box in the 8 slabs of Table II's
+R=8 row, 518,400 rows each) measure the other fwd+bwd workloads the same
+way.
 
 One step = the whole model forward, loss and backward (every layer's edge
 update, aggregation, halo sum, node update and their adjoints, plus the
@@ -36,7 +38,25 @@ WORKLOADS = {
     "C4": {"desc": "C4 mesh fwd+bwd: 32^3 elements P=7 (11390625 nodes, 68040000 edges), "
                    "64 uneven sub-graphs (seeded bisection) with halos, 4 layers, H=64, LayerNorm, "
                    "consistent MSE", "R": None},
+    "T2R8": {"desc": "Table II R=8 partition fwd+bwd: 16x16x128 elements P=5, periodic in x, y, z "
+                     "(4096000 nodes, 24576000 edges), 8 z-slabs of 518400 rows with halos, 4 layers, "
+                     "H=64, LayerNorm, consistent MSE", "R": None},
 }
+
+
+def _progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def global_edges(mesh):
+    """Directed edges of the unpartitioned lattice graph (links along each
+    axis; a periodic axis closes every line into a ring)."""
+    n = mesh.npts
+    total = 0
+    for a in range(3):
+        links = n[a] if mesh.periodic[a] else n[a] - 1
+        total += links * n[(a + 1) % 3] * n[(a + 2) % 3]
+    return 2 * total
 
 
 def _parse():
@@ -189,9 +209,14 @@ def cpu_baseline(cfg, inp, n_layers, sample_gids, outs, min_seconds=10.0):
     from oracle.graph import partition_graph
     from oracle.nmp import consistent_loss, edge_inputs, model_bwd, model_fwd
 
-    part = (inp.elem_part if inp.elem_part.max() > 0 else
-            slab_partition(cfg.nel, 16 if cfg.nel[2] % 16 == 0 else 8))
     mesh = inp.mesh
+    n_parts = int(inp.elem_part.max()) + 1
+    if n_parts > 1 and mesh.n_gid / n_parts <= 200_000:
+        part = inp.elem_part
+    elif n_parts > 1:          # large sub-graphs: one-element-thick z-slabs
+        part = slab_partition(cfg.nel, cfg.nel[2])
+    else:
+        part = slab_partition(cfg.nel, 16 if cfg.nel[2] % 16 == 0 else 8)
     rows = edges = 0
     dt = 0.0
     parts = 0
@@ -200,7 +225,7 @@ def cpu_baseline(cfg, inp, n_layers, sample_gids, outs, min_seconds=10.0):
         (G,), _ = partition_graph(mesh.elem_gid[keep], mesh.P, np.zeros(int(keep.sum()), np.int32), 1)
         X = inp.field.astype(np.float64)[G.gid]
         T = inp.target.astype(np.float64)[G.gid]
-        E0 = edge_inputs(G, mesh.pos)
+        E0 = edge_inputs(G, mesh.pos, mesh.period)
         t = time.perf_counter()
         Y, cache = model_fwd(inp.params, cfg.spec, [G], {}, [X], [E0])
         L, gY, _ = consistent_loss(Y, [T], [G])
@@ -246,8 +271,8 @@ def main():
     inp = make_inputs(cfg, base_seed=a.seed, R=R)
     prob = Problem(inp.mesh, inp.field, inp.target, inp.elem_part, R, "cuda")
     hg = prob.dg.host
-    n = inp.mesh.npts[0]
-    E_global = 6 * n * n * (n - 1)
+    _progress(f"graph built: {hg.n_rows} rows, {hg.n_edges} edges, {hg.R} sub-graphs")
+    E_global = global_edges(inp.mesh)
     N, E, G, M = hg.n_rows, hg.n_edges, hg.n_groups, int(hg.member.shape[0])
 
     rng = np.random.default_rng(a.seed + 1)
@@ -261,7 +286,9 @@ def main():
     for gemm in paths:
         sched = None if a.no_autotune else tuned_schedule(prob.dg, spec.H, spec.layernorm, gemm)
         scheds[gemm] = sched
+        _progress(f"{gemm}: schedule {sched}")
         ms, kern, Y, loss = run_path(gemm, spec, inp.params, prob, a.steps, a.warmup, sched)
+        _progress(f"{gemm}: {ms:.3f} ms/step")
         res[gemm] = {"ms": ms, "kernels": kern, "loss": loss}
         outs[gemm] = Y.cpu().numpy()[sample_rows].astype(np.float64)
         del Y
@@ -327,6 +354,7 @@ def main():
         line["bf16_over_fp32"] = res["f32"]["ms"] / main_path["ms"]
     line["kernels"] = {g: {k: round(v["ms_total"], 4) for k, v in res[g]["kernels"].items()} for g in res}
     if not a.no_cpu_baseline:
+        _progress("timing the FP64 oracle on a bounded sample")
         base, errs = cpu_baseline(cfg, inp, spec.n_layers, sample_gids, outs)
         line["cpu_baseline"] = base
         line["rel_error_vs_fp64"] = errs

@@ -239,10 +239,15 @@ int mp_mlp_backward(const mp_mlp_cfg* cfg, const mp_mlp_params* p, int64_t n_row
                     mp_stream_t stream);
 
 /* Edge input features of Sec. III: e0[k] = (p_j - p_i, |p_j - p_i|) for
- * edge k with receiver i and sender j; row_pos[N][3] in FP64, the
- * difference taken in FP64 and rounded once to FP32.  e0 is [E][4]. */
-int mp_edge_inputs(const mp_dev_graph* g, const double* row_pos, float* e0,
-                   mp_stream_t stream);
+ * edge k with receiver i and sender j; row_pos[N][3] in FP64 (device), the
+ * difference taken in FP64 and rounded once to FP32.  e0 is [E][4] (device).
+ * period (host, 3 doubles, or NULL for none): on an axis with period L > 0
+ * the difference is taken to the nearest periodic image of p_j, so a link
+ * across a periodic boundary gets its element-local difference.  Errors:
+ * MP_EINVAL for NULL or unaligned buffers or a negative or non-finite
+ * period. */
+int mp_edge_inputs(const mp_dev_graph* g, const double* row_pos, const double* period,
+                   float* e0, mp_stream_t stream);
 
 /* Consistent MSE (Eq. 6a-c): loss = sum_i sum_f (1/d_i)(Y-T)^2 / (N_eff F)
  * with N_eff = sum_i 1/d_i, over all rows of all sub-graphs; for R=1

@@ -8,6 +8,9 @@ C3  fwd+bwd: 24^3 elements, P=5, H=128, 4 layers, LayerNorm, MSE against the
              field shifted one node in x; R=1 (R=8 blocks for gradient checks).
 C4  batched: 32^3 elements, P=7, H=64, 4 layers, LayerNorm; 64 uneven
              sub-graphs from a seeded recursive coordinate bisection.
+T2R8 the partition of Table II's R = 8 row: 16 x 16 x 128 elements, P=5,
+             periodic on all three axes, 8 z-slabs of 518,400 rows each;
+             C1's model (H=64, 4 layers, LayerNorm), target shifted in x.
 """
 
 from dataclasses import dataclass, field as dc_field
@@ -32,6 +35,7 @@ class Config:
     noise: float = 0.0
     gemm: str = "f32"        # "f32" or "bf16"
     backward: bool = False
+    periodic: tuple = (False, False, False)
 
 
 CONFIGS = {
@@ -45,6 +49,8 @@ CONFIGS = {
                  "blocks", 8, blocks=(2, 2, 2), backward=True),
     "C4": Config("C4", (32, 32, 32), 7, ModelSpec(H=64, n_layers=4, layernorm=True),
                  "rcb", 64, gemm="bf16", backward=True),
+    "T2R8": Config("T2R8", (16, 16, 128), 5, ModelSpec(H=64, n_layers=4, layernorm=True),
+                   "slabs", 8, gemm="bf16", backward=True, periodic=(True, True, True)),
 }
 
 
@@ -85,7 +91,7 @@ class Inputs:
 
 def make_inputs(cfg, base_seed=0, R=None, perturb=False, spec=None):
     seeds = seeds_for(base_seed)
-    mesh = box_mesh(cfg.nel, cfg.P)
+    mesh = box_mesh(cfg.nel, cfg.P, cfg.periodic)
     field = velocity_field(mesh.pos, seeds["field"], noise_sigma=cfg.noise)
     target = shifted_target(field, mesh.npts)
     params = init_params(spec or cfg.spec, seeds["weights"], perturb=perturb)

@@ -70,7 +70,7 @@ class BoxMesh:
     periodic: tuple       # per-axis periodicity
     npts: tuple           # distinct lattice points per axis
     elem_gid: np.ndarray  # [n_elem, (P+1)^3] int64 global node ids
-    pos: np.ndarray       # [n_gid, 3] float64 positions (None when periodic)
+    pos: np.ndarray       # [n_gid, 3] float64 positions in [0, 1)^3 (None if not asked for)
 
     @property
     def n_elem(self):
@@ -83,6 +83,11 @@ class BoxMesh:
     @property
     def n_gid(self):
         return int(np.prod(self.npts))
+
+    @property
+    def period(self):
+        """Per-axis period of the positions (1.0 on periodic axes, else 0)."""
+        return tuple(1.0 if p else 0.0 for p in self.periodic)
 
 
 def axis_coords(nel, P):
@@ -124,8 +129,9 @@ def box_mesh(nel, P, periodic=(False, False, False), with_positions=True):
         K %= npts[2]
     gid = (I + npts[0] * (J + npts[1] * K.astype(np.int64))).astype(np.int64)
     pos = None
-    if with_positions and not any(periodic):
-        cx, cy, cz = (axis_coords(nel[i], P) for i in range(3))
+    if with_positions:
+        # a periodic axis has nel*P distinct points: the last one is the first
+        cx, cy, cz = (axis_coords(nel[i], P)[:npts[i]] for i in range(3))
         n = npts[0] * npts[1] * npts[2]
         g = np.arange(n, dtype=np.int64)
         pos = np.empty((n, 3))

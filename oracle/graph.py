@@ -80,14 +80,17 @@ def element_links(P):
     return np.array(pairs, dtype=np.int64)
 
 
-def partition_graph(elem_gid, P, elem_part, R):
+def partition_graph(elem_gid, P, elem_part, R, links=None):
     """Reduced sub-graphs, degrees and halo copies for an element partition.
+
+    ``links`` lists the element-local point pairs joined by a link; by
+    default those of a hexahedral element of order P.
 
     Returns ``(graphs, copies)`` where ``graphs[r]`` is the SubGraph of
     sub-graph r and ``copies`` maps each global id held by two or more
     sub-graphs to its list of (r, row) copies, in ascending r.
     """
-    links = element_links(P)
+    links = element_links(P) if links is None else np.asarray(links, np.int64)
     n_gid = int(elem_gid.max()) + 1
     und = []      # per sub-graph: unique undirected keys lo*n_gid + hi
     rows = []

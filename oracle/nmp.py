@@ -105,9 +105,16 @@ def _acc(grads, name, v):
 # --------------------------------------------------------------------------
 
 
-def edge_inputs(graph, pos):
-    """Four edge input channels (p_j - p_i, |p_j - p_i|) per directed edge."""
+def edge_inputs(graph, pos, period=None):
+    """Four edge input channels (p_j - p_i, |p_j - p_i|) per directed edge.
+
+    On a periodic axis of length L > 0 the difference is that of the nearest
+    periodic image of p_j (the element-local difference; a link never spans
+    half a period)."""
     dp = pos[graph.gid[graph.send]] - pos[graph.gid[graph.recv]]
+    for ax, L in enumerate(period or ()):
+        if L > 0:
+            dp[:, ax] -= L * np.round(dp[:, ax] / L)
     return np.concatenate([dp, np.linalg.norm(dp, axis=1, keepdims=True)], axis=1)
 
 

@@ -22,16 +22,19 @@ class Problem:
 
 
 def build_problem(mesh, field, target, elem_part=None, R=1, unpartitioned_from_lattice=True):
-    """R=1 uses the lattice definition of the graph; R>1 the element route."""
-    if R == 1 and unpartitioned_from_lattice:
+    """R=1 on a box mesh uses the lattice definition of the graph; otherwise
+    the element route (with the mesh's own links where it has them)."""
+    links = getattr(mesh, "links", None)
+    period = getattr(mesh, "period", None)
+    if R == 1 and unpartitioned_from_lattice and links is None and not any(period or ()):
         graphs, copies = [lattice_graph(mesh.npts)], {}
     else:
         part = np.zeros(mesh.n_elem, np.int32) if elem_part is None else elem_part
-        graphs, copies = partition_graph(mesh.elem_gid, mesh.P, part, R)
+        graphs, copies = partition_graph(mesh.elem_gid, mesh.P, part, R, links)
     pairs = halo_lists(graphs, copies)
     f = np.asarray(field, np.float64)
     t = np.asarray(target, np.float64)
     X = [f[G.gid] for G in graphs]
     T = [t[G.gid] for G in graphs]
-    E0 = [edge_inputs(G, mesh.pos) for G in graphs]
+    E0 = [edge_inputs(G, mesh.pos, period) for G in graphs]
     return Problem(graphs, copies, pairs, X, E0, T)

@@ -79,7 +79,7 @@ _SIGS = {
     "mp_mlp_forward": (c_i32, [P(MpMlpCfg), P(MpMlpParams), c_i64, vp, vp, vp, C.c_size_t, vp]),
     "mp_mlp_backward": (c_i32, [P(MpMlpCfg), P(MpMlpParams), c_i64, vp, vp, vp, P(MpMlpGrads), vp,
                                 C.c_size_t, vp]),
-    "mp_edge_inputs": (c_i32, [P(MpDevGraph), vp, vp, vp]),
+    "mp_edge_inputs": (c_i32, [P(MpDevGraph), vp, vp, vp, vp]),
     "mp_consistent_mse_workspace_size": (c_i32, [c_i64, P(C.c_size_t)]),
     "mp_consistent_mse": (c_i32, [c_i64, c_i32, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]),
     "mp_profile_enable": (c_i32, [c_i32]),

@@ -1,5 +1,6 @@
 // C ABI entry points: validation, workspace layout and launch sequences.
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -743,12 +744,19 @@ extern "C" int mp_mlp_backward(const mp_mlp_cfg* cfg, const mp_mlp_params* p, in
 
 // ------------------------------------------------------- edge inputs, loss
 
-extern "C" int mp_edge_inputs(const mp_dev_graph* g, const double* row_pos, float* e0, mp_stream_t stream) {
+extern "C" int mp_edge_inputs(const mp_dev_graph* g, const double* row_pos, const double* period, float* e0,
+                              mp_stream_t stream) {
   int rc;
   if ((rc = check_graph(g, false))) return rc;
   if (!row_pos || !e0 || !aligned16(e0)) return mp_fail(MP_EINVAL, "mp_edge_inputs: NULL or unaligned buffer");
+  double L[3] = {0.0, 0.0, 0.0};
+  for (int a = 0; period && a < 3; ++a) {
+    if (!(period[a] >= 0.0) || std::isinf(period[a]))
+      return mp_fail(MP_EINVAL, "mp_edge_inputs: period[%d] must be finite and >= 0", a);
+    L[a] = period[a];
+  }
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  return run("edge_inputs", s, [&] { return launch_edge_inputs(dev_graph(g), row_pos, e0, s); });
+  return run("edge_inputs", s, [&] { return launch_edge_inputs(dev_graph(g), row_pos, L, e0, s); });
 }
 
 static int loss_parts(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(256, (n + 4095) / 4096)); }

@@ -547,24 +547,29 @@ hipError_t launch_mlp_fwd(const MlpFwdArgs& a, int grid, hipStream_t s) {
 // ----------------------------------------------------------- edge inputs
 
 // Edge features of Sec. III: (p_j - p_i, |p_j - p_i|) with i the receiver
-// and j the sender, differences in FP64, rounded once to FP32.
+// and j the sender, differences in FP64, rounded once to FP32.  On an axis
+// with period L > 0 the difference is taken to the nearest image of p_j.
+__device__ inline double nearest_image(double d, double L) { return L > 0.0 ? d - L * rint(d / L) : d; }
+
 __global__ __launch_bounds__(256) void k_edge_inputs(int64_t n_edges, const int32_t* __restrict__ recv,
                                                      const int32_t* __restrict__ col, const double* __restrict__ pos,
-                                                     float* __restrict__ e0) {
+                                                     double Lx, double Ly, double Lz, float* __restrict__ e0) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n_edges) return;
   const int64_t i = recv[k], jj = col[k];
-  const double dx = pos[3 * jj] - pos[3 * i];
-  const double dy = pos[3 * jj + 1] - pos[3 * i + 1];
-  const double dz = pos[3 * jj + 2] - pos[3 * i + 2];
+  const double dx = nearest_image(pos[3 * jj] - pos[3 * i], Lx);
+  const double dy = nearest_image(pos[3 * jj + 1] - pos[3 * i + 1], Ly);
+  const double dz = nearest_image(pos[3 * jj + 2] - pos[3 * i + 2], Lz);
   const double r = sqrt(dx * dx + dy * dy + dz * dz);
   *reinterpret_cast<float4*>(e0 + 4 * k) = make_float4((float)dx, (float)dy, (float)dz, (float)r);
 }
 
-hipError_t launch_edge_inputs(const DevGraph& g, const double* pos, float* e0, hipStream_t s) {
+hipError_t launch_edge_inputs(const DevGraph& g, const double* pos, const double period[3], float* e0,
+                              hipStream_t s) {
   if (g.n_edges == 0) return hipSuccess;
   const int grid = (int)((g.n_edges + 255) / 256);
-  hipLaunchKernelGGL(k_edge_inputs, dim3(grid), dim3(256), 0, s, g.n_edges, g.recv, g.col, pos, e0);
+  hipLaunchKernelGGL(k_edge_inputs, dim3(grid), dim3(256), 0, s, g.n_edges, g.recv, g.col, pos, period[0],
+                     period[1], period[2], e0);
   return hipGetLastError();
 }
 

@@ -81,7 +81,8 @@ struct MlpFwdArgs {
 };
 hipError_t launch_mlp_fwd(const MlpFwdArgs& a, int grid, hipStream_t s);
 
-hipError_t launch_edge_inputs(const DevGraph& g, const double* pos, float* e0, hipStream_t s);
+hipError_t launch_edge_inputs(const DevGraph& g, const double* pos, const double period[3], float* e0,
+                              hipStream_t s);
 
 hipError_t launch_loss(int64_t n_rows, int F, const float* Y, const float* T, const uint8_t* mult,
                        double* part, int n_part, float* loss, float* gY, hipStream_t s);

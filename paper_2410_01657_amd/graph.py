@@ -62,11 +62,14 @@ def hex_links(P):
     return links
 
 
-def build_graph(elem_gid, P, elem_part, R):
-    """Reduced sub-graphs, CSR arrays, degrees and halo plan of a partition."""
+def build_graph(elem_gid, P, elem_part, R, links=None):
+    """Reduced sub-graphs, CSR arrays, degrees and halo plan of a partition.
+
+    ``links`` ([n_links, 2] element-local point pairs) defaults to the links
+    of a hexahedral element of order P; any element type may pass its own."""
     eg = np.ascontiguousarray(elem_gid, dtype=np.int64)
     part = np.ascontiguousarray(elem_part, dtype=np.int32)
-    links = hex_links(P)
+    links = hex_links(P) if links is None else np.ascontiguousarray(links, dtype=np.int32)
     g = C.c_void_p()
     call("graph_partition", eg.shape[0], eg.shape[1], _ptr(eg), links.shape[0], _ptr(links),
          _ptr(part), R, C.byref(g))

@@ -95,9 +95,9 @@ class Problem:
     """Device graph, node inputs, edge inputs and target for one workload."""
 
     def __init__(self, mesh, field, target, elem_part, R, device="cuda"):
-        self.host = build_graph(mesh.elem_gid, mesh.P, elem_part, R)
+        self.host = build_graph(mesh.elem_gid, mesh.P, elem_part, R, getattr(mesh, "links", None))
         self.dg = DeviceGraph(self.host, device)
         self.X = self.dg.rows_of(field).float().contiguous()
         self.T = self.dg.rows_of(target).float().contiguous()
         self.pos = self.dg.rows_of(mesh.pos).double().contiguous()
-        self.E0 = edge_inputs(self.dg, self.pos)
+        self.E0 = edge_inputs(self.dg, self.pos, getattr(mesh, "period", None))

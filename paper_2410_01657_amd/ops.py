@@ -184,13 +184,18 @@ class MLPFn(torch.autograd.Function):
 
 # ----------------------------------------------------------- inputs, loss
 
-def edge_inputs(dg, row_pos):
-    """(p_j - p_i, |p_j - p_i|) per edge from FP64 row positions [N, 3]."""
+def edge_inputs(dg, row_pos, period=None):
+    """(p_j - p_i, |p_j - p_i|) per edge from FP64 row positions [N, 3];
+    ``period`` (3 floats, 0 = not periodic) takes differences to the nearest
+    periodic image."""
     _check(row_pos)
     if row_pos.dtype != torch.float64:
         raise ValueError("row positions must be float64")
     e0 = torch.empty((dg.n_edges, 4), dtype=torch.float32, device=row_pos.device)
-    call("mp_edge_inputs", C.byref(dg.desc), _p(row_pos), _p(e0), _stream())
+    L = None
+    if period is not None and any(period):
+        L = (C.c_double * 3)(*[float(v) for v in period])
+    call("mp_edge_inputs", C.byref(dg.desc), _p(row_pos), L, _p(e0), _stream())
     return e0
 
 

@@ -446,3 +446,67 @@ def test_ball_gradient_matches_full_graph():
     _, g_ball = ball_grad(params, spec, m, field, c, w)
     for k in g_full:
         np.testing.assert_allclose(g_ball[k], g_full[k], rtol=0, atol=1e-13)
+
+
+# ------------------------------------------- periodic boxes (Table II meshes)
+
+
+@pytest.fixture(scope="module")
+def periodic_ref():
+    """A periodic 4 x 4 x 8-element P=3 box (12 x 12 x 24 points)."""
+    spec = ModelSpec(H=6, n_layers=2, layernorm=True)
+    m = box_mesh((4, 4, 8), 3, periodic=(True, True, True))
+    field = velocity_field(m.pos, 5, noise_sigma=0.02)
+    params = init_params(spec, 6, perturb=True)
+    prob = build_problem(m, field, field, None, 1)
+    Y, _ = model_fwd(params, spec, prob.graphs, {}, prob.X, prob.E0)
+    return spec, m, field, params, prob, Y[0]
+
+
+def test_periodic_edge_inputs_are_element_local(periodic_ref):
+    """Every link's difference is that of two neighbouring GLL points of one
+    element: at most the widest GLL gap, wrap links included."""
+    _, m, _, _, prob, _ = periodic_ref
+    E0 = prob.E0[0]
+    G = prob.graphs[0]
+    assert G.e == 6 * m.n_gid                          # every line closes into a ring
+    gap = np.max(np.diff(gll_points(3))) / 2 / 4       # widest gap on a 1/4 element
+    gap_z = np.max(np.diff(gll_points(3))) / 2 / 8
+    assert np.all(E0[:, 3] <= gap + 1e-15)
+    assert np.all(E0[:, 3] >= gap_z * 0.5 - 1e-15)
+    np.testing.assert_allclose(np.linalg.norm(E0[:, :3], axis=1), E0[:, 3], rtol=1e-15)
+
+
+def test_periodic_shift_invariance(periodic_ref):
+    """Shifting the input by one element along each periodic axis shifts the
+    output the same way (the wrap links see the same differences)."""
+    spec, m, field, params, prob, Y1 = periodic_ref
+    n = m.npts
+    g = np.arange(m.n_gid)
+    I, J, K = g % n[0], (g // n[0]) % n[1], g // (n[0] * n[1])
+    for dI, dJ, dK in ((3, 0, 0), (0, 3, 0), (0, 0, 3)):
+        src = (I + dI) % n[0] + n[0] * ((J + dJ) % n[1] + n[1] * ((K + dK) % n[2]))
+        p2 = build_problem(m, field[src], field[src], None, 1)
+        Y, _ = model_fwd(params, spec, p2.graphs, {}, p2.X, p2.E0)
+        assert normwise(Y[0], Y1[src]) <= 1e-12
+
+
+def test_periodic_consistency_slabs(periodic_ref):
+    """Eq. 2 on 8 periodic z-slabs: the first and last slab share nodes
+    through the wrap, so every slab has two neighbours."""
+    spec, m, field, params, _, Y1 = periodic_ref
+    part = slab_partition(m.nel, 8)
+    prob = build_problem(m, field, field, part, 8)
+    _, halo, nbrs = table2_stats(prob.graphs, prob.copies)
+    assert list(nbrs) == [2] * 8 and list(halo) == [2 * 12 * 12] * 8
+    Y, _ = model_fwd(params, spec, prob.graphs, prob.pair_lists, prob.X, prob.E0)
+    err = max(np.abs(Y[r] - Y1[G.gid]).max() for r, G in enumerate(prob.graphs))
+    assert err / np.abs(Y1).max() <= 1e-12
+
+
+def test_periodic_ball_matches_full_graph(periodic_ref):
+    spec, m, field, params, _, Y1 = periodic_ref
+    n = m.npts
+    for c in (0, n[0] - 1, m.n_gid - 1, n[0] * n[1] * (n[2] - 1) + 5):
+        y = ball_output(params, spec, m, field, c)
+        np.testing.assert_allclose(y, Y1[c], rtol=0, atol=1e-13)

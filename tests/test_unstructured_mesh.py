@@ -1,0 +1,161 @@
+"""General unstructured element meshes through the generic graph input
+(Sec. II-A builds the graph from any element -> global-id table and the
+element-local links): a seeded Delaunay tetrahedralisation, node in-degrees
+from 5 to several dozen, links shared by a variable number of sub-graphs.
+
+CPU: the oracle's graph against scipy's own Delaunay neighbour lists and a
+brute-force count of edge and node degrees; FP64 consistency (Eq. 2) and the
+host graph builder against the oracle.  GPU: the model's outputs, loss and
+gradients at R = 1 and R = 8 against the FP64 oracle at R = 1.
+"""
+
+import numpy as np
+import pytest
+
+from mpinputs import ModelSpec, init_params
+from mpinputs.fields import velocity_field
+from mpinputs.tetmesh import centroid_partition, tet_mesh
+from oracle.graph import partition_graph
+from oracle.nmp import consistent_loss, model_bwd, model_fwd
+from oracle.problem import build_problem
+
+from _util import normwise
+
+
+def _mesh(n=2000, seed=21):
+    return tet_mesh(n, seed)
+
+
+def test_oracle_graph_is_the_delaunay_edge_set():
+    from scipy.spatial import Delaunay
+    m = _mesh()
+    (G,), copies = partition_graph(m.elem_gid, None, np.zeros(m.n_elem, np.int32), 1, m.links)
+    assert copies == {}
+    np.testing.assert_array_equal(G.gid, np.arange(m.n_gid))
+    ptr, nbr = Delaunay(m.pos).vertex_neighbor_vertices
+    ref = set()
+    for i in range(m.n_gid):
+        ref.update((i, int(j)) for j in nbr[ptr[i]:ptr[i + 1]])
+    assert set(zip(G.recv.tolist(), G.send.tolist())) == ref
+    deg = np.bincount(G.recv, minlength=m.n_gid)
+    assert deg.min() >= 4 and deg.max() >= 20           # irregular degrees
+
+
+def test_oracle_degrees_brute_force():
+    m = _mesh(600, 3)
+    R = 8
+    part = centroid_partition(m, R)
+    graphs, copies = partition_graph(m.elem_gid, None, part, R, m.links)
+    holders_e, holders_n = {}, {}
+    for el in range(m.n_elem):
+        ids = m.elem_gid[el]
+        for a, b in m.links:
+            key = (min(ids[a], ids[b]), max(ids[a], ids[b]))
+            holders_e.setdefault(key, set()).add(int(part[el]))
+        for g in ids:
+            holders_n.setdefault(int(g), set()).add(int(part[el]))
+    seen = set()
+    for r, G in enumerate(graphs):
+        for k in range(G.e):
+            i, j = int(G.gid[G.recv[k]]), int(G.gid[G.send[k]])
+            key = (min(i, j), max(i, j))
+            assert r in holders_e[key]
+            assert G.d_edge[k] == len(holders_e[key])
+            seen.add((r, key))
+        for row, g in enumerate(G.gid):
+            assert G.d_node[row] == len(holders_n[int(g)])
+    assert seen == {(r, k) for k, rs in holders_e.items() for r in rs}
+    assert max(len(v) for v in holders_e.values()) >= 4   # links shared by 4+ parts
+    assert set(copies) == {g for g, rs in holders_n.items() if len(rs) > 1}
+
+
+def test_oracle_consistency_fp64():
+    m = _mesh(1500, 4)
+    spec = ModelSpec(H=8, n_layers=2, layernorm=True)
+    params = init_params(spec, 6, perturb=True)
+    field = velocity_field(m.pos, 7, noise_sigma=0.01)
+    p1 = build_problem(m, field, field, None, 1)
+    Y1, _ = model_fwd(params, spec, p1.graphs, p1.pair_lists, p1.X, p1.E0)
+    Y1 = Y1[0]
+    part = centroid_partition(m, 8)
+    p8 = build_problem(m, field, field, part, 8)
+    for halo, bound in ((True, 1e-12), (False, None)):
+        Y, _ = model_fwd(params, spec, p8.graphs, p8.pair_lists, p8.X, p8.E0, halo=halo)
+        err = max(np.abs(Y[r] - Y1[G.gid]).max() for r, G in enumerate(p8.graphs)) / np.abs(Y1).max()
+        if halo:
+            assert err <= bound
+        else:
+            assert err > 1e-3
+
+
+def test_host_graph_matches_oracle():
+    from paper_2410_01657_amd import build_graph
+    m = _mesh(1200, 8)
+    for R in (1, 8):
+        part = centroid_partition(m, R) if R > 1 else np.zeros(m.n_elem, np.int32)
+        hg = build_graph(m.elem_gid, None, part, R, m.links)
+        og, copies = partition_graph(m.elem_gid, None, part, R, m.links)
+        for r, G in enumerate(og):
+            r0, r1 = hg.row_off[r], hg.row_off[r + 1]
+            e0, e1 = hg.edge_off[r], hg.edge_off[r + 1]
+            np.testing.assert_array_equal(hg.row_gid[r0:r1], G.gid)
+            np.testing.assert_array_equal(hg.recv[e0:e1] - r0, G.recv)
+            np.testing.assert_array_equal(hg.col[e0:e1] - r0, G.send)
+            np.testing.assert_array_equal(hg.edge_mult[e0:e1], G.d_edge.astype(np.uint8))
+            np.testing.assert_array_equal(hg.node_mult[r0:r1], G.d_node.astype(np.uint8))
+        np.testing.assert_array_equal(hg.recv[hg.rev], hg.col)
+        groups = {}
+        for k in range(hg.n_groups):
+            mem = hg.member[hg.group_ptr[k]:hg.group_ptr[k + 1]]
+            groups[int(hg.row_gid[mem[0]])] = mem.tolist()
+        assert groups == {g: [int(hg.row_off[r]) + i for r, i in c] for g, c in copies.items()}
+
+
+# ------------------------------------------------------------------ GPU
+
+GPU_POINTS = 6000
+TOL = {"f32": (1e-4, 1e-4), "bf16": (3e-2, 1e-1)}
+
+
+@pytest.fixture(scope="module")
+def tet_oracle():
+    """FP64 oracle outputs, loss and gradients at R = 1, per model width."""
+    m = _mesh(GPU_POINTS, 31)
+    field = velocity_field(m.pos, 32, noise_sigma=0.01)
+    target = np.roll(field, 1, axis=1)
+    cache = {}
+
+    def get(H):
+        if H not in cache:
+            spec = ModelSpec(H=H, n_layers=2, layernorm=True)
+            params = init_params(spec, 33, perturb=True)
+            p = build_problem(m, field, target, None, 1)
+            Y, c = model_fwd(params, spec, p.graphs, p.pair_lists, p.X, p.E0)
+            L, gY, _ = consistent_loss(Y, p.T, p.graphs)
+            grads, _ = model_bwd(params, spec, p.graphs, p.pair_lists, c, gY)
+            cache[H] = (spec, params, Y[0], L, grads)
+        return cache[H]
+    return m, field, target, get
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("H,gemm", [(64, "f32"), (64, "bf16"), (128, "bf16"), (32, "f32")])
+@pytest.mark.parametrize("R", [1, 8])
+def test_tet_mesh_model_vs_oracle(tet_oracle, H, gemm, R):
+    from paper_2410_01657_amd.model import ConsistentGNN, Problem
+    m, field, target, get = tet_oracle
+    spec, params, Yo, Lo, go = get(H)
+    part = centroid_partition(m, R) if R > 1 else np.zeros(m.n_elem, np.int32)
+    print(f"tet mesh {m.n_gid} nodes, H={H} {gemm} R={R}", flush=True)
+    prob = Problem(m, field, target, part, R, "cuda")
+    model = ConsistentGNN(spec, params, "cuda", gemm=gemm).requires_grad_(True)
+    Y = model.forward(prob.dg, prob.X, prob.E0)
+    loss = model.loss(prob.dg, Y, prob.T)
+    loss.backward()
+    Yg = Y.detach().cpu().numpy()
+    tol_y, tol_g = TOL[gemm]
+    # every row copy against the unpartitioned FP64 value (Eq. 2 and parity)
+    assert normwise(Yg, Yo[prob.host.row_gid]) < tol_y
+    assert abs(float(loss.detach()) - Lo) / Lo < tol_y
+    for k, t in model.params.items():        # Eq. 3 and parity
+        assert normwise(t.grad.cpu().numpy(), go[k]) < tol_g, k
