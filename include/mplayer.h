@@ -238,6 +238,72 @@ int mp_mlp_backward(const mp_mlp_cfg* cfg, const mp_mlp_params* p, int64_t n_row
                     const mp_mlp_grads* grads, void* ws, size_t ws_bytes,
                     mp_stream_t stream);
 
+/* ---------------------------------------------------------------------
+ * Narrow deep MLPs: the paper's own models (Table I: H = 8 with two and
+ * H = 32 with five extra hidden layers per MLP), FP32, hidden width 8, 16
+ * or 32.  Every MLP is Linear(in->H), ELU, n_hidden x (Linear(H->H), ELU),
+ * Linear(H->out) [, LayerNorm] (Sec. III), and its parameters are ONE
+ * flat device FP32 array in torch.nn.Linear order:
+ *   W0[H][in] b0[H], n_hidden x (W[H][H] b[H]), Wo[out][H] bo[out],
+ *   then with LayerNorm gain[out] and shift[out].
+ * Gradients use the same layout and are overwritten, not accumulated.
+ * Results are bitwise reproducible run to run (fixed-order sums).
+ * ------------------------------------------------------------------- */
+typedef struct {
+  int32_t H;          /* 8, 16 or 32 */
+  int32_t n_hidden;   /* 0..8 */
+  int32_t layernorm;  /* LayerNorm on both MLPs' outputs */
+  int32_t halo;       /* 1: consistent (Eq. 4c-d); 0: "None" mode */
+  float ln_eps;
+} mp_deep_layer_cfg;
+
+/* Floats in the flat parameter array of one MLP. */
+int mp_deep_theta_size(int32_t n_in, int32_t H, int32_t n_hidden, int32_t n_out, int32_t layernorm,
+                       int64_t* floats);
+
+/* Workspace bytes (0 for the forward). */
+int mp_deep_layer_workspace_size(const mp_deep_layer_cfg* cfg, const mp_dev_graph* g,
+                                 int backward, size_t* bytes);
+
+/* One consistent NMP layer (Eq. 4a-e) with deep MLPs: theta_edge is the
+ * edge MLP (input [x_i, x_j, e_ij], 3H -> H), theta_node the node MLP
+ * (input [a*_i, x_i], 2H -> H); both updates residual.  x_in[N][H],
+ * e_in[E][H] -> x_out[N][H], e_out[E][H]; a_star_out[N][H] (required)
+ * receives the synchronised aggregate for the backward.  Outputs must not
+ * alias inputs. */
+int mp_deep_layer_forward(const mp_deep_layer_cfg* cfg, const float* theta_edge,
+                          const float* theta_node, const mp_dev_graph* g, const float* x_in,
+                          const float* e_in, float* x_out, float* e_out, float* a_star_out,
+                          mp_stream_t stream);
+
+/* Adjoint (Eq. 3) of mp_deep_layer_forward for the same inputs and a*:
+ * gradients of x_in, e_in and both parameter arrays.  MLP activations are
+ * recomputed; the workspace (mp_deep_layer_workspace_size) holds per-row
+ * records of them.  g_e_out may be NULL (zero).  The graph needs its
+ * reverse-edge array. */
+int mp_deep_layer_backward(const mp_deep_layer_cfg* cfg, const float* theta_edge,
+                           const float* theta_node, const mp_dev_graph* g, const float* x_in,
+                           const float* e_in, const float* a_star, const float* g_x_out,
+                           const float* g_e_out, float* g_x_in, float* g_e_in,
+                           float* g_theta_edge, float* g_theta_node, void* ws, size_t ws_bytes,
+                           mp_stream_t stream);
+
+/* Encoder / decoder with deep MLPs (Sec. III).  (n_in, n_out) is
+ * (1..4, H), (H, 1..4) or (H, H); LayerNorm needs n_out == H. */
+typedef struct {
+  int32_t n_in, H, n_hidden, n_out, layernorm;
+  float ln_eps;
+} mp_deep_mlp_cfg;
+
+int mp_deep_mlp_workspace_size(const mp_deep_mlp_cfg* cfg, int64_t n_rows, int backward, size_t* bytes);
+/* in[n_rows][n_in] -> out[n_rows][n_out], device FP32. */
+int mp_deep_mlp_forward(const mp_deep_mlp_cfg* cfg, const float* theta, int64_t n_rows,
+                        const float* in, float* out, mp_stream_t stream);
+/* g_in[n_rows][n_in] may be NULL (input gradient not needed). */
+int mp_deep_mlp_backward(const mp_deep_mlp_cfg* cfg, const float* theta, int64_t n_rows,
+                         const float* in, const float* g_out, float* g_in, float* g_theta,
+                         void* ws, size_t ws_bytes, mp_stream_t stream);
+
 /* Edge input features of Sec. III: e0[k] = (p_j - p_i, |p_j - p_i|) for
  * edge k with receiver i and sender j; row_pos[N][3] in FP64 (device), the
  * difference taken in FP64 and rounded once to FP32.  e0 is [E][4] (device).
@@ -267,7 +333,9 @@ int mp_consistent_mse_workspace_size(int64_t n_rows, size_t* bytes);
  * times of one kernel's launches recorded since then.  Kernel names:
  * tiles, pack, proj, edge_fwd, halo, halo_adj, node_fwd, node_bwd, edge_bwd,
  * edge_dw, node_dw (weight gradients of the split adjoints, H = 128), gq,
- * wreduce, mlp_fwd, mlp_bwd, edge_inputs, loss.
+ * wreduce, mlp_fwd, mlp_bwd, edge_inputs, loss; for the deep MLPs deep_edge_fwd,
+ * deep_node_fwd, deep_node_bwd, deep_edge_bwd, deep_gather, deep_node_dw, deep_edge_dw,
+ * deep_mlp_fwd, deep_mlp_bwd, deep_mlp_dw.
  * ------------------------------------------------------------------- */
 int mp_profile_enable(int on);
 int mp_profile_read(const char* kernel, double* total_ms, int64_t* launches);

@@ -56,6 +56,15 @@ class MpMlpGrads(C.Structure):
     _fields_ = [(n, vp) for n in MLP_FIELDS]
 
 
+class MpDeepLayerCfg(C.Structure):
+    _fields_ = [("H", c_i32), ("n_hidden", c_i32), ("layernorm", c_i32), ("halo", c_i32), ("ln_eps", c_f32)]
+
+
+class MpDeepMlpCfg(C.Structure):
+    _fields_ = [("n_in", c_i32), ("H", c_i32), ("n_hidden", c_i32), ("n_out", c_i32), ("layernorm", c_i32),
+                ("ln_eps", c_f32)]
+
+
 P = C.POINTER
 _SIGS = {
     "mp_abi_version": (c_i32, []),
@@ -79,6 +88,14 @@ _SIGS = {
     "mp_mlp_forward": (c_i32, [P(MpMlpCfg), P(MpMlpParams), c_i64, vp, vp, vp, C.c_size_t, vp]),
     "mp_mlp_backward": (c_i32, [P(MpMlpCfg), P(MpMlpParams), c_i64, vp, vp, vp, P(MpMlpGrads), vp,
                                 C.c_size_t, vp]),
+    "mp_deep_theta_size": (c_i32, [c_i32, c_i32, c_i32, c_i32, c_i32, P(c_i64)]),
+    "mp_deep_layer_workspace_size": (c_i32, [P(MpDeepLayerCfg), P(MpDevGraph), c_i32, P(C.c_size_t)]),
+    "mp_deep_layer_forward": (c_i32, [P(MpDeepLayerCfg), vp, vp, P(MpDevGraph), vp, vp, vp, vp, vp, vp]),
+    "mp_deep_layer_backward": (c_i32, [P(MpDeepLayerCfg), vp, vp, P(MpDevGraph), vp, vp, vp, vp, vp, vp, vp,
+                                       vp, vp, vp, C.c_size_t, vp]),
+    "mp_deep_mlp_workspace_size": (c_i32, [P(MpDeepMlpCfg), c_i64, c_i32, P(C.c_size_t)]),
+    "mp_deep_mlp_forward": (c_i32, [P(MpDeepMlpCfg), vp, c_i64, vp, vp, vp]),
+    "mp_deep_mlp_backward": (c_i32, [P(MpDeepMlpCfg), vp, c_i64, vp, vp, vp, vp, vp, C.c_size_t, vp]),
     "mp_edge_inputs": (c_i32, [P(MpDevGraph), vp, vp, vp, vp]),
     "mp_consistent_mse_workspace_size": (c_i32, [c_i64, P(C.c_size_t)]),
     "mp_consistent_mse": (c_i32, [c_i64, c_i32, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]),

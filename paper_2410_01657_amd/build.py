@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmplayer.so")
-SOURCES = ["mp_graph.cpp", "mp_fwd.hip", "mp_bwd.hip", "mp_capi.hip"]
+SOURCES = ["mp_graph.cpp", "mp_fwd.hip", "mp_bwd.hip", "mp_deep.hip", "mp_capi.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -742,6 +742,321 @@ extern "C" int mp_mlp_backward(const mp_mlp_cfg* cfg, const mp_mlp_params* p, in
   return run("wreduce", s, [&] { return launch_wreduce(R, s); });
 }
 
+// ------------------------------------------------ narrow deep MLPs
+
+namespace {
+
+constexpr int kDeepMaxHidden = 8;
+
+bool deep_width_ok(int H) { return H == 8 || H == 16 || H == 32; }
+
+int check_deep_layer_cfg(const mp_deep_layer_cfg* c) {
+  if (!c) return mp_fail(MP_EINVAL, "deep layer config is NULL");
+  if (!deep_width_ok(c->H)) return mp_fail(MP_EINVAL, "deep layers: H must be 8, 16 or 32 (got %d)", c->H);
+  if (c->n_hidden < 0 || c->n_hidden > kDeepMaxHidden)
+    return mp_fail(MP_EINVAL, "n_hidden must be in [0, %d] (got %d)", kDeepMaxHidden, c->n_hidden);
+  if (c->layernorm && !(c->ln_eps > 0.f)) return mp_fail(MP_EINVAL, "ln_eps must be positive");
+  return MP_OK;
+}
+
+// Rows per weight-gradient chunk: at most 2048 chunks, at least 256 rows.
+int64_t deep_chunk(int64_t n) {
+  int64_t ch = std::max<int64_t>(256, (n + 2047) / 2048);
+  return (ch + 31) / 32 * 32;
+}
+int64_t deep_chunks(int64_t n) { return (n + deep_chunk(n) - 1) / deep_chunk(n); }
+
+// One MLP's weight-gradient blocks over its records (K input features in
+// columns [0, K) of the record, padded widths km, om).
+int deep_outer_mats(OuterArgs& oa, int K, int H, int NH, int O, int ln, int km, int om) {
+  auto h = [&](int l) { return km + l * H; };
+  auto d = [&](int l) { return km + (NH + 1) * H + l * H; };
+  const int dout = km + 2 * (NH + 1) * H, lnr = dout + om;
+  auto wh = [&](int l) { return (int64_t)H * K + H + (int64_t)l * (H * H + H); };
+  const int64_t wo = wh(NH), bo = wo + (int64_t)O * H, lg = bo + O;
+  int n = 0;
+  oa.m[n++] = OuterMat{d(0), H, 0, K, 0, (int64_t)H * K};
+  for (int l = 1; l <= NH; ++l) oa.m[n++] = OuterMat{d(l), H, h(l - 1), H, wh(l - 1), wh(l - 1) + (int64_t)H * H};
+  oa.m[n++] = OuterMat{dout, O, h(NH), H, wo, bo};
+  if (ln) oa.m[n++] = OuterMat{lnr, 2 * O, -1, 0, 0, lg};
+  return n;
+}
+
+// Sum the chunk partials of one MLP into its flat gradient.
+int deep_grad_sums(const char* name, const float* rec, int64_t n_rows, int rs, int K, int H, int NH, int O, int ln,
+                   int km, int om, float* part, float* g_theta, hipStream_t s) {
+  OuterArgs oa{};
+  oa.rec = rec;
+  oa.n_rows = n_rows;
+  oa.rs = rs;
+  oa.ch = deep_chunk(n_rows);
+  oa.part = part;
+  oa.slab = deep_theta_floats(K, H, NH, O, ln);
+  const int nm = deep_outer_mats(oa, K, H, NH, O, ln, km, om);
+  for (int i = 0; i < nm; ++i)
+    if (!outer_fits(oa.m[i].gw, oa.m[i].a_off >= 0 ? oa.m[i].aw : 0))
+      return mp_fail(MP_EINVAL, "%s: weight block %d x %d too large", name, oa.m[i].gw, oa.m[i].aw);
+  const int64_t nc = deep_chunks(n_rows);
+  int rc;
+  if ((rc = run(name, s, [&] { return launch_outer_sum(oa, nm, nc, s); }))) return rc;
+  ReduceSegs R;
+  R.n = 1;
+  R.seg[0] = ReduceSeg{part, (int)nc, oa.slab, 0, 1, (int)oa.slab, g_theta, (int)oa.slab, 0};
+  return run("wreduce", s, [&] { return launch_wreduce(R, s); });
+}
+
+struct DeepLayerWs {
+  size_t recN = 0, recE = 0, ga = 0, gxn = 0, gxi = 0, gxj = 0, partN = 0, partE = 0, total = 0;
+  int rsN = 0, rsE = 0;
+  DeepLayerWs(const mp_deep_layer_cfg* c, const mp_dev_graph* g) {
+    const int H = c->H, NH = c->n_hidden, ln = c->layernorm != 0;
+    const int64_t N = g->n_rows, E = g->n_edges;
+    rsN = deep_rec_floats(H, 2 * H, H, NH, ln);
+    rsE = deep_rec_floats(H, 3 * H, H, NH, ln);
+    size_t o = 0;
+    auto take = [&](size_t& slot, size_t floats) {
+      slot = o;
+      o = align_up(o + floats * sizeof(float));
+    };
+    take(recN, (size_t)N * rsN);
+    take(recE, (size_t)E * rsE);
+    take(ga, (size_t)N * H);
+    take(gxn, (size_t)N * H);
+    take(gxi, (size_t)N * H);
+    take(gxj, (size_t)E * H);
+    take(partN, (size_t)deep_chunks(N) * deep_theta_floats(2 * H, H, NH, H, ln));
+    take(partE, (size_t)deep_chunks(E) * deep_theta_floats(3 * H, H, NH, H, ln));
+    total = o;
+  }
+};
+
+int deep_mlp_kind(const mp_deep_mlp_cfg* c, DeepRowKind& kind, int& km, int& om) {
+  if (!c) return mp_fail(MP_EINVAL, "deep mlp config is NULL");
+  if (!deep_width_ok(c->H)) return mp_fail(MP_EINVAL, "deep MLPs: H must be 8, 16 or 32 (got %d)", c->H);
+  if (c->n_hidden < 0 || c->n_hidden > kDeepMaxHidden)
+    return mp_fail(MP_EINVAL, "n_hidden must be in [0, %d] (got %d)", kDeepMaxHidden, c->n_hidden);
+  if (c->layernorm && (c->n_out != c->H || !(c->ln_eps > 0.f)))
+    return mp_fail(MP_EINVAL, "LayerNorm needs n_out == H and a positive ln_eps");
+  const int H = c->H;
+  if (c->n_in >= 1 && c->n_in <= 4 && c->n_out == H) {
+    kind = DeepRowKind::kSmallIn, km = 4, om = H;
+  } else if (c->n_in == H && c->n_out >= 1 && c->n_out <= 4) {
+    kind = DeepRowKind::kSmallOut, km = H, om = 4;
+  } else if (c->n_in == H && c->n_out == H) {
+    kind = DeepRowKind::kWide, km = H, om = H;
+  } else {
+    return mp_fail(MP_EINVAL, "deep MLPs: (n_in, n_out) must be (1..4, H), (H, 1..4) or (H, H); got (%d, %d)",
+                   c->n_in, c->n_out);
+  }
+  return MP_OK;
+}
+
+}  // namespace
+
+extern "C" int mp_deep_theta_size(int32_t n_in, int32_t H, int32_t n_hidden, int32_t n_out, int32_t layernorm,
+                                  int64_t* floats) {
+  if (!floats || n_in <= 0 || H <= 0 || n_hidden < 0 || n_out <= 0)
+    return mp_fail(MP_EINVAL, "mp_deep_theta_size: bad argument");
+  *floats = deep_theta_floats(n_in, H, n_hidden, n_out, layernorm != 0);
+  return MP_OK;
+}
+
+extern "C" int mp_deep_layer_workspace_size(const mp_deep_layer_cfg* cfg, const mp_dev_graph* g, int backward,
+                                            size_t* bytes) {
+  int rc;
+  if ((rc = check_deep_layer_cfg(cfg)) || (rc = check_graph(g, false))) return rc;
+  if (!bytes) return mp_fail(MP_EINVAL, "bytes is NULL");
+  *bytes = backward ? DeepLayerWs(cfg, g).total : 0;
+  return MP_OK;
+}
+
+extern "C" int mp_deep_layer_forward(const mp_deep_layer_cfg* cfg, const float* theta_edge,
+                                     const float* theta_node, const mp_dev_graph* g, const float* x_in,
+                                     const float* e_in, float* x_out, float* e_out, float* a_star_out,
+                                     mp_stream_t stream) {
+  int rc;
+  if ((rc = check_deep_layer_cfg(cfg)) || (rc = check_graph(g, false))) return rc;
+  if (!theta_edge || !theta_node || !x_in || !e_in || !x_out || !e_out || !a_star_out)
+    return mp_fail(MP_EINVAL, "mp_deep_layer_forward: NULL buffer");
+  if (!aligned16(x_in) || !aligned16(e_in) || !aligned16(x_out) || !aligned16(e_out) || !aligned16(a_star_out))
+    return mp_fail(MP_EINVAL, "mp_deep_layer_forward: buffers must be 16-byte aligned");
+  if (x_out == x_in || e_out == e_in || a_star_out == x_in || a_star_out == x_out)
+    return mp_fail(MP_EINVAL, "mp_deep_layer_forward: outputs must not alias inputs");
+  const int H = cfg->H;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const DevGraph d = dev_graph(g);
+  DeepEdgeArgs ea{};
+  ea.g = d;
+  ea.theta = theta_edge;
+  ea.NH = cfg->n_hidden;
+  ea.ln = cfg->layernorm != 0;
+  ea.eps = cfg->ln_eps;
+  ea.x = x_in;
+  ea.e_in = e_in;
+  ea.e_out = e_out;
+  ea.a_out = a_star_out;
+  if ((rc = run("deep_edge_fwd", s, [&] { return launch_deep_edge(ea, H, false, s); }))) return rc;
+  if (cfg->halo && (rc = run("halo", s, [&] { return launch_halo(H, d, a_star_out, s); }))) return rc;
+  DeepRowArgs na{};
+  na.n_rows = g->n_rows;
+  na.theta = theta_node;
+  na.NH = cfg->n_hidden;
+  na.ka = H;
+  na.O = H;
+  na.ln = cfg->layernorm != 0;
+  na.eps = cfg->ln_eps;
+  na.src_a = a_star_out;
+  na.src_b = x_in;
+  na.resid = 1;
+  na.out = x_out;
+  return run("deep_node_fwd", s, [&] { return launch_deep_row(na, H, DeepRowKind::kNode, false, s); });
+}
+
+extern "C" int mp_deep_layer_backward(const mp_deep_layer_cfg* cfg, const float* theta_edge,
+                                      const float* theta_node, const mp_dev_graph* g, const float* x_in,
+                                      const float* e_in, const float* a_star, const float* g_x_out,
+                                      const float* g_e_out, float* g_x_in, float* g_e_in, float* g_theta_edge,
+                                      float* g_theta_node, void* ws, size_t ws_bytes, mp_stream_t stream) {
+  int rc;
+  if ((rc = check_deep_layer_cfg(cfg)) || (rc = check_graph(g, true))) return rc;
+  if (!theta_edge || !theta_node || !x_in || !e_in || !a_star || !g_x_out || !g_x_in || !g_e_in ||
+      !g_theta_edge || !g_theta_node || !ws)
+    return mp_fail(MP_EINVAL, "mp_deep_layer_backward: NULL buffer");
+  const void* al[] = {x_in, e_in, a_star, g_x_out, g_x_in, g_e_in, ws};
+  for (const void* q : al)
+    if (!aligned16(q)) return mp_fail(MP_EINVAL, "mp_deep_layer_backward: buffers must be 16-byte aligned");
+  if (g_e_out && !aligned16(g_e_out)) return mp_fail(MP_EINVAL, "mp_deep_layer_backward: g_e_out not aligned");
+  if (g_x_in == g_x_out || (const float*)g_e_in == g_e_out || g_x_in == x_in || g_e_in == e_in)
+    return mp_fail(MP_EINVAL, "mp_deep_layer_backward: gradient outputs must not alias inputs");
+  const DeepLayerWs W(cfg, g);
+  if (ws_bytes < W.total)
+    return mp_fail(MP_ENOMEM, "mp_deep_layer_backward: workspace %zu < %zu bytes", ws_bytes, W.total);
+  const int H = cfg->H, NH = cfg->n_hidden, ln = cfg->layernorm != 0;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const DevGraph d = dev_graph(g);
+  float* ga = wsf(ws, W.ga);
+  float* gxn = wsf(ws, W.gxn);
+  // node update adjoint: gradient at a* (into ga) and at x (into gxn)
+  DeepRowArgs na{};
+  na.n_rows = g->n_rows;
+  na.theta = theta_node;
+  na.NH = NH;
+  na.ka = H;
+  na.O = H;
+  na.ln = ln;
+  na.eps = cfg->ln_eps;
+  na.src_a = a_star;
+  na.src_b = x_in;
+  na.resid = 1;
+  na.g_out = g_x_out;
+  na.g_a = ga;
+  na.g_b = gxn;
+  na.rec = wsf(ws, W.recN);
+  na.rs = W.rsN;
+  if ((rc = run("deep_node_bwd", s, [&] { return launch_deep_row(na, H, DeepRowKind::kNode, true, s); }))) return rc;
+  if (cfg->halo && (rc = run("halo_adj", s, [&] { return launch_halo(H, d, ga, s); }))) return rc;
+  DeepEdgeArgs ea{};
+  ea.g = d;
+  ea.theta = theta_edge;
+  ea.NH = NH;
+  ea.ln = ln;
+  ea.eps = cfg->ln_eps;
+  ea.x = x_in;
+  ea.e_in = e_in;
+  ea.g_a = ga;
+  ea.g_e_out = g_e_out;
+  ea.g_e_in = g_e_in;
+  ea.gxi = wsf(ws, W.gxi);
+  ea.gxj = wsf(ws, W.gxj);
+  ea.rec = wsf(ws, W.recE);
+  ea.rs = W.rsE;
+  if ((rc = run("deep_edge_bwd", s, [&] { return launch_deep_edge(ea, H, true, s); }))) return rc;
+  if ((rc = run("deep_gather", s, [&] { return launch_deep_gather(H, d, gxn, ea.gxi, ea.gxj, g_x_in, s); })))
+    return rc;
+  if ((rc = deep_grad_sums("deep_node_dw", na.rec, g->n_rows, W.rsN, 2 * H, H, NH, H, ln, 2 * H, H,
+                           wsf(ws, W.partN), g_theta_node, s)))
+    return rc;
+  return deep_grad_sums("deep_edge_dw", ea.rec, g->n_edges, W.rsE, 3 * H, H, NH, H, ln, 3 * H, H,
+                        wsf(ws, W.partE), g_theta_edge, s);
+}
+
+extern "C" int mp_deep_mlp_workspace_size(const mp_deep_mlp_cfg* cfg, int64_t n_rows, int backward,
+                                          size_t* bytes) {
+  int rc, km, om;
+  DeepRowKind kind;
+  if ((rc = deep_mlp_kind(cfg, kind, km, om))) return rc;
+  if (n_rows <= 0 || !bytes) return mp_fail(MP_EINVAL, "mp_deep_mlp_workspace_size: bad n_rows or bytes");
+  if (!backward) {
+    *bytes = 0;
+    return MP_OK;
+  }
+  const int rs = deep_rec_floats(cfg->H, km, om, cfg->n_hidden, cfg->layernorm != 0);
+  *bytes = align_up((size_t)n_rows * rs * sizeof(float)) +
+           align_up((size_t)deep_chunks(n_rows) *
+                    deep_theta_floats(cfg->n_in, cfg->H, cfg->n_hidden, cfg->n_out, cfg->layernorm != 0) *
+                    sizeof(float));
+  return MP_OK;
+}
+
+extern "C" int mp_deep_mlp_forward(const mp_deep_mlp_cfg* cfg, const float* theta, int64_t n_rows,
+                                   const float* in, float* out, mp_stream_t stream) {
+  int rc, km, om;
+  DeepRowKind kind;
+  if ((rc = deep_mlp_kind(cfg, kind, km, om))) return rc;
+  if (n_rows <= 0 || !theta || !in || !out) return mp_fail(MP_EINVAL, "mp_deep_mlp_forward: bad size or NULL buffer");
+  if (!aligned16(in) || !aligned16(out)) return mp_fail(MP_EINVAL, "mp_deep_mlp_forward: unaligned buffer");
+  if ((const float*)out == in) return mp_fail(MP_EINVAL, "mp_deep_mlp_forward: out must not alias in");
+  DeepRowArgs a{};
+  a.n_rows = n_rows;
+  a.theta = theta;
+  a.NH = cfg->n_hidden;
+  a.ka = cfg->n_in;
+  a.O = cfg->n_out;
+  a.ln = cfg->layernorm != 0;
+  a.eps = cfg->ln_eps;
+  a.src_a = in;
+  a.out = out;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  return run("deep_mlp_fwd", s, [&] { return launch_deep_row(a, cfg->H, kind, false, s); });
+}
+
+extern "C" int mp_deep_mlp_backward(const mp_deep_mlp_cfg* cfg, const float* theta, int64_t n_rows,
+                                    const float* in, const float* g_out, float* g_in, float* g_theta, void* ws,
+                                    size_t ws_bytes, mp_stream_t stream) {
+  int rc, km, om;
+  DeepRowKind kind;
+  if ((rc = deep_mlp_kind(cfg, kind, km, om))) return rc;
+  if (n_rows <= 0 || !theta || !in || !g_out || !g_theta || !ws)
+    return mp_fail(MP_EINVAL, "mp_deep_mlp_backward: bad size or NULL buffer");
+  if (!aligned16(in) || !aligned16(g_out) || !aligned16(ws) || (g_in && !aligned16(g_in)))
+    return mp_fail(MP_EINVAL, "mp_deep_mlp_backward: unaligned buffer");
+  if (g_in && ((const float*)g_in == g_out || (const float*)g_in == in))
+    return mp_fail(MP_EINVAL, "mp_deep_mlp_backward: g_in must not alias inputs");
+  size_t need = 0;
+  mp_deep_mlp_workspace_size(cfg, n_rows, 1, &need);
+  if (ws_bytes < need) return mp_fail(MP_ENOMEM, "mp_deep_mlp_backward: workspace %zu < %zu bytes", ws_bytes, need);
+  const int H = cfg->H, NH = cfg->n_hidden, ln = cfg->layernorm != 0;
+  const int rs = deep_rec_floats(H, km, om, NH, ln);
+  DeepRowArgs a{};
+  a.n_rows = n_rows;
+  a.theta = theta;
+  a.NH = NH;
+  a.ka = cfg->n_in;
+  a.O = cfg->n_out;
+  a.ln = ln;
+  a.eps = cfg->ln_eps;
+  a.src_a = in;
+  a.g_out = g_out;
+  a.g_a = g_in;
+  a.rec = reinterpret_cast<float*>(ws);
+  a.rs = rs;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if ((rc = run("deep_mlp_bwd", s, [&] { return launch_deep_row(a, H, kind, true, s); }))) return rc;
+  float* part = wsf(ws, align_up((size_t)n_rows * rs * sizeof(float)));
+  return deep_grad_sums("deep_mlp_dw", a.rec, n_rows, rs, cfg->n_in, H, NH, cfg->n_out, ln, km, om, part, g_theta,
+                        s);
+}
+
 // ------------------------------------------------------- edge inputs, loss
 
 extern "C" int mp_edge_inputs(const mp_dev_graph* g, const double* row_pos, const double* period, float* e0,

@@ -1,0 +1,637 @@
+// Narrow deep MLPs: the paper's own models (Table I: hidden width 8 or 32,
+// two or five extra H -> H layers in every MLP), for the consistent layer
+// (Eq. 4a-e), the encoders and the decoder.
+//
+// At these widths a 16 x 16 matrix-core tile is mostly padding (H = 8) and
+// the products are small, so one thread owns one row (a node, or a
+// receiver with its incoming edges) and runs the whole MLP in registers
+// with FP32 FMAs.  The MLP's weights sit in LDS in the order the products
+// read them: every lane of a wave reads the same address (an LDS
+// broadcast), four weights per read.
+//
+// Forward: k_deep_edge_fwd walks each receiver's incoming edges in CSR
+// order, updates every edge (Eq. 4a, residual) and sums e'/d_ij into the
+// receiver (Eq. 4b) in that order, so no scan or atomic is needed.  The
+// halo sum (Eq. 4c-d) is the shared k_halo; k_deep_row_fwd is the node
+// update (Eq. 4e), the encoders and the decoder.
+//
+// Adjoint (Eq. 3): each row recomputes its MLP and writes, to a per-row
+// record in the workspace, the MLP input, every hidden activation, every
+// pre-activation gradient and the LayerNorm terms; input gradients leave
+// the row kernels directly.  Weight gradients are then sums over rows of
+// outer products of record columns, formed per chunk of rows by
+// k_outer_sum and added chunk by chunk in a fixed order (k_wreduce), so
+// results are bitwise reproducible.  The sender-side input gradient of
+// each edge is written per edge and gathered at the sender through the
+// reverse-edge index (k_deep_gather), in CSR order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "mp_device.hpp"
+#include "mp_kernels.hpp"
+
+namespace mp {
+
+// LDS image of one MLP, zero padded to compile-time widths: input KM
+// columns, output OM rows.  Layout (floats): W0[H][KM] b0[H],
+// NH x (W[H][H] b[H]), Wo[OM][H] bo[OM] gamma[OM] beta[OM].
+template <int H, int KM, int OM>
+struct DeepLds {
+  int NH;
+  __host__ __device__ static constexpr int w0() { return 0; }
+  __host__ __device__ static constexpr int b0() { return H * KM; }
+  __host__ __device__ int wh(int l) const { return H * KM + H + l * (H * H + H); }
+  __host__ __device__ int bh(int l) const { return wh(l) + H * H; }
+  __host__ __device__ int wo() const { return wh(NH); }
+  __host__ __device__ int bo() const { return wo() + OM * H; }
+  __host__ __device__ int lg() const { return bo() + OM; }
+  __host__ __device__ int lb() const { return lg() + OM; }
+  __host__ __device__ int size() const { return lb() + OM; }
+};
+
+// Per-row record (floats): in[KM], h_0..h_NH [H each], d_0..d_NH [H each]
+// (gradients at the pre-activations), d_out[OM], then with LayerNorm
+// (g_y * y_hat)[OM] and g_y[OM].
+template <int H, int KM, int OM>
+struct DeepRec {
+  int NH, ln;
+  __host__ __device__ static constexpr int in() { return 0; }
+  __host__ __device__ static constexpr int h(int l) { return KM + l * H; }
+  __host__ __device__ int d(int l) const { return KM + (NH + 1) * H + l * H; }
+  __host__ __device__ int dout() const { return KM + 2 * (NH + 1) * H; }
+  __host__ __device__ int lnr() const { return dout() + OM; }
+  __host__ __device__ int size() const { return lnr() + (ln ? 2 * OM : 0); }
+};
+
+// Copy the flat parameter array (torch.nn.Linear order) into the LDS image.
+// The MLP's input is [src_a (ka features, padded to KAM), src_b (KM - KAM)].
+template <int H, int KM, int OM>
+__device__ void stage_deep(float* __restrict__ L, const float* __restrict__ theta, const DeepLds<H, KM, OM>& m,
+                           int ka, int kam, int O, int ln) {
+  const int K = ka + (KM - kam);  // the parameter array's input width
+  for (int t = threadIdx.x; t < H * KM; t += blockDim.x) {
+    const int r = t / KM, c = t % KM;
+    const int sc = c < kam ? (c < ka ? c : -1) : ka + (c - kam);
+    L[t] = sc >= 0 ? theta[(int64_t)r * K + sc] : 0.f;
+  }
+  const float* tb0 = theta + (int64_t)H * K;
+  for (int t = threadIdx.x; t < H; t += blockDim.x) L[m.b0() + t] = tb0[t];
+  const float* th = tb0 + H;  // hidden layers, same layout in both
+  for (int t = threadIdx.x; t < m.NH * (H * H + H); t += blockDim.x) L[m.wh(0) + t] = th[t];
+  const float* two = th + (int64_t)m.NH * (H * H + H);
+  for (int t = threadIdx.x; t < OM * H; t += blockDim.x) L[m.wo() + t] = t / H < O ? two[t] : 0.f;
+  const float* tbo = two + (int64_t)O * H;
+  for (int t = threadIdx.x; t < OM; t += blockDim.x) {
+    L[m.bo() + t] = t < O ? tbo[t] : 0.f;
+    L[m.lg() + t] = (ln && t < O) ? tbo[O + t] : 0.f;
+    L[m.lb() + t] = (ln && t < O) ? tbo[2 * O + t] : 0.f;
+  }
+}
+
+// z = W x + b, W [N][M] row-major in LDS.
+// Every block of four rows reads through its own opaque base, so the
+// compiler cannot merge the whole matrix's reads into a few wide loads
+// placed up front (which would hold the matrix in registers).
+template <int N, int M>
+__device__ __forceinline__ void dlin(const float* __restrict__ W, const float* __restrict__ b, const float (&x)[M],
+                                     float (&z)[N]) {
+  const float* Wb = W;
+#pragma unroll
+  for (int o = 0; o < N; ++o) {
+    if (o % 4 == 0) Wb = W + opaque_zero();
+    float s = b[o];
+#pragma unroll
+    for (int c = 0; c < M; c += 4) {
+      const float4 w = *reinterpret_cast<const float4*>(Wb + o * M + c);
+      s = fmaf(w.x, x[c], s);
+      s = fmaf(w.y, x[c + 1], s);
+      s = fmaf(w.z, x[c + 2], s);
+      s = fmaf(w.w, x[c + 3], s);
+    }
+    z[o] = s;
+    if (o % 4 == 3) __builtin_amdgcn_sched_barrier(0);  // bound the reads in flight
+  }
+}
+
+// gx[c] = sum_o W[o][C0 + c] gz[o] for c < MW (a column block of W^T gz).
+// Column blocks of four outermost, so each block's sums finish before the
+// next block's weights are read.
+template <int N, int M, int C0, int MW>
+__device__ __forceinline__ void dlin_t(const float* __restrict__ W, const float (&gz)[N], float (&gx)[MW]) {
+#pragma unroll
+  for (int c = 0; c < MW; c += 4) {
+    const float* Wb = W + opaque_zero();
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+#pragma unroll
+    for (int o = 0; o < N; ++o) {
+      const float4 w = *reinterpret_cast<const float4*>(Wb + o * M + C0 + c);
+      s0 = fmaf(w.x, gz[o], s0);
+      s1 = fmaf(w.y, gz[o], s1);
+      s2 = fmaf(w.z, gz[o], s2);
+      s3 = fmaf(w.w, gz[o], s3);
+    }
+    gx[c] = s0;
+    gx[c + 1] = s1;
+    gx[c + 2] = s2;
+    gx[c + 3] = s3;
+    __builtin_amdgcn_sched_barrier(0);  // bound the reads in flight
+  }
+}
+
+// Keep the scheduler from interleaving consecutive products (which would
+// hold both products' weight reads in registers at once).
+__device__ __forceinline__ void phase_fence() { __builtin_amdgcn_sched_barrier(0); }
+
+template <int W>
+__device__ __forceinline__ void vload(const float* __restrict__ p, float (&v)[W]) {
+#pragma unroll
+  for (int c = 0; c < W; c += 4) {
+    const float4 t = *reinterpret_cast<const float4*>(p + c);
+    v[c] = t.x;
+    v[c + 1] = t.y;
+    v[c + 2] = t.z;
+    v[c + 3] = t.w;
+  }
+}
+template <int W>
+__device__ __forceinline__ void vstore(float* __restrict__ p, const float (&v)[W]) {
+#pragma unroll
+  for (int c = 0; c < W; c += 4) *reinterpret_cast<float4*>(p + c) = make_float4(v[c], v[c + 1], v[c + 2], v[c + 3]);
+}
+
+// MLP forward up to the last Linear's output u (before LayerNorm).  With
+// REC, the hidden activations go to the row's record.
+template <int H, int KM, int OM, bool REC>
+__device__ __forceinline__ void deep_fwd(const float* __restrict__ L, const DeepLds<H, KM, OM>& m,
+                                         const float (&in)[KM], float (&u)[OM], float* __restrict__ rec) {
+  using R = DeepRec<H, KM, OM>;
+  float h[H];
+  dlin<H, KM>(L + m.w0(), L + m.b0(), in, h);
+#pragma unroll
+  for (int c = 0; c < H; ++c) h[c] = elu(h[c]);
+  if constexpr (REC) vstore<H>(rec + R::h(0), h);
+  phase_fence();
+  for (int l = 0; l < m.NH; ++l) {
+    float z[H];
+    dlin<H, H>(L + m.wh(l), L + m.bh(l), h, z);
+#pragma unroll
+    for (int c = 0; c < H; ++c) h[c] = elu(z[c]);
+    if constexpr (REC) vstore<H>(rec + R::h(l + 1), h);
+    phase_fence();
+  }
+  dlin<OM, H>(L + m.wo(), L + m.bo(), h, u);
+  phase_fence();
+}
+
+// LayerNorm over the OM features of one row (biased variance), in place.
+template <int OM>
+__device__ __forceinline__ void dln_stats(const float (&u)[OM], float eps, float& mean, float& rstd) {
+  float s = 0.f;
+#pragma unroll
+  for (int c = 0; c < OM; ++c) s += u[c];
+  mean = s * (1.f / OM);
+  float q = 0.f;
+#pragma unroll
+  for (int c = 0; c < OM; ++c) q += (u[c] - mean) * (u[c] - mean);
+  rstd = 1.f / sqrtf(q * (1.f / OM) + eps);
+}
+
+template <int OM>
+__device__ __forceinline__ void dln_fwd(const float* __restrict__ g, const float* __restrict__ b, float eps,
+                                        float (&u)[OM]) {
+  float mean, rstd;
+  dln_stats<OM>(u, eps, mean, rstd);
+#pragma unroll
+  for (int c = 0; c < OM; ++c) u[c] = (u[c] - mean) * rstd * g[c] + b[c];
+}
+
+// Adjoint of LayerNorm: g_y -> g_u (in gy), recording g_y * y_hat and g_y.
+template <int OM>
+__device__ __forceinline__ void dln_bwd(const float* __restrict__ g, float eps, const float (&u)[OM], float (&gy)[OM],
+                                        float* __restrict__ rec_ln) {
+  float mean, rstd;
+  dln_stats<OM>(u, eps, mean, rstd);
+  float yh[OM], gyh[OM], m1 = 0.f, m2 = 0.f;
+#pragma unroll
+  for (int c = 0; c < OM; ++c) {
+    yh[c] = (u[c] - mean) * rstd;
+    gyh[c] = gy[c] * g[c];
+    m1 += gyh[c];
+    m2 += gyh[c] * yh[c];
+  }
+  m1 *= 1.f / OM;
+  m2 *= 1.f / OM;
+  float t[OM];
+#pragma unroll
+  for (int c = 0; c < OM; ++c) t[c] = gy[c] * yh[c];
+  vstore<OM>(rec_ln, t);
+  vstore<OM>(rec_ln + OM, gy);
+#pragma unroll
+  for (int c = 0; c < OM; ++c) gy[c] = rstd * (gyh[c] - m1 - yh[c] * m2);
+}
+
+// Back through the Linears given g_u (the gradient at the last Linear's
+// output): records every pre-activation gradient and returns the first
+// Linear's in d0.
+template <int H, int KM, int OM>
+__device__ __forceinline__ void deep_bwd(const float* __restrict__ L, const DeepLds<H, KM, OM>& m,
+                                         const DeepRec<H, KM, OM>& rr, const float (&gu)[OM],
+                                         float* __restrict__ rec, float (&d0)[H]) {
+  vstore<OM>(rec + rr.dout(), gu);
+  float gh[H];
+  dlin_t<OM, H, 0, H>(L + m.wo(), gu, gh);
+  phase_fence();
+  for (int l = m.NH; l >= 0; --l) {
+    float hl[H];
+    vload<H>(rec + rr.h(l), hl);
+#pragma unroll
+    for (int c = 0; c < H; ++c) d0[c] = gh[c] * (hl[c] > 0.f ? 1.f : hl[c] + 1.f);  // ELU' from ELU's value
+    vstore<H>(rec + rr.d(l), d0);
+    if (l > 0) dlin_t<H, H, 0, H>(L + m.wh(l - 1), d0, gh);
+    phase_fence();
+  }
+}
+
+// ------------------------------------------------------------- row MLPs
+
+// Input [src_a (ka <= KAM features), src_b (KB features)]; output O <= OM.
+template <int H, int KAM, int KB, int OM>
+struct DeepRowK {
+  static constexpr int KM = KAM + KB;
+  static __device__ __forceinline__ void load_in(const DeepRowArgs& a, int64_t r, float (&in)[KM]) {
+    if constexpr (KAM < 8) {
+#pragma unroll
+      for (int c = 0; c < KAM; ++c) in[c] = c < a.ka ? a.src_a[r * a.ka + c] : 0.f;
+    } else {
+      float t[KAM];
+      vload<KAM>(a.src_a + r * KAM, t);
+#pragma unroll
+      for (int c = 0; c < KAM; ++c) in[c] = t[c];
+    }
+    if constexpr (KB > 0) {
+      float t[KB];
+      vload<KB>(a.src_b + r * KB, t);
+#pragma unroll
+      for (int c = 0; c < KB; ++c) in[KAM + c] = t[c];
+    }
+  }
+};
+
+template <int H, int KAM, int KB, int OM>
+__global__ __launch_bounds__(256) void k_deep_row_fwd(DeepRowArgs a) {
+  extern __shared__ float L[];
+  using K = DeepRowK<H, KAM, KB, OM>;
+  const DeepLds<H, K::KM, OM> m{a.NH};
+  stage_deep<H, K::KM, OM>(L, a.theta, m, a.ka, KAM, a.O, a.ln);
+  __syncthreads();
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= a.n_rows) return;
+  float in[K::KM];
+  K::load_in(a, r, in);
+  float u[OM];
+  deep_fwd<H, K::KM, OM, false>(L, m, in, u, nullptr);
+  if (a.ln) dln_fwd<OM>(L + m.lg(), L + m.lb(), a.eps, u);
+  if constexpr (OM < 8) {
+#pragma unroll
+    for (int c = 0; c < OM; ++c)
+      if (c < a.O) a.out[r * a.O + c] = u[c];
+  } else {
+    if constexpr (KB == OM) {
+      if (a.resid) {
+#pragma unroll
+        for (int c = 0; c < OM; ++c) u[c] += in[KAM + c];
+      }
+    }
+    vstore<OM>(a.out + r * OM, u);
+  }
+}
+
+template <int H, int KAM, int KB, int OM>
+__global__ __launch_bounds__(256) void k_deep_row_bwd(DeepRowArgs a) {
+  extern __shared__ float L[];
+  using K = DeepRowK<H, KAM, KB, OM>;
+  const DeepLds<H, K::KM, OM> m{a.NH};
+  const DeepRec<H, K::KM, OM> rr{a.NH, a.ln};
+  stage_deep<H, K::KM, OM>(L, a.theta, m, a.ka, KAM, a.O, a.ln);
+  __syncthreads();
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= a.n_rows) return;
+  float* rec = a.rec + r * a.rs;
+  float d0[H];
+  float gy[OM];
+  {
+    float in[K::KM];
+    K::load_in(a, r, in);
+    vstore<K::KM>(rec + rr.in(), in);
+    float u[OM];
+    deep_fwd<H, K::KM, OM, true>(L, m, in, u, rec);
+    if constexpr (OM < 8) {
+#pragma unroll
+      for (int c = 0; c < OM; ++c) gy[c] = c < a.O ? a.g_out[r * a.O + c] : 0.f;
+    } else {
+      vload<OM>(a.g_out + r * OM, gy);
+    }
+    float gu[OM];
+#pragma unroll
+    for (int c = 0; c < OM; ++c) gu[c] = gy[c];
+    // a fresh view of the weights: the forward's reads are not reused (they
+    // would all stay live across the adjoint)
+    const float* Lb = L + opaque_zero();
+    if (a.ln) dln_bwd<OM>(Lb + m.lg(), a.eps, u, gu, rec + rr.lnr());
+    deep_bwd<H, K::KM, OM>(Lb, m, rr, gu, rec, d0);
+  }
+  const float* Lb = L + opaque_zero();
+  if (a.g_a) {
+    float t[KAM];
+    dlin_t<H, K::KM, 0, KAM>(Lb + m.w0(), d0, t);
+    if constexpr (KAM < 8) {
+#pragma unroll
+      for (int c = 0; c < KAM; ++c)
+        if (c < a.ka) a.g_a[r * a.ka + c] = t[c];
+    } else {
+      vstore<KAM>(a.g_a + r * KAM, t);
+    }
+  }
+  if constexpr (KB > 0) {
+    float t[KB];
+    dlin_t<H, K::KM, KAM, KB>(Lb + m.w0(), d0, t);
+    if constexpr (KB == OM) {
+      if (a.resid) {
+#pragma unroll
+        for (int c = 0; c < KB; ++c) t[c] += gy[c];
+      }
+    }
+    vstore<KB>(a.g_b + r * KB, t);
+  }
+}
+
+// --------------------------------------------------------- edge update
+
+template <int H>
+__global__ __launch_bounds__(256) void k_deep_edge_fwd(DeepEdgeArgs a) {
+  extern __shared__ float L[];
+  constexpr int KM = 3 * H;
+  const DeepLds<H, KM, H> m{a.NH};
+  stage_deep<H, KM, H>(L, a.theta, m, KM, KM, H, a.ln);
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.g.n_rows) return;
+  float in[KM], acc[H];
+  {
+    float t[H];
+    vload<H>(a.x + i * H, t);
+#pragma unroll
+    for (int c = 0; c < H; ++c) {
+      in[c] = t[c];
+      acc[c] = 0.f;
+    }
+  }
+  const int k1 = a.g.rowptr[i + 1];
+  for (int k = a.g.rowptr[i]; k < k1; ++k) {
+    const float* Lk = L + opaque_zero();  // re-read the weights per edge
+    float t[H];
+    vload<H>(a.x + (int64_t)a.g.col[k] * H, t);
+#pragma unroll
+    for (int c = 0; c < H; ++c) in[H + c] = t[c];
+    vload<H>(a.e_in + (int64_t)k * H, t);
+#pragma unroll
+    for (int c = 0; c < H; ++c) in[2 * H + c] = t[c];
+    float u[H];
+    deep_fwd<H, KM, H, false>(Lk, m, in, u, nullptr);
+    if (a.ln) dln_fwd<H>(Lk + m.lg(), Lk + m.lb(), a.eps, u);
+    const float inv_d = 1.f / (float)a.g.mult[k];
+#pragma unroll
+    for (int c = 0; c < H; ++c) {
+      u[c] += in[2 * H + c];  // residual edge update (Eq. 4a)
+      acc[c] += u[c] * inv_d;  // Eq. 4b
+    }
+    vstore<H>(a.e_out + (int64_t)k * H, u);
+  }
+  vstore<H>(a.a_out + i * H, acc);
+}
+
+template <int H>
+__global__ __launch_bounds__(256) void k_deep_edge_bwd(DeepEdgeArgs a) {
+  extern __shared__ float L[];
+  constexpr int KM = 3 * H;
+  const DeepLds<H, KM, H> m{a.NH};
+  const DeepRec<H, KM, H> rr{a.NH, a.ln};
+  stage_deep<H, KM, H>(L, a.theta, m, KM, KM, H, a.ln);
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.g.n_rows) return;
+  float xi[H], ga[H], gxi[H];
+  vload<H>(a.x + i * H, xi);
+  vload<H>(a.g_a + i * H, ga);
+#pragma unroll
+  for (int c = 0; c < H; ++c) gxi[c] = 0.f;
+  const int k1 = a.g.rowptr[i + 1];
+  for (int k = a.g.rowptr[i]; k < k1; ++k) {
+    const float* Lk = L + opaque_zero();  // re-read the weights per edge
+    float* rec = a.rec + (int64_t)k * a.rs;
+    const float inv_d = 1.f / (float)a.g.mult[k];
+    float gy[H], d0[H];
+    {
+      float in[KM];
+#pragma unroll
+      for (int c = 0; c < H; ++c) in[c] = xi[c];
+      float t[H];
+      vload<H>(a.x + (int64_t)a.g.col[k] * H, t);
+#pragma unroll
+      for (int c = 0; c < H; ++c) in[H + c] = t[c];
+      vload<H>(a.e_in + (int64_t)k * H, t);
+#pragma unroll
+      for (int c = 0; c < H; ++c) in[2 * H + c] = t[c];
+      vstore<KM>(rec + rr.in(), in);
+      float u[H];
+      deep_fwd<H, KM, H, true>(Lk, m, in, u, rec);
+      // gradient of e' = e + MLP(...): the next layer's, plus Eq. 4b's adjoint
+      if (a.g_e_out) {
+        vload<H>(a.g_e_out + (int64_t)k * H, gy);
+      } else {
+#pragma unroll
+        for (int c = 0; c < H; ++c) gy[c] = 0.f;
+      }
+#pragma unroll
+      for (int c = 0; c < H; ++c) gy[c] += ga[c] * inv_d;
+      float gu[H];
+#pragma unroll
+      for (int c = 0; c < H; ++c) gu[c] = gy[c];
+      const float* Lb = L + opaque_zero();  // see k_deep_row_bwd
+      if (a.ln) dln_bwd<H>(Lb + m.lg(), a.eps, u, gu, rec + rr.lnr());
+      deep_bwd<H, KM, H>(Lb, m, rr, gu, rec, d0);
+    }
+    Lk = L + opaque_zero();
+    float t[H];
+    dlin_t<H, KM, 0, H>(Lk + m.w0(), d0, t);  // receiver part
+#pragma unroll
+    for (int c = 0; c < H; ++c) gxi[c] += t[c];
+    phase_fence();
+    dlin_t<H, KM, H, H>(Lk + m.w0(), d0, t);  // sender part, gathered later
+    vstore<H>(a.gxj + (int64_t)k * H, t);
+    phase_fence();
+    dlin_t<H, KM, 2 * H, H>(Lk + m.w0(), d0, t);  // edge-state part + residual
+#pragma unroll
+    for (int c = 0; c < H; ++c) t[c] += gy[c];
+    vstore<H>(a.g_e_in + (int64_t)k * H, t);
+  }
+  vstore<H>(a.gxi + i * H, gxi);
+}
+
+// g_x[j] = g_x_node[j] + receiver part[j] + sender parts of j's outgoing
+// edges (the reverses of its incoming edges), in CSR order.
+template <int H>
+__global__ __launch_bounds__(256) void k_deep_gather(DevGraph g, const float* __restrict__ gxn,
+                                                     const float* __restrict__ gxi, const float* __restrict__ gxj,
+                                                     float* __restrict__ gx) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= g.n_rows) return;
+  float s[H], t[H];
+  vload<H>(gxn + j * H, s);
+  vload<H>(gxi + j * H, t);
+#pragma unroll
+  for (int c = 0; c < H; ++c) s[c] += t[c];
+  const int k1 = g.rowptr[j + 1];
+  for (int k = g.rowptr[j]; k < k1; ++k) {
+    vload<H>(gxj + (int64_t)g.rev[k] * H, t);
+#pragma unroll
+    for (int c = 0; c < H; ++c) s[c] += t[c];
+  }
+  vstore<H>(gx + j * H, s);
+}
+
+// ------------------------------------------------ weight-gradient sums
+
+// Partial sums over one chunk of rows of G^T [A, 1] for one record block:
+// part[chunk][dst_w + o*aw + c] = sum_r G[r][o] A[r][c] and
+// part[chunk][dst_b + o] = sum_r G[r][o]; without A only the latter.
+constexpr int kOuterTR = 32, kOuterGW = 64, kOuterAW = 96, kOuterEPT = 13;
+__global__ __launch_bounds__(256) void k_outer_sum(OuterArgs a) {
+  __shared__ float Gs[kOuterTR][kOuterGW];
+  __shared__ float As[kOuterTR][kOuterAW + 1];
+  const OuterMat M = a.m[blockIdx.y];
+  const bool hasA = M.a_off >= 0;
+  const int aw1 = hasA ? M.aw + 1 : 1;
+  const int n_el = M.gw * aw1;
+  int go[kOuterEPT], ac[kOuterEPT];
+  float acc[kOuterEPT];
+#pragma unroll
+  for (int j = 0; j < kOuterEPT; ++j) {
+    const int e = threadIdx.x + 256 * j;
+    go[j] = e < n_el ? e / aw1 : 0;
+    ac[j] = e < n_el ? e % aw1 : 0;
+    acc[j] = 0.f;
+  }
+  const int64_t r0 = (int64_t)blockIdx.x * a.ch, r1 = std::min<int64_t>(a.n_rows, r0 + a.ch);
+  for (int64_t rb = r0; rb < r1; rb += kOuterTR) {
+    for (int t = threadIdx.x; t < kOuterTR * kOuterGW; t += 256) {
+      const int r = t / kOuterGW, c = t % kOuterGW;
+      const int64_t row = rb + r;
+      Gs[r][c] = (row < r1 && c < M.gw) ? a.rec[row * a.rs + M.g_off + c] : 0.f;
+    }
+    for (int t = threadIdx.x; t < kOuterTR * (kOuterAW + 1); t += 256) {
+      const int r = t / (kOuterAW + 1), c = t % (kOuterAW + 1);
+      const int64_t row = rb + r;
+      float v = 0.f;
+      if (c == aw1 - 1) v = 1.f;
+      else if (hasA && c < M.aw && row < r1) v = a.rec[row * a.rs + M.a_off + c];
+      As[r][c] = v;
+    }
+    __syncthreads();
+    for (int r = 0; r < kOuterTR; ++r) {
+#pragma unroll
+      for (int j = 0; j < kOuterEPT; ++j) acc[j] = fmaf(Gs[r][go[j]], As[r][ac[j]], acc[j]);
+    }
+    __syncthreads();
+  }
+  float* dst = a.part + (int64_t)blockIdx.x * a.slab;
+#pragma unroll
+  for (int j = 0; j < kOuterEPT; ++j) {
+    const int e = threadIdx.x + 256 * j;
+    if (e >= n_el) continue;
+    if (ac[j] == aw1 - 1) dst[M.dst_b + go[j]] = acc[j];
+    else dst[M.dst_w + (int64_t)go[j] * M.aw + ac[j]] = acc[j];
+  }
+}
+
+// ------------------------------------------------------------- launchers
+
+template <int H, int KM, int OM>
+static size_t deep_lds_bytes(int NH) {
+  return (size_t)DeepLds<H, KM, OM>{NH}.size() * sizeof(float);
+}
+
+int deep_rec_floats(int H, int km, int om, int NH, int ln) {
+  return km + 2 * (NH + 1) * H + om + (ln ? 2 * om : 0);
+}
+
+template <int H, int KAM, int KB, int OM>
+static hipError_t row_launch(const DeepRowArgs& a, bool bwd, hipStream_t s) {
+  const int grid = (int)((a.n_rows + 255) / 256);
+  const size_t lds = deep_lds_bytes<H, KAM + KB, OM>(a.NH);
+  if (bwd)
+    hipLaunchKernelGGL((k_deep_row_bwd<H, KAM, KB, OM>), dim3(grid), dim3(256), lds, s, a);
+  else
+    hipLaunchKernelGGL((k_deep_row_fwd<H, KAM, KB, OM>), dim3(grid), dim3(256), lds, s, a);
+  return hipGetLastError();
+}
+
+template <int H>
+static hipError_t row_launch_h(const DeepRowArgs& a, DeepRowKind kind, bool bwd, hipStream_t s) {
+  switch (kind) {
+    case DeepRowKind::kSmallIn: return row_launch<H, 4, 0, H>(a, bwd, s);
+    case DeepRowKind::kSmallOut: return row_launch<H, H, 0, 4>(a, bwd, s);
+    case DeepRowKind::kWide: return row_launch<H, H, 0, H>(a, bwd, s);
+    case DeepRowKind::kNode: return row_launch<H, H, H, H>(a, bwd, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_deep_row(const DeepRowArgs& a, int H, DeepRowKind kind, bool bwd, hipStream_t s) {
+  if (a.n_rows == 0) return hipSuccess;
+  if (H == 8) return row_launch_h<8>(a, kind, bwd, s);
+  if (H == 16) return row_launch_h<16>(a, kind, bwd, s);
+  if (H == 32) return row_launch_h<32>(a, kind, bwd, s);
+  return hipErrorInvalidValue;
+}
+
+template <int H>
+static hipError_t edge_launch(const DeepEdgeArgs& a, bool bwd, hipStream_t s) {
+  const int grid = (int)((a.g.n_rows + 255) / 256);
+  const size_t lds = deep_lds_bytes<H, 3 * H, H>(a.NH);
+  if (bwd)
+    hipLaunchKernelGGL(k_deep_edge_bwd<H>, dim3(grid), dim3(256), lds, s, a);
+  else
+    hipLaunchKernelGGL(k_deep_edge_fwd<H>, dim3(grid), dim3(256), lds, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_deep_edge(const DeepEdgeArgs& a, int H, bool bwd, hipStream_t s) {
+  if (H == 8) return edge_launch<8>(a, bwd, s);
+  if (H == 16) return edge_launch<16>(a, bwd, s);
+  if (H == 32) return edge_launch<32>(a, bwd, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_deep_gather(int H, const DevGraph& g, const float* gxn, const float* gxi, const float* gxj,
+                              float* gx, hipStream_t s) {
+  const int grid = (int)((g.n_rows + 255) / 256);
+  if (H == 8) hipLaunchKernelGGL(k_deep_gather<8>, dim3(grid), dim3(256), 0, s, g, gxn, gxi, gxj, gx);
+  else if (H == 16) hipLaunchKernelGGL(k_deep_gather<16>, dim3(grid), dim3(256), 0, s, g, gxn, gxi, gxj, gx);
+  else if (H == 32) hipLaunchKernelGGL(k_deep_gather<32>, dim3(grid), dim3(256), 0, s, g, gxn, gxi, gxj, gx);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+bool outer_fits(int gw, int aw) {
+  return gw >= 1 && gw <= kOuterGW && aw >= 0 && aw <= kOuterAW && gw * (aw + 1) <= 256 * kOuterEPT;
+}
+
+hipError_t launch_outer_sum(const OuterArgs& a, int n_mats, int64_t n_chunks, hipStream_t s) {
+  if (n_mats <= 0 || n_mats > kMaxOuterMats || n_chunks <= 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_outer_sum, dim3((unsigned)n_chunks, n_mats), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace mp

@@ -353,7 +353,9 @@ hipError_t launch_halo(int H, const DevGraph& g, float* a, hipStream_t s) {
   if (g.n_groups == 0) return hipSuccess;
   const int64_t threads = g.n_groups * (H / 4);
   const int grid = (int)((threads + 255) / 256);
-  if (H == 32) hipLaunchKernelGGL(k_halo<32>, dim3(grid), dim3(256), 0, s, g.n_groups, g.group_ptr, g.member, a);
+  if (H == 8) hipLaunchKernelGGL(k_halo<8>, dim3(grid), dim3(256), 0, s, g.n_groups, g.group_ptr, g.member, a);
+  else if (H == 16) hipLaunchKernelGGL(k_halo<16>, dim3(grid), dim3(256), 0, s, g.n_groups, g.group_ptr, g.member, a);
+  else if (H == 32) hipLaunchKernelGGL(k_halo<32>, dim3(grid), dim3(256), 0, s, g.n_groups, g.group_ptr, g.member, a);
   else if (H == 64) hipLaunchKernelGGL(k_halo<64>, dim3(grid), dim3(256), 0, s, g.n_groups, g.group_ptr, g.member, a);
   else if (H == 128) hipLaunchKernelGGL(k_halo<128>, dim3(grid), dim3(256), 0, s, g.n_groups, g.group_ptr, g.member, a);
   else return hipErrorInvalidValue;

@@ -211,4 +211,75 @@ struct GqArgs {
 };
 hipError_t launch_gq(const GqArgs& a, int grid, hipStream_t s);
 
+// ------------------------------------------------ narrow deep MLPs
+// (hidden width 8, 16 or 32; n_hidden extra H -> H layers; FP32; one
+// thread per row).  Parameters of one MLP are one flat FP32 array in
+// torch.nn.Linear order: W0[H][K] b0[H], n_hidden x (W[H][H] b[H]),
+// Wo[O][H] bo[O], then LayerNorm gain[O] and shift[O].
+__host__ __device__ constexpr int64_t deep_theta_floats(int K, int H, int NH, int O, int ln) {
+  return (int64_t)H * K + H + (int64_t)NH * (H * H + H) + (int64_t)O * H + O + (ln ? 2 * O : 0);
+}
+// floats of one row's adjoint record (padded input width km, output om)
+int deep_rec_floats(int H, int km, int om, int NH, int ln);
+
+enum class DeepRowKind { kSmallIn, kSmallOut, kWide, kNode };
+// kSmallIn: in = src_a (1..4 features) -> H;  kSmallOut: H -> 1..4;
+// kWide: H -> H;  kNode: [src_a (H), src_b (H)] -> H, optionally residual.
+struct DeepRowArgs {
+  int64_t n_rows;
+  const float* theta;
+  int NH, ka, O, ln;
+  float eps;
+  const float* src_a;
+  const float* src_b;
+  int resid;           // out = src_b + MLP (kNode only)
+  float* out;
+  const float* g_out;  // adjoint: [n][O]
+  float* g_a;          // [n][ka] or NULL
+  float* g_b;          // [n][H] (kNode), includes g_out when resid
+  float* rec;          // per-row records, rs floats each
+  int rs;
+};
+hipError_t launch_deep_row(const DeepRowArgs& a, int H, DeepRowKind kind, bool bwd, hipStream_t s);
+
+struct DeepEdgeArgs {
+  DevGraph g;
+  const float* theta;
+  int NH, ln;
+  float eps;
+  const float* x;      // [N][H]
+  const float* e_in;   // [E][H]
+  float* e_out;        // forward: [E][H]
+  float* a_out;        // forward: [N][H]
+  const float* g_a;    // adjoint: gradient of the aggregate after the halo adjoint
+  const float* g_e_out;  // [E][H] or NULL
+  float* g_e_in;       // [E][H]
+  float* gxi;          // [N][H] receiver-side input gradient
+  float* gxj;          // [E][H] sender-side input gradient per edge
+  float* rec;
+  int rs;
+};
+hipError_t launch_deep_edge(const DeepEdgeArgs& a, int H, bool bwd, hipStream_t s);
+hipError_t launch_deep_gather(int H, const DevGraph& g, const float* gxn, const float* gxi, const float* gxj,
+                              float* gx, hipStream_t s);
+
+// Weight-gradient partial sums over chunks of record rows.
+struct OuterMat {
+  int g_off, gw;     // G block: record columns [g_off, g_off + gw)
+  int a_off, aw;     // A block (a_off < 0: none)
+  int64_t dst_w, dst_b;  // offsets in the flat gradient of sum G^T A and sum G
+};
+constexpr int kMaxOuterMats = 12;
+struct OuterArgs {
+  const float* rec;
+  int64_t n_rows;
+  int rs;
+  int64_t ch;        // rows per chunk
+  float* part;       // [n_chunks][slab]
+  int64_t slab;
+  OuterMat m[kMaxOuterMats];
+};
+bool outer_fits(int gw, int aw);
+hipError_t launch_outer_sum(const OuterArgs& a, int n_mats, int64_t n_chunks, hipStream_t s);
+
 }  // namespace mp

@@ -9,7 +9,8 @@ import numpy as np
 import torch
 
 from .graph import DeviceGraph, build_graph
-from .ops import (ConsistentMSEFn, MLPFn, MPLayerFn, edge_inputs, layer_cfg, mlp_cfg)
+from .ops import (ConsistentMSEFn, DeepLayerFn, DeepMLPFn, MLPFn, MPLayerFn, deep_layer_cfg, deep_mlp_cfg,
+                  edge_inputs, layer_cfg, mlp_cfg)
 
 
 def _layer_param_names(m, ln):
@@ -39,8 +40,12 @@ class ConsistentGNN:
     MLP_ORDER = ["W0", "b0", "W1", "b1", "ln_g", "ln_b"]
 
     def __init__(self, spec, params, device="cuda", gemm="f32", halo=True, schedule=None):
-        if spec.n_hidden != 0:
-            raise NotImplementedError("the GPU path implements MLPs of two Linear layers")
+        # Table I's narrow models (extra hidden layers, H = 8/16/32) run on
+        # the deep-MLP kernels; two-Linear MLPs at H = 32/64/128 on the
+        # matrix-core kernels.
+        self.deep = spec.n_hidden > 0 or spec.H in (8, 16)
+        if self.deep and (gemm != "f32" or spec.H not in (8, 16, 32)):
+            raise ValueError("deep MLPs run in FP32 at H = 8, 16 or 32")
         self.spec, self.gemm, self.halo = spec, gemm, halo
         # edge-kernel schedule: None (library defaults) or a dict with
         # tile_edges / edge_grid / edge_bwd_grid (see autotune.py)
@@ -54,7 +59,18 @@ class ConsistentGNN:
             t.requires_grad_(flag)
         return self
 
+    def _theta(self, prefix, ln):
+        """The MLP's parameters as one flat tensor (differentiable)."""
+        names = [f"{prefix}.lin{k}.{t}" for k in range(self.spec.n_hidden + 2) for t in ("W", "b")]
+        if ln:
+            names += [f"{prefix}.ln.g", f"{prefix}.ln.b"]
+        return torch.cat([self.params[n].reshape(-1) for n in names])
+
     def _mlp(self, prefix, x, n_in, n_out, ln):
+        if self.deep:
+            s = self.spec
+            cfg = deep_mlp_cfg(n_in, s.H, s.n_hidden, n_out, ln, s.ln_eps)
+            return DeepMLPFn.apply(cfg, x, self._theta(prefix, ln))
         names = _mlp_param_names(prefix, ln)
         cfg = mlp_cfg(n_in, self.spec.H, n_out, ln, self.gemm, self.spec.ln_eps)
         args = [self.params[names[f]] if f in names else None for f in self.MLP_ORDER]
@@ -68,6 +84,12 @@ class ConsistentGNN:
 
     def process(self, dg, x, e):
         s = self.spec
+        if self.deep:
+            cfg = deep_layer_cfg(s.H, s.n_hidden, s.layernorm, self.halo, s.ln_eps)
+            for m in range(s.n_layers):
+                x, e = DeepLayerFn.apply(cfg, dg, x, e, self._theta(f"mp{m}.edge", s.layernorm),
+                                         self._theta(f"mp{m}.node", s.layernorm))
+            return x, e
         cfg = layer_cfg(s.H, s.layernorm, self.halo, self.gemm, s.ln_eps)
         if self.schedule:
             cfg.tile_edges = int(self.schedule.get("tile_edges", 0))

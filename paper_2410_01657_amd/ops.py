@@ -9,8 +9,8 @@ import ctypes as C
 
 import torch
 
-from ._lib import (LAYER_FIELDS, MLP_FIELDS, MP_BF16, MP_F32, MpLayerCfg, MpLayerGrads,
-                   MpLayerParams, MpMlpCfg, MpMlpGrads, MpMlpParams, call)
+from ._lib import (LAYER_FIELDS, MLP_FIELDS, MP_BF16, MP_F32, MpDeepLayerCfg, MpDeepMlpCfg, MpLayerCfg,
+                   MpLayerGrads, MpLayerParams, MpMlpCfg, MpMlpGrads, MpMlpParams, call)
 
 _GEMM = {"f32": MP_F32, "bf16": MP_BF16}
 
@@ -180,6 +180,96 @@ class MLPFn(torch.autograd.Function):
         want = ctx.needs_input_grad[1] and ctx.cfg.n_in > 4
         g_in, grads = mlp_backward(ctx.cfg, p, x, g_out.contiguous(), want)
         return (None, g_in) + tuple(grads[f] for f in MLP_FIELDS)
+
+
+# ------------------------------------------- narrow deep MLPs (Table I)
+# Each MLP's parameters travel as one flat FP32 tensor in torch.nn.Linear
+# order (W0, b0, hidden W/b pairs, Wo, bo, LayerNorm gain and shift).
+
+def deep_layer_cfg(H, n_hidden, layernorm=True, halo=True, ln_eps=1e-5):
+    c = MpDeepLayerCfg()
+    c.H, c.n_hidden, c.layernorm, c.halo, c.ln_eps = H, n_hidden, int(layernorm), int(halo), ln_eps
+    return c
+
+
+def deep_mlp_cfg(n_in, H, n_hidden, n_out, layernorm, ln_eps=1e-5):
+    c = MpDeepMlpCfg()
+    c.n_in, c.H, c.n_hidden, c.n_out, c.layernorm, c.ln_eps = n_in, H, n_hidden, n_out, int(layernorm), ln_eps
+    return c
+
+
+def deep_theta_size(n_in, H, n_hidden, n_out, layernorm):
+    n = C.c_int64()
+    call("mp_deep_theta_size", n_in, H, n_hidden, n_out, int(layernorm), C.byref(n))
+    return n.value
+
+
+class DeepMLPFn(torch.autograd.Function):
+    """Encoder / decoder MLP with n_hidden extra layers: (x, theta) -> out."""
+
+    @staticmethod
+    def forward(ctx, cfg, x, theta):
+        _check(x, theta)
+        if theta.numel() != deep_theta_size(cfg.n_in, cfg.H, cfg.n_hidden, cfg.n_out, cfg.layernorm):
+            raise ValueError("flat MLP parameter array has the wrong size")
+        if x.shape[1] != cfg.n_in:
+            raise ValueError("input width does not match the MLP")
+        out = torch.empty((x.shape[0], cfg.n_out), dtype=torch.float32, device=x.device)
+        call("mp_deep_mlp_forward", C.byref(cfg), _p(theta), x.shape[0], _p(x), _p(out), _stream())
+        ctx.cfg = cfg
+        ctx.save_for_backward(x, theta)
+        return out
+
+    @staticmethod
+    def backward(ctx, g_out):
+        x, theta = ctx.saved_tensors
+        cfg = ctx.cfg
+        g_out = g_out.contiguous()
+        g_in = torch.empty_like(x) if ctx.needs_input_grad[1] else None
+        g_theta = torch.empty_like(theta)
+        nb = C.c_size_t()
+        call("mp_deep_mlp_workspace_size", C.byref(cfg), x.shape[0], 1, C.byref(nb))
+        ws = WS.get(nb.value, x.device)
+        call("mp_deep_mlp_backward", C.byref(cfg), _p(theta), x.shape[0], _p(x), _p(g_out), _p(g_in),
+             _p(g_theta), _p(ws), ws.numel(), _stream())
+        return None, g_in, g_theta
+
+
+class DeepLayerFn(torch.autograd.Function):
+    """(x, e, theta_edge, theta_node) -> (x', e') for deep MLPs, with the
+    library's adjoint as backward."""
+
+    @staticmethod
+    def forward(ctx, cfg, dg, x, e, theta_e, theta_n):
+        _check(x, e, theta_e, theta_n)
+        H = cfg.H
+        if (theta_e.numel() != deep_theta_size(3 * H, H, cfg.n_hidden, H, cfg.layernorm)
+                or theta_n.numel() != deep_theta_size(2 * H, H, cfg.n_hidden, H, cfg.layernorm)):
+            raise ValueError("flat MLP parameter arrays have the wrong size")
+        if tuple(x.shape) != (dg.n_rows, H) or tuple(e.shape) != (dg.n_edges, H):
+            raise ValueError("state shapes do not match the graph and H")
+        x_out, e_out, a_star = torch.empty_like(x), torch.empty_like(e), torch.empty_like(x)
+        call("mp_deep_layer_forward", C.byref(cfg), _p(theta_e), _p(theta_n), C.byref(dg.desc), _p(x), _p(e),
+             _p(x_out), _p(e_out), _p(a_star), _stream())
+        ctx.cfg, ctx.dg = cfg, dg
+        ctx.set_materialize_grads(False)
+        ctx.save_for_backward(x, e, a_star, theta_e, theta_n)
+        return x_out, e_out
+
+    @staticmethod
+    def backward(ctx, g_x_out, g_e_out):
+        x, e, a_star, theta_e, theta_n = ctx.saved_tensors
+        g_x_out = g_x_out.contiguous() if g_x_out is not None else torch.zeros_like(x)
+        g_e_out = g_e_out.contiguous() if g_e_out is not None else None
+        g_x, g_e = torch.empty_like(x), torch.empty_like(e)
+        g_te, g_tn = torch.empty_like(theta_e), torch.empty_like(theta_n)
+        nb = C.c_size_t()
+        call("mp_deep_layer_workspace_size", C.byref(ctx.cfg), C.byref(ctx.dg.desc), 1, C.byref(nb))
+        ws = WS.get(nb.value, x.device)
+        call("mp_deep_layer_backward", C.byref(ctx.cfg), _p(theta_e), _p(theta_n), C.byref(ctx.dg.desc), _p(x),
+             _p(e), _p(a_star), _p(g_x_out), _p(g_e_out), _p(g_x), _p(g_e), _p(g_te), _p(g_tn), _p(ws),
+             ws.numel(), _stream())
+        return None, None, g_x, g_e, g_te, g_tn
 
 
 # ----------------------------------------------------------- inputs, loss

@@ -7,11 +7,10 @@ the GPU, on a 32^3-element p = 1 box (33^3 nodes):
 * SGD training from the same start at R = 1 and R = 8: the consistent R = 8
   curve follows the R = 1 curve, the "None" curve drifts away.
 
-Fig. 6 uses the "small" model of Table I (H = 8, two hidden H -> H layers).
-The GPU kernels implement two-Linear MLPs at H = 32, 64 or 128, so the model
-here is H = 32, four layers, LayerNorm; the property shown does not depend on
-the model.  The loss values themselves are checked against the FP64 oracle
-at R = 1 and, in "None" mode, at R = 8.
+Both run with the model Fig. 6 uses, Table I's "small" one (H = 8, two
+hidden H -> H layers per MLP, on the deep-MLP kernels), and with an H = 32
+two-Linear model on the matrix-core kernels.  The loss values themselves
+are checked against the FP64 oracle at R = 1 and, in "None" mode, at R = 8.
 """
 
 import numpy as np
@@ -29,18 +28,20 @@ pytestmark = pytest.mark.gpu
 DEV = "cuda"
 
 NEL = (32, 32, 32)
-SPEC = ModelSpec(H=32, n_layers=4, layernorm=True)
+SPECS = {"table1_small": ModelSpec(H=8, n_layers=4, n_hidden=2, layernorm=True),
+         "h32": ModelSpec(H=32, n_layers=4, layernorm=True)}
 # element blocks per axis for each sub-graph count (cut planes: 1, 2, 3, 5, 7, 9)
 BLOCKS = {1: (1, 1, 1), 2: (2, 1, 1), 4: (2, 2, 1), 8: (2, 2, 2),
           16: (4, 2, 2), 32: (4, 4, 2), 64: (4, 4, 4)}
 
 
-@pytest.fixture(scope="module")
-def setup():
+@pytest.fixture(scope="module", params=sorted(SPECS))
+def setup(request):
+    spec = SPECS[request.param]
     mesh = box_mesh(NEL, 1)
     field = velocity_field(mesh.pos, seed=11, noise_sigma=0.01)
-    params = init_params(SPEC, seed=12, perturb=True)
-    return mesh, field, params
+    params = init_params(spec, seed=12, perturb=True)
+    return spec, mesh, field, params
 
 
 def _problem(mesh, field, R):
@@ -59,7 +60,7 @@ def test_loss_vs_r_sweep(setup):
     sums the outputs drift further from R = 1 as the share of boundary nodes
     grows (RMS over every row copy), and the loss moves with them."""
     from paper_2410_01657_amd.model import ConsistentGNN
-    mesh, field, params = setup
+    SPEC, mesh, field, params = setup
     cons = ConsistentGNN(SPEC, params, DEV, halo=True)
     none = ConsistentGNN(SPEC, params, DEV, halo=False)
     Rs = sorted(BLOCKS)
@@ -99,10 +100,10 @@ def test_loss_vs_r_sweep(setup):
     assert abs(Ln[8] - Lo8n) / Lo8n < 1e-5
 
 
-def _curve(mesh, field, params, R, halo, steps, lr):
+def _curve(spec, mesh, field, params, R, halo, steps, lr):
     from paper_2410_01657_amd.model import ConsistentGNN
     prob = _problem(mesh, field, R)
-    model = ConsistentGNN(SPEC, params, DEV, halo=halo).requires_grad_(True)
+    model = ConsistentGNN(spec, params, DEV, halo=halo).requires_grad_(True)
     losses = torch.empty(steps, dtype=torch.float64, device=DEV)
     for it in range(steps):
         for t in model.params.values():
@@ -120,11 +121,11 @@ def _curve(mesh, field, params, R, halo, steps, lr):
 def test_training_1500_iterations_r1_vs_r8(setup):
     """Right panel of Fig. 6: 1,500 SGD iterations (forward, consistent loss,
     backward, update) at R = 1, and at R = 8 with and without halo sums."""
-    mesh, field, params = setup
+    spec, mesh, field, params = setup
     steps, lr = 1500, 0.01
-    l1 = _curve(mesh, field, params, 1, True, steps, lr)
-    l8 = _curve(mesh, field, params, 8, True, steps, lr)
-    l8n = _curve(mesh, field, params, 8, False, steps, lr)
+    l1 = _curve(spec, mesh, field, params, 1, True, steps, lr)
+    l8 = _curve(spec, mesh, field, params, 8, True, steps, lr)
+    l8n = _curve(spec, mesh, field, params, 8, False, steps, lr)
     dc = np.abs(l8 - l1) / l1
     dn = np.abs(l8n - l1) / l1
     print("loss R=1 at 0/500/1000/1499:", l1[[0, 500, 1000, 1499]].tolist())
