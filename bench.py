@@ -10,7 +10,9 @@ node.  Seeded synthetic Taylor-Green-like input, Xavier-uniform weights.
 (32^3 elements of order 7, 64 uneven sub-graphs) and `--workload T2R8`
 (the periodic 16 x 16 x 128-element p=5 box in the 8 slabs of Table II's
 R=8 row, 518,400 rows each) measure the other fwd+bwd workloads the same
-way.
+way.  `--model table1-small|table1-large` runs a workload with one of the
+paper's own models (Table I: extra hidden layers in every MLP) on the FP32
+deep-MLP kernels instead.
 
 One step = the whole model forward, loss and backward (every layer's edge
 update, aggregation, halo sum, node update and their adjoints, plus the
@@ -44,6 +46,12 @@ WORKLOADS = {
 }
 
 
+# The paper's own models (Table I): four layers, LayerNorm, extra hidden
+# layers in every MLP; they run on the FP32 deep-MLP kernels.
+TABLE1 = {"table1-small": dict(H=8, n_layers=4, n_hidden=2, layernorm=True),
+          "table1-large": dict(H=32, n_layers=4, n_hidden=5, layernorm=True)}
+
+
 def _progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -66,6 +74,8 @@ def _parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--workload", default="C1", choices=sorted(WORKLOADS))
+    ap.add_argument("--model", default="workload", choices=["workload"] + sorted(TABLE1),
+                    help="the workload's own model, or one of the paper's Table I models")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 comparison path")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-autotune", action="store_true", help="use the library's default schedule")
@@ -149,7 +159,9 @@ def recorded_traffic(kernel, workload):
 
 
 KERNELS = ("pack", "tiles", "proj", "edge_fwd", "halo", "halo_adj", "node_fwd", "node_bwd", "edge_bwd", "edge_dw", "node_dw",
-           "gq", "wreduce", "mlp_fwd", "mlp_bwd", "edge_inputs", "loss")
+           "gq", "wreduce", "mlp_fwd", "mlp_bwd", "edge_inputs", "loss",
+           "deep_edge_fwd", "deep_node_fwd", "deep_node_bwd", "deep_edge_bwd", "deep_gather", "deep_edge_dw",
+           "deep_node_dw", "deep_mlp_fwd", "deep_mlp_bwd", "deep_mlp_dw")
 
 
 def run_path(gemm, spec, params, prob, steps, warmup, schedule):
@@ -196,7 +208,7 @@ def run_path(gemm, spec, params, prob, steps, warmup, schedule):
     return (ms, kernels) + out
 
 
-def cpu_baseline(cfg, inp, n_layers, sample_gids, outs, min_seconds=10.0):
+def cpu_baseline(cfg, spec, inp, n_layers, sample_gids, outs, min_seconds=10.0):
     """The FP64 oracle as it stands, timed on a bounded sample: full model
     fwd+bwd on whole sub-graphs 0, 1, 2, ... one at a time until at least
     `min_seconds` have been spent (for an unpartitioned workload, on the
@@ -227,16 +239,16 @@ def cpu_baseline(cfg, inp, n_layers, sample_gids, outs, min_seconds=10.0):
         T = inp.target.astype(np.float64)[G.gid]
         E0 = edge_inputs(G, mesh.pos, mesh.period)
         t = time.perf_counter()
-        Y, cache = model_fwd(inp.params, cfg.spec, [G], {}, [X], [E0])
+        Y, cache = model_fwd(inp.params, spec, [G], {}, [X], [E0])
         L, gY, _ = consistent_loss(Y, [T], [G])
-        model_bwd(inp.params, cfg.spec, [G], {}, cache, gY)
+        model_bwd(inp.params, spec, [G], {}, cache, gY)
         dt += time.perf_counter() - t
         rows, edges, parts = rows + G.n, edges + G.e, parts + 1
         del Y, cache, gY
         if dt >= min_seconds:
             break
     threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
-    ref = np.stack([ball_output(inp.params, cfg.spec, mesh, inp.field, int(c)) for c in sample_gids])
+    ref = np.stack([ball_output(inp.params, spec, mesh, inp.field, int(c)) for c in sample_gids])
     errs = {}
     for name, Ys in outs.items():
         d = np.abs(Ys - ref)
@@ -259,16 +271,22 @@ def main():
         return
     import torch
 
-    from mpinputs import CONFIGS, make_inputs
+    from mpinputs import CONFIGS, ModelSpec, make_inputs
     from paper_2410_01657_amd.autotune import tuned_schedule
     from paper_2410_01657_amd.model import Problem
-    from paper_2410_01657_amd.roofline import PEAK, PEAK_HBM, bound_of, layer_kernels
+    from paper_2410_01657_amd.roofline import (PEAK, PEAK_HBM, PEAK_VALU, bound_of, deep_kernels,
+                                               layer_kernels)
 
-    wl = WORKLOADS[a.workload]
+    wl = dict(WORKLOADS[a.workload])
     cfg = CONFIGS[a.workload]
     spec = cfg.spec
+    if a.model != "workload":
+        spec = ModelSpec(**TABLE1[a.model])
+        wl["desc"] += (f", with Table I's {a.model.split('-')[1]} model (H={spec.H}, "
+                       f"{spec.n_hidden} hidden layers per MLP, FP32)")
+    deep = spec.n_hidden > 0 or spec.H in (8, 16)
     R = wl["R"] or cfg.R
-    inp = make_inputs(cfg, base_seed=a.seed, R=R)
+    inp = make_inputs(cfg, base_seed=a.seed, R=R, spec=spec)
     prob = Problem(inp.mesh, inp.field, inp.target, inp.elem_part, R, "cuda")
     hg = prob.dg.host
     _progress(f"graph built: {hg.n_rows} rows, {hg.n_edges} edges, {hg.R} sub-graphs")
@@ -281,10 +299,10 @@ def main():
     sample_rows = order[np.searchsorted(hg.row_gid[order], sample_gids)]
 
     copy_gbps = copy_bandwidth()
-    paths = ["bf16"] + ([] if a.no_fp32 else ["f32"])
+    paths = ["f32"] if deep else ["bf16"] + ([] if a.no_fp32 else ["f32"])
     res, outs, scheds = {}, {}, {}
     for gemm in paths:
-        sched = None if a.no_autotune else tuned_schedule(prob.dg, spec.H, spec.layernorm, gemm)
+        sched = None if (a.no_autotune or deep) else tuned_schedule(prob.dg, spec.H, spec.layernorm, gemm)
         scheds[gemm] = sched
         _progress(f"{gemm}: schedule {sched}")
         ms, kern, Y, loss = run_path(gemm, spec, inp.params, prob, a.steps, a.warmup, sched)
@@ -294,19 +312,23 @@ def main():
         del Y
         torch.cuda.empty_cache()
 
-    main_path = res["bf16"]
+    main_gemm = paths[0]
+    main_path = res[main_gemm]
     value = E_global * spec.n_layers / (main_path["ms"] * 1e-3)
 
     def dominant_roofline(gemm):
         """Roofline of the path's longest-running kernel: algorithmic bytes
         (or flops) per launch / its average launch time, against the peak
         of whichever roof bounds that kernel."""
-        work = layer_kernels(N, E, G, M, spec.H, gemm, spec.n_layers)
+        work = (deep_kernels(N, E, G, M, spec.H, spec.n_hidden, spec.n_layers) if deep
+                else layer_kernels(N, E, G, M, spec.H, gemm, spec.n_layers))
         kern = res[gemm]["kernels"]
         dom = max((k for k in kern if k in work), key=lambda k: kern[k]["ms_total"])
         w = work[dom]
         avg_s = kern[dom]["ms_avg"] * 1e-3
-        if bound_of(w, gemm) == "hbm":
+        if deep and w.flops / PEAK_VALU > w.bytes / PEAK_HBM:
+            r = {"bound": "alu", "achieved": w.flops / avg_s / 1e12, "peak": PEAK_VALU / 1e12, "unit": "TFLOP/s"}
+        elif bound_of(w, gemm) == "hbm":
             r = {"bound": "hbm", "achieved": w.bytes / avg_s / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s"}
         else:
             r = {"bound": "mfma", "achieved": w.flops / avg_s / 1e12, "peak": PEAK[gemm] / 1e12,
@@ -315,13 +337,14 @@ def main():
         return dom, w, r
 
     # dominant kernel of the main path and its roofline
-    dom, w, roof = dominant_roofline("bf16")
+    dom, w, roof = dominant_roofline(main_gemm)
     kern = main_path["kernels"]
     tr = recorded_traffic(dom, a.workload)
     roof["traffic"] = tr / 1e9 if tr is not None else None  # GB per launch, measured
     roof["kernel"] = dom
     roof["ms_avg"] = kern[dom]["ms_avg"]
     roof["algorithmic_GB"] = w.bytes / 1e9
+    roof["algorithmic_GFLOP"] = w.flops / 1e9
     roof["traffic_unit"] = "GB per launch (HBM read + write)"
     # context: the same kernel against the bandwidth a plain 2 GiB copy reaches
     if roof["bound"] == "hbm":
@@ -339,14 +362,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16",
+        "dtype": "bf16" if main_gemm == "bf16" else "f32",
         "data": "synthetic",
         "config": {"workload": wl["desc"], "sub_graphs": hg.R, "sub_graph_rows": N, "sub_graph_edges": E,
                    "halo_groups": G, "halo_members": M, "global_edges": E_global, "layers": spec.n_layers,
                    "H": spec.H, "schedule": scheds},
         "roofline": roof,
     }
-    if "f32" in res:
+    if "f32" in res and main_gemm != "f32":
         dom32, w32, roof32 = dominant_roofline("f32")
         roof32.update({"kernel": dom32, "ms_avg": res["f32"]["kernels"][dom32]["ms_avg"]})
         line["fp32"] = {"value": E_global * spec.n_layers / (res["f32"]["ms"] * 1e-3),
@@ -355,7 +378,7 @@ def main():
     line["kernels"] = {g: {k: round(v["ms_total"], 4) for k, v in res[g]["kernels"].items()} for g in res}
     if not a.no_cpu_baseline:
         _progress("timing the FP64 oracle on a bounded sample")
-        base, errs = cpu_baseline(cfg, inp, spec.n_layers, sample_gids, outs)
+        base, errs = cpu_baseline(cfg, spec, inp, spec.n_layers, sample_gids, outs)
         line["cpu_baseline"] = base
         line["rel_error_vs_fp64"] = errs
     print(json.dumps(line), flush=True)

@@ -822,7 +822,7 @@ struct DeepLayerWs {
     take(recE, (size_t)E * rsE);
     take(ga, (size_t)N * H);
     take(gxn, (size_t)N * H);
-    take(gxi, (size_t)N * H);
+    take(gxi, (size_t)E * H);
     take(gxj, (size_t)E * H);
     take(partN, (size_t)deep_chunks(N) * deep_theta_floats(2 * H, H, NH, H, ln));
     take(partE, (size_t)deep_chunks(E) * deep_theta_floats(3 * H, H, NH, H, ln));

@@ -19,9 +19,9 @@
 // record in the workspace, the MLP input, every hidden activation, every
 // pre-activation gradient and the LayerNorm terms; input gradients leave
 // the row kernels directly.  Weight gradients are then sums over rows of
-// outer products of record columns, formed per chunk of rows by
-// k_outer_sum and added chunk by chunk in a fixed order (k_wreduce), so
-// results are bitwise reproducible.  The sender-side input gradient of
+// outer products of record columns, formed per chunk of rows on the matrix
+// unit by k_outer_sum and added chunk by chunk in a fixed order
+// (k_wreduce), so results are bitwise reproducible.  The sender-side input gradient of
 // each edge is written per edge and gathered at the sender through the
 // reverse-edge index (k_deep_gather), in CSR order.
 #include <hip/hip_runtime.h>
@@ -89,17 +89,32 @@ __device__ void stage_deep(float* __restrict__ L, const float* __restrict__ thet
   }
 }
 
+// An opaque zero that is only available once `dep` is: an LDS address
+// built from it cannot be read before dep has been computed.
+__device__ __forceinline__ int opaque_zero_after(float dep) {
+  int z = 0;
+  asm volatile("" : "+v"(z) : "v"(dep));
+  return z;
+}
+
+__device__ __forceinline__ int opaque_zero_after4(float d0, float d1, float d2, float d3) {
+  int z = 0;
+  asm volatile("" : "+v"(z) : "v"(d0), "v"(d1), "v"(d2), "v"(d3));
+  return z;
+}
+
 // z = W x + b, W [N][M] row-major in LDS.
-// Every block of four rows reads through its own opaque base, so the
-// compiler cannot merge the whole matrix's reads into a few wide loads
-// placed up front (which would hold the matrix in registers).
+// Each block of four rows reads through a base that depends on the
+// previous block's result, so the compiler cannot issue the whole matrix's
+// reads up front (which would hold the matrix in registers and spill).
 template <int N, int M>
 __device__ __forceinline__ void dlin(const float* __restrict__ W, const float* __restrict__ b, const float (&x)[M],
                                      float (&z)[N]) {
+  constexpr int RB = M >= 64 ? 1 : 4;  // rows per block: about 128 weights in flight
   const float* Wb = W;
 #pragma unroll
   for (int o = 0; o < N; ++o) {
-    if (o % 4 == 0) Wb = W + opaque_zero();
+    if (o % RB == 0) Wb = W + (o ? opaque_zero_after(z[o - 1]) : opaque_zero());
     float s = b[o];
 #pragma unroll
     for (int c = 0; c < M; c += 4) {
@@ -110,21 +125,24 @@ __device__ __forceinline__ void dlin(const float* __restrict__ W, const float* _
       s = fmaf(w.w, x[c + 3], s);
     }
     z[o] = s;
-    if (o % 4 == 3) __builtin_amdgcn_sched_barrier(0);  // bound the reads in flight
+    if (o % RB == RB - 1) __builtin_amdgcn_sched_barrier(0);  // bound the reads in flight
   }
 }
 
 // gx[c] = sum_o W[o][C0 + c] gz[o] for c < MW (a column block of W^T gz).
-// Column blocks of four outermost, so each block's sums finish before the
-// next block's weights are read.
+// Column blocks of four outermost, each reading through a base that depends
+// on all four of the previous block's sums (as in dlin).
 template <int N, int M, int C0, int MW>
 __device__ __forceinline__ void dlin_t(const float* __restrict__ W, const float (&gz)[N], float (&gx)[MW]) {
 #pragma unroll
   for (int c = 0; c < MW; c += 4) {
-    const float* Wb = W + opaque_zero();
+    const float* Wb = W + (c ? opaque_zero_after4(gx[c - 4], gx[c - 3], gx[c - 2], gx[c - 1]) : opaque_zero());
     float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
 #pragma unroll
     for (int o = 0; o < N; ++o) {
+      // eight rows in flight; all four sums gate the next reads (gating on
+      // one would let the other three hold their weights in registers)
+      if (o > 0 && o % 8 == 0) Wb = W + opaque_zero_after4(s0, s1, s2, s3);
       const float4 w = *reinterpret_cast<const float4*>(Wb + o * M + C0 + c);
       s0 = fmaf(w.x, gz[o], s0);
       s1 = fmaf(w.y, gz[o], s1);
@@ -319,8 +337,8 @@ __global__ __launch_bounds__(256) void k_deep_row_bwd(DeepRowArgs a) {
   if (r >= a.n_rows) return;
   float* rec = a.rec + r * a.rs;
   float d0[H];
-  float gy[OM];
   {
+    float gy[OM];
     float in[K::KM];
     K::load_in(a, r, in);
     vstore<K::KM>(rec + rr.in(), in);
@@ -358,8 +376,10 @@ __global__ __launch_bounds__(256) void k_deep_row_bwd(DeepRowArgs a) {
     dlin_t<H, K::KM, KAM, KB>(Lb + m.w0(), d0, t);
     if constexpr (KB == OM) {
       if (a.resid) {
+        float go[OM];
+        vload<OM>(a.g_out + r * OM, go);  // re-read rather than kept live
 #pragma unroll
-        for (int c = 0; c < KB; ++c) t[c] += gy[c];
+        for (int c = 0; c < KB; ++c) t[c] += go[c];
       }
     }
     vstore<KB>(a.g_b + r * KB, t);
@@ -421,11 +441,9 @@ __global__ __launch_bounds__(256) void k_deep_edge_bwd(DeepEdgeArgs a) {
   __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.g.n_rows) return;
-  float xi[H], ga[H], gxi[H];
-  vload<H>(a.x + i * H, xi);
-  vload<H>(a.g_a + i * H, ga);
-#pragma unroll
-  for (int c = 0; c < H; ++c) gxi[c] = 0.f;
+  // Nothing row-sized is carried from edge to edge: x_i and g_a_i are
+  // re-read (cache hits) and each edge's receiver-side gradient is written
+  // out, which keeps the recompute and the adjoint within the register file.
   const int k1 = a.g.rowptr[i + 1];
   for (int k = a.g.rowptr[i]; k < k1; ++k) {
     const float* Lk = L + opaque_zero();  // re-read the weights per edge
@@ -434,9 +452,10 @@ __global__ __launch_bounds__(256) void k_deep_edge_bwd(DeepEdgeArgs a) {
     float gy[H], d0[H];
     {
       float in[KM];
-#pragma unroll
-      for (int c = 0; c < H; ++c) in[c] = xi[c];
       float t[H];
+      vload<H>(a.x + i * H, t);
+#pragma unroll
+      for (int c = 0; c < H; ++c) in[c] = t[c];
       vload<H>(a.x + (int64_t)a.g.col[k] * H, t);
 #pragma unroll
       for (int c = 0; c < H; ++c) in[H + c] = t[c];
@@ -453,8 +472,9 @@ __global__ __launch_bounds__(256) void k_deep_edge_bwd(DeepEdgeArgs a) {
 #pragma unroll
         for (int c = 0; c < H; ++c) gy[c] = 0.f;
       }
+      vload<H>(a.g_a + i * H, t);
 #pragma unroll
-      for (int c = 0; c < H; ++c) gy[c] += ga[c] * inv_d;
+      for (int c = 0; c < H; ++c) gy[c] += t[c] * inv_d;
       float gu[H];
 #pragma unroll
       for (int c = 0; c < H; ++c) gu[c] = gy[c];
@@ -464,11 +484,10 @@ __global__ __launch_bounds__(256) void k_deep_edge_bwd(DeepEdgeArgs a) {
     }
     Lk = L + opaque_zero();
     float t[H];
-    dlin_t<H, KM, 0, H>(Lk + m.w0(), d0, t);  // receiver part
-#pragma unroll
-    for (int c = 0; c < H; ++c) gxi[c] += t[c];
+    dlin_t<H, KM, 0, H>(Lk + m.w0(), d0, t);  // receiver part, summed by k_deep_gather
+    vstore<H>(a.gxi + (int64_t)k * H, t);
     phase_fence();
-    dlin_t<H, KM, H, H>(Lk + m.w0(), d0, t);  // sender part, gathered later
+    dlin_t<H, KM, H, H>(Lk + m.w0(), d0, t);  // sender part, gathered through rev
     vstore<H>(a.gxj + (int64_t)k * H, t);
     phase_fence();
     dlin_t<H, KM, 2 * H, H>(Lk + m.w0(), d0, t);  // edge-state part + residual
@@ -476,11 +495,11 @@ __global__ __launch_bounds__(256) void k_deep_edge_bwd(DeepEdgeArgs a) {
     for (int c = 0; c < H; ++c) t[c] += gy[c];
     vstore<H>(a.g_e_in + (int64_t)k * H, t);
   }
-  vstore<H>(a.gxi + i * H, gxi);
 }
 
-// g_x[j] = g_x_node[j] + receiver part[j] + sender parts of j's outgoing
-// edges (the reverses of its incoming edges), in CSR order.
+// g_x[j] = g_x_node[j] + the input gradients of j's incoming edges (their
+// receiver parts) and of j's outgoing edges (the reverses of its incoming
+// edges; their sender parts), in CSR order.
 template <int H>
 __global__ __launch_bounds__(256) void k_deep_gather(DevGraph g, const float* __restrict__ gxn,
                                                      const float* __restrict__ gxi, const float* __restrict__ gxj,
@@ -489,11 +508,11 @@ __global__ __launch_bounds__(256) void k_deep_gather(DevGraph g, const float* __
   if (j >= g.n_rows) return;
   float s[H], t[H];
   vload<H>(gxn + j * H, s);
-  vload<H>(gxi + j * H, t);
-#pragma unroll
-  for (int c = 0; c < H; ++c) s[c] += t[c];
   const int k1 = g.rowptr[j + 1];
   for (int k = g.rowptr[j]; k < k1; ++k) {
+    vload<H>(gxi + (int64_t)k * H, t);
+#pragma unroll
+    for (int c = 0; c < H; ++c) s[c] += t[c];
     vload<H>(gxj + (int64_t)g.rev[k] * H, t);
 #pragma unroll
     for (int c = 0; c < H; ++c) s[c] += t[c];
@@ -506,53 +525,72 @@ __global__ __launch_bounds__(256) void k_deep_gather(DevGraph g, const float* __
 // Partial sums over one chunk of rows of G^T [A, 1] for one record block:
 // part[chunk][dst_w + o*aw + c] = sum_r G[r][o] A[r][c] and
 // part[chunk][dst_b + o] = sum_r G[r][o]; without A only the latter.
-constexpr int kOuterTR = 32, kOuterGW = 64, kOuterAW = 96, kOuterEPT = 13;
-__global__ __launch_bounds__(256) void k_outer_sum(OuterArgs a) {
-  __shared__ float Gs[kOuterTR][kOuterGW];
-  __shared__ float As[kOuterTR][kOuterAW + 1];
+//
+// One wave per (chunk, block), on the matrix unit with the rows as the
+// reduction dimension: for each group of four rows, v_mfma_f32_16x16x4f32
+// takes from lane l the value G[r + l/16][16 to + l%16] as its A operand and
+// [A, 1][r + l/16][16 tc + l%16] as its B operand, and accumulates the
+// 16 x 16 tile (to, tc) of G^T [A, 1]; lane l then holds rows
+// 4 (l/16) .. 4 (l/16) + 3, column l%16 of each tile.  Rows are added in
+// order, so the partial sums are reproducible.
+constexpr int kOuterTO = 4, kOuterTC = 7;  // up to 64 G and 112 [A, 1] columns
+__global__ __launch_bounds__(64) void k_outer_sum(OuterArgs a) {
   const OuterMat M = a.m[blockIdx.y];
   const bool hasA = M.a_off >= 0;
-  const int aw1 = hasA ? M.aw + 1 : 1;
-  const int n_el = M.gw * aw1;
-  int go[kOuterEPT], ac[kOuterEPT];
-  float acc[kOuterEPT];
+  const int aw = hasA ? M.aw : 0;  // the ones column sits at index aw
+  const int TO = (M.gw + 15) / 16, TC = (aw + 1 + 15) / 16;
+  const int lane = threadIdx.x, k = lane >> 4, col = lane & 15;
+  v4f acc[kOuterTO][kOuterTC];
 #pragma unroll
-  for (int j = 0; j < kOuterEPT; ++j) {
-    const int e = threadIdx.x + 256 * j;
-    go[j] = e < n_el ? e / aw1 : 0;
-    ac[j] = e < n_el ? e % aw1 : 0;
-    acc[j] = 0.f;
-  }
+  for (int to = 0; to < kOuterTO; ++to)
+#pragma unroll
+    for (int tc = 0; tc < kOuterTC; ++tc) acc[to][tc] = v4f{0.f, 0.f, 0.f, 0.f};
   const int64_t r0 = (int64_t)blockIdx.x * a.ch, r1 = std::min<int64_t>(a.n_rows, r0 + a.ch);
-  for (int64_t rb = r0; rb < r1; rb += kOuterTR) {
-    for (int t = threadIdx.x; t < kOuterTR * kOuterGW; t += 256) {
-      const int r = t / kOuterGW, c = t % kOuterGW;
-      const int64_t row = rb + r;
-      Gs[r][c] = (row < r1 && c < M.gw) ? a.rec[row * a.rs + M.g_off + c] : 0.f;
-    }
-    for (int t = threadIdx.x; t < kOuterTR * (kOuterAW + 1); t += 256) {
-      const int r = t / (kOuterAW + 1), c = t % (kOuterAW + 1);
-      const int64_t row = rb + r;
-      float v = 0.f;
-      if (c == aw1 - 1) v = 1.f;
-      else if (hasA && c < M.aw && row < r1) v = a.rec[row * a.rs + M.a_off + c];
-      As[r][c] = v;
-    }
-    __syncthreads();
-    for (int r = 0; r < kOuterTR; ++r) {
+  // kOuterRG groups of four rows per step: all their loads are issued before
+  // the first product, so several row groups' latencies overlap.
+  constexpr int kOuterRG = 4;
+  for (int64_t rb = r0; rb < r1; rb += 4 * kOuterRG) {
+    float g[kOuterRG][kOuterTO], b[kOuterRG][kOuterTC];
 #pragma unroll
-      for (int j = 0; j < kOuterEPT; ++j) acc[j] = fmaf(Gs[r][go[j]], As[r][ac[j]], acc[j]);
+    for (int q = 0; q < kOuterRG; ++q) {
+      const int64_t row = rb + 4 * q + k;
+      const bool rv = row < r1;
+      const float* rp = a.rec + (rv ? row : r0) * a.rs;
+#pragma unroll
+      for (int to = 0; to < kOuterTO; ++to) {
+        const int o = 16 * to + col;
+        g[q][to] = (to < TO && rv && o < M.gw) ? rp[M.g_off + o] : 0.f;
+      }
+#pragma unroll
+      for (int tc = 0; tc < kOuterTC; ++tc) {
+        const int c = 16 * tc + col;
+        b[q][tc] = (tc < TC && rv) ? (c < aw ? rp[M.a_off + c] : (c == aw ? 1.f : 0.f)) : 0.f;
+      }
     }
-    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kOuterRG; ++q)
+#pragma unroll
+      for (int to = 0; to < kOuterTO; ++to)
+#pragma unroll
+        for (int tc = 0; tc < kOuterTC; ++tc)
+          if (to < TO && tc < TC)
+            acc[to][tc] = __builtin_amdgcn_mfma_f32_16x16x4f32(g[q][to], b[q][tc], acc[to][tc], 0, 0, 0);
   }
   float* dst = a.part + (int64_t)blockIdx.x * a.slab;
 #pragma unroll
-  for (int j = 0; j < kOuterEPT; ++j) {
-    const int e = threadIdx.x + 256 * j;
-    if (e >= n_el) continue;
-    if (ac[j] == aw1 - 1) dst[M.dst_b + go[j]] = acc[j];
-    else dst[M.dst_w + (int64_t)go[j] * M.aw + ac[j]] = acc[j];
-  }
+  for (int to = 0; to < kOuterTO; ++to)
+#pragma unroll
+    for (int tc = 0; tc < kOuterTC; ++tc) {
+      if (to >= TO || tc >= TC) continue;
+      const int c = 16 * tc + col;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int o = 16 * to + 4 * k + v;
+        if (o >= M.gw || c > aw) continue;
+        if (c == aw) dst[M.dst_b + o] = acc[to][tc][v];
+        else dst[M.dst_w + (int64_t)o * aw + c] = acc[to][tc][v];
+      }
+    }
 }
 
 // ------------------------------------------------------------- launchers
@@ -625,12 +663,12 @@ hipError_t launch_deep_gather(int H, const DevGraph& g, const float* gxn, const 
 }
 
 bool outer_fits(int gw, int aw) {
-  return gw >= 1 && gw <= kOuterGW && aw >= 0 && aw <= kOuterAW && gw * (aw + 1) <= 256 * kOuterEPT;
+  return gw >= 1 && gw <= 16 * kOuterTO && aw >= 0 && aw + 1 <= 16 * kOuterTC;
 }
 
 hipError_t launch_outer_sum(const OuterArgs& a, int n_mats, int64_t n_chunks, hipStream_t s) {
   if (n_mats <= 0 || n_mats > kMaxOuterMats || n_chunks <= 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_outer_sum, dim3((unsigned)n_chunks, n_mats), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_outer_sum, dim3((unsigned)n_chunks, n_mats), dim3(64), 0, s, a);
   return hipGetLastError();
 }
 

@@ -254,7 +254,7 @@ struct DeepEdgeArgs {
   const float* g_a;    // adjoint: gradient of the aggregate after the halo adjoint
   const float* g_e_out;  // [E][H] or NULL
   float* g_e_in;       // [E][H]
-  float* gxi;          // [N][H] receiver-side input gradient
+  float* gxi;          // [E][H] receiver-side input gradient per edge
   float* gxj;          // [E][H] sender-side input gradient per edge
   float* rec;
   int rs;

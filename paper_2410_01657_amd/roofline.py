@@ -17,6 +17,10 @@ from dataclasses import dataclass
 # MI355X published peaks
 PEAK_HBM = 8.0e12          # bytes/s
 PEAK = {"f32": 157.3e12, "bf16": 2.5e15}   # dense MFMA flop/s by operand type
+# FP32 vector ALU: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2 (packed
+# FP32) x 2.4 GHz.  The library is built without packed FP32 operations, so
+# its own ceiling is half of this (78.6 TFLOP/s).
+PEAK_VALU = 157.3e12
 
 
 @dataclass(frozen=True)
@@ -56,3 +60,30 @@ def layer_kernels(N, E, G, M, H, gemm="bf16", n_layers=1):
 def bound_of(work, gemm):
     """'hbm' or 'mfma': whichever roof takes longer for this work."""
     return "hbm" if work.bytes / PEAK_HBM >= work.flops / PEAK[gemm] else "mfma"
+
+
+def mlp_flops(K, H, NH, O):
+    """Flops of one row through Linear(K->H), NH x Linear(H->H), Linear(H->O)."""
+    return 2.0 * (K * H + NH * H * H + O * H)
+
+
+def deep_kernels(N, E, G, M, H, NH, n_layers=1):
+    """Per launch, one layer of the narrow deep-MLP kernels (keys match the
+    library's profile names).  Bytes: the layer's inputs and outputs only
+    (each row once); the per-row adjoint records the kernels keep in HBM are
+    an implementation choice and not counted.  Flops: the MLP products
+    (recomputed forward plus transposed products in the adjoint kernels; one
+    product per weight per row in the weight-gradient sums)."""
+    f = 4.0
+    ge = (n_layers - 1) / n_layers if n_layers > 1 else 1.0
+    fe, fn = mlp_flops(3 * H, H, NH, H), mlp_flops(2 * H, H, NH, H)
+    return {
+        "deep_edge_fwd": Work(E * (2 * H * f + 5) + N * (3 * H * f + 4), E * fe),
+        "halo": Work(M * 2 * H * f + 4 * (M + G + 1), 0.0),
+        "deep_node_fwd": Work(N * 3 * H * f, N * fn),
+        "deep_node_bwd": Work(N * 5 * H * f, N * 2 * fn),
+        "deep_edge_bwd": Work(E * ((2 + ge) * H * f + 5) + N * (3 * H * f + 4), E * 2 * fe),
+        "deep_gather": Work(E * (H * f + 4) + N * (3 * H * f + 4), 0.0),
+        "deep_edge_dw": Work(0.0, E * fe),
+        "deep_node_dw": Work(0.0, N * fn),
+    }
