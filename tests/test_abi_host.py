@@ -209,3 +209,47 @@ def test_mlp_and_loss_validation(L):
     call("mp_mlp_workspace_size", C.byref(mlp_cfg(64, 64, 3, False)), 10, 1, C.byref(nb))
     with pytest.raises(MPError):
         call("mp_consistent_mse", 0, 3, None, None, None, None, None, None, 0, None)
+
+
+def test_deep_entry_points_validate_before_launch(L):
+    """The deep-MLP entry points reject bad widths, depths, NULL or unaligned
+    buffers, aliasing and short workspaces before any launch."""
+    from paper_2410_01657_amd._lib import MPError, call
+    from paper_2410_01657_amd.ops import deep_layer_cfg, deep_mlp_cfg, deep_theta_size
+    d = _fake_desc(L)
+    nb = C.c_size_t()
+    for bad in (deep_layer_cfg(12, 2), deep_layer_cfg(64, 2), deep_layer_cfg(8, 9), deep_layer_cfg(8, -1)):
+        with pytest.raises(MPError) as e:
+            call("mp_deep_layer_workspace_size", C.byref(bad), C.byref(d), 1, C.byref(nb))
+        assert e.value.code == L.MP_EINVAL
+    cfg = deep_layer_cfg(8, 2)
+    call("mp_deep_layer_workspace_size", C.byref(cfg), C.byref(d), 0, C.byref(nb))
+    assert nb.value == 0
+    call("mp_deep_layer_workspace_size", C.byref(cfg), C.byref(d), 1, C.byref(nb))
+    assert nb.value > 0
+    with pytest.raises(MPError) as e:  # a NULL buffer
+        call("mp_deep_layer_forward", C.byref(cfg), 4096, 4096, C.byref(d), 8192, 12288, 16384, 20480, None,
+             None)
+    assert e.value.code == L.MP_EINVAL
+    with pytest.raises(MPError) as e:  # aliasing
+        call("mp_deep_layer_forward", C.byref(cfg), 4096, 4096, C.byref(d), 8192, 12288, 8192, 20480, 24576,
+             None)
+    assert e.value.code == L.MP_EINVAL
+    with pytest.raises(MPError) as e:  # unaligned
+        call("mp_deep_layer_forward", C.byref(cfg), 4096, 4096, C.byref(d), 8196, 12288, 16384, 20480, 24576,
+             None)
+    assert e.value.code == L.MP_EINVAL
+    with pytest.raises(MPError) as e:  # workspace too small
+        call("mp_deep_layer_backward", C.byref(cfg), 4096, 4096, C.byref(d), 8192, 12288, 16384, 20480, None,
+             24576, 28672, 32768, 36864, 40960, 16, None)
+    assert e.value.code == L.MP_ENOMEM
+    for c in (deep_mlp_cfg(5, 8, 2, 8, True), deep_mlp_cfg(8, 8, 2, 3, True), deep_mlp_cfg(3, 8, 2, 3, False),
+              deep_mlp_cfg(16, 8, 2, 8, False)):
+        with pytest.raises(MPError) as e:
+            call("mp_deep_mlp_workspace_size", C.byref(c), 10, 1, C.byref(nb))
+        assert e.value.code == L.MP_EINVAL
+    call("mp_deep_mlp_workspace_size", C.byref(deep_mlp_cfg(4, 32, 5, 32, True)), 10, 1, C.byref(nb))
+    assert nb.value > 0
+    # flat parameter sizes follow the torch.nn.Linear layout
+    assert deep_theta_size(3, 8, 2, 8, True) == 8 * 3 + 8 + 2 * (64 + 8) + 64 + 8 + 16
+    assert deep_theta_size(8, 8, 0, 3, False) == 64 + 8 + 24 + 3
