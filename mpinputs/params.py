@@ -30,6 +30,7 @@ class ModelSpec:
     edge_in: int = 4
     out: int = 3
     ln_eps: float = 1e-5
+    aggregate: str = "state"  # Eq. 4b sums the updated edge state e'; "message": the MLP output
 
 
 def _mlp_shapes(prefix, fan_in, H, out, n_hidden, ln):

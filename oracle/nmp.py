@@ -171,7 +171,9 @@ def nmp_layer_fwd(params, m, spec, graphs, pair_lists, x_list, e_list, halo=True
         cache["edge"].append(c)
         e2 = e + msg
         e_new.append(e2)
-        a_list.append(local_aggregate(e2, G))                          # Eq. 4b
+        # Eq. 4b sums the updated edge state; the "message" variant sums the
+        # MLP output alone
+        a_list.append(local_aggregate(msg if spec.aggregate == "message" else e2, G))
     a_star = halo_sync(a_list, pair_lists) if halo else a_list         # Eq. 4c-d
     x_new = []
     for r, G in enumerate(graphs):
@@ -196,12 +198,16 @@ def nmp_layer_bwd(params, m, spec, graphs, pair_lists, cache, gx_list, ge_list, 
     ga = halo_sync_adj(ga_star, pair_lists) if cache["halo"] else ga_star
     ge_in = []
     for r, G in enumerate(graphs):
-        ge2 = ge_list[r] + local_aggregate_adj(ga[r], G)
-        gin = mlp_bwd(params, pre + ".edge", cache["edge"][r], ge2, spec, ln, grads)
+        # gradient at the MLP output: through e' = e + MLP and through Eq. 4b
+        gmsg = ge_list[r] + local_aggregate_adj(ga[r], G)
+        gin = mlp_bwd(params, pre + ".edge", cache["edge"][r], gmsg, spec, ln, grads)
         gx = gx_in[r]
         np.add.at(gx, G.recv, gin[:, :H])
         np.add.at(gx, G.send, gin[:, H:2 * H])
-        ge_in.append(ge2 + gin[:, 2 * H:])
+        # the residual path carries the gradient of e' (which includes Eq.
+        # 4b's when e' is what is summed)
+        g_res = ge_list[r] if spec.aggregate == "message" else gmsg
+        ge_in.append(g_res + gin[:, 2 * H:])
     return gx_in, ge_in
 
 

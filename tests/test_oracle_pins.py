@@ -292,8 +292,8 @@ def test_consistent_loss_equals_mse(c0_ref):
 # ------------------------------------------------ P5, P6 gradients (Eq. 3)
 
 
-def _tiny(perturb=True, ln=True, H=4, layers=2, hidden=0):
-    spec = ModelSpec(H=H, n_layers=layers, n_hidden=hidden, layernorm=ln)
+def _tiny(perturb=True, ln=True, H=4, layers=2, hidden=0, aggregate="state"):
+    spec = ModelSpec(H=H, n_layers=layers, n_hidden=hidden, layernorm=ln, aggregate=aggregate)
     m = box_mesh((2, 2, 1), 2)
     field = velocity_field(m.pos, 1, noise_sigma=0.05)
     params = init_params(spec, 2, perturb=perturb)
@@ -310,9 +310,10 @@ def _loss_and_grads(spec, m, field, params, part, R):
     return L, grads
 
 
-@pytest.mark.parametrize("ln,hidden", [(True, 0), (False, 0), (True, 1)])
-def test_gradients_vs_central_differences(ln, hidden):
-    spec, m, field, params = _tiny(ln=ln, hidden=hidden)
+@pytest.mark.parametrize("ln,hidden,agg", [(True, 0, "state"), (False, 0, "state"), (True, 1, "state"),
+                                            (True, 0, "message")])
+def test_gradients_vs_central_differences(ln, hidden, agg):
+    spec, m, field, params = _tiny(ln=ln, hidden=hidden, aggregate=agg)
     part = block_partition((2, 2, 1), (2, 1, 1))
     L, grads = _loss_and_grads(spec, m, field, params, part, 2)
     rng = np.random.default_rng(7)
@@ -334,8 +335,9 @@ def test_gradients_vs_central_differences(ln, hidden):
             assert abs(fd - g) <= 2e-8 * max(1.0, abs(g)), (name, idx, fd, g)
 
 
-def test_gradient_consistency_r1_vs_r4():
-    spec, m, field, params = _tiny()
+@pytest.mark.parametrize("agg", ["state", "message"])
+def test_gradient_consistency_r1_vs_r4(agg):
+    spec, m, field, params = _tiny(aggregate=agg)
     L1, g1 = _loss_and_grads(spec, m, field, params, None, 1)
     part = block_partition((2, 2, 1), (2, 2, 1))
     L4, g4 = _loss_and_grads(spec, m, field, params, part, 4)
@@ -510,3 +512,44 @@ def test_periodic_ball_matches_full_graph(periodic_ref):
     for c in (0, n[0] - 1, m.n_gid - 1, n[0] * n[1] * (n[2] - 1) + 5):
         y = ball_output(params, spec, m, field, c)
         np.testing.assert_allclose(y, Y1[c], rtol=0, atol=1e-13)
+
+
+# ------------------------------------------- message aggregation (variant)
+
+
+def _first_layer_aggregate(spec, m, field, params, zero_message=False):
+    prob = build_problem(m, field, field, None, 1)
+    G = prob.graphs[0]
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal((G.n, spec.H))
+    e = rng.standard_normal((G.e, spec.H))
+    p = {k: v.astype(np.float64) for k, v in params.items()}
+    if zero_message:
+        last = spec.n_hidden + 1
+        p[f"mp0.edge.lin{last}.W"][:] = 0.0
+        p[f"mp0.edge.lin{last}.b"][:] = 0.0
+    _, e_new, cache = nmp_layer_fwd(p, 0, spec, [G], {}, [x], [e], halo=False)
+    return G, e, e_new[0], cache["a_star"][0]
+
+
+def test_message_aggregation_sums_the_mlp_output():
+    """With message aggregation the aggregate is the state aggregate minus
+    the aggregate of the incoming edge states (e' = e + m), row by row."""
+    spec, m, field, params = _tiny(ln=False)
+    spec_m = ModelSpec(**{**spec.__dict__, "aggregate": "message"})
+    G, e, e_new, a_state = _first_layer_aggregate(spec, m, field, params)
+    _, _, e_new_m, a_msg = _first_layer_aggregate(spec_m, m, field, params)
+    np.testing.assert_array_equal(e_new, e_new_m)          # edge states do not change
+    ref = np.zeros_like(a_state)
+    for k in range(G.e):                                    # brute-force sum of e / d
+        ref[G.recv[k]] += e[k] / G.d_edge[k]
+    np.testing.assert_allclose(a_msg, a_state - ref, rtol=0, atol=1e-13)
+
+
+def test_message_aggregation_of_a_zero_message_is_zero():
+    """An edge MLP whose last Linear is zero (no LayerNorm) sends nothing:
+    e' = e, the message aggregate is exactly 0, the state aggregate sum e/d."""
+    spec, m, field, params = _tiny(ln=False, aggregate="message")
+    G, e, e_new, a_msg = _first_layer_aggregate(spec, m, field, params, zero_message=True)
+    np.testing.assert_array_equal(e_new, e)
+    assert np.all(a_msg == 0.0)
