@@ -49,6 +49,7 @@ enum {
 };
 
 enum { MP_F32 = 0, MP_BF16 = 1 }; /* arithmetic type of the MLP GEMM operands */
+enum { MP_AGG_STATE = 0, MP_AGG_MESSAGE = 1 }; /* what Eq. 4b sums (mp_layer_cfg.aggregate) */
 
 typedef struct ihipStream_t* mp_stream_t; /* the same type as hipStream_t */
 
@@ -160,6 +161,10 @@ typedef struct {
   int32_t tile_edges;
   int32_t edge_grid;
   int32_t edge_bwd_grid;
+  /* What Eq. 4b sums: MP_AGG_STATE (0) the updated edge state e' = e + MLP
+   * (the equations as written), or MP_AGG_MESSAGE (1) the MLP output alone
+   * (a variant; the edge-state update is unchanged). */
+  int32_t aggregate;
 } mp_layer_cfg;
 
 /* Parameters of one layer, device FP32.  Edge MLP: Linear(3H->H), ELU,
@@ -255,6 +260,7 @@ typedef struct {
   int32_t layernorm;  /* LayerNorm on both MLPs' outputs */
   int32_t halo;       /* 1: consistent (Eq. 4c-d); 0: "None" mode */
   float ln_eps;
+  int32_t aggregate;  /* MP_AGG_STATE or MP_AGG_MESSAGE, as in mp_layer_cfg */
 } mp_deep_layer_cfg;
 
 /* Floats in the flat parameter array of one MLP. */

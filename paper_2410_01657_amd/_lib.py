@@ -13,6 +13,7 @@ LIB_PATH = os.path.join(HERE, "libmplayer.so")
 
 MP_OK, MP_EINVAL, MP_EPLAN, MP_ENOMEM, MP_EHIP = 0, 1, 2, 3, 4
 MP_F32, MP_BF16 = 0, 1
+MP_AGG_STATE, MP_AGG_MESSAGE = 0, 1
 
 c_i32, c_i64, c_u64, c_f32 = C.c_int32, C.c_int64, C.c_uint64, C.c_float
 vp = C.c_void_p
@@ -26,7 +27,8 @@ class MpDevGraph(C.Structure):
 
 class MpLayerCfg(C.Structure):
     _fields_ = [("H", c_i32), ("layernorm", c_i32), ("halo", c_i32), ("gemm_dtype", c_i32),
-                ("ln_eps", c_f32), ("tile_edges", c_i32), ("edge_grid", c_i32), ("edge_bwd_grid", c_i32)]
+                ("ln_eps", c_f32), ("tile_edges", c_i32), ("edge_grid", c_i32), ("edge_bwd_grid", c_i32),
+                ("aggregate", c_i32)]
 
 
 LAYER_FIELDS = ["We1", "be1", "We2", "be2", "ge", "bge", "Wn1", "bn1", "Wn2", "bn2", "gn", "bgn"]
@@ -57,7 +59,8 @@ class MpMlpGrads(C.Structure):
 
 
 class MpDeepLayerCfg(C.Structure):
-    _fields_ = [("H", c_i32), ("n_hidden", c_i32), ("layernorm", c_i32), ("halo", c_i32), ("ln_eps", c_f32)]
+    _fields_ = [("H", c_i32), ("n_hidden", c_i32), ("layernorm", c_i32), ("halo", c_i32), ("ln_eps", c_f32),
+                ("aggregate", c_i32)]
 
 
 class MpDeepMlpCfg(C.Structure):

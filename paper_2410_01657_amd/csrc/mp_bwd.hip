@@ -273,7 +273,9 @@ struct EdgeBwdCfg {
 //   g_e  = gE + W1c^T gh                     (residual + first Linear)
 //   g_P[i] = sum of gh over i's incoming edges (segmented scan, as forward)
 //   g_h[k] = gh, summed per sender by k_gq through the reverse edges.
-template <int H, bool BF>
+// AM: the forward aggregated the MLP output, so the residual path carries
+// only the next layer's gradient (not Eq. 4b's).
+template <int H, bool BF, bool AM>
 __global__ __launch_bounds__((64 * EdgeBwdCfg<H, BF>::NW)) void k_edge_bwd(EdgeBwdArgs a) {
   using C = EdgeBwdCfg<H, BF>;
   constexpr int NF = H / 4, MB = H / 16, NW = C::NW, ROWS = C::ROWS, NT = dw_tiles_per_wave<H, H, NW>();
@@ -453,6 +455,14 @@ __global__ __launch_bounds__((64 * EdgeBwdCfg<H, BF>::NW)) void k_edge_bwd(EdgeB
       for (int i = 0; i < NF; ++i) t[i] *= (u[i] > 0.f ? 1.f : u[i] + 1.f);
       stage_row<H, BF, ROWS>(tG1, srow, g, t);
       stage_row<H, BF, ROWS>(tA1, srow, g, ev);
+      if constexpr (AM) {
+        if (a.g_e_out) {
+          load_row<H>(a.g_e_out + kk * H, g, gE);
+        } else {
+#pragma unroll
+          for (int i = 0; i < NF; ++i) gE[i] = 0.f;
+        }
+      }
       // g_e = gE + W1c^T gh
       gemm<BF, MB, MB>(fW1ct, t, gE, lane);
       if (valid) {
@@ -517,12 +527,17 @@ __global__ __launch_bounds__((64 * EdgeBwdCfg<H, BF>::NW)) void k_edge_bwd(EdgeB
   }
 }
 
+template <int H, bool BF, bool AM>
+static hipError_t launch_edge_bwd_am(const EdgeBwdArgs& a, int grid, hipStream_t s) {
+  using C = EdgeBwdCfg<H, BF>;
+  (void)hipFuncSetAttribute((const void*)k_edge_bwd<H, BF, AM>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)C::LDS);
+  hipLaunchKernelGGL((k_edge_bwd<H, BF, AM>), dim3(grid), dim3(64 * C::NW), C::LDS, s, a);
+  return hipGetLastError();
+}
 template <int H, bool BF>
 static hipError_t launch_edge_bwd_t(const EdgeBwdArgs& a, int grid, hipStream_t s) {
-  using C = EdgeBwdCfg<H, BF>;
-  (void)hipFuncSetAttribute((const void*)k_edge_bwd<H, BF>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)C::LDS);
-  hipLaunchKernelGGL((k_edge_bwd<H, BF>), dim3(grid), dim3(64 * C::NW), C::LDS, s, a);
-  return hipGetLastError();
+  return a.am ? launch_edge_bwd_am<H, BF, true>(a, grid, s) : launch_edge_bwd_am<H, BF, false>(a, grid, s);
 }
 
 hipError_t launch_edge_bwd(const EdgeBwdArgs& a, int grid, hipStream_t s) {
@@ -571,7 +586,7 @@ struct EdgeBwdSplitCfg {
 // accumulating them: gm and u (dW2 = sum gm u^T, db2 = sum gm), gE and
 // gE * normalised m (dbeta, dgamma); dW1c = sum g_h e^T is formed from g_h
 // and e.  Waves walk their tiles independently (no barriers in the loop).
-template <int H, bool BF>
+template <int H, bool BF, bool AM>
 __global__ __launch_bounds__((64 * EdgeBwdSplitCfg<H, BF>::NW)) void k_edge_bwd_split(EdgeBwdArgs a) {
   using C = EdgeBwdSplitCfg<H, BF>;
   constexpr int NF = H / 4, MB = H / 16, NW = C::NW;
@@ -691,6 +706,14 @@ __global__ __launch_bounds__((64 * EdgeBwdSplitCfg<H, BF>::NW)) void k_edge_bwd_
         gemm<BF, MB, MB>(fW2t, mp, t, lane);
 #pragma unroll
       for (int i = 0; i < NF; ++i) t[i] *= (u[i] > 0.f ? 1.f : u[i] + 1.f);
+      if constexpr (AM) {  // residual path: the next layer's gradient only
+        if (a.g_e_out) {
+          load_row<H>(a.g_e_out + kk * H, g, gE);
+        } else {
+#pragma unroll
+          for (int i = 0; i < NF; ++i) gE[i] = 0.f;
+        }
+      }
       // g_e = gE + W1c^T gh
       if constexpr (!BF && C::LDS_FRAG)
         gemm_f32_tr<H>(reinterpret_cast<const float*>(fW1c), t, gE, lane);
@@ -730,13 +753,18 @@ __global__ __launch_bounds__((64 * EdgeBwdSplitCfg<H, BF>::NW)) void k_edge_bwd_
   }
 }
 
+template <int H, bool BF, bool AM>
+static hipError_t launch_edge_bwd_split_am(const EdgeBwdArgs& a, int grid, hipStream_t s) {
+  using C = EdgeBwdSplitCfg<H, BF>;
+  (void)hipFuncSetAttribute((const void*)k_edge_bwd_split<H, BF, AM>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)C::LDS);
+  hipLaunchKernelGGL((k_edge_bwd_split<H, BF, AM>), dim3(grid), dim3(64 * C::NW), C::LDS, s, a);
+  return hipGetLastError();
+}
+
 template <int H, bool BF>
 static hipError_t launch_edge_bwd_split_t(const EdgeBwdArgs& a, int grid, hipStream_t s) {
-  using C = EdgeBwdSplitCfg<H, BF>;
-  (void)hipFuncSetAttribute((const void*)k_edge_bwd_split<H, BF>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)C::LDS);
-  hipLaunchKernelGGL((k_edge_bwd_split<H, BF>), dim3(grid), dim3(64 * C::NW), C::LDS, s, a);
-  return hipGetLastError();
+  return a.am ? launch_edge_bwd_split_am<H, BF, true>(a, grid, s) : launch_edge_bwd_split_am<H, BF, false>(a, grid, s);
 }
 
 hipError_t launch_edge_bwd_split(const EdgeBwdArgs& a, int grid, hipStream_t s) {

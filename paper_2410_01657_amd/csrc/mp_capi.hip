@@ -95,6 +95,8 @@ int check_cfg(const mp_layer_cfg* c) {
     return mp_fail(MP_EINVAL, "tile_edges must be 0 or in [16, 4096] (got %d)", c->tile_edges);
   if (c->edge_grid < 0 || c->edge_grid > 65536 || c->edge_bwd_grid < 0 || c->edge_bwd_grid > 65536)
     return mp_fail(MP_EINVAL, "edge grids must be 0 or in [1, 65536]");
+  if (c->aggregate != MP_AGG_STATE && c->aggregate != MP_AGG_MESSAGE)
+    return mp_fail(MP_EINVAL, "aggregate must be MP_AGG_STATE or MP_AGG_MESSAGE");
   return MP_OK;
 }
 
@@ -339,7 +341,7 @@ extern "C" int mp_layer_forward(const mp_layer_cfg* cfg, const mp_layer_params* 
     return rc;
   if ((rc = run("pack", s, [&] { return launch_pack(layer_jobs(cfg, p, W.fr, false), ws, s); }))) return rc;
   if ((rc = run("proj", s, [&] { return launch_proj(H, bf, d, x_in, ws_at(ws, W.fr.proj), p->be1, P, Q, W.gn, s); }))) return rc;
-  if ((rc = run("edge_fwd", s, [&] { return launch_edge_fwd(H, cfg->layernorm != 0, bf, d, P, Q, e_in, ws_at(ws, W.fr.edge), p->be2,
+  if ((rc = run("edge_fwd", s, [&] { return launch_edge_fwd(H, cfg->layernorm != 0, bf, cfg->aggregate != 0, d, P, Q, e_in, ws_at(ws, W.fr.edge), p->be2,
                                       p->ge, p->bge, cfg->ln_eps, e_out, a, W.ge, s); })))
     return rc;
   if (cfg->halo && (rc = run("halo", s, [&] { return launch_halo(H, d, a, s); }))) return rc;
@@ -485,6 +487,7 @@ extern "C" int mp_layer_backward(const mp_layer_cfg* cfg, const mp_layer_params*
   eb.H = H;
   eb.ln = cfg->layernorm;
   eb.bf = bf;
+  eb.am = cfg->aggregate;
   eb.P = P;
   eb.Q = Q;
   eb.e_in = e_in;
@@ -756,6 +759,8 @@ int check_deep_layer_cfg(const mp_deep_layer_cfg* c) {
   if (c->n_hidden < 0 || c->n_hidden > kDeepMaxHidden)
     return mp_fail(MP_EINVAL, "n_hidden must be in [0, %d] (got %d)", kDeepMaxHidden, c->n_hidden);
   if (c->layernorm && !(c->ln_eps > 0.f)) return mp_fail(MP_EINVAL, "ln_eps must be positive");
+  if (c->aggregate != MP_AGG_STATE && c->aggregate != MP_AGG_MESSAGE)
+    return mp_fail(MP_EINVAL, "aggregate must be MP_AGG_STATE or MP_AGG_MESSAGE");
   return MP_OK;
 }
 
@@ -890,6 +895,7 @@ extern "C" int mp_deep_layer_forward(const mp_deep_layer_cfg* cfg, const float* 
   ea.theta = theta_edge;
   ea.NH = cfg->n_hidden;
   ea.ln = cfg->layernorm != 0;
+  ea.am = cfg->aggregate != 0;
   ea.eps = cfg->ln_eps;
   ea.x = x_in;
   ea.e_in = e_in;
@@ -960,6 +966,7 @@ extern "C" int mp_deep_layer_backward(const mp_deep_layer_cfg* cfg, const float*
   ea.theta = theta_edge;
   ea.NH = NH;
   ea.ln = ln;
+  ea.am = cfg->aggregate != 0;
   ea.eps = cfg->ln_eps;
   ea.x = x_in;
   ea.e_in = e_in;

@@ -423,8 +423,9 @@ __global__ __launch_bounds__(256) void k_deep_edge_fwd(DeepEdgeArgs a) {
     const float inv_d = 1.f / (float)a.g.mult[k];
 #pragma unroll
     for (int c = 0; c < H; ++c) {
-      u[c] += in[2 * H + c];  // residual edge update (Eq. 4a)
-      acc[c] += u[c] * inv_d;  // Eq. 4b
+      const float msg = u[c];
+      u[c] += in[2 * H + c];                     // residual edge update (Eq. 4a)
+      acc[c] += (a.am ? msg : u[c]) * inv_d;     // Eq. 4b (or the message variant)
     }
     vstore<H>(a.e_out + (int64_t)k * H, u);
   }
@@ -491,6 +492,14 @@ __global__ __launch_bounds__(256) void k_deep_edge_bwd(DeepEdgeArgs a) {
     vstore<H>(a.gxj + (int64_t)k * H, t);
     phase_fence();
     dlin_t<H, KM, 2 * H, H>(Lk + m.w0(), d0, t);  // edge-state part + residual
+    if (a.am) {  // message aggregation: the residual carries the next layer's gradient only
+      if (a.g_e_out) {
+        vload<H>(a.g_e_out + (int64_t)k * H, gy);
+      } else {
+#pragma unroll
+        for (int c = 0; c < H; ++c) gy[c] = 0.f;
+      }
+    }
 #pragma unroll
     for (int c = 0; c < H; ++c) t[c] += gy[c];
     vstore<H>(a.g_e_in + (int64_t)k * H, t);

@@ -168,7 +168,8 @@ hipError_t launch_tiles(const DevGraph& g, int32_t* tile_r, int32_t* tile_e, hip
 // segmented scan across the 16 edges of each block with the open row
 // carried into the next block.  Every row's sum is written once by the lane
 // holding its last edge; no atomics, so results are bitwise reproducible.
-template <int H, bool BF>
+// AM: aggregate the MLP output (message) instead of the updated state.
+template <int H, bool BF, bool AM>
 __global__ __launch_bounds__(256, (H <= 64 ? 4 : 2)) void k_edge_fwd(DevGraph gr, const float* __restrict__ P,
                                                   const float* __restrict__ Q, const float* __restrict__ e_in,
                                                   const void* __restrict__ frag, const float* __restrict__ b2,
@@ -267,7 +268,7 @@ __global__ __launch_bounds__(256, (H <= 64 ? 4 : 2)) void k_edge_fwd(DevGraph gr
 
       // aggregation: segmented scan of e'/d across the block, plus carry
 #pragma unroll
-      for (int i = 0; i < NF; ++i) ev[i] = valid ? ev[i] * inv_d : 0.f;
+      for (int i = 0; i < NF; ++i) ev[i] = valid ? (AM ? m[i] : ev[i]) * inv_d : 0.f;
       if (j == 0 && key == carry_key) {
 #pragma unroll
         for (int i = 0; i < NF; i += 4) {
@@ -296,7 +297,7 @@ __global__ __launch_bounds__(256, (H <= 64 ? 4 : 2)) void k_edge_fwd(DevGraph gr
   }
 }
 
-template <int H, bool BF>
+template <int H, bool BF, bool AM>
 static hipError_t launch_edge_fwd_t(const DevGraph& g, const float* P, const float* Q, const float* e_in,
                                     const void* frag, const float* b2, const float* lng, const float* lnb, int ln,
                                     float eps, float* e_out, float* a_out, int grid, hipStream_t s) {
@@ -304,19 +305,28 @@ static hipError_t launch_edge_fwd_t(const DevGraph& g, const float* P, const flo
   // fragments, 3 per-feature vectors, per-wave carries (4 waves)
   const size_t lds = ((2 * FB <= kEdgeLdsBudget) ? 2 * FB : 0) + 3 * H * sizeof(float) + 4 * H * sizeof(float);
   if (lds > 64 * 1024)
-    (void)hipFuncSetAttribute((const void*)k_edge_fwd<H, BF>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL((k_edge_fwd<H, BF>), dim3(grid), dim3(256), lds, s, g, P, Q, e_in, frag, b2, lng, lnb, ln,
+    (void)hipFuncSetAttribute((const void*)k_edge_fwd<H, BF, AM>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+  hipLaunchKernelGGL((k_edge_fwd<H, BF, AM>), dim3(grid), dim3(256), lds, s, g, P, Q, e_in, frag, b2, lng, lnb, ln,
                      eps, e_out, a_out);
   return hipGetLastError();
 }
 
-hipError_t launch_edge_fwd(int H, bool ln, bool bf, const DevGraph& g, const float* P, const float* Q,
+template <int H, bool BF>
+static hipError_t launch_edge_fwd_am(bool am, const DevGraph& g, const float* P, const float* Q, const float* e_in,
+                                     const void* frag, const float* b2, const float* lng, const float* lnb, int ln,
+                                     float eps, float* e_out, float* a_out, int grid, hipStream_t s) {
+  return am ? launch_edge_fwd_t<H, BF, true>(g, P, Q, e_in, frag, b2, lng, lnb, ln, eps, e_out, a_out, grid, s)
+            : launch_edge_fwd_t<H, BF, false>(g, P, Q, e_in, frag, b2, lng, lnb, ln, eps, e_out, a_out, grid, s);
+}
+
+hipError_t launch_edge_fwd(int H, bool ln, bool bf, bool am, const DevGraph& g, const float* P, const float* Q,
                            const float* e_in, const void* frag, const float* b2, const float* lng, const float* lnb,
                            float eps, float* e_out, float* a_out, int grid, hipStream_t s) {
-#define MP_CASE(HH)                                                                                    \
-  if (H == HH)                                                                                         \
-    return bf ? launch_edge_fwd_t<HH, true>(g, P, Q, e_in, frag, b2, lng, lnb, ln, eps, e_out, a_out, grid, s) \
-              : launch_edge_fwd_t<HH, false>(g, P, Q, e_in, frag, b2, lng, lnb, ln, eps, e_out, a_out, grid, s);
+#define MP_CASE(HH)                                                                                           \
+  if (H == HH)                                                                                                \
+    return bf ? launch_edge_fwd_am<HH, true>(am, g, P, Q, e_in, frag, b2, lng, lnb, ln, eps, e_out, a_out, grid, s) \
+              : launch_edge_fwd_am<HH, false>(am, g, P, Q, e_in, frag, b2, lng, lnb, ln, eps, e_out, a_out, grid, s);
   MP_CASE(32) MP_CASE(64) MP_CASE(128)
 #undef MP_CASE
   return hipErrorInvalidValue;

@@ -51,7 +51,8 @@ hipError_t launch_pack(const PackJobs& jobs, void* dst, hipStream_t s);
 hipError_t launch_proj(int H, bool bf, const DevGraph& g, const float* x, const void* frag_ab,
                        const float* b1, float* P, float* Q, int grid, hipStream_t s);
 
-hipError_t launch_edge_fwd(int H, bool ln, bool bf, const DevGraph& g, const float* P, const float* Q,
+// am: aggregate the edge MLP's output (message) instead of the updated state
+hipError_t launch_edge_fwd(int H, bool ln, bool bf, bool am, const DevGraph& g, const float* P, const float* Q,
                            const float* e_in, const void* frag_c2, const float* b2, const float* lng,
                            const float* lnb, float eps, float* e_out, float* a_out, int grid,
                            hipStream_t s);
@@ -120,6 +121,8 @@ hipError_t launch_wreduce(const ReduceSegs& segs, hipStream_t s);
 struct EdgeBwdArgs {
   DevGraph g;
   int H, ln, bf;
+  int am;  // the forward aggregated the MLP output (message), not e'
+
   const float* P;
   const float* Q;
   const float* e_in;
@@ -246,6 +249,8 @@ struct DeepEdgeArgs {
   DevGraph g;
   const float* theta;
   int NH, ln;
+  int am;              // aggregate the MLP output (message), not e'
+
   float eps;
   const float* x;      // [N][H]
   const float* e_in;   // [E][H]

@@ -85,12 +85,12 @@ class ConsistentGNN:
     def process(self, dg, x, e):
         s = self.spec
         if self.deep:
-            cfg = deep_layer_cfg(s.H, s.n_hidden, s.layernorm, self.halo, s.ln_eps)
+            cfg = deep_layer_cfg(s.H, s.n_hidden, s.layernorm, self.halo, s.ln_eps, s.aggregate)
             for m in range(s.n_layers):
                 x, e = DeepLayerFn.apply(cfg, dg, x, e, self._theta(f"mp{m}.edge", s.layernorm),
                                          self._theta(f"mp{m}.node", s.layernorm))
             return x, e
-        cfg = layer_cfg(s.H, s.layernorm, self.halo, self.gemm, s.ln_eps)
+        cfg = layer_cfg(s.H, s.layernorm, self.halo, self.gemm, s.ln_eps, s.aggregate)
         if self.schedule:
             cfg.tile_edges = int(self.schedule.get("tile_edges", 0))
             cfg.edge_grid = int(self.schedule.get("edge_grid", 0))

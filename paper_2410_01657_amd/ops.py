@@ -53,9 +53,13 @@ WS = _Workspace()
 
 # ------------------------------------------------------------------ layer
 
-def layer_cfg(H, layernorm=True, halo=True, gemm="f32", ln_eps=1e-5):
+_AGG = {"state": 0, "message": 1}
+
+
+def layer_cfg(H, layernorm=True, halo=True, gemm="f32", ln_eps=1e-5, aggregate="state"):
     c = MpLayerCfg()
     c.H, c.layernorm, c.halo, c.gemm_dtype, c.ln_eps = H, int(layernorm), int(halo), _GEMM[gemm], ln_eps
+    c.aggregate = _AGG[aggregate]
     return c
 
 
@@ -186,9 +190,10 @@ class MLPFn(torch.autograd.Function):
 # Each MLP's parameters travel as one flat FP32 tensor in torch.nn.Linear
 # order (W0, b0, hidden W/b pairs, Wo, bo, LayerNorm gain and shift).
 
-def deep_layer_cfg(H, n_hidden, layernorm=True, halo=True, ln_eps=1e-5):
+def deep_layer_cfg(H, n_hidden, layernorm=True, halo=True, ln_eps=1e-5, aggregate="state"):
     c = MpDeepLayerCfg()
     c.H, c.n_hidden, c.layernorm, c.halo, c.ln_eps = H, n_hidden, int(layernorm), int(halo), ln_eps
+    c.aggregate = _AGG[aggregate]
     return c
 
 
