@@ -105,8 +105,10 @@ def _acc(grads, name, v):
 # --------------------------------------------------------------------------
 
 
-def edge_inputs(graph, pos, period=None):
-    """Four edge input channels (p_j - p_i, |p_j - p_i|) per directed edge.
+def edge_inputs(graph, pos, period=None, field=None):
+    """Four edge input channels (p_j - p_i, |p_j - p_i|) per directed edge,
+    and with a node field u (per global id) three more, u_j - u_i: the
+    relative velocity Sec. III lists among the edge features.
 
     On a periodic axis of length L > 0 the difference is that of the nearest
     periodic image of p_j (the element-local difference; a link never spans
@@ -115,7 +117,11 @@ def edge_inputs(graph, pos, period=None):
     for ax, L in enumerate(period or ()):
         if L > 0:
             dp[:, ax] -= L * np.round(dp[:, ax] / L)
-    return np.concatenate([dp, np.linalg.norm(dp, axis=1, keepdims=True)], axis=1)
+    cols = [dp, np.linalg.norm(dp, axis=1, keepdims=True)]
+    if field is not None:
+        u = np.asarray(field, np.float64)
+        cols.append(u[graph.gid[graph.send]] - u[graph.gid[graph.recv]])
+    return np.concatenate(cols, axis=1)
 
 
 def local_aggregate(e, graph):

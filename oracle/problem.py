@@ -17,11 +17,11 @@ class Problem:
     copies: dict
     pair_lists: dict
     X: list          # per sub-graph [n, 3] node inputs (float64 of the FP32 field)
-    E0: list         # per sub-graph [e, 4] edge inputs
+    E0: list         # per sub-graph [e, 4] (or [e, 7]) edge inputs
     T: list          # per sub-graph [n, 3] targets
 
 
-def build_problem(mesh, field, target, elem_part=None, R=1, unpartitioned_from_lattice=True):
+def build_problem(mesh, field, target, elem_part=None, R=1, unpartitioned_from_lattice=True, edge_in=4):
     """R=1 on a box mesh uses the lattice definition of the graph; otherwise
     the element route (with the mesh's own links where it has them)."""
     links = getattr(mesh, "links", None)
@@ -36,5 +36,5 @@ def build_problem(mesh, field, target, elem_part=None, R=1, unpartitioned_from_l
     t = np.asarray(target, np.float64)
     X = [f[G.gid] for G in graphs]
     T = [t[G.gid] for G in graphs]
-    E0 = [edge_inputs(G, mesh.pos, period) for G in graphs]
+    E0 = [edge_inputs(G, mesh.pos, period, f if edge_in == 7 else None) for G in graphs]
     return Problem(graphs, copies, pairs, X, E0, T)

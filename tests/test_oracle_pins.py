@@ -292,8 +292,8 @@ def test_consistent_loss_equals_mse(c0_ref):
 # ------------------------------------------------ P5, P6 gradients (Eq. 3)
 
 
-def _tiny(perturb=True, ln=True, H=4, layers=2, hidden=0, aggregate="state"):
-    spec = ModelSpec(H=H, n_layers=layers, n_hidden=hidden, layernorm=ln, aggregate=aggregate)
+def _tiny(perturb=True, ln=True, H=4, layers=2, hidden=0, aggregate="state", edge_in=4):
+    spec = ModelSpec(H=H, n_layers=layers, n_hidden=hidden, layernorm=ln, aggregate=aggregate, edge_in=edge_in)
     m = box_mesh((2, 2, 1), 2)
     field = velocity_field(m.pos, 1, noise_sigma=0.05)
     params = init_params(spec, 2, perturb=perturb)
@@ -303,17 +303,18 @@ def _tiny(perturb=True, ln=True, H=4, layers=2, hidden=0, aggregate="state"):
 def _loss_and_grads(spec, m, field, params, part, R):
     from mpinputs import shifted_target
     target = shifted_target(field, m.npts)
-    prob = build_problem(m, field, target, part, R, unpartitioned_from_lattice=(R == 1))
+    prob = build_problem(m, field, target, part, R, unpartitioned_from_lattice=(R == 1), edge_in=spec.edge_in)
     Y, cache = model_fwd(params, spec, prob.graphs, prob.pair_lists, prob.X, prob.E0)
     L, gY, _ = consistent_loss(Y, prob.T, prob.graphs)
     grads, _ = model_bwd(params, spec, prob.graphs, prob.pair_lists, cache, gY)
     return L, grads
 
 
-@pytest.mark.parametrize("ln,hidden,agg", [(True, 0, "state"), (False, 0, "state"), (True, 1, "state"),
-                                            (True, 0, "message")])
-def test_gradients_vs_central_differences(ln, hidden, agg):
-    spec, m, field, params = _tiny(ln=ln, hidden=hidden, aggregate=agg)
+@pytest.mark.parametrize("ln,hidden,agg,edge_in", [(True, 0, "state", 4), (False, 0, "state", 4),
+                                                    (True, 1, "state", 4), (True, 0, "message", 4),
+                                                    (True, 1, "state", 7)])
+def test_gradients_vs_central_differences(ln, hidden, agg, edge_in):
+    spec, m, field, params = _tiny(ln=ln, hidden=hidden, aggregate=agg, edge_in=edge_in)
     part = block_partition((2, 2, 1), (2, 1, 1))
     L, grads = _loss_and_grads(spec, m, field, params, part, 2)
     rng = np.random.default_rng(7)
@@ -335,9 +336,9 @@ def test_gradients_vs_central_differences(ln, hidden, agg):
             assert abs(fd - g) <= 2e-8 * max(1.0, abs(g)), (name, idx, fd, g)
 
 
-@pytest.mark.parametrize("agg", ["state", "message"])
-def test_gradient_consistency_r1_vs_r4(agg):
-    spec, m, field, params = _tiny(aggregate=agg)
+@pytest.mark.parametrize("agg,edge_in", [("state", 4), ("message", 4), ("state", 7)])
+def test_gradient_consistency_r1_vs_r4(agg, edge_in):
+    spec, m, field, params = _tiny(aggregate=agg, edge_in=edge_in)
     L1, g1 = _loss_and_grads(spec, m, field, params, None, 1)
     part = block_partition((2, 2, 1), (2, 2, 1))
     L4, g4 = _loss_and_grads(spec, m, field, params, part, 4)
@@ -553,3 +554,24 @@ def test_message_aggregation_of_a_zero_message_is_zero():
     G, e, e_new, a_msg = _first_layer_aggregate(spec, m, field, params, zero_message=True)
     np.testing.assert_array_equal(e_new, e)
     assert np.all(a_msg == 0.0)
+
+
+# ------------------------------------- seven edge input channels (variant)
+
+
+def test_seven_channel_edge_inputs_reverse_antisymmetrically():
+    """For the reverse edge j -> i the differences change sign and the
+    distance does not: E0[rev(k)] = (-dp, |dp|, -du); and channels 4..6 vanish
+    for a uniform field."""
+    m = box_mesh((2, 2, 2), 3)
+    field = velocity_field(m.pos, 9, noise_sigma=0.05)
+    prob = build_problem(m, field, field, None, 1, edge_in=7)
+    G, E = prob.graphs[0], prob.E0[0]
+    assert E.shape == (G.e, 7)
+    key = {(int(a), int(b)): k for k, (a, b) in enumerate(zip(G.recv, G.send))}
+    rev = np.array([key[(int(b), int(a))] for a, b in zip(G.recv, G.send)])
+    flip = np.array([-1, -1, -1, 1, -1, -1, -1])
+    np.testing.assert_array_equal(E[rev], E * flip)
+    np.testing.assert_array_equal(E[:, :4], build_problem(m, field, field, None, 1).E0[0])
+    uni = np.ones_like(field) * np.array([0.3, -1.2, 2.0], np.float32)
+    assert np.all(build_problem(m, uni, uni, None, 1, edge_in=7).E0[0][:, 4:] == 0.0)
