@@ -295,7 +295,7 @@ int mp_deep_layer_backward(const mp_deep_layer_cfg* cfg, const float* theta_edge
                            mp_stream_t stream);
 
 /* Encoder / decoder with deep MLPs (Sec. III).  (n_in, n_out) is
- * (1..4, H), (H, 1..4) or (H, H); LayerNorm needs n_out == H. */
+ * (1..8, H), (H, 1..4) or (H, H); LayerNorm needs n_out == H. */
 typedef struct {
   int32_t n_in, H, n_hidden, n_out, layernorm;
   float ln_eps;
@@ -316,10 +316,13 @@ int mp_deep_mlp_backward(const mp_deep_mlp_cfg* cfg, const float* theta, int64_t
  * period (host, 3 doubles, or NULL for none): on an axis with period L > 0
  * the difference is taken to the nearest periodic image of p_j, so a link
  * across a periodic boundary gets its element-local difference.  Errors:
- * MP_EINVAL for NULL or unaligned buffers or a negative or non-finite
- * period. */
+ * row_u (device FP32 [N][3], or NULL): a node field; with it e0 is [E][7]
+ * and channels 4..6 are u_j - u_i (the relative velocity of the edge
+ * features Sec. III lists; the models of Table I use the first four), an
+ * FP32 difference.  Errors: MP_EINVAL for NULL buffers, a 4-channel e0 not
+ * 16-byte aligned, or a negative or non-finite period. */
 int mp_edge_inputs(const mp_dev_graph* g, const double* row_pos, const double* period,
-                   float* e0, mp_stream_t stream);
+                   const float* row_u, float* e0, mp_stream_t stream);
 
 /* Consistent MSE (Eq. 6a-c): loss = sum_i sum_f (1/d_i)(Y-T)^2 / (N_eff F)
  * with N_eff = sum_i 1/d_i, over all rows of all sub-graphs; for R=1

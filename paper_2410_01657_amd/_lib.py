@@ -99,7 +99,7 @@ _SIGS = {
     "mp_deep_mlp_workspace_size": (c_i32, [P(MpDeepMlpCfg), c_i64, c_i32, P(C.c_size_t)]),
     "mp_deep_mlp_forward": (c_i32, [P(MpDeepMlpCfg), vp, c_i64, vp, vp, vp]),
     "mp_deep_mlp_backward": (c_i32, [P(MpDeepMlpCfg), vp, c_i64, vp, vp, vp, vp, vp, C.c_size_t, vp]),
-    "mp_edge_inputs": (c_i32, [P(MpDevGraph), vp, vp, vp, vp]),
+    "mp_edge_inputs": (c_i32, [P(MpDevGraph), vp, vp, vp, vp, vp]),
     "mp_consistent_mse_workspace_size": (c_i32, [c_i64, P(C.c_size_t)]),
     "mp_consistent_mse": (c_i32, [c_i64, c_i32, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]),
     "mp_profile_enable": (c_i32, [c_i32]),

@@ -845,12 +845,14 @@ int deep_mlp_kind(const mp_deep_mlp_cfg* c, DeepRowKind& kind, int& km, int& om)
   const int H = c->H;
   if (c->n_in >= 1 && c->n_in <= 4 && c->n_out == H) {
     kind = DeepRowKind::kSmallIn, km = 4, om = H;
+  } else if (c->n_in >= 5 && c->n_in <= 8 && c->n_in != H && c->n_out == H) {
+    kind = DeepRowKind::kSmallIn8, km = 8, om = H;
   } else if (c->n_in == H && c->n_out >= 1 && c->n_out <= 4) {
     kind = DeepRowKind::kSmallOut, km = H, om = 4;
   } else if (c->n_in == H && c->n_out == H) {
     kind = DeepRowKind::kWide, km = H, om = H;
   } else {
-    return mp_fail(MP_EINVAL, "deep MLPs: (n_in, n_out) must be (1..4, H), (H, 1..4) or (H, H); got (%d, %d)",
+    return mp_fail(MP_EINVAL, "deep MLPs: (n_in, n_out) must be (1..8, H), (H, 1..4) or (H, H); got (%d, %d)",
                    c->n_in, c->n_out);
   }
   return MP_OK;
@@ -1066,11 +1068,12 @@ extern "C" int mp_deep_mlp_backward(const mp_deep_mlp_cfg* cfg, const float* the
 
 // ------------------------------------------------------- edge inputs, loss
 
-extern "C" int mp_edge_inputs(const mp_dev_graph* g, const double* row_pos, const double* period, float* e0,
-                              mp_stream_t stream) {
+extern "C" int mp_edge_inputs(const mp_dev_graph* g, const double* row_pos, const double* period,
+                              const float* row_u, float* e0, mp_stream_t stream) {
   int rc;
   if ((rc = check_graph(g, false))) return rc;
-  if (!row_pos || !e0 || !aligned16(e0)) return mp_fail(MP_EINVAL, "mp_edge_inputs: NULL or unaligned buffer");
+  if (!row_pos || !e0 || (!row_u && !aligned16(e0)))
+    return mp_fail(MP_EINVAL, "mp_edge_inputs: NULL or unaligned buffer");
   double L[3] = {0.0, 0.0, 0.0};
   for (int a = 0; period && a < 3; ++a) {
     if (!(period[a] >= 0.0) || std::isinf(period[a]))
@@ -1078,7 +1081,7 @@ extern "C" int mp_edge_inputs(const mp_dev_graph* g, const double* row_pos, cons
     L[a] = period[a];
   }
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  return run("edge_inputs", s, [&] { return launch_edge_inputs(dev_graph(g), row_pos, L, e0, s); });
+  return run("edge_inputs", s, [&] { return launch_edge_inputs(dev_graph(g), row_pos, L, row_u, e0, s); });
 }
 
 static int loss_parts(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(256, (n + 4095) / 4096)); }

@@ -274,11 +274,12 @@ __device__ __forceinline__ void deep_bwd(const float* __restrict__ L, const Deep
 // ------------------------------------------------------------- row MLPs
 
 // Input [src_a (ka <= KAM features), src_b (KB features)]; output O <= OM.
-template <int H, int KAM, int KB, int OM>
+// SI: src_a is a narrow input (rows of ka floats, not 16-byte aligned).
+template <int H, int KAM, int KB, int OM, bool SI>
 struct DeepRowK {
   static constexpr int KM = KAM + KB;
   static __device__ __forceinline__ void load_in(const DeepRowArgs& a, int64_t r, float (&in)[KM]) {
-    if constexpr (KAM < 8) {
+    if constexpr (SI) {
 #pragma unroll
       for (int c = 0; c < KAM; ++c) in[c] = c < a.ka ? a.src_a[r * a.ka + c] : 0.f;
     } else {
@@ -296,10 +297,10 @@ struct DeepRowK {
   }
 };
 
-template <int H, int KAM, int KB, int OM>
+template <int H, int KAM, int KB, int OM, bool SI>
 __global__ __launch_bounds__(256) void k_deep_row_fwd(DeepRowArgs a) {
   extern __shared__ float L[];
-  using K = DeepRowK<H, KAM, KB, OM>;
+  using K = DeepRowK<H, KAM, KB, OM, SI>;
   const DeepLds<H, K::KM, OM> m{a.NH};
   stage_deep<H, K::KM, OM>(L, a.theta, m, a.ka, KAM, a.O, a.ln);
   __syncthreads();
@@ -325,10 +326,10 @@ __global__ __launch_bounds__(256) void k_deep_row_fwd(DeepRowArgs a) {
   }
 }
 
-template <int H, int KAM, int KB, int OM>
+template <int H, int KAM, int KB, int OM, bool SI>
 __global__ __launch_bounds__(256) void k_deep_row_bwd(DeepRowArgs a) {
   extern __shared__ float L[];
-  using K = DeepRowK<H, KAM, KB, OM>;
+  using K = DeepRowK<H, KAM, KB, OM, SI>;
   const DeepLds<H, K::KM, OM> m{a.NH};
   const DeepRec<H, K::KM, OM> rr{a.NH, a.ln};
   stage_deep<H, K::KM, OM>(L, a.theta, m, a.ka, KAM, a.O, a.ln);
@@ -363,7 +364,7 @@ __global__ __launch_bounds__(256) void k_deep_row_bwd(DeepRowArgs a) {
   if (a.g_a) {
     float t[KAM];
     dlin_t<H, K::KM, 0, KAM>(Lb + m.w0(), d0, t);
-    if constexpr (KAM < 8) {
+    if constexpr (SI) {
 #pragma unroll
       for (int c = 0; c < KAM; ++c)
         if (c < a.ka) a.g_a[r * a.ka + c] = t[c];
@@ -613,24 +614,25 @@ int deep_rec_floats(int H, int km, int om, int NH, int ln) {
   return km + 2 * (NH + 1) * H + om + (ln ? 2 * om : 0);
 }
 
-template <int H, int KAM, int KB, int OM>
+template <int H, int KAM, int KB, int OM, bool SI>
 static hipError_t row_launch(const DeepRowArgs& a, bool bwd, hipStream_t s) {
   const int grid = (int)((a.n_rows + 255) / 256);
   const size_t lds = deep_lds_bytes<H, KAM + KB, OM>(a.NH);
   if (bwd)
-    hipLaunchKernelGGL((k_deep_row_bwd<H, KAM, KB, OM>), dim3(grid), dim3(256), lds, s, a);
+    hipLaunchKernelGGL((k_deep_row_bwd<H, KAM, KB, OM, SI>), dim3(grid), dim3(256), lds, s, a);
   else
-    hipLaunchKernelGGL((k_deep_row_fwd<H, KAM, KB, OM>), dim3(grid), dim3(256), lds, s, a);
+    hipLaunchKernelGGL((k_deep_row_fwd<H, KAM, KB, OM, SI>), dim3(grid), dim3(256), lds, s, a);
   return hipGetLastError();
 }
 
 template <int H>
 static hipError_t row_launch_h(const DeepRowArgs& a, DeepRowKind kind, bool bwd, hipStream_t s) {
   switch (kind) {
-    case DeepRowKind::kSmallIn: return row_launch<H, 4, 0, H>(a, bwd, s);
-    case DeepRowKind::kSmallOut: return row_launch<H, H, 0, 4>(a, bwd, s);
-    case DeepRowKind::kWide: return row_launch<H, H, 0, H>(a, bwd, s);
-    case DeepRowKind::kNode: return row_launch<H, H, H, H>(a, bwd, s);
+    case DeepRowKind::kSmallIn: return row_launch<H, 4, 0, H, true>(a, bwd, s);
+    case DeepRowKind::kSmallIn8: return row_launch<H, 8, 0, H, true>(a, bwd, s);
+    case DeepRowKind::kSmallOut: return row_launch<H, H, 0, 4, false>(a, bwd, s);
+    case DeepRowKind::kWide: return row_launch<H, H, 0, H, false>(a, bwd, s);
+    case DeepRowKind::kNode: return row_launch<H, H, H, H, false>(a, bwd, s);
   }
   return hipErrorInvalidValue;
 }

@@ -563,9 +563,12 @@ hipError_t launch_mlp_fwd(const MlpFwdArgs& a, int grid, hipStream_t s) {
 // with period L > 0 the difference is taken to the nearest image of p_j.
 __device__ inline double nearest_image(double d, double L) { return L > 0.0 ? d - L * rint(d / L) : d; }
 
+// With a node field u, three more channels: u_j - u_i (the relative
+// velocity of the edge features Sec. III lists), an FP32 difference.
 __global__ __launch_bounds__(256) void k_edge_inputs(int64_t n_edges, const int32_t* __restrict__ recv,
                                                      const int32_t* __restrict__ col, const double* __restrict__ pos,
-                                                     double Lx, double Ly, double Lz, float* __restrict__ e0) {
+                                                     double Lx, double Ly, double Lz, const float* __restrict__ u,
+                                                     float* __restrict__ e0) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n_edges) return;
   const int64_t i = recv[k], jj = col[k];
@@ -573,15 +576,26 @@ __global__ __launch_bounds__(256) void k_edge_inputs(int64_t n_edges, const int3
   const double dy = nearest_image(pos[3 * jj + 1] - pos[3 * i + 1], Ly);
   const double dz = nearest_image(pos[3 * jj + 2] - pos[3 * i + 2], Lz);
   const double r = sqrt(dx * dx + dy * dy + dz * dz);
-  *reinterpret_cast<float4*>(e0 + 4 * k) = make_float4((float)dx, (float)dy, (float)dz, (float)r);
+  if (!u) {
+    *reinterpret_cast<float4*>(e0 + 4 * k) = make_float4((float)dx, (float)dy, (float)dz, (float)r);
+    return;
+  }
+  float* o = e0 + 7 * k;
+  o[0] = (float)dx;
+  o[1] = (float)dy;
+  o[2] = (float)dz;
+  o[3] = (float)r;
+  o[4] = u[3 * jj] - u[3 * i];
+  o[5] = u[3 * jj + 1] - u[3 * i + 1];
+  o[6] = u[3 * jj + 2] - u[3 * i + 2];
 }
 
-hipError_t launch_edge_inputs(const DevGraph& g, const double* pos, const double period[3], float* e0,
-                              hipStream_t s) {
+hipError_t launch_edge_inputs(const DevGraph& g, const double* pos, const double period[3], const float* u,
+                              float* e0, hipStream_t s) {
   if (g.n_edges == 0) return hipSuccess;
   const int grid = (int)((g.n_edges + 255) / 256);
   hipLaunchKernelGGL(k_edge_inputs, dim3(grid), dim3(256), 0, s, g.n_edges, g.recv, g.col, pos, period[0],
-                     period[1], period[2], e0);
+                     period[1], period[2], u, e0);
   return hipGetLastError();
 }
 

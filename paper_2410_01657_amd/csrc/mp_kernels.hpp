@@ -82,8 +82,10 @@ struct MlpFwdArgs {
 };
 hipError_t launch_mlp_fwd(const MlpFwdArgs& a, int grid, hipStream_t s);
 
-hipError_t launch_edge_inputs(const DevGraph& g, const double* pos, const double period[3], float* e0,
-                              hipStream_t s);
+// u (nullable): FP32 [N][3] node field; with it e0 is [E][7] and its last
+// three channels are u_j - u_i.
+hipError_t launch_edge_inputs(const DevGraph& g, const double* pos, const double period[3], const float* u,
+                              float* e0, hipStream_t s);
 
 hipError_t launch_loss(int64_t n_rows, int F, const float* Y, const float* T, const uint8_t* mult,
                        double* part, int n_part, float* loss, float* gY, hipStream_t s);
@@ -225,8 +227,9 @@ __host__ __device__ constexpr int64_t deep_theta_floats(int K, int H, int NH, in
 // floats of one row's adjoint record (padded input width km, output om)
 int deep_rec_floats(int H, int km, int om, int NH, int ln);
 
-enum class DeepRowKind { kSmallIn, kSmallOut, kWide, kNode };
-// kSmallIn: in = src_a (1..4 features) -> H;  kSmallOut: H -> 1..4;
+enum class DeepRowKind { kSmallIn, kSmallIn8, kSmallOut, kWide, kNode };
+// kSmallIn: in = src_a (1..4 features) -> H;  kSmallIn8: 5..8 features -> H;
+// kSmallOut: H -> 1..4;
 // kWide: H -> H;  kNode: [src_a (H), src_b (H)] -> H, optionally residual.
 struct DeepRowArgs {
   int64_t n_rows;

@@ -116,10 +116,12 @@ class ConsistentGNN:
 class Problem:
     """Device graph, node inputs, edge inputs and target for one workload."""
 
-    def __init__(self, mesh, field, target, elem_part, R, device="cuda"):
+    def __init__(self, mesh, field, target, elem_part, R, device="cuda", edge_in=4):
         self.host = build_graph(mesh.elem_gid, mesh.P, elem_part, R, getattr(mesh, "links", None))
         self.dg = DeviceGraph(self.host, device)
         self.X = self.dg.rows_of(field).float().contiguous()
         self.T = self.dg.rows_of(target).float().contiguous()
         self.pos = self.dg.rows_of(mesh.pos).double().contiguous()
-        self.E0 = edge_inputs(self.dg, self.pos, getattr(mesh, "period", None))
+        # 4 edge channels (p_j - p_i, |p_j - p_i|), or 7 with u_j - u_i
+        self.E0 = edge_inputs(self.dg, self.pos, getattr(mesh, "period", None),
+                              self.X if edge_in == 7 else None)

@@ -279,18 +279,21 @@ class DeepLayerFn(torch.autograd.Function):
 
 # ----------------------------------------------------------- inputs, loss
 
-def edge_inputs(dg, row_pos, period=None):
+def edge_inputs(dg, row_pos, period=None, row_u=None):
     """(p_j - p_i, |p_j - p_i|) per edge from FP64 row positions [N, 3];
     ``period`` (3 floats, 0 = not periodic) takes differences to the nearest
-    periodic image."""
-    _check(row_pos)
+    periodic image.  With an FP32 node field ``row_u`` [N, 3] three more
+    channels u_j - u_i follow (7 in all)."""
+    _check(row_pos, row_u)
     if row_pos.dtype != torch.float64:
         raise ValueError("row positions must be float64")
-    e0 = torch.empty((dg.n_edges, 4), dtype=torch.float32, device=row_pos.device)
+    if row_u is not None and (row_u.dtype != torch.float32 or tuple(row_u.shape) != (dg.n_rows, 3)):
+        raise ValueError("row_u must be float32 [N, 3]")
+    e0 = torch.empty((dg.n_edges, 4 if row_u is None else 7), dtype=torch.float32, device=row_pos.device)
     L = None
     if period is not None and any(period):
         L = (C.c_double * 3)(*[float(v) for v in period])
-    call("mp_edge_inputs", C.byref(dg.desc), _p(row_pos), L, _p(e0), _stream())
+    call("mp_edge_inputs", C.byref(dg.desc), _p(row_pos), L, _p(row_u), _p(e0), _stream())
     return e0
 
 

@@ -243,7 +243,7 @@ def test_deep_entry_points_validate_before_launch(L):
         call("mp_deep_layer_backward", C.byref(cfg), 4096, 4096, C.byref(d), 8192, 12288, 16384, 20480, None,
              24576, 28672, 32768, 36864, 40960, 16, None)
     assert e.value.code == L.MP_ENOMEM
-    for c in (deep_mlp_cfg(5, 8, 2, 8, True), deep_mlp_cfg(8, 8, 2, 3, True), deep_mlp_cfg(3, 8, 2, 3, False),
+    for c in (deep_mlp_cfg(9, 8, 2, 8, True), deep_mlp_cfg(8, 8, 2, 3, True), deep_mlp_cfg(3, 8, 2, 3, False),
               deep_mlp_cfg(16, 8, 2, 8, False)):
         with pytest.raises(MPError) as e:
             call("mp_deep_mlp_workspace_size", C.byref(c), 10, 1, C.byref(nb))

@@ -129,3 +129,31 @@ def test_deep_mlp_h_to_h_vs_oracle(H, NH):
         sz = params[k].size
         assert normwise(g[off:off + sz].reshape(params[k].shape), go[k]) < 1e-5, k
         off += sz
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("R", [1, 8])
+def test_table1_small_with_seven_edge_inputs(R):
+    """The seven-channel edge input (u_j - u_i added, Sec. III) with the small
+    model: edge inputs bit-exact against the oracle's rounded FP64 values,
+    then outputs, loss and gradients against the FP64 oracle at R = 1."""
+    from paper_2410_01657_amd.model import ConsistentGNN, Problem
+    spec = ModelSpec(H=8, n_layers=4, n_hidden=2, layernorm=True, edge_in=7)
+    inp = make_inputs(CONFIGS["C0"], perturb=True, spec=spec)
+    part = inp.elem_part if R > 1 else np.zeros(inp.mesh.n_elem, np.int32)
+    prob = Problem(inp.mesh, inp.field, inp.target, part, R, "cuda", edge_in=7)
+    o_r = build_problem(inp.mesh, inp.field, inp.target, part if R > 1 else None, R,
+                        unpartitioned_from_lattice=False, edge_in=7)
+    np.testing.assert_array_equal(prob.E0.cpu().numpy(), np.concatenate(o_r.E0).astype(np.float32))
+    p = build_problem(inp.mesh, inp.field, inp.target, None, 1, edge_in=7)
+    Y, c = model_fwd(inp.params, spec, p.graphs, p.pair_lists, p.X, p.E0)
+    Lo, gY, _ = consistent_loss(Y, p.T, p.graphs)
+    go, _ = model_bwd(inp.params, spec, p.graphs, p.pair_lists, c, gY)
+    model = ConsistentGNN(spec, inp.params, "cuda").requires_grad_(True)
+    Yg = model.forward(prob.dg, prob.X, prob.E0)
+    loss = model.loss(prob.dg, Yg, prob.T)
+    loss.backward()
+    assert normwise(Yg.detach().cpu().numpy(), Y[0][prob.host.row_gid]) < 1e-4
+    assert abs(float(loss.detach()) - Lo) / Lo < 1e-5
+    for k, t in model.params.items():
+        assert normwise(t.grad.cpu().numpy(), go[k]) < 1e-4, k
