@@ -1546,9 +1546,15 @@ struct NodeBwdSplitCfg {
   static constexpr int NW = 8;  // independent waves sharing the LDS weights
   static constexpr size_t F0 = frag_bytes(H, 2 * H, BF), F1 = frag_bytes(H, H, BF);
   static constexpr size_t VECS = 3 * H * sizeof(float);  // b0, b1, LayerNorm gain
-  static constexpr size_t LDS1 = F0 + 2 * F1 + VECS;     // pass 1: W0, W1, W1^T
-  static constexpr size_t LDS2 = F0;                      // pass 2: W0^T
-  static_assert(LDS1 <= kLdsLimit, "split node adjoint: weights must fit in LDS");
+  // BF16: pass 1 holds W0, W1 and W1^T.  FP32 (twice the bytes): pass 1 is
+  // cut after u = ELU(W0 [a*, x] + b0) (W0 only), and pass 1b continues
+  // from the stored u with W1 and W1^T.
+  static constexpr bool CUT = F0 + 2 * F1 + VECS > kLdsLimit;
+  static constexpr size_t LDS1 = CUT ? F0 + VECS : F0 + 2 * F1 + VECS;
+  static constexpr size_t LDS1B = 2 * F1 + VECS;
+  static constexpr size_t LDS2 = F0;  // pass 2: W0^T
+  static_assert(LDS1 <= kLdsLimit && (!CUT || LDS1B <= kLdsLimit) && LDS2 <= kLdsLimit,
+                "split node adjoint: weights must fit in LDS");
 };
 
 // Adjoint of the node update x' = x + LN(W1 ELU(W0 [a*, x] + b0) + b1)
@@ -1557,20 +1563,26 @@ struct NodeBwdSplitCfg {
 // weights each fit in LDS.  Pass 1 writes per row the factors u, g_y
 // (dW1 = sum g_y u^T, db1), g_z (dW0 = sum g_z [a*, x]^T, db0) and
 // g_out * normalised y (dgamma; dbeta sums g_out itself).
-template <int H, bool BF>
+// PH: 0 the whole pass; 1 only up to u (stored); 2 from the stored u on.
+template <int H, bool BF, int PH>
 __global__ __launch_bounds__((64 * NodeBwdSplitCfg<H, BF>::NW)) void k_node_bwd_split(MlpBwdArgs a, void* u_out,
                                                                                       void* gy_out, void* gz_out,
                                                                                       void* goxh_out) {
   using C = NodeBwdSplitCfg<H, BF>;
   constexpr int NF = H / 4, MB = H / 16, KB = 2 * H / 16, NW = C::NW;
+  constexpr size_t F0 = PH == 2 ? 0 : C::F0;                   // W0 present
+  constexpr size_t F1 = PH == 1 ? 0 : C::F1;                   // W1, W1^T present
+  constexpr size_t LDS = F0 + 2 * F1 + C::VECS;
   extern __shared__ uint4 smem[];
-  stage_frags(smem, a.frag0, C::F0);
-  stage_frags(smem + C::F0 / 16, a.frag1, C::F1);
-  stage_frags(smem + (C::F0 + C::F1) / 16, a.frag1t, C::F1);
+  if constexpr (PH != 2) stage_frags(smem, a.frag0, C::F0);
+  if constexpr (PH != 1) {
+    stage_frags(smem + F0 / 16, a.frag1, C::F1);
+    stage_frags(smem + (F0 + C::F1) / 16, a.frag1t, C::F1);
+  }
   const char* f0 = reinterpret_cast<const char*>(smem);
-  const char* f1 = f0 + C::F0;
-  const char* f1t = f1 + C::F1;
-  float* vecs = reinterpret_cast<float*>(reinterpret_cast<char*>(smem) + C::LDS1 - C::VECS);
+  const char* f1 = f0 + F0;
+  const char* f1t = f1 + F1;
+  float* vecs = reinterpret_cast<float*>(reinterpret_cast<char*>(smem) + LDS - C::VECS);
   for (int t = threadIdx.x; t < 3 * H; t += blockDim.x)
     vecs[t] = t < H ? a.b0[t] : (t < 2 * H ? a.b1[t - H] : (a.ln ? a.lng[t - 2 * H] : 0.f));
   __syncthreads();
@@ -1582,21 +1594,33 @@ __global__ __launch_bounds__((64 * NodeBwdSplitCfg<H, BF>::NW)) void k_node_bwd_
     const int64_t row = blk * 16 + j;
     const bool valid = row < n;
     const int64_t rr = valid ? row : n - 1;
-    float in[2 * NF], go[NF];
-    load_row<H>(a.src0 + rr * H, g, *reinterpret_cast<float(*)[NF]>(in));
-    load_row<H>(a.src1 + rr * H, g, *reinterpret_cast<float(*)[NF]>(in + NF));
-    load_row<H>(a.g_out + rr * H, g, go);
-    __builtin_amdgcn_sched_barrier(0);
-    if (!valid) {
+    float u[NF], go[NF];
+    if constexpr (PH != 2) {
+      float in[2 * NF];
+      load_row<H>(a.src0 + rr * H, g, *reinterpret_cast<float(*)[NF]>(in));
+      load_row<H>(a.src1 + rr * H, g, *reinterpret_cast<float(*)[NF]>(in + NF));
+      if constexpr (PH == 0) load_row<H>(a.g_out + rr * H, g, go);
+      __builtin_amdgcn_sched_barrier(0);
+      if constexpr (PH == 0) {
+        if (!valid) {
 #pragma unroll
-      for (int i = 0; i < NF; ++i) go[i] = 0.f;
+          for (int i = 0; i < NF; ++i) go[i] = 0.f;
+        }
+      }
+      load_vec<H>(vb, g, u);
+      gemm<BF, MB, KB>(f0 + oz, in, u, lane);
+#pragma unroll
+      for (int i = 0; i < NF; ++i) u[i] = elu(u[i]);
+      if (valid) store_row_t<H, BF>(u_out, row, g, u);
+      if constexpr (PH == 1) continue;
+    } else {
+      load_row_t<H, BF>(u_out, rr, g, u);
+      load_row<H>(a.g_out + rr * H, g, go);
+      if (!valid) {
+#pragma unroll
+        for (int i = 0; i < NF; ++i) go[i] = 0.f;
+      }
     }
-    float u[NF];
-    load_vec<H>(vb, g, u);
-    gemm<BF, MB, KB>(f0 + oz, in, u, lane);
-#pragma unroll
-    for (int i = 0; i < NF; ++i) u[i] = elu(u[i]);
-    if (valid) store_row_t<H, BF>(u_out, row, g, u);
     float y[NF];
     load_vec<H>(vb + H, g, y);
     gemm<BF, MB, MB>(f1 + oz, u, y, lane);
@@ -1668,14 +1692,27 @@ __global__ __launch_bounds__((64 * NodeBwdSplitCfg<H, BF>::NW)) void k_node_gin(
   }
 }
 
+template <int H, bool BF, int PH>
+static hipError_t launch_node_pass1(const MlpBwdArgs& a, void* u, void* gy, void* gz, void* goxh, int grid,
+                                    size_t lds, hipStream_t s) {
+  using C = NodeBwdSplitCfg<H, BF>;
+  (void)hipFuncSetAttribute((const void*)k_node_bwd_split<H, BF, PH>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds);
+  hipLaunchKernelGGL((k_node_bwd_split<H, BF, PH>), dim3(grid), dim3(64 * C::NW), lds, s, a, u, gy, gz, goxh);
+  return hipGetLastError();
+}
+
 template <int H, bool BF>
 static hipError_t launch_node_bwd_split_t(const MlpBwdArgs& a, void* u, void* gy, void* gz, void* goxh, int grid,
                                           hipStream_t s) {
   using C = NodeBwdSplitCfg<H, BF>;
-  (void)hipFuncSetAttribute((const void*)k_node_bwd_split<H, BF>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)C::LDS1);
-  hipLaunchKernelGGL((k_node_bwd_split<H, BF>), dim3(grid), dim3(64 * C::NW), C::LDS1, s, a, u, gy, gz, goxh);
-  hipError_t e = hipGetLastError();
+  hipError_t e;
+  if constexpr (C::CUT) {
+    e = launch_node_pass1<H, BF, 1>(a, u, gy, gz, goxh, grid, C::LDS1, s);
+    if (e == hipSuccess) e = launch_node_pass1<H, BF, 2>(a, u, gy, gz, goxh, grid, C::LDS1B, s);
+  } else {
+    e = launch_node_pass1<H, BF, 0>(a, u, gy, gz, goxh, grid, C::LDS1, s);
+  }
   if (e != hipSuccess) return e;
   (void)hipFuncSetAttribute((const void*)k_node_gin<H, BF>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)C::LDS2);
   hipLaunchKernelGGL((k_node_gin<H, BF>), dim3(grid), dim3(64 * C::NW), C::LDS2, s, a, (const void*)gz);
@@ -1684,8 +1721,9 @@ static hipError_t launch_node_bwd_split_t(const MlpBwdArgs& a, void* u, void* gy
 
 hipError_t launch_node_bwd_split(const MlpBwdArgs& a, void* u, void* gy, void* gz, void* goxh, int grid,
                                  hipStream_t s) {
-  if (a.H != 128 || a.k0 != a.H || a.k1 != a.H || a.n_out != a.H || !a.bf) return hipErrorInvalidValue;
-  return launch_node_bwd_split_t<128, true>(a, u, gy, gz, goxh, grid, s);
+  if (a.H != 128 || a.k0 != a.H || a.k1 != a.H || a.n_out != a.H) return hipErrorInvalidValue;
+  return a.bf ? launch_node_bwd_split_t<128, true>(a, u, gy, gz, goxh, grid, s)
+              : launch_node_bwd_split_t<128, false>(a, u, gy, gz, goxh, grid, s);
 }
 
 // ------------------------------------------------------ slab reduction

@@ -156,7 +156,7 @@ struct LayerWs {
         sgEx = o; o = align_up(o + eb);
       }
       if (node_bwd_split(c->H, c->gemm_dtype == MP_BF16)) {
-        const size_t nb = N * H * 2;  // BF16
+        const size_t nb = N * H * (c->gemm_dtype == MP_BF16 ? 2 : 4);  // factors in the product type
         nu = o; o = align_up(o + nb);
         ngy = o; o = align_up(o + nb);
         ngz = o; o = align_up(o + nb);
@@ -452,14 +452,14 @@ extern "C" int mp_layer_backward(const mp_layer_cfg* cfg, const mp_layer_params*
     RowDwArgs rd{};
     rd.n_rows = g->n_rows;
     rd.GW = H;
-    rd.bf = 1;
+    rd.bf = bf;
     rd.part = m.part;
     rd.slab = m.slab;
     rd.AW = H;  // dW1 = sum g_y u^T, db1 = sum g_y
     rd.G = ngy;
-    rd.g_bf = 1;
+    rd.g_bf = bf;
     rd.A = nu;
-    rd.a_bf = 1;
+    rd.a_bf = bf;
     rd.off = s1;
     rd.colsum_off = s1 + (int64_t)H * H;
     if ((rc = run("node_dw", s, [&] { return launch_row_dw(rd, W.gbn, s); }))) return rc;
@@ -473,7 +473,7 @@ extern "C" int mp_layer_backward(const mp_layer_cfg* cfg, const mp_layer_params*
     if ((rc = run("node_dw", s, [&] { return launch_row_dw(rd, W.gbn, s); }))) return rc;
     if (cfg->layernorm &&
         (rc = run("node_dw", s, [&] {
-           return launch_colsum2(g->n_rows, H, 1, 0, ngx, g_x_out, m.part, m.slab, s1 + (int64_t)H * H + H,
+           return launch_colsum2(g->n_rows, H, bf, 0, ngx, g_x_out, m.part, m.slab, s1 + (int64_t)H * H + H,
                                  s1 + (int64_t)H * H + 2 * H, W.gbn, s);
          })))
       return rc;

@@ -199,8 +199,9 @@ struct MlpBwdArgs {
 };
 hipError_t launch_mlp_bwd(const MlpBwdArgs& a, int grid, hipStream_t s);
 // Whether the node update's adjoint (2H input) at width H uses the split
-// form: BF16 only (the FP32 weights of the split passes do not fit in LDS).
-constexpr bool node_bwd_split(int H, bool bf) { return H > 64 && bf; }
+// form (both product types; FP32 cuts its first pass in two so that each
+// pass's weights fit in LDS).
+constexpr bool node_bwd_split(int H, bool /*bf*/) { return H > 64; }
 hipError_t launch_node_bwd_split(const MlpBwdArgs& a, void* u, void* gy, void* gz, void* goxh, int grid, hipStream_t s);
 
 struct GqArgs {
