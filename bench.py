@@ -159,7 +159,7 @@ def recorded_traffic(kernel, workload):
 
 
 KERNELS = ("pack", "tiles", "proj", "edge_fwd", "halo", "halo_adj", "node_fwd", "node_bwd", "edge_bwd", "edge_dw", "node_dw",
-           "gq", "wreduce", "mlp_fwd", "mlp_bwd", "edge_inputs", "loss",
+           "gq", "gq_dw", "wreduce", "mlp_fwd", "mlp_bwd", "edge_inputs", "loss",
            "deep_edge_fwd", "deep_node_fwd", "deep_node_bwd", "deep_edge_bwd", "deep_gather", "deep_edge_dw",
            "deep_node_dw", "deep_mlp_fwd", "deep_mlp_bwd", "deep_mlp_dw")
 

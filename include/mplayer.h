@@ -341,7 +341,7 @@ int mp_consistent_mse_workspace_size(int64_t n_rows, size_t* bytes);
  * recording on or off); mp_profile_read waits for and sums the elapsed
  * times of one kernel's launches recorded since then.  Kernel names:
  * tiles, pack, proj, edge_fwd, halo, halo_adj, node_fwd, node_bwd, edge_bwd,
- * edge_dw, node_dw (weight gradients of the split adjoints, H = 128), gq,
+ * edge_dw, node_dw, gq_dw (weight gradients of the split adjoints, H = 128), gq,
  * wreduce, mlp_fwd, mlp_bwd, edge_inputs, loss; for the deep MLPs deep_edge_fwd,
  * deep_node_fwd, deep_node_bwd, deep_edge_bwd, deep_gather, deep_node_dw, deep_edge_dw,
  * deep_mlp_fwd, deep_mlp_bwd, deep_mlp_dw.

@@ -993,7 +993,11 @@ struct GqRaw {
 template <int H, bool BF>
 struct GqCfg {
   static constexpr size_t FB = frag_bytes(H, 2 * H, BF);
-  static constexpr size_t STAGE = tile_bytes<2 * H, BF>() + tile_bytes<H, BF>();
+  // FP32 at H = 128: the weight-gradient tiles and accumulators do not fit
+  // beside the gather; the kernel writes g_Q per node instead and the weight
+  // gradients are summed from g_P, g_Q and x by launch_row_dw.
+  static constexpr bool SPLIT = gq_split(H, BF);
+  static constexpr size_t STAGE = SPLIT ? 0 : tile_bytes<2 * H, BF>() + tile_bytes<H, BF>();
   static constexpr bool LDS_FRAG = FB + STAGE <= kLdsLimit;
   static constexpr size_t LDS = STAGE + (LDS_FRAG ? FB : 0);
 };
@@ -1012,7 +1016,7 @@ __global__ __launch_bounds__(256, (H <= 64 ? 2 : 1)) void k_gq(GqArgs a) {
   constexpr int GQ_CH = 48 / RAWREG < 2 ? 2 : (48 / RAWREG > 8 ? 8 : 48 / RAWREG);
   extern __shared__ uint4 smem[];
   char* tG = reinterpret_cast<char*>(smem);
-  char* tA = tG + tile_bytes<2 * H, BF>();
+  char* tA = tG + (C::SPLIT ? 0 : tile_bytes<2 * H, BF>());
   const char* fr;
   if constexpr (C::LDS_FRAG) {
     uint4* fl = smem + C::STAGE / 16;
@@ -1094,6 +1098,12 @@ __global__ __launch_bounds__(256, (H <= 64 ? 2 : 1)) void k_gq(GqArgs a) {
 #pragma unroll
       for (int i = 0; i < 2 * NF; ++i) in[i] = 0.f;
     }
+    if constexpr (C::SPLIT) {
+      if (valid) store_row<H>(a.gq_out + row * H, g, *reinterpret_cast<float(*)[NF]>(in + NF));
+      gemm<BF, MB, 2 * MB>(fr, in, gx, lane);
+      if (valid) store_row<H>(a.g_x + row * H, g, gx);
+      continue;
+    }
 #pragma unroll
     for (int i = 0; i < NF; ++i) db1[i] += in[i];
     stage_row<2 * H, BF>(tG, wave * 16 + j, g, in);
@@ -1104,9 +1114,11 @@ __global__ __launch_bounds__(256, (H <= 64 ? 2 : 1)) void k_gq(GqArgs a) {
     dw_tiles<2 * H, H, BF>(tG, tA, acc, wave, lane);
     __syncthreads();
   }
-  float* slab = a.part + blockIdx.x * a.slab;
-  dw_store<2 * H, H>(acc, slab, H, wave, lane);
-  block_sum_vec<H>(db1, reinterpret_cast<float*>(tG), slab + 2 * H * H, wave, lane);
+  if constexpr (!C::SPLIT) {
+    float* slab = a.part + blockIdx.x * a.slab;
+    dw_store<2 * H, H>(acc, slab, H, wave, lane);
+    block_sum_vec<H>(db1, reinterpret_cast<float*>(tG), slab + 2 * H * H, wave, lane);
+  }
 }
 
 template <int H, bool BF>

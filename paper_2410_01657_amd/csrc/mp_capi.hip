@@ -124,7 +124,7 @@ struct LayerFrags {
 
 struct LayerWs {
   LayerFrags fr;
-  size_t P, Q, a, gP, gh, part_e, part_n, part_q, tile_r, tile_e, total;
+  size_t P, Q, a, gP, gh, gQ, part_e, part_n, part_q, tile_r, tile_e, total;
   size_t sgm, su, sgE, sgEx;  // split edge adjoint: per-edge weight-gradient factors
   size_t nu, ngy, ngz, ngx;   // split node adjoint: per-row weight-gradient factors
   int ge, gbe, gn, gbn;
@@ -142,12 +142,16 @@ struct LayerWs {
     P = o; o = align_up(o + N * H * 4);
     Q = o; o = align_up(o + N * H * 4);
     a = o; o = align_up(o + N * H * 4);
-    gP = gh = part_e = part_n = part_q = 0;
+    gP = gh = gQ = part_e = part_n = part_q = 0;
     sgm = su = sgE = sgEx = 0;
     nu = ngy = ngz = ngx = 0;
     if (bwd) {
       const size_t eb = E * H * (c->gemm_dtype == MP_BF16 ? 2 : 4);
       gP = o; o = align_up(o + N * H * 4);
+      if (gq_split(c->H, c->gemm_dtype == MP_BF16)) {
+        gQ = o;
+        o = align_up(o + N * H * 4);
+      }
       gh = o; o = align_up(o + eb);
       if (edge_bwd_split(c->H)) {
         sgm = o; o = align_up(o + eb);
@@ -550,7 +554,27 @@ extern "C" int mp_layer_backward(const mp_layer_cfg* cfg, const mp_layer_params*
   q.g_x = g_x_in;
   q.part = wsf(ws, W.part_q);
   q.slab = gq_slab(H);
+  q.gq_out = gq_split(H, bf) ? wsf(ws, W.gQ) : nullptr;
   if ((rc = run("gq", s, [&] { return launch_gq(q, W.gbn, s); }))) return rc;
+  if (gq_split(H, bf)) {
+    // dW1a = sum g_P x^T with db1 = sum g_P, dW1b = sum g_Q x^T, into the
+    // slab layout of the fused form
+    RowDwArgs rq{};
+    rq.n_rows = g->n_rows;
+    rq.GW = H;
+    rq.AW = H;
+    rq.part = q.part;
+    rq.slab = q.slab;
+    rq.G = gP;
+    rq.A = x_in;
+    rq.off = 0;
+    rq.colsum_off = 2 * (int64_t)H * H;
+    if ((rc = run("gq_dw", s, [&] { return launch_row_dw(rq, W.gbn, s); }))) return rc;
+    rq.G = q.gq_out;
+    rq.off = (int64_t)H * H;
+    rq.colsum_off = -1;
+    if ((rc = run("gq_dw", s, [&] { return launch_row_dw(rq, W.gbn, s); }))) return rc;
+  }
   // weight gradients: fixed-order sums of the workgroup slabs
   ReduceSegs R;
   R.n = 0;

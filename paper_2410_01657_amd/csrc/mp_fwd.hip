@@ -12,6 +12,9 @@ namespace mp {
 
 constexpr size_t kRowMlpLdsBudget = 100 * 1024;
 constexpr size_t kEdgeLdsBudget = 128 * 1024;
+// the projection kernel keeps nothing else in LDS: both FP32 128 x 128
+// matrices (128 KB) still fit
+constexpr size_t kProjLdsBudget = 128 * 1024;
 
 // --------------------------------------------------------------- packing
 
@@ -76,7 +79,7 @@ __global__ __launch_bounds__(256, (H <= 64 ? 4 : 1)) void k_proj(int64_t n_rows,
                                               float* __restrict__ P, float* __restrict__ Q) {
   constexpr int NF = H / 4, MB = H / 16;
   constexpr size_t FB = frag_bytes(H, H, BF);
-  constexpr bool LDS = 2 * FB <= kRowMlpLdsBudget;
+  constexpr bool LDS = 2 * FB <= kProjLdsBudget;
   extern __shared__ uint4 smem[];
   const char* fr;
   if constexpr (LDS) {
@@ -121,7 +124,7 @@ template <int H, bool BF>
 static hipError_t launch_proj_t(const DevGraph& gr, const float* x, const void* frag, const float* b1,
                                 float* P, float* Q, int grid, hipStream_t s) {
   constexpr size_t FB = frag_bytes(H, H, BF);
-  const size_t lds = (2 * FB <= kRowMlpLdsBudget) ? 2 * FB : 0;
+  const size_t lds = (2 * FB <= kProjLdsBudget) ? 2 * FB : 0;
   if (lds > 64 * 1024) (void)hipFuncSetAttribute((const void*)k_proj<H, BF>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   hipLaunchKernelGGL((k_proj<H, BF>), dim3(grid), dim3(256), lds, s, gr.n_rows, x, frag, b1, P, Q);
   return hipGetLastError();

@@ -214,7 +214,11 @@ struct GqArgs {
   float* g_x;            // accumulated: g_x += W1a^T g_P + W1b^T g_Q
   float* part;
   int64_t slab;
+  float* gq_out;         // split form only: g_Q [N][H] (FP32)
 };
+// Whether the sender-side pass leaves its weight gradients to launch_row_dw
+// (FP32 at H = 128, where its tiles and accumulators do not fit).
+constexpr bool gq_split(int H, bool bf) { return H > 64 && !bf; }
 hipError_t launch_gq(const GqArgs& a, int grid, hipStream_t s);
 
 // ------------------------------------------------ narrow deep MLPs
