@@ -1148,8 +1148,14 @@ struct MlpBwdCfg {
   static constexpr int AW0 = TIN ? 16 : KIN;  // staged input width
   static constexpr size_t F0 = TIN ? 0 : frag_bytes(H, KIN, BF);
   static constexpr size_t F1 = TOUT ? 0 : frag_bytes(H, H, BF);
+  // FP32 at H = 128: the square transposed products read the forward
+  // matrix's own fragments (gemm_f32_tr), so W1^T / W0^T need no copy and
+  // the remaining fragments fit in LDS beside the tiles
+  static constexpr bool TR1 = !BF && H == 128 && !TOUT;
+  static constexpr bool TR0 = !BF && H == 128 && !TIN && KIN == H;
+  static constexpr size_t F1T = TR1 ? 0 : F1;
   // fragments: W0, W1, W1^T, W0^T
-  static constexpr size_t FRAG = 2 * F0 + 2 * F1;
+  static constexpr size_t FRAG = 2 * F0 + F1 + F1T - (TR0 ? F0 : 0);
   static constexpr size_t TB = tile_bytes<H, BF, ROWS>();
   // phase 1: [g_y, u (, g_out, g_out * normalised y)]; small output: [g_out (16 wide), u];
   // phase 0 reuses the first tile for g_z.  The input tile has its own
@@ -1240,8 +1246,9 @@ __global__ __launch_bounds__((64 * MlpBwdCfg<H, KIN, TIN, TOUT, BF>::NW)) void k
     uint4* fl = smem + C::STAGE / 16;
     stage_frags(fl, a.frag0, C::F0);
     stage_frags(fl + C::F0 / 16, a.frag1, C::F1);
-    stage_frags(fl + (C::F0 + C::F1) / 16, a.frag1t, C::F1);
-    if (a.frag0t) stage_frags(fl + (C::F0 + 2 * C::F1) / 16, a.frag0t, C::F0);
+    if constexpr (!C::TR1) stage_frags(fl + (C::F0 + C::F1) / 16, a.frag1t, C::F1);
+    if constexpr (!C::TR0)
+      if (a.frag0t) stage_frags(fl + (C::F0 + C::F1 + C::F1T) / 16, a.frag0t, C::F0);
     fr = reinterpret_cast<const char*>(fl);
   } else {
     fr = nullptr;
@@ -1313,7 +1320,7 @@ __global__ __launch_bounds__((64 * MlpBwdCfg<H, KIN, TIN, TOUT, BF>::NW)) void k
     const char* f0 = (C::LDS_FRAG ? fr : reinterpret_cast<const char*>(a.frag0)) + oz;
     const char* f1 = (C::LDS_FRAG ? fr + C::F0 : reinterpret_cast<const char*>(a.frag1)) + oz;
     const char* f1t = (C::LDS_FRAG ? fr + C::F0 + C::F1 : reinterpret_cast<const char*>(a.frag1t)) + oz;
-    const char* f0t = (C::LDS_FRAG ? fr + C::F0 + 2 * C::F1 : reinterpret_cast<const char*>(a.frag0t)) + oz;
+    const char* f0t = (C::LDS_FRAG ? fr + C::F0 + C::F1 + C::F1T : reinterpret_cast<const char*>(a.frag0t)) + oz;
     const float* vb = vecs + oz;
     const int64_t bk = b0 + it * NW + wave;
     const int64_t row = bk * 16 + j;
@@ -1432,7 +1439,10 @@ __global__ __launch_bounds__((64 * MlpBwdCfg<H, KIN, TIN, TOUT, BF>::NW)) void k
       }
 #pragma unroll
       for (int i = 0; i < NF; ++i) gu[i] = 0.f;
-      gemm<BF, MB, MB>(f1t, y, gu, lane);
+      if constexpr (C::TR1)
+        gemm_f32_tr<H>(reinterpret_cast<const float*>(f1), y, gu, lane);
+      else
+        gemm<BF, MB, MB>(f1t, y, gu, lane);
     }
     // ---- gradient at z; phase 0: dW0, db0
 #pragma unroll
@@ -1454,7 +1464,10 @@ __global__ __launch_bounds__((64 * MlpBwdCfg<H, KIN, TIN, TOUT, BF>::NW)) void k
         float gi[KIN / 4];
 #pragma unroll
         for (int i = 0; i < KIN / 4; ++i) gi[i] = 0.f;
-        gemm<BF, KIN / 16, MB>(f0t, gu, gi, lane);
+        if constexpr (C::TR0)
+          gemm_f32_tr<H>(reinterpret_cast<const float*>(f0), gu, gi, lane);
+        else
+          gemm<BF, KIN / 16, MB>(f0t, gu, gi, lane);
         if constexpr (KIN == 2 * H) {
           float t0[NF], t1[NF];
 #pragma unroll
