@@ -11,6 +11,7 @@
 namespace mp {
 
 constexpr size_t kRowMlpLdsBudget = 100 * 1024;
+constexpr size_t kRowMlpLdsMax = 150 * 1024;  // one workgroup per CU
 constexpr size_t kEdgeLdsBudget = 128 * 1024;
 // the projection kernel keeps nothing else in LDS: both FP32 128 x 128
 // matrices (128 KB) still fit
@@ -429,7 +430,11 @@ struct MlpFwdCfg {
   static constexpr bool LDS_FRAG = (F0 + F1) <= kRowMlpLdsBudget;
   static constexpr size_t SMALL = (TIN || TOUT) ? 16 * H : 0;  // small W0 [H][4] or W1 [4][H]
   static constexpr size_t VECS = 4 * H * sizeof(float);        // b0, b1, LayerNorm gain, shift
-  static constexpr size_t LDS = (LDS_FRAG ? F0 + F1 : 0) + SMALL + VECS;
+  // when both do not fit (FP32, H = 128, 2H inputs), W0 alone may: the larger
+  // matrix is then read from LDS and only W1 from L2
+  static constexpr bool LDS_F0 = !LDS_FRAG && F0 > 0 && F0 + SMALL + VECS <= kRowMlpLdsMax;
+  static constexpr size_t FRAG_LDS = LDS_FRAG ? F0 + F1 : (LDS_F0 ? F0 : 0);
+  static constexpr size_t LDS = FRAG_LDS + SMALL + VECS;
 };
 
 template <int H, int KIN, bool TIN, bool TOUT, bool BF>
@@ -439,7 +444,7 @@ __global__ __launch_bounds__(256, (H <= 64 ? 4 : 1)) void k_mlp_fwd(MlpFwdArgs a
   extern __shared__ uint4 smem[];
   const char* f0;
   const char* f1;
-  float* small = reinterpret_cast<float*>(reinterpret_cast<char*>(smem) + (C::LDS_FRAG ? C::F0 + C::F1 : 0));
+  float* small = reinterpret_cast<float*>(reinterpret_cast<char*>(smem) + C::FRAG_LDS);
   float* vecs = small + C::SMALL / 4;
   if constexpr (TIN) stage_small(small, a.W0, H, a.k0);
   if constexpr (TOUT)
@@ -453,6 +458,10 @@ __global__ __launch_bounds__(256, (H <= 64 ? 4 : 1)) void k_mlp_fwd(MlpFwdArgs a
     if (C::F1) stage_to_lds(smem + C::F0 / 16, a.frag1, C::F1);
     f0 = reinterpret_cast<const char*>(smem);
     f1 = f0 + C::F0;
+  } else if constexpr (C::LDS_F0) {
+    stage_to_lds(smem, a.frag0, C::F0);
+    f0 = reinterpret_cast<const char*>(smem);
+    f1 = reinterpret_cast<const char*>(a.frag1);
   } else {
     f0 = reinterpret_cast<const char*>(a.frag0);
     f1 = reinterpret_cast<const char*>(a.frag1);
