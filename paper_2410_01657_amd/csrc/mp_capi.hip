@@ -822,9 +822,7 @@ int deep_grad_sums(const char* name, const float* rec, int64_t n_rows, int rs, i
   oa.part = part;
   oa.slab = deep_theta_floats(K, H, NH, O, ln);
   const int nm = deep_outer_mats(oa, K, H, NH, O, ln, km, om);
-  for (int i = 0; i < nm; ++i)
-    if (!outer_fits(oa.m[i].gw, oa.m[i].a_off >= 0 ? oa.m[i].aw : 0))
-      return mp_fail(MP_EINVAL, "%s: weight block %d x %d too large", name, oa.m[i].gw, oa.m[i].aw);
+  if (!outer_fits(oa.m, nm)) return mp_fail(MP_EINVAL, "%s: weight blocks too large for one workgroup", name);
   const int64_t nc = deep_chunks(n_rows);
   int rc;
   if ((rc = run(name, s, [&] { return launch_outer_sum(oa, nm, nc, s); }))) return rc;

@@ -532,75 +532,150 @@ __global__ __launch_bounds__(256) void k_deep_gather(DevGraph g, const float* __
 
 // ------------------------------------------------ weight-gradient sums
 
-// Partial sums over one chunk of rows of G^T [A, 1] for one record block:
+// Partial sums over one chunk of rows, for every weight block of one MLP:
 // part[chunk][dst_w + o*aw + c] = sum_r G[r][o] A[r][c] and
-// part[chunk][dst_b + o] = sum_r G[r][o]; without A only the latter.
+// part[chunk][dst_b + o] = sum_r G[r][o] (blocks without A: only the latter).
 //
-// One wave per (chunk, block), on the matrix unit with the rows as the
-// reduction dimension: for each group of four rows, v_mfma_f32_16x16x4f32
-// takes from lane l the value G[r + l/16][16 to + l%16] as its A operand and
-// [A, 1][r + l/16][16 tc + l%16] as its B operand, and accumulates the
-// 16 x 16 tile (to, tc) of G^T [A, 1]; lane l then holds rows
-// 4 (l/16) .. 4 (l/16) + 3, column l%16 of each tile.  Rows are added in
-// order, so the partial sums are reproducible.
-constexpr int kOuterTO = 4, kOuterTC = 7;  // up to 64 G and 112 [A, 1] columns
-__global__ __launch_bounds__(64) void k_outer_sum(OuterArgs a) {
-  const OuterMat M = a.m[blockIdx.y];
-  const bool hasA = M.a_off >= 0;
-  const int aw = hasA ? M.aw : 0;  // the ones column sits at index aw
-  const int TO = (M.gw + 15) / 16, TC = (aw + 1 + 15) / 16;
-  const int lane = threadIdx.x, k = lane >> 4, col = lane & 15;
-  v4f acc[kOuterTO][kOuterTC];
+// One workgroup per chunk.  The chunk's records are one contiguous range of
+// memory; the workgroup streams it through LDS a few rows at a time with
+// coalesced 16-byte loads (the next rows' loads in flight while the current
+// rows are used), so every record is read from HBM once however many weight
+// blocks it feeds.  The products run on the matrix unit with the rows as the
+// reduction dimension: a 16 x 16 tile (to, tc) of G^T A takes, for each
+// group of four rows, v_mfma_f32_16x16x4f32 with G[r + l/16][16 to + l%16]
+// from lane l as its A operand and A[r + l/16][16 tc + l%16] as its B
+// operand; lane l then holds rows 4 (l/16) .. 4 (l/16) + 3, column l%16 of
+// the tile.  The column sums of G are plain adds of the same G values per
+// lane, combined over the four row phases at the end.  Tiles are numbered
+// block by block, strip (to) by strip, and each wave takes a contiguous
+// range of them, so consecutive tiles of a wave mostly share their G values.
+// Rows are added in order, so the partial sums are reproducible.
+constexpr int kOuterMaxMT = 16;  // tiles per wave
+constexpr int kOuterNW = 4;      // waves per workgroup
+constexpr int kOuterPF = 8;      // 16-byte loads per thread per staged row block
+
+struct OuterTile {
+  int m, to, tc;  // block, G strip, A tile; tc < 0: column sums only
+};
+
+__host__ __device__ inline int outer_strips(const OuterMat& M) { return (M.gw + 15) / 16; }
+__host__ __device__ inline int outer_tiles_per_strip(const OuterMat& M) {
+  return M.a_off >= 0 && M.aw > 0 ? (M.aw + 15) / 16 : 1;
+}
+
+__device__ __forceinline__ OuterTile outer_tile(const OuterArgs& a, int id) {
+  for (int m = 0; m < a.n_mats; ++m) {
+    const OuterMat& M = a.m[m];
+    const int per = outer_tiles_per_strip(M), n = outer_strips(M) * per;
+    if (id < n) {
+      const bool hasA = M.a_off >= 0 && M.aw > 0;
+      return OuterTile{m, id / per, hasA ? id % per : -1};
+    }
+    id -= n;
+  }
+  return OuterTile{-1, 0, 0};
+}
+
+// MT: tile slots per wave (a wave's unused slots, and the A operand of
+// column-sum-only tiles, read a column of zeros, so the loop has no
+// branches and every LDS read of a row group can be issued before its
+// products).
+template <int MT>
+__global__ __launch_bounds__(64 * kOuterNW) void k_outer_sum(OuterArgs a) {
+  extern __shared__ float L[];
+  const int tid = threadIdx.x, nthr = 64 * kOuterNW;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lane = tid & 63, k = lane >> 4, col = lane & 15;
+  const int rs = a.rs, rp = a.rs_pad, T = a.tile_rows, q = rs >> 2;
+  const int zc = rs;  // a column of zeros after every staged row
+
+  int ntiles = 0;
+  for (int m = 0; m < a.n_mats; ++m) ntiles += outer_strips(a.m[m]) * outer_tiles_per_strip(a.m[m]);
+  const int t0 = w * ntiles / kOuterNW, nt = (w + 1) * ntiles / kOuterNW - t0;
+
+  // per tile slot: the LDS columns this lane reads for G and for A
+  int og[MT], ob[MT];
 #pragma unroll
-  for (int to = 0; to < kOuterTO; ++to)
+  for (int t = 0; t < MT; ++t) {
+    const OuterTile d = t < nt ? outer_tile(a, t0 + t) : OuterTile{-1, 0, 0};
+    og[t] = ob[t] = zc;
+    if (d.m >= 0) {
+      const OuterMat& M = a.m[d.m];
+      const int o = 16 * d.to + col, c = 16 * d.tc + col;
+      if (o < M.gw) og[t] = M.g_off + o;
+      if (d.tc >= 0 && c < M.aw) ob[t] = M.a_off + c;
+    }
+  }
+
+  // staging: thread tid moves 16-byte pieces tid + i * nthr of each block of
+  // T rows (T * q pieces, contiguous in the records)
+  int so[kOuterPF], sr[kOuterPF];
 #pragma unroll
-    for (int tc = 0; tc < kOuterTC; ++tc) acc[to][tc] = v4f{0.f, 0.f, 0.f, 0.f};
+  for (int i = 0; i < kOuterPF; ++i) {
+    const int idx = tid + i * nthr;
+    sr[i] = idx / q;
+    so[i] = idx < T * q ? sr[i] * rp + 4 * (idx % q) : -1;
+  }
+  for (int i = tid; i < T * (rp - rs); i += nthr) L[(i / (rp - rs)) * rp + rs + i % (rp - rs)] = 0.f;
+
   const int64_t r0 = (int64_t)blockIdx.x * a.ch, r1 = std::min<int64_t>(a.n_rows, r0 + a.ch);
-  // kOuterRG groups of four rows per step: all their loads are issued before
-  // the first product, so several row groups' latencies overlap.
-  constexpr int kOuterRG = 4;
-  for (int64_t rb = r0; rb < r1; rb += 4 * kOuterRG) {
-    float g[kOuterRG][kOuterTO], b[kOuterRG][kOuterTC];
+  float4 pf[kOuterPF];
+  auto fetch = [&](int64_t rt) {
+    const float* src = a.rec + rt * rs;
 #pragma unroll
-    for (int q = 0; q < kOuterRG; ++q) {
-      const int64_t row = rb + 4 * q + k;
-      const bool rv = row < r1;
-      const float* rp = a.rec + (rv ? row : r0) * a.rs;
+    for (int i = 0; i < kOuterPF; ++i)
+      pf[i] = (so[i] >= 0 && rt + sr[i] < r1) ? *reinterpret_cast<const float4*>(src + 4 * (tid + i * nthr))
+                                               : make_float4(0.f, 0.f, 0.f, 0.f);
+  };
+
+  v4f acc[MT];
+  float gs[MT];
 #pragma unroll
-      for (int to = 0; to < kOuterTO; ++to) {
-        const int o = 16 * to + col;
-        g[q][to] = (to < TO && rv && o < M.gw) ? rp[M.g_off + o] : 0.f;
-      }
+  for (int t = 0; t < MT; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f}, gs[t] = 0.f;
+
+  if (r0 < r1) fetch(r0);
+  for (int64_t rt = r0; rt < r1; rt += T) {
+    __syncthreads();  // every wave is done with the previous rows
 #pragma unroll
-      for (int tc = 0; tc < kOuterTC; ++tc) {
-        const int c = 16 * tc + col;
-        b[q][tc] = (tc < TC && rv) ? (c < aw ? rp[M.a_off + c] : (c == aw ? 1.f : 0.f)) : 0.f;
+    for (int i = 0; i < kOuterPF; ++i)
+      if (so[i] >= 0) *reinterpret_cast<float4*>(L + so[i]) = pf[i];
+    __syncthreads();
+    if (rt + T < r1) fetch(rt + T);
+    const int ng = (int)((std::min<int64_t>(T, r1 - rt) + 3) >> 2);  // rows past r1 are zeros
+    for (int gq = 0; gq < ng; ++gq) {
+      const float* Lr = L + (4 * gq + k) * rp;
+      float gv[MT], bv[MT];
+#pragma unroll
+      for (int t = 0; t < MT; ++t) gv[t] = Lr[og[t]], bv[t] = Lr[ob[t]];
+#pragma unroll
+      for (int t = 0; t < MT; ++t) {
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[t], bv[t], acc[t], 0, 0, 0);
+        gs[t] += gv[t];
       }
     }
-#pragma unroll
-    for (int q = 0; q < kOuterRG; ++q)
-#pragma unroll
-      for (int to = 0; to < kOuterTO; ++to)
-#pragma unroll
-        for (int tc = 0; tc < kOuterTC; ++tc)
-          if (to < TO && tc < TC)
-            acc[to][tc] = __builtin_amdgcn_mfma_f32_16x16x4f32(g[q][to], b[q][tc], acc[to][tc], 0, 0, 0);
   }
+
   float* dst = a.part + (int64_t)blockIdx.x * a.slab;
 #pragma unroll
-  for (int to = 0; to < kOuterTO; ++to)
-#pragma unroll
-    for (int tc = 0; tc < kOuterTC; ++tc) {
-      if (to >= TO || tc >= TC) continue;
-      const int c = 16 * tc + col;
+  for (int t = 0; t < MT; ++t) {
+    if (t >= nt) continue;
+    const OuterTile d = outer_tile(a, t0 + t);
+    const OuterMat& M = a.m[d.m];
+    if (d.tc <= 0) {
+      // column sums: the four row phases, added in a fixed order
+      const float s1 = __shfl(gs[t], col + 16), s2 = __shfl(gs[t], col + 32), s3 = __shfl(gs[t], col + 48);
+      const int o = 16 * d.to + col;
+      if (k == 0 && o < M.gw) dst[M.dst_b + o] = ((gs[t] + s1) + s2) + s3;
+    }
+    if (d.tc >= 0) {
+      const int c = 16 * d.tc + col;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int o = 16 * to + 4 * k + v;
-        if (o >= M.gw || c > aw) continue;
-        if (c == aw) dst[M.dst_b + o] = acc[to][tc][v];
-        else dst[M.dst_w + (int64_t)o * aw + c] = acc[to][tc][v];
+        const int o = 16 * d.to + 4 * k + v;
+        if (o < M.gw && c < M.aw) dst[M.dst_w + (int64_t)o * M.aw + c] = acc[t][v];
       }
     }
+  }
 }
 
 // ------------------------------------------------------------- launchers
@@ -673,13 +748,40 @@ hipError_t launch_deep_gather(int H, const DevGraph& g, const float* gxn, const 
   return hipGetLastError();
 }
 
-bool outer_fits(int gw, int aw) {
-  return gw >= 1 && gw <= 16 * kOuterTO && aw >= 0 && aw + 1 <= 16 * kOuterTC;
+int outer_tiles(const OuterMat* m, int n_mats) {
+  if (n_mats <= 0 || n_mats > kMaxOuterMats) return 0;
+  int n = 0;
+  for (int i = 0; i < n_mats; ++i) {
+    if (m[i].gw < 1 || (m[i].a_off >= 0 && m[i].aw < 0)) return 0;
+    n += outer_strips(m[i]) * outer_tiles_per_strip(m[i]);
+  }
+  return n;
 }
 
-hipError_t launch_outer_sum(const OuterArgs& a, int n_mats, int64_t n_chunks, hipStream_t s) {
-  if (n_mats <= 0 || n_mats > kMaxOuterMats || n_chunks <= 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_outer_sum, dim3((unsigned)n_chunks, n_mats), dim3(64), 0, s, a);
+bool outer_fits(const OuterMat* m, int n_mats) {
+  const int n = outer_tiles(m, n_mats);
+  return n >= 1 && n <= kOuterNW * kOuterMaxMT;
+}
+
+hipError_t launch_outer_sum(const OuterArgs& args, int n_mats, int64_t n_chunks, hipStream_t s) {
+  if (n_chunks <= 0 || !outer_fits(args.m, n_mats) || args.rs < 4 || args.rs % 4) return hipErrorInvalidValue;
+  OuterArgs a = args;
+  a.n_mats = n_mats;
+  const int nthr = 64 * kOuterNW, per_wave = (outer_tiles(a.m, n_mats) + kOuterNW - 1) / kOuterNW;
+  // row stride in LDS: at least one zero column, 16 mod 32 so that the four
+  // rows one product reads fall in different banks
+  a.rs_pad = a.rs + 1;
+  while (a.rs_pad % 32 != 16) ++a.rs_pad;
+  a.tile_rows = std::min(64, (kOuterPF * nthr * 4 / a.rs) / 4 * 4);
+  if (a.tile_rows < 4) return hipErrorInvalidValue;
+  const size_t lds = (size_t)a.tile_rows * a.rs_pad * sizeof(float);
+  const dim3 grid((unsigned)n_chunks), block(nthr);
+  if (per_wave <= 1) hipLaunchKernelGGL(k_outer_sum<1>, grid, block, lds, s, a);
+  else if (per_wave <= 2) hipLaunchKernelGGL(k_outer_sum<2>, grid, block, lds, s, a);
+  else if (per_wave <= 4) hipLaunchKernelGGL(k_outer_sum<4>, grid, block, lds, s, a);
+  else if (per_wave <= 8) hipLaunchKernelGGL(k_outer_sum<8>, grid, block, lds, s, a);
+  else if (per_wave <= 12) hipLaunchKernelGGL(k_outer_sum<12>, grid, block, lds, s, a);
+  else hipLaunchKernelGGL(k_outer_sum<16>, grid, block, lds, s, a);
   return hipGetLastError();
 }
 

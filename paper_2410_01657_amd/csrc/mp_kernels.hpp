@@ -291,8 +291,11 @@ struct OuterArgs {
   float* part;       // [n_chunks][slab]
   int64_t slab;
   OuterMat m[kMaxOuterMats];
+  int n_mats, rs_pad, tile_rows;  // set by launch_outer_sum
 };
-bool outer_fits(int gw, int aw);
+// Matrix-unit tiles of one set of weight blocks; 0 if a block is malformed.
+int outer_tiles(const OuterMat* m, int n_mats);
+bool outer_fits(const OuterMat* m, int n_mats);
 hipError_t launch_outer_sum(const OuterArgs& a, int n_mats, int64_t n_chunks, hipStream_t s);
 
 }  // namespace mp
