@@ -788,10 +788,11 @@ int check_deep_layer_cfg(const mp_deep_layer_cfg* c) {
   return MP_OK;
 }
 
-// Rows per weight-gradient chunk: at most 2048 chunks, at least 256 rows.
+// Rows per weight-gradient chunk: at most 2048 chunks, at least 256 rows,
+// whole record blocks.
 int64_t deep_chunk(int64_t n) {
   int64_t ch = std::max<int64_t>(256, (n + 2047) / 2048);
-  return (ch + 31) / 32 * 32;
+  return (ch + kRecRows - 1) / kRecRows * kRecRows;
 }
 int64_t deep_chunks(int64_t n) { return (n + deep_chunk(n) - 1) / deep_chunk(n); }
 
@@ -845,8 +846,8 @@ struct DeepLayerWs {
       slot = o;
       o = align_up(o + floats * sizeof(float));
     };
-    take(recN, (size_t)N * rsN);
-    take(recE, (size_t)E * rsE);
+    take(recN, (size_t)deep_rec_size(N, rsN));
+    take(recE, (size_t)deep_rec_size(E, rsE));
     take(ga, (size_t)N * H);
     take(gxn, (size_t)N * H);
     take(gxi, (size_t)E * H);
@@ -1022,7 +1023,7 @@ extern "C" int mp_deep_mlp_workspace_size(const mp_deep_mlp_cfg* cfg, int64_t n_
     return MP_OK;
   }
   const int rs = deep_rec_floats(cfg->H, km, om, cfg->n_hidden, cfg->layernorm != 0);
-  *bytes = align_up((size_t)n_rows * rs * sizeof(float)) +
+  *bytes = align_up((size_t)deep_rec_size(n_rows, rs) * sizeof(float)) +
            align_up((size_t)deep_chunks(n_rows) *
                     deep_theta_floats(cfg->n_in, cfg->H, cfg->n_hidden, cfg->n_out, cfg->layernorm != 0) *
                     sizeof(float));
@@ -1083,7 +1084,7 @@ extern "C" int mp_deep_mlp_backward(const mp_deep_mlp_cfg* cfg, const float* the
   a.rs = rs;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if ((rc = run("deep_mlp_bwd", s, [&] { return launch_deep_row(a, H, kind, true, s); }))) return rc;
-  float* part = wsf(ws, align_up((size_t)n_rows * rs * sizeof(float)));
+  float* part = wsf(ws, align_up((size_t)deep_rec_size(n_rows, rs) * sizeof(float)));
   return deep_grad_sums("deep_mlp_dw", a.rec, n_rows, rs, cfg->n_in, H, NH, cfg->n_out, ln, km, om, part, g_theta,
                         s);
 }

@@ -18,7 +18,10 @@
 // Adjoint (Eq. 3): each row recomputes its MLP and writes, to a per-row
 // record in the workspace, the MLP input, every hidden activation, every
 // pre-activation gradient and the LayerNorm terms; input gradients leave
-// the row kernels directly.  Weight gradients are then sums over rows of
+// the row kernels directly.  The records are stored column by column in
+// blocks of 64 rows, so a wave's store of one column is one contiguous run
+// of memory and no cache line is left half written.  The edge adjoint runs
+// one thread per edge.  Weight gradients are then sums over rows of
 // outer products of record columns, formed per chunk of rows on the matrix
 // unit by k_outer_sum and added chunk by chunk in a fixed order
 // (k_wreduce), so results are bitwise reproducible.  The sender-side input gradient of
@@ -50,7 +53,7 @@ struct DeepLds {
   __host__ __device__ int size() const { return lb() + OM; }
 };
 
-// Per-row record (floats): in[KM], h_0..h_NH [H each], d_0..d_NH [H each]
+// Per-row record columns: in[KM], h_0..h_NH [H each], d_0..d_NH [H each]
 // (gradients at the pre-activations), d_out[OM], then with LayerNorm
 // (g_y * y_hat)[OM] and g_y[OM].
 template <int H, int KM, int OM>
@@ -161,6 +164,21 @@ __device__ __forceinline__ void dlin_t(const float* __restrict__ W, const float 
 // hold both products' weight reads in registers at once).
 __device__ __forceinline__ void phase_fence() { __builtin_amdgcn_sched_barrier(0); }
 
+// One row's record: column c at p[c * kRecRows] (p = rec + deep_rec_at(r, 0, rs)).
+struct RecRef {
+  float* p;
+};
+template <int W>
+__device__ __forceinline__ void rstore(const RecRef& r, int c0, const float (&v)[W]) {
+#pragma unroll
+  for (int c = 0; c < W; ++c) r.p[(c0 + c) * kRecRows] = v[c];
+}
+template <int W>
+__device__ __forceinline__ void rload(const RecRef& r, int c0, float (&v)[W]) {
+#pragma unroll
+  for (int c = 0; c < W; ++c) v[c] = r.p[(c0 + c) * kRecRows];
+}
+
 template <int W>
 __device__ __forceinline__ void vload(const float* __restrict__ p, float (&v)[W]) {
 #pragma unroll
@@ -182,20 +200,20 @@ __device__ __forceinline__ void vstore(float* __restrict__ p, const float (&v)[W
 // REC, the hidden activations go to the row's record.
 template <int H, int KM, int OM, bool REC>
 __device__ __forceinline__ void deep_fwd(const float* __restrict__ L, const DeepLds<H, KM, OM>& m,
-                                         const float (&in)[KM], float (&u)[OM], float* __restrict__ rec) {
+                                         const float (&in)[KM], float (&u)[OM], const RecRef& rec) {
   using R = DeepRec<H, KM, OM>;
   float h[H];
   dlin<H, KM>(L + m.w0(), L + m.b0(), in, h);
 #pragma unroll
   for (int c = 0; c < H; ++c) h[c] = elu(h[c]);
-  if constexpr (REC) vstore<H>(rec + R::h(0), h);
+  if constexpr (REC) rstore<H>(rec, R::h(0), h);
   phase_fence();
   for (int l = 0; l < m.NH; ++l) {
     float z[H];
     dlin<H, H>(L + m.wh(l), L + m.bh(l), h, z);
 #pragma unroll
     for (int c = 0; c < H; ++c) h[c] = elu(z[c]);
-    if constexpr (REC) vstore<H>(rec + R::h(l + 1), h);
+    if constexpr (REC) rstore<H>(rec, R::h(l + 1), h);
     phase_fence();
   }
   dlin<OM, H>(L + m.wo(), L + m.bo(), h, u);
@@ -227,7 +245,7 @@ __device__ __forceinline__ void dln_fwd(const float* __restrict__ g, const float
 // Adjoint of LayerNorm: g_y -> g_u (in gy), recording g_y * y_hat and g_y.
 template <int OM>
 __device__ __forceinline__ void dln_bwd(const float* __restrict__ g, float eps, const float (&u)[OM], float (&gy)[OM],
-                                        float* __restrict__ rec_ln) {
+                                        const RecRef& rec, int c_ln) {
   float mean, rstd;
   dln_stats<OM>(u, eps, mean, rstd);
   float yh[OM], gyh[OM], m1 = 0.f, m2 = 0.f;
@@ -243,8 +261,8 @@ __device__ __forceinline__ void dln_bwd(const float* __restrict__ g, float eps, 
   float t[OM];
 #pragma unroll
   for (int c = 0; c < OM; ++c) t[c] = gy[c] * yh[c];
-  vstore<OM>(rec_ln, t);
-  vstore<OM>(rec_ln + OM, gy);
+  rstore<OM>(rec, c_ln, t);
+  rstore<OM>(rec, c_ln + OM, gy);
 #pragma unroll
   for (int c = 0; c < OM; ++c) gy[c] = rstd * (gyh[c] - m1 - yh[c] * m2);
 }
@@ -255,17 +273,17 @@ __device__ __forceinline__ void dln_bwd(const float* __restrict__ g, float eps, 
 template <int H, int KM, int OM>
 __device__ __forceinline__ void deep_bwd(const float* __restrict__ L, const DeepLds<H, KM, OM>& m,
                                          const DeepRec<H, KM, OM>& rr, const float (&gu)[OM],
-                                         float* __restrict__ rec, float (&d0)[H]) {
-  vstore<OM>(rec + rr.dout(), gu);
+                                         const RecRef& rec, float (&d0)[H]) {
+  rstore<OM>(rec, rr.dout(), gu);
   float gh[H];
   dlin_t<OM, H, 0, H>(L + m.wo(), gu, gh);
   phase_fence();
   for (int l = m.NH; l >= 0; --l) {
     float hl[H];
-    vload<H>(rec + rr.h(l), hl);
+    rload<H>(rec, rr.h(l), hl);
 #pragma unroll
     for (int c = 0; c < H; ++c) d0[c] = gh[c] * (hl[c] > 0.f ? 1.f : hl[c] + 1.f);  // ELU' from ELU's value
-    vstore<H>(rec + rr.d(l), d0);
+    rstore<H>(rec, rr.d(l), d0);
     if (l > 0) dlin_t<H, H, 0, H>(L + m.wh(l - 1), d0, gh);
     phase_fence();
   }
@@ -309,7 +327,7 @@ __global__ __launch_bounds__(256) void k_deep_row_fwd(DeepRowArgs a) {
   float in[K::KM];
   K::load_in(a, r, in);
   float u[OM];
-  deep_fwd<H, K::KM, OM, false>(L, m, in, u, nullptr);
+  deep_fwd<H, K::KM, OM, false>(L, m, in, u, RecRef{nullptr});
   if (a.ln) dln_fwd<OM>(L + m.lg(), L + m.lb(), a.eps, u);
   if constexpr (OM < 8) {
 #pragma unroll
@@ -336,13 +354,13 @@ __global__ __launch_bounds__(256) void k_deep_row_bwd(DeepRowArgs a) {
   __syncthreads();
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= a.n_rows) return;
-  float* rec = a.rec + r * a.rs;
+  const RecRef rec{a.rec + deep_rec_at(r, 0, a.rs)};
   float d0[H];
   {
     float gy[OM];
     float in[K::KM];
     K::load_in(a, r, in);
-    vstore<K::KM>(rec + rr.in(), in);
+    rstore<K::KM>(rec, rr.in(), in);
     float u[OM];
     deep_fwd<H, K::KM, OM, true>(L, m, in, u, rec);
     if constexpr (OM < 8) {
@@ -357,7 +375,7 @@ __global__ __launch_bounds__(256) void k_deep_row_bwd(DeepRowArgs a) {
     // a fresh view of the weights: the forward's reads are not reused (they
     // would all stay live across the adjoint)
     const float* Lb = L + opaque_zero();
-    if (a.ln) dln_bwd<OM>(Lb + m.lg(), a.eps, u, gu, rec + rr.lnr());
+    if (a.ln) dln_bwd<OM>(Lb + m.lg(), a.eps, u, gu, rec, rr.lnr());
     deep_bwd<H, K::KM, OM>(Lb, m, rr, gu, rec, d0);
   }
   const float* Lb = L + opaque_zero();
@@ -419,7 +437,7 @@ __global__ __launch_bounds__(256) void k_deep_edge_fwd(DeepEdgeArgs a) {
 #pragma unroll
     for (int c = 0; c < H; ++c) in[2 * H + c] = t[c];
     float u[H];
-    deep_fwd<H, KM, H, false>(Lk, m, in, u, nullptr);
+    deep_fwd<H, KM, H, false>(Lk, m, in, u, RecRef{nullptr});
     if (a.ln) dln_fwd<H>(Lk + m.lg(), Lk + m.lb(), a.eps, u);
     const float inv_d = 1.f / (float)a.g.mult[k];
 #pragma unroll
@@ -441,70 +459,66 @@ __global__ __launch_bounds__(256) void k_deep_edge_bwd(DeepEdgeArgs a) {
   const DeepRec<H, KM, H> rr{a.NH, a.ln};
   stage_deep<H, KM, H>(L, a.theta, m, KM, KM, H, a.ln);
   __syncthreads();
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a.g.n_rows) return;
-  // Nothing row-sized is carried from edge to edge: x_i and g_a_i are
-  // re-read (cache hits) and each edge's receiver-side gradient is written
-  // out, which keeps the recompute and the adjoint within the register file.
-  const int k1 = a.g.rowptr[i + 1];
-  for (int k = a.g.rowptr[i]; k < k1; ++k) {
-    const float* Lk = L + opaque_zero();  // re-read the weights per edge
-    float* rec = a.rec + (int64_t)k * a.rs;
-    const float inv_d = 1.f / (float)a.g.mult[k];
-    float gy[H], d0[H];
-    {
-      float in[KM];
-      float t[H];
-      vload<H>(a.x + i * H, t);
-#pragma unroll
-      for (int c = 0; c < H; ++c) in[c] = t[c];
-      vload<H>(a.x + (int64_t)a.g.col[k] * H, t);
-#pragma unroll
-      for (int c = 0; c < H; ++c) in[H + c] = t[c];
-      vload<H>(a.e_in + (int64_t)k * H, t);
-#pragma unroll
-      for (int c = 0; c < H; ++c) in[2 * H + c] = t[c];
-      vstore<KM>(rec + rr.in(), in);
-      float u[H];
-      deep_fwd<H, KM, H, true>(Lk, m, in, u, rec);
-      // gradient of e' = e + MLP(...): the next layer's, plus Eq. 4b's adjoint
-      if (a.g_e_out) {
-        vload<H>(a.g_e_out + (int64_t)k * H, gy);
-      } else {
-#pragma unroll
-        for (int c = 0; c < H; ++c) gy[c] = 0.f;
-      }
-      vload<H>(a.g_a + i * H, t);
-#pragma unroll
-      for (int c = 0; c < H; ++c) gy[c] += t[c] * inv_d;
-      float gu[H];
-#pragma unroll
-      for (int c = 0; c < H; ++c) gu[c] = gy[c];
-      const float* Lb = L + opaque_zero();  // see k_deep_row_bwd
-      if (a.ln) dln_bwd<H>(Lb + m.lg(), a.eps, u, gu, rec + rr.lnr());
-      deep_bwd<H, KM, H>(Lb, m, rr, gu, rec, d0);
-    }
-    Lk = L + opaque_zero();
+  // one thread per edge: every output is per edge (the receiver's and the
+  // sender's input gradients are summed afterwards by k_deep_gather)
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= a.g.n_edges) return;
+  const int64_t i = a.g.recv[k];
+  const RecRef rec{a.rec + deep_rec_at(k, 0, a.rs)};
+  const float inv_d = 1.f / (float)a.g.mult[k];
+  float gy[H], d0[H];
+  {
+    float in[KM];
     float t[H];
-    dlin_t<H, KM, 0, H>(Lk + m.w0(), d0, t);  // receiver part, summed by k_deep_gather
-    vstore<H>(a.gxi + (int64_t)k * H, t);
-    phase_fence();
-    dlin_t<H, KM, H, H>(Lk + m.w0(), d0, t);  // sender part, gathered through rev
-    vstore<H>(a.gxj + (int64_t)k * H, t);
-    phase_fence();
-    dlin_t<H, KM, 2 * H, H>(Lk + m.w0(), d0, t);  // edge-state part + residual
-    if (a.am) {  // message aggregation: the residual carries the next layer's gradient only
-      if (a.g_e_out) {
-        vload<H>(a.g_e_out + (int64_t)k * H, gy);
-      } else {
+    vload<H>(a.x + i * H, t);
 #pragma unroll
-        for (int c = 0; c < H; ++c) gy[c] = 0.f;
-      }
+    for (int c = 0; c < H; ++c) in[c] = t[c];
+    vload<H>(a.x + (int64_t)a.g.col[k] * H, t);
+#pragma unroll
+    for (int c = 0; c < H; ++c) in[H + c] = t[c];
+    vload<H>(a.e_in + k * H, t);
+#pragma unroll
+    for (int c = 0; c < H; ++c) in[2 * H + c] = t[c];
+    rstore<KM>(rec, rr.in(), in);
+    float u[H];
+    deep_fwd<H, KM, H, true>(L, m, in, u, rec);
+    // gradient of e' = e + MLP(...): the next layer's, plus Eq. 4b's adjoint
+    if (a.g_e_out) {
+      vload<H>(a.g_e_out + k * H, gy);
+    } else {
+#pragma unroll
+      for (int c = 0; c < H; ++c) gy[c] = 0.f;
     }
+    vload<H>(a.g_a + i * H, t);
 #pragma unroll
-    for (int c = 0; c < H; ++c) t[c] += gy[c];
-    vstore<H>(a.g_e_in + (int64_t)k * H, t);
+    for (int c = 0; c < H; ++c) gy[c] += t[c] * inv_d;
+    float gu[H];
+#pragma unroll
+    for (int c = 0; c < H; ++c) gu[c] = gy[c];
+    const float* Lb = L + opaque_zero();  // see k_deep_row_bwd
+    if (a.ln) dln_bwd<H>(Lb + m.lg(), a.eps, u, gu, rec, rr.lnr());
+    deep_bwd<H, KM, H>(Lb, m, rr, gu, rec, d0);
   }
+  const float* Lk = L + opaque_zero();
+  float t[H];
+  dlin_t<H, KM, 0, H>(Lk + m.w0(), d0, t);  // receiver part, summed by k_deep_gather
+  vstore<H>(a.gxi + k * H, t);
+  phase_fence();
+  dlin_t<H, KM, H, H>(Lk + m.w0(), d0, t);  // sender part, gathered through rev
+  vstore<H>(a.gxj + k * H, t);
+  phase_fence();
+  dlin_t<H, KM, 2 * H, H>(Lk + m.w0(), d0, t);  // edge-state part + residual
+  if (a.am) {  // message aggregation: the residual carries the next layer's gradient only
+    if (a.g_e_out) {
+      vload<H>(a.g_e_out + k * H, gy);
+    } else {
+#pragma unroll
+      for (int c = 0; c < H; ++c) gy[c] = 0.f;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < H; ++c) t[c] += gy[c];
+  vstore<H>(a.g_e_in + k * H, t);
 }
 
 // g_x[j] = g_x_node[j] + the input gradients of j's incoming edges (their
@@ -536,23 +550,23 @@ __global__ __launch_bounds__(256) void k_deep_gather(DevGraph g, const float* __
 // part[chunk][dst_w + o*aw + c] = sum_r G[r][o] A[r][c] and
 // part[chunk][dst_b + o] = sum_r G[r][o] (blocks without A: only the latter).
 //
-// One workgroup per chunk.  The chunk's records are one contiguous range of
-// memory; the workgroup streams it through LDS a few rows at a time with
-// coalesced 16-byte loads (the next rows' loads in flight while the current
-// rows are used), so every record is read from HBM once however many weight
-// blocks it feeds.  The products run on the matrix unit with the rows as the
-// reduction dimension: a 16 x 16 tile (to, tc) of G^T A takes, for each
-// group of four rows, v_mfma_f32_16x16x4f32 with G[r + l/16][16 to + l%16]
-// from lane l as its A operand and A[r + l/16][16 tc + l%16] as its B
-// operand; lane l then holds rows 4 (l/16) .. 4 (l/16) + 3, column l%16 of
+// One workgroup per chunk (whole record blocks); its four waves split the
+// 16 x 16 tiles (to, tc) of G^T A of all blocks between them, numbered block
+// by block, strip (to) by strip, a contiguous range per wave.  The products
+// run on the matrix unit with the rows as the reduction dimension, 16 rows
+// per step: lane l = 16 k + i loads, as one 16-byte piece, rows 4k .. 4k+3 of
+// record column G[16 to + i] (and of A[16 tc + i]) -- the column-by-column
+// record blocks make that piece contiguous -- and step v of four takes
+// component v of both pieces as the A and B operands of
+// v_mfma_f32_16x16x4f32, so the instruction's four k slots hold rows
+// 4k + v.  Lane l then holds rows 4 (l/16) .. 4 (l/16) + 3, column l%16 of
 // the tile.  The column sums of G are plain adds of the same G values per
-// lane, combined over the four row phases at the end.  Tiles are numbered
-// block by block, strip (to) by strip, and each wave takes a contiguous
-// range of them, so consecutive tiles of a wave mostly share their G values.
-// Rows are added in order, so the partial sums are reproducible.
+// lane, combined over the four k at the end.  Lanes past a block's width
+// read its last column: their products land in rows and columns of the
+// tile that are never stored.  Rows are added in a fixed order, so the
+// partial sums are reproducible.
 constexpr int kOuterMaxMT = 16;  // tiles per wave
 constexpr int kOuterNW = 4;      // waves per workgroup
-constexpr int kOuterPF = 8;      // 16-byte loads per thread per staged row block
 
 struct OuterTile {
   int m, to, tc;  // block, G strip, A tile; tc < 0: column sums only
@@ -576,82 +590,67 @@ __device__ __forceinline__ OuterTile outer_tile(const OuterArgs& a, int id) {
   return OuterTile{-1, 0, 0};
 }
 
-// MT: tile slots per wave (a wave's unused slots, and the A operand of
-// column-sum-only tiles, read a column of zeros, so the loop has no
-// branches and every LDS read of a row group can be issued before its
-// products).
+// MT: tile slots per wave; a wave's unused slots (and the A operand of
+// column-sum-only tiles) read G's column again and are not stored, so the
+// loop has no branches and all of a step's loads are issued before its
+// products.
 template <int MT>
 __global__ __launch_bounds__(64 * kOuterNW) void k_outer_sum(OuterArgs a) {
-  extern __shared__ float L[];
-  const int tid = threadIdx.x, nthr = 64 * kOuterNW;
+  const int tid = threadIdx.x;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lane = tid & 63, k = lane >> 4, col = lane & 15;
-  const int rs = a.rs, rp = a.rs_pad, T = a.tile_rows, q = rs >> 2;
-  const int zc = rs;  // a column of zeros after every staged row
+  const int rs = a.rs;
 
   int ntiles = 0;
   for (int m = 0; m < a.n_mats; ++m) ntiles += outer_strips(a.m[m]) * outer_tiles_per_strip(a.m[m]);
   const int t0 = w * ntiles / kOuterNW, nt = (w + 1) * ntiles / kOuterNW - t0;
 
-  // per tile slot: the LDS columns this lane reads for G and for A
+  // per tile slot: offsets (from a step's first row) of this lane's G and A pieces
   int og[MT], ob[MT];
 #pragma unroll
   for (int t = 0; t < MT; ++t) {
     const OuterTile d = t < nt ? outer_tile(a, t0 + t) : OuterTile{-1, 0, 0};
-    og[t] = ob[t] = zc;
+    int cg = 0, cb = 0;
     if (d.m >= 0) {
       const OuterMat& M = a.m[d.m];
-      const int o = 16 * d.to + col, c = 16 * d.tc + col;
-      if (o < M.gw) og[t] = M.g_off + o;
-      if (d.tc >= 0 && c < M.aw) ob[t] = M.a_off + c;
+      cg = M.g_off + std::min(16 * d.to + col, M.gw - 1);
+      cb = d.tc >= 0 ? M.a_off + std::min(16 * d.tc + col, M.aw - 1) : cg;
     }
+    og[t] = cg * kRecRows + 4 * k;
+    ob[t] = cb * kRecRows + 4 * k;
   }
-
-  // staging: thread tid moves 16-byte pieces tid + i * nthr of each block of
-  // T rows (T * q pieces, contiguous in the records)
-  int so[kOuterPF], sr[kOuterPF];
-#pragma unroll
-  for (int i = 0; i < kOuterPF; ++i) {
-    const int idx = tid + i * nthr;
-    sr[i] = idx / q;
-    so[i] = idx < T * q ? sr[i] * rp + 4 * (idx % q) : -1;
-  }
-  for (int i = tid; i < T * (rp - rs); i += nthr) L[(i / (rp - rs)) * rp + rs + i % (rp - rs)] = 0.f;
-
-  const int64_t r0 = (int64_t)blockIdx.x * a.ch, r1 = std::min<int64_t>(a.n_rows, r0 + a.ch);
-  float4 pf[kOuterPF];
-  auto fetch = [&](int64_t rt) {
-    const float* src = a.rec + rt * rs;
-#pragma unroll
-    for (int i = 0; i < kOuterPF; ++i)
-      pf[i] = (so[i] >= 0 && rt + sr[i] < r1) ? *reinterpret_cast<const float4*>(src + 4 * (tid + i * nthr))
-                                               : make_float4(0.f, 0.f, 0.f, 0.f);
-  };
 
   v4f acc[MT];
   float gs[MT];
 #pragma unroll
   for (int t = 0; t < MT; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f}, gs[t] = 0.f;
 
-  if (r0 < r1) fetch(r0);
-  for (int64_t rt = r0; rt < r1; rt += T) {
-    __syncthreads();  // every wave is done with the previous rows
+  const int64_t r0 = (int64_t)blockIdx.x * a.ch, r1 = std::min<int64_t>(a.n_rows, r0 + a.ch);
+  for (int64_t rb = r0; rb < r1; rb += 16) {
+    const float* base = a.rec + deep_rec_at(rb, 0, rs);  // rb is a multiple of 16: one record block
+    float4 gv[MT], bv[MT];
 #pragma unroll
-    for (int i = 0; i < kOuterPF; ++i)
-      if (so[i] >= 0) *reinterpret_cast<float4*>(L + so[i]) = pf[i];
-    __syncthreads();
-    if (rt + T < r1) fetch(rt + T);
-    const int ng = (int)((std::min<int64_t>(T, r1 - rt) + 3) >> 2);  // rows past r1 are zeros
-    for (int gq = 0; gq < ng; ++gq) {
-      const float* Lr = L + (4 * gq + k) * rp;
-      float gv[MT], bv[MT];
-#pragma unroll
-      for (int t = 0; t < MT; ++t) gv[t] = Lr[og[t]], bv[t] = Lr[ob[t]];
+    for (int t = 0; t < MT; ++t) {
+      gv[t] = *reinterpret_cast<const float4*>(base + og[t]);
+      bv[t] = *reinterpret_cast<const float4*>(base + ob[t]);
+    }
+    if (rb + 16 > r1) {  // past the last row the block holds no data: zero both operands
+      const int64_t rr = rb + 4 * k;
 #pragma unroll
       for (int t = 0; t < MT; ++t) {
-        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[t], bv[t], acc[t], 0, 0, 0);
-        gs[t] += gv[t];
+        if (rr >= r1) gv[t].x = bv[t].x = 0.f;
+        if (rr + 1 >= r1) gv[t].y = bv[t].y = 0.f;
+        if (rr + 2 >= r1) gv[t].z = bv[t].z = 0.f;
+        if (rr + 3 >= r1) gv[t].w = bv[t].w = 0.f;
       }
+    }
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[t].x, bv[t].x, acc[t], 0, 0, 0);
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[t].y, bv[t].y, acc[t], 0, 0, 0);
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[t].z, bv[t].z, acc[t], 0, 0, 0);
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[t].w, bv[t].w, acc[t], 0, 0, 0);
+      gs[t] += ((gv[t].x + gv[t].y) + gv[t].z) + gv[t].w;
     }
   }
 
@@ -662,7 +661,7 @@ __global__ __launch_bounds__(64 * kOuterNW) void k_outer_sum(OuterArgs a) {
     const OuterTile d = outer_tile(a, t0 + t);
     const OuterMat& M = a.m[d.m];
     if (d.tc <= 0) {
-      // column sums: the four row phases, added in a fixed order
+      // column sums: the four k, added in a fixed order
       const float s1 = __shfl(gs[t], col + 16), s2 = __shfl(gs[t], col + 32), s3 = __shfl(gs[t], col + 48);
       const int o = 16 * d.to + col;
       if (k == 0 && o < M.gw) dst[M.dst_b + o] = ((gs[t] + s1) + s2) + s3;
@@ -722,12 +721,11 @@ hipError_t launch_deep_row(const DeepRowArgs& a, int H, DeepRowKind kind, bool b
 
 template <int H>
 static hipError_t edge_launch(const DeepEdgeArgs& a, bool bwd, hipStream_t s) {
-  const int grid = (int)((a.g.n_rows + 255) / 256);
   const size_t lds = deep_lds_bytes<H, 3 * H, H>(a.NH);
   if (bwd)
-    hipLaunchKernelGGL(k_deep_edge_bwd<H>, dim3(grid), dim3(256), lds, s, a);
+    hipLaunchKernelGGL(k_deep_edge_bwd<H>, dim3((unsigned)((a.g.n_edges + 255) / 256)), dim3(256), lds, s, a);
   else
-    hipLaunchKernelGGL(k_deep_edge_fwd<H>, dim3(grid), dim3(256), lds, s, a);
+    hipLaunchKernelGGL(k_deep_edge_fwd<H>, dim3((unsigned)((a.g.n_rows + 255) / 256)), dim3(256), lds, s, a);
   return hipGetLastError();
 }
 
@@ -764,24 +762,18 @@ bool outer_fits(const OuterMat* m, int n_mats) {
 }
 
 hipError_t launch_outer_sum(const OuterArgs& args, int n_mats, int64_t n_chunks, hipStream_t s) {
-  if (n_chunks <= 0 || !outer_fits(args.m, n_mats) || args.rs < 4 || args.rs % 4) return hipErrorInvalidValue;
+  if (n_chunks <= 0 || !outer_fits(args.m, n_mats) || args.rs < 1) return hipErrorInvalidValue;
+  if (args.ch % kRecRows) return hipErrorInvalidValue;  // chunks of whole record blocks
   OuterArgs a = args;
   a.n_mats = n_mats;
-  const int nthr = 64 * kOuterNW, per_wave = (outer_tiles(a.m, n_mats) + kOuterNW - 1) / kOuterNW;
-  // row stride in LDS: at least one zero column, 16 mod 32 so that the four
-  // rows one product reads fall in different banks
-  a.rs_pad = a.rs + 1;
-  while (a.rs_pad % 32 != 16) ++a.rs_pad;
-  a.tile_rows = std::min(64, (kOuterPF * nthr * 4 / a.rs) / 4 * 4);
-  if (a.tile_rows < 4) return hipErrorInvalidValue;
-  const size_t lds = (size_t)a.tile_rows * a.rs_pad * sizeof(float);
-  const dim3 grid((unsigned)n_chunks), block(nthr);
-  if (per_wave <= 1) hipLaunchKernelGGL(k_outer_sum<1>, grid, block, lds, s, a);
-  else if (per_wave <= 2) hipLaunchKernelGGL(k_outer_sum<2>, grid, block, lds, s, a);
-  else if (per_wave <= 4) hipLaunchKernelGGL(k_outer_sum<4>, grid, block, lds, s, a);
-  else if (per_wave <= 8) hipLaunchKernelGGL(k_outer_sum<8>, grid, block, lds, s, a);
-  else if (per_wave <= 12) hipLaunchKernelGGL(k_outer_sum<12>, grid, block, lds, s, a);
-  else hipLaunchKernelGGL(k_outer_sum<16>, grid, block, lds, s, a);
+  const int per_wave = (outer_tiles(a.m, n_mats) + kOuterNW - 1) / kOuterNW;
+  const dim3 grid((unsigned)n_chunks), block(64 * kOuterNW);
+  if (per_wave <= 1) hipLaunchKernelGGL(k_outer_sum<1>, grid, block, 0, s, a);
+  else if (per_wave <= 2) hipLaunchKernelGGL(k_outer_sum<2>, grid, block, 0, s, a);
+  else if (per_wave <= 4) hipLaunchKernelGGL(k_outer_sum<4>, grid, block, 0, s, a);
+  else if (per_wave <= 8) hipLaunchKernelGGL(k_outer_sum<8>, grid, block, 0, s, a);
+  else if (per_wave <= 12) hipLaunchKernelGGL(k_outer_sum<12>, grid, block, 0, s, a);
+  else hipLaunchKernelGGL(k_outer_sum<16>, grid, block, 0, s, a);
   return hipGetLastError();
 }
 

@@ -248,7 +248,7 @@ struct DeepRowArgs {
   const float* g_out;  // adjoint: [n][O]
   float* g_a;          // [n][ka] or NULL
   float* g_b;          // [n][H] (kNode), includes g_out when resid
-  float* rec;          // per-row records, rs floats each
+  float* rec;          // per-row records (deep_rec_at), rs columns
   int rs;
 };
 hipError_t launch_deep_row(const DeepRowArgs& a, int H, DeepRowKind kind, bool bwd, hipStream_t s);
@@ -269,12 +269,22 @@ struct DeepEdgeArgs {
   float* g_e_in;       // [E][H]
   float* gxi;          // [E][H] receiver-side input gradient per edge
   float* gxj;          // [E][H] sender-side input gradient per edge
-  float* rec;
+  float* rec;          // per-edge records (deep_rec_at), rs columns
   int rs;
 };
 hipError_t launch_deep_edge(const DeepEdgeArgs& a, int H, bool bwd, hipStream_t s);
 hipError_t launch_deep_gather(int H, const DevGraph& g, const float* gxn, const float* gxi, const float* gxj,
                               float* gx, hipStream_t s);
+
+// Per-row records of rs columns are stored in blocks of kRecRows rows,
+// column by column inside a block: column c of row r is at
+// deep_rec_at(r, c, rs).  A wave's store of one column of 64 consecutive
+// rows is one contiguous 256-byte run, and a block is one contiguous range.
+constexpr int kRecRows = 64;
+__host__ __device__ constexpr int64_t deep_rec_at(int64_t r, int c, int rs) {
+  return (r / kRecRows) * kRecRows * rs + (int64_t)c * kRecRows + r % kRecRows;
+}
+constexpr int64_t deep_rec_size(int64_t n, int rs) { return (n + kRecRows - 1) / kRecRows * kRecRows * rs; }
 
 // Weight-gradient partial sums over chunks of record rows.
 struct OuterMat {
@@ -284,14 +294,14 @@ struct OuterMat {
 };
 constexpr int kMaxOuterMats = 12;
 struct OuterArgs {
-  const float* rec;
+  const float* rec;  // records (deep_rec_at)
   int64_t n_rows;
-  int rs;
+  int rs;            // columns
   int64_t ch;        // rows per chunk
   float* part;       // [n_chunks][slab]
   int64_t slab;
   OuterMat m[kMaxOuterMats];
-  int n_mats, rs_pad, tile_rows;  // set by launch_outer_sum
+  int n_mats;        // set by launch_outer_sum
 };
 // Matrix-unit tiles of one set of weight blocks; 0 if a block is malformed.
 int outer_tiles(const OuterMat* m, int n_mats);
