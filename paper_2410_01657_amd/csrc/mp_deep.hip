@@ -414,7 +414,8 @@ __global__ __launch_bounds__(256) void k_deep_edge_fwd(DeepEdgeArgs a) {
   const DeepLds<H, KM, H> m{a.NH};
   stage_deep<H, KM, H>(L, a.theta, m, KM, KM, H, a.ln);
   __syncthreads();
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // XCD-aware numbering: each XCD's L2 sees a compact window of receivers
+  const int64_t i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (i >= a.g.n_rows) return;
   float in[KM], acc[H];
   {
@@ -451,20 +452,13 @@ __global__ __launch_bounds__(256) void k_deep_edge_fwd(DeepEdgeArgs a) {
   vstore<H>(a.a_out + i * H, acc);
 }
 
+// The adjoint of one edge k: its record (at rec) and its per-edge outputs.
 template <int H>
-__global__ __launch_bounds__(256) void k_deep_edge_bwd(DeepEdgeArgs a) {
-  extern __shared__ float L[];
+__device__ __forceinline__ void deep_edge_bwd_one(const DeepEdgeArgs& a, const float* __restrict__ L,
+                                                  const DeepLds<H, 3 * H, H>& m, const DeepRec<H, 3 * H, H>& rr,
+                                                  int64_t k, const RecRef& rec) {
   constexpr int KM = 3 * H;
-  const DeepLds<H, KM, H> m{a.NH};
-  const DeepRec<H, KM, H> rr{a.NH, a.ln};
-  stage_deep<H, KM, H>(L, a.theta, m, KM, KM, H, a.ln);
-  __syncthreads();
-  // one thread per edge: every output is per edge (the receiver's and the
-  // sender's input gradients are summed afterwards by k_deep_gather)
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= a.g.n_edges) return;
   const int64_t i = a.g.recv[k];
-  const RecRef rec{a.rec + deep_rec_at(k, 0, a.rs)};
   const float inv_d = 1.f / (float)a.g.mult[k];
   float gy[H], d0[H];
   {
@@ -521,6 +515,21 @@ __global__ __launch_bounds__(256) void k_deep_edge_bwd(DeepEdgeArgs a) {
   vstore<H>(a.g_e_in + k * H, t);
 }
 
+template <int H>
+__global__ __launch_bounds__(256) void k_deep_edge_bwd(DeepEdgeArgs a) {
+  extern __shared__ float L[];
+  constexpr int KM = 3 * H;
+  const DeepLds<H, KM, H> m{a.NH};
+  const DeepRec<H, KM, H> rr{a.NH, a.ln};
+  stage_deep<H, KM, H>(L, a.theta, m, KM, KM, H, a.ln);
+  __syncthreads();
+  // one thread per edge: every output is per edge (the receiver's and the
+  // sender's input gradients are summed afterwards by k_deep_gather)
+  const int64_t k = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (k >= a.g.n_edges) return;
+  deep_edge_bwd_one<H>(a, L, m, rr, k, RecRef{a.rec + deep_rec_at(k, 0, a.rs)});
+}
+
 // g_x[j] = g_x_node[j] + the input gradients of j's incoming edges (their
 // receiver parts) and of j's outgoing edges (the reverses of its incoming
 // edges; their sender parts), in CSR order.
@@ -528,7 +537,7 @@ template <int H>
 __global__ __launch_bounds__(256) void k_deep_gather(DevGraph g, const float* __restrict__ gxn,
                                                      const float* __restrict__ gxi, const float* __restrict__ gxj,
                                                      float* __restrict__ gx) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t j = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (j >= g.n_rows) return;
   float s[H], t[H];
   vload<H>(gxn + j * H, s);
@@ -590,44 +599,37 @@ __device__ __forceinline__ OuterTile outer_tile(const OuterArgs& a, int id) {
   return OuterTile{-1, 0, 0};
 }
 
-// MT: tile slots per wave; a wave's unused slots (and the A operand of
-// column-sum-only tiles) read G's column again and are not stored, so the
-// loop has no branches and all of a step's loads are issued before its
+// MT tile slots of one wave: tiles t0 .. t0 + nt - 1.  Unused slots (and
+// the A operand of column-sum-only tiles) read G's column again and are not
+// stored, so a step has no branches and all its loads are issued before its
 // products.
 template <int MT>
-__global__ __launch_bounds__(64 * kOuterNW) void k_outer_sum(OuterArgs a) {
-  const int tid = threadIdx.x;
-  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int lane = tid & 63, k = lane >> 4, col = lane & 15;
-  const int rs = a.rs;
-
-  int ntiles = 0;
-  for (int m = 0; m < a.n_mats; ++m) ntiles += outer_strips(a.m[m]) * outer_tiles_per_strip(a.m[m]);
-  const int t0 = w * ntiles / kOuterNW, nt = (w + 1) * ntiles / kOuterNW - t0;
-
-  // per tile slot: offsets (from a step's first row) of this lane's G and A pieces
-  int og[MT], ob[MT];
-#pragma unroll
-  for (int t = 0; t < MT; ++t) {
-    const OuterTile d = t < nt ? outer_tile(a, t0 + t) : OuterTile{-1, 0, 0};
-    int cg = 0, cb = 0;
-    if (d.m >= 0) {
-      const OuterMat& M = a.m[d.m];
-      cg = M.g_off + std::min(16 * d.to + col, M.gw - 1);
-      cb = d.tc >= 0 ? M.a_off + std::min(16 * d.tc + col, M.aw - 1) : cg;
-    }
-    og[t] = cg * kRecRows + 4 * k;
-    ob[t] = cb * kRecRows + 4 * k;
-  }
-
+struct OuterAcc {
+  int og[MT], ob[MT];  // offsets (from a step's first row) of this lane's G and A pieces
   v4f acc[MT];
   float gs[MT];
-#pragma unroll
-  for (int t = 0; t < MT; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f}, gs[t] = 0.f;
 
-  const int64_t r0 = (int64_t)blockIdx.x * a.ch, r1 = std::min<int64_t>(a.n_rows, r0 + a.ch);
-  for (int64_t rb = r0; rb < r1; rb += 16) {
-    const float* base = a.rec + deep_rec_at(rb, 0, rs);  // rb is a multiple of 16: one record block
+  __device__ __forceinline__ void init(const OuterArgs& a, int t0, int nt, int lane) {
+    const int k = lane >> 4, col = lane & 15;
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+      const OuterTile d = t < nt ? outer_tile(a, t0 + t) : OuterTile{-1, 0, 0};
+      int cg = 0, cb = 0;
+      if (d.m >= 0) {
+        const OuterMat& M = a.m[d.m];
+        cg = M.g_off + std::min(16 * d.to + col, M.gw - 1);
+        cb = d.tc >= 0 ? M.a_off + std::min(16 * d.tc + col, M.aw - 1) : cg;
+      }
+      og[t] = cg * kRecRows + 4 * k;
+      ob[t] = cb * kRecRows + 4 * k;
+      acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+      gs[t] = 0.f;
+    }
+  }
+
+  // Sixteen rows rb .. rb + 15 whose record pieces start at base; rows from
+  // r1 on add nothing.
+  __device__ __forceinline__ void step(const float* __restrict__ base, int64_t rb, int64_t r1, int lane) {
     float4 gv[MT], bv[MT];
 #pragma unroll
     for (int t = 0; t < MT; ++t) {
@@ -635,7 +637,7 @@ __global__ __launch_bounds__(64 * kOuterNW) void k_outer_sum(OuterArgs a) {
       bv[t] = *reinterpret_cast<const float4*>(base + ob[t]);
     }
     if (rb + 16 > r1) {  // past the last row the block holds no data: zero both operands
-      const int64_t rr = rb + 4 * k;
+      const int64_t rr = rb + 4 * (lane >> 4);
 #pragma unroll
       for (int t = 0; t < MT; ++t) {
         if (rr >= r1) gv[t].x = bv[t].x = 0.f;
@@ -654,27 +656,48 @@ __global__ __launch_bounds__(64 * kOuterNW) void k_outer_sum(OuterArgs a) {
     }
   }
 
-  float* dst = a.part + (int64_t)blockIdx.x * a.slab;
+  __device__ __forceinline__ void store(const OuterArgs& a, int t0, int nt, int lane, float* __restrict__ dst) {
+    const int k = lane >> 4, col = lane & 15;
 #pragma unroll
-  for (int t = 0; t < MT; ++t) {
-    if (t >= nt) continue;
-    const OuterTile d = outer_tile(a, t0 + t);
-    const OuterMat& M = a.m[d.m];
-    if (d.tc <= 0) {
-      // column sums: the four k, added in a fixed order
-      const float s1 = __shfl(gs[t], col + 16), s2 = __shfl(gs[t], col + 32), s3 = __shfl(gs[t], col + 48);
-      const int o = 16 * d.to + col;
-      if (k == 0 && o < M.gw) dst[M.dst_b + o] = ((gs[t] + s1) + s2) + s3;
-    }
-    if (d.tc >= 0) {
-      const int c = 16 * d.tc + col;
+    for (int t = 0; t < MT; ++t) {
+      if (t >= nt) continue;
+      const OuterTile d = outer_tile(a, t0 + t);
+      const OuterMat& M = a.m[d.m];
+      if (d.tc <= 0) {
+        // column sums: the four k, added in a fixed order
+        const float s1 = __shfl(gs[t], col + 16), s2 = __shfl(gs[t], col + 32), s3 = __shfl(gs[t], col + 48);
+        const int o = 16 * d.to + col;
+        if (k == 0 && o < M.gw) dst[M.dst_b + o] = ((gs[t] + s1) + s2) + s3;
+      }
+      if (d.tc >= 0) {
+        const int c = 16 * d.tc + col;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int o = 16 * d.to + 4 * k + v;
-        if (o < M.gw && c < M.aw) dst[M.dst_w + (int64_t)o * M.aw + c] = acc[t][v];
+        for (int v = 0; v < 4; ++v) {
+          const int o = 16 * d.to + 4 * k + v;
+          if (o < M.gw && c < M.aw) dst[M.dst_w + (int64_t)o * M.aw + c] = acc[t][v];
+        }
       }
     }
   }
+};
+
+__device__ __forceinline__ int outer_ntiles(const OuterArgs& a) {
+  int n = 0;
+  for (int m = 0; m < a.n_mats; ++m) n += outer_strips(a.m[m]) * outer_tiles_per_strip(a.m[m]);
+  return n;
+}
+
+template <int MT>
+__global__ __launch_bounds__(64 * kOuterNW) void k_outer_sum(OuterArgs a) {
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int ntiles = outer_ntiles(a);
+  const int t0 = w * ntiles / kOuterNW, nt = (w + 1) * ntiles / kOuterNW - t0;
+  OuterAcc<MT> s;
+  s.init(a, t0, nt, lane);
+  const int64_t r0 = (int64_t)blockIdx.x * a.ch, r1 = std::min<int64_t>(a.n_rows, r0 + a.ch);
+  for (int64_t rb = r0; rb < r1; rb += 16)  // rb is a multiple of 16: one record block
+    s.step(a.rec + deep_rec_at(rb, 0, a.rs), rb, r1, lane);
+  s.store(a, t0, nt, lane, a.part + (int64_t)blockIdx.x * a.slab);
 }
 
 // ------------------------------------------------------------- launchers

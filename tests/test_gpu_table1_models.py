@@ -84,13 +84,39 @@ def test_table1_none_mode_differs(oracle_r1):
 
 
 @pytest.mark.gpu
-def test_table1_deterministic():
-    spec, _ = TABLE1["large"]
+@pytest.mark.parametrize("name", sorted(TABLE1))
+def test_table1_deterministic(name):
+    spec, _ = TABLE1[name]
     inp = make_inputs(CONFIGS["C0"], perturb=True, spec=spec)
     runs = [_gpu(spec, inp.params, inp, inp.elem_part, 8) for _ in range(2)]
     assert np.array_equal(runs[0][1], runs[1][1])
     for k in runs[0][3]:
         assert np.array_equal(runs[0][3][k], runs[1][3][k]), k
+
+
+# Other narrow deep MLPs: every tile count the fused edge adjoint is built
+# for (3 to 12 weight tiles at H = 8 and 16), with and without LayerNorm.
+VARIANTS = {"h8-nh0": ModelSpec(H=8, n_layers=2, n_hidden=0, layernorm=False),
+            "h8-nh5-ln": ModelSpec(H=8, n_layers=2, n_hidden=5, layernorm=True),
+            "h16-nh1-ln": ModelSpec(H=16, n_layers=2, n_hidden=1, layernorm=True),
+            "h16-nh3": ModelSpec(H=16, n_layers=2, n_hidden=3, layernorm=False)}
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("name", sorted(VARIANTS))
+def test_deep_layer_variants_vs_oracle(name):
+    spec = VARIANTS[name]
+    inp = make_inputs(CONFIGS["C0"], perturb=True, spec=spec)
+    p = build_problem(inp.mesh, inp.field, inp.target, None, 1)
+    Yo, c = model_fwd(inp.params, spec, p.graphs, p.pair_lists, p.X, p.E0)
+    Lo, gY, _ = consistent_loss(Yo, p.T, p.graphs)
+    go, _ = model_bwd(inp.params, spec, p.graphs, p.pair_lists, c, gY)
+    print(f"deep layer variant {name}, R=8", flush=True)
+    prob, Y, L, g = _gpu(spec, inp.params, inp, inp.elem_part, 8)
+    assert normwise(Y, Yo[0][prob.host.row_gid]) < 1e-4
+    assert abs(L - Lo) / Lo < 1e-5
+    for k in go:
+        assert normwise(g[k], go[k]) < 1e-4, k
 
 
 @pytest.mark.gpu
