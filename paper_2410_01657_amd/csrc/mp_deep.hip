@@ -113,7 +113,7 @@ __device__ __forceinline__ int opaque_zero_after4(float d0, float d1, float d2, 
 template <int N, int M>
 __device__ __forceinline__ void dlin(const float* __restrict__ W, const float* __restrict__ b, const float (&x)[M],
                                      float (&z)[N]) {
-  constexpr int RB = M >= 64 ? 1 : 4;  // rows per block: about 128 weights in flight
+  constexpr int RB = M >= 32 ? 1 : (M >= 16 ? 2 : 4);  // rows per block: at most 96 weights in flight
   const float* Wb = W;
 #pragma unroll
   for (int o = 0; o < N; ++o) {
@@ -578,7 +578,8 @@ constexpr int kOuterMaxMT = 16;  // tiles per wave
 constexpr int kOuterNW = 4;      // waves per workgroup
 
 struct OuterTile {
-  int m, to, tc;  // block, G strip, A tile; tc < 0: column sums only
+  int to, tc;  // G strip, A tile; tc < 0: column sums only
+  OuterMat M;  // its weight block (M.gw == 0: no tile)
 };
 
 __host__ __device__ inline int outer_strips(const OuterMat& M) { return (M.gw + 15) / 16; }
@@ -586,17 +587,27 @@ __host__ __device__ inline int outer_tiles_per_strip(const OuterMat& M) {
   return M.a_off >= 0 && M.aw > 0 ? (M.aw + 15) / 16 : 1;
 }
 
+// Tile id of the block list; the blocks are visited with constant indices
+// (a dynamic index into the kernel's argument block would copy it to
+// scratch memory).
 __device__ __forceinline__ OuterTile outer_tile(const OuterArgs& a, int id) {
-  for (int m = 0; m < a.n_mats; ++m) {
-    const OuterMat& M = a.m[m];
-    const int per = outer_tiles_per_strip(M), n = outer_strips(M) * per;
-    if (id < n) {
-      const bool hasA = M.a_off >= 0 && M.aw > 0;
-      return OuterTile{m, id / per, hasA ? id % per : -1};
+  OuterTile r{0, 0, OuterMat{0, 0, -1, 0, 0, 0}};
+  bool found = false;
+#pragma unroll
+  for (int m = 0; m < kMaxOuterMats; ++m) {
+    if (m < a.n_mats && !found) {
+      const OuterMat& M = a.m[m];
+      const int per = outer_tiles_per_strip(M), n = outer_strips(M) * per;
+      if (id < n) {
+        const bool hasA = M.a_off >= 0 && M.aw > 0;
+        r = OuterTile{id / per, hasA ? id % per : -1, M};
+        found = true;
+      } else {
+        id -= n;
+      }
     }
-    id -= n;
   }
-  return OuterTile{-1, 0, 0};
+  return r;
 }
 
 // MT tile slots of one wave: tiles t0 .. t0 + nt - 1.  Unused slots (and
@@ -613,10 +624,10 @@ struct OuterAcc {
     const int k = lane >> 4, col = lane & 15;
 #pragma unroll
     for (int t = 0; t < MT; ++t) {
-      const OuterTile d = t < nt ? outer_tile(a, t0 + t) : OuterTile{-1, 0, 0};
+      const OuterTile d = outer_tile(a, t < nt ? t0 + t : 1 << 30);
+      const OuterMat& M = d.M;
       int cg = 0, cb = 0;
-      if (d.m >= 0) {
-        const OuterMat& M = a.m[d.m];
+      if (M.gw > 0) {
         cg = M.g_off + std::min(16 * d.to + col, M.gw - 1);
         cb = d.tc >= 0 ? M.a_off + std::min(16 * d.tc + col, M.aw - 1) : cg;
       }
@@ -629,30 +640,40 @@ struct OuterAcc {
 
   // Sixteen rows rb .. rb + 15 whose record pieces start at base; rows from
   // r1 on add nothing.
+  // (More than eight tiles go in two halves, loads then products, to bound
+  // the registers the loads hold.)
   __device__ __forceinline__ void step(const float* __restrict__ base, int64_t rb, int64_t r1, int lane) {
-    float4 gv[MT], bv[MT];
+    constexpr int HB = MT > 8 ? (MT + 1) / 2 : MT;
+    const int64_t rr = rb + 4 * (lane >> 4);
 #pragma unroll
-    for (int t = 0; t < MT; ++t) {
-      gv[t] = *reinterpret_cast<const float4*>(base + og[t]);
-      bv[t] = *reinterpret_cast<const float4*>(base + ob[t]);
-    }
-    if (rb + 16 > r1) {  // past the last row the block holds no data: zero both operands
-      const int64_t rr = rb + 4 * (lane >> 4);
+    for (int h0 = 0; h0 < MT; h0 += HB) {
+      float4 gv[HB], bv[HB];
 #pragma unroll
-      for (int t = 0; t < MT; ++t) {
-        if (rr >= r1) gv[t].x = bv[t].x = 0.f;
-        if (rr + 1 >= r1) gv[t].y = bv[t].y = 0.f;
-        if (rr + 2 >= r1) gv[t].z = bv[t].z = 0.f;
-        if (rr + 3 >= r1) gv[t].w = bv[t].w = 0.f;
+      for (int j = 0; j < HB; ++j) {
+        if (h0 + j < MT) {
+          gv[j] = *reinterpret_cast<const float4*>(base + og[h0 + j]);
+          bv[j] = *reinterpret_cast<const float4*>(base + ob[h0 + j]);
+        }
       }
-    }
+      if (rb + 16 > r1) {  // past the last row the block holds no data: zero both operands
 #pragma unroll
-    for (int t = 0; t < MT; ++t) {
-      acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[t].x, bv[t].x, acc[t], 0, 0, 0);
-      acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[t].y, bv[t].y, acc[t], 0, 0, 0);
-      acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[t].z, bv[t].z, acc[t], 0, 0, 0);
-      acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[t].w, bv[t].w, acc[t], 0, 0, 0);
-      gs[t] += ((gv[t].x + gv[t].y) + gv[t].z) + gv[t].w;
+        for (int j = 0; j < HB; ++j) {
+          if (rr >= r1) gv[j].x = bv[j].x = 0.f;
+          if (rr + 1 >= r1) gv[j].y = bv[j].y = 0.f;
+          if (rr + 2 >= r1) gv[j].z = bv[j].z = 0.f;
+          if (rr + 3 >= r1) gv[j].w = bv[j].w = 0.f;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < HB; ++j) {
+        if (h0 + j >= MT) continue;
+        const int t = h0 + j;
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[j].x, bv[j].x, acc[t], 0, 0, 0);
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[j].y, bv[j].y, acc[t], 0, 0, 0);
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[j].z, bv[j].z, acc[t], 0, 0, 0);
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[j].w, bv[j].w, acc[t], 0, 0, 0);
+        gs[t] += ((gv[j].x + gv[j].y) + gv[j].z) + gv[j].w;
+      }
     }
   }
 
@@ -662,7 +683,7 @@ struct OuterAcc {
     for (int t = 0; t < MT; ++t) {
       if (t >= nt) continue;
       const OuterTile d = outer_tile(a, t0 + t);
-      const OuterMat& M = a.m[d.m];
+      const OuterMat& M = d.M;
       if (d.tc <= 0) {
         // column sums: the four k, added in a fixed order
         const float s1 = __shfl(gs[t], col + 16), s2 = __shfl(gs[t], col + 32), s3 = __shfl(gs[t], col + 48);
