@@ -86,6 +86,19 @@ int graph_partition(int64_t n_elem, int32_t npe, const int64_t* elem_gid,
                     int32_t n_links, const int32_t* links,
                     const int32_t* elem_part, int32_t R, mp_graph** out);
 
+/* Renumber the rows of every sub-graph of g, in place, in reverse
+ * Cuthill-McKee order (breadth-first levels from a pseudo-peripheral row,
+ * neighbours in ascending degree, reversed; ties to the lower row): the
+ * rows an edge joins end up close in memory, so a kernel sweeping the rows
+ * finds the rows it gathers still in cache.  Sub-graphs keep their rows and
+ * their place in the concatenation; edges stay sorted by (receiver row,
+ * sender row) in the new numbering, with rev, recv, col, edge_mult,
+ * node_mult and row_gid carried along.  The order is a function of the
+ * graph alone.  Call before halo_plan_build.  Errors: MP_EINVAL for a NULL
+ * graph, MP_ENOMEM on host allocation failure (g is then unchanged only
+ * up to the sub-graphs already renumbered). */
+int graph_order_rows(mp_graph* g);
+
 int mp_graph_sizes(const mp_graph* g, int64_t* n_rows, int64_t* n_edges, int32_t* R);
 
 /* Copy the graph out (host memory, sizes from mp_graph_sizes; any pointer

@@ -74,6 +74,7 @@ _SIGS = {
     "mp_last_error": (C.c_char_p, []),
     "mp_hex_links": (c_i32, [c_i32, vp, P(c_i32)]),
     "graph_partition": (c_i32, [c_i64, c_i32, vp, c_i32, vp, vp, c_i32, P(vp)]),
+    "graph_order_rows": (c_i32, [vp]),
     "mp_graph_sizes": (c_i32, [vp, P(c_i64), P(c_i64), P(c_i32)]),
     "mp_graph_export": (c_i32, [vp] + [vp] * 9),
     "mp_graph_destroy": (c_i32, [vp]),

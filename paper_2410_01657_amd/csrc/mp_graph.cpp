@@ -228,6 +228,141 @@ extern "C" int graph_partition(int64_t n_elem, int32_t npe, const int64_t* elem_
   return MP_OK;
 }
 
+namespace {
+
+// Reverse Cuthill-McKee order of one sub-graph (n rows, CSR rowptr/col with
+// local indices): breadth-first levels from a pseudo-peripheral row of
+// least degree, neighbours taken in ascending degree, the whole order
+// reversed.  ord[new] = old.  Ties go to the lower index, so the order is a
+// function of the graph alone.
+std::vector<int32_t> rcm_order(int32_t n, const std::vector<int32_t>& rowptr, const std::vector<int32_t>& col) {
+  auto deg = [&](int32_t i) { return rowptr[i + 1] - rowptr[i]; };
+  std::vector<int32_t> ord;
+  ord.reserve(n);
+  std::vector<int32_t> level(n, -1), nb;
+  std::vector<char> done(n, 0);
+  // last level of a breadth-first sweep from s over s's component (level
+  // marks are reset afterwards)
+  auto far_row = [&](int32_t s) {
+    std::vector<int32_t> q{s};
+    level[s] = 0;
+    for (size_t h = 0; h < q.size(); ++h)
+      for (int32_t k = rowptr[q[h]]; k < rowptr[q[h] + 1]; ++k)
+        if (level[col[k]] < 0) {
+          level[col[k]] = level[q[h]] + 1;
+          q.push_back(col[k]);
+        }
+    int32_t best = q.back();
+    for (int32_t v : q)
+      if (level[v] == level[q.back()] && (deg(v) < deg(best) || (deg(v) == deg(best) && v < best))) best = v;
+    const int32_t depth = level[q.back()];
+    for (int32_t v : q) level[v] = -1;
+    return std::make_pair(best, depth);
+  };
+  for (int32_t s0 = 0; s0 < n; ++s0) {
+    if (done[s0]) continue;
+    // start: the least-degree row of the component, moved to the far end
+    // of its sweeps while that lengthens them (two sweeps at most)
+    int32_t s = s0;
+    {
+      std::vector<int32_t> q{s0};
+      level[s0] = 0;
+      for (size_t h = 0; h < q.size(); ++h)
+        for (int32_t k = rowptr[q[h]]; k < rowptr[q[h] + 1]; ++k)
+          if (level[col[k]] < 0) {
+            level[col[k]] = 0;
+            q.push_back(col[k]);
+          }
+      for (int32_t v : q) {
+        if (deg(v) < deg(s) || (deg(v) == deg(s) && v < s)) s = v;
+        level[v] = -1;
+      }
+    }
+    auto fr = far_row(s);
+    for (int it = 0; it < 2; ++it) {
+      auto nx = far_row(fr.first);
+      if (nx.second <= fr.second) break;
+      s = fr.first;
+      fr = nx;
+    }
+    const size_t base = ord.size();
+    ord.push_back(s);
+    done[s] = 1;
+    for (size_t h = base; h < ord.size(); ++h) {
+      const int32_t v = ord[h];
+      nb.clear();
+      for (int32_t k = rowptr[v]; k < rowptr[v + 1]; ++k)
+        if (!done[col[k]]) {
+          done[col[k]] = 1;
+          nb.push_back(col[k]);
+        }
+      std::sort(nb.begin(), nb.end(), [&](int32_t a, int32_t b) { return deg(a) != deg(b) ? deg(a) < deg(b) : a < b; });
+      ord.insert(ord.end(), nb.begin(), nb.end());
+    }
+  }
+  std::reverse(ord.begin(), ord.end());
+  return ord;
+}
+
+}  // namespace
+
+extern "C" int graph_order_rows(mp_graph* g) {
+  if (!g) return mp_fail(MP_EINVAL, "graph_order_rows: graph is NULL");
+  try {
+    const int R = g->R;
+    mp_graph& G = *g;
+    parallel_for(R, [&](int r) {
+      const int64_t r0 = G.row_off[r], e0 = G.edge_off[r];
+      const int32_t n = (int32_t)(G.row_off[r + 1] - r0);
+      const int64_t ne = G.edge_off[r + 1] - e0;
+      std::vector<int32_t> rp(n + 1), cl(ne);
+      for (int32_t i = 0; i <= n; ++i) rp[i] = (int32_t)(G.rowptr[r0 + i] - e0);
+      for (int64_t k = 0; k < ne; ++k) cl[k] = (int32_t)(G.col[e0 + k] - r0);
+      const std::vector<int32_t> ord = rcm_order(n, rp, cl);
+      std::vector<int32_t> inv(n);
+      for (int32_t i = 0; i < n; ++i) inv[ord[i]] = i;
+      std::vector<int64_t> gid(n);
+      std::vector<uint8_t> nm(n), em(ne);
+      std::vector<int32_t> nrp(n + 1), ncl(ne);
+      std::vector<std::pair<int32_t, uint8_t>> row;
+      int64_t k = 0;
+      for (int32_t i = 0; i < n; ++i) {
+        const int32_t o = ord[i];
+        gid[i] = G.row_gid[r0 + o];
+        nm[i] = G.node_mult[r0 + o];
+        nrp[i] = (int32_t)k;
+        row.clear();
+        for (int32_t t = rp[o]; t < rp[o + 1]; ++t) row.emplace_back(inv[cl[t]], G.edge_mult[e0 + t]);
+        std::sort(row.begin(), row.end());
+        for (const auto& x : row) {
+          ncl[k] = x.first;
+          em[k] = x.second;
+          ++k;
+        }
+      }
+      nrp[n] = (int32_t)k;
+      for (int32_t i = 0; i < n; ++i) {
+        G.row_gid[r0 + i] = gid[i];
+        G.node_mult[r0 + i] = nm[i];
+        G.rowptr[r0 + i] = (int32_t)(e0 + nrp[i]);
+        for (int32_t t = nrp[i]; t < nrp[i + 1]; ++t) {
+          G.recv[e0 + t] = (int32_t)(r0 + i);
+          G.col[e0 + t] = (int32_t)(r0 + ncl[t]);
+          G.edge_mult[e0 + t] = em[t];
+          // reverse edge: in the sender's row, found by its sender i
+          const int32_t j = ncl[t];
+          const int32_t pos = (int32_t)(std::lower_bound(ncl.begin() + nrp[j], ncl.begin() + nrp[j + 1], i) -
+                                        ncl.begin());
+          G.rev[e0 + t] = (int32_t)(e0 + pos);
+        }
+      }
+    });
+  } catch (const std::bad_alloc&) {
+    return mp_fail(MP_ENOMEM, "graph_order_rows: host allocation failed");
+  }
+  return MP_OK;
+}
+
 extern "C" int mp_graph_sizes(const mp_graph* g, int64_t* n_rows, int64_t* n_edges, int32_t* R) {
   if (!g) return mp_fail(MP_EINVAL, "mp_graph_sizes: graph is NULL");
   if (n_rows) *n_rows = g->row_off.back();

@@ -62,11 +62,16 @@ def hex_links(P):
     return links
 
 
-def build_graph(elem_gid, P, elem_part, R, links=None):
+def build_graph(elem_gid, P, elem_part, R, links=None, order="locality"):
     """Reduced sub-graphs, CSR arrays, degrees and halo plan of a partition.
 
     ``links`` ([n_links, 2] element-local point pairs) defaults to the links
-    of a hexahedral element of order P; any element type may pass its own."""
+    of a hexahedral element of order P; any element type may pass its own.
+    ``order``: "locality" renumbers each sub-graph's rows in reverse
+    Cuthill-McKee order (graph_order_rows); "gid" keeps them in ascending
+    global id."""
+    if order not in ("locality", "gid"):
+        raise ValueError("order must be 'locality' or 'gid'")
     eg = np.ascontiguousarray(elem_gid, dtype=np.int64)
     part = np.ascontiguousarray(elem_part, dtype=np.int32)
     links = hex_links(P) if links is None else np.ascontiguousarray(links, dtype=np.int32)
@@ -74,6 +79,8 @@ def build_graph(elem_gid, P, elem_part, R, links=None):
     call("graph_partition", eg.shape[0], eg.shape[1], _ptr(eg), links.shape[0], _ptr(links),
          _ptr(part), R, C.byref(g))
     try:
+        if order == "locality":
+            call("graph_order_rows", g)
         n, e, r = C.c_int64(), C.c_int64(), C.c_int32()
         call("mp_graph_sizes", g, C.byref(n), C.byref(e), C.byref(r))
         N, E = n.value, e.value

@@ -30,3 +30,31 @@ def layer_params(H, ln, seed=3, perturb=True):
 
 def split_rows(a, off):
     return [a[off[r]:off[r + 1]] for r in range(len(off) - 1)]
+
+
+def oracle_row_order(host):
+    """Permutation that puts a host graph's rows in the oracle's order
+    (sub-graph by sub-graph, ascending global id): rows[perm] lines up with
+    the oracle's concatenated rows whatever numbering the library chose."""
+    off = host.row_off
+    return np.concatenate([off[r] + np.argsort(host.row_gid[off[r]:off[r + 1]], kind="stable")
+                           for r in range(len(off) - 1)])
+
+
+def oracle_edge_order(host):
+    """Permutation that puts a host graph's edges in the oracle's order
+    (sub-graph by sub-graph, by receiver then sender global id)."""
+    parts = []
+    for r in range(len(host.edge_off) - 1):
+        e0, e1 = host.edge_off[r], host.edge_off[r + 1]
+        gi, gj = host.row_gid[host.recv[e0:e1]], host.row_gid[host.col[e0:e1]]
+        parts.append(e0 + np.lexsort((gj, gi)))
+    return np.concatenate(parts)
+
+
+def by_gid(host, Y):
+    """Rows of a one-sub-graph run, indexed by global id."""
+    out = np.zeros((int(host.row_gid.max()) + 1,) + Y.shape[1:], Y.dtype)
+    out[host.row_gid] = Y
+    return out
+

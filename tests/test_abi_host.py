@@ -51,7 +51,7 @@ def test_hex_links_counts():
 
 def _compare_with_oracle(mesh, part, R):
     from paper_2410_01657_amd import build_graph
-    hg = build_graph(mesh.elem_gid, mesh.P, part, R)
+    hg = build_graph(mesh.elem_gid, mesh.P, part, R, order="gid")
     og, copies = partition_graph(mesh.elem_gid, mesh.P, part, R)
     assert hg.R == R
     for r, G in enumerate(og):
@@ -103,6 +103,71 @@ def test_graph_rcb_t_junctions():
     assert 3 in set(hg.edge_mult.tolist())
 
 
+def _by_gid(hg):
+    """Everything of a host graph that does not depend on its row numbering:
+    per sub-graph the rows (gid, node degree) and the edges (receiver gid,
+    sender gid, edge degree), and the halo groups as gid -> (sub-graph, gid)."""
+    out = []
+    for r in range(hg.R):
+        r0, r1 = hg.row_off[r], hg.row_off[r + 1]
+        e0, e1 = hg.edge_off[r], hg.edge_off[r + 1]
+        rows = sorted(zip(hg.row_gid[r0:r1].tolist(), hg.node_mult[r0:r1].tolist()))
+        edges = sorted(zip(hg.row_gid[hg.recv[e0:e1]].tolist(), hg.row_gid[hg.col[e0:e1]].tolist(),
+                           hg.edge_mult[e0:e1].tolist()))
+        out.append((rows, edges))
+    part = np.searchsorted(hg.row_off, np.arange(hg.n_rows), side="right") - 1
+    groups = {}
+    for k in range(hg.n_groups):
+        mem = hg.member[hg.group_ptr[k]:hg.group_ptr[k + 1]]
+        groups[int(hg.row_gid[mem[0]])] = [int(part[m]) for m in mem]
+    return out, groups
+
+
+def _csr_invariants(hg):
+    assert hg.rowptr[0] == 0 and hg.rowptr[-1] == hg.n_edges
+    np.testing.assert_array_equal(np.repeat(np.arange(hg.n_rows), np.diff(hg.rowptr)), hg.recv)
+    np.testing.assert_array_equal(hg.rev[hg.rev], np.arange(hg.n_edges))
+    np.testing.assert_array_equal(hg.recv[hg.rev], hg.col)
+    for r in range(hg.R):  # senders ascend inside each receiver's range, inside the sub-graph
+        e0, e1 = hg.edge_off[r], hg.edge_off[r + 1]
+        key = hg.recv[e0:e1].astype(np.int64) * hg.n_rows + hg.col[e0:e1]
+        assert np.all(np.diff(key) > 0)
+        assert hg.col[e0:e1].min() >= hg.row_off[r] and hg.col[e0:e1].max() < hg.row_off[r + 1]
+
+
+@pytest.mark.parametrize("case", ["c0_r8", "rcb_r8", "slab_r4"])
+def test_graph_locality_order_is_a_renumbering(case):
+    """graph_order_rows changes only the row numbering: the same rows,
+    edges, degrees and halo groups by global id, the CSR invariants hold,
+    and the bandwidth (largest |receiver - sender|) does not grow -- on a
+    z-slab it shrinks from a plane of the lattice to about a level of the
+    breadth-first sweep."""
+    from paper_2410_01657_amd import build_graph
+    if case == "c0_r8":
+        inp = make_inputs(CONFIGS["C0"])
+        m, part, R = inp.mesh, inp.elem_part, 8
+    elif case == "rcb_r8":
+        nel = (6, 5, 4)
+        m = box_mesh(nel, 2)
+        part, _ = rcb_partition(nel, 8, seed=11, ratio=(1.0, 10.0))
+        R = 8
+    else:
+        nel = (8, 8, 8)
+        m = box_mesh(nel, 3, with_positions=False)
+        part, R = slab_partition(nel, 4), 4
+    g0 = build_graph(m.elem_gid, m.P, part, R, order="gid")
+    g1 = build_graph(m.elem_gid, m.P, part, R)
+    _csr_invariants(g1)
+    assert _by_gid(g1) == _by_gid(g0)
+    bw0, bw1 = np.abs(g0.recv - g0.col).max(), np.abs(g1.recv - g1.col).max()
+    assert bw1 <= bw0
+    if case == "slab_r4":
+        assert bw0 == 25 * 25 and bw1 < bw0 / 2
+    g2 = build_graph(m.elem_gid, m.P, part, R)  # the order is a function of the graph
+    for f in ("row_gid", "rowptr", "col", "rev", "edge_mult", "node_mult", "member", "pair_rows_r"):
+        np.testing.assert_array_equal(getattr(g1, f), getattr(g2, f))
+
+
 @pytest.mark.slow
 def test_graph_c1_r16_sizes():
     from paper_2410_01657_amd import build_graph
@@ -148,6 +213,9 @@ def test_graph_partition_rejects_bad_input(L):
     with pytest.raises(MPError):
         call("graph_partition", 2, 8, None, links.shape[0], ptr(links), ptr(empty_part), 1, C.byref(g))
     assert g.value is None
+    with pytest.raises(MPError) as e:
+        call("graph_order_rows", None)
+    assert e.value.code == L.MP_EINVAL
 
 
 def _fake_desc(L, n_rows=10, n_edges=20):

@@ -23,7 +23,7 @@ DEV = "cuda"
 
 def _graphs(mesh, part, R):
     from paper_2410_01657_amd import DeviceGraph, build_graph
-    hg = build_graph(mesh.elem_gid, mesh.P, part, R)
+    hg = build_graph(mesh.elem_gid, mesh.P, part, R, order="gid")  # rows as the oracle's
     og, copies = partition_graph(mesh.elem_gid, mesh.P, part, R)
     return DeviceGraph(hg, DEV), og, halo_lists(og, copies)
 

@@ -11,7 +11,7 @@ from oracle.ball import ball_output
 from oracle.nmp import consistent_loss, model_bwd, model_fwd
 from oracle.problem import build_problem
 
-from _util import normwise
+from _util import by_gid, normwise, oracle_row_order
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
@@ -53,7 +53,8 @@ def test_model_fwd_bwd_fp32(model, R):
     spec = MODELS[model]
     inp = make_inputs(CONFIGS["C0"], perturb=True, spec=spec)
     part = inp.elem_part if R > 1 else None
-    _, Yg, Lg, gg = _gpu_run(spec, inp.params, inp, part if R > 1 else np.zeros(inp.mesh.n_elem, np.int32), R)
+    prob, Yg, Lg, gg = _gpu_run(spec, inp.params, inp, part if R > 1 else np.zeros(inp.mesh.n_elem, np.int32), R)
+    Yg = Yg[oracle_row_order(prob.dg.host)]
     Yo, Lo, go = _oracle_run(spec, inp.params, inp, part, R)
     tol_y = 1e-5 if model == "C0" else 1e-4
     assert normwise(Yg, Yo) < tol_y
@@ -66,7 +67,8 @@ def test_model_fwd_bwd_fp32(model, R):
 def test_model_bf16_error_bounded():
     spec = MODELS["H64-LN"]
     inp = make_inputs(CONFIGS["C0"], perturb=True, spec=spec)
-    _, Yg, Lg, gg = _gpu_run(spec, inp.params, inp, inp.elem_part, 8, gemm="bf16")
+    prob, Yg, Lg, gg = _gpu_run(spec, inp.params, inp, inp.elem_part, 8, gemm="bf16")
+    Yg = Yg[oracle_row_order(prob.dg.host)]
     Yo, Lo, go = _oracle_run(spec, inp.params, inp, inp.elem_part, 8)
     assert normwise(Yg, Yo) < 3e-2
     assert abs(Lg - Lo) / abs(Lo) < 3e-2
@@ -81,7 +83,7 @@ def test_r_consistency_gpu_c0():
     inp = make_inputs(CONFIGS["C0"], perturb=True, spec=spec)
     p1, Y1, L1, g1 = _gpu_run(spec, inp.params, inp, np.zeros(inp.mesh.n_elem, np.int32), 1)
     p8, Y8, L8, g8 = _gpu_run(spec, inp.params, inp, inp.elem_part, 8)
-    assert normwise(Y8, Y1[p8.dg.host.row_gid]) < 1e-5
+    assert normwise(Y8, by_gid(p1.dg.host, Y1)[p8.dg.host.row_gid]) < 1e-5
     assert abs(L8 - L1) / abs(L1) < 1e-5
     for k in g1:
         assert normwise(g8[k], g1[k]) < 1e-4, k
@@ -96,7 +98,7 @@ def test_none_mode_is_inconsistent_gpu():
     with torch.no_grad():
         Y1 = ConsistentGNN(spec, inp.params, DEV).forward(p1.dg, p1.X, p1.E0).cpu().numpy()
         Y8 = ConsistentGNN(spec, inp.params, DEV, halo=False).forward(p8.dg, p8.X, p8.E0).cpu().numpy()
-    assert normwise(Y8, Y1[p8.dg.host.row_gid]) > 1e-2
+    assert normwise(Y8, by_gid(p1.dg.host, Y1)[p8.dg.host.row_gid]) > 1e-2
 
 
 @pytest.mark.slow
@@ -113,6 +115,8 @@ def test_c1_consistency_and_sampled_parity():
         with torch.no_grad():
             Y = ConsistentGNN(cfg.spec, inp.params, DEV).forward(prob.dg, prob.X, prob.E0)
         outs[R] = (prob.dg.host.row_gid, Y.cpu().numpy())
+        if R == 1:
+            outs[R] = (None, by_gid(prob.dg.host, outs[R][1]))
         del prob
     gid16, Y16 = outs[16]
     _, Y1 = outs[1]

@@ -20,7 +20,7 @@ from oracle.ball import ball_grad
 from oracle.nmp import consistent_loss, model_bwd, model_fwd
 from oracle.problem import build_problem
 
-from _util import normwise
+from _util import normwise, oracle_edge_order
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
@@ -48,7 +48,7 @@ def test_periodic_edge_inputs_bit_exact(small):
     prob = Problem(m, field, target, part, 8, DEV)
     o = build_problem(m, field, target, part, 8)
     ref = np.concatenate(o.E0).astype(np.float32)
-    np.testing.assert_array_equal(prob.E0.cpu().numpy(), ref)
+    np.testing.assert_array_equal(prob.E0.cpu().numpy()[oracle_edge_order(prob.host)], ref)
 
 
 @pytest.mark.parametrize("gemm", ["f32", "bf16"])

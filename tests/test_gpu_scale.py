@@ -20,7 +20,7 @@ import torch
 from mpinputs import CONFIGS, make_inputs
 from oracle.ball import ball_grad, ball_output
 
-from _util import normwise
+from _util import by_gid, normwise
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 DEV = "cuda"
@@ -96,7 +96,7 @@ def test_c4_r64_matches_r1_fp32():
             out[R] = (hg.row_gid[m], Y.cpu().numpy()[m])
             assert (hg.edge_mult == 3).any()  # T-junctions of the uneven cut
         else:
-            out[R] = Y.cpu().numpy()
+            out[R] = by_gid(hg, Y.cpu().numpy())
         del prob, Y
         torch.cuda.empty_cache()
     g64, y64 = out[64]

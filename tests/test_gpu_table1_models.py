@@ -16,7 +16,7 @@ from mpinputs import CONFIGS, ModelSpec, count_params, init_params, make_inputs
 from oracle.nmp import consistent_loss, mlp_bwd, mlp_fwd, model_bwd, model_fwd
 from oracle.problem import build_problem
 
-from _util import normwise
+from _util import normwise, oracle_edge_order
 
 TABLE1 = {"small": (ModelSpec(H=8, n_layers=4, n_hidden=2, layernorm=True), 3979),
           "large": (ModelSpec(H=32, n_layers=4, n_hidden=5, layernorm=True), 91459)}
@@ -170,7 +170,8 @@ def test_table1_small_with_seven_edge_inputs(R):
     prob = Problem(inp.mesh, inp.field, inp.target, part, R, "cuda", edge_in=7)
     o_r = build_problem(inp.mesh, inp.field, inp.target, part if R > 1 else None, R,
                         unpartitioned_from_lattice=False, edge_in=7)
-    np.testing.assert_array_equal(prob.E0.cpu().numpy(), np.concatenate(o_r.E0).astype(np.float32))
+    np.testing.assert_array_equal(prob.E0.cpu().numpy()[oracle_edge_order(prob.host)],
+                                  np.concatenate(o_r.E0).astype(np.float32))
     p = build_problem(inp.mesh, inp.field, inp.target, None, 1, edge_in=7)
     Y, c = model_fwd(inp.params, spec, p.graphs, p.pair_lists, p.X, p.E0)
     Lo, gY, _ = consistent_loss(Y, p.T, p.graphs)

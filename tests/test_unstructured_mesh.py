@@ -93,7 +93,7 @@ def test_host_graph_matches_oracle():
     m = _mesh(1200, 8)
     for R in (1, 8):
         part = centroid_partition(m, R) if R > 1 else np.zeros(m.n_elem, np.int32)
-        hg = build_graph(m.elem_gid, None, part, R, m.links)
+        hg = build_graph(m.elem_gid, None, part, R, m.links, order="gid")
         og, copies = partition_graph(m.elem_gid, None, part, R, m.links)
         for r, G in enumerate(og):
             r0, r1 = hg.row_off[r], hg.row_off[r + 1]
