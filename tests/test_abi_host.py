@@ -135,7 +135,7 @@ def _csr_invariants(hg):
         assert hg.col[e0:e1].min() >= hg.row_off[r] and hg.col[e0:e1].max() < hg.row_off[r + 1]
 
 
-@pytest.mark.parametrize("case", ["c0_r8", "rcb_r8", "slab_r4"])
+@pytest.mark.parametrize("case", ["c0_r8", "rcb_r8", "slab_r4", "tet_r8"])
 def test_graph_locality_order_is_a_renumbering(case):
     """graph_order_rows changes only the row numbering: the same rows,
     edges, degrees and halo groups by global id, the CSR invariants hold,
@@ -151,19 +151,24 @@ def test_graph_locality_order_is_a_renumbering(case):
         m = box_mesh(nel, 2)
         part, _ = rcb_partition(nel, 8, seed=11, ratio=(1.0, 10.0))
         R = 8
-    else:
+    elif case == "slab_r4":
         nel = (8, 8, 8)
         m = box_mesh(nel, 3, with_positions=False)
         part, R = slab_partition(nel, 4), 4
-    g0 = build_graph(m.elem_gid, m.P, part, R, order="gid")
-    g1 = build_graph(m.elem_gid, m.P, part, R)
+    else:  # tetrahedra: irregular degrees, no lattice to follow
+        from mpinputs.tetmesh import centroid_partition, tet_mesh
+        m = tet_mesh(800, 3)
+        part, R = centroid_partition(m, 8), 8
+    links = getattr(m, "links", None)
+    g0 = build_graph(m.elem_gid, m.P, part, R, links, order="gid")
+    g1 = build_graph(m.elem_gid, m.P, part, R, links)
     _csr_invariants(g1)
     assert _by_gid(g1) == _by_gid(g0)
     bw0, bw1 = np.abs(g0.recv - g0.col).max(), np.abs(g1.recv - g1.col).max()
     assert bw1 <= bw0
     if case == "slab_r4":
         assert bw0 == 25 * 25 and bw1 < bw0 / 2
-    g2 = build_graph(m.elem_gid, m.P, part, R)  # the order is a function of the graph
+    g2 = build_graph(m.elem_gid, m.P, part, R, links)  # the order is a function of the graph
     for f in ("row_gid", "rowptr", "col", "rev", "edge_mult", "node_mult", "member", "pair_rows_r"):
         np.testing.assert_array_equal(getattr(g1, f), getattr(g2, f))
 
