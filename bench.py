@@ -263,7 +263,7 @@ def cpu_baseline(cfg, spec, inp, n_layers, sample_gids, outs, min_seconds=10.0):
 def main():
     a = _parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
+        print(json.dumps({"error": "one GPU only: all sub-graphs share one device and the halo sum runs on it; there is no multi-GPU halo exchange",
                           "n_gpus": a.gpus}))
         sys.exit(2)
     if a.copy_calibration:
