@@ -539,16 +539,34 @@ __global__ __launch_bounds__(256) void k_deep_gather(DevGraph g, const float* __
                                                      float* __restrict__ gx) {
   const int64_t j = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (j >= g.n_rows) return;
-  float s[H], t[H];
+  float s[H];
   vload<H>(gxn + j * H, s);
-  const int k1 = g.rowptr[j + 1];
-  for (int k = g.rowptr[j]; k < k1; ++k) {
-    vload<H>(gxi + (int64_t)k * H, t);
+  const int k0 = g.rowptr[j], k1 = g.rowptr[j + 1];
+  // a few edges at a time (4 at H = 8, else 2): their reverse indices
+  // first, then all their rows, so the dependent loads cost one round trip
+  // per group; the sums stay in edge order
+  constexpr int B = H == 8 ? 4 : 2;
+  for (int kb = k0; kb < k1; kb += B) {
+    int rv[B];
 #pragma unroll
-    for (int c = 0; c < H; ++c) s[c] += t[c];
-    vload<H>(gxj + (int64_t)g.rev[k] * H, t);
+    for (int q = 0; q < B; ++q) rv[q] = kb + q < k1 ? g.rev[kb + q] : 0;
+    float ti[B][H], tj[B][H];
 #pragma unroll
-    for (int c = 0; c < H; ++c) s[c] += t[c];
+    for (int q = 0; q < B; ++q) {
+      if (kb + q < k1) {
+        vload<H>(gxi + (int64_t)(kb + q) * H, ti[q]);
+        vload<H>(gxj + (int64_t)rv[q] * H, tj[q]);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < B; ++q) {
+      if (kb + q < k1) {
+#pragma unroll
+        for (int c = 0; c < H; ++c) s[c] += ti[q][c];
+#pragma unroll
+        for (int c = 0; c < H; ++c) s[c] += tj[q][c];
+      }
+    }
   }
   vstore<H>(gx + j * H, s);
 }
