@@ -427,16 +427,39 @@ __global__ __launch_bounds__(256) void k_deep_edge_fwd(DeepEdgeArgs a) {
       acc[c] = 0.f;
     }
   }
-  const int k1 = a.g.rowptr[i + 1];
-  for (int k = a.g.rowptr[i]; k < k1; ++k) {
+  const int k0 = a.g.rowptr[i], k1 = a.g.rowptr[i + 1];
+  // H = 8: the next edge's x_j and e are loaded before this edge's MLP
+  // runs, so their round trips (index, then row) overlap the arithmetic
+  // (at 16 and 32 the extra registers cost a wave per SIMD)
+  constexpr bool PF = H == 8;
+  float nxj[PF ? H : 1], ne[PF ? H : 1];
+  if constexpr (PF) {
+    if (k0 < k1) {
+      vload<H>(a.x + (int64_t)a.g.col[k0] * H, nxj);
+      vload<H>(a.e_in + (int64_t)k0 * H, ne);
+    }
+  }
+  for (int k = k0; k < k1; ++k) {
     const float* Lk = L + opaque_zero();  // re-read the weights per edge
-    float t[H];
-    vload<H>(a.x + (int64_t)a.g.col[k] * H, t);
+    if constexpr (PF) {
 #pragma unroll
-    for (int c = 0; c < H; ++c) in[H + c] = t[c];
-    vload<H>(a.e_in + (int64_t)k * H, t);
+      for (int c = 0; c < H; ++c) {
+        in[H + c] = nxj[c];
+        in[2 * H + c] = ne[c];
+      }
+      if (k + 1 < k1) {
+        vload<H>(a.x + (int64_t)a.g.col[k + 1] * H, nxj);
+        vload<H>(a.e_in + (int64_t)(k + 1) * H, ne);
+      }
+    } else {
+      float t[H];
+      vload<H>(a.x + (int64_t)a.g.col[k] * H, t);
 #pragma unroll
-    for (int c = 0; c < H; ++c) in[2 * H + c] = t[c];
+      for (int c = 0; c < H; ++c) in[H + c] = t[c];
+      vload<H>(a.e_in + (int64_t)k * H, t);
+#pragma unroll
+      for (int c = 0; c < H; ++c) in[2 * H + c] = t[c];
+    }
     float u[H];
     deep_fwd<H, KM, H, false>(Lk, m, in, u, RecRef{nullptr});
     if (a.ln) dln_fwd<H>(Lk + m.lg(), Lk + m.lb(), a.eps, u);
