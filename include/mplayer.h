@@ -289,7 +289,10 @@ int mp_deep_layer_workspace_size(const mp_deep_layer_cfg* cfg, const mp_dev_grap
  * (input [a*_i, x_i], 2H -> H); both updates residual.  x_in[N][H],
  * e_in[E][H] -> x_out[N][H], e_out[E][H]; a_star_out[N][H] (required)
  * receives the synchronised aggregate for the backward.  Outputs must not
- * alias inputs. */
+ * alias inputs.  Errors: MP_EINVAL for a bad configuration (H not 8, 16 or
+ * 32, n_hidden outside [0, 8], a non-positive ln_eps with LayerNorm, an
+ * unknown aggregate), NULL, unaligned or aliasing buffers; MP_EPLAN for a
+ * graph descriptor whose seal does not match its sizes. */
 int mp_deep_layer_forward(const mp_deep_layer_cfg* cfg, const float* theta_edge,
                           const float* theta_node, const mp_dev_graph* g, const float* x_in,
                           const float* e_in, float* x_out, float* e_out, float* a_star_out,
@@ -299,7 +302,9 @@ int mp_deep_layer_forward(const mp_deep_layer_cfg* cfg, const float* theta_edge,
  * gradients of x_in, e_in and both parameter arrays.  MLP activations are
  * recomputed; the workspace (mp_deep_layer_workspace_size) holds per-row
  * records of them.  g_e_out may be NULL (zero).  The graph needs its
- * reverse-edge array. */
+ * reverse-edge array.  Errors: as mp_deep_layer_forward, plus MP_EINVAL
+ * for a missing reverse-edge array or gradient outputs aliasing inputs and
+ * MP_ENOMEM for ws_bytes below mp_deep_layer_workspace_size. */
 int mp_deep_layer_backward(const mp_deep_layer_cfg* cfg, const float* theta_edge,
                            const float* theta_node, const mp_dev_graph* g, const float* x_in,
                            const float* e_in, const float* a_star, const float* g_x_out,
