@@ -168,10 +168,17 @@ __device__ __forceinline__ void phase_fence() { __builtin_amdgcn_sched_barrier(0
 struct RecRef {
   float* p;
 };
-template <int W>
+// NT: a column no kernel reads back before the weight-gradient pass, stored
+// non-temporally so it does not displace the node rows the kernel gathers.
+template <int W, bool NT = false>
 __device__ __forceinline__ void rstore(const RecRef& r, int c0, const float (&v)[W]) {
 #pragma unroll
-  for (int c = 0; c < W; ++c) r.p[(c0 + c) * kRecRows] = v[c];
+  for (int c = 0; c < W; ++c) {
+    if constexpr (NT)
+      __builtin_nontemporal_store(v[c], r.p + (c0 + c) * kRecRows);
+    else
+      r.p[(c0 + c) * kRecRows] = v[c];
+  }
 }
 template <int W>
 __device__ __forceinline__ void rload(const RecRef& r, int c0, float (&v)[W]) {
@@ -261,8 +268,8 @@ __device__ __forceinline__ void dln_bwd(const float* __restrict__ g, float eps, 
   float t[OM];
 #pragma unroll
   for (int c = 0; c < OM; ++c) t[c] = gy[c] * yh[c];
-  rstore<OM>(rec, c_ln, t);
-  rstore<OM>(rec, c_ln + OM, gy);
+  rstore<OM, true>(rec, c_ln, t);
+  rstore<OM, true>(rec, c_ln + OM, gy);
 #pragma unroll
   for (int c = 0; c < OM; ++c) gy[c] = rstd * (gyh[c] - m1 - yh[c] * m2);
 }
@@ -274,7 +281,7 @@ template <int H, int KM, int OM>
 __device__ __forceinline__ void deep_bwd(const float* __restrict__ L, const DeepLds<H, KM, OM>& m,
                                          const DeepRec<H, KM, OM>& rr, const float (&gu)[OM],
                                          const RecRef& rec, float (&d0)[H]) {
-  rstore<OM>(rec, rr.dout(), gu);
+  rstore<OM, true>(rec, rr.dout(), gu);
   float gh[H];
   dlin_t<OM, H, 0, H>(L + m.wo(), gu, gh);
   phase_fence();
@@ -283,7 +290,7 @@ __device__ __forceinline__ void deep_bwd(const float* __restrict__ L, const Deep
     rload<H>(rec, rr.h(l), hl);
 #pragma unroll
     for (int c = 0; c < H; ++c) d0[c] = gh[c] * (hl[c] > 0.f ? 1.f : hl[c] + 1.f);  // ELU' from ELU's value
-    rstore<H>(rec, rr.d(l), d0);
+    rstore<H, true>(rec, rr.d(l), d0);
     if (l > 0) dlin_t<H, H, 0, H>(L + m.wh(l - 1), d0, gh);
     phase_fence();
   }
@@ -360,7 +367,7 @@ __global__ __launch_bounds__(256) void k_deep_row_bwd(DeepRowArgs a) {
     float gy[OM];
     float in[K::KM];
     K::load_in(a, r, in);
-    rstore<K::KM>(rec, rr.in(), in);
+    rstore<K::KM, true>(rec, rr.in(), in);
     float u[OM];
     deep_fwd<H, K::KM, OM, true>(L, m, in, u, rec);
     if constexpr (OM < 8) {
@@ -496,7 +503,7 @@ __device__ __forceinline__ void deep_edge_bwd_one(const DeepEdgeArgs& a, const f
     vload<H>(a.e_in + k * H, t);
 #pragma unroll
     for (int c = 0; c < H; ++c) in[2 * H + c] = t[c];
-    rstore<KM>(rec, rr.in(), in);
+    rstore<KM, true>(rec, rr.in(), in);
     float u[H];
     deep_fwd<H, KM, H, true>(L, m, in, u, rec);
     // gradient of e' = e + MLP(...): the next layer's, plus Eq. 4b's adjoint
