@@ -173,6 +173,28 @@ def test_graph_locality_order_is_a_renumbering(case):
         np.testing.assert_array_equal(getattr(g1, f), getattr(g2, f))
 
 
+def test_graph_locality_order_disconnected_sub_graph():
+    """A sub-graph made of two meshes that share no node (two connected
+    components, each swept from its own start): still a renumbering, and
+    each component's rows stay together."""
+    from paper_2410_01657_amd import build_graph
+    a = box_mesh((3, 2, 2), 2, with_positions=False)
+    b = box_mesh((2, 2, 2), 2, with_positions=False)
+    eg = np.concatenate([a.elem_gid, b.elem_gid + a.n_gid])
+    part = np.zeros(eg.shape[0], np.int32)
+    part[a.n_elem:] = 1  # sub-graph 1: mesh b alone
+    part[: a.n_elem // 2] = 1  # ...and half of mesh a
+    g0 = build_graph(eg, 2, part, 2, order="gid")
+    g1 = build_graph(eg, 2, part, 2)
+    _csr_invariants(g1)
+    assert _by_gid(g1) == _by_gid(g0)
+    r0, r1 = g1.row_off[1], g1.row_off[2]
+    in_b = g1.row_gid[r0:r1] >= a.n_gid
+    # the order is component by component: mesh b's rows are one contiguous run
+    idx = np.flatnonzero(in_b)
+    assert idx.size > 0 and idx[-1] - idx[0] + 1 == idx.size
+
+
 @pytest.mark.slow
 def test_graph_c1_r16_sizes():
     from paper_2410_01657_amd import build_graph
