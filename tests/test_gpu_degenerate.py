@@ -4,7 +4,9 @@ A single P = 1 hexahedral element gives 8 rows and 24 directed edges: fewer
 edges than one edge tile and fewer rows than one wave, so every kernel runs
 only its ragged tail.  Two such elements cut into two sub-graphs of one
 element each make every row of the shared face a halo copy (Eq. 4c, 4d), with
-four two-member groups.  Forward and adjoint are compared element by element
+four two-member groups.  A 4 x 2 x 1 box cut into one element and the other
+seven puts a one-element sub-graph beside a larger one in the same launch.
+Forward and adjoint are compared element by element
 with the FP64 oracle, at the tolerances of the one-layer parity tests.
 """
 
@@ -22,7 +24,8 @@ pytestmark = pytest.mark.gpu
 
 DEV = "cuda"
 
-CASES = {"one_element": ((1, 1, 1), [0], 1), "two_elements_R2": ((2, 1, 1), [0, 1], 2)}
+CASES = {"one_element": ((1, 1, 1), [0], 1), "two_elements_R2": ((2, 1, 1), [0, 1], 2),
+         "one_and_seven_R2": ((4, 2, 1), [0] + [1] * 7, 2)}
 
 
 def _t(a):
@@ -41,7 +44,8 @@ def test_smallest_graphs_forward_and_adjoint(case, H, ln, gemm):
     og, copies = partition_graph(m.elem_gid, m.P, part, R)
     pairs = halo_lists(og, copies)
     dg = DeviceGraph(hg, DEV)
-    assert (dg.n_rows, dg.n_edges) == (8 * R, 24 * R)
+    assert (dg.n_rows, dg.n_edges) == (sum(G.n for G in og), sum(G.e for G in og))
+    assert og[0].n == 8 and og[0].e == 24
     spec, o, names = layer_params(H, ln)
     rng = np.random.default_rng(5 + H + R)
     x = rng.standard_normal((dg.n_rows, H)).astype(np.float32)
