@@ -17,9 +17,9 @@ from mpinputs import (CONFIGS, ModelSpec, box_mesh, block_partition, count_param
                       gll_points, init_params, make_inputs, rcb_partition,
                       slab_partition, velocity_field)
 from oracle.graph import lattice_graph, partition_graph, halo_lists, table2_stats
-from oracle.nmp import (consistent_loss, halo_sync, halo_sync_adj, local_aggregate,
-                        local_aggregate_adj, model_bwd, model_fwd, mse_loss,
-                        nmp_layer_fwd)
+from oracle.nmp import (consistent_loss, edge_inputs, elu, elu_deriv, halo_sync,
+                        halo_sync_adj, layer_norm_fwd, local_aggregate, local_aggregate_adj,
+                        mlp_fwd, model_bwd, model_fwd, mse_loss, nmp_layer_fwd)
 from oracle.problem import build_problem
 from oracle.ball import ball_output, ball_grad
 
@@ -393,6 +393,102 @@ def test_hand_computed_single_element():
     # and the edge states: e' = x_i + x_j + 1 for the edge 0 <- 1 (receiver 0)
     k = np.nonzero((G.recv == 0) & (G.send == 1))[0][0]
     assert en[0][k, 0] == 1 + 2 + 1
+
+
+def test_hand_computed_single_element_negative_branch():
+    """The same P=1 element with pre-activations of both signs, so ELU's
+    negative branch (exp(z) - 1) enters the result.
+
+    H=1, edge MLP [1, -1, 0] then 1, node MLP [1, 0] then 1, zero biases,
+    e = 0: e'_ij = ELU(x_i - x_j) and x'_i = x_i + ELU(sum_j e'_ij).  With
+    x_k = k+1, node 0 (neighbours 1, 2, 4) gets sum = e^-1 + e^-2 + e^-4 - 3
+    = -2.4784696367032108..., so x'_0 = 1 + (e^sum - 1) = e^sum; node 3
+    (neighbours 1, 2, 7) gets 2 + 1 + (e^-4 - 1); node 7 (neighbours 3, 5,
+    6) gets 4 + 2 + 1.  Decimals worked out to 40 digits.
+    """
+    spec = ModelSpec(H=1, n_layers=1, layernorm=False)
+    m = box_mesh((1, 1, 1), 1)
+    G = lattice_graph(m.npts)
+    params = {"mp0.edge.lin0.W": np.array([[1.0, -1.0, 0.0]]), "mp0.edge.lin0.b": np.zeros(1),
+              "mp0.edge.lin1.W": np.array([[1.0]]), "mp0.edge.lin1.b": np.zeros(1),
+              "mp0.node.lin0.W": np.array([[1.0, 0.0]]), "mp0.node.lin0.b": np.zeros(1),
+              "mp0.node.lin1.W": np.array([[1.0]]), "mp0.node.lin1.b": np.zeros(1)}
+    x = (np.arange(8, dtype=np.float64) + 1.0)[:, None]
+    e = np.zeros((G.e, 1))
+    xn, en, _ = nmp_layer_fwd(params, 0, spec, [G], {}, [x], [e])
+    np.testing.assert_allclose(xn[0][0, 0], 0.08387148126485265363, rtol=1e-14)
+    np.testing.assert_allclose(xn[0][3, 0], 6.018315638888734180, rtol=1e-15)
+    np.testing.assert_allclose(xn[0][7, 0], 15.0, rtol=1e-15)
+    k = np.nonzero((G.recv == 0) & (G.send == 4))[0][0]
+    np.testing.assert_allclose(en[0][k, 0], -0.9816843611112658, rtol=1e-15)   # e^-4 - 1
+
+
+# ---------------------------------------- elementary functions of Sec. III
+
+
+def test_elu_values():
+    """ELU with alpha = 1: z for z > 0, exp(z) - 1 otherwise; its derivative
+    1, else exp(z).  Decimal values of e^-1 - 1, e^-0.5 - 1 and e^-1."""
+    z = np.array([-1.0, -0.5, 0.0, 2.0, -40.0, 1e-300])
+    np.testing.assert_allclose(elu(z), [-0.63212055882855767840, -0.39346934028736657640, 0.0, 2.0,
+                                        -1.0, 1e-300], rtol=1e-15, atol=0)
+    # small |z|: exp(z) - 1 without cancellation (~z)
+    np.testing.assert_allclose(elu(np.array([-1e-10])), [-9.9999999995e-11], rtol=1e-15)
+    np.testing.assert_allclose(elu_deriv(np.array([-1.0, 3.0])), [0.36787944117144232160, 1.0],
+                               rtol=1e-15)
+
+
+def test_layer_norm_closed_forms():
+    """LayerNorm over a row's features: mean, biased variance (divide by H),
+    eps added inside the square root, then the per-feature gain and shift."""
+    z = np.array([[1.0, 2.0, 3.0, 4.0]])
+    one, zero = np.ones(4), np.zeros(4)
+    # mean 5/2, biased variance 5/4; with eps = 1 the scale is 1/sqrt(9/4) = 2/3
+    y, _ = layer_norm_fwd(z, one, zero, 1.0)
+    np.testing.assert_allclose(y[0], [-1.0, -1.0 / 3.0, 1.0 / 3.0, 1.0], rtol=0, atol=2e-16)
+    # eps = 1e-5: scale 1/sqrt(1.25001), decimals worked out to 40 digits
+    y, _ = layer_norm_fwd(z, one, zero, 1e-5)
+    np.testing.assert_allclose(y[0], [-1.3416354199689269826, -0.44721180665630899419,
+                                      0.44721180665630899419, 1.3416354199689269826], rtol=1e-15)
+    # gain and shift act per feature after the normalisation
+    y, _ = layer_norm_fwd(z, np.array([2.0, 3.0, -1.0, 0.5]), np.array([0.5, 0.0, 1.0, -2.0]), 1.0)
+    np.testing.assert_allclose(y[0], [-1.5, -1.0, 2.0 / 3.0, -1.5], rtol=0, atol=4e-16)
+    # a constant row normalises to zero, leaving the shift
+    y, _ = layer_norm_fwd(np.full((1, 4), 7.0), one, np.array([0.25, -1.0, 0.0, 3.0]), 1e-5)
+    np.testing.assert_array_equal(y[0], [0.25, -1.0, 0.0, 3.0])
+
+
+def test_mlp_with_layer_norm_hand_computed():
+    """One row through Linear(1 -> 4), ELU, Linear(4 -> 4), LayerNorm: with
+    W0 = (1, 2, -3, 4)^T, W1 = identity and zero biases the last Linear
+    outputs (1, 2, e^-3 - 1, 4); LayerNorm with eps = 1 then gives its
+    centred values over sqrt(biased variance + 1)."""
+    spec = ModelSpec(H=4, n_layers=1, layernorm=True, ln_eps=1.0)
+    params = {"t.lin0.W": np.array([[1.0], [2.0], [-3.0], [4.0]]), "t.lin0.b": np.zeros(4),
+              "t.lin1.W": np.eye(4), "t.lin1.b": np.zeros(4),
+              "t.ln.g": np.ones(4), "t.ln.b": np.zeros(4)}
+    y, _ = mlp_fwd(params, "t", np.array([[1.0]]), spec, True)
+    # v = (1, 2, -0.95021293163213605702, 4): mean 1.5124467670919659857,
+    # biased variance 3.1882309305732950135; decimals worked out to 40 digits
+    np.testing.assert_allclose(y[0], [-0.25039949445572325360, 0.23823563905617466003,
+                                      -1.2033420506804218937, 1.2155059060799704873], rtol=1e-14)
+
+
+def test_edge_input_orientation():
+    """Edge inputs on one P=1 element of size 0.5 x 1 x 1: for receiver i and
+    sender j they are (p_j - p_i, |p_j - p_i|).  Lattice ids: i + 3j + 6k."""
+    m = box_mesh((2, 1, 1), 1)
+    G = lattice_graph(m.npts)
+    E = edge_inputs(G, m.pos)
+
+    def at(i, j):
+        return E[np.nonzero((G.recv == i) & (G.send == j))[0][0]]
+
+    np.testing.assert_array_equal(at(0, 1), [0.5, 0.0, 0.0, 0.5])     # sender at x = 0.5
+    np.testing.assert_array_equal(at(1, 0), [-0.5, 0.0, 0.0, 0.5])
+    np.testing.assert_array_equal(at(0, 3), [0.0, 1.0, 0.0, 1.0])     # sender at y = 1
+    np.testing.assert_array_equal(at(6, 0), [0.0, 0.0, -1.0, 1.0])    # receiver at z = 1
+    np.testing.assert_array_equal(at(2, 1), [-0.5, 0.0, 0.0, 0.5])
 
 
 # ------------------------------------------------------------ P11 symmetry
