@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define MP_ABI_VERSION 1
+#define MP_ABI_VERSION 2
 
 enum {
   MP_OK = 0,
@@ -112,6 +112,12 @@ int mp_graph_sizes(const mp_graph* g, int64_t* n_rows, int64_t* n_edges, int32_t
 int mp_graph_export(const mp_graph* g, int64_t* row_off, int64_t* edge_off,
                     int64_t* row_gid, int32_t* rowptr, int32_t* recv, int32_t* col,
                     int32_t* rev, uint8_t* edge_mult, uint8_t* node_mult);
+/* Content checksum of the graph's device-side arrays (rowptr, recv, col,
+ * rev, edge_mult, in that order), computed by graph_partition and again by
+ * graph_order_rows.  Two graphs whose arrays differ anywhere (for instance
+ * one mesh in ascending-id and in locality row order, which have the same
+ * sizes) get different checksums with overwhelming probability. */
+int mp_graph_checksum(const mp_graph* g, uint64_t* checksum);
 int mp_graph_destroy(mp_graph* g);
 
 typedef struct mp_halo_plan mp_halo_plan;
@@ -135,13 +141,24 @@ int mp_halo_plan_export(const mp_halo_plan* p, int32_t* group_ptr, int32_t* memb
                         int32_t* pair_r, int32_t* pair_s, int64_t* pair_ptr,
                         int32_t* pair_rows_r, int32_t* pair_rows_s,
                         int64_t* halo_rows, int32_t* neighbours);
+/* checksum: content checksum of group_ptr and member, chained to the
+ * checksum of the graph the plan was built on; graph_checksum: that graph's
+ * mp_graph_checksum at build time.  A plan is valid only beside the graph
+ * whose checksum equals its graph_checksum. */
+int mp_halo_plan_checksum(const mp_halo_plan* p, uint64_t* checksum, uint64_t* graph_checksum);
 int mp_halo_plan_destroy(mp_halo_plan* p);
 
 /* ---------------------------------------------------------------------
- * Device graph descriptor.  All arrays are device memory exported from
- * mp_graph / mp_halo_plan; the caller keeps them alive.  seal is the value
- * mp_dev_graph_seal() computes from the sizes; entry points reject a
- * descriptor whose seal does not match (MP_EPLAN).
+ * Device graph descriptor (the reduced graph of Sec. II-A and the halo plan
+ * of Eq. 4c-d).  All arrays are device memory holding copies of what
+ * mp_graph_export / mp_halo_plan_export return; the caller keeps them
+ * alive.  graph_checksum is mp_graph_checksum of the graph exported;
+ * plan_checksum and plan_graph_checksum are the two values
+ * mp_halo_plan_checksum returns for the plan exported.  seal is written by
+ * mp_dev_graph_seal; every device entry point recomputes it from the
+ * descriptor's sizes, pointers and checksums and rejects a descriptor that
+ * is unsealed, was changed after sealing, or pairs a graph with a plan
+ * built for another graph (MP_EPLAN, before any launch).
  * ------------------------------------------------------------------- */
 typedef struct {
   int64_t n_rows, n_edges, n_groups, n_members;
@@ -151,11 +168,23 @@ typedef struct {
   const int32_t* rev;       /* [n_edges] reverse edge */
   const uint8_t* edge_mult; /* [n_edges] d_ij >= 1 */
   const int32_t* group_ptr; /* [n_groups+1] */
-  const int32_t* member;    /* [n_members] */
+  const int32_t* member;    /* [n_members] (may be NULL when n_members = 0) */
+  uint64_t graph_checksum;
+  uint64_t plan_checksum;
+  uint64_t plan_graph_checksum;
   uint64_t seal;
 } mp_dev_graph;
 
-uint64_t mp_dev_graph_seal(const mp_dev_graph* g);
+/* Seal a filled descriptor (a set-up call, not asynchronous).  Checks the
+ * sizes and pointers, and that the plan was built for this graph
+ * (plan_graph_checksum == graph_checksum); with verify_device != 0 it also
+ * reads every array back from the device (synchronous copies; host memory
+ * for the largest array is allocated and freed) and recomputes both content
+ * checksums, so arrays uploaded from another graph or plan, or changed on
+ * the device, are refused.  Errors: MP_EINVAL (NULL descriptor or array,
+ * bad sizes), MP_EPLAN (checksum mismatch), MP_EHIP (a copy failed).  On
+ * error seal is left 0. */
+int mp_dev_graph_seal(mp_dev_graph* g, int verify_device);
 
 /* ---------------------------------------------------------------------
  * One consistent NMP layer (Eq. 4a-e) on all sub-graphs at once.
@@ -292,7 +321,8 @@ int mp_deep_layer_workspace_size(const mp_deep_layer_cfg* cfg, const mp_dev_grap
  * alias inputs.  Errors: MP_EINVAL for a bad configuration (H not 8, 16 or
  * 32, n_hidden outside [0, 8], a non-positive ln_eps with LayerNorm, an
  * unknown aggregate), NULL, unaligned or aliasing buffers; MP_EPLAN for a
- * graph descriptor whose seal does not match its sizes. */
+ * graph descriptor that is unsealed, changed after sealing, or pairs a
+ * graph with another graph's halo plan. */
 int mp_deep_layer_forward(const mp_deep_layer_cfg* cfg, const float* theta_edge,
                           const float* theta_node, const mp_dev_graph* g, const float* x_in,
                           const float* e_in, float* x_out, float* e_out, float* a_star_out,

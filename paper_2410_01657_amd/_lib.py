@@ -12,6 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmplayer.so")
 
 MP_OK, MP_EINVAL, MP_EPLAN, MP_ENOMEM, MP_EHIP = 0, 1, 2, 3, 4
+ABI_VERSION = 2
 MP_F32, MP_BF16 = 0, 1
 MP_AGG_STATE, MP_AGG_MESSAGE = 0, 1
 
@@ -22,7 +23,8 @@ vp = C.c_void_p
 class MpDevGraph(C.Structure):
     _fields_ = [("n_rows", c_i64), ("n_edges", c_i64), ("n_groups", c_i64), ("n_members", c_i64),
                 ("rowptr", vp), ("recv", vp), ("col", vp), ("rev", vp), ("edge_mult", vp),
-                ("group_ptr", vp), ("member", vp), ("seal", c_u64)]
+                ("group_ptr", vp), ("member", vp), ("graph_checksum", c_u64), ("plan_checksum", c_u64),
+                ("plan_graph_checksum", c_u64), ("seal", c_u64)]
 
 
 class MpLayerCfg(C.Structure):
@@ -77,12 +79,14 @@ _SIGS = {
     "graph_order_rows": (c_i32, [vp]),
     "mp_graph_sizes": (c_i32, [vp, P(c_i64), P(c_i64), P(c_i32)]),
     "mp_graph_export": (c_i32, [vp] + [vp] * 9),
+    "mp_graph_checksum": (c_i32, [vp, P(c_u64)]),
     "mp_graph_destroy": (c_i32, [vp]),
     "halo_plan_build": (c_i32, [vp, P(vp)]),
     "mp_halo_plan_sizes": (c_i32, [vp, P(c_i64), P(c_i64), P(c_i64), P(c_i64)]),
     "mp_halo_plan_export": (c_i32, [vp] + [vp] * 9),
+    "mp_halo_plan_checksum": (c_i32, [vp, P(c_u64), P(c_u64)]),
     "mp_halo_plan_destroy": (c_i32, [vp]),
-    "mp_dev_graph_seal": (c_u64, [P(MpDevGraph)]),
+    "mp_dev_graph_seal": (c_i32, [P(MpDevGraph), c_i32]),
     "mp_layer_workspace_size": (c_i32, [P(MpLayerCfg), P(MpDevGraph), c_i32, P(C.c_size_t)]),
     "mp_layer_forward": (c_i32, [P(MpLayerCfg), P(MpLayerParams), P(MpDevGraph), vp, vp, vp, vp, vp,
                                  vp, vp, C.c_size_t, vp]),
@@ -130,7 +134,7 @@ def lib():
             f = getattr(L, name)
             f.restype = res
             f.argtypes = args
-        if L.mp_abi_version() != 1:
+        if L.mp_abi_version() != ABI_VERSION:
             raise RuntimeError("libmplayer.so ABI version mismatch")
         _lib = L
     return _lib

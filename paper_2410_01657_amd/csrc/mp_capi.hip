@@ -27,16 +27,64 @@ int mp_fail(int code, const char* fmt, ...) {
 extern "C" int mp_abi_version(void) { return MP_ABI_VERSION; }
 extern "C" const char* mp_last_error(void) { return g_err; }
 
-extern "C" uint64_t mp_dev_graph_seal(const mp_dev_graph* g) {
-  if (!g) return 0;
-  uint64_t h = 1469598103934665603ull;  // FNV-1a over the four sizes
-  const int64_t v[4] = {g->n_rows, g->n_edges, g->n_groups, g->n_members};
-  const unsigned char* p = reinterpret_cast<const unsigned char*>(v);
-  for (size_t i = 0; i < sizeof(v); ++i) {
-    h ^= p[i];
-    h *= 1099511628211ull;
+namespace {
+
+// The value a sealed descriptor carries: a hash of its sizes, array
+// pointers and checksums, so a descriptor edited after sealing is refused.
+uint64_t seal_value(const mp_dev_graph* g) {
+  const uint64_t v[14] = {(uint64_t)g->n_rows, (uint64_t)g->n_edges, (uint64_t)g->n_groups,
+                          (uint64_t)g->n_members, (uint64_t)(uintptr_t)g->rowptr, (uint64_t)(uintptr_t)g->recv,
+                          (uint64_t)(uintptr_t)g->col, (uint64_t)(uintptr_t)g->rev,
+                          (uint64_t)(uintptr_t)g->edge_mult, (uint64_t)(uintptr_t)g->group_ptr,
+                          (uint64_t)(uintptr_t)g->member, g->graph_checksum, g->plan_checksum,
+                          g->plan_graph_checksum};
+  return mp::hash_bytes(v, sizeof(v), 0x6d707365616cull) | 1u;  // never 0: 0 means "not sealed"
+}
+
+}  // namespace
+
+extern "C" int mp_dev_graph_seal(mp_dev_graph* g, int verify_device) {
+  if (!g) return mp_fail(MP_EINVAL, "mp_dev_graph_seal: descriptor is NULL");
+  g->seal = 0;
+  if (g->n_rows <= 0 || g->n_edges <= 0 || g->n_groups < 0 || g->n_members < 0)
+    return mp_fail(MP_EINVAL, "mp_dev_graph_seal: sizes must be positive (rows %lld, edges %lld)",
+                   (long long)g->n_rows, (long long)g->n_edges);
+  if (!g->rowptr || !g->recv || !g->col || !g->rev || !g->edge_mult || !g->group_ptr ||
+      (g->n_members > 0 && !g->member))
+    return mp_fail(MP_EINVAL, "mp_dev_graph_seal: an array pointer is NULL");
+  if (g->plan_graph_checksum != g->graph_checksum)
+    return mp_fail(MP_EPLAN, "mp_dev_graph_seal: the halo plan was built for another graph "
+                   "(plan's graph checksum %016llx, graph checksum %016llx)",
+                   (unsigned long long)g->plan_graph_checksum, (unsigned long long)g->graph_checksum);
+  if (verify_device) {
+    // Read every array back and recompute both checksums.
+    std::vector<unsigned char> buf;
+    hipError_t err = hipSuccess;
+    auto fetch = [&](const void* p, size_t bytes) -> const void* {
+      try {
+        buf.resize(bytes);
+      } catch (...) {
+        err = hipErrorOutOfMemory;
+        return nullptr;
+      }
+      if (bytes == 0) return buf.data();
+      err = hipMemcpy(buf.data(), p, bytes, hipMemcpyDeviceToHost);
+      return err == hipSuccess ? buf.data() : nullptr;
+    };
+    const uint64_t gcs = mp::graph_checksum_of(g->n_rows, g->n_edges, g->rowptr, g->recv, g->col, g->rev,
+                                               g->edge_mult, fetch);
+    if (err != hipSuccess) return mp_fail(MP_EHIP, "mp_dev_graph_seal: reading the graph arrays: %s", hipGetErrorString(err));
+    if (gcs != g->graph_checksum)
+      return mp_fail(MP_EPLAN, "mp_dev_graph_seal: the device graph arrays do not match the graph checksum");
+    const uint64_t pcs = mp::plan_checksum_of(g->graph_checksum, g->n_groups, g->n_members, g->group_ptr,
+                                              g->member, fetch);
+    if (err != hipSuccess) return mp_fail(MP_EHIP, "mp_dev_graph_seal: reading the halo plan: %s", hipGetErrorString(err));
+    if (pcs != g->plan_checksum)
+      return mp_fail(MP_EPLAN, "mp_dev_graph_seal: the device halo plan does not match the plan checksum "
+                     "(or was built for another graph)");
   }
-  return h;
+  g->seal = seal_value(g);
+  return MP_OK;
 }
 
 namespace {
@@ -60,7 +108,10 @@ int check_graph(const mp_dev_graph* g, bool need_rev) {
   if (!g->rowptr || !g->recv || !g->col || !g->edge_mult || (need_rev && !g->rev))
     return mp_fail(MP_EINVAL, "graph array is NULL");
   if (g->n_groups > 0 && (!g->group_ptr || !g->member)) return mp_fail(MP_EINVAL, "halo plan array is NULL");
-  if (g->seal != mp_dev_graph_seal(g)) return mp_fail(MP_EPLAN, "graph descriptor seal does not match its sizes");
+  if (g->plan_graph_checksum != g->graph_checksum)
+    return mp_fail(MP_EPLAN, "graph descriptor pairs a graph with a halo plan built for another graph");
+  if (g->seal == 0 || g->seal != seal_value(g))
+    return mp_fail(MP_EPLAN, "graph descriptor is not sealed, or was changed after mp_dev_graph_seal");
   return MP_OK;
 }
 

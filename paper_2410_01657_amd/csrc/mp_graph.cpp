@@ -3,7 +3,9 @@
 #include <algorithm>
 #include <cstdint>
 #include <cstring>
+#include <exception>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <thread>
@@ -19,6 +21,11 @@ struct mp_graph {
   std::vector<int32_t> recv, col, rev;     // [E]
   std::vector<uint8_t> edge_mult;          // [E]
   std::vector<uint8_t> node_mult;          // [N]
+  uint64_t checksum = 0;                   // of rowptr, recv, col, rev, edge_mult
+  void seal() {
+    checksum = mp::graph_checksum_of(row_off.back(), edge_off.back(), rowptr.data(), recv.data(), col.data(),
+                                     rev.data(), edge_mult.data(), mp::host_fetch);
+  }
 };
 
 struct mp_halo_plan {
@@ -29,10 +36,17 @@ struct mp_halo_plan {
   std::vector<int32_t> pair_rows_r, pair_rows_s;
   std::vector<int64_t> halo_rows;
   std::vector<int32_t> neighbours;
+  uint64_t graph_checksum = 0;  // checksum of the graph the plan was built on
+  uint64_t checksum = 0;        // of group_ptr, member, chained to graph_checksum
 };
 
 namespace {
 
+// Runs f(0..n-1) on up to 16 threads.  An exception thrown by f (a failed
+// allocation) stops the worker that threw it; after every thread has joined
+// the first one is rethrown on the calling thread, where the entry point
+// turns it into an error code.  If a thread cannot be started, its share of
+// the work runs on the calling thread.
 template <class F>
 void parallel_for(int n, F&& f) {
   unsigned hw = std::thread::hardware_concurrency();
@@ -41,13 +55,26 @@ void parallel_for(int n, F&& f) {
     for (int i = 0; i < n; ++i) f(i);
     return;
   }
-  std::vector<std::thread> th;
-  th.reserve(nt);
-  for (int t = 0; t < nt; ++t)
-    th.emplace_back([&, t] {
+  std::mutex mu;
+  std::exception_ptr first;
+  auto work = [&](int t) {
+    try {
       for (int i = t; i < n; i += nt) f(i);
-    });
+    } catch (...) {
+      std::lock_guard<std::mutex> lk(mu);
+      if (!first) first = std::current_exception();
+    }
+  };
+  std::vector<std::thread> th;
+  int started = 0;
+  try {
+    th.reserve(nt);
+    for (; started < nt; ++started) th.emplace_back(work, started);
+  } catch (...) {
+  }
+  for (int t = started; t < nt; ++t) work(t);
   for (auto& x : th) x.join();
+  if (first) std::rethrow_exception(first);
 }
 
 struct SubGraphBuild {
@@ -221,8 +248,11 @@ extern "C" int graph_partition(int64_t n_elem, int32_t npe, const int64_t* elem_
       }
     });
     if (bad_mult) return mp_fail(MP_EINVAL, "graph_partition: edge degree outside [1, 255]");
+    G->seal();
   } catch (const std::bad_alloc&) {
     return mp_fail(MP_ENOMEM, "graph_partition: host allocation failed");
+  } catch (...) {
+    return mp_fail(MP_ENOMEM, "graph_partition: host resources (memory or threads) exhausted");
   }
   *out = G.release();
   return MP_OK;
@@ -358,8 +388,13 @@ extern "C" int graph_order_rows(mp_graph* g) {
       }
     });
   } catch (const std::bad_alloc&) {
+    g->seal();
     return mp_fail(MP_ENOMEM, "graph_order_rows: host allocation failed");
+  } catch (...) {
+    g->seal();
+    return mp_fail(MP_ENOMEM, "graph_order_rows: host resources (memory or threads) exhausted");
   }
+  g->seal();
   return MP_OK;
 }
 
@@ -389,6 +424,12 @@ extern "C" int mp_graph_export(const mp_graph* g, int64_t* row_off, int64_t* edg
   copy_out(rev, g->rev);
   copy_out(edge_mult, g->edge_mult);
   copy_out(node_mult, g->node_mult);
+  return MP_OK;
+}
+
+extern "C" int mp_graph_checksum(const mp_graph* g, uint64_t* checksum) {
+  if (!g || !checksum) return mp_fail(MP_EINVAL, "mp_graph_checksum: NULL argument");
+  *checksum = g->checksum;
   return MP_OK;
 }
 
@@ -465,7 +506,10 @@ extern "C" int halo_plan_build(const mp_graph* g, mp_halo_plan** out) {
     // pairs are sorted by (r, s): each listed pair is one neighbour of r
     P->neighbours.assign(R, 0);
     for (int32_t r : P->pair_r) ++P->neighbours[r];
-  } catch (const std::bad_alloc&) {
+    P->graph_checksum = g->checksum;
+    P->checksum = mp::plan_checksum_of(g->checksum, (int64_t)P->group_ptr.size() - 1, (int64_t)P->member.size(),
+                                       P->group_ptr.data(), P->member.data(), mp::host_fetch);
+  } catch (...) {
     return mp_fail(MP_ENOMEM, "halo_plan_build: host allocation failed");
   }
   *out = P.release();
@@ -496,6 +540,13 @@ extern "C" int mp_halo_plan_export(const mp_halo_plan* p, int32_t* group_ptr, in
   copy_out(pair_rows_s, p->pair_rows_s);
   copy_out(halo_rows, p->halo_rows);
   copy_out(neighbours, p->neighbours);
+  return MP_OK;
+}
+
+extern "C" int mp_halo_plan_checksum(const mp_halo_plan* p, uint64_t* checksum, uint64_t* graph_checksum) {
+  if (!p || !checksum || !graph_checksum) return mp_fail(MP_EINVAL, "mp_halo_plan_checksum: NULL argument");
+  *checksum = p->checksum;
+  *graph_checksum = p->graph_checksum;
   return MP_OK;
 }
 

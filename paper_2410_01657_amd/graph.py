@@ -40,6 +40,9 @@ class HostGraph:
     pair_rows_s: np.ndarray
     halo_rows: np.ndarray
     neighbours: np.ndarray
+    graph_checksum: int = 0        # mp_graph_checksum
+    plan_checksum: int = 0         # mp_halo_plan_checksum: the plan's own
+    plan_graph_checksum: int = 0   # ... and that of the graph it was built on
 
     @property
     def n_rows(self):
@@ -91,6 +94,8 @@ def build_graph(elem_gid, P, elem_part, R, links=None, order="locality"):
         call("mp_graph_export", g, *[_ptr(arr[k]) for k in
                                      ("row_off", "edge_off", "row_gid", "rowptr", "recv", "col",
                                       "rev", "edge_mult", "node_mult")])
+        gcs = C.c_uint64()
+        call("mp_graph_checksum", g, C.byref(gcs))
         h = C.c_void_p()
         call("halo_plan_build", g, C.byref(h))
         try:
@@ -105,11 +110,14 @@ def build_graph(elem_gid, P, elem_part, R, links=None, order="locality"):
             call("mp_halo_plan_export", h, *[_ptr(harr[k]) for k in
                                              ("group_ptr", "member", "pair_r", "pair_s", "pair_ptr",
                                               "pair_rows_r", "pair_rows_s", "halo_rows", "neighbours")])
+            pcs, pgcs = C.c_uint64(), C.c_uint64()
+            call("mp_halo_plan_checksum", h, C.byref(pcs), C.byref(pgcs))
         finally:
             lib().mp_halo_plan_destroy(h)
     finally:
         lib().mp_graph_destroy(g)
-    return HostGraph(R=R, **arr, **harr)
+    return HostGraph(R=R, **arr, **harr, graph_checksum=gcs.value, plan_checksum=pcs.value,
+                     plan_graph_checksum=pgcs.value)
 
 
 def check_host_graph(hg):
@@ -152,7 +160,10 @@ class DeviceGraph:
         d.rowptr, d.recv, d.col = self.rowptr.data_ptr(), self.recv.data_ptr(), self.col.data_ptr()
         d.rev, d.edge_mult = self.rev.data_ptr(), self.edge_mult.data_ptr()
         d.group_ptr, d.member = self.group_ptr.data_ptr(), self.member.data_ptr()
-        d.seal = lib().mp_dev_graph_seal(C.byref(d))
+        d.graph_checksum, d.plan_checksum = hg.graph_checksum, hg.plan_checksum
+        d.plan_graph_checksum = hg.plan_graph_checksum
+        # reads the arrays back and checks them against the host checksums
+        call("mp_dev_graph_seal", C.byref(d), 1)
         self.desc = d
 
     @property

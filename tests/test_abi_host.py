@@ -36,7 +36,7 @@ def test_exports_every_declared_symbol(L):
     for name in declared:
         assert hasattr(lib, name), name
     assert set(declared) == set(L.EXPORTED)
-    assert lib.mp_abi_version() == 1
+    assert lib.mp_abi_version() == L.ABI_VERSION == 2
 
 
 def test_hex_links_counts():
@@ -246,12 +246,124 @@ def test_graph_partition_rejects_bad_input(L):
 
 
 def _fake_desc(L, n_rows=10, n_edges=20):
+    from paper_2410_01657_amd._lib import call
     d = L.MpDevGraph()
     d.n_rows, d.n_edges, d.n_groups, d.n_members = n_rows, n_edges, 0, 0
-    for f in ("rowptr", "recv", "col", "rev", "edge_mult"):
+    for f in ("rowptr", "recv", "col", "rev", "edge_mult", "group_ptr"):
         setattr(d, f, 4096)  # never dereferenced: validation fails first
-    d.seal = L.lib().mp_dev_graph_seal(C.byref(d))
+    call("mp_dev_graph_seal", C.byref(d), 0)  # checksums taken on trust (0 = 0), no device read
     return d
+
+
+def _desc_from(L, hg, plan=None):
+    """A descriptor holding hg's sizes and checksums, paired with the halo
+    plan of `plan` (another HostGraph; default hg's own), on fake pointers."""
+    plan = plan or hg
+    d = L.MpDevGraph()
+    d.n_rows, d.n_edges = hg.n_rows, hg.n_edges
+    d.n_groups, d.n_members = plan.n_groups, int(plan.member.shape[0])
+    for f in ("rowptr", "recv", "col", "rev", "edge_mult", "group_ptr", "member"):
+        setattr(d, f, 4096)
+    d.graph_checksum = hg.graph_checksum
+    d.plan_checksum, d.plan_graph_checksum = plan.plan_checksum, plan.plan_graph_checksum
+    return d
+
+
+def test_graph_and_plan_checksums_catch_a_plan_from_another_graph(L):
+    """Sec. II-A / Eq. 4c-d: a halo plan is only meaningful beside the graph
+    whose rows it names.  The ascending-id and the locality-ordered graph of
+    one mesh have identical sizes; pairing one's CSR with the other's plan
+    is refused (MP_EPLAN) by the seal and by every entry point, before any
+    device access."""
+    from paper_2410_01657_amd import build_graph
+    from paper_2410_01657_amd._lib import MPError, call
+    from paper_2410_01657_amd.ops import layer_cfg
+    m = box_mesh((4, 4, 4), 3)
+    part = block_partition((4, 4, 4), (2, 2, 2))
+    g_id = build_graph(m.elem_gid, m.P, part, 8, order="gid")
+    g_rcm = build_graph(m.elem_gid, m.P, part, 8, order="locality")
+    assert (g_id.n_rows, g_id.n_edges, g_id.n_groups) == (g_rcm.n_rows, g_rcm.n_edges, g_rcm.n_groups)
+    assert g_id.graph_checksum != g_rcm.graph_checksum
+    assert g_id.plan_checksum != g_rcm.plan_checksum
+    for g in (g_id, g_rcm):
+        assert g.plan_graph_checksum == g.graph_checksum
+    # the checksum is a function of the content: rebuilding gives the same value
+    assert build_graph(m.elem_gid, m.P, part, 8, order="gid").graph_checksum == g_id.graph_checksum
+    # another partition of the same mesh
+    g_r1 = build_graph(m.elem_gid, m.P, np.zeros(64, np.int32), 1, order="gid")
+    assert g_r1.graph_checksum not in (g_id.graph_checksum, g_rcm.graph_checksum)
+    # matched pairs seal; crossed pairs do not
+    for g in (g_id, g_rcm):
+        call("mp_dev_graph_seal", C.byref(_desc_from(L, g)), 0)
+    for g, p in ((g_rcm, g_id), (g_id, g_rcm)):
+        d = _desc_from(L, g, p)
+        with pytest.raises(MPError) as e:
+            call("mp_dev_graph_seal", C.byref(d), 0)
+        assert e.value.code == L.MP_EPLAN
+        assert d.seal == 0
+    # a sealed descriptor whose plan is swapped afterwards is refused by the entry points
+    d = _desc_from(L, g_rcm)
+    call("mp_dev_graph_seal", C.byref(d), 0)
+    cfg = layer_cfg(32)
+    nb = C.c_size_t()
+    call("mp_layer_workspace_size", C.byref(cfg), C.byref(d), 1, C.byref(nb))
+    d.plan_checksum, d.plan_graph_checksum = g_id.plan_checksum, g_id.plan_graph_checksum
+    with pytest.raises(MPError) as e:
+        call("mp_layer_workspace_size", C.byref(cfg), C.byref(d), 1, C.byref(nb))
+    assert e.value.code == L.MP_EPLAN
+    d.seal = 0  # an unsealed descriptor
+    d.plan_checksum, d.plan_graph_checksum = g_rcm.plan_checksum, g_rcm.plan_graph_checksum
+    with pytest.raises(MPError) as e:
+        call("mp_layer_workspace_size", C.byref(cfg), C.byref(d), 1, C.byref(nb))
+    assert e.value.code == L.MP_EPLAN
+
+
+_ALLOC_CHILD = r"""
+import ctypes as C, resource, sys
+import numpy as np
+sys.path.insert(0, sys.argv[1])
+from mpinputs import box_mesh, slab_partition
+from paper_2410_01657_amd._lib import lib
+from paper_2410_01657_amd.graph import hex_links
+m = box_mesh((12, 12, 12), 5)
+part = slab_partition((12, 12, 12), 4)
+eg = np.ascontiguousarray(m.elem_gid, np.int64)
+links = hex_links(5)
+L = lib()
+def vm():
+    for line in open("/proc/self/status"):
+        if line.startswith("VmSize:"):
+            return int(line.split()[1]) * 1024
+extra = int(sys.argv[2]) << 20
+resource.setrlimit(resource.RLIMIT_AS, (vm() + extra, resource.RLIM_INFINITY))
+g = C.c_void_p()
+rc = L.graph_partition(eg.shape[0], eg.shape[1], eg.ctypes.data_as(C.c_void_p), links.shape[0],
+                       links.ctypes.data_as(C.c_void_p), part.ctypes.data_as(C.c_void_p), 4, C.byref(g))
+if rc == 0:
+    rc = L.graph_order_rows(g)
+print("rc", rc, flush=True)
+"""
+
+
+def test_graph_builder_reports_exhausted_memory_instead_of_aborting(tmp_path):
+    """The graph builder runs its per-sub-graph work on threads; a failed
+    allocation inside one must come back as MP_ENOMEM, not terminate the
+    process.  The address space is capped at a range of levels so the
+    failure lands in different places (before, inside and after the
+    threaded parts)."""
+    import subprocess
+    import sys
+    script = tmp_path / "child.py"
+    script.write_text(_ALLOC_CHILD)
+    codes = set()
+    for extra_mib in (8, 24, 48, 96, 160, 256, 4096):
+        p = subprocess.run([sys.executable, str(script), ROOT, str(extra_mib)], capture_output=True, text=True,
+                           timeout=300)
+        assert p.returncode == 0, (extra_mib, p.returncode, p.stderr[-2000:])
+        rc = int(p.stdout.split()[-1])
+        assert rc in (0, 3), (extra_mib, rc)
+        codes.add(rc)
+    assert codes == {0, 3}
 
 
 def test_device_entry_points_validate_before_launch(L):
