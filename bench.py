@@ -1,26 +1,30 @@
 """Benchmark: consistent message-passing fwd+bwd edges/s on one MI355X.
 
-Default workload (C1 mesh): 16^3 spectral elements of order 5 (81^3 =
-531,441 GLL nodes, 3,149,280 directed edges), split into 16 z-slab
-sub-graphs with halos (629,856 rows, 3,538,080 sub-graph edges), an
-encode-process-decode model with 4 consistent NMP layers, hidden width 64,
-LayerNorm, and the consistent MSE (Eq. 6) against the field shifted by one
-node.  Seeded synthetic Taylor-Green-like input, Xavier-uniform weights.
-`--workload C3` (24^3 elements, H=128, one graph), `--workload C4`
-(32^3 elements of order 7, 64 uneven sub-graphs) and `--workload T2R8`
-(the periodic 16 x 16 x 128-element p=5 box in the 8 slabs of Table II's
-R=8 row, 518,400 rows each) measure the other fwd+bwd workloads the same
-way.  `--model table1-small|table1-large` runs a workload with one of the
-paper's own models (Table I: extra hidden layers in every MLP) on the FP32
-deep-MLP kernels instead.
+Default workload (C4): 32^3 spectral elements of order 7 (225^3 =
+11,390,625 GLL nodes, 68,040,000 directed edges), split into 64 uneven
+sub-graphs by a seeded recursive coordinate bisection (1x-3x element
+counts), each with its halo rows (11,852,352 rows, 69,866,496 sub-graph
+edges in one set of buffers, one launch per kernel for all sub-graphs);
+an encode-process-decode model with 4 consistent NMP layers, hidden width
+64, LayerNorm, and the consistent MSE (Eq. 6) against the field shifted by
+one node.  Seeded synthetic Taylor-Green-like input, Xavier-uniform
+weights.  `--workload C1` (16^3 elements P=5, 16 z-slabs), `C3` (24^3
+elements, H=128, one graph) and `T2R8` (the periodic 16 x 16 x 128-element
+p=5 box in the 8 slabs of Table II's R=8 row) measure the other fwd+bwd
+workloads the same way.  `--model table1-small|table1-large` runs a
+workload with one of the paper's own models (Table I: extra hidden layers
+in every MLP) on the FP32 deep-MLP kernels instead.
 
 One step = the whole model forward, loss and backward (every layer's edge
 update, aggregation, halo sum, node update and their adjoints, plus the
 encoders, decoder and loss).  value = global directed edges x layers / step
 time, for the BF16-GEMM path; the FP32 path is measured beside it.  The
-edge-kernel schedule is autotuned first (outside the timed region).
+message-passing layers alone (forward and adjoint of the 4 layers, no
+encoders, decoder or loss) are timed in a separate loop and reported as
+`mp_layers`.  The edge-kernel schedule is autotuned first, and per-kernel
+times come from a separate profiled pass; neither is inside a timed region.
 
-    python bench.py [--gpus 1] [--steps 10] [--warmup 3] [--workload C1]
+    python bench.py [--gpus 1] [--steps 10] [--warmup 3] [--workload C4]
 
 Prints one JSON line.
 """
@@ -73,13 +77,15 @@ def _parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--workload", default="C1", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="C4", choices=sorted(WORKLOADS))
     ap.add_argument("--model", default="workload", choices=["workload"] + sorted(TABLE1),
                     help="the workload's own model, or one of the paper's Table I models")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 comparison path")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-autotune", action="store_true", help="use the library's default schedule")
     ap.add_argument("--sample-nodes", type=int, default=24, help="nodes for the error vs FP64")
+    ap.add_argument("--profile-steps", type=int, default=2,
+                    help="steps of the separate pass that records per-kernel times")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (reference for HBM byte counters)")
     return ap.parse_args()
@@ -119,11 +125,12 @@ def copy_calibration():
     print(json.dumps({"copy_bytes": n * 4}), flush=True)
 
 
-# Measured HBM traffic of the dominant kernel: a summary of two rocprofv3
+# Measured HBM traffic of the dominant kernel: summaries of two rocprofv3
 # --pmc runs (FETCH_SIZE, WRITE_SIZE), scaled by the same counters on a plain
-# copy of known size.  It holds the SHA-256 of the kernel's source files and
-# is used only while they are unchanged (else traffic is null).
-TRAFFIC_PROFILE = "profiles/c1_r16_bf16_hbm_traffic.md"
+# copy of known size, in profiles/*_hbm_traffic.md.  Each record holds the
+# SHA-256 of the kernel's source files and is used only while they are
+# unchanged (else traffic is null).
+TRAFFIC_GLOB = "profiles/*_hbm_traffic.md"
 KERNEL_SOURCES = {"edge_bwd": ("mp_bwd.hip", "mp_device.hpp", "mp_kernels.hpp"),
                   "edge_fwd": ("mp_fwd.hip", "mp_device.hpp", "mp_kernels.hpp")}
 
@@ -139,21 +146,24 @@ def sources_sha256(kernel):
     return h.hexdigest()
 
 
-def recorded_traffic(kernel, workload):
+def recorded_traffic(kernel, workload, gemm="bf16"):
     """HBM bytes per launch (read + write) of `kernel` from the traffic
-    summary, or None when absent, for another workload, or stale."""
+    summaries, or None when absent, for another workload or path, or stale."""
+    import glob
     import os
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), TRAFFIC_PROFILE)
-    if kernel not in KERNEL_SOURCES or not os.path.exists(path):
+    if kernel not in KERNEL_SOURCES:
         return None
+    root = os.path.dirname(os.path.abspath(__file__))
     rec = {}
-    with open(path) as f:
-        for line in f:
-            if line.startswith("traffic:"):
-                kv = dict(t.split("=", 1) for t in line.split()[1:])
-                if kv.get("kernel") == kernel:
-                    rec = kv
-    if not rec or rec.get("workload") != workload or rec.get("sources_sha256") != sources_sha256(kernel):
+    for path in sorted(glob.glob(os.path.join(root, TRAFFIC_GLOB))):
+        with open(path) as f:
+            for line in f:
+                if line.startswith("traffic:"):
+                    kv = dict(t.split("=", 1) for t in line.split()[1:])
+                    if (kv.get("kernel") == kernel and kv.get("workload") == workload
+                            and kv.get("gemm", "bf16") == gemm):
+                        rec = kv
+    if not rec or rec.get("sources_sha256") != sources_sha256(kernel):
         return None
     return float(rec["read_bytes"]) + float(rec["write_bytes"])
 
@@ -164,8 +174,16 @@ KERNELS = ("pack", "tiles", "proj", "edge_fwd", "halo", "halo_adj", "node_fwd", 
            "deep_node_dw", "deep_mlp_fwd", "deep_mlp_bwd", "deep_mlp_dw")
 
 
-def run_path(gemm, spec, params, prob, steps, warmup, schedule):
-    """Time `steps` full fwd+bwd steps; returns timing, per-kernel stats, outputs."""
+def _events():
+    import torch
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def run_path(gemm, spec, params, prob, steps, warmup, schedule, profile_steps):
+    """Time `steps` full fwd+bwd steps (no per-launch instrumentation), then
+    the message-passing layers alone, then record per-kernel times in a
+    separate pass.  Returns a dict with the timings, per-kernel stats, the
+    outputs, the loss and the parameter gradients of the last step."""
     import ctypes as C
 
     import torch
@@ -186,26 +204,68 @@ def run_path(gemm, spec, params, prob, steps, warmup, schedule):
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    call("mp_profile_enable", 1)
     stream = torch.cuda.current_stream()
-    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0, t1 = _events()
     t0.record(stream)
     for _ in range(steps):
         Y, loss = step()
     t1.record(stream)
     torch.cuda.synchronize()
     ms = t0.elapsed_time(t1) / steps
+    out = {"ms": ms, "Y": Y.detach(), "loss": float(loss.detach().cpu()),
+           "grads": {k: t.grad.detach().clone() for k, t in model.params.items() if t.grad is not None}}
+    del Y, loss
+    out["mp_ms"] = _time_layers_only(model, prob, steps, max(1, warmup // 2))
+    # per-kernel times: HIP events around every launch, in a pass of its own
+    call("mp_profile_enable", 1)
+    for _ in range(profile_steps):
+        step()
+    torch.cuda.synchronize()
     kernels = {}
     for name in KERNELS:
         tot, n = C.c_double(), C.c_int64()
         call("mp_profile_read", name.encode(), C.byref(tot), C.byref(n))
         if n.value:
-            kernels[name] = {"ms_total": tot.value / steps, "launches_per_step": n.value / steps,
+            kernels[name] = {"ms_total": tot.value / profile_steps, "launches_per_step": n.value / profile_steps,
                              "ms_avg": tot.value / n.value}
     call("mp_profile_enable", 0)
-    out = Y.detach(), float(loss.detach().cpu())
+    out["kernels"] = kernels
+    for t in model.params.values():
+        t.grad = None
     del model
-    return (ms, kernels) + out
+    return out
+
+
+def _time_layers_only(model, prob, steps, warmup):
+    """Forward and adjoint of the message-passing layers alone (Eq. 4a-e and
+    their adjoint, parameter gradients included), on the encoders' outputs
+    with a fixed upstream gradient: the same entry points and launch
+    configuration as the model step, none of its encoders, decoder or loss."""
+    import torch
+
+    with torch.no_grad():
+        x0, e0 = model.encode(prob.X, prob.E0)
+    g_top = torch.full_like(x0, 1.0 / x0.numel())
+
+    def layers():
+        for t in model.params.values():
+            t.grad = None
+        x, _ = model.process(prob.dg, x0, e0)
+        torch.autograd.backward([x], [g_top])
+
+    for _ in range(warmup):
+        layers()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    t0, t1 = _events()
+    t0.record(stream)
+    for _ in range(steps):
+        layers()
+    t1.record(stream)
+    torch.cuda.synchronize()
+    del x0, e0, g_top
+    torch.cuda.empty_cache()
+    return t0.elapsed_time(t1) / steps
 
 
 def cpu_baseline(cfg, spec, inp, n_layers, sample_gids, outs, min_seconds=10.0):
@@ -275,7 +335,7 @@ def main():
     from paper_2410_01657_amd.autotune import tuned_schedule
     from paper_2410_01657_amd.model import Problem
     from paper_2410_01657_amd.roofline import (PEAK, PEAK_HBM, PEAK_VALU, bound_of, deep_kernels,
-                                               layer_kernels)
+                                               layer_kernels, layer_roof_seconds)
 
     wl = dict(WORKLOADS[a.workload])
     cfg = CONFIGS[a.workload]
@@ -300,16 +360,18 @@ def main():
 
     copy_gbps = copy_bandwidth()
     paths = ["f32"] if deep else ["bf16"] + ([] if a.no_fp32 else ["f32"])
-    res, outs, scheds = {}, {}, {}
+    res, outs, scheds, grads = {}, {}, {}, {}
     for gemm in paths:
         sched = None if (a.no_autotune or deep) else tuned_schedule(prob.dg, spec.H, spec.layernorm, gemm)
         scheds[gemm] = sched
         _progress(f"{gemm}: schedule {sched}")
-        ms, kern, Y, loss = run_path(gemm, spec, inp.params, prob, a.steps, a.warmup, sched)
-        _progress(f"{gemm}: {ms:.3f} ms/step")
-        res[gemm] = {"ms": ms, "kernels": kern, "loss": loss}
-        outs[gemm] = Y.cpu().numpy()[sample_rows].astype(np.float64)
-        del Y
+        r = run_path(gemm, spec, inp.params, prob, a.steps, a.warmup, sched, a.profile_steps)
+        _progress(f"{gemm}: {r['ms']:.3f} ms/step, message-passing layers alone {r['mp_ms']:.3f} ms")
+        outs[gemm] = r.pop("Y").cpu().numpy()[sample_rows].astype(np.float64)
+        grads[gemm] = {k: v.cpu().numpy().astype(np.float64) for k, v in r.pop("grads").items()}
+        if not np.all(np.isfinite(outs[gemm])) or not np.isfinite(r["loss"]):
+            raise RuntimeError(f"{gemm} path produced a non-finite output or loss")
+        res[gemm] = r
         torch.cuda.empty_cache()
 
     main_gemm = paths[0]
@@ -334,17 +396,27 @@ def main():
             r = {"bound": "mfma", "achieved": w.flops / avg_s / 1e12, "peak": PEAK[gemm] / 1e12,
                  "unit": "TFLOP/s"}
         r["frac"] = r["achieved"] / r["peak"]
-        return dom, w, r
+        r.update({"kernel": dom, "ms_avg": kern[dom]["ms_avg"], "algorithmic_GB": w.bytes / 1e9,
+                  "algorithmic_GFLOP": w.flops / 1e9})
+        return r
+
+    def mp_layers(gemm):
+        """The message-passing layers alone: edges/s and the fraction of
+        their roofline time (every layer kernel at the higher of its HBM and
+        matrix floors, published peaks; and against the measured copy rate)."""
+        ms = res[gemm]["mp_ms"]
+        out = {"value": E_global * spec.n_layers / (ms * 1e-3), "ms": ms}
+        if not deep:
+            t_roof = layer_roof_seconds(N, E, G, M, spec.H, gemm, spec.n_layers)
+            t_copy = layer_roof_seconds(N, E, G, M, spec.H, gemm, spec.n_layers, hbm=copy_gbps * 1e9)
+            out.update({"roof_ms": t_roof * 1e3, "frac_of_roof": t_roof * 1e3 / ms,
+                        "roof_ms_at_copy_rate": t_copy * 1e3, "frac_of_roof_at_copy_rate": t_copy * 1e3 / ms})
+        return out
 
     # dominant kernel of the main path and its roofline
-    dom, w, roof = dominant_roofline(main_gemm)
-    kern = main_path["kernels"]
-    tr = recorded_traffic(dom, a.workload)
+    roof = dominant_roofline(main_gemm)
+    tr = recorded_traffic(roof["kernel"], a.workload, main_gemm)
     roof["traffic"] = tr / 1e9 if tr is not None else None  # GB per launch, measured
-    roof["kernel"] = dom
-    roof["ms_avg"] = kern[dom]["ms_avg"]
-    roof["algorithmic_GB"] = w.bytes / 1e9
-    roof["algorithmic_GFLOP"] = w.flops / 1e9
     roof["traffic_unit"] = "GB per launch (HBM read + write)"
     # context: the same kernel against the bandwidth a plain 2 GiB copy reaches
     if roof["bound"] == "hbm":
@@ -368,13 +440,22 @@ def main():
                    "halo_groups": G, "halo_members": M, "global_edges": E_global, "layers": spec.n_layers,
                    "H": spec.H, "schedule": scheds},
         "roofline": roof,
+        "mp_layers": mp_layers(main_gemm),
     }
     if "f32" in res and main_gemm != "f32":
-        dom32, w32, roof32 = dominant_roofline("f32")
-        roof32.update({"kernel": dom32, "ms_avg": res["f32"]["kernels"][dom32]["ms_avg"]})
         line["fp32"] = {"value": E_global * spec.n_layers / (res["f32"]["ms"] * 1e-3),
-                        "ms_per_step": res["f32"]["ms"], "roofline": roof32}
+                        "ms_per_step": res["f32"]["ms"], "roofline": dominant_roofline("f32"),
+                        "mp_layers": mp_layers("f32")}
         line["bf16_over_fp32"] = res["f32"]["ms"] / main_path["ms"]
+        line["bf16_over_fp32_mp_layers"] = res["f32"]["mp_ms"] / main_path["mp_ms"]
+        # BF16 parameter gradients against the FP32 path's (which match the
+        # FP64 oracle to ~1e-5 in the parity tests): max |d| / max |g_fp32|
+        # per parameter tensor, the worst tensor reported
+        dev = {k: float(np.abs(grads["bf16"][k] - v).max() / max(np.abs(v).max(), 1e-30))
+               for k, v in grads["f32"].items()}
+        worst = max(dev, key=dev.get)
+        line["bf16_grad_rel_dev_vs_fp32"] = {"max": dev[worst], "tensor": worst,
+                                             "median": float(np.median(list(dev.values())))}
     line["kernels"] = {g: {k: round(v["ms_total"], 4) for k, v in res[g]["kernels"].items()} for g in res}
     if not a.no_cpu_baseline:
         _progress("timing the FP64 oracle on a bounded sample")

@@ -21,6 +21,12 @@ EDGE_GRIDS = (512, 1024, 2048)
 EDGE_BWD_GRIDS = (256, 512, 1024)
 
 
+def candidates():
+    """Every schedule the tuner can return, as mp_layer_cfg field values."""
+    return [{"tile_edges": te, "edge_grid": eg, "edge_bwd_grid": bg}
+            for te in TILE_EDGES for eg in EDGE_GRIDS for bg in EDGE_BWD_GRIDS]
+
+
 def _cache_path():
     return os.environ.get("MPLAYER_TUNE_CACHE",
                           os.path.join(os.path.expanduser("~"), ".cache", "mplayer", "tune.json"))

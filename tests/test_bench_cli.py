@@ -39,3 +39,28 @@ def test_recorded_traffic_requires_matching_sources(tmp_path):
     assert bench.recorded_traffic("gq", "C1") is None
     sha = bench.sources_sha256("edge_bwd")
     assert len(sha) == 64 and sha == bench.sources_sha256("edge_bwd")
+
+
+def test_split_adjoints_are_counted_where_their_products_run():
+    """At H > 64 the edge and node adjoints run in two passes: the products
+    are charged to the pass that executes them, and the total over the
+    passes equals the fused form's count (6 H x H products per edge, 9 per
+    node-update row; the sender-side pass 4 per row)."""
+    sys.path.insert(0, ROOT)
+    from paper_2410_01657_amd.roofline import layer_kernels, layer_roof_seconds
+    N, E, G, M = 1771561, 10541520, 0, 0
+    for gemm in ("bf16", "f32"):
+        w64 = layer_kernels(N, E, G, M, 64, gemm, 4)
+        assert "edge_dw" not in w64 and "node_dw" not in w64 and "gq_dw" not in w64
+        H = 128
+        w = layer_kernels(N, E, G, M, H, gemm, 4)
+        assert w["edge_bwd"].flops == E * 8 * H * H
+        assert w["edge_dw"].flops == E * 4 * H * H
+        assert w["edge_bwd"].flops + w["edge_dw"].flops == E * 12 * H * H
+        assert w["node_bwd"].flops + w["node_dw"].flops == N * 18 * H * H
+        gq = w["gq"].flops + w.get("gq_dw", w["gq"].__class__(0, 0)).flops
+        assert gq == N * 8 * H * H
+        assert ("gq_dw" in w) == (gemm == "f32")
+    # the layer roofline is the sum over kernels of the higher floor, per layer
+    t = layer_roof_seconds(N, E, G, M, 128, "f32", 4)
+    assert 0.09 < t < 0.11  # C3, FP32: about 25 ms of matrix time per layer
