@@ -236,11 +236,38 @@ int mp_layer_workspace_size(const mp_layer_cfg* cfg, const mp_dev_graph* g,
  * backward); it may be NULL.  pq_out[2][N][H], if not NULL, receives the
  * node projections of the first edge-MLP Linear (Eq. 4a split over its
  * input): P = W1a x_in + b1, then Q = W1b x_in; handing them to the
- * backward saves recomputing them.  Outputs must not alias inputs. */
+ * backward saves recomputing them.  Outputs must not alias inputs.
+ * ws_bytes must be at least mp_layer_workspace_size(cfg, g, 0); when both
+ * a_star_out and pq_out are given, only a prefix of that layout is used
+ * (the packed weights and the edge tile bounds), and a workspace of that
+ * prefix's size is accepted. */
 int mp_layer_forward(const mp_layer_cfg* cfg, const mp_layer_params* p,
                      const mp_dev_graph* g, const float* x_in, const float* e_in,
                      float* x_out, float* e_out, float* a_star_out, float* pq_out,
                      void* ws, size_t ws_bytes, mp_stream_t stream);
+
+/* The same forward for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, hosts that forbid it): no
+ * workspace argument, and no device or host allocation in the call.  Its
+ * scratch (the packed weights and the edge tile bounds) is a module array
+ * of mp_layer_forward_noalloc_max_scratch() bytes (32 MiB) that every GPU
+ * the library runs on holds until the process ends; its device address is
+ * looked up once per device on the first call there.  a_star_out and
+ * pq_out are required (so no node-sized scratch is needed); all other
+ * arguments and the results are those of mp_layer_forward, bit for bit.
+ * Errors: as mp_layer_forward, plus MP_EINVAL when a_star_out or pq_out is
+ * NULL, when the scratch needed (weights plus 8 bytes per edge tile)
+ * exceeds the maximum, or when the stream belongs to another device than
+ * the current one; MP_EHIP if the scratch address cannot be obtained.
+ * Every call on one GPU shares that GPU's scratch: calls that overlap on
+ * one GPU (two streams, two threads) race.  Nothing in the scratch needs
+ * to start at zero (each call writes what it reads).  Launches of this
+ * entry point are not recorded by mp_profile_enable. */
+int mp_layer_forward_noalloc(const mp_layer_cfg* cfg, const mp_layer_params* p,
+                             const mp_dev_graph* g, const float* x_in, const float* e_in,
+                             float* x_out, float* e_out, float* a_star_out, float* pq_out,
+                             mp_stream_t stream);
+size_t mp_layer_forward_noalloc_max_scratch(void);
 
 /* Backward (adjoint of the forward, Eq. 3): given the forward inputs, the
  * saved a*, and the gradients of the loss with respect to x_out and e_out,

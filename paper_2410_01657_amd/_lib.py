@@ -90,6 +90,9 @@ _SIGS = {
     "mp_layer_workspace_size": (c_i32, [P(MpLayerCfg), P(MpDevGraph), c_i32, P(C.c_size_t)]),
     "mp_layer_forward": (c_i32, [P(MpLayerCfg), P(MpLayerParams), P(MpDevGraph), vp, vp, vp, vp, vp,
                                  vp, vp, C.c_size_t, vp]),
+    "mp_layer_forward_noalloc": (c_i32, [P(MpLayerCfg), P(MpLayerParams), P(MpDevGraph), vp, vp, vp, vp, vp,
+                                         vp, vp]),
+    "mp_layer_forward_noalloc_max_scratch": (C.c_size_t, []),
     "mp_layer_backward": (c_i32, [P(MpLayerCfg), P(MpLayerParams), P(MpDevGraph), vp, vp, vp, vp, vp, vp,
                                   vp, vp, P(MpLayerGrads), vp, C.c_size_t, vp]),
     "mp_mlp_workspace_size": (c_i32, [P(MpMlpCfg), c_i64, c_i32, P(C.c_size_t)]),

@@ -303,7 +303,12 @@ hipEvent_t prof_event() {
   return e;
 }
 
+// Set while an entry point that must not create anything runs (the
+// allocation-free forward): its launches are not bracketed by events.
+thread_local bool t_no_prof = false;
+
 long prof_begin(const char* name, hipStream_t s) {
+  if (t_no_prof) return -1;
   std::lock_guard<std::mutex> lk(g_prof_mu);
   if (!g_prof_on) return -1;
   ProfRec r{name, prof_event(), prof_event()};
@@ -365,20 +370,36 @@ extern "C" int mp_layer_workspace_size(const mp_layer_cfg* cfg, const mp_dev_gra
   return MP_OK;
 }
 
-extern "C" int mp_layer_forward(const mp_layer_cfg* cfg, const mp_layer_params* p, const mp_dev_graph* g,
-                                const float* x_in, const float* e_in, float* x_out, float* e_out, float* a_star_out,
-                                float* pq_out, void* ws, size_t ws_bytes, mp_stream_t stream) {
+namespace {
+
+// Validation of the forward's arguments (everything but the workspace).
+int check_layer_forward(const mp_layer_cfg* cfg, const mp_layer_params* p, const mp_dev_graph* g,
+                        const float* x_in, const float* e_in, const float* x_out, const float* e_out,
+                        const float* a_star_out, const float* pq_out) {
   int rc;
   if ((rc = check_cfg(cfg)) || (rc = check_graph(g, false)) || (rc = check_layer_params(cfg, p))) return rc;
-  if (!x_in || !e_in || !x_out || !e_out || !ws) return mp_fail(MP_EINVAL, "mp_layer_forward: NULL buffer");
-  if (!aligned16(x_in) || !aligned16(e_in) || !aligned16(x_out) || !aligned16(e_out) || !aligned16(ws) ||
+  if (!x_in || !e_in || !x_out || !e_out) return mp_fail(MP_EINVAL, "mp_layer_forward: NULL buffer");
+  if (!aligned16(x_in) || !aligned16(e_in) || !aligned16(x_out) || !aligned16(e_out) ||
       (a_star_out && !aligned16(a_star_out)) || (pq_out && !aligned16(pq_out)))
     return mp_fail(MP_EINVAL, "mp_layer_forward: buffers must be 16-byte aligned");
   if (x_out == x_in || e_out == e_in || (const float*)e_out == x_in || (const float*)x_out == e_in ||
       (pq_out && ((const float*)pq_out == x_in || (const float*)pq_out == e_in)))
     return mp_fail(MP_EINVAL, "mp_layer_forward: outputs must not alias inputs");
-  const LayerWs W(cfg, g, false);
-  if (ws_bytes < W.total) return mp_fail(MP_ENOMEM, "mp_layer_forward: workspace %zu < %zu bytes", ws_bytes, W.total);
+  return MP_OK;
+}
+
+// Bytes of the forward workspace actually used: the whole layout, or only
+// its prefix (packed weights and tile bounds) when the caller supplies the
+// node projections and the aggregate.
+size_t layer_forward_ws_need(const LayerWs& W, const float* a_star_out, const float* pq_out) {
+  return (a_star_out && pq_out) ? W.P : W.total;
+}
+
+// The forward's launch sequence (arguments validated, workspace checked).
+int layer_forward_launch(const mp_layer_cfg* cfg, const mp_layer_params* p, const mp_dev_graph* g,
+                         const float* x_in, const float* e_in, float* x_out, float* e_out, float* a_star_out,
+                         float* pq_out, void* ws, const LayerWs& W, mp_stream_t stream) {
+  int rc;
   const int H = cfg->H;
   const bool bf = cfg->gemm_dtype == MP_BF16;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -420,6 +441,88 @@ extern "C" int mp_layer_forward(const mp_layer_cfg* cfg, const mp_layer_params* 
   m.frag1 = ws_at(ws, W.fr.node + W.fr.f2);
   m.out = x_out;
   return run("node_fwd", s, [&] { return launch_mlp_fwd(m, W.gn, s); });
+}
+
+}  // namespace
+
+extern "C" int mp_layer_forward(const mp_layer_cfg* cfg, const mp_layer_params* p, const mp_dev_graph* g,
+                                const float* x_in, const float* e_in, float* x_out, float* e_out, float* a_star_out,
+                                float* pq_out, void* ws, size_t ws_bytes, mp_stream_t stream) {
+  int rc;
+  if ((rc = check_layer_forward(cfg, p, g, x_in, e_in, x_out, e_out, a_star_out, pq_out))) return rc;
+  if (!ws) return mp_fail(MP_EINVAL, "mp_layer_forward: NULL workspace");
+  if (!aligned16(ws)) return mp_fail(MP_EINVAL, "mp_layer_forward: workspace must be 16-byte aligned");
+  const LayerWs W(cfg, g, false);
+  const size_t need = layer_forward_ws_need(W, a_star_out, pq_out);
+  if (ws_bytes < need) return mp_fail(MP_ENOMEM, "mp_layer_forward: workspace %zu < %zu bytes", ws_bytes, need);
+  return layer_forward_launch(cfg, p, g, x_in, e_in, x_out, e_out, a_star_out, pq_out, ws, W, stream);
+}
+
+// ----------------------------------------- allocation-free layer forward
+// Scratch of mp_layer_forward_noalloc: the packed weights and the edge
+// tile bounds, in a module array that every GPU the library runs on holds
+// until the process ends.  Host code never passes the array's name to a
+// kernel (on the host it is only a stand-in); it uses the device address
+// hipGetSymbolAddress returns, looked up once per device.
+constexpr size_t kNoallocScratchBytes = size_t(32) << 20;
+__device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int noalloc_scratch(hipStream_t s, void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return mp_fail(MP_EHIP, "mp_layer_forward_noalloc: hipGetDevice: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return mp_fail(MP_EINVAL, "mp_layer_forward_noalloc: device %d out of range", dev);
+  if (s) {
+    hipDevice_t sd = -1;
+    e = hipStreamGetDevice(s, &sd);
+    if (e != hipSuccess)
+      return mp_fail(MP_EHIP, "mp_layer_forward_noalloc: hipStreamGetDevice: %s", hipGetErrorString(e));
+    if (sd != dev)
+      return mp_fail(MP_EINVAL, "mp_layer_forward_noalloc: the stream belongs to device %d, the current device is %d",
+                     (int)sd, dev);
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return mp_fail(MP_EHIP, "mp_layer_forward_noalloc: hipGetSymbolAddress: %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return MP_OK;
+}
+
+struct NoProfile {
+  NoProfile() { t_no_prof = true; }
+  ~NoProfile() { t_no_prof = false; }
+};
+}  // namespace
+
+extern "C" size_t mp_layer_forward_noalloc_max_scratch(void) { return kNoallocScratchBytes; }
+
+extern "C" int mp_layer_forward_noalloc(const mp_layer_cfg* cfg, const mp_layer_params* p, const mp_dev_graph* g,
+                                        const float* x_in, const float* e_in, float* x_out, float* e_out,
+                                        float* a_star_out, float* pq_out, mp_stream_t stream) {
+  int rc;
+  if ((rc = check_layer_forward(cfg, p, g, x_in, e_in, x_out, e_out, a_star_out, pq_out))) return rc;
+  if (!a_star_out || !pq_out)
+    return mp_fail(MP_EINVAL, "mp_layer_forward_noalloc: a_star_out and pq_out are required");
+  const LayerWs W(cfg, g, false);
+  const size_t need = layer_forward_ws_need(W, a_star_out, pq_out);
+  if (need > kNoallocScratchBytes)
+    return mp_fail(MP_EINVAL, "mp_layer_forward_noalloc: needs %zu bytes of scratch, the maximum is %zu "
+                   "(fewer edges or larger tiles)", need, kNoallocScratchBytes);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  void* ws = nullptr;
+  if ((rc = noalloc_scratch(s, &ws))) return rc;
+  NoProfile np;
+  return layer_forward_launch(cfg, p, g, x_in, e_in, x_out, e_out, a_star_out, pq_out, ws, W, stream);
 }
 
 extern "C" int mp_layer_backward(const mp_layer_cfg* cfg, const mp_layer_params* p, const mp_dev_graph* g,

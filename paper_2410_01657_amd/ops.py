@@ -84,6 +84,18 @@ def layer_forward(cfg, p, dg, x, e, want_pq=False):
     return (x_out, e_out, a_star, pq) if want_pq else (x_out, e_out, a_star)
 
 
+def layer_forward_noalloc(cfg, p, dg, x, e):
+    """layer_forward through the entry point that allocates nothing (its
+    scratch is a library-held module array); returns (x_out, e_out, a_star,
+    pq).  The outputs here are torch tensors the caller allocates."""
+    _check(x, e)
+    x_out, e_out, a_star = torch.empty_like(x), torch.empty_like(e), torch.empty_like(x)
+    pq = torch.empty((2,) + tuple(x.shape), dtype=x.dtype, device=x.device)
+    call("mp_layer_forward_noalloc", C.byref(cfg), C.byref(_layer_params(p)), C.byref(dg.desc), _p(x), _p(e),
+         _p(x_out), _p(e_out), _p(a_star), _p(pq), _stream())
+    return x_out, e_out, a_star, pq
+
+
 def layer_backward(cfg, p, dg, x, e, a_star, g_x_out, g_e_out, pq=None):
     """Adjoint of layer_forward; pq (from layer_forward(want_pq=True)) skips
     recomputing the node projections."""

@@ -460,3 +460,28 @@ def test_deep_entry_points_validate_before_launch(L):
     # flat parameter sizes follow the torch.nn.Linear layout
     assert deep_theta_size(3, 8, 2, 8, True) == 8 * 3 + 8 + 2 * (64 + 8) + 64 + 8 + 16
     assert deep_theta_size(8, 8, 0, 3, False) == 64 + 8 + 24 + 3
+
+
+def test_noalloc_forward_validates_before_touching_a_gpu(L):
+    """mp_layer_forward_noalloc refuses, before any device call, a missing
+    a_star_out / pq_out and a graph whose tile bounds would exceed its fixed
+    scratch (32 MiB)."""
+    from paper_2410_01657_amd._lib import MPError, call, lib
+    from paper_2410_01657_amd.ops import layer_cfg
+    assert lib().mp_layer_forward_noalloc_max_scratch() == 32 << 20
+    cfg = layer_cfg(64)
+    params = L.MpLayerParams()
+    for f in L.LAYER_FIELDS:
+        setattr(params, f, 4096)
+    d = _fake_desc(L)
+    with pytest.raises(MPError) as e:  # a_star_out and pq_out are required
+        call("mp_layer_forward_noalloc", C.byref(cfg), C.byref(params), C.byref(d), 4096, 8192, 12288, 16384,
+             None, None, None)
+    assert e.value.code == L.MP_EINVAL and "required" in str(e.value)
+    # 2^30 edges in 16-edge tiles: 2^26 tiles of 8 bytes, beyond the scratch
+    big = _fake_desc(L, n_rows=1 << 20, n_edges=1 << 30)
+    cfg.tile_edges = 16
+    with pytest.raises(MPError) as e:
+        call("mp_layer_forward_noalloc", C.byref(cfg), C.byref(params), C.byref(big), 4096, 8192, 12288, 16384,
+             20480, 24576, None)
+    assert e.value.code == L.MP_EINVAL and "maximum" in str(e.value)
