@@ -232,6 +232,8 @@ int mp_layer_workspace_size(const mp_layer_cfg* cfg, const mp_dev_graph* g,
                             int backward, size_t* bytes);
 
 /* Forward.  x_in[N][H], e_in[E][H] -> x_out[N][H], e_out[E][H] (FP32).
+ * e_out may be NULL: the updated edge state is then not written (a model's
+ * last layer, whose e' nothing reads; Eq. 4b still sums it into a).
  * a_star_out[N][H] receives the synchronised aggregate a* (needed by the
  * backward); it may be NULL.  pq_out[2][N][H], if not NULL, receives the
  * node projections of the first edge-MLP Linear (Eq. 4a split over its

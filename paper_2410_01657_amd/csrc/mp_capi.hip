@@ -378,11 +378,11 @@ int check_layer_forward(const mp_layer_cfg* cfg, const mp_layer_params* p, const
                         const float* a_star_out, const float* pq_out) {
   int rc;
   if ((rc = check_cfg(cfg)) || (rc = check_graph(g, false)) || (rc = check_layer_params(cfg, p))) return rc;
-  if (!x_in || !e_in || !x_out || !e_out) return mp_fail(MP_EINVAL, "mp_layer_forward: NULL buffer");
-  if (!aligned16(x_in) || !aligned16(e_in) || !aligned16(x_out) || !aligned16(e_out) ||
+  if (!x_in || !e_in || !x_out) return mp_fail(MP_EINVAL, "mp_layer_forward: NULL buffer");
+  if (!aligned16(x_in) || !aligned16(e_in) || !aligned16(x_out) || (e_out && !aligned16(e_out)) ||
       (a_star_out && !aligned16(a_star_out)) || (pq_out && !aligned16(pq_out)))
     return mp_fail(MP_EINVAL, "mp_layer_forward: buffers must be 16-byte aligned");
-  if (x_out == x_in || e_out == e_in || (const float*)e_out == x_in || (const float*)x_out == e_in ||
+  if (x_out == x_in || (e_out && (e_out == e_in || (const float*)e_out == x_in)) || (const float*)x_out == e_in ||
       (pq_out && ((const float*)pq_out == x_in || (const float*)pq_out == e_in)))
     return mp_fail(MP_EINVAL, "mp_layer_forward: outputs must not alias inputs");
   return MP_OK;

@@ -268,7 +268,7 @@ __global__ __launch_bounds__(256, (H <= 64 ? 4 : 2)) void k_edge_fwd(DevGraph gr
       }
 #pragma unroll
       for (int i = 0; i < NF; ++i) ev[i] += m[i];
-      if (valid) store_row<H>(e_out + k * H, g, ev);
+      if (valid && e_out) store_row<H>(e_out + k * H, g, ev);  // no e' for a last layer
 
       // aggregation: segmented scan of e'/d across the block, plus carry
 #pragma unroll

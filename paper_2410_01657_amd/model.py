@@ -82,7 +82,10 @@ class ConsistentGNN:
         e = self._mlp("eenc", E0, s.edge_in, s.H, s.layernorm)
         return x, e
 
-    def process(self, dg, x, e):
+    def process(self, dg, x, e, want_e=False):
+        """The message-passing layers.  The last layer's edge state is
+        returned only when want_e (nothing in the model reads it, so by
+        default it is not written)."""
         s = self.spec
         if self.deep:
             cfg = deep_layer_cfg(s.H, s.n_hidden, s.layernorm, self.halo, s.ln_eps, s.aggregate)
@@ -98,7 +101,8 @@ class ConsistentGNN:
         for m in range(s.n_layers):
             names = _layer_param_names(m, s.layernorm)
             args = [self.params[names[f]] if f in names else None for f in self.LAYER_ORDER]
-            x, e = MPLayerFn.apply(cfg, dg, x, e, *args)
+            last = m == s.n_layers - 1
+            x, e = MPLayerFn.apply(cfg, dg, want_e or not last, x, e, *args)
         return x, e
 
     def decode(self, x):

@@ -70,11 +70,14 @@ def _layer_params(p):
     return s
 
 
-def layer_forward(cfg, p, dg, x, e, want_pq=False):
+def layer_forward(cfg, p, dg, x, e, want_pq=False, want_e=True):
     """One consistent NMP layer; returns (x_out, e_out, a_star), plus the node
-    projections pq = [P; Q] ([2, N, H], for the backward) when want_pq."""
+    projections pq = [P; Q] ([2, N, H], for the backward) when want_pq.
+    want_e=False: the updated edge state is not written (e_out is None), for
+    a last layer whose e' nothing reads."""
     _check(x, e)
-    x_out, e_out, a_star = torch.empty_like(x), torch.empty_like(e), torch.empty_like(x)
+    x_out, a_star = torch.empty_like(x), torch.empty_like(x)
+    e_out = torch.empty_like(e) if want_e else None
     pq = torch.empty((2,) + tuple(x.shape), dtype=x.dtype, device=x.device) if want_pq else None
     nb = C.c_size_t()
     call("mp_layer_workspace_size", C.byref(cfg), C.byref(dg.desc), 0, C.byref(nb))
@@ -115,12 +118,14 @@ def layer_backward(cfg, p, dg, x, e, a_star, g_x_out, g_e_out, pq=None):
 
 
 class MPLayerFn(torch.autograd.Function):
-    """(x, e, *layer params) -> (x', e') with the library's adjoint as backward."""
+    """(x, e, *layer params) -> (x', e') with the library's adjoint as backward.
+    want_e=False returns e' = None (a last layer: the edge state is not
+    written, and its gradient is zero)."""
 
     @staticmethod
-    def forward(ctx, cfg, dg, x, e, *params):
+    def forward(ctx, cfg, dg, want_e, x, e, *params):
         p = dict(zip(LAYER_FIELDS, params))
-        x_out, e_out, a_star, pq = layer_forward(cfg, p, dg, x, e, want_pq=True)
+        x_out, e_out, a_star, pq = layer_forward(cfg, p, dg, x, e, want_pq=True, want_e=want_e)
         ctx.cfg, ctx.dg = cfg, dg
         # an unused edge-state output (the last layer's) arrives as None in
         # the backward instead of a materialised zero tensor
@@ -136,7 +141,7 @@ class MPLayerFn(torch.autograd.Function):
         g_x_out = g_x_out.contiguous() if g_x_out is not None else torch.zeros_like(x)
         g_e_out = g_e_out.contiguous() if g_e_out is not None else None
         g_x, g_e, grads = layer_backward(ctx.cfg, p, ctx.dg, x, e, a_star, g_x_out, g_e_out, pq)
-        return (None, None, g_x, g_e) + tuple(grads[f] for f in LAYER_FIELDS)
+        return (None, None, None, g_x, g_e) + tuple(grads[f] for f in LAYER_FIELDS)
 
 
 # -------------------------------------------------------------------- MLPs

@@ -248,3 +248,27 @@ def test_layer_backward_with_forward_projections(c0, H, gemm):
     assert torch.equal(g1[0], g2[0]) and torch.equal(g1[1], g2[1])
     for k in names:
         assert torch.equal(g1[2][k], g2[2][k]), k
+
+
+@pytest.mark.parametrize("gemm", ["f32", "bf16"])
+def test_layer_forward_without_edge_output(c0, gemm):
+    """A last layer's e' is read by nothing: with e_out = NULL the kernels
+    skip its store, and x', a* (whose Eq. 4b sum still uses e') are bitwise
+    those of the full forward; the adjoint without g_e' is unchanged."""
+    from paper_2410_01657_amd.ops import layer_backward, layer_cfg, layer_forward
+    inp, gs = c0
+    dg, og, pairs = gs[8]
+    H = 64
+    spec, o, names = layer_params(H, True)
+    rng = np.random.default_rng(9)
+    x, e = _t(rng.standard_normal((dg.n_rows, H))), _t(rng.standard_normal((dg.n_edges, H)))
+    gx = _t(rng.standard_normal((dg.n_rows, H)))
+    cfg = layer_cfg(H, True, gemm=gemm)
+    p = _lib_params(o, names)
+    xo, eo, a, pq = layer_forward(cfg, p, dg, x, e, want_pq=True)
+    xo2, eo2, a2, pq2 = layer_forward(cfg, p, dg, x, e, want_pq=True, want_e=False)
+    assert eo2 is None
+    assert torch.equal(xo, xo2) and torch.equal(a, a2) and torch.equal(pq, pq2)
+    g1 = layer_backward(cfg, p, dg, x, e, a, gx, None, pq)
+    g2 = layer_backward(cfg, p, dg, x, e, a2, gx, None, pq2)
+    assert torch.equal(g1[0], g2[0]) and torch.equal(g1[1], g2[1])
