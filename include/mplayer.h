@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define MP_ABI_VERSION 2
+#define MP_ABI_VERSION 3
 
 enum {
   MP_OK = 0,
@@ -207,6 +207,17 @@ typedef struct {
    * (the equations as written), or MP_AGG_MESSAGE (1) the MLP output alone
    * (a variant; the edge-state update is unchanged). */
   int32_t aggregate;
+  /* More schedule dimensions (0 = library default; the results of every
+   * choice are bitwise reproducible, and equal up to the grouping of the
+   * weight-gradient sums): waves per workgroup of the fused edge adjoint
+   * (4, or 8 for BF16 GEMMs at H <= 64, which stage 16 x waves edges per
+   * weight-gradient round), and the tile order of the edge forward (0: a
+   * fixed round robin over each XCD's range of tiles; 1: waves take the
+   * next tile of their XCD's range from an atomic counter and move on to
+   * the other ranges when theirs is empty; tiles are row aligned, so the
+   * results are bitwise those of the fixed order). */
+  int32_t edge_bwd_waves;
+  int32_t edge_fwd_queue;
 } mp_layer_cfg;
 
 /* Parameters of one layer, device FP32.  Edge MLP: Linear(3H->H), ELU,

@@ -1,12 +1,25 @@
 """Schedule autotuner for the edge kernels of one layer.
 
-The edge kernels run persistent workgroups over row-aligned tiles
-(mp_layer_cfg.tile_edges, .edge_grid, .edge_bwd_grid).  The tuner times the
-library's own forward and backward on the actual graph for a small set of
-schedules and keeps the fastest, cached per (arch, H, GEMM type, LayerNorm,
-rows, edges, sub-graphs) in a JSON file ($MPLAYER_TUNE_CACHE, default
-~/.cache/mplayer/tune.json).  Every schedule computes the same function;
-they differ only in the grouping of floating-point sums.
+The edge kernels run persistent workgroups over row-aligned tiles.  A
+schedule sets, in mp_layer_cfg: edges per tile (tile_edges), the workgroup
+counts of the forward and adjoint edge kernels (edge_grid, edge_bwd_grid),
+the waves per workgroup of the fused edge adjoint (edge_bwd_waves: 4, or 8
+for BF16 GEMMs at H <= 64, i.e. 64 or 128 edges staged per weight-gradient
+round) and the tile order of the edge forward (edge_fwd_queue: fixed round
+robin, or per-XCD atomic tile counters).  The tuner times the library's own
+forward and backward on the actual graph and keeps the fastest, cached per
+(arch, H, GEMM type, LayerNorm, rows, edges, sub-graphs) in a JSON file
+($MPLAYER_TUNE_CACHE, default ~/.cache/mplayer/tune.json).  Every schedule
+computes the same function; they differ only in the grouping of
+floating-point sums (and the forward's tile order not even in that).
+
+Not searched: 32 x 32 matrix-core tiles (every kernel's row-block layout is
+built on 16 x 16 products; the BF16 path is not bound by its products, and
+the FP32 products already issue back to back); the unsplit first edge
+Linear (twice the flops for the same bytes, never faster); BF16 storage of
+the edge states (it changes the stored precision, not just the grouping of
+sums; measured on the largest workload as a timing-only variant, it cut
+the edge forward by 18% and the edge adjoint by 1%).
 """
 
 import json
@@ -19,12 +32,29 @@ from .ops import layer_backward, layer_cfg, layer_forward
 TILE_EDGES = (64, 128, 256, 512)
 EDGE_GRIDS = (512, 1024, 2048)
 EDGE_BWD_GRIDS = (256, 512, 1024)
+EDGE_FWD_QUEUES = (0, 1)
+SCHEDULE_FIELDS = ("tile_edges", "edge_grid", "edge_bwd_grid", "edge_bwd_waves", "edge_fwd_queue")
 
 
-def candidates():
-    """Every schedule the tuner can return, as mp_layer_cfg field values."""
-    return [{"tile_edges": te, "edge_grid": eg, "edge_bwd_grid": bg}
-            for te in TILE_EDGES for eg in EDGE_GRIDS for bg in EDGE_BWD_GRIDS]
+def edge_bwd_waves_options(H, gemm):
+    """Waves per workgroup of the fused edge adjoint the library accepts."""
+    return (4, 8) if gemm == "bf16" and H <= 64 else (4,)
+
+
+def candidates(H=64, gemm="bf16"):
+    """Every schedule the tuner can return for this width and GEMM type, as
+    mp_layer_cfg field values."""
+    return [{"tile_edges": te, "edge_grid": eg, "edge_bwd_grid": bg, "edge_bwd_waves": w, "edge_fwd_queue": q}
+            for te in TILE_EDGES for eg in EDGE_GRIDS for bg in EDGE_BWD_GRIDS
+            for w in edge_bwd_waves_options(H, gemm) for q in EDGE_FWD_QUEUES]
+
+
+def apply_schedule(cfg, schedule):
+    """Set the schedule fields of an mp_layer_cfg from a schedule dict (other
+    keys, such as recorded timings, are ignored)."""
+    for f in SCHEDULE_FIELDS:
+        setattr(cfg, f, int(schedule.get(f, 0)))
+    return cfg
 
 
 def _cache_path():
@@ -34,7 +64,7 @@ def _cache_path():
 
 def _key(dg, H, layernorm, gemm):
     arch = torch.cuda.get_device_properties(dg.device).gcnArchName.split(":")[0]
-    return f"{arch}|H{H}|{gemm}|ln{int(layernorm)}|N{dg.n_rows}|E{dg.n_edges}|R{dg.host.R}"
+    return f"{arch}|H{H}|{gemm}|ln{int(layernorm)}|N{dg.n_rows}|E{dg.n_edges}|R{dg.host.R}|v2"
 
 
 def _load():
@@ -70,7 +100,9 @@ def _time(fn, reps):
 
 
 def tune_layer(dg, H, layernorm=True, gemm="bf16", reps=3, seed=0):
-    """Time the candidate schedules; returns the best as a dict."""
+    """Time the candidate schedules; returns the best as a dict.  For each
+    tile size: the best forward over (edge_grid, edge_fwd_queue), then the
+    best adjoint over (edge_bwd_grid, edge_bwd_waves) with that forward."""
     g = torch.Generator(device="cpu").manual_seed(seed)
     dev = dg.device
 
@@ -86,26 +118,30 @@ def tune_layer(dg, H, layernorm=True, gemm="bf16", reps=3, seed=0):
                   "gn": 1 + rnd(H, scale=0.1), "bgn": rnd(H, scale=0.1)})
     x, e = rnd(dg.n_rows, H), rnd(dg.n_edges, H)
     gx, ge = rnd(dg.n_rows, H), rnd(dg.n_edges, H)
+
+    def cfg_of(sched):
+        return apply_schedule(layer_cfg(H, layernorm, True, gemm), sched)
+
     best = None
     for te in TILE_EDGES:
         fwd = {}
         for eg in EDGE_GRIDS:
-            c = layer_cfg(H, layernorm, True, gemm)
-            c.tile_edges, c.edge_grid = te, eg
-            fwd[eg] = _time(lambda: layer_forward(c, p, dg, x, e), reps)
-        eg = min(fwd, key=fwd.get)
-        c = layer_cfg(H, layernorm, True, gemm)
-        c.tile_edges, c.edge_grid = te, eg
-        _, _, a_star = layer_forward(c, p, dg, x, e)
+            for q in EDGE_FWD_QUEUES:
+                c = cfg_of({"tile_edges": te, "edge_grid": eg, "edge_fwd_queue": q})
+                fwd[(eg, q)] = _time(lambda: layer_forward(c, p, dg, x, e), reps)
+        eg, q = min(fwd, key=fwd.get)
+        sched = {"tile_edges": te, "edge_grid": eg, "edge_fwd_queue": q}
+        _, _, a_star = layer_forward(cfg_of(sched), p, dg, x, e)
         bwd = {}
         for bg in EDGE_BWD_GRIDS:
-            c.edge_bwd_grid = bg
-            bwd[bg] = _time(lambda: layer_backward(c, p, dg, x, e, a_star, gx, ge), reps)
-        bg = min(bwd, key=bwd.get)
-        ms = fwd[eg] + bwd[bg]
+            for w in edge_bwd_waves_options(H, gemm):
+                c = cfg_of(dict(sched, edge_bwd_grid=bg, edge_bwd_waves=w))
+                bwd[(bg, w)] = _time(lambda: layer_backward(c, p, dg, x, e, a_star, gx, ge), reps)
+        bg, w = min(bwd, key=bwd.get)
+        ms = fwd[(eg, q)] + bwd[(bg, w)]
         if best is None or ms < best["ms"]:
-            best = {"tile_edges": te, "edge_grid": eg, "edge_bwd_grid": bg, "ms": ms,
-                    "fwd_ms": fwd[eg], "bwd_ms": bwd[bg]}
+            best = dict(sched, edge_bwd_grid=bg, edge_bwd_waves=w, ms=ms, fwd_ms=fwd[(eg, q)],
+                        bwd_ms=bwd[(bg, w)])
     del x, e, gx, ge
     torch.cuda.empty_cache()
     return best

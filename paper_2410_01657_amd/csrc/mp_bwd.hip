@@ -246,11 +246,12 @@ __device__ __forceinline__ void stage_frags(uint4* __restrict__ dst, const void*
 // ----------------------------------------------------------- edge adjoint
 
 
-template <int H, bool BF>
+template <int H, bool BF, int NWQ = 0>
 struct EdgeBwdCfg {
-  // BF16: eight waves per workgroup (128 staged rows) so the fragments are
-  // shared by more waves; FP32 (MFMA-bound) and H=128: four waves.
-  static constexpr int NW = (BF && H <= 64) ? 8 : 4;
+  // Default: BF16 eight waves per workgroup (128 staged rows) so the
+  // fragments are shared by more waves; FP32 (MFMA-bound) and H=128: four
+  // waves.  NWQ (4 or 8) overrides it (a schedule dimension).
+  static constexpr int NW = NWQ ? NWQ : ((BF && H <= 64) ? 8 : 4);
   static constexpr int ROWS = 16 * NW;
   // BF16: bias / LayerNorm gradients are column sums of staged tiles instead
   // of per-lane accumulators (frees registers); FP32 keeps them per lane.
@@ -301,9 +302,9 @@ struct EdgeBwdRows {
 //   g_h[k] = gh, summed per sender by k_gq through the reverse edges.
 // AM: the forward aggregated the MLP output, so the residual path carries
 // only the next layer's gradient (not Eq. 4b's).
-template <int H, bool BF, bool AM>
-__global__ __launch_bounds__((64 * EdgeBwdCfg<H, BF>::NW)) void k_edge_bwd(EdgeBwdArgs a) {
-  using C = EdgeBwdCfg<H, BF>;
+template <int H, bool BF, bool AM, int NWQ>
+__global__ __launch_bounds__((64 * EdgeBwdCfg<H, BF, NWQ>::NW)) void k_edge_bwd(EdgeBwdArgs a) {
+  using C = EdgeBwdCfg<H, BF, NWQ>;
   constexpr int NF = H / 4, MB = H / 16, NW = C::NW, ROWS = C::ROWS, NT = dw_tiles_per_wave<H, H, NW>();
   extern __shared__ uint4 smem[];
   char* tG2 = reinterpret_cast<char*>(smem);
@@ -584,17 +585,23 @@ __global__ __launch_bounds__((64 * EdgeBwdCfg<H, BF>::NW)) void k_edge_bwd(EdgeB
   }
 }
 
-template <int H, bool BF, bool AM>
+template <int H, bool BF, bool AM, int NWQ>
 static hipError_t launch_edge_bwd_am(const EdgeBwdArgs& a, int grid, hipStream_t s) {
-  using C = EdgeBwdCfg<H, BF>;
-  (void)hipFuncSetAttribute((const void*)k_edge_bwd<H, BF, AM>, hipFuncAttributeMaxDynamicSharedMemorySize,
+  using C = EdgeBwdCfg<H, BF, NWQ>;
+  (void)hipFuncSetAttribute((const void*)k_edge_bwd<H, BF, AM, NWQ>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)C::LDS);
-  hipLaunchKernelGGL((k_edge_bwd<H, BF, AM>), dim3(grid), dim3(64 * C::NW), C::LDS, s, a);
+  hipLaunchKernelGGL((k_edge_bwd<H, BF, AM, NWQ>), dim3(grid), dim3(64 * C::NW), C::LDS, s, a);
   return hipGetLastError();
 }
+// Waves per workgroup: the default, or 4 (any width and type), or 8 (the
+// BF16 kernel at H <= 64, whose default it is); the C ABI validates it.
 template <int H, bool BF>
 static hipError_t launch_edge_bwd_t(const EdgeBwdArgs& a, int grid, hipStream_t s) {
-  return a.am ? launch_edge_bwd_am<H, BF, true>(a, grid, s) : launch_edge_bwd_am<H, BF, false>(a, grid, s);
+  if constexpr (BF && H <= 64) {
+    if (a.waves == 4)
+      return a.am ? launch_edge_bwd_am<H, BF, true, 4>(a, grid, s) : launch_edge_bwd_am<H, BF, false, 4>(a, grid, s);
+  }
+  return a.am ? launch_edge_bwd_am<H, BF, true, 0>(a, grid, s) : launch_edge_bwd_am<H, BF, false, 0>(a, grid, s);
 }
 
 hipError_t launch_edge_bwd(const EdgeBwdArgs& a, int grid, hipStream_t s) {
@@ -632,17 +639,25 @@ struct EdgeBwdSplitCfg {
   static constexpr int NFR = BF ? 4 : 2;
   static constexpr size_t VECS = 2 * H * sizeof(float);
   static constexpr size_t CARRY = NW * H * sizeof(float);
-  static constexpr bool LDS_FRAG = NFR * FB + VECS + CARRY <= kLdsLimit;
-  static constexpr size_t LDS = (LDS_FRAG ? NFR * FB : 0) + CARRY + VECS;
+  // per-lane LayerNorm-parameter sums of every wave, added up at the end
+  static constexpr int NS = H / 64;  // values per lane after the 16-lane reduce-scatter
+  static constexpr size_t RED = NW * 64 * 2 * NS * sizeof(float);
+  static constexpr bool LDS_FRAG = NFR * FB + VECS + CARRY + RED <= kLdsLimit;
+  static constexpr size_t RED_OFF = LDS_FRAG ? NFR * FB : 0;
+  static constexpr size_t LDS = RED_OFF + RED + CARRY + VECS;
 };
 
-// The edge adjoint without its weight gradients, for widths where the
-// fused kernel's staging tiles and accumulators do not fit next to the
+// The edge adjoint without its matrix weight gradients, for widths where
+// the fused kernel's staging tiles and accumulators do not fit next to the
 // weights.  Per edge it computes what k_edge_bwd computes (g_e, g_h, the
 // segmented g_P) and writes the factors of the weight gradients instead of
-// accumulating them: gm and u (dW2 = sum gm u^T, db2 = sum gm), gE and
-// gE * normalised m (dbeta, dgamma); dW1c = sum g_h e^T is formed from g_h
-// and e.  Waves walk their tiles independently (no barriers in the loop).
+// accumulating them: gm and u (dW2 = sum gm u^T, db2 = sum gm); dW1c =
+// sum g_h e^T is formed from g_h and e.  The LayerNorm-parameter gradients
+// (dbeta = sum gE, dgamma = sum gE * normalised m) are summed here: each
+// block's 16 rows are reduced across lanes (sum16_scatter, so a lane keeps
+// H/64 features), accumulated per lane, and the waves' sums are added in
+// wave order into the workgroup's slab at the end.  Waves walk their tiles
+// independently (no barriers in the loop).
 template <int H, bool BF, bool AM>
 __global__ __launch_bounds__((64 * EdgeBwdSplitCfg<H, BF>::NW)) void k_edge_bwd_split(EdgeBwdArgs a) {
   using C = EdgeBwdSplitCfg<H, BF>;
@@ -664,6 +679,10 @@ __global__ __launch_bounds__((64 * EdgeBwdSplitCfg<H, BF>::NW)) void k_edge_bwd_
   const DevGraph& gr = a.g;
   const int lane = lane_id(), j = lane & 15, g = lane >> 4, wave = threadIdx.x / 64;
   const TileSched ts = tile_sched(gr.n_tiles);
+  constexpr int NS = C::NS;
+  float sbe[NS], sga[NS];  // this lane's share of dbeta, dgamma
+#pragma unroll
+  for (int c = 0; c < NS; ++c) sbe[c] = sga[c] = 0.f;
   for (int64_t tile = ts.t0 + ts.rank * NW + wave; tile < ts.t1; tile += ts.nr * NW) {
     const int64_t r0 = gr.tile_r[tile], r1 = gr.tile_r[tile + 1];
     const int64_t e0 = gr.tile_e[tile], e1 = gr.tile_e[tile + 1];
@@ -740,9 +759,14 @@ __global__ __launch_bounds__((64 * EdgeBwdSplitCfg<H, BF>::NW)) void k_edge_bwd_
           s2 += gx * xh;
           mp[i] = xh;
         }
-        if (valid) {
-          store_row_t<H, BF>(a.gE, k, g, gE);
-          store_row_t<H, BF>(a.gEx, k, g, t);
+        {
+          float rs[NS];  // gE and t are zero on lanes past the tile's last edge
+          sum16_scatter<NF>(gE, rs, j);
+#pragma unroll
+          for (int c = 0; c < NS; ++c) sbe[c] += rs[c];
+          sum16_scatter<NF>(t, rs, j);
+#pragma unroll
+          for (int c = 0; c < NS; ++c) sga[c] += rs[c];
         }
         s1 = row_sum(s1) * (1.f / H);
         s2 = row_sum(s2) * (1.f / H);
@@ -751,7 +775,6 @@ __global__ __launch_bounds__((64 * EdgeBwdSplitCfg<H, BF>::NW)) void k_edge_bwd_
       } else {
 #pragma unroll
         for (int i = 0; i < NF; ++i) mp[i] = gE[i];
-        if (valid) store_row_t<H, BF>(a.gE, k, g, gE);
       }
       if (valid) store_row_t<H, BF>(a.gm, k, g, mp);
       // gh = (W2^T gm) * ELU'(h); ELU'(h) = 1 for h > 0 else exp(h) = u + 1
@@ -806,6 +829,26 @@ __global__ __launch_bounds__((64 * EdgeBwdSplitCfg<H, BF>::NW)) void k_edge_bwd_
         float* dst = a.g_P + r * H;
         for (int c = (lane & 3) * 4; c < H; c += 16) *reinterpret_cast<float4*>(dst + c) = make_float4(0.f, 0.f, 0.f, 0.f);
       }
+    }
+  }
+  if (a.ln) {
+    // lane j of group g holds value indices q = j*NS + c of the row-block
+    // layout, i.e. feature 16 (q / 4) + 4 g + q % 4; add the waves in order
+    float* red = reinterpret_cast<float*>(reinterpret_cast<char*>(smem) + C::RED_OFF);
+#pragma unroll
+    for (int c = 0; c < NS; ++c) {
+      red[((wave * 64 + lane) * 2 + 0) * NS + c] = sbe[c];
+      red[((wave * 64 + lane) * 2 + 1) * NS + c] = sga[c];
+    }
+    __syncthreads();
+    float* slab = a.part + blockIdx.x * a.slab;
+    for (int t = threadIdx.x; t < 2 * H; t += blockDim.x) {
+      const int v = t / H, f = t % H;
+      const int q = 4 * (f / 16) + f % 4, gg = (f % 16) / 4;
+      const int l = q / NS + 16 * gg, c = q % NS;
+      float sum = 0.f;
+      for (int w = 0; w < NW; ++w) sum += red[((w * 64 + l) * 2 + v) * NS + c];
+      slab[(v == 0 ? 2 * (int64_t)H * H + 2 * H : 2 * (int64_t)H * H + H) + f] = sum;  // dbeta, dgamma
     }
   }
 }

@@ -129,6 +129,7 @@ DevGraph dev_graph(const mp_dev_graph* g) {
   d.member = g->member;
   d.n_tiles = 0;
   d.tile_r = d.tile_e = nullptr;
+  d.queue = nullptr;
   return d;
 }
 
@@ -148,6 +149,12 @@ int check_cfg(const mp_layer_cfg* c) {
     return mp_fail(MP_EINVAL, "edge grids must be 0 or in [1, 65536]");
   if (c->aggregate != MP_AGG_STATE && c->aggregate != MP_AGG_MESSAGE)
     return mp_fail(MP_EINVAL, "aggregate must be MP_AGG_STATE or MP_AGG_MESSAGE");
+  if (c->edge_bwd_waves != 0 && c->edge_bwd_waves != 4 &&
+      !(c->edge_bwd_waves == 8 && c->gemm_dtype == MP_BF16 && c->H <= 64))
+    return mp_fail(MP_EINVAL, "edge_bwd_waves must be 0, 4, or 8 (BF16 GEMMs at H <= 64 only; got %d)",
+                   c->edge_bwd_waves);
+  if (c->edge_fwd_queue != 0 && c->edge_fwd_queue != 1)
+    return mp_fail(MP_EINVAL, "edge_fwd_queue must be 0 or 1 (got %d)", c->edge_fwd_queue);
   return MP_OK;
 }
 
@@ -175,8 +182,8 @@ struct LayerFrags {
 
 struct LayerWs {
   LayerFrags fr;
-  size_t P, Q, a, gP, gh, gQ, part_e, part_n, part_q, tile_r, tile_e, total;
-  size_t sgm, su, sgE, sgEx;  // split edge adjoint: per-edge weight-gradient factors
+  size_t P, Q, a, gP, gh, gQ, part_e, part_n, part_q, tile_r, tile_e, queue, total;
+  size_t sgm, su;  // split edge adjoint: per-edge weight-gradient factors
   size_t nu, ngy, ngz, ngx;   // split node adjoint: per-row weight-gradient factors
   int ge, gbe, gn, gbn;
   int64_t n_tiles;
@@ -190,11 +197,12 @@ struct LayerWs {
     size_t o = fr.total;
     tile_r = o; o = align_up(o + (size_t)(n_tiles + 1) * 4);
     tile_e = o; o = align_up(o + (size_t)(n_tiles + 1) * 4);
+    queue = o; o = align_up(o + 8 * 4);
     P = o; o = align_up(o + N * H * 4);
     Q = o; o = align_up(o + N * H * 4);
     a = o; o = align_up(o + N * H * 4);
     gP = gh = gQ = part_e = part_n = part_q = 0;
-    sgm = su = sgE = sgEx = 0;
+    sgm = su = 0;
     nu = ngy = ngz = ngx = 0;
     if (bwd) {
       const size_t eb = E * H * (c->gemm_dtype == MP_BF16 ? 2 : 4);
@@ -207,8 +215,6 @@ struct LayerWs {
       if (edge_bwd_split(c->H)) {
         sgm = o; o = align_up(o + eb);
         su = o; o = align_up(o + eb);
-        sgE = o; o = align_up(o + eb);
-        sgEx = o; o = align_up(o + eb);
       }
       if (node_bwd_split(c->H, c->gemm_dtype == MP_BF16)) {
         const size_t nb = N * H * (c->gemm_dtype == MP_BF16 ? 2 : 4);  // factors in the product type
@@ -407,17 +413,18 @@ int layer_forward_launch(const mp_layer_cfg* cfg, const mp_layer_params* p, cons
   d.n_tiles = W.n_tiles;
   d.tile_r = reinterpret_cast<const int32_t*>(ws_at(ws, W.tile_r));
   d.tile_e = reinterpret_cast<const int32_t*>(ws_at(ws, W.tile_e));
+  d.queue = reinterpret_cast<int32_t*>(ws_at(ws, W.queue));
   float* P = pq_out ? pq_out : wsf(ws, W.P);
   float* Q = pq_out ? pq_out + (size_t)g->n_rows * cfg->H : wsf(ws, W.Q);
   float* a = a_star_out ? a_star_out : wsf(ws, W.a);
   if ((rc = run("tiles", s, [&] {
          return launch_tiles(d, reinterpret_cast<int32_t*>(ws_at(ws, W.tile_r)),
-                             reinterpret_cast<int32_t*>(ws_at(ws, W.tile_e)), s);
+                             reinterpret_cast<int32_t*>(ws_at(ws, W.tile_e)), d.queue, s);
        })))
     return rc;
   if ((rc = run("pack", s, [&] { return launch_pack(layer_jobs(cfg, p, W.fr, false), ws, s); }))) return rc;
   if ((rc = run("proj", s, [&] { return launch_proj(H, bf, d, x_in, ws_at(ws, W.fr.proj), p->be1, P, Q, W.gn, s); }))) return rc;
-  if ((rc = run("edge_fwd", s, [&] { return launch_edge_fwd(H, cfg->layernorm != 0, bf, cfg->aggregate != 0, d, P, Q, e_in, ws_at(ws, W.fr.edge), p->be2,
+  if ((rc = run("edge_fwd", s, [&] { return launch_edge_fwd(H, cfg->layernorm != 0, bf, cfg->aggregate != 0, cfg->edge_fwd_queue != 0, d, P, Q, e_in, ws_at(ws, W.fr.edge), p->be2,
                                       p->ge, p->bge, cfg->ln_eps, e_out, a, W.ge, s); })))
     return rc;
   if (cfg->halo && (rc = run("halo", s, [&] { return launch_halo(H, d, a, s); }))) return rc;
@@ -556,12 +563,13 @@ extern "C" int mp_layer_backward(const mp_layer_cfg* cfg, const mp_layer_params*
   d.n_tiles = W.n_tiles;
   d.tile_r = reinterpret_cast<const int32_t*>(ws_at(ws, W.tile_r));
   d.tile_e = reinterpret_cast<const int32_t*>(ws_at(ws, W.tile_e));
+  d.queue = reinterpret_cast<int32_t*>(ws_at(ws, W.queue));
   const float* P = pq ? pq : wsf(ws, W.P);
   const float* Q = pq ? pq + (size_t)g->n_rows * H : wsf(ws, W.Q);
   float* ga = wsf(ws, W.a);
   if ((rc = run("tiles", s, [&] {
          return launch_tiles(d, reinterpret_cast<int32_t*>(ws_at(ws, W.tile_r)),
-                             reinterpret_cast<int32_t*>(ws_at(ws, W.tile_e)), s);
+                             reinterpret_cast<int32_t*>(ws_at(ws, W.tile_e)), d.queue, s);
        })))
     return rc;
   float* gP = wsf(ws, W.gP);
@@ -646,6 +654,7 @@ extern "C" int mp_layer_backward(const mp_layer_cfg* cfg, const mp_layer_params*
   eb.ln = cfg->layernorm;
   eb.bf = bf;
   eb.am = cfg->aggregate;
+  eb.waves = cfg->edge_bwd_waves;
   eb.P = P;
   eb.Q = Q;
   eb.e_in = e_in;
@@ -666,8 +675,6 @@ extern "C" int mp_layer_backward(const mp_layer_cfg* cfg, const mp_layer_params*
     // gradients are summed from them (same slab layout as the fused kernel)
     eb.gm = ws_at(ws, W.sgm);
     eb.u = ws_at(ws, W.su);
-    eb.gE = ws_at(ws, W.sgE);
-    eb.gEx = ws_at(ws, W.sgEx);
     if ((rc = run("edge_bwd", s, [&] { return launch_edge_bwd_split(eb, W.gbe, s); }))) return rc;
     RowDwArgs rd{};
     rd.n_rows = g->n_edges;
@@ -688,12 +695,6 @@ extern "C" int mp_layer_backward(const mp_layer_cfg* cfg, const mp_layer_params*
     rd.off = (int64_t)H * H;
     rd.colsum_off = 2 * (int64_t)H * H;
     if ((rc = run("edge_dw", s, [&] { return launch_row_dw(rd, W.gbe, s); }))) return rc;
-    if (cfg->layernorm &&
-        (rc = run("edge_dw", s, [&] {
-           return launch_colsum2(g->n_edges, H, bf, bf, eb.gEx, eb.gE, eb.part, eb.slab, 2 * (int64_t)H * H + H,
-                                 2 * (int64_t)H * H + 2 * H, W.gbe, s);
-         })))
-      return rc;
   } else if ((rc = run("edge_bwd", s, [&] { return launch_edge_bwd(eb, W.gbe, s); }))) {
     return rc;
   }

@@ -297,6 +297,51 @@ __device__ __forceinline__ void seg_scan16(float (&v)[N], int key) {
 #undef MP_SEG_STEP
 }
 
+// Value of the lane whose index j (within its 16-lane group) differs in
+// bit M (M = 1, 2, 4, 8): DPP quad permutations for 1 and 2, a 16-lane
+// rotation by 8 for 8, and a bitmask swizzle (xor 4) for 4.
+template <int M>
+__device__ __forceinline__ float lane_xor16(float x) {
+  const int v = __builtin_bit_cast(int, x);
+  if constexpr (M == 1)
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xf, 0xf, false));  // [1,0,3,2]
+  else if constexpr (M == 2)
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xf, 0xf, false));  // [2,3,0,1]
+  else if constexpr (M == 4)
+    return __builtin_bit_cast(float, __builtin_amdgcn_ds_swizzle(v, 0x101F));  // and 0x1f, xor 4
+  else
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, v, 0x128, 0xf, 0xf, false));  // row_ror:8
+}
+
+// One halving step of a reduce-scatter over the 16 lanes j of a lane
+// group: the lane keeps the half of its N values selected by bit M of j
+// and adds the partner's copy of that half (the partner sends the half it
+// does not keep).
+template <int N, int M>
+__device__ __forceinline__ void sum16_half(const float (&in)[N], float (&out)[N / 2], int j) {
+  const bool hi = (j & M) != 0;
+#pragma unroll
+  for (int q = 0; q < N / 2; ++q) {
+    const float lo_v = in[q], hi_v = in[q + N / 2];
+    out[q] = (hi ? hi_v : lo_v) + lane_xor16<M>(hi ? lo_v : hi_v);
+  }
+}
+
+// Sum over the 16 lanes of each lane group, scattered: on return lane j
+// holds in out[c] the sum over the group's lanes of v[j * (N / 16) + c]
+// (N a multiple of 16).  Four halving steps (bits 8, 4, 2, 1 of j), N - N/16
+// exchanged values in all; the additions are in a fixed order, so the sums
+// are bitwise reproducible.
+template <int N>
+__device__ __forceinline__ void sum16_scatter(const float (&v)[N], float (&out)[N / 16], int j) {
+  static_assert(N % 16 == 0, "sum16_scatter needs a multiple of 16 values");
+  float a8[N / 2], a4[N / 4], a2[N / 8];
+  sum16_half<N, 8>(v, a8, j);
+  sum16_half<N / 2, 4>(a8, a4, j);
+  sum16_half<N / 4, 2>(a4, a2, j);
+  sum16_half<N / 8, 1>(a2, out, j);
+}
+
 // Value of lane 15 of the same lane group, delivered to lane 0 (and lane
 // j+1 receives lane j, which callers ignore).
 __device__ __forceinline__ float from_prev_lane(float x) {
@@ -349,6 +394,27 @@ __device__ __forceinline__ TileSched tile_sched(int64_t n_tiles) {
   s.t0 = vx * n_tiles / V;
   s.t1 = (vx + 1) * n_tiles / V;
   return s;
+}
+
+// Dynamic tile order: the tiles are cut into V contiguous ranges (one per
+// XCD, V = min(grid, 8), workgroup b on XCD b % V as in tile_sched); a wave
+// takes the next tile of its XCD's range from an atomic counter, and once
+// that range is empty moves on to the next XCD's range, and so on.
+// Returns -1 when every range is exhausted.  Tiles are row aligned, so a
+// tile's results do not depend on which wave computes it: the order is
+// dynamic but the results stay bitwise reproducible.
+__device__ __forceinline__ int64_t queue_next(int32_t* queue, int64_t n_tiles, int64_t V, int x0, int& q) {
+  while (q < V) {
+    const int x = (int)((x0 + q) % V);
+    const int64_t t0 = x * n_tiles / V, t1 = (x + 1) * n_tiles / V;
+    int old = 0;
+    if ((threadIdx.x & 63) == 0) old = atomicAdd(queue + x, 1);
+    old = __builtin_amdgcn_readfirstlane(old);
+    const int64_t t = t0 + old;
+    if (t < t1) return t;
+    ++q;
+  }
+  return -1;
 }
 
 // XCD-aware block numbering: the dispatcher hands consecutive workgroups to

@@ -147,8 +147,10 @@ hipError_t launch_proj(int H, bool bf, const DevGraph& g, const float* x, const 
 // row whose first edge index is at least floor(t * E / T); the last tile
 // ends at n_rows.  One thread per boundary.
 __global__ __launch_bounds__(256) void k_tiles(const int32_t* __restrict__ rowptr, int64_t n_rows, int64_t T,
-                                               int32_t* __restrict__ tile_r, int32_t* __restrict__ tile_e) {
+                                               int32_t* __restrict__ tile_r, int32_t* __restrict__ tile_e,
+                                               int32_t* __restrict__ queue) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (queue && t < 8) queue[t] = 0;
   if (t > T) return;
   const int64_t E = rowptr[n_rows];
   int64_t r = (t == 0) ? 0 : (t == T ? n_rows : lower_bound_i32(rowptr, n_rows + 1, (t * E) / T));
@@ -157,9 +159,9 @@ __global__ __launch_bounds__(256) void k_tiles(const int32_t* __restrict__ rowpt
   tile_e[t] = rowptr[r];
 }
 
-hipError_t launch_tiles(const DevGraph& g, int32_t* tile_r, int32_t* tile_e, hipStream_t s) {
+hipError_t launch_tiles(const DevGraph& g, int32_t* tile_r, int32_t* tile_e, int32_t* queue, hipStream_t s) {
   const int grid = (int)((g.n_tiles + 1 + 255) / 256);
-  hipLaunchKernelGGL(k_tiles, dim3(grid), dim3(256), 0, s, g.rowptr, g.n_rows, g.n_tiles, tile_r, tile_e);
+  hipLaunchKernelGGL(k_tiles, dim3(grid), dim3(256), 0, s, g.rowptr, g.n_rows, g.n_tiles, tile_r, tile_e, queue);
   return hipGetLastError();
 }
 
@@ -173,7 +175,9 @@ hipError_t launch_tiles(const DevGraph& g, int32_t* tile_r, int32_t* tile_e, hip
 // carried into the next block.  Every row's sum is written once by the lane
 // holding its last edge; no atomics, so results are bitwise reproducible.
 // AM: aggregate the MLP output (message) instead of the updated state.
-template <int H, bool BF, bool AM>
+// DQ: take tiles from the per-XCD atomic counters (queue_next) instead of
+// the fixed round robin of tile_sched.
+template <int H, bool BF, bool AM, bool DQ>
 __global__ __launch_bounds__(256, (H <= 64 ? 4 : 2)) void k_edge_fwd(DevGraph gr, const float* __restrict__ P,
                                                   const float* __restrict__ Q, const float* __restrict__ e_in,
                                                   const void* __restrict__ frag, const float* __restrict__ b2,
@@ -203,8 +207,13 @@ __global__ __launch_bounds__(256, (H <= 64 ? 4 : 2)) void k_edge_fwd(DevGraph gr
   const int lane = lane_id(), j = lane & 15, g = lane >> 4;
   const int nw = blockDim.x / 64;
   const TileSched ts = tile_sched(gr.n_tiles);
+  const int64_t V = gridDim.x < 8 ? gridDim.x : 8;
+  const int x0 = (int)(blockIdx.x % V);
+  int qi = 0;
 
-  for (int64_t tile = ts.t0 + ts.rank * nw + threadIdx.x / 64; tile < ts.t1; tile += ts.nr * nw) {
+  for (int64_t tile = DQ ? queue_next(gr.queue, gr.n_tiles, V, x0, qi) : ts.t0 + ts.rank * nw + threadIdx.x / 64;
+       DQ ? tile >= 0 : tile < ts.t1;
+       tile = DQ ? queue_next(gr.queue, gr.n_tiles, V, x0, qi) : tile + ts.nr * nw) {
     const int64_t r0 = gr.tile_r[tile], r1 = gr.tile_r[tile + 1];
     const int64_t e0 = gr.tile_e[tile], e1 = gr.tile_e[tile + 1];
     int carry_key = 0;  // no open row at the start of a tile
@@ -301,7 +310,7 @@ __global__ __launch_bounds__(256, (H <= 64 ? 4 : 2)) void k_edge_fwd(DevGraph gr
   }
 }
 
-template <int H, bool BF, bool AM>
+template <int H, bool BF, bool AM, bool DQ>
 static hipError_t launch_edge_fwd_t(const DevGraph& g, const float* P, const float* Q, const float* e_in,
                                     const void* frag, const float* b2, const float* lng, const float* lnb, int ln,
                                     float eps, float* e_out, float* a_out, int grid, hipStream_t s) {
@@ -309,28 +318,32 @@ static hipError_t launch_edge_fwd_t(const DevGraph& g, const float* P, const flo
   // fragments, 3 per-feature vectors, per-wave carries (4 waves)
   const size_t lds = ((2 * FB <= kEdgeLdsBudget) ? 2 * FB : 0) + 3 * H * sizeof(float) + 4 * H * sizeof(float);
   if (lds > 64 * 1024)
-    (void)hipFuncSetAttribute((const void*)k_edge_fwd<H, BF, AM>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute((const void*)k_edge_fwd<H, BF, AM, DQ>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds);
-  hipLaunchKernelGGL((k_edge_fwd<H, BF, AM>), dim3(grid), dim3(256), lds, s, g, P, Q, e_in, frag, b2, lng, lnb, ln,
+  hipLaunchKernelGGL((k_edge_fwd<H, BF, AM, DQ>), dim3(grid), dim3(256), lds, s, g, P, Q, e_in, frag, b2, lng, lnb, ln,
                      eps, e_out, a_out);
   return hipGetLastError();
 }
 
 template <int H, bool BF>
-static hipError_t launch_edge_fwd_am(bool am, const DevGraph& g, const float* P, const float* Q, const float* e_in,
-                                     const void* frag, const float* b2, const float* lng, const float* lnb, int ln,
-                                     float eps, float* e_out, float* a_out, int grid, hipStream_t s) {
-  return am ? launch_edge_fwd_t<H, BF, true>(g, P, Q, e_in, frag, b2, lng, lnb, ln, eps, e_out, a_out, grid, s)
-            : launch_edge_fwd_t<H, BF, false>(g, P, Q, e_in, frag, b2, lng, lnb, ln, eps, e_out, a_out, grid, s);
+static hipError_t launch_edge_fwd_am(bool am, bool dq, const DevGraph& g, const float* P, const float* Q,
+                                     const float* e_in, const void* frag, const float* b2, const float* lng,
+                                     const float* lnb, int ln, float eps, float* e_out, float* a_out, int grid,
+                                     hipStream_t s) {
+#define MP_EFWD(AMV, DQV) \
+  launch_edge_fwd_t<H, BF, AMV, DQV>(g, P, Q, e_in, frag, b2, lng, lnb, ln, eps, e_out, a_out, grid, s)
+  if (dq) return am ? MP_EFWD(true, true) : MP_EFWD(false, true);
+  return am ? MP_EFWD(true, false) : MP_EFWD(false, false);
+#undef MP_EFWD
 }
 
-hipError_t launch_edge_fwd(int H, bool ln, bool bf, bool am, const DevGraph& g, const float* P, const float* Q,
+hipError_t launch_edge_fwd(int H, bool ln, bool bf, bool am, bool dq, const DevGraph& g, const float* P, const float* Q,
                            const float* e_in, const void* frag, const float* b2, const float* lng, const float* lnb,
                            float eps, float* e_out, float* a_out, int grid, hipStream_t s) {
 #define MP_CASE(HH)                                                                                           \
   if (H == HH)                                                                                                \
-    return bf ? launch_edge_fwd_am<HH, true>(am, g, P, Q, e_in, frag, b2, lng, lnb, ln, eps, e_out, a_out, grid, s) \
-              : launch_edge_fwd_am<HH, false>(am, g, P, Q, e_in, frag, b2, lng, lnb, ln, eps, e_out, a_out, grid, s);
+    return bf ? launch_edge_fwd_am<HH, true>(am, dq, g, P, Q, e_in, frag, b2, lng, lnb, ln, eps, e_out, a_out, grid, s) \
+              : launch_edge_fwd_am<HH, false>(am, dq, g, P, Q, e_in, frag, b2, lng, lnb, ln, eps, e_out, a_out, grid, s);
   MP_CASE(32) MP_CASE(64) MP_CASE(128)
 #undef MP_CASE
   return hipErrorInvalidValue;

@@ -39,11 +39,15 @@ struct DevGraph {
   int64_t n_tiles;
   const int32_t* tile_r;
   const int32_t* tile_e;
+  // dynamic tile order (edge forward, queue = 1): one tile counter per XCD
+  // range, zeroed by launch_tiles
+  int32_t* queue;
 };
 
 // Edges per tile of the edge kernels' schedule.
 constexpr int kTileEdges = 128;
-hipError_t launch_tiles(const DevGraph& g, int32_t* tile_r, int32_t* tile_e, hipStream_t s);
+// Also zeroes queue[0..7] when queue is not null.
+hipError_t launch_tiles(const DevGraph& g, int32_t* tile_r, int32_t* tile_e, int32_t* queue, hipStream_t s);
 
 // Launch helpers; each returns the hipError_t of the launch.
 hipError_t launch_pack(const PackJobs& jobs, void* dst, hipStream_t s);
@@ -51,8 +55,10 @@ hipError_t launch_pack(const PackJobs& jobs, void* dst, hipStream_t s);
 hipError_t launch_proj(int H, bool bf, const DevGraph& g, const float* x, const void* frag_ab,
                        const float* b1, float* P, float* Q, int grid, hipStream_t s);
 
-// am: aggregate the edge MLP's output (message) instead of the updated state
-hipError_t launch_edge_fwd(int H, bool ln, bool bf, bool am, const DevGraph& g, const float* P, const float* Q,
+// am: aggregate the edge MLP's output (message) instead of the updated state;
+// dq: waves take tiles from per-XCD atomic counters (g.queue) instead of a
+// fixed round robin
+hipError_t launch_edge_fwd(int H, bool ln, bool bf, bool am, bool dq, const DevGraph& g, const float* P, const float* Q,
                            const float* e_in, const void* frag_c2, const float* b2, const float* lng,
                            const float* lnb, float eps, float* e_out, float* a_out, int grid,
                            hipStream_t s);
@@ -124,6 +130,7 @@ struct EdgeBwdArgs {
   DevGraph g;
   int H, ln, bf;
   int am;  // the forward aggregated the MLP output (message), not e'
+  int waves;  // waves per workgroup of the fused kernel: 0 (default), 4, or 8 (BF16, H <= 64)
 
   const float* P;
   const float* Q;
@@ -140,13 +147,11 @@ struct EdgeBwdArgs {
   float* g_P;            // [N][H] sum of g_h over each row's incoming edges
   float* part;           // partial weight gradients, slab per workgroup
   int64_t slab;
-  // split form (edge_bwd_split): per-edge factors of the weight gradients,
-  // [E][H] each, BF16 on the BF16 path: gm (pre-LayerNorm gradient), u
-  // (ELU output), gE (gradient reaching e') and gEx (gE * normalised m)
+  // split form (edge_bwd_split): per-edge factors of the matrix weight
+  // gradients, [E][H] each, BF16 on the BF16 path: gm (pre-LayerNorm
+  // gradient) and u (ELU output)
   void* gm;
   void* u;
-  void* gE;
-  void* gEx;
 };
 hipError_t launch_edge_bwd(const EdgeBwdArgs& a, int grid, hipStream_t s);
 // Whether layers of width H use the split edge adjoint (the fused kernel's

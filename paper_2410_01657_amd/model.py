@@ -9,6 +9,7 @@ import numpy as np
 import torch
 
 from .graph import DeviceGraph, build_graph
+from .autotune import apply_schedule
 from .ops import (ConsistentMSEFn, DeepLayerFn, DeepMLPFn, MLPFn, MPLayerFn, deep_layer_cfg, deep_mlp_cfg,
                   edge_inputs, layer_cfg, mlp_cfg)
 
@@ -47,8 +48,8 @@ class ConsistentGNN:
         if self.deep and (gemm != "f32" or spec.H not in (8, 16, 32)):
             raise ValueError("deep MLPs run in FP32 at H = 8, 16 or 32")
         self.spec, self.gemm, self.halo = spec, gemm, halo
-        # edge-kernel schedule: None (library defaults) or a dict with
-        # tile_edges / edge_grid / edge_bwd_grid (see autotune.py)
+        # edge-kernel schedule: None (library defaults) or a dict of
+        # mp_layer_cfg schedule fields (see autotune.SCHEDULE_FIELDS)
         self.schedule = schedule
         self.device = torch.device(device)
         self.params = {k: torch.as_tensor(np.asarray(v), dtype=torch.float32).to(self.device).contiguous()
@@ -95,9 +96,7 @@ class ConsistentGNN:
             return x, e
         cfg = layer_cfg(s.H, s.layernorm, self.halo, self.gemm, s.ln_eps, s.aggregate)
         if self.schedule:
-            cfg.tile_edges = int(self.schedule.get("tile_edges", 0))
-            cfg.edge_grid = int(self.schedule.get("edge_grid", 0))
-            cfg.edge_bwd_grid = int(self.schedule.get("edge_bwd_grid", 0))
+            apply_schedule(cfg, self.schedule)
         for m in range(s.n_layers):
             names = _layer_param_names(m, s.layernorm)
             args = [self.params[names[f]] if f in names else None for f in self.LAYER_ORDER]

@@ -36,7 +36,7 @@ def test_exports_every_declared_symbol(L):
     for name in declared:
         assert hasattr(lib, name), name
     assert set(declared) == set(L.EXPORTED)
-    assert lib.mp_abi_version() == L.ABI_VERSION == 2
+    assert lib.mp_abi_version() == L.ABI_VERSION == 3
 
 
 def test_hex_links_counts():
@@ -485,3 +485,34 @@ def test_noalloc_forward_validates_before_touching_a_gpu(L):
         call("mp_layer_forward_noalloc", C.byref(cfg), C.byref(params), C.byref(big), 4096, 8192, 12288, 16384,
              20480, 24576, None)
     assert e.value.code == L.MP_EINVAL and "maximum" in str(e.value)
+
+
+def test_schedule_fields_are_validated(L):
+    """The schedule dimensions of mp_layer_cfg are checked before any
+    launch: waves per workgroup of the edge adjoint (0, 4, or 8 with BF16
+    GEMMs at H <= 64) and the forward's tile order (0 or 1)."""
+    from paper_2410_01657_amd._lib import MPError, call
+    from paper_2410_01657_amd.autotune import candidates
+    from paper_2410_01657_amd.ops import layer_cfg
+    d = _fake_desc(L)
+    nb = C.c_size_t()
+    for H, gemm, waves, q, ok in ((64, "bf16", 8, 1, True), (64, "bf16", 4, 0, True), (32, "bf16", 8, 0, True),
+                                  (128, "bf16", 8, 0, False), (64, "f32", 8, 0, False), (64, "f32", 4, 1, True),
+                                  (64, "bf16", 6, 0, False), (64, "bf16", 0, 2, False)):
+        cfg = layer_cfg(H, gemm=gemm)
+        cfg.edge_bwd_waves, cfg.edge_fwd_queue = waves, q
+        if ok:
+            call("mp_layer_workspace_size", C.byref(cfg), C.byref(d), 1, C.byref(nb))
+        else:
+            with pytest.raises(MPError) as e:
+                call("mp_layer_workspace_size", C.byref(cfg), C.byref(d), 1, C.byref(nb))
+            assert e.value.code == L.MP_EINVAL
+    # every candidate the tuner may return is accepted
+    for H, gemm in ((32, "bf16"), (64, "bf16"), (64, "f32"), (128, "bf16"), (128, "f32")):
+        cs = candidates(H, gemm)
+        assert len(cs) == len({tuple(sorted(c.items())) for c in cs})
+        for sched in cs[:: max(1, len(cs) // 12)]:
+            cfg = layer_cfg(H, gemm=gemm)
+            for k, v in sched.items():
+                setattr(cfg, k, v)
+            call("mp_layer_workspace_size", C.byref(cfg), C.byref(d), 1, C.byref(nb))

@@ -2,7 +2,8 @@
 schedule the autotuner may pick (Eq. 4a-e and their adjoint, Eq. 3).
 
 A schedule (edges per row-aligned tile, workgroups of the forward and of
-the adjoint edge kernels) regroups floating-point sums only: every
+the adjoint edge kernels, waves per workgroup of the adjoint, fixed or
+queued tile order of the forward) regroups floating-point sums only: every
 candidate is compared element by element with the FP64 oracle at the
 tolerances of the default-schedule tests, on the C0 mesh cut into 2x2x2
 blocks, on a seeded uneven bisection with T-junctions, and on a
@@ -49,9 +50,9 @@ def _graph(name):
     return DeviceGraph(hg, DEV), og, halo_lists(og, copies)
 
 
-def _candidates():
+def _candidates(H, gemm):
     from paper_2410_01657_amd.autotune import candidates
-    return candidates()
+    return candidates(H, gemm)
 
 
 @pytest.mark.parametrize("graph,H,gemm", [("c0_blocks", 64, "bf16"), ("c0_blocks", 64, "f32"),
@@ -78,10 +79,9 @@ def test_every_candidate_schedule_matches_the_oracle(graph, H, gemm):
     X, Ein, GX, GE = _t(x), _t(e), _t(gx), _t(ge)
     tol_f, tol_b = (1e-5, 1e-4) if gemm == "f32" else (3e-2, 5e-2)
     worst = {}
-    for sched in _candidates():
-        cfg = layer_cfg(H, True, gemm=gemm)
-        for k, v in sched.items():
-            setattr(cfg, k, v)
+    from paper_2410_01657_amd.autotune import apply_schedule
+    for sched in _candidates(H, gemm):
+        cfg = apply_schedule(layer_cfg(H, True, gemm=gemm), sched)
         runs = []
         for _ in range(2):
             xg, eg, ag = layer_forward(cfg, p, dg, X, Ein)
@@ -100,5 +100,5 @@ def test_every_candidate_schedule_matches_the_oracle(graph, H, gemm):
             tol = tol_f if k in ("x", "e", "a") else tol_b
             assert err < tol, (sched, k, err)
             worst[k] = max(worst.get(k, 0.0), err)
-    print(f"{graph} H={H} {gemm}: {len(_candidates())} schedules, worst errors "
+    print(f"{graph} H={H} {gemm}: {len(_candidates(H, gemm))} schedules, worst errors "
           + ", ".join(f"{k} {v:.1e}" for k, v in sorted(worst.items())))
