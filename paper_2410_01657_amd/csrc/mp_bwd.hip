@@ -253,23 +253,30 @@ struct EdgeBwdCfg {
   // waves.  NWQ (4 or 8) overrides it (a schedule dimension).
   static constexpr int NW = NWQ ? NWQ : ((BF && H <= 64) ? 8 : 4);
   static constexpr int ROWS = 16 * NW;
+  // TP (FP32 at H = 64): two workgroups per CU, so two waves per SIMD (the
+  // VALU phases between one wave's products overlap the other wave's
+  // matrix work; with one wave per SIMD they could not): the weight-gradient
+  // factors are staged in two rounds through one pair of tiles, only W1c
+  // and W2 sit in LDS (the transposed products read them at transposed
+  // addresses), and the bias / LayerNorm sums are reduced across the
+  // block's lanes (sum16_scatter) into one register per lane, which brings
+  // the kernel to 249 VGPRs and 68 KB of LDS.  Measured on C4: 45.4 ->
+  // 40.6 ms per launch (one wave per SIMD with the next block's rows
+  // loaded ahead had given 47.7 -> 45.4).
+  static constexpr bool TP = !BF && H == 64;
+  static constexpr int MINB = TP ? 2 : 1;
   // BF16: bias / LayerNorm gradients are column sums of staged tiles instead
   // of per-lane accumulators (frees registers); FP32 keeps them per lane.
   static constexpr bool VEC = BF;
-  static constexpr int NTILES = VEC ? 6 : 4;
+  static constexpr int NTILES = TP ? 2 : (VEC ? 6 : 4);
+  static constexpr int NFRAG = TP ? 2 : 4;
   static constexpr size_t FB = frag_bytes(H, H, BF);
   static constexpr size_t TB = tile_bytes<H, BF, ROWS>();
   static constexpr size_t STAGE = NTILES * TB;
-  static constexpr bool LDS_FRAG = 4 * FB + STAGE <= kLdsLimit;
+  static constexpr bool LDS_FRAG = NFRAG * FB + STAGE <= kLdsLimit;
   static constexpr size_t VECS = 2 * H * sizeof(float);  // b2 and the LayerNorm gain
   static constexpr size_t CARRY = NW * H * sizeof(float);  // per-wave open-row sums between blocks
-  static constexpr size_t LDS = STAGE + (LDS_FRAG ? 4 * FB : 0) + CARRY + VECS;
-  // FP32 runs one wave per SIMD (its accumulators and fragments exceed
-  // half the register file), with registers to spare for loading the next
-  // block's rows ahead (measured on C4: 47.7 -> 44.7 ms per launch); the
-  // BF16 kernel keeps two waves per SIMD instead (prefetching there would
-  // spill or halve the occupancy: 18.3 -> 23.7 ms).
-  static constexpr bool PF = !BF && H == 64;
+  static constexpr size_t LDS = STAGE + (LDS_FRAG ? NFRAG * FB : 0) + CARRY + VECS;
 };
 
 // The rows one 16-edge block of the edge adjoint reads: e_k, P_i, Q_j,
@@ -303,20 +310,21 @@ struct EdgeBwdRows {
 // AM: the forward aggregated the MLP output, so the residual path carries
 // only the next layer's gradient (not Eq. 4b's).
 template <int H, bool BF, bool AM, int NWQ>
-__global__ __launch_bounds__((64 * EdgeBwdCfg<H, BF, NWQ>::NW)) void k_edge_bwd(EdgeBwdArgs a) {
+__global__ __launch_bounds__((64 * EdgeBwdCfg<H, BF, NWQ>::NW), (EdgeBwdCfg<H, BF, NWQ>::MINB)) void k_edge_bwd(EdgeBwdArgs a) {
   using C = EdgeBwdCfg<H, BF, NWQ>;
   constexpr int NF = H / 4, MB = H / 16, NW = C::NW, ROWS = C::ROWS, NT = dw_tiles_per_wave<H, H, NW>();
+  constexpr bool TP = C::TP;
   extern __shared__ uint4 smem[];
   char* tG2 = reinterpret_cast<char*>(smem);
   char* tA2 = tG2 + C::TB;
-  char* tG1 = tA2 + C::TB;
-  char* tA1 = tG1 + C::TB;
+  char* tG1 = TP ? tG2 : tA2 + C::TB;   // TP: the second round reuses the first round's tiles
+  char* tA1 = TP ? tA2 : tG1 + C::TB;
   char* tGE = tA1 + C::TB;   // VEC: gE and gE * LN-normalised m, for dbeta / dgamma
   char* tGM = tGE + C::TB;
   const char* fr;
   if constexpr (C::LDS_FRAG) {
     uint4* fl = smem + C::STAGE / 16;
-    stage_frags(fl, a.frag, 4 * C::FB);
+    stage_frags(fl, a.frag, C::NFRAG * C::FB);
     fr = reinterpret_cast<const char*>(fl);
   } else {
     fr = reinterpret_cast<const char*>(a.frag);
@@ -335,7 +343,7 @@ __global__ __launch_bounds__((64 * EdgeBwdCfg<H, BF, NWQ>::NW)) void k_edge_bwd(
   v4f acc2[NT], acc1[NT];
 #pragma unroll
   for (int n = 0; n < NT; ++n) acc2[n] = acc1[n] = v4f{0.f, 0.f, 0.f, 0.f};
-  constexpr int NV = C::VEC ? 1 : NF;  // per-lane vector accumulators (FP32 path)
+  constexpr int NV = (C::VEC || TP) ? 1 : NF;  // per-lane vector accumulators (FP32 path)
   float db2[NV], dga[NV], dbe[NV];
 #pragma unroll
   for (int i = 0; i < NV; ++i) db2[i] = dga[i] = dbe[i] = 0.f;
@@ -364,35 +372,15 @@ __global__ __launch_bounds__((64 * EdgeBwdCfg<H, BF, NWQ>::NW)) void k_edge_bwd(
     int carry_key = 0;  // no open row at the start of a tile
 
     // Index loads run one block ahead, so each block waits on a single
-    // round trip to memory (its rows), not on indices and then rows.  With
-    // PF (the FP32 path, one wave per SIMD and registers to spare) the rows
-    // run one block ahead as well and the indices two: the next block's
-    // rows are in flight while this block is computed, issued before this
-    // block's stores so that waiting for them never waits for the stores.
-    constexpr bool PF = C::PF;
+    // round trip to memory (its rows), not on indices and then rows.
     const int64_t e_last = e1 > e0 ? e1 - 1 : 0;  // in-bounds stand-in for absent edges
-    int ri_n, sj_n, md_n, nx_n;  // indices of the next block
-    int ri_c = 0, sj_c = 0, md_c = 1, nx_c = -1;  // PF: indices of the current block
-    EdgeBwdRows<H> nx;  // PF: rows of the next block
+    int ri_n, sj_n, md_n, nx_n;
     {
       const int64_t k = e0 + j, kk = k < e1 ? k : e_last;
-      if constexpr (PF) {
-        ri_c = gr.recv[kk];
-        sj_c = gr.col[kk];
-        md_c = gr.mult[kk];
-        nx_c = (k + 1 < e1) ? gr.recv[k + 1] : -1;
-        const int64_t k2 = k + 16, kk2 = k2 < e1 ? k2 : e_last;
-        ri_n = gr.recv[kk2];
-        sj_n = gr.col[kk2];
-        md_n = gr.mult[kk2];
-        nx_n = (k2 + 1 < e1) ? gr.recv[k2 + 1] : -1;
-        nx.load(a, kk, ri_c, sj_c, g);
-      } else {
-        ri_n = gr.recv[kk];
-        sj_n = gr.col[kk];
-        md_n = gr.mult[kk];
-        nx_n = (k + 1 < e1) ? gr.recv[k + 1] : -1;
-      }
+      ri_n = gr.recv[kk];
+      sj_n = gr.col[kk];
+      md_n = gr.mult[kk];
+      nx_n = (k + 1 < e1) ? gr.recv[k + 1] : -1;
       // complete these loads here, so that the loop's entry state holds no
       // pending loads (else the compiler's wait at the loop head, merged
       // with the back edge, also drains the previous block's stores)
@@ -409,40 +397,25 @@ __global__ __launch_bounds__((64 * EdgeBwdCfg<H, BF, NWQ>::NW)) void k_edge_bwd(
       const int64_t k = e0 + it * 16 + j;
       const bool valid = k < e1;
       const int64_t kk = valid ? k : e_last;
-      const int ri = PF ? ri_c : ri_n;
-      const int sj = PF ? sj_c : sj_n;
-      const float inv_d = 1.f / (float)(PF ? md_c : md_n);
-      const int next = PF ? nx_c : nx_n;
+      const int ri = ri_n;
+      const int sj = sj_n;
+      const float inv_d = 1.f / (float)md_n;
+      const int next = nx_n;
       const bool last = valid && next != ri;
       const int key = valid ? ri + 1 : -1;
 
-      EdgeBwdRows<H> cur;
-      if constexpr (PF) {
-        cur = nx;
-        ri_c = ri_n;
-        sj_c = sj_n;
-        md_c = md_n;
-        nx_c = nx_n;
-        // the next block's rows (its indices arrived with the previous
-        // block), then the indices of the block after it
-        const int64_t k1 = k + 16, kk1 = k1 < e1 ? k1 : e_last;
-        nx.load(a, kk1, ri_c, sj_c, g);
-        const int64_t k2 = k + 32, kk2 = k2 < e1 ? k2 : e_last;
-        ri_n = gr.recv[kk2];
-        sj_n = gr.col[kk2];
-        md_n = gr.mult[kk2];
-        nx_n = (k2 + 1 < e1) ? gr.recv[k2 + 1] : -1;
-      } else {
-        // next block's indices first (the only loads issued before this
-        // block's stores that the next block waits on), then every row this
-        // block reads, issued together
+      // next block's indices first (the only loads issued before this
+      // block's stores that the next block waits on), then every row this
+      // block reads, issued together
+      {
         const int64_t k2 = k + 16, kk2 = k2 < e1 ? k2 : e_last;
         ri_n = gr.recv[kk2];
         sj_n = gr.col[kk2];
         md_n = gr.mult[kk2];
         nx_n = (k2 + 1 < e1) ? gr.recv[k2 + 1] : -1;
-        cur.load(a, kk, ri, sj, g);
       }
+      EdgeBwdRows<H> cur;
+      cur.load(a, kk, ri, sj, g);
       float (&ev)[NF] = cur.ev;
       float (&u)[NF] = cur.u;
       float (&t)[NF] = cur.t;
@@ -476,7 +449,7 @@ __global__ __launch_bounds__((64 * EdgeBwdCfg<H, BF, NWQ>::NW)) void k_edge_bwd(
 #pragma unroll
         for (int i = 0; i < NF; ++i) {
           const float xh = (mp[i] - mean) * rstd;
-          if constexpr (!C::VEC) {
+          if constexpr (!C::VEC && !TP) {
             dga[i] += gE[i] * xh;
             dbe[i] += gE[i];
           } else {
@@ -491,6 +464,13 @@ __global__ __launch_bounds__((64 * EdgeBwdCfg<H, BF, NWQ>::NW)) void k_edge_bwd(
           stage_row<H, BF, ROWS>(tGE, srow, g, gE);
           stage_row<H, BF, ROWS>(tGM, srow, g, t);
         }
+        if constexpr (TP) {  // dbeta += sum of gE, dgamma += sum of gE * x^ over the block's rows
+          float rs[1];
+          sum16_scatter<NF>(gE, rs, j);
+          dbe[0] += rs[0];
+          sum16_scatter<NF>(t, rs, j);
+          dga[0] += rs[0];
+        }
         s1 = row_sum(s1) * (1.f / H);
         s2 = row_sum(s2) * (1.f / H);
 #pragma unroll
@@ -499,7 +479,11 @@ __global__ __launch_bounds__((64 * EdgeBwdCfg<H, BF, NWQ>::NW)) void k_edge_bwd(
 #pragma unroll
         for (int i = 0; i < NF; ++i) mp[i] = gE[i];
       }
-      if constexpr (!C::VEC) {
+      if constexpr (TP) {
+        float rs[1];
+        sum16_scatter<NF>(mp, rs, j);
+        db2[0] += rs[0];
+      } else if constexpr (!C::VEC) {
 #pragma unroll
         for (int i = 0; i < NF; ++i) db2[i] += mp[i];
       }
@@ -508,11 +492,16 @@ __global__ __launch_bounds__((64 * EdgeBwdCfg<H, BF, NWQ>::NW)) void k_edge_bwd(
       // gh = (W2^T gm) * ELU'(h); ELU'(h) = 1 for h > 0 else exp(h) = u + 1
 #pragma unroll
       for (int i = 0; i < NF; ++i) t[i] = 0.f;
-      gemm<BF, MB, MB>(fW2t, mp, t, lane);
+      if constexpr (TP)
+        gemm_f32_tr<H>(reinterpret_cast<const float*>(fW2), mp, t, lane);
+      else
+        gemm<BF, MB, MB>(fW2t, mp, t, lane);
 #pragma unroll
       for (int i = 0; i < NF; ++i) t[i] *= (u[i] > 0.f ? 1.f : u[i] + 1.f);
-      stage_row<H, BF, ROWS>(tG1, srow, g, t);
-      stage_row<H, BF, ROWS>(tA1, srow, g, ev);
+      if constexpr (!TP) {
+        stage_row<H, BF, ROWS>(tG1, srow, g, t);
+        stage_row<H, BF, ROWS>(tA1, srow, g, ev);
+      }
       if constexpr (AM) {
         if (a.g_e_out) {
           load_row<H>(a.g_e_out + kk * H, g, gE);
@@ -522,13 +511,24 @@ __global__ __launch_bounds__((64 * EdgeBwdCfg<H, BF, NWQ>::NW)) void k_edge_bwd(
         }
       }
       // g_e = gE + W1c^T gh
-      gemm<BF, MB, MB>(fW1ct, t, gE, lane);
+      if constexpr (TP)
+        gemm_f32_tr<H>(reinterpret_cast<const float*>(fW1c), t, gE, lane);
+      else
+        gemm<BF, MB, MB>(fW1ct, t, gE, lane);
       if (valid) {
         store_row<H>(a.g_e_in + k * H, g, gE);
         if constexpr (BF)
           store_row_bf16<H>(reinterpret_cast<__bf16*>(a.g_h) + k * H, g, t);
         else
           store_row<H>(reinterpret_cast<float*>(a.g_h) + k * H, g, t);
+      }
+      if constexpr (TP) {
+        // round 1: dW2 from the staged (gm, u); then the same tiles take (gh, e)
+        __syncthreads();
+        dw_tiles<H, H, BF, NW>(tG2, tA2, acc2, wave, lane);
+        __syncthreads();
+        stage_row<H, BF, ROWS>(tG1, srow, g, t);
+        stage_row<H, BF, ROWS>(tA1, srow, g, ev);
       }
       // g_P: segmented sum of gh per receiver
 #pragma unroll
@@ -552,7 +552,7 @@ __global__ __launch_bounds__((64 * EdgeBwdCfg<H, BF, NWQ>::NW)) void k_edge_bwd(
       carry_key = from_prev_lane_i(key);
 
       __syncthreads();
-      dw_tiles<H, H, BF, NW>(tG2, tA2, acc2, wave, lane);
+      if constexpr (!TP) dw_tiles<H, H, BF, NW>(tG2, tA2, acc2, wave, lane);
       dw_tiles<H, H, BF, NW>(tG1, tA1, acc1, wave, lane);
       if constexpr (C::VEC) {
         cs_b2.add(tG2, wave, lane);
@@ -578,6 +578,21 @@ __global__ __launch_bounds__((64 * EdgeBwdCfg<H, BF, NWQ>::NW)) void k_edge_bwd(
     cs_b2.store(scratch, slab + 2 * H * H, wave, lane);
     cs_ga.store(scratch, slab + 2 * H * H + H, wave, lane);
     cs_be.store(scratch, slab + 2 * H * H + 2 * H, wave, lane);
+  } else if constexpr (TP) {
+    // lane j of group g holds feature 16 (j / 4) + 4 g + j % 4 (H = 64: one
+    // value per lane after the reduce-scatter); waves added in order
+    __syncthreads();
+    scratch[(wave * 64 + lane) * 3 + 0] = db2[0];
+    scratch[(wave * 64 + lane) * 3 + 1] = dga[0];
+    scratch[(wave * 64 + lane) * 3 + 2] = dbe[0];
+    __syncthreads();
+    for (int t = threadIdx.x; t < 3 * H; t += blockDim.x) {
+      const int v = t / H, f = t % H;
+      const int l = (4 * (f / 16) + f % 4) + 16 * ((f % 16) / 4);
+      float sum = 0.f;
+      for (int w = 0; w < NW; ++w) sum += scratch[(w * 64 + l) * 3 + v];
+      slab[2 * H * H + v * H + f] = sum;
+    }
   } else {
     block_sum_vec<H>(db2, scratch, slab + 2 * H * H, wave, lane);
     block_sum_vec<H>(dga, scratch, slab + 2 * H * H + H, wave, lane);
