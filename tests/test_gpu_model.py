@@ -72,8 +72,10 @@ def test_model_bf16_error_bounded():
     Yo, Lo, go = _oracle_run(spec, inp.params, inp, inp.elem_part, 8)
     assert normwise(Yg, Yo) < 3e-2
     assert abs(Lg - Lo) / abs(Lo) < 3e-2
-    worst = max(normwise(gg[k], go[k]) for k in go)
-    assert worst < 1e-1, worst
+    errs = {k: normwise(gg[k], go[k]) for k in go}
+    worst = max(errs, key=errs.get)
+    print(f"C0 H64-LN BF16: output {normwise(Yg, Yo):.2e}, worst parameter gradient {errs[worst]:.2e} ({worst})")
+    assert errs[worst] < 5e-2, (worst, errs[worst])
 
 
 def test_r_consistency_gpu_c0():

@@ -24,7 +24,7 @@ from _util import normwise, oracle_edge_order
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
-TOL = {"f32": (1e-4, 1e-4), "bf16": (3e-2, 1e-1)}
+TOL = {"f32": (1e-4, 1e-4), "bf16": (3e-2, 5e-2)}
 
 
 @pytest.fixture(scope="module")
@@ -65,8 +65,10 @@ def test_periodic_model_vs_oracle(small, gemm, R):
     tol_y, tol_g = TOL["bf16" if gemm == "bf16" else "f32"]
     assert normwise(Y.detach().cpu().numpy(), Yo[prob.host.row_gid]) < tol_y
     assert abs(float(loss.detach()) - Lo) / Lo < tol_y
-    for k, t in model.params.items():
-        assert normwise(t.grad.cpu().numpy(), go[k]) < tol_g, k
+    errs = {k: normwise(t.grad.cpu().numpy(), go[k]) for k, t in model.params.items()}
+    worst = max(errs, key=errs.get)
+    print(f"periodic {gemm} R={R}: worst parameter gradient {errs[worst]:.2e} ({worst})")
+    assert errs[worst] < tol_g, (worst, errs[worst])
 
 
 # Table I's models (deep narrow MLPs) on the same full-size partition
@@ -110,5 +112,7 @@ def test_table2_r8_sampled_outputs_and_gradients(gemm):
             ref_g[k] = ref_g.get(k, 0.0) + v
     tol_y, tol_g = TOL["bf16" if gemm == "bf16" else "f32"]
     assert normwise(Ys, np.stack(ref_y)) < tol_y
-    for k, t in model.params.items():
-        assert normwise(t.grad.cpu().numpy(), ref_g[k]) < tol_g, k
+    errs = {k: normwise(t.grad.cpu().numpy(), ref_g[k]) for k, t in model.params.items()}
+    worst = max(errs, key=errs.get)
+    print(f"Table II R=8 {gemm}: worst parameter gradient {errs[worst]:.2e} ({worst})")
+    assert errs[worst] < tol_g, (worst, errs[worst])

@@ -78,7 +78,7 @@ def _report(tag, Ys, Yr, g, gr):
     return ey, eg[worst]
 
 
-@pytest.mark.parametrize("gemm,tol_y,tol_g", [("f32", 1e-4, 1e-4), ("bf16", 3e-2, 1e-1)])
+@pytest.mark.parametrize("gemm,tol_y,tol_g", [("f32", 1e-4, 1e-4), ("bf16", 3e-2, 5e-2)])
 def test_c3_sampled_outputs_and_gradients(gemm, tol_y, tol_g):
     ey, eg = _report(f"C3 {gemm}", *_sampled_run("C3", gemm, 24, 31))
     assert ey < tol_y
@@ -88,10 +88,10 @@ def test_c3_sampled_outputs_and_gradients(gemm, tol_y, tol_g):
 def test_c4_sampled_outputs_and_gradients_bf16():
     ey, eg = _report("C4 bf16", *_sampled_run("C4", "bf16", 24, 41))
     assert ey < 3e-2
-    assert eg < 1e-1, eg
+    assert eg < 5e-2, eg
 
 
-@pytest.mark.parametrize("gemm,tol_y,tol_g", [("bf16", 3e-2, 1e-1), ("f32", 1e-4, 1e-4)])
+@pytest.mark.parametrize("gemm,tol_y,tol_g", [("bf16", 3e-2, 5e-2), ("f32", 1e-4, 1e-4)])
 def test_c4_sampled_outputs_and_gradients_tuned_schedule(gemm, tol_y, tol_g):
     """The timed launch configuration: C4 at full size under the schedule
     the autotuner picks, outputs and parameter gradients against the

@@ -114,7 +114,7 @@ def test_host_graph_matches_oracle():
 # ------------------------------------------------------------------ GPU
 
 GPU_POINTS = 6000
-TOL = {"f32": (1e-4, 1e-4), "bf16": (3e-2, 1e-1)}
+TOL = {"f32": (1e-4, 1e-4), "bf16": (3e-2, 5e-2)}
 
 
 @pytest.fixture(scope="module")
@@ -157,5 +157,7 @@ def test_tet_mesh_model_vs_oracle(tet_oracle, H, gemm, R):
     # every row copy against the unpartitioned FP64 value (Eq. 2 and parity)
     assert normwise(Yg, Yo[prob.host.row_gid]) < tol_y
     assert abs(float(loss.detach()) - Lo) / Lo < tol_y
-    for k, t in model.params.items():        # Eq. 3 and parity
-        assert normwise(t.grad.cpu().numpy(), go[k]) < tol_g, k
+    errs = {k: normwise(t.grad.cpu().numpy(), go[k]) for k, t in model.params.items()}  # Eq. 3 and parity
+    worst = max(errs, key=errs.get)
+    print(f"tet mesh {gemm}: worst parameter gradient {errs[worst]:.2e} ({worst})")
+    assert errs[worst] < tol_g, (worst, errs[worst])
