@@ -146,6 +146,35 @@ __device__ __forceinline__ void gemm_f32_tr(const float* __restrict__ frag, cons
   }
 }
 
+// acc += W^T in for an M x K matrix W stored as FP32 fragments (the layout
+// gemm_f32 reads for W in): in holds M features, acc K.  The same
+// transposed addressing as gemm_f32_tr, with the fragment row-block
+// stride of a K-wide matrix (gemm_f32_tr is the case M = K = H).
+template <int M, int K>
+__device__ __forceinline__ void gemm_f32_tr_mk(const float* __restrict__ frag, const float (&in)[M / 4],
+                                               float (&acc)[K / 4], int lane) {
+  constexpr int MB = K / 16, S = K / 4, STEPS = M / 4;
+  const int i = lane & 15, k = lane >> 4;
+  const int lane_off = (i & 3) * 64 + 4 * k + 16 * (i >> 2);
+  v4f c[MB];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb) c[mb] = v4f{acc[4 * mb], acc[4 * mb + 1], acc[4 * mb + 2], acc[4 * mb + 3]};
+#pragma unroll
+  for (int s = 0; s < STEPS; ++s) {
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+      c[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(frag[((s >> 2) * S + 4 * mb) * 64 + (s & 3) + lane_off], in[s],
+                                                   c[mb], 0, 0, 0);
+  }
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb) {
+    acc[4 * mb] = c[mb][0];
+    acc[4 * mb + 1] = c[mb][1];
+    acc[4 * mb + 2] = c[mb][2];
+    acc[4 * mb + 3] = c[mb][3];
+  }
+}
+
 __device__ __forceinline__ v8bf to_bf8(const float* x) {
   v8bf r;
 #pragma unroll
