@@ -262,6 +262,16 @@ __device__ __forceinline__ void stage_frags(uint4* __restrict__ dst, const void*
   const uint4* s = reinterpret_cast<const uint4*>(src);
   for (size_t i = threadIdx.x; i < bytes / 16; i += blockDim.x) dst[i] = s[i];
 }
+// FP32 fragments in the rotated LDS layout (gemm_f32 / gemm_f32_tr with
+// ROT): element o of 64-float chunk c at c*64 + (o + c%4) % 64.
+__device__ __forceinline__ void stage_frags_rot(void* __restrict__ dst, const void* __restrict__ src, size_t bytes) {
+  const float* s = reinterpret_cast<const float*>(src);
+  float* d = reinterpret_cast<float*>(dst);
+  for (size_t e = threadIdx.x; e < bytes / 4; e += blockDim.x) {
+    const size_t c = e >> 6;
+    d[(c << 6) + ((e + (c & 3)) & 63)] = s[e];
+  }
+}
 
 // ----------------------------------------------------------- edge adjoint
 
@@ -280,9 +290,11 @@ struct EdgeBwdCfg {
   // and W2 sit in LDS (the transposed products read them at transposed
   // addresses), and the bias / LayerNorm sums are reduced across the
   // block's lanes (sum16_scatter) into one register per lane, which brings
-  // the kernel to 249 VGPRs and 68 KB of LDS.  Measured on C4: 45.4 ->
+  // the kernel to 245 VGPRs and 68 KB of LDS.  Measured on C4: 45.4 ->
   // 40.6 ms per launch (one wave per SIMD with the next block's rows
-  // loaded ahead had given 47.7 -> 45.4).
+  // loaded ahead had given 47.7 -> 45.4); W1c / W2 in the rotated LDS
+  // layout (stage_frags_rot, no bank conflicts in the transposed reads):
+  // 40.1 -> 37.2 ms.
   static constexpr bool TP = !BF && H == 64;
   static constexpr int MINB = TP ? 2 : 1;
   // BF16: bias / LayerNorm gradients are column sums of staged tiles instead
@@ -342,9 +354,14 @@ __global__ __launch_bounds__((64 * EdgeBwdCfg<H, BF, NWQ>::NW), (EdgeBwdCfg<H, B
   char* tGE = tA1 + C::TB;   // VEC: gE and gE * LN-normalised m, for dbeta / dgamma
   char* tGM = tGE + C::TB;
   const char* fr;
+  // TP's transposed products read W1c / W2 in the rotated layout
+  constexpr bool ROT = TP && C::LDS_FRAG;
   if constexpr (C::LDS_FRAG) {
     uint4* fl = smem + C::STAGE / 16;
-    stage_frags(fl, a.frag, C::NFRAG * C::FB);
+    if constexpr (ROT)
+      stage_frags_rot(fl, a.frag, C::NFRAG * C::FB);
+    else
+      stage_frags(fl, a.frag, C::NFRAG * C::FB);
     fr = reinterpret_cast<const char*>(fl);
   } else {
     fr = reinterpret_cast<const char*>(a.frag);
@@ -446,13 +463,13 @@ __global__ __launch_bounds__((64 * EdgeBwdCfg<H, BF, NWQ>::NW), (EdgeBwdCfg<H, B
       // recompute the forward
 #pragma unroll
       for (int i = 0; i < NF; ++i) u[i] += t[i];
-      gemm<BF, MB, MB>(fW1c, ev, u, lane);
+      gemm<BF, MB, MB, ROT>(fW1c, ev, u, lane);
 #pragma unroll
       for (int i = 0; i < NF; ++i) u[i] = elu(u[i]);
       float mp[NF];
       const float* vb = vecs + opaque_zero();
       load_vec<H>(vb, g, mp);
-      gemm<BF, MB, MB>(fW2, u, mp, lane);
+      gemm<BF, MB, MB, ROT>(fW2, u, mp, lane);
 
       // gradient reaching e'
 #pragma unroll
@@ -513,7 +530,7 @@ __global__ __launch_bounds__((64 * EdgeBwdCfg<H, BF, NWQ>::NW), (EdgeBwdCfg<H, B
 #pragma unroll
       for (int i = 0; i < NF; ++i) t[i] = 0.f;
       if constexpr (TP)
-        gemm_f32_tr<H>(reinterpret_cast<const float*>(fW2), mp, t, lane);
+        gemm_f32_tr<H, ROT>(reinterpret_cast<const float*>(fW2), mp, t, lane);
       else
         gemm<BF, MB, MB>(fW2t, mp, t, lane);
 #pragma unroll
@@ -532,7 +549,7 @@ __global__ __launch_bounds__((64 * EdgeBwdCfg<H, BF, NWQ>::NW), (EdgeBwdCfg<H, B
       }
       // g_e = gE + W1c^T gh
       if constexpr (TP)
-        gemm_f32_tr<H>(reinterpret_cast<const float*>(fW1c), t, gE, lane);
+        gemm_f32_tr<H, ROT>(reinterpret_cast<const float*>(fW1c), t, gE, lane);
       else
         gemm<BF, MB, MB>(fW1ct, t, gE, lane);
       if (valid) {
@@ -697,10 +714,15 @@ template <int H, bool BF, bool AM>
 __global__ __launch_bounds__((64 * EdgeBwdSplitCfg<H, BF>::NW)) void k_edge_bwd_split(EdgeBwdArgs a) {
   using C = EdgeBwdSplitCfg<H, BF>;
   constexpr int NF = H / 4, MB = H / 16, NW = C::NW;
+  // FP32: the transposed products read W1c / W2 in the rotated layout
+  constexpr bool ROT = !BF && C::LDS_FRAG;
   extern __shared__ uint4 smem[];
   const char* fr;
   if constexpr (C::LDS_FRAG) {
-    stage_frags(smem, a.frag, C::NFR * C::FB);
+    if constexpr (ROT)
+      stage_frags_rot(smem, a.frag, C::NFR * C::FB);
+    else
+      stage_frags(smem, a.frag, C::NFR * C::FB);
     fr = reinterpret_cast<const char*>(smem);
   } else {
     fr = reinterpret_cast<const char*>(a.frag);
@@ -761,14 +783,14 @@ __global__ __launch_bounds__((64 * EdgeBwdSplitCfg<H, BF>::NW)) void k_edge_bwd_
       // recompute the forward
 #pragma unroll
       for (int i = 0; i < NF; ++i) u[i] += t[i];
-      gemm<BF, MB, MB>(fW1c, ev, u, lane);
+      gemm<BF, MB, MB, ROT>(fW1c, ev, u, lane);
 #pragma unroll
       for (int i = 0; i < NF; ++i) u[i] = elu(u[i]);
       if (valid) store_row_t<H, BF>(a.u, k, g, u);
       float mp[NF];
       const float* vb = vecs + opaque_zero();
       load_vec<H>(vb, g, mp);
-      gemm<BF, MB, MB>(fW2, u, mp, lane);
+      gemm<BF, MB, MB, ROT>(fW2, u, mp, lane);
       // gradient reaching e'
       if (a.g_e_out) {
         load_row<H>(a.g_e_out + kk * H, g, t);
@@ -816,7 +838,7 @@ __global__ __launch_bounds__((64 * EdgeBwdSplitCfg<H, BF>::NW)) void k_edge_bwd_
 #pragma unroll
       for (int i = 0; i < NF; ++i) t[i] = 0.f;
       if constexpr (!BF && C::LDS_FRAG)
-        gemm_f32_tr<H>(reinterpret_cast<const float*>(fW2), mp, t, lane);
+        gemm_f32_tr<H, ROT>(reinterpret_cast<const float*>(fW2), mp, t, lane);
       else
         gemm<BF, MB, MB>(fW2t, mp, t, lane);
 #pragma unroll
@@ -831,7 +853,7 @@ __global__ __launch_bounds__((64 * EdgeBwdSplitCfg<H, BF>::NW)) void k_edge_bwd_
       }
       // g_e = gE + W1c^T gh
       if constexpr (!BF && C::LDS_FRAG)
-        gemm_f32_tr<H>(reinterpret_cast<const float*>(fW1c), t, gE, lane);
+        gemm_f32_tr<H, ROT>(reinterpret_cast<const float*>(fW1c), t, gE, lane);
       else
         gemm<BF, MB, MB>(fW1ct, t, gE, lane);
       if (valid) {
@@ -1376,6 +1398,9 @@ __global__ __launch_bounds__((64 * MlpBwdCfg<H, KIN, TIN, TOUT, BF>::NW)) void k
   constexpr int NF = H / 4, MB = H / 16, KB = TIN ? 1 : KIN / 16, AW0 = C::AW0, NW = C::NW, ROWS = C::ROWS;
   constexpr int NT1 = TOUT ? dw_tiles_per_wave<16, H, NW>() : dw_tiles_per_wave<H, H, NW>();
   constexpr int NT0 = dw_tiles_per_wave<H, AW0, NW>();
+  // FP32 transposed products (TR1 / TR0) read W0 / W1 in the rotated
+  // layout; W1^T / W0^T copies, where staged, keep the packed one
+  constexpr bool ROT = !BF && (C::TR1 || C::TR0) && C::LDS_FRAG;
   extern __shared__ uint4 smem[];
   char* tG = reinterpret_cast<char*>(smem);
   char* tA = tG + C::TB;
@@ -1386,8 +1411,13 @@ __global__ __launch_bounds__((64 * MlpBwdCfg<H, KIN, TIN, TOUT, BF>::NW)) void k
   const char* fr;
   if constexpr (C::LDS_FRAG) {
     uint4* fl = smem + C::STAGE / 16;
-    stage_frags(fl, a.frag0, C::F0);
-    stage_frags(fl + C::F0 / 16, a.frag1, C::F1);
+    if constexpr (ROT) {
+      stage_frags_rot(fl, a.frag0, C::F0);
+      stage_frags_rot(fl + C::F0 / 16, a.frag1, C::F1);
+    } else {
+      stage_frags(fl, a.frag0, C::F0);
+      stage_frags(fl + C::F0 / 16, a.frag1, C::F1);
+    }
     if constexpr (!C::TR1) stage_frags(fl + (C::F0 + C::F1) / 16, a.frag1t, C::F1);
     if constexpr (!C::TR0)
       if (a.frag0t) stage_frags(fl + (C::F0 + C::F1 + C::F1T) / 16, a.frag0t, C::F0);
@@ -1487,7 +1517,7 @@ __global__ __launch_bounds__((64 * MlpBwdCfg<H, KIN, TIN, TOUT, BF>::NW)) void k
     if constexpr (TIN) {
       small_in_linear<H>(small + oz, cur.in, g, z);
     } else {
-      gemm<BF, MB, KB>(f0, cur.in, z, lane);
+      gemm<BF, MB, KB, ROT>(f0, cur.in, z, lane);
     }
     // the input tile for dW0: staged now when it has its own region
     auto stage_in = [&]() {
@@ -1535,7 +1565,7 @@ __global__ __launch_bounds__((64 * MlpBwdCfg<H, KIN, TIN, TOUT, BF>::NW)) void k
     } else {
       float y[NF];
       load_vec<H>(vb + H, g, y);
-      gemm<BF, MB, MB>(f1, u, y, lane);
+      gemm<BF, MB, MB, ROT>(f1, u, y, lane);
       const float* go = cur.go;
       if (a.ln) {
         float mean, rstd, s1 = 0.f, s2 = 0.f, gam[NF];
@@ -1595,7 +1625,7 @@ __global__ __launch_bounds__((64 * MlpBwdCfg<H, KIN, TIN, TOUT, BF>::NW)) void k
 #pragma unroll
       for (int i = 0; i < NF; ++i) gu[i] = 0.f;
       if constexpr (C::TR1)
-        gemm_f32_tr<H>(reinterpret_cast<const float*>(f1), y, gu, lane);
+        gemm_f32_tr<H, ROT>(reinterpret_cast<const float*>(f1), y, gu, lane);
       else
         gemm<BF, MB, MB>(f1t, y, gu, lane);
     }
@@ -1624,7 +1654,7 @@ __global__ __launch_bounds__((64 * MlpBwdCfg<H, KIN, TIN, TOUT, BF>::NW)) void k
 #pragma unroll
         for (int i = 0; i < KIN / 4; ++i) gi[i] = 0.f;
         if constexpr (C::TR0)
-          gemm_f32_tr_mk<H, KIN>(reinterpret_cast<const float*>(f0), gu, gi, lane);
+          gemm_f32_tr_mk<H, KIN, ROT>(reinterpret_cast<const float*>(f0), gu, gi, lane);
         else
           gemm<BF, KIN / 16, MB>(f0t, gu, gi, lane);
         if constexpr (KIN == 2 * H) {

@@ -93,7 +93,10 @@ __device__ __forceinline__ void load_vec(const float* __restrict__ p, int g, flo
 // acc[f] += sum_k A[f][k] in[k]  (A packed as FP32 fragments; MB = M/16,
 // KB = K/16).  Independent output blocks are interleaved so consecutive
 // MFMAs do not depend on each other.
-template <int MB, int KB>
+// ROT: the fragments sit in LDS in the rotated layout of stage_frags_rot
+// (element o of 64-float chunk c at c*64 + (o + c%4) % 64); chunk
+// mb*4KB + s has c%4 = s%4.
+template <int MB, int KB, bool ROT = false>
 __device__ __forceinline__ void gemm_f32(const float* __restrict__ frag, const float (&in)[4 * KB],
                                          float (&acc)[4 * MB], int lane) {
   v4f c[MB];
@@ -101,9 +104,10 @@ __device__ __forceinline__ void gemm_f32(const float* __restrict__ frag, const f
   for (int mb = 0; mb < MB; ++mb) c[mb] = v4f{acc[4 * mb], acc[4 * mb + 1], acc[4 * mb + 2], acc[4 * mb + 3]};
 #pragma unroll
   for (int s = 0; s < 4 * KB; ++s) {
+    const int l = ROT ? ((lane + (s & 3)) & 63) : lane;
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
-      c[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(frag[(mb * 4 * KB + s) * 64 + lane], in[s], c[mb], 0, 0, 0);
+      c[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(frag[(mb * 4 * KB + s) * 64 + l], in[s], c[mb], 0, 0, 0);
   }
 #pragma unroll
   for (int mb = 0; mb < MB; ++mb) {
@@ -120,22 +124,27 @@ __device__ __forceinline__ void gemm_f32(const float* __restrict__ frag, const f
 // feature order of the row-block layout; W^T's element for step s, output
 // block mb' and lane (i, k) is W[f(s, k)][16 mb' + i], found at fragment
 // (s/4, 4 mb' + i%4, lane 4k + s%4 + 16 (i/4)).  One LDS read per MFMA as
-// in gemm_f32, so the transposed matrix need not be stored.
-template <int H>
+// in gemm_f32, so the transposed matrix need not be stored.  In the packed
+// layout the 64 lanes of one read reach only 16 LDS banks (lanes with equal
+// i/4 and k but different i%4 read the same bank of four fragments); in the
+// rotated layout (ROT) they reach 64 distinct banks.
+template <int H, bool ROT = false>
 __device__ __forceinline__ void gemm_f32_tr(const float* __restrict__ frag, const float (&in)[H / 4],
                                             float (&acc)[H / 4], int lane) {
   constexpr int MB = H / 16, S = H / 4;
   const int i = lane & 15, k = lane >> 4;
-  const int lane_off = (i & 3) * 64 + 4 * k + 16 * (i >> 2);
   v4f c[MB];
 #pragma unroll
   for (int mb = 0; mb < MB; ++mb) c[mb] = v4f{acc[4 * mb], acc[4 * mb + 1], acc[4 * mb + 2], acc[4 * mb + 3]};
 #pragma unroll
   for (int s = 0; s < S; ++s) {
+    // fragment (s/4) S + 4 mb + i%4 (its chunk index is i%4 mod 4), element s%4 + 4k + 16 (i/4)
+    const int o = (s & 3) + 4 * k + 16 * (i >> 2);
+    const int lane_off = (i & 3) * 64 + (ROT ? ((o + (i & 3)) & 63) : o);
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
-      c[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(frag[((s >> 2) * S + 4 * mb) * 64 + (s & 3) + lane_off], in[s],
-                                                   c[mb], 0, 0, 0);
+      c[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(frag[((s >> 2) * S + 4 * mb) * 64 + lane_off], in[s], c[mb], 0,
+                                                   0, 0);
   }
 #pragma unroll
   for (int mb = 0; mb < MB; ++mb) {
@@ -150,21 +159,22 @@ __device__ __forceinline__ void gemm_f32_tr(const float* __restrict__ frag, cons
 // gemm_f32 reads for W in): in holds M features, acc K.  The same
 // transposed addressing as gemm_f32_tr, with the fragment row-block
 // stride of a K-wide matrix (gemm_f32_tr is the case M = K = H).
-template <int M, int K>
+template <int M, int K, bool ROT = false>
 __device__ __forceinline__ void gemm_f32_tr_mk(const float* __restrict__ frag, const float (&in)[M / 4],
                                                float (&acc)[K / 4], int lane) {
   constexpr int MB = K / 16, S = K / 4, STEPS = M / 4;
   const int i = lane & 15, k = lane >> 4;
-  const int lane_off = (i & 3) * 64 + 4 * k + 16 * (i >> 2);
   v4f c[MB];
 #pragma unroll
   for (int mb = 0; mb < MB; ++mb) c[mb] = v4f{acc[4 * mb], acc[4 * mb + 1], acc[4 * mb + 2], acc[4 * mb + 3]};
 #pragma unroll
   for (int s = 0; s < STEPS; ++s) {
+    const int o = (s & 3) + 4 * k + 16 * (i >> 2);
+    const int lane_off = (i & 3) * 64 + (ROT ? ((o + (i & 3)) & 63) : o);
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
-      c[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(frag[((s >> 2) * S + 4 * mb) * 64 + (s & 3) + lane_off], in[s],
-                                                   c[mb], 0, 0, 0);
+      c[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(frag[((s >> 2) * S + 4 * mb) * 64 + lane_off], in[s], c[mb], 0,
+                                                   0, 0);
   }
 #pragma unroll
   for (int mb = 0; mb < MB; ++mb) {
@@ -210,12 +220,13 @@ __device__ __forceinline__ void gemm_bf16(const uint4* __restrict__ frag, const 
 
 // Dispatch on the GEMM operand type.  frag points at the fragments of one
 // matrix (FP32: M*K floats; BF16: M*K bf16 values).
-template <bool BF, int MB, int KB>
+template <bool BF, int MB, int KB, bool ROT = false>
 __device__ __forceinline__ void gemm(const void* frag, const float (&in)[4 * KB], float (&acc)[4 * MB], int lane) {
+  static_assert(!(BF && ROT), "the rotated layout is an FP32 fragment layout");
   if constexpr (BF)
     gemm_bf16<MB, KB>(reinterpret_cast<const uint4*>(frag), in, acc, lane);
   else
-    gemm_f32<MB, KB>(reinterpret_cast<const float*>(frag), in, acc, lane);
+    gemm_f32<MB, KB, ROT>(reinterpret_cast<const float*>(frag), in, acc, lane);
 }
 
 // Bytes of the packed fragments of an M x K matrix.
