@@ -1149,12 +1149,18 @@ struct GqRaw {
 
 template <int H, bool BF>
 struct GqCfg {
+  // FP32 at H = 64: the staging tiles and fragments (84 KB at four waves)
+  // leave room for one workgroup per CU, so it has eight waves (two per
+  // SIMD, 133 KB); otherwise four waves and two workgroups per CU at H <= 64
+  static constexpr int NW = (!BF && H == 64) ? 8 : 4;
+  static constexpr int ROWS = 16 * NW;
+  static constexpr int MINB = NW == 8 ? 1 : (H <= 64 ? 2 : 1);
   static constexpr size_t FB = frag_bytes(H, 2 * H, BF);
   // FP32 at H = 128: the weight-gradient tiles and accumulators do not fit
   // beside the gather; the kernel writes g_Q per node instead and the weight
   // gradients are summed from g_P, g_Q and x by launch_row_dw.
   static constexpr bool SPLIT = gq_split(H, BF);
-  static constexpr size_t STAGE = SPLIT ? 0 : tile_bytes<2 * H, BF>() + tile_bytes<H, BF>();
+  static constexpr size_t STAGE = SPLIT ? 0 : tile_bytes<2 * H, BF, ROWS>() + tile_bytes<H, BF, ROWS>();
   static constexpr bool LDS_FRAG = FB + STAGE <= kLdsLimit;
   static constexpr size_t LDS = STAGE + (LDS_FRAG ? FB : 0);
 };
@@ -1164,16 +1170,16 @@ struct GqCfg {
 //   g_x[j] += W1a^T g_P[j] + W1b^T g_Q[j]
 //   dW1a += g_P x^T, dW1b += g_Q x^T, db1 += g_P.
 template <int H, bool BF>
-__global__ __launch_bounds__(256, (H <= 64 ? 2 : 1)) void k_gq(GqArgs a) {
+__global__ __launch_bounds__((64 * GqCfg<H, BF>::NW), (GqCfg<H, BF>::MINB)) void k_gq(GqArgs a) {
   using C = GqCfg<H, BF>;
-  constexpr int NF = H / 4, MB = H / 16, NT = dw_tiles_per_wave<2 * H, H>();
+  constexpr int NF = H / 4, MB = H / 16, NW = C::NW, ROWS = C::ROWS, NT = dw_tiles_per_wave<2 * H, H, NW>();
   // edges gathered per round trip: as many raw rows as fit in 48 registers
   // (6 at H=64 in BF16, the lattice's largest degree), at least 2, at most 8
   constexpr int RAWREG = BF ? H / 8 : H / 4;
   constexpr int GQ_CH = 48 / RAWREG < 2 ? 2 : (48 / RAWREG > 8 ? 8 : 48 / RAWREG);
   extern __shared__ uint4 smem[];
   char* tG = reinterpret_cast<char*>(smem);
-  char* tA = tG + (C::SPLIT ? 0 : tile_bytes<2 * H, BF>());
+  char* tA = tG + (C::SPLIT ? 0 : tile_bytes<2 * H, BF, ROWS>());
   const char* fr;
   if constexpr (C::LDS_FRAG) {
     uint4* fl = smem + C::STAGE / 16;
@@ -1186,10 +1192,10 @@ __global__ __launch_bounds__(256, (H <= 64 ? 2 : 1)) void k_gq(GqArgs a) {
   const DevGraph& gr = a.g;
   const int lane = lane_id(), j = lane & 15, g = lane >> 4, wave = threadIdx.x / 64;
   const int64_t n = gr.n_rows, nblk = (n + 15) / 16;
-  // contiguous row blocks per workgroup, 4 blocks (one per wave) per step
+  // contiguous row blocks per workgroup, NW blocks (one per wave) per step
   const int64_t per = (nblk + gridDim.x - 1) / gridDim.x;
   const int64_t b0 = blockIdx.x * per, b1 = std::min(nblk, b0 + per);
-  const int64_t n_iter = (b1 - b0 + kWaves - 1) / kWaves;
+  const int64_t n_iter = (b1 - b0 + NW - 1) / NW;
   v4f acc[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
@@ -1210,13 +1216,13 @@ __global__ __launch_bounds__(256, (H <= 64 ? 2 : 1)) void k_gq(GqArgs a) {
   }
 
   for (int64_t it = 0; it < n_iter; ++it) {
-    const int64_t bk = b0 + it * kWaves + wave;
+    const int64_t bk = b0 + it * NW + wave;
     const int64_t row = bk * 16 + j;
     const bool valid = bk < b1 && row < n;
     const int64_t rr = valid ? row : n - 1;
     const int p0 = p0_n, deg = p1_n - p0_n;
     {
-      const int64_t bk2 = bk + kWaves, row2 = bk2 * 16 + j;
+      const int64_t bk2 = bk + NW, row2 = bk2 * 16 + j;
       const int64_t rr2 = (bk2 < b1 && row2 < n) ? row2 : n - 1;
       p0_n = gr.rowptr[rr2];
       p1_n = gr.rowptr[rr2 + 1];
@@ -1263,18 +1269,18 @@ __global__ __launch_bounds__(256, (H <= 64 ? 2 : 1)) void k_gq(GqArgs a) {
     }
 #pragma unroll
     for (int i = 0; i < NF; ++i) db1[i] += in[i];
-    stage_row<2 * H, BF>(tG, wave * 16 + j, g, in);
-    stage_row<H, BF>(tA, wave * 16 + j, g, xv);
+    stage_row<2 * H, BF, ROWS>(tG, wave * 16 + j, g, in);
+    stage_row<H, BF, ROWS>(tA, wave * 16 + j, g, xv);
     gemm<BF, MB, 2 * MB>(fr, in, gx, lane);
     if (valid) store_row<H>(a.g_x + row * H, g, gx);
     __syncthreads();
-    dw_tiles<2 * H, H, BF>(tG, tA, acc, wave, lane);
+    dw_tiles<2 * H, H, BF, NW>(tG, tA, acc, wave, lane);
     __syncthreads();
   }
   if constexpr (!C::SPLIT) {
     float* slab = a.part + blockIdx.x * a.slab;
-    dw_store<2 * H, H>(acc, slab, H, wave, lane);
-    block_sum_vec<H>(db1, reinterpret_cast<float*>(tG), slab + 2 * H * H, wave, lane);
+    dw_store<2 * H, H, NW>(acc, slab, H, wave, lane);
+    block_sum_vec<H, NW>(db1, reinterpret_cast<float*>(tG), slab + 2 * H * H, wave, lane);
   }
 }
 
@@ -1282,7 +1288,7 @@ template <int H, bool BF>
 static hipError_t launch_gq_t(const GqArgs& a, int grid, hipStream_t s) {
   using C = GqCfg<H, BF>;
   (void)hipFuncSetAttribute((const void*)k_gq<H, BF>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)C::LDS);
-  hipLaunchKernelGGL((k_gq<H, BF>), dim3(grid), dim3(256), C::LDS, s, a);
+  hipLaunchKernelGGL((k_gq<H, BF>), dim3(grid), dim3(64 * C::NW), C::LDS, s, a);
   return hipGetLastError();
 }
 
