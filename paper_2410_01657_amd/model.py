@@ -5,6 +5,9 @@ message-passing layers (Eq. 4a-e), node decoder MLP (H -> 3), and the
 consistent MSE (Eq. 6).  Every piece runs through libmplayer.so.
 """
 
+import dataclasses
+import json
+
 import numpy as np
 import torch
 
@@ -34,6 +37,31 @@ def _mlp_param_names(prefix, ln):
     return names
 
 
+def save_checkpoint(path, params, spec, **meta):
+    """Write a model to an .npz file that loads without unpickling: every
+    parameter (name -> FP32 array, bitwise as held), the model description
+    (the fields of the spec dataclass) and free-form metadata such as seeds,
+    step counts or the learning rate, both as JSON text."""
+    arrays = {}
+    for k, v in params.items():
+        t = v.detach().cpu().numpy() if isinstance(v, torch.Tensor) else np.asarray(v)
+        arrays["param/" + k] = np.ascontiguousarray(t, dtype=np.float32)
+    spec_fields = dataclasses.asdict(spec) if dataclasses.is_dataclass(spec) else dict(spec)
+    arrays["spec"] = np.frombuffer(json.dumps(spec_fields, sort_keys=True).encode(), dtype=np.uint8)
+    arrays["meta"] = np.frombuffer(json.dumps(meta, sort_keys=True).encode(), dtype=np.uint8)
+    np.savez(path, **arrays)
+
+
+def load_checkpoint(path):
+    """Read a file written by save_checkpoint: (params as name -> FP32
+    array, spec fields as a dict, metadata as a dict)."""
+    with np.load(path, allow_pickle=False) as z:
+        params = {k[len("param/"):]: z[k].copy() for k in z.files if k.startswith("param/")}
+        spec_fields = json.loads(z["spec"].tobytes().decode())
+        meta = json.loads(z["meta"].tobytes().decode())
+    return params, spec_fields, meta
+
+
 class ConsistentGNN:
     """Parameters live in ``self.params`` (name -> device tensor, FP32)."""
 
@@ -54,6 +82,12 @@ class ConsistentGNN:
         self.device = torch.device(device)
         self.params = {k: torch.as_tensor(np.asarray(v), dtype=torch.float32).to(self.device).contiguous()
                        for k, v in params.items()}
+
+    def save(self, path, **meta):
+        """Checkpoint the parameters, the spec and `meta` (see
+        save_checkpoint); ConsistentGNN(spec, load_checkpoint(path)[0], ...)
+        resumes from it."""
+        save_checkpoint(path, self.params, self.spec, gemm=self.gemm, **meta)
 
     def requires_grad_(self, flag=True):
         for t in self.params.values():
