@@ -283,14 +283,15 @@ struct EdgeBwdCfg {
   // waves.  NWQ (4 or 8) overrides it (a schedule dimension).
   static constexpr int NW = NWQ ? NWQ : ((BF && H <= 64) ? 8 : 4);
   static constexpr int ROWS = 16 * NW;
-  // TP (FP32 at H = 64): two workgroups per CU, so two waves per SIMD (the
-  // VALU phases between one wave's products overlap the other wave's
-  // matrix work; with one wave per SIMD they could not): the weight-gradient
-  // factors are staged in two rounds through one pair of tiles, only W1c
-  // and W2 sit in LDS (the transposed products read them at transposed
-  // addresses), and the bias / LayerNorm sums are reduced across the
-  // block's lanes (sum16_scatter) into one register per lane, which brings
-  // the kernel to 245 VGPRs and 68 KB of LDS.  Measured on C4: 45.4 ->
+  // TP (FP32 at H = 64): two workgroups per CU, so two waves per SIMD (one
+  // wave's memory and LDS waits and barriers are covered by the other
+  // wave's work; FP32 matrix instructions do not issue beside VALU ones, so
+  // the gain is in the waits): the weight-gradient factors are staged in
+  // two rounds through one pair of tiles, only W1c and W2 sit in LDS (the
+  // transposed products read them at transposed addresses), db2 is a
+  // column sum of the staged gm tile and the LayerNorm-parameter sums are
+  // reduced across the block's lanes (sum16_scatter) into one register per
+  // lane, which brings the kernel to 245 VGPRs and 68 KB of LDS.  Measured on C4: 45.4 ->
   // 40.6 ms per launch (one wave per SIMD with the next block's rows
   // loaded ahead had given 47.7 -> 45.4); W1c / W2 in the rotated LDS
   // layout (stage_frags_rot, no bank conflicts in the transposed reads):
@@ -517,9 +518,7 @@ __global__ __launch_bounds__((64 * EdgeBwdCfg<H, BF, NWQ>::NW), (EdgeBwdCfg<H, B
         for (int i = 0; i < NF; ++i) mp[i] = gE[i];
       }
       if constexpr (TP) {
-        float rs[1];
-        sum16_scatter<NF>(mp, rs, j);
-        db2[0] += rs[0];
+        // db2: column sums of the staged gm tile after the first barrier
       } else if constexpr (!C::VEC) {
 #pragma unroll
         for (int i = 0; i < NF; ++i) db2[i] += mp[i];
@@ -534,7 +533,7 @@ __global__ __launch_bounds__((64 * EdgeBwdCfg<H, BF, NWQ>::NW), (EdgeBwdCfg<H, B
       else
         gemm<BF, MB, MB>(fW2t, mp, t, lane);
 #pragma unroll
-      for (int i = 0; i < NF; ++i) t[i] *= (u[i] > 0.f ? 1.f : u[i] + 1.f);
+      for (int i = 0; i < NF; ++i) t[i] *= elu_deriv_from_value(u[i]);
       if constexpr (!TP) {
         stage_row<H, BF, ROWS>(tG1, srow, g, t);
         stage_row<H, BF, ROWS>(tA1, srow, g, ev);
@@ -560,16 +559,28 @@ __global__ __launch_bounds__((64 * EdgeBwdCfg<H, BF, NWQ>::NW), (EdgeBwdCfg<H, B
           store_row<H>(reinterpret_cast<float*>(a.g_h) + k * H, g, t);
       }
       if constexpr (TP) {
-        // round 1: dW2 from the staged (gm, u); then the same tiles take (gh, e)
+        // round 1: dW2 and db2 from the staged (gm, u); then the same tiles
+        // take (gh, e).  db2: lane = feature (H = 64), wave w adds the staged
+        // rows 16w .. 16w+15 (four 16-byte LDS reads, conflict-free).
         __syncthreads();
         dw_tiles<H, H, BF, NW>(tG2, tA2, acc2, wave, lane);
+        {
+          const float* col = reinterpret_cast<const float*>(tG2) + lane * Stg<BF, ROWS>::RS + 16 * wave;
+          float s = 0.f;
+#pragma unroll
+          for (int r = 0; r < 16; r += 4) {
+            const float4 q = *reinterpret_cast<const float4*>(col + r);
+            s += ((q.x + q.y) + q.z) + q.w;
+          }
+          db2[0] += s;
+        }
         __syncthreads();
         stage_row<H, BF, ROWS>(tG1, srow, g, t);
         stage_row<H, BF, ROWS>(tA1, srow, g, ev);
       }
-      // g_P: segmented sum of gh per receiver
-#pragma unroll
-      for (int i = 0; i < NF; ++i) t[i] = valid ? t[i] : 0.f;
+      // g_P: segmented sum of gh per receiver.  Lanes past the tile's last
+      // edge hold gh = 0 (their gE is zeroed, so are gm and W2^T gm) and a
+      // key of their own, so they add nothing to any row's sum.
       if (j == 0 && key == carry_key) {
 #pragma unroll
         for (int i = 0; i < NF; i += 4) {
@@ -616,8 +627,9 @@ __global__ __launch_bounds__((64 * EdgeBwdCfg<H, BF, NWQ>::NW), (EdgeBwdCfg<H, B
     cs_ga.store(scratch, slab + 2 * H * H + H, wave, lane);
     cs_be.store(scratch, slab + 2 * H * H + 2 * H, wave, lane);
   } else if constexpr (TP) {
-    // lane j of group g holds feature 16 (j / 4) + 4 g + j % 4 (H = 64: one
-    // value per lane after the reduce-scatter); waves added in order
+    // db2: lane l holds feature l (column sums of the staged gm); dgamma,
+    // dbeta: lane j of group g holds feature 16 (j / 4) + 4 g + j % 4 (H =
+    // 64: one value per lane after the reduce-scatter); waves added in order
     __syncthreads();
     scratch[(wave * 64 + lane) * 3 + 0] = db2[0];
     scratch[(wave * 64 + lane) * 3 + 1] = dga[0];
@@ -625,7 +637,7 @@ __global__ __launch_bounds__((64 * EdgeBwdCfg<H, BF, NWQ>::NW), (EdgeBwdCfg<H, B
     __syncthreads();
     for (int t = threadIdx.x; t < 3 * H; t += blockDim.x) {
       const int v = t / H, f = t % H;
-      const int l = (4 * (f / 16) + f % 4) + 16 * ((f % 16) / 4);
+      const int l = v == 0 ? f : (4 * (f / 16) + f % 4) + 16 * ((f % 16) / 4);
       float sum = 0.f;
       for (int w = 0; w < NW; ++w) sum += scratch[(w * 64 + l) * 3 + v];
       slab[2 * H * H + v * H + f] = sum;
@@ -842,7 +854,7 @@ __global__ __launch_bounds__((64 * EdgeBwdSplitCfg<H, BF>::NW)) void k_edge_bwd_
       else
         gemm<BF, MB, MB>(fW2t, mp, t, lane);
 #pragma unroll
-      for (int i = 0; i < NF; ++i) t[i] *= (u[i] > 0.f ? 1.f : u[i] + 1.f);
+      for (int i = 0; i < NF; ++i) t[i] *= elu_deriv_from_value(u[i]);
       if constexpr (AM) {  // residual path: the next layer's gradient only
         if (a.g_e_out) {
           load_row<H>(a.g_e_out + kk * H, g, gE);
@@ -860,9 +872,8 @@ __global__ __launch_bounds__((64 * EdgeBwdSplitCfg<H, BF>::NW)) void k_edge_bwd_
         store_row<H>(a.g_e_in + k * H, g, gE);
         store_row_t<H, BF>(a.g_h, k, g, t);
       }
-      // g_P: segmented sum of gh per receiver (carry through LDS)
-#pragma unroll
-      for (int i = 0; i < NF; ++i) t[i] = valid ? t[i] : 0.f;
+      // g_P: segmented sum of gh per receiver (carry through LDS); lanes
+      // past the tile's last edge hold gh = 0 (gE zeroed) and a key of their own
       if (j == 0 && key == carry_key) {
 #pragma unroll
         for (int i = 0; i < NF; i += 4) {
@@ -1176,7 +1187,8 @@ __global__ __launch_bounds__((64 * GqCfg<H, BF>::NW), (GqCfg<H, BF>::MINB)) void
   // edges gathered per round trip: as many raw rows as fit in 48 registers
   // (6 at H=64 in BF16, the lattice's largest degree), at least 2, at most 8
   constexpr int RAWREG = BF ? H / 8 : H / 4;
-  constexpr int GQ_CH = 48 / RAWREG < 2 ? 2 : (48 / RAWREG > 8 ? 8 : 48 / RAWREG);
+  constexpr int RAWBUD = (!BF && H == 64) ? 96 : 48;
+  constexpr int GQ_CH = RAWBUD / RAWREG < 2 ? 2 : (RAWBUD / RAWREG > 8 ? 8 : RAWBUD / RAWREG);
   extern __shared__ uint4 smem[];
   char* tG = reinterpret_cast<char*>(smem);
   char* tA = tG + (C::SPLIT ? 0 : tile_bytes<2 * H, BF, ROWS>());
@@ -1637,7 +1649,7 @@ __global__ __launch_bounds__((64 * MlpBwdCfg<H, KIN, TIN, TOUT, BF>::NW)) void k
     }
     // ---- gradient at z; phase 0: dW0, db0
 #pragma unroll
-    for (int i = 0; i < NF; ++i) gu[i] *= (u[i] > 0.f ? 1.f : u[i] + 1.f);
+    for (int i = 0; i < NF; ++i) gu[i] *= elu_deriv_from_value(u[i]);
     if constexpr (C::TP) {
       float rs[1];  // rows past n: go = 0, so gu = 0
       sum16_scatter<NF>(gu, rs, j);
@@ -1880,7 +1892,7 @@ __global__ __launch_bounds__((64 * NodeBwdSplitCfg<H, BF>::NW)) void k_node_bwd_
     for (int i = 0; i < NF; ++i) gu[i] = 0.f;
     gemm<BF, MB, MB>(f1t + oz, y, gu, lane);
 #pragma unroll
-    for (int i = 0; i < NF; ++i) gu[i] *= (u[i] > 0.f ? 1.f : u[i] + 1.f);
+    for (int i = 0; i < NF; ++i) gu[i] *= elu_deriv_from_value(u[i]);
     if (valid) store_row_t<H, BF>(gz_out, row, g, gu);
   }
 }

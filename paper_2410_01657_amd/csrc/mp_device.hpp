@@ -248,6 +248,10 @@ __device__ __forceinline__ int opaque_zero() {
 // at most ~1e-7 in absolute terms for z <= 0, far below FP32 tolerances.
 __device__ __forceinline__ float elu(float z) { return z > 0.f ? z : __expf(z) - 1.f; }
 __device__ __forceinline__ float elu_deriv(float z) { return z > 0.f ? 1.f : __expf(z); }
+// ELU'(h) from u = ELU(h): 1 for h > 0, else exp(h) = u + 1.  u > 0 exactly
+// when h > 0, and then u + 1 >= 1, so min(u + 1, 1) is the same value in
+// two instructions instead of four.
+__device__ __forceinline__ float elu_deriv_from_value(float u) { return fminf(u + 1.f, 1.f); }
 
 // Sum over the four lanes that share a row (lane groups g = 0..3), on the
 // matrix unit: v_mfma_f32_16x16x4f32 with A = 1 and B[k][j] = the value of
