@@ -511,8 +511,10 @@ __global__ __launch_bounds__((64 * EdgeBwdCfg<H, BF, NWQ>::NW), (EdgeBwdCfg<H, B
         }
         s1 = row_sum(s1) * (1.f / H);
         s2 = row_sum(s2) * (1.f / H);
+        // rstd (gE gam - s1 - x^ s2) as two multiply-adds per feature
+        const float c1 = -rstd * s1, c2 = -rstd * s2;
 #pragma unroll
-        for (int i = 0; i < NF; ++i) mp[i] = rstd * (gE[i] * gam[i] - s1 - mp[i] * s2);
+        for (int i = 0; i < NF; ++i) mp[i] = fmaf(mp[i], c2, fmaf(gE[i] * gam[i], rstd, c1));
       } else {
 #pragma unroll
         for (int i = 0; i < NF; ++i) mp[i] = gE[i];
@@ -839,8 +841,10 @@ __global__ __launch_bounds__((64 * EdgeBwdSplitCfg<H, BF>::NW)) void k_edge_bwd_
         }
         s1 = row_sum(s1) * (1.f / H);
         s2 = row_sum(s2) * (1.f / H);
+        // rstd (gE gam - s1 - x^ s2) as two multiply-adds per feature
+        const float c1 = -rstd * s1, c2 = -rstd * s2;
 #pragma unroll
-        for (int i = 0; i < NF; ++i) mp[i] = rstd * (gE[i] * gam[i] - s1 - mp[i] * s2);
+        for (int i = 0; i < NF; ++i) mp[i] = fmaf(mp[i], c2, fmaf(gE[i] * gam[i], rstd, c1));
       } else {
 #pragma unroll
         for (int i = 0; i < NF; ++i) mp[i] = gE[i];
@@ -1619,8 +1623,9 @@ __global__ __launch_bounds__((64 * MlpBwdCfg<H, KIN, TIN, TOUT, BF>::NW)) void k
         }
         s1 = row_sum(s1) * (1.f / H);
         s2 = row_sum(s2) * (1.f / H);
+        const float c1 = -rstd * s1, c2 = -rstd * s2;
 #pragma unroll
-        for (int i = 0; i < NF; ++i) y[i] = rstd * (go[i] * gam[i] - s1 - y[i] * s2);
+        for (int i = 0; i < NF; ++i) y[i] = fmaf(y[i], c2, fmaf(go[i] * gam[i], rstd, c1));
       } else {
 #pragma unroll
         for (int i = 0; i < NF; ++i) y[i] = go[i];
@@ -1880,8 +1885,9 @@ __global__ __launch_bounds__((64 * NodeBwdSplitCfg<H, BF>::NW)) void k_node_bwd_
       if (valid) store_row_t<H, BF>(goxh_out, row, g, t);
       s1 = row_sum(s1) * (1.f / H);
       s2 = row_sum(s2) * (1.f / H);
+      const float c1 = -rstd * s1, c2 = -rstd * s2;
 #pragma unroll
-      for (int i = 0; i < NF; ++i) y[i] = rstd * (go[i] * gam[i] - s1 - y[i] * s2);
+      for (int i = 0; i < NF; ++i) y[i] = fmaf(y[i], c2, fmaf(go[i] * gam[i], rstd, c1));
     } else {
 #pragma unroll
       for (int i = 0; i < NF; ++i) y[i] = go[i];
