@@ -279,9 +279,11 @@ __global__ __launch_bounds__(256, (H <= 64 ? 4 : 2)) void k_edge_fwd(DevGraph gr
       for (int i = 0; i < NF; ++i) ev[i] += m[i];
       if (valid && e_out) store_row<H>(e_out + k * H, g, ev);  // no e' for a last layer
 
-      // aggregation: segmented scan of e'/d across the block, plus carry
+      // aggregation: segmented scan of e'/d across the block, plus carry.
+      // Lanes past the tile's last edge (finite values from an in-bounds
+      // edge, a key of their own) add nothing to any row's sum.
 #pragma unroll
-      for (int i = 0; i < NF; ++i) ev[i] = valid ? (AM ? m[i] : ev[i]) * inv_d : 0.f;
+      for (int i = 0; i < NF; ++i) ev[i] = (AM ? m[i] : ev[i]) * inv_d;
       if (j == 0 && key == carry_key) {
 #pragma unroll
         for (int i = 0; i < NF; i += 4) {
