@@ -81,6 +81,8 @@ def _parse():
     ap.add_argument("--model", default="workload", choices=["workload"] + sorted(TABLE1),
                     help="the workload's own model, or one of the paper's Table I models")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 comparison path")
+    ap.add_argument("--no-bf16-state", action="store_true",
+                    help="skip the separately reported path with BF16 edge-state storage")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-autotune", action="store_true", help="use the library's default schedule")
     ap.add_argument("--sample-nodes", type=int, default=24, help="nodes for the error vs FP64")
@@ -179,7 +181,7 @@ def _events():
     return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
 
-def run_path(gemm, spec, params, prob, steps, warmup, schedule, profile_steps):
+def run_path(gemm, spec, params, prob, steps, warmup, schedule, profile_steps, estate="f32"):
     """Time `steps` full fwd+bwd steps (no per-launch instrumentation), then
     the message-passing layers alone, then record per-kernel times in a
     separate pass.  Returns a dict with the timings, per-kernel stats, the
@@ -191,7 +193,8 @@ def run_path(gemm, spec, params, prob, steps, warmup, schedule, profile_steps):
     from paper_2410_01657_amd._lib import call
     from paper_2410_01657_amd.model import ConsistentGNN
 
-    model = ConsistentGNN(spec, params, "cuda", gemm=gemm, schedule=schedule).requires_grad_(True)
+    model = ConsistentGNN(spec, params, "cuda", gemm=gemm, schedule=schedule,
+                          estate=estate).requires_grad_(True)
 
     def step():
         for t in model.params.values():
@@ -359,32 +362,38 @@ def main():
     sample_rows = order[np.searchsorted(hg.row_gid[order], sample_gids)]
 
     copy_gbps = copy_bandwidth()
-    paths = ["f32"] if deep else ["bf16"] + ([] if a.no_fp32 else ["f32"])
+    # path name -> (GEMM operand type, edge-state storage type)
+    PATHS = {"bf16": ("bf16", "f32"), "f32": ("f32", "f32"), "bf16_state": ("bf16", "bf16")}
+    paths = (["f32"] if deep else ["bf16"] + ([] if a.no_fp32 else ["f32"])
+             + ([] if a.no_bf16_state else ["bf16_state"]))
     res, outs, scheds, grads = {}, {}, {}, {}
-    for gemm in paths:
-        sched = None if (a.no_autotune or deep) else tuned_schedule(prob.dg, spec.H, spec.layernorm, gemm)
-        scheds[gemm] = sched
-        _progress(f"{gemm}: schedule {sched}")
-        r = run_path(gemm, spec, inp.params, prob, a.steps, a.warmup, sched, a.profile_steps)
-        _progress(f"{gemm}: {r['ms']:.3f} ms/step, message-passing layers alone {r['mp_ms']:.3f} ms")
-        outs[gemm] = r.pop("Y").cpu().numpy()[sample_rows].astype(np.float64)
-        grads[gemm] = {k: v.cpu().numpy().astype(np.float64) for k, v in r.pop("grads").items()}
-        if not np.all(np.isfinite(outs[gemm])) or not np.isfinite(r["loss"]):
-            raise RuntimeError(f"{gemm} path produced a non-finite output or loss")
-        res[gemm] = r
+    for name in paths:
+        gemm, estate = PATHS[name]
+        sched = None if (a.no_autotune or deep) else tuned_schedule(prob.dg, spec.H, spec.layernorm, gemm,
+                                                                    estate=estate)
+        scheds[name] = sched
+        _progress(f"{name}: schedule {sched}")
+        r = run_path(gemm, spec, inp.params, prob, a.steps, a.warmup, sched, a.profile_steps, estate)
+        _progress(f"{name}: {r['ms']:.3f} ms/step, message-passing layers alone {r['mp_ms']:.3f} ms")
+        outs[name] = r.pop("Y").cpu().numpy()[sample_rows].astype(np.float64)
+        grads[name] = {k: v.cpu().numpy().astype(np.float64) for k, v in r.pop("grads").items()}
+        if not np.all(np.isfinite(outs[name])) or not np.isfinite(r["loss"]):
+            raise RuntimeError(f"{name} path produced a non-finite output or loss")
+        res[name] = r
         torch.cuda.empty_cache()
 
     main_gemm = paths[0]
     main_path = res[main_gemm]
     value = E_global * spec.n_layers / (main_path["ms"] * 1e-3)
 
-    def dominant_roofline(gemm):
+    def dominant_roofline(name):
         """Roofline of the path's longest-running kernel: algorithmic bytes
         (or flops) per launch / its average launch time, against the peak
         of whichever roof bounds that kernel."""
+        gemm, estate = PATHS[name]
         work = (deep_kernels(N, E, G, M, spec.H, spec.n_hidden, spec.n_layers) if deep
-                else layer_kernels(N, E, G, M, spec.H, gemm, spec.n_layers))
-        kern = res[gemm]["kernels"]
+                else layer_kernels(N, E, G, M, spec.H, gemm, spec.n_layers, estate))
+        kern = res[name]["kernels"]
         dom = max((k for k in kern if k in work), key=lambda k: kern[k]["ms_total"])
         w = work[dom]
         avg_s = kern[dom]["ms_avg"] * 1e-3
@@ -400,15 +409,17 @@ def main():
                   "algorithmic_GFLOP": w.flops / 1e9})
         return r
 
-    def mp_layers(gemm):
+    def mp_layers(name):
         """The message-passing layers alone: edges/s and the fraction of
         their roofline time (every layer kernel at the higher of its HBM and
         matrix floors, published peaks; and against the measured copy rate)."""
-        ms = res[gemm]["mp_ms"]
+        gemm, estate = PATHS[name]
+        ms = res[name]["mp_ms"]
         out = {"value": E_global * spec.n_layers / (ms * 1e-3), "ms": ms}
         if not deep:
-            t_roof = layer_roof_seconds(N, E, G, M, spec.H, gemm, spec.n_layers)
-            t_copy = layer_roof_seconds(N, E, G, M, spec.H, gemm, spec.n_layers, hbm=copy_gbps * 1e9)
+            t_roof = layer_roof_seconds(N, E, G, M, spec.H, gemm, spec.n_layers, estate=estate)
+            t_copy = layer_roof_seconds(N, E, G, M, spec.H, gemm, spec.n_layers, hbm=copy_gbps * 1e9,
+                                        estate=estate)
             out.update({"roof_ms": t_roof * 1e3, "frac_of_roof": t_roof * 1e3 / ms,
                         "roof_ms_at_copy_rate": t_copy * 1e3, "frac_of_roof_at_copy_rate": t_copy * 1e3 / ms})
         return out
@@ -422,6 +433,15 @@ def main():
     if roof["bound"] == "hbm":
         roof["copy_GBps"] = copy_gbps
         roof["frac_of_copy"] = roof["achieved"] / copy_gbps
+
+    def grad_dev(name):
+        """Parameter gradients of a BF16 path against the FP32 path's (which
+        match the FP64 oracle to ~1e-5 in the parity tests): max |d| /
+        max |g_fp32| per parameter tensor, the worst tensor reported."""
+        dev = {k: float(np.abs(grads[name][k] - v).max() / max(np.abs(v).max(), 1e-30))
+               for k, v in grads["f32"].items()}
+        worst = max(dev, key=dev.get)
+        return {"max": dev[worst], "tensor": worst, "median": float(np.median(list(dev.values())))}
 
     line = {
         "metric": "MP-layer fwd+bwd edges/sec, BF16-MFMA vs FP32, at stated rel. error vs FP64",
@@ -448,14 +468,16 @@ def main():
                         "mp_layers": mp_layers("f32")}
         line["bf16_over_fp32"] = res["f32"]["ms"] / main_path["ms"]
         line["bf16_over_fp32_mp_layers"] = res["f32"]["mp_ms"] / main_path["mp_ms"]
-        # BF16 parameter gradients against the FP32 path's (which match the
-        # FP64 oracle to ~1e-5 in the parity tests): max |d| / max |g_fp32|
-        # per parameter tensor, the worst tensor reported
-        dev = {k: float(np.abs(grads["bf16"][k] - v).max() / max(np.abs(v).max(), 1e-30))
-               for k, v in grads["f32"].items()}
-        worst = max(dev, key=dev.get)
-        line["bf16_grad_rel_dev_vs_fp32"] = {"max": dev[worst], "tensor": worst,
-                                             "median": float(np.median(list(dev.values())))}
+        line["bf16_grad_rel_dev_vs_fp32"] = grad_dev("bf16")
+    if "bf16_state" in res:
+        # BF16 GEMMs with the edge states (and their gradients) stored in
+        # BF16 between kernels: a separate option, reported beside the line
+        bs = res["bf16_state"]
+        line["bf16_state"] = {"value": E_global * spec.n_layers / (bs["ms"] * 1e-3), "ms_per_step": bs["ms"],
+                              "over_bf16": main_path["ms"] / bs["ms"] if main_gemm == "bf16" else None,
+                              "roofline": dominant_roofline("bf16_state"), "mp_layers": mp_layers("bf16_state")}
+        if "f32" in res:
+            line["bf16_state"]["grad_rel_dev_vs_fp32"] = grad_dev("bf16_state")
     line["kernels"] = {g: {k: round(v["ms_total"], 4) for k, v in res[g]["kernels"].items()} for g in res}
     if not a.no_cpu_baseline:
         _progress("timing the FP64 oracle on a bounded sample")

@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define MP_ABI_VERSION 3
+#define MP_ABI_VERSION 4
 
 enum {
   MP_OK = 0,
@@ -218,6 +218,13 @@ typedef struct {
    * results are bitwise those of the fixed order). */
   int32_t edge_bwd_waves;
   int32_t edge_fwd_queue;
+  /* Storage type of the edge states and their gradients (e_in, e_out,
+   * g_e_out, g_e_in of the entry points below): MP_F32, or MP_BF16 (with
+   * gemm_dtype = MP_BF16 only; rounded to nearest even where stored, while
+   * the edge update, the aggregation of Eq. 4b and the adjoint still run
+   * in FP32 registers).  Halves the edge-state traffic at the cost of
+   * BF16-rounded states between layers. */
+  int32_t estate_dtype;
 } mp_layer_cfg;
 
 /* Parameters of one layer, device FP32.  Edge MLP: Linear(3H->H), ELU,
@@ -242,7 +249,8 @@ typedef struct {
 int mp_layer_workspace_size(const mp_layer_cfg* cfg, const mp_dev_graph* g,
                             int backward, size_t* bytes);
 
-/* Forward.  x_in[N][H], e_in[E][H] -> x_out[N][H], e_out[E][H] (FP32).
+/* Forward.  x_in[N][H], e_in[E][H] -> x_out[N][H], e_out[E][H] (edge
+ * states FP32, or BF16 with estate_dtype = MP_BF16; node arrays FP32).
  * e_out may be NULL: the updated edge state is then not written (a model's
  * last layer, whose e' nothing reads; Eq. 4b still sums it into a).
  * a_star_out[N][H] receives the synchronised aggregate a* (needed by the
@@ -255,8 +263,8 @@ int mp_layer_workspace_size(const mp_layer_cfg* cfg, const mp_dev_graph* g,
  * (the packed weights and the edge tile bounds), and a workspace of that
  * prefix's size is accepted. */
 int mp_layer_forward(const mp_layer_cfg* cfg, const mp_layer_params* p,
-                     const mp_dev_graph* g, const float* x_in, const float* e_in,
-                     float* x_out, float* e_out, float* a_star_out, float* pq_out,
+                     const mp_dev_graph* g, const float* x_in, const void* e_in,
+                     float* x_out, void* e_out, float* a_star_out, float* pq_out,
                      void* ws, size_t ws_bytes, mp_stream_t stream);
 
 /* The same forward for callers that cannot allocate device memory (code
@@ -277,8 +285,8 @@ int mp_layer_forward(const mp_layer_cfg* cfg, const mp_layer_params* p,
  * to start at zero (each call writes what it reads).  Launches of this
  * entry point are not recorded by mp_profile_enable. */
 int mp_layer_forward_noalloc(const mp_layer_cfg* cfg, const mp_layer_params* p,
-                             const mp_dev_graph* g, const float* x_in, const float* e_in,
-                             float* x_out, float* e_out, float* a_star_out, float* pq_out,
+                             const mp_dev_graph* g, const float* x_in, const void* e_in,
+                             float* x_out, void* e_out, float* a_star_out, float* pq_out,
                              mp_stream_t stream);
 size_t mp_layer_forward_noalloc_max_scratch(void);
 
@@ -290,9 +298,9 @@ size_t mp_layer_forward_noalloc_max_scratch(void);
  * may be NULL (zero).  pq is the forward's pq_out for the same inputs and
  * parameters, or NULL (then P and Q are recomputed). */
 int mp_layer_backward(const mp_layer_cfg* cfg, const mp_layer_params* p,
-                      const mp_dev_graph* g, const float* x_in, const float* e_in,
-                      const float* a_star, const float* pq, const float* g_x_out, const float* g_e_out,
-                      float* g_x_in, float* g_e_in, const mp_layer_grads* grads,
+                      const mp_dev_graph* g, const float* x_in, const void* e_in,
+                      const float* a_star, const float* pq, const float* g_x_out, const void* g_e_out,
+                      float* g_x_in, void* g_e_in, const mp_layer_grads* grads,
                       void* ws, size_t ws_bytes, mp_stream_t stream);
 
 /* ---------------------------------------------------------------------
@@ -305,6 +313,10 @@ typedef struct {
   int32_t layernorm;  /* LayerNorm on the output (requires n_out == H) */
   int32_t gemm_dtype; /* MP_F32 or MP_BF16 for the H x H products */
   float ln_eps;
+  /* Storage type of `out` (forward) and `g_out` (backward): MP_F32, or
+   * MP_BF16 for the edge encoder of a model with BF16 edge states (n_in
+   * <= 4, n_out == H, BF16 GEMMs only). */
+  int32_t out_dtype;
 } mp_mlp_cfg;
 
 /* Linear(n_in->H), ELU, Linear(H->n_out) [, LayerNorm]. */
@@ -317,11 +329,11 @@ typedef struct {
 
 int mp_mlp_workspace_size(const mp_mlp_cfg* cfg, int64_t n_rows, int backward, size_t* bytes);
 int mp_mlp_forward(const mp_mlp_cfg* cfg, const mp_mlp_params* p, int64_t n_rows,
-                   const float* in, float* out, void* ws, size_t ws_bytes,
+                   const float* in, void* out, void* ws, size_t ws_bytes,
                    mp_stream_t stream);
 /* g_in may be NULL (input gradient not needed). */
 int mp_mlp_backward(const mp_mlp_cfg* cfg, const mp_mlp_params* p, int64_t n_rows,
-                    const float* in, const float* g_out, float* g_in,
+                    const float* in, const void* g_out, float* g_in,
                     const mp_mlp_grads* grads, void* ws, size_t ws_bytes,
                     mp_stream_t stream);
 

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmplayer.so")
 
 MP_OK, MP_EINVAL, MP_EPLAN, MP_ENOMEM, MP_EHIP = 0, 1, 2, 3, 4
-ABI_VERSION = 3
+ABI_VERSION = 4
 MP_F32, MP_BF16 = 0, 1
 MP_AGG_STATE, MP_AGG_MESSAGE = 0, 1
 
@@ -30,7 +30,8 @@ class MpDevGraph(C.Structure):
 class MpLayerCfg(C.Structure):
     _fields_ = [("H", c_i32), ("layernorm", c_i32), ("halo", c_i32), ("gemm_dtype", c_i32),
                 ("ln_eps", c_f32), ("tile_edges", c_i32), ("edge_grid", c_i32), ("edge_bwd_grid", c_i32),
-                ("aggregate", c_i32), ("edge_bwd_waves", c_i32), ("edge_fwd_queue", c_i32)]
+                ("aggregate", c_i32), ("edge_bwd_waves", c_i32), ("edge_fwd_queue", c_i32),
+                ("estate_dtype", c_i32)]
 
 
 LAYER_FIELDS = ["We1", "be1", "We2", "be2", "ge", "bge", "Wn1", "bn1", "Wn2", "bn2", "gn", "bgn"]
@@ -46,7 +47,7 @@ class MpLayerGrads(C.Structure):
 
 class MpMlpCfg(C.Structure):
     _fields_ = [("n_in", c_i32), ("H", c_i32), ("n_out", c_i32), ("layernorm", c_i32),
-                ("gemm_dtype", c_i32), ("ln_eps", c_f32)]
+                ("gemm_dtype", c_i32), ("ln_eps", c_f32), ("out_dtype", c_i32)]
 
 
 MLP_FIELDS = ["W0", "b0", "W1", "b1", "ln_g", "ln_b"]

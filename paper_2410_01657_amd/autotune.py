@@ -8,7 +8,8 @@ for BF16 GEMMs at H <= 64, i.e. 64 or 128 edges staged per weight-gradient
 round) and the tile order of the edge forward (edge_fwd_queue: fixed round
 robin, or per-XCD atomic tile counters).  The tuner times the library's own
 forward and backward on the actual graph and keeps the fastest, cached per
-(arch, H, GEMM type, LayerNorm, rows, edges, sub-graphs) in a JSON file
+(arch, H, GEMM type, edge-state type, LayerNorm, rows, edges, sub-graphs)
+in a JSON file
 ($MPLAYER_TUNE_CACHE, default ~/.cache/mplayer/tune.json).  Every schedule
 computes the same function; they differ only in the grouping of
 floating-point sums (and the forward's tile order not even in that).
@@ -16,10 +17,10 @@ floating-point sums (and the forward's tile order not even in that).
 Not searched: 32 x 32 matrix-core tiles (every kernel's row-block layout is
 built on 16 x 16 products; the BF16 path is not bound by its products, and
 the FP32 products already issue back to back); the unsplit first edge
-Linear (twice the flops for the same bytes, never faster); BF16 storage of
-the edge states (it changes the stored precision, not just the grouping of
-sums; measured on the largest workload as a timing-only variant, it cut
-the edge forward by 18% and the edge adjoint by 1%).
+Linear (twice the flops for the same bytes, never faster).  BF16 storage of
+the edge states (estate="bf16") is not a schedule: it changes the stored
+precision, not just the grouping of sums, so the caller chooses it and the
+tuner keeps a separate entry for it.
 """
 
 import json
@@ -62,9 +63,10 @@ def _cache_path():
                           os.path.join(os.path.expanduser("~"), ".cache", "mplayer", "tune.json"))
 
 
-def _key(dg, H, layernorm, gemm):
+def _key(dg, H, layernorm, gemm, estate="f32"):
     arch = torch.cuda.get_device_properties(dg.device).gcnArchName.split(":")[0]
-    return f"{arch}|H{H}|{gemm}|ln{int(layernorm)}|N{dg.n_rows}|E{dg.n_edges}|R{dg.host.R}|v2"
+    es = "" if estate == "f32" else f"|es{estate}"
+    return f"{arch}|H{H}|{gemm}{es}|ln{int(layernorm)}|N{dg.n_rows}|E{dg.n_edges}|R{dg.host.R}|v2"
 
 
 def _load():
@@ -99,7 +101,7 @@ def _time(fn, reps):
     return a.elapsed_time(b) / reps
 
 
-def tune_layer(dg, H, layernorm=True, gemm="bf16", reps=3, seed=0):
+def tune_layer(dg, H, layernorm=True, gemm="bf16", reps=3, seed=0, estate="f32"):
     """Time the candidate schedules; returns the best as a dict.  For each
     tile size: the best forward over (edge_grid, edge_fwd_queue), then the
     best adjoint over (edge_bwd_grid, edge_bwd_waves) with that forward."""
@@ -116,11 +118,12 @@ def tune_layer(dg, H, layernorm=True, gemm="bf16", reps=3, seed=0):
     if layernorm:
         p.update({"ge": 1 + rnd(H, scale=0.1), "bge": rnd(H, scale=0.1),
                   "gn": 1 + rnd(H, scale=0.1), "bgn": rnd(H, scale=0.1)})
-    x, e = rnd(dg.n_rows, H), rnd(dg.n_edges, H)
-    gx, ge = rnd(dg.n_rows, H), rnd(dg.n_edges, H)
+    edt = torch.bfloat16 if estate == "bf16" else torch.float32
+    x, e = rnd(dg.n_rows, H), rnd(dg.n_edges, H).to(edt)
+    gx, ge = rnd(dg.n_rows, H), rnd(dg.n_edges, H).to(edt)
 
     def cfg_of(sched):
-        return apply_schedule(layer_cfg(H, layernorm, True, gemm), sched)
+        return apply_schedule(layer_cfg(H, layernorm, True, gemm, estate=estate), sched)
 
     best = None
     for te in TILE_EDGES:
@@ -147,11 +150,11 @@ def tune_layer(dg, H, layernorm=True, gemm="bf16", reps=3, seed=0):
     return best
 
 
-def tuned_schedule(dg, H, layernorm=True, gemm="bf16", retune=False):
+def tuned_schedule(dg, H, layernorm=True, gemm="bf16", retune=False, estate="f32"):
     """The cached best schedule for this graph and layer shape (tuned on a miss)."""
     cache = _load()
-    key = _key(dg, H, layernorm, gemm)
+    key = _key(dg, H, layernorm, gemm, estate)
     if retune or key not in cache:
-        cache[key] = tune_layer(dg, H, layernorm, gemm)
+        cache[key] = tune_layer(dg, H, layernorm, gemm, estate=estate)
         _store(cache)
     return cache[key]

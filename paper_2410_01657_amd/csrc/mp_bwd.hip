@@ -313,18 +313,18 @@ struct EdgeBwdCfg {
 };
 
 // The rows one 16-edge block of the edge adjoint reads: e_k, P_i, Q_j,
-// g_a_i and g_e'_k (zero when absent).
-template <int H>
+// g_a_i and g_e'_k (zero when absent); ES: e and g_e' stored as BF16.
+template <int H, bool ES>
 struct EdgeBwdRows {
   static constexpr int NF = H / 4;
   float ev[NF], u[NF], t[NF], gE[NF], go[NF];
   __device__ __forceinline__ void load(const EdgeBwdArgs& a, int64_t kk, int ri, int sj, int g) {
-    load_row<H>(a.e_in + kk * H, g, ev);
+    load_row_t<H, ES>(a.e_in, kk, g, ev);
     load_row<H>(a.P + (int64_t)ri * H, g, u);
     load_row<H>(a.Q + (int64_t)sj * H, g, t);
     load_row<H>(a.g_a + (int64_t)ri * H, g, gE);
     if (a.g_e_out) {
-      load_row<H>(a.g_e_out + kk * H, g, go);
+      load_row_t<H, ES>(a.g_e_out, kk, g, go);
     } else {
 #pragma unroll
       for (int i = 0; i < NF; ++i) go[i] = 0.f;
@@ -342,7 +342,8 @@ struct EdgeBwdRows {
 //   g_h[k] = gh, summed per sender by k_gq through the reverse edges.
 // AM: the forward aggregated the MLP output, so the residual path carries
 // only the next layer's gradient (not Eq. 4b's).
-template <int H, bool BF, bool AM, int NWQ>
+// ES: edge states and their gradients (e, g_e', g_e) stored as BF16.
+template <int H, bool BF, bool AM, int NWQ, bool ES>
 __global__ __launch_bounds__((64 * EdgeBwdCfg<H, BF, NWQ>::NW), (EdgeBwdCfg<H, BF, NWQ>::MINB)) void k_edge_bwd(EdgeBwdArgs a) {
   using C = EdgeBwdCfg<H, BF, NWQ>;
   constexpr int NF = H / 4, MB = H / 16, NW = C::NW, ROWS = C::ROWS, NT = dw_tiles_per_wave<H, H, NW>();
@@ -452,7 +453,7 @@ __global__ __launch_bounds__((64 * EdgeBwdCfg<H, BF, NWQ>::NW), (EdgeBwdCfg<H, B
         md_n = gr.mult[kk2];
         nx_n = (k2 + 1 < e1) ? gr.recv[k2 + 1] : -1;
       }
-      EdgeBwdRows<H> cur;
+      EdgeBwdRows<H, ES> cur;
       cur.load(a, kk, ri, sj, g);
       float (&ev)[NF] = cur.ev;
       float (&u)[NF] = cur.u;
@@ -542,7 +543,7 @@ __global__ __launch_bounds__((64 * EdgeBwdCfg<H, BF, NWQ>::NW), (EdgeBwdCfg<H, B
       }
       if constexpr (AM) {
         if (a.g_e_out) {
-          load_row<H>(a.g_e_out + kk * H, g, gE);
+          load_row_t<H, ES>(a.g_e_out, kk, g, gE);
         } else {
 #pragma unroll
           for (int i = 0; i < NF; ++i) gE[i] = 0.f;
@@ -554,7 +555,7 @@ __global__ __launch_bounds__((64 * EdgeBwdCfg<H, BF, NWQ>::NW), (EdgeBwdCfg<H, B
       else
         gemm<BF, MB, MB>(fW1ct, t, gE, lane);
       if (valid) {
-        store_row<H>(a.g_e_in + k * H, g, gE);
+        store_row_t<H, ES>(a.g_e_in, k, g, gE);
         if constexpr (BF)
           store_row_bf16<H>(reinterpret_cast<__bf16*>(a.g_h) + k * H, g, t);
         else
@@ -651,13 +652,20 @@ __global__ __launch_bounds__((64 * EdgeBwdCfg<H, BF, NWQ>::NW), (EdgeBwdCfg<H, B
   }
 }
 
+template <int H, bool BF, bool AM, int NWQ, bool ES>
+static hipError_t launch_edge_bwd_es(const EdgeBwdArgs& a, int grid, hipStream_t s) {
+  using C = EdgeBwdCfg<H, BF, NWQ>;
+  (void)hipFuncSetAttribute((const void*)k_edge_bwd<H, BF, AM, NWQ, ES>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)C::LDS);
+  hipLaunchKernelGGL((k_edge_bwd<H, BF, AM, NWQ, ES>), dim3(grid), dim3(64 * C::NW), C::LDS, s, a);
+  return hipGetLastError();
+}
 template <int H, bool BF, bool AM, int NWQ>
 static hipError_t launch_edge_bwd_am(const EdgeBwdArgs& a, int grid, hipStream_t s) {
-  using C = EdgeBwdCfg<H, BF, NWQ>;
-  (void)hipFuncSetAttribute((const void*)k_edge_bwd<H, BF, AM, NWQ>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)C::LDS);
-  hipLaunchKernelGGL((k_edge_bwd<H, BF, AM, NWQ>), dim3(grid), dim3(64 * C::NW), C::LDS, s, a);
-  return hipGetLastError();
+  if constexpr (BF) {
+    if (a.es) return launch_edge_bwd_es<H, BF, AM, NWQ, true>(a, grid, s);
+  }
+  return launch_edge_bwd_es<H, BF, AM, NWQ, false>(a, grid, s);
 }
 // Waves per workgroup: the default, or 4 (any width and type), or 8 (the
 // BF16 kernel at H <= 64, whose default it is); the C ABI validates it.
@@ -671,6 +679,7 @@ static hipError_t launch_edge_bwd_t(const EdgeBwdArgs& a, int grid, hipStream_t 
 }
 
 hipError_t launch_edge_bwd(const EdgeBwdArgs& a, int grid, hipStream_t s) {
+  if (a.es && !a.bf) return hipErrorInvalidValue;
 #define MP_CASE(HH) \
   if (a.H == HH) return a.bf ? launch_edge_bwd_t<HH, true>(a, grid, s) : launch_edge_bwd_t<HH, false>(a, grid, s);
   MP_CASE(32) MP_CASE(64) MP_CASE(128)
@@ -680,21 +689,6 @@ hipError_t launch_edge_bwd(const EdgeBwdArgs& a, int grid, hipStream_t s) {
 
 // ------------------------------------------- split edge adjoint (wide H)
 
-// Stores of a row-block vector as FP32 or BF16.
-template <int H, bool BF>
-__device__ __forceinline__ void store_row_t(void* __restrict__ base, int64_t row, int g, const float (&v)[H / 4]) {
-  if constexpr (BF)
-    store_row_bf16<H>(reinterpret_cast<__bf16*>(base) + row * H, g, v);
-  else
-    store_row<H>(reinterpret_cast<float*>(base) + row * H, g, v);
-}
-template <int H, bool BF>
-__device__ __forceinline__ void load_row_t(const void* __restrict__ base, int64_t row, int g, float (&v)[H / 4]) {
-  if constexpr (BF)
-    load_row_bf16<H>(reinterpret_cast<const __bf16*>(base) + row * H, g, v);
-  else
-    load_row<H>(reinterpret_cast<const float*>(base) + row * H, g, v);
-}
 
 template <int H, bool BF>
 struct EdgeBwdSplitCfg {
@@ -724,7 +718,7 @@ struct EdgeBwdSplitCfg {
 // H/64 features), accumulated per lane, and the waves' sums are added in
 // wave order into the workgroup's slab at the end.  Waves walk their tiles
 // independently (no barriers in the loop).
-template <int H, bool BF, bool AM>
+template <int H, bool BF, bool AM, bool ES>
 __global__ __launch_bounds__((64 * EdgeBwdSplitCfg<H, BF>::NW)) void k_edge_bwd_split(EdgeBwdArgs a) {
   using C = EdgeBwdSplitCfg<H, BF>;
   constexpr int NF = H / 4, MB = H / 16, NW = C::NW;
@@ -789,7 +783,7 @@ __global__ __launch_bounds__((64 * EdgeBwdSplitCfg<H, BF>::NW)) void k_edge_bwd_
         nx_n = (k2 + 1 < e1) ? gr.recv[k2 + 1] : -1;
       }
       float ev[NF], u[NF], t[NF], gE[NF];
-      load_row<H>(a.e_in + kk * H, g, ev);
+      load_row_t<H, ES>(a.e_in, kk, g, ev);
       load_row<H>(a.P + (int64_t)ri * H, g, u);
       load_row<H>(a.Q + (int64_t)sj * H, g, t);
       load_row<H>(a.g_a + (int64_t)ri * H, g, gE);
@@ -807,7 +801,7 @@ __global__ __launch_bounds__((64 * EdgeBwdSplitCfg<H, BF>::NW)) void k_edge_bwd_
       gemm<BF, MB, MB, ROT>(fW2, u, mp, lane);
       // gradient reaching e'
       if (a.g_e_out) {
-        load_row<H>(a.g_e_out + kk * H, g, t);
+        load_row_t<H, ES>(a.g_e_out, kk, g, t);
 #pragma unroll
         for (int i = 0; i < NF; ++i) gE[i] = gE[i] * inv_d + t[i];
       } else {
@@ -861,7 +855,7 @@ __global__ __launch_bounds__((64 * EdgeBwdSplitCfg<H, BF>::NW)) void k_edge_bwd_
       for (int i = 0; i < NF; ++i) t[i] *= elu_deriv_from_value(u[i]);
       if constexpr (AM) {  // residual path: the next layer's gradient only
         if (a.g_e_out) {
-          load_row<H>(a.g_e_out + kk * H, g, gE);
+          load_row_t<H, ES>(a.g_e_out, kk, g, gE);
         } else {
 #pragma unroll
           for (int i = 0; i < NF; ++i) gE[i] = 0.f;
@@ -873,7 +867,7 @@ __global__ __launch_bounds__((64 * EdgeBwdSplitCfg<H, BF>::NW)) void k_edge_bwd_
       else
         gemm<BF, MB, MB>(fW1ct, t, gE, lane);
       if (valid) {
-        store_row<H>(a.g_e_in + k * H, g, gE);
+        store_row_t<H, ES>(a.g_e_in, k, g, gE);
         store_row_t<H, BF>(a.g_h, k, g, t);
       }
       // g_P: segmented sum of gh per receiver (carry through LDS); lanes
@@ -925,13 +919,20 @@ __global__ __launch_bounds__((64 * EdgeBwdSplitCfg<H, BF>::NW)) void k_edge_bwd_
   }
 }
 
+template <int H, bool BF, bool AM, bool ES>
+static hipError_t launch_edge_bwd_split_es(const EdgeBwdArgs& a, int grid, hipStream_t s) {
+  using C = EdgeBwdSplitCfg<H, BF>;
+  (void)hipFuncSetAttribute((const void*)k_edge_bwd_split<H, BF, AM, ES>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)C::LDS);
+  hipLaunchKernelGGL((k_edge_bwd_split<H, BF, AM, ES>), dim3(grid), dim3(64 * C::NW), C::LDS, s, a);
+  return hipGetLastError();
+}
 template <int H, bool BF, bool AM>
 static hipError_t launch_edge_bwd_split_am(const EdgeBwdArgs& a, int grid, hipStream_t s) {
-  using C = EdgeBwdSplitCfg<H, BF>;
-  (void)hipFuncSetAttribute((const void*)k_edge_bwd_split<H, BF, AM>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)C::LDS);
-  hipLaunchKernelGGL((k_edge_bwd_split<H, BF, AM>), dim3(grid), dim3(64 * C::NW), C::LDS, s, a);
-  return hipGetLastError();
+  if constexpr (BF) {
+    if (a.es) return launch_edge_bwd_split_es<H, BF, AM, true>(a, grid, s);
+  }
+  return launch_edge_bwd_split_es<H, BF, AM, false>(a, grid, s);
 }
 
 template <int H, bool BF>
@@ -940,6 +941,7 @@ static hipError_t launch_edge_bwd_split_t(const EdgeBwdArgs& a, int grid, hipStr
 }
 
 hipError_t launch_edge_bwd_split(const EdgeBwdArgs& a, int grid, hipStream_t s) {
+  if (a.es && !a.bf) return hipErrorInvalidValue;
   if (a.H == 128) return a.bf ? launch_edge_bwd_split_t<128, true>(a, grid, s) : launch_edge_bwd_split_t<128, false>(a, grid, s);
   return hipErrorInvalidValue;
 }
@@ -1365,7 +1367,7 @@ struct MlpBwdCfg {
 
 // The rows one 16-row block of k_mlp_bwd reads: its inputs and the
 // gradient at its output.
-template <int H, int KIN, bool TIN, bool TOUT>
+template <int H, int KIN, bool TIN, bool TOUT, bool GB = false>
 struct MlpBwdIn {
   static constexpr int NF = H / 4, NIN = TIN ? 4 : KIN / 4, NGO = TOUT ? 4 : H / 4;
   float in[NIN];
@@ -1392,11 +1394,12 @@ struct MlpBwdIn {
     if constexpr (TOUT) {
       // n_out <= 4 outputs; the same clamp-then-zero as the inputs
 #pragma unroll
-      for (int o = 0; o < 4; ++o) go[o] = a.g_out[rr * a.n_out + (o < a.n_out ? o : a.n_out - 1)];
+      for (int o = 0; o < 4; ++o)
+        go[o] = reinterpret_cast<const float*>(a.g_out)[rr * a.n_out + (o < a.n_out ? o : a.n_out - 1)];
 #pragma unroll
       for (int o = 0; o < 4; ++o) go[o] = o < a.n_out ? go[o] : 0.f;
     } else {
-      load_row<H>(a.g_out + rr * H, g, go);
+      load_row_t<H, GB>(a.g_out, rr, g, go);
     }
   }
   __device__ __forceinline__ void settle() {
@@ -1412,10 +1415,12 @@ struct MlpBwdIn {
 // Two staging phases per step (dW1 with its bias / LayerNorm sums, then
 // dW0 and db0) share the same LDS.  The next block's rows are loaded while
 // the current one is processed (one block ahead, as in k_mlp_fwd).
-template <int H, int KIN, bool TIN, bool TOUT, bool BF>
+// GB: the H-wide output gradient is stored as BF16 (the edge encoder's, an
+// edge-state gradient, when edge states are BF16).
+template <int H, int KIN, bool TIN, bool TOUT, bool BF, bool GB>
 __global__ __launch_bounds__((64 * MlpBwdCfg<H, KIN, TIN, TOUT, BF>::NW)) void k_mlp_bwd(MlpBwdArgs a) {
   using C = MlpBwdCfg<H, KIN, TIN, TOUT, BF>;
-  using In = MlpBwdIn<H, KIN, TIN, TOUT>;
+  using In = MlpBwdIn<H, KIN, TIN, TOUT, GB>;
   constexpr bool PK = KIN != 2 * H;  // packed BF16 staging, except where registers are short
   constexpr int NF = H / 4, MB = H / 16, KB = TIN ? 1 : KIN / 16, AW0 = C::AW0, NW = C::NW, ROWS = C::ROWS;
   constexpr int NT1 = TOUT ? dw_tiles_per_wave<16, H, NW>() : dw_tiles_per_wave<H, H, NW>();
@@ -1457,7 +1462,7 @@ __global__ __launch_bounds__((64 * MlpBwdCfg<H, KIN, TIN, TOUT, BF>::NW)) void k
   __syncthreads();
   const bool want_gin = (a.g_src0 || a.g_src1) && !TIN;
   // the residual path's gradient is usually g_out itself (node update)
-  const bool add1_is_gout = a.g_add1 != nullptr && a.g_add1 == a.g_out;
+  const bool add1_is_gout = a.g_add1 != nullptr && static_cast<const void*>(a.g_add1) == a.g_out;
 
   const int lane = lane_id(), j = lane & 15, g = lane >> 4, wave = threadIdx.x / 64;
   const int srow = wave * 16 + j;
@@ -1755,13 +1760,13 @@ __global__ __launch_bounds__((64 * MlpBwdCfg<H, KIN, TIN, TOUT, BF>::NW)) void k
   }
 }
 
-template <int H, int KIN, bool TIN, bool TOUT, bool BF>
+template <int H, int KIN, bool TIN, bool TOUT, bool BF, bool GB = false>
 static hipError_t launch_mlp_bwd_t(const MlpBwdArgs& a, int grid, hipStream_t s) {
   using C = MlpBwdCfg<H, KIN, TIN, TOUT, BF>;
   const size_t lds = C::LDS;
-  (void)hipFuncSetAttribute((const void*)k_mlp_bwd<H, KIN, TIN, TOUT, BF>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)lds);
-  hipLaunchKernelGGL((k_mlp_bwd<H, KIN, TIN, TOUT, BF>), dim3(grid), dim3(64 * C::NW), lds, s, a);
+  (void)hipFuncSetAttribute((const void*)k_mlp_bwd<H, KIN, TIN, TOUT, BF, GB>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL((k_mlp_bwd<H, KIN, TIN, TOUT, BF, GB>), dim3(grid), dim3(64 * C::NW), lds, s, a);
   return hipGetLastError();
 }
 
@@ -1769,6 +1774,10 @@ template <int H, bool BF>
 static hipError_t launch_mlp_bwd_h(const MlpBwdArgs& a, int grid, hipStream_t s) {
   const bool tin = a.k0 <= 4, tout = a.n_out < 16;
   const int kin = a.k0 + a.k1;
+  if (a.gout_bf && !(tin && !tout && BF)) return hipErrorInvalidValue;
+  if constexpr (BF) {
+    if (tin && !tout && a.gout_bf) return launch_mlp_bwd_t<H, 4, true, false, BF, true>(a, grid, s);
+  }
   if (tin && !tout) return launch_mlp_bwd_t<H, 4, true, false, BF>(a, grid, s);
   if (!tin && kin == H && tout) return launch_mlp_bwd_t<H, H, false, true, BF>(a, grid, s);
   if (!tin && kin == H && !tout) return launch_mlp_bwd_t<H, H, false, false, BF>(a, grid, s);
@@ -1844,7 +1853,7 @@ __global__ __launch_bounds__((64 * NodeBwdSplitCfg<H, BF>::NW)) void k_node_bwd_
       float in[2 * NF];
       load_row<H>(a.src0 + rr * H, g, *reinterpret_cast<float(*)[NF]>(in));
       load_row<H>(a.src1 + rr * H, g, *reinterpret_cast<float(*)[NF]>(in + NF));
-      if constexpr (PH == 0) load_row<H>(a.g_out + rr * H, g, go);
+      if constexpr (PH == 0) load_row<H>(reinterpret_cast<const float*>(a.g_out) + rr * H, g, go);
       __builtin_amdgcn_sched_barrier(0);
       if constexpr (PH == 0) {
         if (!valid) {
@@ -1860,7 +1869,7 @@ __global__ __launch_bounds__((64 * NodeBwdSplitCfg<H, BF>::NW)) void k_node_bwd_
       if constexpr (PH == 1) continue;
     } else {
       load_row_t<H, BF>(u_out, rr, g, u);
-      load_row<H>(a.g_out + rr * H, g, go);
+      load_row<H>(reinterpret_cast<const float*>(a.g_out) + rr * H, g, go);
       if (!valid) {
 #pragma unroll
         for (int i = 0; i < NF; ++i) go[i] = 0.f;

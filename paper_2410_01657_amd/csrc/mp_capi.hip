@@ -155,6 +155,10 @@ int check_cfg(const mp_layer_cfg* c) {
                    c->edge_bwd_waves);
   if (c->edge_fwd_queue != 0 && c->edge_fwd_queue != 1)
     return mp_fail(MP_EINVAL, "edge_fwd_queue must be 0 or 1 (got %d)", c->edge_fwd_queue);
+  if (c->estate_dtype != MP_F32 && c->estate_dtype != MP_BF16)
+    return mp_fail(MP_EINVAL, "estate_dtype must be MP_F32 or MP_BF16");
+  if (c->estate_dtype == MP_BF16 && c->gemm_dtype != MP_BF16)
+    return mp_fail(MP_EINVAL, "BF16 edge states need BF16 GEMMs (gemm_dtype = MP_BF16)");
   return MP_OK;
 }
 
@@ -380,7 +384,7 @@ namespace {
 
 // Validation of the forward's arguments (everything but the workspace).
 int check_layer_forward(const mp_layer_cfg* cfg, const mp_layer_params* p, const mp_dev_graph* g,
-                        const float* x_in, const float* e_in, const float* x_out, const float* e_out,
+                        const float* x_in, const void* e_in, const float* x_out, const void* e_out,
                         const float* a_star_out, const float* pq_out) {
   int rc;
   if ((rc = check_cfg(cfg)) || (rc = check_graph(g, false)) || (rc = check_layer_params(cfg, p))) return rc;
@@ -388,8 +392,8 @@ int check_layer_forward(const mp_layer_cfg* cfg, const mp_layer_params* p, const
   if (!aligned16(x_in) || !aligned16(e_in) || !aligned16(x_out) || (e_out && !aligned16(e_out)) ||
       (a_star_out && !aligned16(a_star_out)) || (pq_out && !aligned16(pq_out)))
     return mp_fail(MP_EINVAL, "mp_layer_forward: buffers must be 16-byte aligned");
-  if (x_out == x_in || (e_out && (e_out == e_in || (const float*)e_out == x_in)) || (const float*)x_out == e_in ||
-      (pq_out && ((const float*)pq_out == x_in || (const float*)pq_out == e_in)))
+  if (x_out == x_in || (e_out && (e_out == e_in || e_out == (const void*)x_in)) ||
+      (const void*)x_out == e_in || (pq_out && ((const float*)pq_out == x_in || (const void*)pq_out == e_in)))
     return mp_fail(MP_EINVAL, "mp_layer_forward: outputs must not alias inputs");
   return MP_OK;
 }
@@ -403,7 +407,7 @@ size_t layer_forward_ws_need(const LayerWs& W, const float* a_star_out, const fl
 
 // The forward's launch sequence (arguments validated, workspace checked).
 int layer_forward_launch(const mp_layer_cfg* cfg, const mp_layer_params* p, const mp_dev_graph* g,
-                         const float* x_in, const float* e_in, float* x_out, float* e_out, float* a_star_out,
+                         const float* x_in, const void* e_in, float* x_out, void* e_out, float* a_star_out,
                          float* pq_out, void* ws, const LayerWs& W, mp_stream_t stream) {
   int rc;
   const int H = cfg->H;
@@ -424,8 +428,11 @@ int layer_forward_launch(const mp_layer_cfg* cfg, const mp_layer_params* p, cons
     return rc;
   if ((rc = run("pack", s, [&] { return launch_pack(layer_jobs(cfg, p, W.fr, false), ws, s); }))) return rc;
   if ((rc = run("proj", s, [&] { return launch_proj(H, bf, d, x_in, ws_at(ws, W.fr.proj), p->be1, P, Q, W.gn, s); }))) return rc;
-  if ((rc = run("edge_fwd", s, [&] { return launch_edge_fwd(H, cfg->layernorm != 0, bf, cfg->aggregate != 0, cfg->edge_fwd_queue != 0, d, P, Q, e_in, ws_at(ws, W.fr.edge), p->be2,
-                                      p->ge, p->bge, cfg->ln_eps, e_out, a, W.ge, s); })))
+  const bool es = cfg->estate_dtype == MP_BF16;
+  if ((rc = run("edge_fwd", s, [&] {
+         return launch_edge_fwd(H, cfg->layernorm != 0, bf, cfg->aggregate != 0, cfg->edge_fwd_queue != 0, es, d, P,
+                                Q, e_in, ws_at(ws, W.fr.edge), p->be2, p->ge, p->bge, cfg->ln_eps, e_out, a, W.ge, s);
+       })))
     return rc;
   if (cfg->halo && (rc = run("halo", s, [&] { return launch_halo(H, d, a, s); }))) return rc;
   MlpFwdArgs m{};
@@ -453,7 +460,7 @@ int layer_forward_launch(const mp_layer_cfg* cfg, const mp_layer_params* p, cons
 }  // namespace
 
 extern "C" int mp_layer_forward(const mp_layer_cfg* cfg, const mp_layer_params* p, const mp_dev_graph* g,
-                                const float* x_in, const float* e_in, float* x_out, float* e_out, float* a_star_out,
+                                const float* x_in, const void* e_in, float* x_out, void* e_out, float* a_star_out,
                                 float* pq_out, void* ws, size_t ws_bytes, mp_stream_t stream) {
   int rc;
   if ((rc = check_layer_forward(cfg, p, g, x_in, e_in, x_out, e_out, a_star_out, pq_out))) return rc;
@@ -514,7 +521,7 @@ struct NoProfile {
 extern "C" size_t mp_layer_forward_noalloc_max_scratch(void) { return kNoallocScratchBytes; }
 
 extern "C" int mp_layer_forward_noalloc(const mp_layer_cfg* cfg, const mp_layer_params* p, const mp_dev_graph* g,
-                                        const float* x_in, const float* e_in, float* x_out, float* e_out,
+                                        const float* x_in, const void* e_in, float* x_out, void* e_out,
                                         float* a_star_out, float* pq_out, mp_stream_t stream) {
   int rc;
   if ((rc = check_layer_forward(cfg, p, g, x_in, e_in, x_out, e_out, a_star_out, pq_out))) return rc;
@@ -533,8 +540,8 @@ extern "C" int mp_layer_forward_noalloc(const mp_layer_cfg* cfg, const mp_layer_
 }
 
 extern "C" int mp_layer_backward(const mp_layer_cfg* cfg, const mp_layer_params* p, const mp_dev_graph* g,
-                                 const float* x_in, const float* e_in, const float* a_star, const float* pq,
-                                 const float* g_x_out, const float* g_e_out, float* g_x_in, float* g_e_in,
+                                 const float* x_in, const void* e_in, const float* a_star, const float* pq,
+                                 const float* g_x_out, const void* g_e_out, float* g_x_in, void* g_e_in,
                                  const mp_layer_grads* gr,
                                  void* ws, size_t ws_bytes, mp_stream_t stream) {
   int rc;
@@ -551,7 +558,7 @@ extern "C" int mp_layer_backward(const mp_layer_cfg* cfg, const mp_layer_params*
     if (!q) return mp_fail(MP_EINVAL, "mp_layer_backward: a gradient buffer is NULL");
   if (cfg->layernorm && (!gr->ge || !gr->bge || !gr->gn || !gr->bgn))
     return mp_fail(MP_EINVAL, "mp_layer_backward: a LayerNorm gradient buffer is NULL");
-  if ((const float*)g_x_in == g_x_out || (const float*)g_e_in == g_e_out || (const float*)g_e_in == e_in ||
+  if ((const float*)g_x_in == g_x_out || (const void*)g_e_in == g_e_out || (const void*)g_e_in == e_in ||
       (const float*)g_x_in == x_in)
     return mp_fail(MP_EINVAL, "mp_layer_backward: gradient outputs must not alias inputs");
   const LayerWs W(cfg, g, true);
@@ -655,6 +662,7 @@ extern "C" int mp_layer_backward(const mp_layer_cfg* cfg, const mp_layer_params*
   eb.bf = bf;
   eb.am = cfg->aggregate;
   eb.waves = cfg->edge_bwd_waves;
+  eb.es = cfg->estate_dtype == MP_BF16;
   eb.P = P;
   eb.Q = Q;
   eb.e_in = e_in;
@@ -685,7 +693,7 @@ extern "C" int mp_layer_backward(const mp_layer_cfg* cfg, const mp_layer_params*
     rd.G = gh;  // dW1c = sum g_h e^T
     rd.g_bf = bf;
     rd.A = e_in;
-    rd.a_bf = 0;
+    rd.a_bf = eb.es;
     rd.off = 0;
     rd.colsum_off = -1;
     if ((rc = run("edge_dw", s, [&] { return launch_row_dw(rd, W.gbe, s); }))) return rc;
@@ -777,6 +785,9 @@ int check_mlp_cfg(const mp_mlp_cfg* c) {
   if (c->layernorm && c->n_out != c->H) return mp_fail(MP_EINVAL, "LayerNorm needs n_out == H");
   if (c->layernorm && !(c->ln_eps > 0.f)) return mp_fail(MP_EINVAL, "ln_eps must be positive");
   if (c->gemm_dtype != MP_F32 && c->gemm_dtype != MP_BF16) return mp_fail(MP_EINVAL, "bad gemm_dtype");
+  if (c->out_dtype != MP_F32 && c->out_dtype != MP_BF16) return mp_fail(MP_EINVAL, "bad out_dtype");
+  if (c->out_dtype == MP_BF16 && !(c->n_in <= 4 && c->n_out == c->H && c->gemm_dtype == MP_BF16))
+    return mp_fail(MP_EINVAL, "a BF16 output needs n_in <= 4, n_out == H and BF16 GEMMs (the edge encoder)");
   return MP_OK;
 }
 
@@ -832,12 +843,12 @@ extern "C" int mp_mlp_workspace_size(const mp_mlp_cfg* cfg, int64_t n_rows, int 
 }
 
 extern "C" int mp_mlp_forward(const mp_mlp_cfg* cfg, const mp_mlp_params* p, int64_t n_rows, const float* in,
-                              float* out, void* ws, size_t ws_bytes, mp_stream_t stream) {
+                              void* out, void* ws, size_t ws_bytes, mp_stream_t stream) {
   int rc;
   if ((rc = check_mlp_cfg(cfg)) || (rc = check_mlp_params(cfg, p))) return rc;
   if (n_rows <= 0 || !in || !out || !ws) return mp_fail(MP_EINVAL, "mp_mlp_forward: bad size or NULL buffer");
   if (!aligned16(in) || !aligned16(out) || !aligned16(ws)) return mp_fail(MP_EINVAL, "mp_mlp_forward: unaligned buffer");
-  if ((const float*)out == in) return mp_fail(MP_EINVAL, "mp_mlp_forward: out must not alias in");
+  if (out == (const void*)in) return mp_fail(MP_EINVAL, "mp_mlp_forward: out must not alias in");
   const MlpWs W(cfg, n_rows, false);
   if (ws_bytes < W.total) return mp_fail(MP_ENOMEM, "mp_mlp_forward: workspace %zu < %zu bytes", ws_bytes, W.total);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -861,11 +872,12 @@ extern "C" int mp_mlp_forward(const mp_mlp_cfg* cfg, const mp_mlp_params* p, int
   m.frag0 = ws_at(ws, W.fr0);
   m.frag1 = ws_at(ws, W.fr1);
   m.out = out;
+  m.out_bf = cfg->out_dtype == MP_BF16;
   return run("mlp_fwd", s, [&] { return launch_mlp_fwd(m, W.grid, s); });
 }
 
 extern "C" int mp_mlp_backward(const mp_mlp_cfg* cfg, const mp_mlp_params* p, int64_t n_rows, const float* in,
-                               const float* g_out, float* g_in, const mp_mlp_grads* gr, void* ws, size_t ws_bytes,
+                               const void* g_out, float* g_in, const mp_mlp_grads* gr, void* ws, size_t ws_bytes,
                                mp_stream_t stream) {
   int rc;
   if ((rc = check_mlp_cfg(cfg)) || (rc = check_mlp_params(cfg, p))) return rc;
@@ -875,7 +887,7 @@ extern "C" int mp_mlp_backward(const mp_mlp_cfg* cfg, const mp_mlp_params* p, in
   if (!aligned16(in) || !aligned16(g_out) || !aligned16(ws) || (g_in && !aligned16(g_in)))
     return mp_fail(MP_EINVAL, "mp_mlp_backward: unaligned buffer");
   if (g_in && cfg->n_in <= 4) return mp_fail(MP_EINVAL, "mp_mlp_backward: no input gradient for n_in <= 4");
-  if (g_in && ((const float*)g_in == g_out || (const float*)g_in == in))
+  if (g_in && ((const void*)g_in == g_out || (const float*)g_in == in))
     return mp_fail(MP_EINVAL, "mp_mlp_backward: g_in must not alias inputs");
   const MlpWs W(cfg, n_rows, true);
   if (ws_bytes < W.total) return mp_fail(MP_ENOMEM, "mp_mlp_backward: workspace %zu < %zu bytes", ws_bytes, W.total);
@@ -903,6 +915,7 @@ extern "C" int mp_mlp_backward(const mp_mlp_cfg* cfg, const mp_mlp_params* p, in
   m.frag1t = ws_at(ws, W.fr1t);
   m.frag0t = g_in ? ws_at(ws, W.fr0t) : nullptr;
   m.g_out = g_out;
+  m.gout_bf = cfg->out_dtype == MP_BF16;
   m.g_src0 = g_in;
   m.part = wsf(ws, W.part);
   m.slab = mlp_slab(H, cfg->n_in, cfg->n_out);

@@ -82,6 +82,22 @@ __device__ __forceinline__ void load_row_bf16(const __bf16* __restrict__ ptr, in
   }
 }
 
+// Row `row` of an [n][W] array stored as FP32 or (BF) BF16.
+template <int W, bool BF>
+__device__ __forceinline__ void store_row_t(void* __restrict__ base, int64_t row, int g, const float (&v)[W / 4]) {
+  if constexpr (BF)
+    store_row_bf16<W>(reinterpret_cast<__bf16*>(base) + row * W, g, v);
+  else
+    store_row<W>(reinterpret_cast<float*>(base) + row * W, g, v);
+}
+template <int W, bool BF>
+__device__ __forceinline__ void load_row_t(const void* __restrict__ base, int64_t row, int g, float (&v)[W / 4]) {
+  if constexpr (BF)
+    load_row_bf16<W>(reinterpret_cast<const __bf16*>(base) + row * W, g, v);
+  else
+    load_row<W>(reinterpret_cast<const float*>(base) + row * W, g, v);
+}
+
 // Per-feature vector (bias, LayerNorm gain) in row-block layout.
 template <int W>
 __device__ __forceinline__ void load_vec(const float* __restrict__ p, int g, float (&v)[W / 4]) {

@@ -176,13 +176,14 @@ hipError_t launch_tiles(const DevGraph& g, int32_t* tile_r, int32_t* tile_e, int
 // holding its last edge; no atomics, so results are bitwise reproducible.
 // AM: aggregate the MLP output (message) instead of the updated state.
 // DQ: take tiles from the per-XCD atomic counters (queue_next) instead of
-// the fixed round robin of tile_sched.
-template <int H, bool BF, bool AM, bool DQ>
+// the fixed round robin of tile_sched.  ES: e_in and e_out hold BF16 (the
+// update and the aggregation run in FP32; e' is rounded where it is stored).
+template <int H, bool BF, bool AM, bool DQ, bool ES>
 __global__ __launch_bounds__(256, (H <= 64 ? 4 : 2)) void k_edge_fwd(DevGraph gr, const float* __restrict__ P,
-                                                  const float* __restrict__ Q, const float* __restrict__ e_in,
+                                                  const float* __restrict__ Q, const void* __restrict__ e_in,
                                                   const void* __restrict__ frag, const float* __restrict__ b2,
                                                   const float* __restrict__ lng, const float* __restrict__ lnb,
-                                                  int ln, float eps, float* __restrict__ e_out,
+                                                  int ln, float eps, void* __restrict__ e_out,
                                                   float* __restrict__ a_out) {
   constexpr int NF = H / 4, MB = H / 16;
   constexpr size_t FB = frag_bytes(H, H, BF);
@@ -254,7 +255,7 @@ __global__ __launch_bounds__(256, (H <= 64 ? 4 : 2)) void k_edge_fwd(DevGraph gr
       }
 
       float ev[NF], h[NF], q[NF];
-      load_row<H>(e_in + kk * H, g, ev);
+      load_row_t<H, ES>(e_in, kk, g, ev);
       load_row<H>(P + (int64_t)ri * H, g, h);
       load_row<H>(Q + (int64_t)sj * H, g, q);
       __builtin_amdgcn_sched_barrier(0);  // all row loads issue before any use
@@ -277,7 +278,7 @@ __global__ __launch_bounds__(256, (H <= 64 ? 4 : 2)) void k_edge_fwd(DevGraph gr
       }
 #pragma unroll
       for (int i = 0; i < NF; ++i) ev[i] += m[i];
-      if (valid && e_out) store_row<H>(e_out + k * H, g, ev);  // no e' for a last layer
+      if (valid && e_out) store_row_t<H, ES>(e_out, k, g, ev);  // no e' for a last layer
 
       // aggregation: segmented scan of e'/d across the block, plus carry.
       // Lanes past the tile's last edge (finite values from an in-bounds
@@ -312,40 +313,47 @@ __global__ __launch_bounds__(256, (H <= 64 ? 4 : 2)) void k_edge_fwd(DevGraph gr
   }
 }
 
-template <int H, bool BF, bool AM, bool DQ>
-static hipError_t launch_edge_fwd_t(const DevGraph& g, const float* P, const float* Q, const float* e_in,
+template <int H, bool BF, bool AM, bool DQ, bool ES>
+static hipError_t launch_edge_fwd_t(const DevGraph& g, const float* P, const float* Q, const void* e_in,
                                     const void* frag, const float* b2, const float* lng, const float* lnb, int ln,
-                                    float eps, float* e_out, float* a_out, int grid, hipStream_t s) {
+                                    float eps, void* e_out, float* a_out, int grid, hipStream_t s) {
   constexpr size_t FB = frag_bytes(H, H, BF);
   // fragments, 3 per-feature vectors, per-wave carries (4 waves)
   const size_t lds = ((2 * FB <= kEdgeLdsBudget) ? 2 * FB : 0) + 3 * H * sizeof(float) + 4 * H * sizeof(float);
   if (lds > 64 * 1024)
-    (void)hipFuncSetAttribute((const void*)k_edge_fwd<H, BF, AM, DQ>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute((const void*)k_edge_fwd<H, BF, AM, DQ, ES>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds);
-  hipLaunchKernelGGL((k_edge_fwd<H, BF, AM, DQ>), dim3(grid), dim3(256), lds, s, g, P, Q, e_in, frag, b2, lng, lnb, ln,
-                     eps, e_out, a_out);
+  hipLaunchKernelGGL((k_edge_fwd<H, BF, AM, DQ, ES>), dim3(grid), dim3(256), lds, s, g, P, Q, e_in, frag, b2, lng, lnb,
+                     ln, eps, e_out, a_out);
   return hipGetLastError();
 }
 
-template <int H, bool BF>
+template <int H, bool BF, bool ES>
 static hipError_t launch_edge_fwd_am(bool am, bool dq, const DevGraph& g, const float* P, const float* Q,
-                                     const float* e_in, const void* frag, const float* b2, const float* lng,
-                                     const float* lnb, int ln, float eps, float* e_out, float* a_out, int grid,
+                                     const void* e_in, const void* frag, const float* b2, const float* lng,
+                                     const float* lnb, int ln, float eps, void* e_out, float* a_out, int grid,
                                      hipStream_t s) {
 #define MP_EFWD(AMV, DQV) \
-  launch_edge_fwd_t<H, BF, AMV, DQV>(g, P, Q, e_in, frag, b2, lng, lnb, ln, eps, e_out, a_out, grid, s)
+  launch_edge_fwd_t<H, BF, AMV, DQV, ES>(g, P, Q, e_in, frag, b2, lng, lnb, ln, eps, e_out, a_out, grid, s)
   if (dq) return am ? MP_EFWD(true, true) : MP_EFWD(false, true);
   return am ? MP_EFWD(true, false) : MP_EFWD(false, false);
 #undef MP_EFWD
 }
 
-hipError_t launch_edge_fwd(int H, bool ln, bool bf, bool am, bool dq, const DevGraph& g, const float* P, const float* Q,
-                           const float* e_in, const void* frag, const float* b2, const float* lng, const float* lnb,
-                           float eps, float* e_out, float* a_out, int grid, hipStream_t s) {
-#define MP_CASE(HH)                                                                                           \
-  if (H == HH)                                                                                                \
-    return bf ? launch_edge_fwd_am<HH, true>(am, dq, g, P, Q, e_in, frag, b2, lng, lnb, ln, eps, e_out, a_out, grid, s) \
-              : launch_edge_fwd_am<HH, false>(am, dq, g, P, Q, e_in, frag, b2, lng, lnb, ln, eps, e_out, a_out, grid, s);
+hipError_t launch_edge_fwd(int H, bool ln, bool bf, bool am, bool dq, bool es, const DevGraph& g, const float* P,
+                           const float* Q, const void* e_in, const void* frag, const float* b2, const float* lng,
+                           const float* lnb, float eps, void* e_out, float* a_out, int grid, hipStream_t s) {
+  if (es && !bf) return hipErrorInvalidValue;  // BF16 edge states go with BF16 products
+#define MP_CASE(HH)                                                                                              \
+  if (H == HH) {                                                                                                 \
+    if (bf && es)                                                                                                \
+      return launch_edge_fwd_am<HH, true, true>(am, dq, g, P, Q, e_in, frag, b2, lng, lnb, ln, eps, e_out, a_out, \
+                                                grid, s);                                                        \
+    return bf ? launch_edge_fwd_am<HH, true, false>(am, dq, g, P, Q, e_in, frag, b2, lng, lnb, ln, eps, e_out,    \
+                                                    a_out, grid, s)                                              \
+              : launch_edge_fwd_am<HH, false, false>(am, dq, g, P, Q, e_in, frag, b2, lng, lnb, ln, eps, e_out,   \
+                                                     a_out, grid, s);                                            \
+  }
   MP_CASE(32) MP_CASE(64) MP_CASE(128)
 #undef MP_CASE
   return hipErrorInvalidValue;
@@ -452,7 +460,9 @@ struct MlpFwdCfg {
   static constexpr size_t LDS = FRAG_LDS + SMALL + VECS;
 };
 
-template <int H, int KIN, bool TIN, bool TOUT, bool BF>
+// OB: the H-wide output is stored as BF16 (the edge encoder's output, an
+// edge state, when edge states are BF16).
+template <int H, int KIN, bool TIN, bool TOUT, bool BF, bool OB>
 __global__ __launch_bounds__(256, (H <= 64 ? 4 : 1)) void k_mlp_fwd(MlpFwdArgs a) {
   using C = MlpFwdCfg<H, KIN, TIN, TOUT, BF>;
   constexpr int NF = H / 4, MB = H / 16, KB = TIN ? 1 : KIN / 16;
@@ -522,7 +532,7 @@ __global__ __launch_bounds__(256, (H <= 64 ? 4 : 1)) void k_mlp_fwd(MlpFwdArgs a
       }
       nx.settle();  // next block's loads complete before this block's stores
       for (int o = 0; o < a.n_out; ++o)
-        if (valid && g == 0) a.out[row * a.n_out + o] = p[o] + a.b1[o];
+        if (valid && g == 0) reinterpret_cast<float*>(a.out)[row * a.n_out + o] = p[o] + a.b1[o];
     } else {
       float y[NF];
       load_vec<H>(vb + H, g, y);
@@ -547,20 +557,20 @@ __global__ __launch_bounds__(256, (H <= 64 ? 4 : 1)) void k_mlp_fwd(MlpFwdArgs a
         }
       }
       nx.settle();  // next block's loads complete before this block's stores
-      if (valid) store_row<H>(a.out + row * H, g, y);
+      if (valid) store_row_t<H, OB>(a.out, row, g, y);
     }
   }
 }
 
-template <int H, int KIN, bool TIN, bool TOUT, bool BF>
+template <int H, int KIN, bool TIN, bool TOUT, bool BF, bool OB = false>
 static hipError_t launch_mlp_fwd_t(const MlpFwdArgs& a, int grid, hipStream_t s) {
   using C = MlpFwdCfg<H, KIN, TIN, TOUT, BF>;
   // residual rows other than src1 exist only for the H-input form
   if (a.resid && !(KIN == H && !TIN && !TOUT) && !(KIN == 2 * H && a.resid == a.src1)) return hipErrorInvalidValue;
   if (C::LDS > 64 * 1024)
-    (void)hipFuncSetAttribute((const void*)k_mlp_fwd<H, KIN, TIN, TOUT, BF>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)C::LDS);
-  hipLaunchKernelGGL((k_mlp_fwd<H, KIN, TIN, TOUT, BF>), dim3(grid), dim3(256), C::LDS, s, a);
+    (void)hipFuncSetAttribute((const void*)k_mlp_fwd<H, KIN, TIN, TOUT, BF, OB>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)C::LDS);
+  hipLaunchKernelGGL((k_mlp_fwd<H, KIN, TIN, TOUT, BF, OB>), dim3(grid), dim3(256), C::LDS, s, a);
   return hipGetLastError();
 }
 
@@ -568,6 +578,10 @@ template <int H, bool BF>
 static hipError_t launch_mlp_fwd_h(const MlpFwdArgs& a, int grid, hipStream_t s) {
   const bool tin = a.k0 <= 4, tout = a.n_out < 16;
   const int kin = a.k0 + a.k1;
+  if (a.out_bf && !(tin && !tout && BF)) return hipErrorInvalidValue;
+  if constexpr (BF) {
+    if (tin && !tout && a.out_bf) return launch_mlp_fwd_t<H, 4, true, false, BF, true>(a, grid, s);
+  }
   if (tin && !tout) return launch_mlp_fwd_t<H, 4, true, false, BF>(a, grid, s);
   if (!tin && kin == H && tout) return launch_mlp_fwd_t<H, H, false, true, BF>(a, grid, s);
   if (!tin && kin == H && !tout) return launch_mlp_fwd_t<H, H, false, false, BF>(a, grid, s);

@@ -57,10 +57,10 @@ hipError_t launch_proj(int H, bool bf, const DevGraph& g, const float* x, const 
 
 // am: aggregate the edge MLP's output (message) instead of the updated state;
 // dq: waves take tiles from per-XCD atomic counters (g.queue) instead of a
-// fixed round robin
-hipError_t launch_edge_fwd(int H, bool ln, bool bf, bool am, bool dq, const DevGraph& g, const float* P, const float* Q,
-                           const float* e_in, const void* frag_c2, const float* b2, const float* lng,
-                           const float* lnb, float eps, float* e_out, float* a_out, int grid,
+// fixed round robin; es: edge states e_in / e_out stored as BF16 (with bf only)
+hipError_t launch_edge_fwd(int H, bool ln, bool bf, bool am, bool dq, bool es, const DevGraph& g, const float* P,
+                           const float* Q, const void* e_in, const void* frag_c2, const float* b2,
+                           const float* lng, const float* lnb, float eps, void* e_out, float* a_out, int grid,
                            hipStream_t s);
 
 hipError_t launch_halo(int H, const DevGraph& g, float* a, hipStream_t s);
@@ -84,7 +84,8 @@ struct MlpFwdArgs {
   float eps;
   const void* frag0;  // packed W0 (when k0 >= 16)
   const void* frag1;  // packed W1 (when n_out == H)
-  float* out;
+  void* out;          // [n][n_out], FP32, or BF16 with out_bf
+  int out_bf;         // small-input form with BF16 GEMMs and n_out == H only
 };
 hipError_t launch_mlp_fwd(const MlpFwdArgs& a, int grid, hipStream_t s);
 
@@ -131,18 +132,19 @@ struct EdgeBwdArgs {
   int H, ln, bf;
   int am;  // the forward aggregated the MLP output (message), not e'
   int waves;  // waves per workgroup of the fused kernel: 0 (default), 4, or 8 (BF16, H <= 64)
+  int es;     // edge states and their gradients (e_in, g_e_out, g_e_in) stored as BF16 (with bf only)
 
   const float* P;
   const float* Q;
-  const float* e_in;
-  const float* g_e_out;  // may be null
+  const void* e_in;
+  const void* g_e_out;   // may be null
   const float* g_a;      // gradient of a (after the adjoint halo sum)
   const void* frag;      // W1c, W2, W2^T, W1c^T fragments, consecutive
   const float* b2;
   const float* lng;
   const float* lnb;
   float eps;
-  float* g_e_in;
+  void* g_e_in;
   void* g_h;             // [E][H] gradient of the first pre-activation (BF16 on the BF16 path)
   float* g_P;            // [N][H] sum of g_h over each row's incoming edges
   float* part;           // partial weight gradients, slab per workgroup
@@ -195,7 +197,8 @@ struct MlpBwdArgs {
   const void* frag1;   // W1 (n_out == H)
   const void* frag1t;  // W1^T (n_out == H)
   const void* frag0t;  // W0^T (k0 >= 16 and an input gradient is wanted)
-  const float* g_out;
+  const void* g_out;   // [n][n_out], FP32, or BF16 with gout_bf
+  int gout_bf;         // small-input form with BF16 GEMMs and n_out == H only
   float* g_src0;       // may be null
   float* g_src1;       // may be null
   const float* g_add1; // added to g_src1 (residual path); may be null

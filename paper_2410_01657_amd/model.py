@@ -68,14 +68,17 @@ class ConsistentGNN:
     LAYER_ORDER = ["We1", "be1", "We2", "be2", "ge", "bge", "Wn1", "bn1", "Wn2", "bn2", "gn", "bgn"]
     MLP_ORDER = ["W0", "b0", "W1", "b1", "ln_g", "ln_b"]
 
-    def __init__(self, spec, params, device="cuda", gemm="f32", halo=True, schedule=None):
+    def __init__(self, spec, params, device="cuda", gemm="f32", halo=True, schedule=None, estate="f32"):
         # Table I's narrow models (extra hidden layers, H = 8/16/32) run on
         # the deep-MLP kernels; two-Linear MLPs at H = 32/64/128 on the
-        # matrix-core kernels.
+        # matrix-core kernels.  estate: storage type of the edge states
+        # between layers and of their gradients ("bf16" with gemm="bf16").
         self.deep = spec.n_hidden > 0 or spec.H in (8, 16)
         if self.deep and (gemm != "f32" or spec.H not in (8, 16, 32)):
             raise ValueError("deep MLPs run in FP32 at H = 8, 16 or 32")
-        self.spec, self.gemm, self.halo = spec, gemm, halo
+        if estate not in ("f32", "bf16") or (estate == "bf16" and gemm != "bf16"):
+            raise ValueError("estate is 'f32', or 'bf16' with gemm='bf16'")
+        self.spec, self.gemm, self.halo, self.estate = spec, gemm, halo, estate
         # edge-kernel schedule: None (library defaults) or a dict of
         # mp_layer_cfg schedule fields (see autotune.SCHEDULE_FIELDS)
         self.schedule = schedule
@@ -87,7 +90,7 @@ class ConsistentGNN:
         """Checkpoint the parameters, the spec and `meta` (see
         save_checkpoint); ConsistentGNN(spec, load_checkpoint(path)[0], ...)
         resumes from it."""
-        save_checkpoint(path, self.params, self.spec, gemm=self.gemm, **meta)
+        save_checkpoint(path, self.params, self.spec, gemm=self.gemm, estate=self.estate, **meta)
 
     def requires_grad_(self, flag=True):
         for t in self.params.values():
@@ -101,20 +104,20 @@ class ConsistentGNN:
             names += [f"{prefix}.ln.g", f"{prefix}.ln.b"]
         return torch.cat([self.params[n].reshape(-1) for n in names])
 
-    def _mlp(self, prefix, x, n_in, n_out, ln):
+    def _mlp(self, prefix, x, n_in, n_out, ln, out="f32"):
         if self.deep:
             s = self.spec
             cfg = deep_mlp_cfg(n_in, s.H, s.n_hidden, n_out, ln, s.ln_eps)
             return DeepMLPFn.apply(cfg, x, self._theta(prefix, ln))
         names = _mlp_param_names(prefix, ln)
-        cfg = mlp_cfg(n_in, self.spec.H, n_out, ln, self.gemm, self.spec.ln_eps)
+        cfg = mlp_cfg(n_in, self.spec.H, n_out, ln, self.gemm, self.spec.ln_eps, out)
         args = [self.params[names[f]] if f in names else None for f in self.MLP_ORDER]
         return MLPFn.apply(cfg, x, *args)
 
     def encode(self, X, E0):
         s = self.spec
         x = self._mlp("nenc", X, s.node_in, s.H, s.layernorm)
-        e = self._mlp("eenc", E0, s.edge_in, s.H, s.layernorm)
+        e = self._mlp("eenc", E0, s.edge_in, s.H, s.layernorm, self.estate)  # an edge state
         return x, e
 
     def process(self, dg, x, e, want_e=False):
@@ -128,7 +131,7 @@ class ConsistentGNN:
                 x, e = DeepLayerFn.apply(cfg, dg, x, e, self._theta(f"mp{m}.edge", s.layernorm),
                                          self._theta(f"mp{m}.node", s.layernorm))
             return x, e
-        cfg = layer_cfg(s.H, s.layernorm, self.halo, self.gemm, s.ln_eps, s.aggregate)
+        cfg = layer_cfg(s.H, s.layernorm, self.halo, self.gemm, s.ln_eps, s.aggregate, self.estate)
         if self.schedule:
             apply_schedule(cfg, self.schedule)
         for m in range(s.n_layers):

@@ -56,11 +56,24 @@ WS = _Workspace()
 _AGG = {"state": 0, "message": 1}
 
 
-def layer_cfg(H, layernorm=True, halo=True, gemm="f32", ln_eps=1e-5, aggregate="state"):
+def layer_cfg(H, layernorm=True, halo=True, gemm="f32", ln_eps=1e-5, aggregate="state", estate="f32"):
+    """estate: storage type of the edge states and their gradients, "f32",
+    or "bf16" (with gemm="bf16")."""
     c = MpLayerCfg()
     c.H, c.layernorm, c.halo, c.gemm_dtype, c.ln_eps = H, int(layernorm), int(halo), _GEMM[gemm], ln_eps
     c.aggregate = _AGG[aggregate]
+    c.estate_dtype = _GEMM[estate]
     return c
+
+
+def estate_dtype(cfg):
+    """torch dtype of a layer's edge states under cfg."""
+    return torch.bfloat16 if cfg.estate_dtype == _GEMM["bf16"] else torch.float32
+
+
+def _check_dtype(t, dtype, what):
+    if t is not None and t.dtype != dtype:
+        raise ValueError(f"{what} must be {dtype} (got {t.dtype})")
 
 
 def _layer_params(p):
@@ -76,6 +89,7 @@ def layer_forward(cfg, p, dg, x, e, want_pq=False, want_e=True):
     want_e=False: the updated edge state is not written (e_out is None), for
     a last layer whose e' nothing reads."""
     _check(x, e)
+    _check_dtype(e, estate_dtype(cfg), "the edge state")
     x_out, a_star = torch.empty_like(x), torch.empty_like(x)
     e_out = torch.empty_like(e) if want_e else None
     pq = torch.empty((2,) + tuple(x.shape), dtype=x.dtype, device=x.device) if want_pq else None
@@ -92,6 +106,7 @@ def layer_forward_noalloc(cfg, p, dg, x, e):
     scratch is a library-held module array); returns (x_out, e_out, a_star,
     pq).  The outputs here are torch tensors the caller allocates."""
     _check(x, e)
+    _check_dtype(e, estate_dtype(cfg), "the edge state")
     x_out, e_out, a_star = torch.empty_like(x), torch.empty_like(e), torch.empty_like(x)
     pq = torch.empty((2,) + tuple(x.shape), dtype=x.dtype, device=x.device)
     call("mp_layer_forward_noalloc", C.byref(cfg), C.byref(_layer_params(p)), C.byref(dg.desc), _p(x), _p(e),
@@ -103,6 +118,8 @@ def layer_backward(cfg, p, dg, x, e, a_star, g_x_out, g_e_out, pq=None):
     """Adjoint of layer_forward; pq (from layer_forward(want_pq=True)) skips
     recomputing the node projections."""
     _check(x, e, a_star, g_x_out, g_e_out, pq)
+    _check_dtype(e, estate_dtype(cfg), "the edge state")
+    _check_dtype(g_e_out, estate_dtype(cfg), "the edge-state gradient")
     g_x, g_e = torch.empty_like(x), torch.empty_like(e)
     grads = {f: (torch.empty_like(p[f]) if p.get(f) is not None else None) for f in LAYER_FIELDS}
     gs = MpLayerGrads()
@@ -146,10 +163,17 @@ class MPLayerFn(torch.autograd.Function):
 
 # -------------------------------------------------------------------- MLPs
 
-def mlp_cfg(n_in, H, n_out, layernorm, gemm="f32", ln_eps=1e-5):
+def mlp_cfg(n_in, H, n_out, layernorm, gemm="f32", ln_eps=1e-5, out="f32"):
+    """out: storage type of the output and its gradient, "f32", or "bf16"
+    (the edge encoder of a model with BF16 edge states)."""
     c = MpMlpCfg()
     c.n_in, c.H, c.n_out, c.layernorm, c.gemm_dtype, c.ln_eps = n_in, H, n_out, int(layernorm), _GEMM[gemm], ln_eps
+    c.out_dtype = _GEMM[out]
     return c
+
+
+def _mlp_out_dtype(cfg):
+    return torch.bfloat16 if cfg.out_dtype == _GEMM["bf16"] else torch.float32
 
 
 def _mlp_params(p):
@@ -161,7 +185,7 @@ def _mlp_params(p):
 
 def mlp_forward(cfg, p, x):
     _check(x)
-    out = torch.empty((x.shape[0], cfg.n_out), dtype=torch.float32, device=x.device)
+    out = torch.empty((x.shape[0], cfg.n_out), dtype=_mlp_out_dtype(cfg), device=x.device)
     nb = C.c_size_t()
     call("mp_mlp_workspace_size", C.byref(cfg), x.shape[0], 0, C.byref(nb))
     ws = WS.get(nb.value, x.device)
@@ -172,6 +196,7 @@ def mlp_forward(cfg, p, x):
 
 def mlp_backward(cfg, p, x, g_out, want_g_in):
     _check(x, g_out)
+    _check_dtype(g_out, _mlp_out_dtype(cfg), "the output gradient")
     g_in = torch.empty_like(x) if want_g_in else None
     grads = {f: (torch.empty_like(p[f]) if p.get(f) is not None else None) for f in MLP_FIELDS}
     gs = MpMlpGrads()

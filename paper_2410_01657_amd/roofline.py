@@ -2,7 +2,8 @@
 through HBM and the flops it must execute, independent of how it is built.
 
 Units: N rows (node copies over all sub-graphs), E directed sub-graph edges,
-G halo groups with M members, hidden width H, FP32 node and edge states.
+G halo groups with M members, hidden width H, FP32 node states, FP32 or BF16
+edge states.
 Index arrays: int32 receiver and sender per edge plus a uint8 degree;
 int32 reverse-edge and row-offset arrays where a kernel follows them.
 Each row or edge is counted once per kernel even when it is gathered several
@@ -43,13 +44,14 @@ def gq_split(H, gemm):
     return H > 64 and gemm == "f32"
 
 
-def layer_kernels(N, E, G, M, H, gemm="bf16", n_layers=1):
+def layer_kernels(N, E, G, M, H, gemm="bf16", n_layers=1, estate="f32"):
     """Per launch, for one layer; keys match the library's profile names.
 
     gemm: "bf16" stores the edge-state adjoint g_h in BF16 (2 bytes per
     value), "f32" in FP32.  n_layers: the adjoint kernels are averaged over
     the layers of a model, whose last layer gets no gradient at its edge
-    output (g_e' is absent there).
+    output (g_e' is absent there).  estate: storage type of the edge states
+    e, e' and their gradients ("bf16": 2 bytes per value).
 
     At H > 64 the edge and node adjoints (and, in FP32, the sender-side
     pass) run split: the first pass recomputes the MLP and forms the input
@@ -60,13 +62,14 @@ def layer_kernels(N, E, G, M, H, gemm="bf16", n_layers=1):
     it must read (one launch of edge_dw / node_dw / gq_dw stands for all of
     that pass's launches in a layer)."""
     f = 4.0                              # bytes per FP32 value
+    fe = 2.0 if estate == "bf16" else 4.0  # bytes per edge-state value
     fh = 2.0 if gemm == "bf16" else 4.0  # bytes per g_h value (and per stored factor)
     ge = (n_layers - 1) / n_layers if n_layers > 1 else 1.0  # launches that read g_e'
     w = {
         # x -> P = W1a x + b1, Q = W1b x
         "proj": Work(N * 3 * H * f, N * 2 * 2 * H * H),
         # e, P_i, Q_j -> e', a ; per edge 2 H x H products
-        "edge_fwd": Work(E * (2 * H * f + 9) + N * 3 * H * f, E * 2 * 2 * H * H),
+        "edge_fwd": Work(E * (2 * H * fe + 9) + N * 3 * H * f, E * 2 * 2 * H * H),
         # every member row read and written once, plus the plan
         "halo": Work(M * 2 * H * f + 4 * (M + G + 1), 0.0),
         "halo_adj": Work(M * 2 * H * f + 4 * (M + G + 1), 0.0),
@@ -75,7 +78,7 @@ def layer_kernels(N, E, G, M, H, gemm="bf16", n_layers=1):
         # a*, x, g_x' -> g_a*, g_x ; recompute (3H^2) + input grads (3H^2) + weight grads (3H^2)
         "node_bwd": Work(N * 5 * H * f, N * 2 * 9 * H * H),
         # e, [g_e'], P_i, Q_j, g_a_i -> g_e, g_h, g_P ; 6 H x H products per edge
-        "edge_bwd": Work(E * ((2 + ge) * H * f + H * fh + 9) + N * 4 * H * f, E * 2 * 6 * H * H),
+        "edge_bwd": Work(E * ((2 + ge) * H * fe + H * fh + 9) + N * 4 * H * f, E * 2 * 6 * H * H),
         # g_P, g_h (through reverse edges), x, g_x -> g_x ; 2 (2H x H) products per node
         "gq": Work(E * (H * fh + 4) + N * (4 * H * f + 4), N * 2 * 4 * H * H),
     }
@@ -83,7 +86,7 @@ def layer_kernels(N, E, G, M, H, gemm="bf16", n_layers=1):
         # pass 1: recompute (W1c, W2) and the input-gradient products (W2^T, W1c^T)
         w["edge_bwd"] = Work(w["edge_bwd"].bytes, E * 2 * 4 * H * H)
         # pass 2: dW1c = sum g_h e^T, dW2 = sum gm u^T (+ LayerNorm sums)
-        w["edge_dw"] = Work(E * (H * fh + H * f + 2 * H * fh + 2 * H * fh), E * 2 * 2 * H * H)
+        w["edge_dw"] = Work(E * (H * fh + H * fe + 2 * H * fh + 2 * H * fh), E * 2 * 2 * H * H)
     if node_bwd_split(H):
         w["node_bwd"] = Work(w["node_bwd"].bytes, N * 2 * 6 * H * H)
         # dW1 = sum g_y u^T, dW0 = sum g_z [a*, x]^T (+ LayerNorm sums)
@@ -101,7 +104,7 @@ LAYER_KERNEL_NAMES = ("pack", "tiles", "proj", "edge_fwd", "halo", "halo_adj", "
                       "edge_bwd", "edge_dw", "node_dw", "gq", "gq_dw", "wreduce")
 
 
-def layer_roof_seconds(N, E, G, M, H, gemm, n_layers, hbm=None, peak=None):
+def layer_roof_seconds(N, E, G, M, H, gemm, n_layers, hbm=None, peak=None, estate="f32"):
     """Lower bound on the time of the message-passing layers' forward and
     adjoint: every kernel of every layer at the higher of its HBM floor
     (algorithmic bytes / bandwidth) and its product floor (flops / matrix
@@ -109,7 +112,7 @@ def layer_roof_seconds(N, E, G, M, H, gemm, n_layers, hbm=None, peak=None):
     figures."""
     hbm = PEAK_HBM if hbm is None else hbm
     peak = PEAK[gemm] if peak is None else peak
-    w = layer_kernels(N, E, G, M, H, gemm, n_layers)
+    w = layer_kernels(N, E, G, M, H, gemm, n_layers, estate)
     return n_layers * sum(max(k.bytes / hbm, k.flops / peak) for k in w.values())
 
 

@@ -36,7 +36,7 @@ def test_exports_every_declared_symbol(L):
     for name in declared:
         assert hasattr(lib, name), name
     assert set(declared) == set(L.EXPORTED)
-    assert lib.mp_abi_version() == L.ABI_VERSION == 3
+    assert lib.mp_abi_version() == L.ABI_VERSION == 4
 
 
 def test_hex_links_counts():
@@ -516,3 +516,31 @@ def test_schedule_fields_are_validated(L):
             for k, v in sched.items():
                 setattr(cfg, k, v)
             call("mp_layer_workspace_size", C.byref(cfg), C.byref(d), 1, C.byref(nb))
+
+
+def test_edge_state_dtype_is_validated(L):
+    """BF16 edge states (estate_dtype) need BF16 GEMMs; a BF16 MLP output
+    exists for the edge encoder's form only (small input, n_out == H, BF16
+    GEMMs); other values are refused before any launch."""
+    from paper_2410_01657_amd._lib import MPError, call
+    from paper_2410_01657_amd.ops import layer_cfg, mlp_cfg
+    d = _fake_desc(L)
+    nb = C.c_size_t()
+    for H in (32, 64, 128):
+        call("mp_layer_workspace_size", C.byref(layer_cfg(H, gemm="bf16", estate="bf16")), C.byref(d), 1,
+             C.byref(nb))
+        with pytest.raises(MPError) as e:
+            call("mp_layer_workspace_size", C.byref(layer_cfg(H, gemm="f32", estate="bf16")), C.byref(d), 1,
+                 C.byref(nb))
+        assert e.value.code == L.MP_EINVAL
+    cfg = layer_cfg(64, gemm="bf16")
+    cfg.estate_dtype = 2
+    with pytest.raises(MPError) as e:
+        call("mp_layer_workspace_size", C.byref(cfg), C.byref(d), 0, C.byref(nb))
+    assert e.value.code == L.MP_EINVAL
+    call("mp_mlp_workspace_size", C.byref(mlp_cfg(4, 64, 64, True, gemm="bf16", out="bf16")), 10, 1, C.byref(nb))
+    for bad in (mlp_cfg(4, 64, 64, True, gemm="f32", out="bf16"), mlp_cfg(64, 64, 64, True, gemm="bf16", out="bf16"),
+                mlp_cfg(64, 64, 3, False, gemm="bf16", out="bf16")):
+        with pytest.raises(MPError) as e:
+            call("mp_mlp_workspace_size", C.byref(bad), 10, 0, C.byref(nb))
+        assert e.value.code == L.MP_EINVAL

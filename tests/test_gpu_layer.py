@@ -272,3 +272,90 @@ def test_layer_forward_without_edge_output(c0, gemm):
     g1 = layer_backward(cfg, p, dg, x, e, a, gx, None, pq)
     g2 = layer_backward(cfg, p, dg, x, e, a2, gx, None, pq2)
     assert torch.equal(g1[0], g2[0]) and torch.equal(g1[1], g2[1])
+
+
+# ------------------------------------------- BF16 edge-state storage
+
+
+def _bf16(a):
+    """FP32 array -> BF16 tensor on the device (round to nearest even)."""
+    return _t(a).to(torch.bfloat16)
+
+
+@pytest.mark.parametrize("H,ln,agg,R", [(32, False, "state", 8), (64, True, "state", 8), (64, True, "message", 1),
+                                        (128, True, "state", 8), (128, False, "message", 8)])
+def test_edge_state_bf16_is_the_rounded_fp32_state(c0, H, ln, agg, R):
+    """BF16 edge-state storage changes only what is stored: given the same
+    BF16-representable e and g_e', the layer computes exactly what the
+    FP32-state layer computes (x', a*, P/Q, g_x and every parameter
+    gradient bitwise equal) and stores e' and g_e rounded to nearest even."""
+    from paper_2410_01657_amd.ops import layer_backward, layer_cfg, layer_forward
+    dg, og, pairs = c0[1][R]
+    spec, o, names = layer_params(H, ln)
+    rng = np.random.default_rng(40 + H)
+    x = _t(rng.standard_normal((dg.n_rows, H)))
+    e16 = _bf16(rng.standard_normal((dg.n_edges, H)))
+    gx = _t(rng.standard_normal((dg.n_rows, H)))
+    ge16 = _bf16(rng.standard_normal((dg.n_edges, H)))
+    p = _lib_params(o, names)
+    c32 = layer_cfg(H, ln, gemm="bf16", aggregate=agg)
+    c16 = layer_cfg(H, ln, gemm="bf16", aggregate=agg, estate="bf16")
+    xo, eo, a, pq = layer_forward(c32, p, dg, x, e16.float(), want_pq=True)
+    xo2, eo2, a2, pq2 = layer_forward(c16, p, dg, x, e16, want_pq=True)
+    assert eo2.dtype == torch.bfloat16
+    assert torch.equal(xo, xo2) and torch.equal(a, a2) and torch.equal(pq, pq2)
+    assert torch.equal(eo.to(torch.bfloat16), eo2)
+    for g_e_out in (ge16, None):   # a middle layer, and a last layer (no g_e')
+        g1 = layer_backward(c32, p, dg, x, e16.float(), a, gx, None if g_e_out is None else g_e_out.float(), pq)
+        g2 = layer_backward(c16, p, dg, x, e16, a2, gx, g_e_out, pq2)
+        assert g2[1].dtype == torch.bfloat16
+        assert torch.equal(g1[0], g2[0])
+        assert torch.equal(g1[1].to(torch.bfloat16), g2[1])
+        for k in names:
+            assert torch.equal(g1[2][k], g2[2][k]), k
+
+
+@pytest.mark.parametrize("H,ln,R", [(32, False, 8), (64, True, 8), (128, True, 1)])
+def test_edge_state_bf16_against_the_oracle(c0, H, ln, R):
+    """Forward and adjoint with BF16 edge states against the FP64 oracle
+    (Eq. 4a-e, Eq. 3) on the same BF16-representable e and g_e', at the
+    BF16-GEMM tolerances."""
+    from paper_2410_01657_amd.ops import layer_backward, layer_cfg, layer_forward
+    dg, og, pairs = c0[1][R]
+    spec, o, names = layer_params(H, ln)
+    rng = np.random.default_rng(70 + H)
+    x = rng.standard_normal((dg.n_rows, H)).astype(np.float32)
+    e16 = _bf16(rng.standard_normal((dg.n_edges, H)))
+    gx = rng.standard_normal((dg.n_rows, H)).astype(np.float32)
+    ge16 = _bf16(rng.standard_normal((dg.n_edges, H)))
+    e, ge = e16.float().cpu().numpy(), ge16.float().cpu().numpy()
+    cfg = layer_cfg(H, ln, gemm="bf16", estate="bf16")
+    p = _lib_params(o, names)
+    xg, eg, ag = layer_forward(cfg, p, dg, _t(x), e16)
+    g_x, g_e, grads = layer_backward(cfg, p, dg, _t(x), e16, ag, _t(gx), ge16)
+    xr, er, ar, cache, xs, es = _oracle_layer(o, spec, og, pairs, x, e)
+    for got, ref in ((ag, ar), (eg, er), (xg, xr)):
+        err = normwise(got.float().cpu().numpy(), ref)
+        assert 1e-6 < err < 3e-2, err
+    n_off = [0] + list(np.cumsum([G.n for G in og]))
+    e_off = [0] + list(np.cumsum([G.e for G in og]))
+    ogr = {}
+    gxs, ges = nmp_layer_bwd(o, 0, spec, og, pairs, cache, split_rows(gx.astype(np.float64), n_off),
+                             split_rows(ge.astype(np.float64), e_off), ogr)
+    assert normwise(g_x.cpu().numpy(), np.concatenate(gxs)) < 5e-2
+    assert normwise(g_e.float().cpu().numpy(), np.concatenate(ges)) < 5e-2
+    for k, v in names.items():
+        err = normwise(grads[k].cpu().numpy(), ogr[v])
+        assert err < 5e-2, (k, err)
+
+
+def test_edge_state_dtype_mismatch_is_rejected(c0):
+    from paper_2410_01657_amd.ops import layer_cfg, layer_forward
+    dg, og, pairs = c0[1][8]
+    spec, o, names = layer_params(32, False)
+    x = torch.zeros(dg.n_rows, 32, device=DEV)
+    e = torch.zeros(dg.n_edges, 32, device=DEV)
+    with pytest.raises(ValueError):
+        layer_forward(layer_cfg(32, False, gemm="bf16", estate="bf16"), _lib_params(o, names), dg, x, e)
+    with pytest.raises(ValueError):
+        layer_forward(layer_cfg(32, False, gemm="bf16"), _lib_params(o, names), dg, x, e.to(torch.bfloat16))

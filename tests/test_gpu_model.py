@@ -17,10 +17,10 @@ pytestmark = pytest.mark.gpu
 DEV = "cuda"
 
 
-def _gpu_run(spec, params, inp, part, R, gemm="f32", backward=True):
+def _gpu_run(spec, params, inp, part, R, gemm="f32", backward=True, estate="f32"):
     from paper_2410_01657_amd.model import ConsistentGNN, Problem
     prob = Problem(inp.mesh, inp.field, inp.target, part, R, DEV)
-    model = ConsistentGNN(spec, params, DEV, gemm=gemm).requires_grad_(backward)
+    model = ConsistentGNN(spec, params, DEV, gemm=gemm, estate=estate).requires_grad_(backward)
     Y = model.forward(prob.dg, prob.X, prob.E0)
     loss = model.loss(prob.dg, Y, prob.T)
     grads = None
@@ -76,6 +76,49 @@ def test_model_bf16_error_bounded():
     worst = max(errs, key=errs.get)
     print(f"C0 H64-LN BF16: output {normwise(Yg, Yo):.2e}, worst parameter gradient {errs[worst]:.2e} ({worst})")
     assert errs[worst] < 5e-2, (worst, errs[worst])
+
+
+@pytest.mark.parametrize("model", ["H64-LN", "C3-model"])
+def test_model_bf16_edge_state_error_bounded(model):
+    """The model with BF16 GEMMs and BF16 edge states (encoder output,
+    layer edge states and their gradients) against the FP64 oracle, at the
+    BF16 tolerances."""
+    spec = MODELS[model]
+    inp = make_inputs(CONFIGS["C0"], perturb=True, spec=spec)
+    prob, Yg, Lg, gg = _gpu_run(spec, inp.params, inp, inp.elem_part, 8, gemm="bf16", estate="bf16")
+    Yg = Yg[oracle_row_order(prob.dg.host)]
+    Yo, Lo, go = _oracle_run(spec, inp.params, inp, inp.elem_part, 8)
+    assert normwise(Yg, Yo) < 3e-2
+    assert abs(Lg - Lo) / abs(Lo) < 3e-2
+    errs = {k: normwise(gg[k], go[k]) for k in go}
+    worst = max(errs, key=errs.get)
+    print(f"C0 {model} BF16 edge states: output {normwise(Yg, Yo):.2e}, worst parameter gradient "
+          f"{errs[worst]:.2e} ({worst})")
+    assert errs[worst] < 5e-2, (worst, errs[worst])
+
+
+@pytest.mark.parametrize("H,ln", [(64, True), (128, False)])
+def test_edge_encoder_bf16_output_is_the_rounded_fp32_output(H, ln):
+    """The edge encoder (4 inputs -> H) with a BF16 output stores the FP32
+    output rounded to nearest even, and its adjoint given a BF16 output
+    gradient equals the adjoint given that gradient in FP32, bitwise."""
+    from paper_2410_01657_amd.ops import mlp_backward, mlp_cfg, mlp_forward
+    rng = np.random.default_rng(H)
+    n = 1000
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(DEV)
+    p = {"W0": t(rng.standard_normal((H, 4)) * 0.5), "b0": t(rng.standard_normal(H) * 0.1),
+         "W1": t(rng.standard_normal((H, H)) / H ** 0.5), "b1": t(rng.standard_normal(H) * 0.1)}
+    if ln:
+        p.update({"ln_g": t(1 + 0.1 * rng.standard_normal(H)), "ln_b": t(0.1 * rng.standard_normal(H))})
+    x = t(rng.standard_normal((n, 4)))
+    c32, c16 = mlp_cfg(4, H, H, ln, "bf16"), mlp_cfg(4, H, H, ln, "bf16", out="bf16")
+    y32, y16 = mlp_forward(c32, p, x), mlp_forward(c16, p, x)
+    assert y16.dtype == torch.bfloat16 and torch.equal(y32.to(torch.bfloat16), y16)
+    g16 = t(rng.standard_normal((n, H))).to(torch.bfloat16)
+    _, gr32 = mlp_backward(c32, p, x, g16.float(), False)
+    _, gr16 = mlp_backward(c16, p, x, g16, False)
+    for k in p:
+        assert torch.equal(gr32[k], gr16[k]), k
 
 
 def test_r_consistency_gpu_c0():

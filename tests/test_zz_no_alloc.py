@@ -24,7 +24,7 @@ def _t(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(DEV)
 
 
-def _case(mesh, part, R, H, ln, gemm, seed):
+def _case(mesh, part, R, H, ln, gemm, seed, estate="f32"):
     from paper_2410_01657_amd import DeviceGraph, build_graph
     from paper_2410_01657_amd.ops import layer_cfg, layer_forward, layer_forward_noalloc
     hg = build_graph(mesh.elem_gid, mesh.P, part, R, order="gid")
@@ -34,9 +34,10 @@ def _case(mesh, part, R, H, ln, gemm, seed):
     rng = np.random.default_rng(seed)
     x = rng.standard_normal((dg.n_rows, H)).astype(np.float32)
     e = rng.standard_normal((dg.n_edges, H)).astype(np.float32)
-    cfg = layer_cfg(H, ln, gemm=gemm)
-    ref = layer_forward(cfg, p, dg, _t(x), _t(e), want_pq=True)
-    got = layer_forward_noalloc(cfg, p, dg, _t(x), _t(e))
+    cfg = layer_cfg(H, ln, gemm=gemm, estate=estate)
+    et = _t(e).to(torch.bfloat16 if estate == "bf16" else torch.float32)
+    ref = layer_forward(cfg, p, dg, _t(x), et, want_pq=True)
+    got = layer_forward_noalloc(cfg, p, dg, _t(x), et)
     torch.cuda.synchronize()
     for a, b in zip(got, ref):
         assert torch.equal(a, b)
@@ -58,5 +59,6 @@ def test_noalloc_forward_equals_the_workspace_forward_on_two_calls():
     # second call: a smaller graph, BF16, H=32, no LayerNorm
     m = box_mesh((2, 2, 1), 2)
     _case(m, np.array([0, 1, 0, 1], np.int32), 2, 32, False, "bf16", 6)
-    # and the first shape again, BF16 this time
+    # and the first shape again, BF16 this time, then with BF16 edge states
     _case(inp.mesh, inp.elem_part, 8, 64, True, "bf16", 7)
+    _case(m, np.array([0, 1, 0, 1], np.int32), 2, 128, True, "bf16", 8, estate="bf16")
