@@ -39,18 +39,20 @@ def _first_rows(row_gid, gids):
     return order[pos]
 
 
-def _sampled_run(cfg_name, gemm, n_sample, seed, tuned=False):
+def _sampled_run(cfg_name, gemm, n_sample, seed, tuned=False, estate="f32"):
     """tuned: run under the schedule the autotuner picks for this graph
-    (the launch configuration bench.py times), else the library default."""
+    (the launch configuration bench.py times), else the library default.
+    estate: storage type of the edge states."""
     from paper_2410_01657_amd.autotune import tuned_schedule
     from paper_2410_01657_amd.model import ConsistentGNN, Problem
     cfg = CONFIGS[cfg_name]
     inp = make_inputs(cfg, perturb=True)
     prob = Problem(inp.mesh, inp.field, inp.target, inp.elem_part, cfg.R, DEV)
-    sched = tuned_schedule(prob.dg, cfg.spec.H, cfg.spec.layernorm, gemm) if tuned else None
+    sched = tuned_schedule(prob.dg, cfg.spec.H, cfg.spec.layernorm, gemm, estate=estate) if tuned else None
     if tuned:
-        print(f"{cfg_name} {gemm}: tuned schedule {sched}")
-    model = ConsistentGNN(cfg.spec, inp.params, DEV, gemm=gemm, schedule=sched).requires_grad_(True)
+        print(f"{cfg_name} {gemm} (edge states {estate}): tuned schedule {sched}")
+    model = ConsistentGNN(cfg.spec, inp.params, DEV, gemm=gemm, schedule=sched,
+                          estate=estate).requires_grad_(True)
     Y = model.forward(prob.dg, prob.X, prob.E0)
     gids = _sample(inp.mesh, n_sample, seed)
     rows = _first_rows(prob.dg.host.row_gid, np.array(gids))
@@ -91,12 +93,15 @@ def test_c4_sampled_outputs_and_gradients_bf16():
     assert eg < 5e-2, eg
 
 
-@pytest.mark.parametrize("gemm,tol_y,tol_g", [("bf16", 3e-2, 5e-2), ("f32", 1e-4, 1e-4)])
-def test_c4_sampled_outputs_and_gradients_tuned_schedule(gemm, tol_y, tol_g):
-    """The timed launch configuration: C4 at full size under the schedule
-    the autotuner picks, outputs and parameter gradients against the
-    oracle's exact receptive-field values (Eq. 2-3)."""
-    ey, eg = _report(f"C4 {gemm} tuned", *_sampled_run("C4", gemm, 24, 43, tuned=True))
+@pytest.mark.parametrize("gemm,estate,tol_y,tol_g", [("bf16", "f32", 3e-2, 5e-2), ("f32", "f32", 1e-4, 1e-4),
+                                                     ("bf16", "bf16", 3e-2, 5e-2)])
+def test_c4_sampled_outputs_and_gradients_tuned_schedule(gemm, estate, tol_y, tol_g):
+    """The timed launch configurations: C4 at full size under the schedule
+    the autotuner picks (BF16, FP32, and BF16 with BF16 edge states),
+    outputs and parameter gradients against the oracle's exact
+    receptive-field values (Eq. 2-3)."""
+    ey, eg = _report(f"C4 {gemm} edge states {estate} tuned",
+                     *_sampled_run("C4", gemm, 24, 43, tuned=True, estate=estate))
     assert ey < tol_y
     assert eg < tol_g, eg
 

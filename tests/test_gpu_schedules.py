@@ -102,3 +102,32 @@ def test_every_candidate_schedule_matches_the_oracle(graph, H, gemm):
             worst[k] = max(worst.get(k, 0.0), err)
     print(f"{graph} H={H} {gemm}: {len(_candidates(H, gemm))} schedules, worst errors "
           + ", ".join(f"{k} {v:.1e}" for k, v in sorted(worst.items())))
+
+
+@pytest.mark.parametrize("graph,H", [("c0_blocks", 64), ("rcb", 64), ("c0_blocks", 128)])
+def test_every_candidate_schedule_with_bf16_edge_states(graph, H):
+    """The BF16 edge-state option at every schedule: the FP32-state layer's
+    results on the same BF16-representable e and g_e', bitwise, with e' and
+    g_e rounded to nearest even (the FP32-state results themselves are
+    checked against the oracle above)."""
+    from paper_2410_01657_amd.autotune import apply_schedule
+    from paper_2410_01657_amd.ops import layer_backward, layer_cfg, layer_forward
+    dg, og, pairs = _graph(graph)
+    spec, o, names = layer_params(H, True)
+    rng = np.random.default_rng(H + 23)
+    X, GX = _t(rng.standard_normal((dg.n_rows, H))), _t(rng.standard_normal((dg.n_rows, H)))
+    E16 = _t(rng.standard_normal((dg.n_edges, H))).to(torch.bfloat16)
+    GE16 = _t(rng.standard_normal((dg.n_edges, H))).to(torch.bfloat16)
+    p = {k: _t(o[v]) for k, v in names.items()}
+    for sched in _candidates(H, "bf16"):
+        c32 = apply_schedule(layer_cfg(H, True, gemm="bf16"), sched)
+        c16 = apply_schedule(layer_cfg(H, True, gemm="bf16", estate="bf16"), sched)
+        xo, eo, a = layer_forward(c32, p, dg, X, E16.float())
+        xo2, eo2, a2 = layer_forward(c16, p, dg, X, E16)
+        assert torch.equal(xo, xo2) and torch.equal(a, a2), sched
+        assert torch.equal(eo.to(torch.bfloat16), eo2), sched
+        g1 = layer_backward(c32, p, dg, X, E16.float(), a, GX, GE16.float())
+        g2 = layer_backward(c16, p, dg, X, E16, a2, GX, GE16)
+        assert torch.equal(g1[0], g2[0]) and torch.equal(g1[1].to(torch.bfloat16), g2[1]), sched
+        for k in names:
+            assert torch.equal(g1[2][k], g2[2][k]), (sched, k)
