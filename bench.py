@@ -148,7 +148,7 @@ def sources_sha256(kernel):
     return h.hexdigest()
 
 
-def recorded_traffic(kernel, workload, gemm="bf16"):
+def recorded_traffic(kernel, workload, gemm="bf16", estate="f32"):
     """HBM bytes per launch (read + write) of `kernel` from the traffic
     summaries, or None when absent, for another workload or path, or stale."""
     import glob
@@ -163,7 +163,7 @@ def recorded_traffic(kernel, workload, gemm="bf16"):
                 if line.startswith("traffic:"):
                     kv = dict(t.split("=", 1) for t in line.split()[1:])
                     if (kv.get("kernel") == kernel and kv.get("workload") == workload
-                            and kv.get("gemm", "bf16") == gemm):
+                            and kv.get("gemm", "bf16") == gemm and kv.get("estate", "f32") == estate):
                         rec = kv
     if not rec or rec.get("sources_sha256") != sources_sha256(kernel):
         return None
@@ -407,6 +407,13 @@ def main():
         r["frac"] = r["achieved"] / r["peak"]
         r.update({"kernel": dom, "ms_avg": kern[dom]["ms_avg"], "algorithmic_GB": w.bytes / 1e9,
                   "algorithmic_GFLOP": w.flops / 1e9})
+        tr = None if deep else recorded_traffic(dom, a.workload, gemm, estate)
+        r["traffic"] = tr / 1e9 if tr is not None else None  # GB per launch, measured
+        r["traffic_unit"] = "GB per launch (HBM read + write)"
+        # context: the same kernel against the bandwidth a plain 2 GiB copy reaches
+        if r["bound"] == "hbm":
+            r["copy_GBps"] = copy_gbps
+            r["frac_of_copy"] = r["achieved"] / copy_gbps
         return r
 
     def mp_layers(name):
@@ -426,13 +433,6 @@ def main():
 
     # dominant kernel of the main path and its roofline
     roof = dominant_roofline(main_gemm)
-    tr = recorded_traffic(roof["kernel"], a.workload, main_gemm)
-    roof["traffic"] = tr / 1e9 if tr is not None else None  # GB per launch, measured
-    roof["traffic_unit"] = "GB per launch (HBM read + write)"
-    # context: the same kernel against the bandwidth a plain 2 GiB copy reaches
-    if roof["bound"] == "hbm":
-        roof["copy_GBps"] = copy_gbps
-        roof["frac_of_copy"] = roof["achieved"] / copy_gbps
 
     def grad_dev(name):
         """Parameter gradients of a BF16 path against the FP32 path's (which
