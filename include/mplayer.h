@@ -209,9 +209,11 @@ typedef struct {
   int32_t aggregate;
   /* More schedule dimensions (0 = library default; the results of every
    * choice are bitwise reproducible, and equal up to the grouping of the
-   * weight-gradient sums): waves per workgroup of the fused edge adjoint
-   * (4, or 8 for BF16 GEMMs at H <= 64, which stage 16 x waves edges per
-   * weight-gradient round), and the tile order of the edge forward (0: a
+   * weight-gradient sums): waves per workgroup of the edge adjoint (4, or
+   * 8 for BF16 GEMMs at H <= 64, which stage 16 x waves edges per
+   * weight-gradient round, and at H > 64, whose split adjoint then runs
+   * two waves per SIMD instead of one), and the tile order of the edge
+   * forward (0: a
    * fixed round robin over each XCD's range of tiles; 1: waves take the
    * next tile of their XCD's range from an atomic counter and move on to
    * the other ranges when theirs is empty; tiles are row aligned, so the

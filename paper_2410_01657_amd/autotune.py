@@ -3,10 +3,12 @@
 The edge kernels run persistent workgroups over row-aligned tiles.  A
 schedule sets, in mp_layer_cfg: edges per tile (tile_edges), the workgroup
 counts of the forward and adjoint edge kernels (edge_grid, edge_bwd_grid),
-the waves per workgroup of the fused edge adjoint (edge_bwd_waves: 4, or 8
-for BF16 GEMMs at H <= 64, i.e. 64 or 128 edges staged per weight-gradient
-round) and the tile order of the edge forward (edge_fwd_queue: fixed round
-robin, or per-XCD atomic tile counters).  The tuner times the library's own
+the waves per workgroup of the edge adjoint (edge_bwd_waves: 4, or 8 for
+BF16 GEMMs at H <= 64, i.e. 64 or 128 edges staged per weight-gradient
+round, and at H > 64, where 8 puts two waves of the split adjoint on each
+SIMD and 4 gives one wave all the registers it wants) and the tile order
+of the edge forward (edge_fwd_queue: fixed round robin, or per-XCD atomic
+tile counters).  The tuner times the library's own
 forward and backward on the actual graph and keeps the fastest, cached per
 (arch, H, GEMM type, edge-state type, LayerNorm, rows, edges, sub-graphs)
 in a JSON file
@@ -38,8 +40,9 @@ SCHEDULE_FIELDS = ("tile_edges", "edge_grid", "edge_bwd_grid", "edge_bwd_waves",
 
 
 def edge_bwd_waves_options(H, gemm):
-    """Waves per workgroup of the fused edge adjoint the library accepts."""
-    return (4, 8) if gemm == "bf16" and H <= 64 else (4,)
+    """Waves per workgroup of the edge adjoint the library accepts (the
+    fused kernel: 8 only with BF16 GEMMs; the split one at H > 64: both)."""
+    return (4, 8) if (gemm == "bf16" and H <= 64) or H > 64 else (4,)
 
 
 def candidates(H=64, gemm="bf16"):

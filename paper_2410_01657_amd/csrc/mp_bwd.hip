@@ -690,9 +690,16 @@ hipError_t launch_edge_bwd(const EdgeBwdArgs& a, int grid, hipStream_t s) {
 // ------------------------------------------- split edge adjoint (wide H)
 
 
-template <int H, bool BF>
+template <int H, bool BF, int NWQ>
 struct EdgeBwdSplitCfg {
-  static constexpr int NW = 8;  // independent waves sharing the LDS weight fragments
+  // NWQ independent waves sharing the LDS weight fragments: 8 (two per
+  // SIMD, 256 registers each), or 4 (one per SIMD with up to 512: the
+  // per-edge adjoint at H = 128 wants about 340, and at 256 the compiler
+  // spills, reloading row addresses between the block's loads).  Measured
+  // on C3 (one launch, same box): BF16 7.83 ms at 8 waves, 6.85 at 4; FP32,
+  // whose products keep the matrix unit busy, 15.2 at 8 and 15.6 at 4.
+  static_assert(NWQ == 4 || NWQ == 8, "4 or 8 waves per workgroup");
+  static constexpr int NW = NWQ;
   static constexpr size_t FB = frag_bytes(H, H, BF);
   // BF16 keeps W1c, W2, W2^T, W1c^T; FP32 only W1c and W2 (the transposed
   // products read them at transposed addresses, gemm_f32_tr)
@@ -718,9 +725,9 @@ struct EdgeBwdSplitCfg {
 // H/64 features), accumulated per lane, and the waves' sums are added in
 // wave order into the workgroup's slab at the end.  Waves walk their tiles
 // independently (no barriers in the loop).
-template <int H, bool BF, bool AM, bool ES>
-__global__ __launch_bounds__((64 * EdgeBwdSplitCfg<H, BF>::NW)) void k_edge_bwd_split(EdgeBwdArgs a) {
-  using C = EdgeBwdSplitCfg<H, BF>;
+template <int H, bool BF, bool AM, bool ES, int NWQ>
+__global__ __launch_bounds__((64 * EdgeBwdSplitCfg<H, BF, NWQ>::NW)) void k_edge_bwd_split(EdgeBwdArgs a) {
+  using C = EdgeBwdSplitCfg<H, BF, NWQ>;
   constexpr int NF = H / 4, MB = H / 16, NW = C::NW;
   // FP32: the transposed products read W1c / W2 in the rotated layout
   constexpr bool ROT = !BF && C::LDS_FRAG;
@@ -919,25 +926,30 @@ __global__ __launch_bounds__((64 * EdgeBwdSplitCfg<H, BF>::NW)) void k_edge_bwd_
   }
 }
 
-template <int H, bool BF, bool AM, bool ES>
+template <int H, bool BF, bool AM, bool ES, int NWQ>
 static hipError_t launch_edge_bwd_split_es(const EdgeBwdArgs& a, int grid, hipStream_t s) {
-  using C = EdgeBwdSplitCfg<H, BF>;
-  (void)hipFuncSetAttribute((const void*)k_edge_bwd_split<H, BF, AM, ES>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)C::LDS);
-  hipLaunchKernelGGL((k_edge_bwd_split<H, BF, AM, ES>), dim3(grid), dim3(64 * C::NW), C::LDS, s, a);
+  using C = EdgeBwdSplitCfg<H, BF, NWQ>;
+  (void)hipFuncSetAttribute((const void*)k_edge_bwd_split<H, BF, AM, ES, NWQ>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)C::LDS);
+  hipLaunchKernelGGL((k_edge_bwd_split<H, BF, AM, ES, NWQ>), dim3(grid), dim3(64 * C::NW), C::LDS, s, a);
   return hipGetLastError();
 }
-template <int H, bool BF, bool AM>
+template <int H, bool BF, bool AM, int NWQ>
 static hipError_t launch_edge_bwd_split_am(const EdgeBwdArgs& a, int grid, hipStream_t s) {
   if constexpr (BF) {
-    if (a.es) return launch_edge_bwd_split_es<H, BF, AM, true>(a, grid, s);
+    if (a.es) return launch_edge_bwd_split_es<H, BF, AM, true, NWQ>(a, grid, s);
   }
-  return launch_edge_bwd_split_es<H, BF, AM, false>(a, grid, s);
+  return launch_edge_bwd_split_es<H, BF, AM, false, NWQ>(a, grid, s);
 }
 
+// Waves per workgroup: 4 or 8; the default is 4 with BF16 GEMMs and 8 in
+// FP32 (the C ABI validates the field).
 template <int H, bool BF>
 static hipError_t launch_edge_bwd_split_t(const EdgeBwdArgs& a, int grid, hipStream_t s) {
-  return a.am ? launch_edge_bwd_split_am<H, BF, true>(a, grid, s) : launch_edge_bwd_split_am<H, BF, false>(a, grid, s);
+  const int nw = a.waves ? a.waves : (BF ? 4 : 8);
+  if (nw == 4)
+    return a.am ? launch_edge_bwd_split_am<H, BF, true, 4>(a, grid, s) : launch_edge_bwd_split_am<H, BF, false, 4>(a, grid, s);
+  return a.am ? launch_edge_bwd_split_am<H, BF, true, 8>(a, grid, s) : launch_edge_bwd_split_am<H, BF, false, 8>(a, grid, s);
 }
 
 hipError_t launch_edge_bwd_split(const EdgeBwdArgs& a, int grid, hipStream_t s) {

@@ -150,8 +150,8 @@ int check_cfg(const mp_layer_cfg* c) {
   if (c->aggregate != MP_AGG_STATE && c->aggregate != MP_AGG_MESSAGE)
     return mp_fail(MP_EINVAL, "aggregate must be MP_AGG_STATE or MP_AGG_MESSAGE");
   if (c->edge_bwd_waves != 0 && c->edge_bwd_waves != 4 &&
-      !(c->edge_bwd_waves == 8 && c->gemm_dtype == MP_BF16 && c->H <= 64))
-    return mp_fail(MP_EINVAL, "edge_bwd_waves must be 0, 4, or 8 (BF16 GEMMs at H <= 64 only; got %d)",
+      !(c->edge_bwd_waves == 8 && ((c->gemm_dtype == MP_BF16 && c->H <= 64) || c->H > 64)))
+    return mp_fail(MP_EINVAL, "edge_bwd_waves must be 0, 4, or 8 (BF16 GEMMs at H <= 64, or H > 64; got %d)",
                    c->edge_bwd_waves);
   if (c->edge_fwd_queue != 0 && c->edge_fwd_queue != 1)
     return mp_fail(MP_EINVAL, "edge_fwd_queue must be 0 or 1 (got %d)", c->edge_fwd_queue);

@@ -131,7 +131,7 @@ struct EdgeBwdArgs {
   DevGraph g;
   int H, ln, bf;
   int am;  // the forward aggregated the MLP output (message), not e'
-  int waves;  // waves per workgroup of the fused kernel: 0 (default), 4, or 8 (BF16, H <= 64)
+  int waves;  // waves per workgroup: 0 (default), 4, or 8 (fused kernel: BF16, H <= 64; split kernel: any)
   int es;     // edge states and their gradients (e_in, g_e_out, g_e_in) stored as BF16 (with bf only)
 
   const float* P;

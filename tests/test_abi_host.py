@@ -490,14 +490,15 @@ def test_noalloc_forward_validates_before_touching_a_gpu(L):
 def test_schedule_fields_are_validated(L):
     """The schedule dimensions of mp_layer_cfg are checked before any
     launch: waves per workgroup of the edge adjoint (0, 4, or 8 with BF16
-    GEMMs at H <= 64) and the forward's tile order (0 or 1)."""
+    GEMMs at H <= 64 or at H > 64) and the forward's tile order (0 or 1)."""
     from paper_2410_01657_amd._lib import MPError, call
     from paper_2410_01657_amd.autotune import candidates
     from paper_2410_01657_amd.ops import layer_cfg
     d = _fake_desc(L)
     nb = C.c_size_t()
     for H, gemm, waves, q, ok in ((64, "bf16", 8, 1, True), (64, "bf16", 4, 0, True), (32, "bf16", 8, 0, True),
-                                  (128, "bf16", 8, 0, False), (64, "f32", 8, 0, False), (64, "f32", 4, 1, True),
+                                  (128, "bf16", 8, 0, True), (128, "f32", 8, 1, True), (32, "f32", 8, 0, False),
+                                  (64, "f32", 8, 0, False), (64, "f32", 4, 1, True),
                                   (64, "bf16", 6, 0, False), (64, "bf16", 0, 2, False)):
         cfg = layer_cfg(H, gemm=gemm)
         cfg.edge_bwd_waves, cfg.edge_fwd_queue = waves, q

@@ -359,3 +359,29 @@ def test_edge_state_dtype_mismatch_is_rejected(c0):
         layer_forward(layer_cfg(32, False, gemm="bf16", estate="bf16"), _lib_params(o, names), dg, x, e)
     with pytest.raises(ValueError):
         layer_forward(layer_cfg(32, False, gemm="bf16"), _lib_params(o, names), dg, x, e.to(torch.bfloat16))
+
+
+@pytest.mark.parametrize("gemm", ["bf16", "f32"])
+def test_split_adjoint_waves_per_workgroup(c0, gemm):
+    """The split edge adjoint (H = 128) with 4 and with 8 waves per
+    workgroup: the per-edge work is the same, so g_x and g_e are bitwise
+    equal; the weight gradients differ only in the grouping of their sums
+    (Eq. 3) and agree to FP32 rounding."""
+    from paper_2410_01657_amd.ops import layer_backward, layer_cfg, layer_forward
+    dg, og, pairs = c0[1][8]
+    H = 128
+    spec, o, names = layer_params(H, True)
+    rng = np.random.default_rng(17)
+    x, e = _t(rng.standard_normal((dg.n_rows, H))), _t(rng.standard_normal((dg.n_edges, H)))
+    gx, ge = _t(rng.standard_normal((dg.n_rows, H))), _t(rng.standard_normal((dg.n_edges, H)))
+    p = _lib_params(o, names)
+    out = []
+    for waves in (4, 8):
+        cfg = layer_cfg(H, True, gemm=gemm)
+        cfg.edge_bwd_waves = waves
+        _, _, a = layer_forward(cfg, p, dg, x, e)
+        out.append(layer_backward(cfg, p, dg, x, e, a, gx, ge))
+    (gx4, ge4, w4), (gx8, ge8, w8) = out
+    assert torch.equal(gx4, gx8) and torch.equal(ge4, ge8)
+    for k in names:
+        assert normwise(w4[k].cpu().numpy(), w8[k].cpu().numpy()) < 1e-5, k
