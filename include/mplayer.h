@@ -298,7 +298,9 @@ size_t mp_layer_forward_noalloc_max_scratch(void);
  * Edge-MLP activations are recomputed from (x_in, e_in), not stored.  The
  * halo sum is its own adjoint and is applied to the a* gradient.  g_e_out
  * may be NULL (zero).  pq is the forward's pq_out for the same inputs and
- * parameters, or NULL (then P and Q are recomputed). */
+ * parameters, or NULL (then P and Q are recomputed).  e_in, g_e_out and
+ * g_e_in are [E][H] in cfg->estate_dtype (FP32 or BF16); everything else
+ * FP32. */
 int mp_layer_backward(const mp_layer_cfg* cfg, const mp_layer_params* p,
                       const mp_dev_graph* g, const float* x_in, const void* e_in,
                       const float* a_star, const float* pq, const float* g_x_out, const void* g_e_out,
