@@ -64,3 +64,25 @@ def test_split_adjoints_are_counted_where_their_products_run():
     # the layer roofline is the sum over kernels of the higher floor, per layer
     t = layer_roof_seconds(N, E, G, M, 128, "f32", 4)
     assert 0.09 < t < 0.11  # C3, FP32: about 25 ms of matrix time per layer
+
+
+def test_bf16_edge_states_change_only_the_edge_state_bytes():
+    """BF16 edge-state storage halves the bytes of e, e', g_e' and g_e in
+    the edge kernels (and of e in the split weight-gradient pass); node
+    arrays, flops and every other kernel are unchanged."""
+    sys.path.insert(0, ROOT)
+    from paper_2410_01657_amd.roofline import layer_kernels
+    N, E, G, M = 11852352, 69866496, 449577, 911304
+    for H in (64, 128):
+        a = layer_kernels(N, E, G, M, H, "bf16", 4)
+        b = layer_kernels(N, E, G, M, H, "bf16", 4, "bf16")
+        assert a.keys() == b.keys()
+        ge = 3 / 4  # three of four layers receive g_e'
+        assert a["edge_fwd"].bytes - b["edge_fwd"].bytes == E * 2 * H * 2
+        assert abs((a["edge_bwd"].bytes - b["edge_bwd"].bytes) - E * (2 + ge) * H * 2) < 1
+        if H > 64:
+            assert a["edge_dw"].bytes - b["edge_dw"].bytes == E * H * 2
+        for k in a:
+            assert a[k].flops == b[k].flops
+            if k not in ("edge_fwd", "edge_bwd", "edge_dw"):
+                assert a[k].bytes == b[k].bytes, k
