@@ -21,8 +21,9 @@ built on 16 x 16 products; the BF16 path is not bound by its products, and
 the FP32 products already issue back to back); the unsplit first edge
 Linear (twice the flops for the same bytes, never faster).  BF16 storage of
 the edge states (estate="bf16") is not a schedule: it changes the stored
-precision, not just the grouping of sums, so the caller chooses it and the
-tuner keeps a separate entry for it.
+precision, not just the grouping of sums, so tuned_schedule takes it from
+the caller and keeps a separate entry for it; tuned_edge_state searches it
+too, for callers that accept BF16 edge states.
 """
 
 import json
@@ -161,3 +162,19 @@ def tuned_schedule(dg, H, layernorm=True, gemm="bf16", retune=False, estate="f32
         cache[key] = tune_layer(dg, H, layernorm, gemm, estate=estate)
         _store(cache)
     return cache[key]
+
+
+def tuned_edge_state(dg, H, layernorm=True, gemm="bf16", retune=False):
+    """The edge-state storage type searched as well (an opt-in, BF16 GEMMs
+    only): the faster of the tuned schedules with FP32 and with BF16 edge
+    states, its storage type under "estate" (pass it to ConsistentGNN or
+    layer_cfg with the schedule).  BF16 storage rounds the edge states
+    between layers, so only callers that accept that precision use it."""
+    if gemm != "bf16":
+        return dict(tuned_schedule(dg, H, layernorm, gemm, retune), estate="f32")
+    best = None
+    for es in ("f32", "bf16"):
+        sched = tuned_schedule(dg, H, layernorm, gemm, retune, estate=es)
+        if best is None or sched["ms"] < best["ms"]:
+            best = dict(sched, estate=es)
+    return best

@@ -131,3 +131,29 @@ def test_every_candidate_schedule_with_bf16_edge_states(graph, H):
         assert torch.equal(g1[0], g2[0]) and torch.equal(g1[1].to(torch.bfloat16), g2[1]), sched
         for k in names:
             assert torch.equal(g1[2][k], g2[2][k]), (sched, k)
+
+
+def test_edge_state_search_returns_a_usable_choice(tmp_path, monkeypatch):
+    """The opt-in search over the edge-state storage type returns one of the
+    two tuned schedules with its storage type, and a model built with both
+    runs forward and backward to finite values."""
+    from paper_2410_01657_amd.autotune import tuned_edge_state, tuned_schedule
+    from paper_2410_01657_amd.model import ConsistentGNN, Problem
+    from mpinputs import ModelSpec
+    monkeypatch.setenv("MPLAYER_TUNE_CACHE", str(tmp_path / "tune.json"))
+    inp = make_inputs(CONFIGS["C0"])
+    spec = ModelSpec(H=64, n_layers=2, layernorm=True)
+    prob = Problem(inp.mesh, inp.field, inp.target, inp.elem_part, 8, DEV)
+    best = tuned_edge_state(prob.dg, spec.H, spec.layernorm, "bf16")
+    assert best["estate"] in ("f32", "bf16")
+    other = tuned_schedule(prob.dg, spec.H, spec.layernorm, "bf16",
+                           estate="bf16" if best["estate"] == "f32" else "f32")
+    assert best["ms"] <= other["ms"]
+    assert tuned_edge_state(prob.dg, spec.H, spec.layernorm, "f32")["estate"] == "f32"
+    from mpinputs import init_params
+    model = ConsistentGNN(spec, init_params(spec, 0), DEV, gemm="bf16", schedule=best,
+                          estate=best["estate"]).requires_grad_(True)
+    loss = model.loss(prob.dg, model.forward(prob.dg, prob.X, prob.E0), prob.T)
+    loss.backward()
+    assert torch.isfinite(loss).item()
+    assert all(torch.isfinite(t.grad).all().item() for t in model.params.values())
