@@ -694,10 +694,10 @@ template <int H, bool BF, int NWQ>
 struct EdgeBwdSplitCfg {
   // NWQ independent waves sharing the LDS weight fragments: 8 (two per
   // SIMD, 256 registers each), or 4 (one per SIMD with up to 512: the
-  // per-edge adjoint at H = 128 wants about 340, and at 256 the compiler
-  // spills, reloading row addresses between the block's loads).  Measured
-  // on C3 (one launch, same box): BF16 7.83 ms at 8 waves, 6.85 at 4; FP32,
-  // whose products keep the matrix unit busy, 15.2 at 8 and 15.6 at 4.
+  // per-edge adjoint at H = 128 wants about 320, and at 256 the compiler
+  // spills).  Measured on C3 (one launch, same box): BF16 7.30 ms at 8
+  // waves, 7.04 at 4; FP32, whose products keep the matrix unit busy, 14.3
+  // at 8 and 15.6 at 4.
   static_assert(NWQ == 4 || NWQ == 8, "4 or 8 waves per workgroup");
   static constexpr int NW = NWQ;
   static constexpr size_t FB = frag_bytes(H, H, BF);
@@ -749,7 +749,7 @@ __global__ __launch_bounds__((64 * EdgeBwdSplitCfg<H, BF, NWQ>::NW)) void k_edge
   __syncthreads();
 
   const DevGraph& gr = a.g;
-  const int lane = lane_id(), j = lane & 15, g = lane >> 4, wave = threadIdx.x / 64;
+  const int lane = lane_id(), j = lane & 15, g0 = lane >> 4, wave = threadIdx.x / 64;
   const TileSched ts = tile_sched(gr.n_tiles);
   constexpr int NS = C::NS;
   float sbe[NS], sga[NS];  // this lane's share of dbeta, dgamma
@@ -779,6 +779,12 @@ __global__ __launch_bounds__((64 * EdgeBwdSplitCfg<H, BF, NWQ>::NW)) void k_edge
       const bool valid = k < e1;
       const int64_t kk = valid ? k : e_last;
       const int ri = ri_n, sj = sj_n;
+      // the lane's feature offset, recomputed per block: hoisted out of the
+      // loop, every array's 64-bit base plus offset would be held in
+      // registers (at eight waves they spilled, and their reloads
+      // serialised the block's row loads; C3: BF16 7.9 -> 7.3 ms, FP32
+      // 14.8 -> 14.3 ms per launch at eight waves)
+      const int g = g0 + opaque_zero();
       const float inv_d = 1.f / (float)md_n;
       const bool last = valid && nx_n != ri;
       const int key = valid ? ri + 1 : -1;
